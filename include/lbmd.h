@@ -1,0 +1,192 @@
+/*
+ * lbmd.h -- C ABI of the MI355X coupled lattice-Boltzmann / molecular-dynamics
+ * library (liblbmd.so).
+ *
+ * The library advances the per-time-step hot path of the multiscale scheme of
+ * Fyta, Sircar, Kaxiras, Melchionna, Bernaschi and Succi, "Parallel multiscale
+ * modeling of biopolymer dynamics with hydrodynamic correlations":
+ *   - a D3Q19 BGK solvent (Sec. 2, Eqs. (dens), (vel), (lbe2) and the
+ *     equilibrium that follows it) with a force source term (the S_i of
+ *     Sec. 2, Eq. (momentum_cons)) and halfway bounce-back at a wall plane
+ *     with a square pore (Sec. 4);
+ *   - a bead-spring polymer (Sec. 2, Eqs. (MD), (MDFORCES): truncated LJ,
+ *     harmonic bonds, bending) advanced by the stochastic position Verlet
+ *     scheme (Sec. 2, Eq. (SPValgo)) with the fluid velocity frozen during
+ *     the MD sub-cycle;
+ *   - the bead <-> fluid exchange: trilinear interpolation of u at each bead,
+ *     friction gamma (u - v) plus Gaussian noise, and the reaction impulse
+ *     spread back onto the 8 surrounding nodes.
+ *
+ * Conventions (all entry points):
+ *   - Ownership: the caller allocates every device buffer (sizes from
+ *     lb_buffer_sizes) and keeps it alive until lb_destroy; the library
+ *     borrows the pointers and never allocates device memory.
+ *   - Streams: every call enqueues work on the stream given to lb_init and
+ *     returns without synchronising, except lb_check, lb_autotune and the
+ *     host-copy helpers, which say so.
+ *   - Errors: each call returns LB_OK (0) or a negative LB_ERR_* code; the
+ *     message of the last failure of the calling thread is returned by
+ *     lb_last_error().  No C++ exception crosses this boundary.
+ *   - Units: lattice units, lattice spacing = LB time step = 1.
+ *   - Node index: c = x + nx * (y + ny * z).
+ */
+#ifndef LBMD_H
+#define LBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LB_OK = 0,
+  LB_ERR_ARG = -1,         /* invalid description, size or pointer          */
+  LB_ERR_DEVICE = -2,      /* a HIP call or kernel launch failed            */
+  LB_ERR_UNSTABLE = -3,    /* watchdog: non-finite value or density <= 0    */
+  LB_ERR_UNSUPPORTED = -4  /* valid request this build does not handle      */
+};
+
+/* Storage of the populations. */
+enum {
+  LB_FP64 = 0,     /* f_i in double                                           */
+  LB_FP32_DEV = 1  /* f_i - w_i in float, collision in float, bead side FP64 */
+};
+
+/* Number of doubles lb_observables writes. */
+#define LB_NOBS 23
+
+/*
+ * Run description.  The geometry follows Sec. 4: one wall plane normal to
+ * wall_axis at lattice plane wall_pos, solid except a pore_h x pore_h block
+ * centred on the two transverse axes (block [n/2 - pore_h/2, n/2 - pore_h/2 +
+ * pore_h - 1] on each), periodic on all three axes.  wall_axis = -1 means no
+ * wall (and no driving field).
+ */
+typedef struct lb_desc {
+  int32_t nx, ny, nz;
+  int32_t precision;      /* LB_FP64 or LB_FP32_DEV                          */
+  double tau;             /* BGK relaxation time (> 0.5); nu = (tau-1/2)/3   */
+  double g[3];            /* uniform body-force density on every fluid node  */
+  int32_t wall_axis;      /* -1, 0, 1, 2                                     */
+  int32_t wall_pos;       /* 2 <= wall_pos <= n - 3 along wall_axis          */
+  int32_t pore_h;         /* 0 <= pore_h <= transverse extent                */
+  int32_t nb;             /* beads in the chain (0: fluid only)              */
+  double mass;            /* bead mass                                        */
+  double k_bond, r0;      /* harmonic bond constant and rest length          */
+  double kappa;           /* bending constant, V = kappa phi^2 / 2           */
+  double eps, sigma, rc;  /* truncated LJ (bead-bead and bead-wall site)     */
+  double gamma, kT;       /* friction rate and thermal energy of the beads   */
+  double f_drive;         /* force along +normal on beads in the pore channel */
+  int32_t n_sub;          /* MD sub-steps per LB step                        */
+  uint32_t seed, replica; /* Philox key of the bead noise                     */
+} lb_desc;
+
+/* Byte sizes of the caller-allocated device buffers (256-byte aligned). */
+typedef struct lb_sizes {
+  size_t pops_bytes;   /* one population array, [19][N] of double or float;
+                          two are needed (pops_a, pops_b)                     */
+  size_t flags_bytes;  /* uint8 per node                                      */
+  size_t force_bytes;  /* bead force density on the lattice, [3][N]          */
+  size_t beads_bytes;  /* bead state, doubles: r, v, u_p, J, r_start, each [nb][3] */
+  size_t work_bytes;   /* private scratch: lists, counters, partial sums      */
+  size_t state_bytes;  /* size of the buffer lb_get_state writes              */
+} lb_sizes;
+
+/* Device pointers (hipMalloc'ed or torch CUDA tensors), 256-byte aligned. */
+typedef struct lb_buffers {
+  void* pops_a;
+  void* pops_b;
+  void* flags;
+  void* force;
+  void* beads;
+  void* work;
+} lb_buffers;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Validates *d and fills *out.  Host only: calls no HIP function.
+ * LB_ERR_ARG: extents <= 0 or N > 2^31 - 1, tau <= 0.5, a wall plane outside
+ * [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative gamma
+ * or kT, rc > 2, or nb > 0 without a positive mass. */
+int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
+
+/* Creates a context (host memory only) on the current HIP device, builds the
+ * solid flags of the geometry on the host and uploads them, fills both
+ * population arrays with the rest equilibrium f_i = w_i (zero in
+ * LB_FP32_DEV; Sec. 4: unit density, zero velocity) and uploads the bead
+ * positions r0_host and velocities v0_host ([nb][3] doubles, host memory;
+ * v0_host may be NULL for zero; positions are unwrapped).  stream is a
+ * hipStream_t (NULL: the default stream).  The uploads are enqueued on
+ * stream from pageable host memory.  LB_ERR_ARG: as lb_buffer_sizes, a NULL
+ * or misaligned buffer, or a bead whose base node is solid. */
+int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const double* v0_host,
+            void* stream, lb_ctx** out);
+
+/* Releases the host-side context; the caller frees its buffers afterwards. */
+void lb_destroy(lb_ctx* ctx);
+
+/* nsteps fluid-only LB steps (Sec. 2, Eq. (lbe2)): pull-stream with halfway
+ * bounce-back, BGK collision towards the second-order equilibrium, source
+ * 3 w_i g.c_i of the uniform body force.  Beads are not moved. */
+int lb_step(lb_ctx* ctx, int nsteps);
+
+/* nsteps coupled steps.  Each step, at the bead positions r(n):
+ *   1. u_p = trilinear interpolation of the fluid velocity (from the pulled
+ *      populations of the stored array; u = 0 at solid nodes) (Sec. 2, the
+ *      particle-to-grid transfer, here trilinear instead of nearest point);
+ *   2. n_sub SPV sub-steps of h = 1/n_sub with u_p frozen (Sec. 2,
+ *      Eq. (SPValgo) without constraints): r += h/2 v;
+ *      v = e v + (1-e)/(m gamma) (F(r) + gamma u_p) + sqrt(kT/m (1-e^2)) xi;
+ *      r += h/2 v; e = exp(-gamma h); F = bonds + bending + bead LJ + wall LJ
+ *      + field; xi from Philox4x32-10 keyed (seed, replica) with counter
+ *      (step, sub-step, bead, 0) and Box-Muller;
+ *   3. J_p = -(friction + noise impulse) is spread trilinearly at r(n) onto
+ *      the 8 nodes, summed per node in ascending bead order (no atomics);
+ *   4. one LB step with the source 3 w_i (F(x) + g).c_i (Sec. 2, S_i). */
+int md_couple_step(lb_ctx* ctx, int nsteps);
+
+/* Pre-relaxation of the chain (Sec. 4: the initial walk is relaxed by MD):
+ * nsub_total SPV sub-steps with no fluid coupling, no field, no noise and
+ * friction gamma_relax; the velocities are zeroed at the end. */
+int md_relax(lb_ctx* ctx, int nsub_total, double gamma_relax);
+
+/* Writes LB_NOBS doubles to out_dev (device memory): [0] fluid mass,
+ * [1..3] fluid momentum (Sec. 3: global momentum reductions), [4] bead
+ * temperature m<v^2>/3 (Sec. 2: the monitored bead temperature), [5..7] bead
+ * momentum, [8] mean unwrapped normal coordinate, [9] translocated fraction,
+ * [10] beads in the pore channel, [11] R_U, [12] R_T, [13] R_eff with
+ * nu = 0.6 (Sec. 4, Eq. (R_eff)), [14] dW_H/dt = gamma sum v.u_p and
+ * [15] dW_E/dt = sum F_drive.v (Sec. 4, translocation work), [16..21] wall
+ * momentum ledgers (not tracked on the device: NaN), [22] step count.
+ * Sums are FP64. */
+int lb_observables(lb_ctx* ctx, double* out_dev);
+
+/* Checkpoint: copies the current populations ([19][N], the storage type),
+ * r and v ([nb][3] doubles each) and the step counter (uint64) to dst_dev
+ * (device, lb_sizes.state_bytes) / restores them from src_dev.  Device to
+ * device, enqueued on the stream. */
+int lb_get_state(lb_ctx* ctx, void* dst_dev);
+int lb_set_state(lb_ctx* ctx, const void* src_dev);
+
+/* Device pointer of the populations that the next step reads. */
+void* lb_current_pops(lb_ctx* ctx);
+
+/* Synchronises the stream and reads the device watchdog word: LB_OK, or
+ * LB_ERR_UNSTABLE (non-finite or non-positive density, non-finite bead
+ * state, a neighbour list or node-contributor list overflow), with the
+ * reason in lb_last_error(). */
+int lb_check(lb_ctx* ctx);
+
+/* Steps taken so far (host copy). */
+int64_t lb_step_count(lb_ctx* ctx);
+
+/* Message of the last failed call on this thread (never NULL). */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMD_H */

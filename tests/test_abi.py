@@ -1,0 +1,79 @@
+"""The C ABI: liblbmd.so loads on a host without a GPU, exports every entry
+point include/lbmd.h declares, and validates descriptions on the host
+(lb_buffer_sizes calls no HIP function)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                            txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("lb_buffer_sizes", "lb_init", "lb_step", "md_couple_step", "lb_observables", "lb_destroy",
+              "lb_get_state", "lb_set_state", "lb_check", "lb_last_error", "md_relax"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_0711_2665_amd import lbmd
+    L = lbmd.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_desc_layout_matches_header():
+    # the ctypes mirror has the field order and sizes of struct lb_desc
+    from paper_0711_2665_amd import lbmd
+    assert C.sizeof(lbmd.LbDesc) == 4 * 4 + 8 * 4 + 4 * 4 + 8 * 10 + 4 * 3 + 4  # trailing pad to 8
+    assert C.sizeof(lbmd.LbSizes) == 6 * 8
+    assert C.sizeof(lbmd.LbBuffers) == 6 * 8
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(shape=(0, 4, 4)), "extents"),
+    (dict(wall_axis=2, wall_pos=1), "wall plane"),
+    (dict(wall_axis=2, wall_pos=8, pore_h=40), "pore"),
+    (dict(n_sub=0), "n_sub"),
+    (dict(nb=-1), "negative"),
+    (dict(nb=3, mass=0.0), "mass"),
+    (dict(nb=3, rc=2.5), "rc"),
+    (dict(shape=(1024, 1024, 128)), "too large"),
+])
+def test_host_validation(bad, msg):
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import BASE
+    cfg = dict(BASE)
+    cfg.update(shape=(16, 16, 16), wall_axis=-1, wall_pos=0, pore_h=0, nb=0)
+    cfg.update(bad)
+    with pytest.raises(lbmd.LbError) as e:
+        lbmd.buffer_sizes(cfg)
+    assert e.value.code == lbmd.LB_ERR_ARG
+    assert msg in str(e.value)
+
+
+def test_buffer_sizes_are_aligned_and_exact():
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import C3
+    s = lbmd.buffer_sizes(C3, lbmd.LB_FP32_DEV)
+    N = 512 * 256 * 256
+    assert s["pops_bytes"] == 19 * N * 4
+    assert s["flags_bytes"] == N
+    assert all(v % 256 == 0 for v in s.values())
+    s64 = lbmd.buffer_sizes(C3, lbmd.LB_FP64)
+    assert s64["pops_bytes"] == 19 * N * 8
