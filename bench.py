@@ -1,0 +1,172 @@
+"""Benchmark of the coupled LB/MD hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c1|c0|c4]
+
+A step is one full coupled step (trilinear gather, the 100-sub-step bead
+cycle, deterministic spreading, and the fused stream + collide sweep over
+every lattice node).  The default workload is the large single run:
+512 x 256 x 256 nodes (33.5 M), wall normal to x at x = 256 with a 7 x 7
+pore, one 8000-bead chain, FP32 deviation storage of the populations.
+Inputs are synthetic (seeded self-avoiding coil, relaxed on the GPU before
+timing) and resident in HBM before the timed region.
+
+Prints one JSON line: the metric (MLUPS of the whole coupled step), the
+roofline of the dominant kernel (the LB sweep, timed with HIP events inside
+the library on the stream it runs on), the FP64 path on the same workload,
+bead throughput, and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+Q = 19
+
+
+def lb_bytes_per_update(elem_bytes):
+    """Algorithmic bytes of one fluid-node update of the pull sweep: read 19
+    populations, write 19 populations, read the 1-byte node flag."""
+    return 2 * Q * elem_bytes + 1
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lb_kernels.hip", "lbmd_dev.h", "lbmd_kernels.h"):
+        with open(os.path.join(ROOT, "paper_0711_2665_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"lb_sweep_{precision}_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_gpu(cfg, precision_name, steps, warmup):
+    import torch
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import initial_chain
+
+    prec = lbmd.LB_FP32_DEV if precision_name == "fp32dev" else lbmd.LB_FP64
+    r, v = initial_chain(cfg)
+    sim = lbmd.Simulation(cfg, r, v, precision=prec, device="cuda:0")
+    sim.relax(cfg["relax_substeps"], cfg["gamma_relax"])
+    sim.couple_step(warmup)
+    torch.cuda.synchronize()
+    sim.check()
+    sim.profile_start(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.couple_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lb_ms, bead_ms, nrec = sim.profile_stop()
+    sim.check()
+    obs = sim.observables().cpu().numpy()
+    nfluid = int(((sim.flags() & 1) == 0).sum().item())
+    del sim
+    torch.cuda.empty_cache()
+    return dict(seconds=t1 - t0, lb_ms=lb_ms, bead_ms=bead_ms, nrec=nrec, nfluid=nfluid, obs=obs)
+
+
+def run_cpu_baseline(cfg, steps):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload:
+    `steps` coupled steps of the full lattice and chain (the chain given a
+    short oracle relaxation first), all host threads."""
+    import oracle
+    from paper_0711_2665_amd.workloads import initial_chain
+    r, v = initial_chain(cfg)
+    o = oracle.Oracle(cfg, r, v)
+    o.relax(200, cfg["gamma_relax"])
+    o.couple_step(1)
+    t0 = time.perf_counter()
+    o.couple_step(steps)
+    t1 = time.perf_counter()
+    cells = cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2]
+    return dict(value=cells * steps / (t1 - t0) / 1e6, cores=oracle.max_threads(), seconds=t1 - t0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_0711_2665_amd.workloads import CONFIGS
+    cfg = CONFIGS[args.workload]
+    nx, ny, nz = cfg["shape"]
+    cells = nx * ny * nz
+
+    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    ms_per_step = 1e3 * main_run["seconds"] / args.steps
+    mlups = cells * args.steps / main_run["seconds"] / 1e6
+    elem = 4 if args.precision == "fp32dev" else 8
+    alg_bytes = main_run["nfluid"] * lb_bytes_per_update(elem) + (cells - main_run["nfluid"])
+    achieved = alg_bytes / (main_run["lb_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.precision)
+    out = {
+        "metric": "LB MLUPS of the coupled LB/MD step (and %HBM roofline of the LB sweep)",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32dev" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "lattice": [nx, ny, nz], "beads": cfg["nb"],
+                   "n_sub": cfg["n_sub"], "storage": args.precision, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_lb (fused stream+collide)", "bytes_per_launch": alg_bytes,
+                     "mean_launch_ms": round(main_run["lb_ms"], 5)},
+        "lb_sweep_mlups": round(cells / (main_run["lb_ms"] * 1e-3) / 1e6, 1),
+        "bead_phase_ms": round(main_run["bead_ms"], 4),
+        "bead_steps_per_s": round(cfg["nb"] * args.steps / main_run["seconds"], 1),
+        "bead_substeps_per_s": round(cfg["nb"] * cfg["n_sub"] * args.steps / main_run["seconds"], 1),
+    }
+    if not args.no_fp64 and args.precision == "fp32dev":
+        k64 = max(20, args.steps // 4)
+        r64 = run_gpu(cfg, "fp64", k64, max(5, args.warmup // 4))
+        ach64 = (r64["nfluid"] * lb_bytes_per_update(8) + (cells - r64["nfluid"])) / (r64["lb_ms"] * 1e-3) / 1e9
+        out["fp64"] = {"value": round(cells * k64 / r64["seconds"] / 1e6, 1), "unit": "MLUPS", "steps": k64,
+                       "ms_per_step": round(1e3 * r64["seconds"] / k64, 4),
+                       "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
+    if not args.no_cpu:
+        cb = run_cpu_baseline(cfg, args.cpu_steps)
+        out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "MLUPS", "cores": cb["cores"],
+                               "kind": "oracle",
+                               "sample": f"{args.cpu_steps} coupled FP64 steps of the full {nx}x{ny}x{nz} lattice "
+                                         f"with the {cfg['nb']}-bead chain ({cb['seconds']:.1f} s)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,17 @@ int lb_check(lb_ctx* ctx);
 /* Steps taken so far (host copy). */
 int64_t lb_step_count(lb_ctx* ctx);
 
+/* Kernel timing: from lb_profile_start on, HIP events are recorded on the
+ * stream around every LB sweep (phase 0) and every bead phase -- gather, MD
+ * sub-cycle and spreading -- (phase 1) of lb_step / md_couple_step, for at
+ * most max_steps steps.  lb_profile_stop synchronises the stream, writes the
+ * mean duration in ms of each phase and the number of steps recorded, and
+ * stops recording.  Events are host-side objects; no device memory is
+ * allocated by the library.  LB_ERR_ARG: max_steps < 1 or recording already
+ * active / not active. */
+int lb_profile_start(lb_ctx* ctx, int max_steps);
+int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* nsteps);
+
 /* Message of the last failed call on this thread (never NULL). */
 const char* lb_last_error(void);
 

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <unordered_map>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -306,6 +307,10 @@ struct Sim {
   // swap.  Solid nodes are never written.  The bounce-back momentum given to
   // the wall is recorded in ledger_bb.
   void lb_sweep() {
+    // Ledger: every link (x, i) whose upstream node x - c_i is solid carried
+    // A_opp(i)(x) into the wall and came back as f_i(x): the wall took
+    // 2 A_opp(i)(x) c_opp(i).  Summed per z plane, then over planes in order.
+    std::vector<R> plane_ledger((size_t)3 * nz, R(0.0));
 #pragma omp parallel for schedule(static) if (std::is_same<R, double>::value)
     for (int z = 0; z < nz; ++z) {
       R f[Q], out[Q], Fx[3];
@@ -317,23 +322,16 @@ struct Sim {
           for (int a = 0; a < 3; ++a) Fx[a] = F[(size_t)a * N + c] + R(d.g[a]);
           collide(f, Fx, out);
           for (int i = 0; i < Q; ++i) B[(size_t)i * N + c] = out[i];
-        }
-    }
-    // Ledger: every link (x, i) whose upstream node x - c_i is solid carried
-    // A_opp(i)(x) into the wall and came back as f_i(x): the wall took
-    // 2 A_opp(i)(x) c_opp(i).
-    for (int z = 0; z < nz; ++z)
-      for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-          long c = idx(x, y, z);
-          if (solid[c]) continue;
           for (int i = 1; i < Q; ++i) {
             long src = idx(wrapi(x - CV[i][0], nx), wrapi(y - CV[i][1], ny), wrapi(z - CV[i][2], nz));
             if (!solid[src]) continue;
             R fo = A[(size_t)OPP[i] * N + c];
-            for (int a = 0; a < 3; ++a) ledger_bb[a] += R(2.0) * fo * R((double)CV[OPP[i]][a]);
+            for (int a = 0; a < 3; ++a) plane_ledger[3 * (size_t)z + a] += R(2.0) * fo * R((double)CV[OPP[i]][a]);
           }
         }
+    }
+    for (int z = 0; z < nz; ++z)
+      for (int a = 0; a < 3; ++a) ledger_bb[a] += plane_ledger[3 * (size_t)z + a];
     std::swap(A, B);
   }
 
@@ -528,7 +526,9 @@ struct Sim {
       mc[a] = (int)std::floor((double)ext(a) / d.rc);
       side[a] = (double)ext(a) / (double)mc[a];
     }
-    std::vector<std::vector<int>> cells((size_t)mc[0] * mc[1] * mc[2]);
+    // occupied cells only (most cells of a large box are empty)
+    std::unordered_map<long, std::vector<int>> cells;
+    auto cell_of = [&](int x, int y, int z) { return (long)x + (long)mc[0] * ((long)y + (long)mc[1] * (long)z); };
     std::vector<int> cid(nb * 3);
     for (int p = 0; p < nb; ++p) {
       for (int a = 0; a < 3; ++a) {
@@ -537,7 +537,7 @@ struct Sim {
         if (c >= mc[a]) c = mc[a] - 1;
         cid[3 * p + a] = c;
       }
-      cells[(size_t)cid[3 * p] + (size_t)mc[0] * (cid[3 * p + 1] + (size_t)mc[1] * cid[3 * p + 2])].push_back(p);
+      cells[cell_of(cid[3 * p], cid[3 * p + 1], cid[3 * p + 2])].push_back(p);
     }
     cand.assign(nb, {});
     for (int p = 0; p < nb; ++p) {
@@ -546,7 +546,9 @@ struct Sim {
           for (int ox = -1; ox <= 1; ++ox) {
             int cx = wrapi(cid[3 * p] + ox, mc[0]), cy = wrapi(cid[3 * p + 1] + oy, mc[1]),
                 cz = wrapi(cid[3 * p + 2] + oz, mc[2]);
-            for (int j : cells[(size_t)cx + (size_t)mc[0] * (cy + (size_t)mc[1] * cz)])
+            auto it = cells.find(cell_of(cx, cy, cz));
+            if (it == cells.end()) continue;
+            for (int j : it->second)
               if (j != p) cand[p].push_back(j);
           }
       std::sort(cand[p].begin(), cand[p].end());

@@ -158,12 +158,26 @@ struct lb_ctx {
   double nfluid;
   int64_t steps;
   bool dev;
+  // kernel timing (lb_profile_start / lb_profile_stop)
+  std::vector<hipEvent_t> ev;   // 4 per recorded step: bead start/end, LB start/end
+  int prof_max = 0;
+  int prof_n = 0;
+  bool prof_on = false;
 };
 
 namespace {
 
 void* cur_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_a : c->b.pops_b; }
 void* other_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_b : c->b.pops_a; }
+
+// Event slot k of the current recorded step (0, 1: bead phase; 2, 3: sweep).
+void prof_mark(lb_ctx* c, int k) {
+  if (!c->prof_on || c->prof_n >= c->prof_max) return;
+  acc(hipEventRecord(c->ev[4 * (size_t)c->prof_n + k], c->s));
+}
+void prof_next(lb_ctx* c) {
+  if (c->prof_on && c->prof_n < c->prof_max) ++c->prof_n;
+}
 
 void launch_lb_any(lb_ctx* c) {
   if (c->dev) launch_lb<float, true>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl, c->s);
@@ -305,13 +319,61 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
   return LB_OK;
 }
 
-void lb_destroy(lb_ctx* ctx) { delete ctx; }
+void lb_destroy(lb_ctx* ctx) {
+  if (!ctx) return;
+  for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+int lb_profile_start(lb_ctx* c, int max_steps) {
+  if (!c || max_steps < 1) return fail(LB_ERR_ARG, "bad arguments");
+  if (c->prof_on) return fail(LB_ERR_ARG, "profiling already active");
+  size_t need = 4 * (size_t)max_steps;
+  while (c->ev.size() < need) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return fail(LB_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(r));
+    c->ev.push_back(e);
+  }
+  c->prof_max = max_steps;
+  c->prof_n = 0;
+  c->prof_on = true;
+  return LB_OK;
+}
+
+int lb_profile_stop(lb_ctx* c, double* mean_lb_ms, double* mean_bead_ms, int* nsteps) {
+  if (!c) return fail(LB_ERR_ARG, "null context");
+  if (!c->prof_on) return fail(LB_ERR_ARG, "profiling not active");
+  c->prof_on = false;
+  hipError_t r = hipStreamSynchronize(c->s);
+  if (r != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(r));
+  double tl = 0.0, tb = 0.0;
+  for (int k = 0; k < c->prof_n; ++k) {
+    float a = 0.f, b = 0.f;
+    r = hipEventElapsedTime(&b, c->ev[4 * (size_t)k], c->ev[4 * (size_t)k + 1]);
+    if (r != hipSuccess) return fail(LB_ERR_DEVICE, "event time: %s", hipGetErrorString(r));
+    r = hipEventElapsedTime(&a, c->ev[4 * (size_t)k + 2], c->ev[4 * (size_t)k + 3]);
+    if (r != hipSuccess) return fail(LB_ERR_DEVICE, "event time: %s", hipGetErrorString(r));
+    tl += a;
+    tb += b;
+  }
+  int n = c->prof_n;
+  if (mean_lb_ms) *mean_lb_ms = n ? tl / n : 0.0;
+  if (mean_bead_ms) *mean_bead_ms = n ? tb / n : 0.0;
+  if (nsteps) *nsteps = n;
+  return take_acc("lb_profile_stop");
+}
 
 int lb_step(lb_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return fail(LB_ERR_ARG, "bad arguments");
   for (int k = 0; k < nsteps; ++k) {
+    prof_mark(c, 0);
+    prof_mark(c, 1);
+    prof_mark(c, 2);
     launch_lb_any(c);
+    prof_mark(c, 3);
     launch_step_end(0, c->base, c->head, c->touched, (uint8_t*)c->b.flags, c->ctrl, 1, c->s);
+    prof_next(c);
   }
   c->steps += nsteps;
   return check_hip("lb_step");
@@ -322,6 +384,7 @@ int md_couple_step(lb_ctx* c, int nsteps) {
   const int nb = c->d.nb;
   uint8_t* flags = (uint8_t*)c->b.flags;
   for (int k = 0; k < nsteps; ++k) {
+    prof_mark(c, 0);
     if (nb > 0) {
       launch_bead_prep(c->bp, c->g, nb, c->head, c->next, c->base, c->s);
       if (c->dev) launch_gather<float, true>(cur_pops(c), flags, c->lp, c->g, c->bp, nb, c->s);
@@ -330,8 +393,12 @@ int md_couple_step(lb_ctx* c, int nsteps) {
       if (c->dev) launch_spread<float>(c->bp, c->g, nb, c->head, c->next, flags, c->b.force, c->touched, c->ctrl, c->s);
       else launch_spread<double>(c->bp, c->g, nb, c->head, c->next, flags, c->b.force, c->touched, c->ctrl, c->s);
     }
+    prof_mark(c, 1);
+    prof_mark(c, 2);
     launch_lb_any(c);
+    prof_mark(c, 3);
     launch_step_end(nb, c->base, c->head, c->touched, flags, c->ctrl, 1, c->s);
+    prof_next(c);
   }
   c->steps += nsteps;
   return check_hip("md_couple_step");

@@ -83,6 +83,8 @@ def _declare(L):
     L.lb_check.argtypes = [P]
     L.lb_step_count.argtypes = [P]
     L.lb_step_count.restype = C.c_int64
+    L.lb_profile_start.argtypes = [P, C.c_int]
+    L.lb_profile_stop.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
 
 
 def _raise(code):
@@ -187,6 +189,15 @@ class Simulation:
 
     def check(self):
         _raise(lib().lb_check(self.ctx))
+
+    def profile_start(self, max_steps):
+        _raise(lib().lb_profile_start(self.ctx, int(max_steps)))
+
+    def profile_stop(self):
+        """Mean LB-sweep and bead-phase durations (ms) of the recorded steps."""
+        a, b, n = C.c_double(), C.c_double(), C.c_int()
+        _raise(lib().lb_profile_stop(self.ctx, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))
