@@ -193,6 +193,11 @@ int64_t lb_step_count(lb_ctx* ctx);
 int lb_profile_start(lb_ctx* ctx, int max_steps);
 int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* nsteps);
 
+/* Diagnostics: synchronises the stream and writes out[0] = neighbour-list
+ * rebuilds, out[1] = MD sub-steps taken, out[2] = nodes carrying bead force
+ * in the last step, out[3] = watchdog bits, out[4] = LB steps taken. */
+int lb_diagnostics(lb_ctx* ctx, int64_t* out);
+
 /* Message of the last failed call on this thread (never NULL). */
 const char* lb_last_error(void);
 

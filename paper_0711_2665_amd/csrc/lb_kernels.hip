@@ -101,16 +101,12 @@ __device__ inline R cdot(int i, R vx, R vy, R vz) {
 
 // ---------------------------------------------------------------------------
 // K1: fused stream + collide (Sec. 2, Eq. (lbe2) as a BGK relaxation with the
-// source S_i = 3 w_i F.c_i).  One thread per node; solid nodes are skipped.
+// source S_i = 3 w_i F.c_i) of one fluid node c.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B,
-                                            const uint8_t* __restrict__ flags, const T* __restrict__ force,
-                                            LbParams p, Ctrl* __restrict__ ctrl) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p.N) return;
-  uint8_t fl = flags[c];
-  if (fl & F_SOLID) return;
+__device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
+                               const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
+                               uint8_t fl) {
   int x = c % p.nx;
   int yz = c / p.nx;
   int y = yz % p.ny;
@@ -175,6 +171,36 @@ __global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restri
   }
 }
 
+// Sweep over all nodes; solid nodes are skipped, and so are nodes carrying a
+// bead force when skip_forced is set (those are updated by k_lb_forced once
+// the force is known).
+template <typename T, bool DEV>
+__global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B,
+                                            const uint8_t* __restrict__ flags, const T* __restrict__ force,
+                                            LbParams p, Ctrl* __restrict__ ctrl, int skip_forced) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= p.N) return;
+  uint8_t fl = flags[c];
+  if (fl & F_SOLID) return;
+  if (skip_forced && (fl & F_FORCED)) return;
+  lb_node<T, DEV>(A, B, flags, force, p, ctrl, c, fl);
+}
+
+// The nodes that carry a bead force this step (the list written by the
+// spreading kernel).
+template <typename T, bool DEV>
+__global__ __launch_bounds__(64) void k_lb_forced(const T* __restrict__ A, T* __restrict__ B,
+                                                  const uint8_t* __restrict__ flags, const T* __restrict__ force,
+                                                  LbParams p, Ctrl* __restrict__ ctrl,
+                                                  const int* __restrict__ touched, int maxlist) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  int nt = (int)ctrl->touched;
+  if (k >= nt || k >= maxlist) return;
+  int c = touched[k];
+  uint8_t fl = flags[c];
+  lb_node<T, DEV>(A, B, flags, force, p, ctrl, c, fl);
+}
+
 // ---------------------------------------------------------------------------
 // Fluid velocity at node c from the pulled populations (zero at solid nodes),
 // accumulated in FP64.
@@ -211,7 +237,7 @@ __device__ inline void node_velocity(const T* __restrict__ A, const uint8_t* __r
 // its base node, clear J.
 // ---------------------------------------------------------------------------
 __global__ void k_bead_prep(BeadPtrs b, Geom g, int nb, int* __restrict__ head, int* __restrict__ next,
-                            int* __restrict__ base) {
+                            int* __restrict__ base, uint8_t* __restrict__ flags) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nb) return;
   double rp[3] = {b.r[3 * p], b.r[3 * p + 1], b.r[3 * p + 2]};
@@ -221,6 +247,13 @@ __global__ void k_bead_prep(BeadPtrs b, Geom g, int nb, int* __restrict__ head, 
   for (int a = 0; a < 3; ++a) { b.rs[3 * p + a] = rp[a]; b.J[3 * p + a] = 0.0; }
   base[p] = cell;
   next[p] = atomicExch(&head[cell], p);
+  // the 8 stencil nodes of r(n) receive bead force this step (solid ones are
+  // dropped by the spreading); every writer of a node stores the same byte
+  for (int k = 0; k < 8; ++k) {
+    int n = (int)corner_node(g, st, k);
+    uint8_t fl = flags[n];
+    if (!(fl & F_SOLID)) flags[n] = fl | F_FORCED;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +333,6 @@ __global__ void k_spread(BeadPtrs b, Geom g, int nb, const int* __restrict__ hea
   force[n] = (T)F[0];
   force[N + n] = (T)F[1];
   force[2 * N + n] = (T)F[2];
-  flags[n] = flags[n] | F_FORCED;
   int slot = atomicAdd(&ctrl->touched, 1u);
   touched[slot] = n;
 }
@@ -457,9 +489,17 @@ void launch_fill_f64(double* p, long n, double v, hipStream_t s) {
 
 template <typename T, bool DEV>
 void launch_lb(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
-               hipStream_t s) {
+               int skip_forced, hipStream_t s) {
   hipLaunchKernelGGL((k_lb<T, DEV>), dim3(blocks_for(p.N, 256)), dim3(256), 0, s, (const T*)A, (T*)B, flags,
-                     (const T*)force, p, ctrl);
+                     (const T*)force, p, ctrl, skip_forced);
+}
+
+template <typename T, bool DEV>
+void launch_lb_forced(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
+                      const int* touched, int maxlist, hipStream_t s) {
+  if (maxlist > 0)
+    hipLaunchKernelGGL((k_lb_forced<T, DEV>), dim3(blocks_for(maxlist, 64)), dim3(64), 0, s, (const T*)A, (T*)B,
+                       flags, (const T*)force, p, ctrl, touched, maxlist);
 }
 
 template <typename T, bool DEV>
@@ -469,8 +509,10 @@ void launch_gather(const void* A, const uint8_t* flags, const LbParams& p, const
     hipLaunchKernelGGL((k_gather<T, DEV>), dim3(blocks_for(nb, 64)), dim3(64), 0, s, (const T*)A, flags, p, g, b, nb);
 }
 
-void launch_bead_prep(const BeadPtrs& b, const Geom& g, int nb, int* head, int* next, int* base, hipStream_t s) {
-  if (nb > 0) hipLaunchKernelGGL(k_bead_prep, dim3(blocks_for(nb, 64)), dim3(64), 0, s, b, g, nb, head, next, base);
+void launch_bead_prep(const BeadPtrs& b, const Geom& g, int nb, int* head, int* next, int* base, uint8_t* flags,
+                      hipStream_t s) {
+  if (nb > 0)
+    hipLaunchKernelGGL(k_bead_prep, dim3(blocks_for(nb, 64)), dim3(64), 0, s, b, g, nb, head, next, base, flags);
 }
 
 template <typename T>
@@ -500,9 +542,13 @@ void launch_observables(const void* A, const uint8_t* flags, long N, double nflu
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);
 template void launch_fill_rest<float, true>(void*, long, hipStream_t);
 template void launch_lb<double, false>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*,
-                                       hipStream_t);
-template void launch_lb<float, true>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*,
+                                       int, hipStream_t);
+template void launch_lb<float, true>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*, int,
                                      hipStream_t);
+template void launch_lb_forced<double, false>(const void*, void*, const uint8_t*, const void*, const LbParams&,
+                                              Ctrl*, const int*, int, hipStream_t);
+template void launch_lb_forced<float, true>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*,
+                                            const int*, int, hipStream_t);
 template void launch_gather<double, false>(const void*, const uint8_t*, const LbParams&, const Geom&, const BeadPtrs&,
                                            int, hipStream_t);
 template void launch_gather<float, true>(const void*, const uint8_t*, const LbParams&, const Geom&, const BeadPtrs&,

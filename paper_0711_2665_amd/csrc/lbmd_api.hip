@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbmd.h"
+#include "lbmd.h"
 #include "lbmd_kernels.h"
 
 using namespace lbmd;
@@ -53,10 +53,13 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int NPARTS = 1024;
 
 struct WorkLayout {
-  size_t ctrl, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, total;
+  size_t ctrl, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part;
+  size_t total;
 };
 
-WorkLayout work_layout(long N, int nb) {
+WorkLayout work_layout(const lb_desc* d) {
+  long N = (long)d->nx * d->ny * d->nz;
+  int nb = d->nb;
   WorkLayout w;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
@@ -157,7 +160,12 @@ struct lb_ctx {
   double* part;
   double nfluid;
   int64_t steps;
+  int64_t last_touched = 0;
   bool dev;
+  // second stream for the sweep over the nodes without bead force, which
+  // runs concurrently with the bead phase; fork/join events
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   // kernel timing (lb_profile_start / lb_profile_stop)
   std::vector<hipEvent_t> ev;   // 4 per recorded step: bead start/end, LB start/end
   int prof_max = 0;
@@ -170,19 +178,33 @@ namespace {
 void* cur_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_a : c->b.pops_b; }
 void* other_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_b : c->b.pops_a; }
 
-// Event slot k of the current recorded step (0, 1: bead phase; 2, 3: sweep).
-void prof_mark(lb_ctx* c, int k) {
+// Event slot k of the current recorded step (0, 1: bead phase; 2, 3: sweep),
+// recorded on stream st.
+void prof_mark(lb_ctx* c, int k, hipStream_t st) {
   if (!c->prof_on || c->prof_n >= c->prof_max) return;
-  acc(hipEventRecord(c->ev[4 * (size_t)c->prof_n + k], c->s));
+  acc(hipEventRecord(c->ev[4 * (size_t)c->prof_n + k], st));
 }
 void prof_next(lb_ctx* c) {
   if (c->prof_on && c->prof_n < c->prof_max) ++c->prof_n;
 }
 
-void launch_lb_any(lb_ctx* c) {
-  if (c->dev) launch_lb<float, true>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl, c->s);
-  else launch_lb<double, false>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl, c->s);
-  c->cur ^= 1;
+void launch_lb_any(lb_ctx* c, int skip_forced, hipStream_t st) {
+  if (c->dev)
+    launch_lb<float, true>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl,
+                           skip_forced, st);
+  else
+    launch_lb<double, false>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl,
+                             skip_forced, st);
+}
+
+void launch_lb_forced_any(lb_ctx* c, hipStream_t st) {
+  int maxlist = 8 * c->d.nb;
+  if (c->dev)
+    launch_lb_forced<float, true>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp,
+                                  c->ctrl, c->touched, maxlist, st);
+  else
+    launch_lb_forced<double, false>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp,
+                                    c->ctrl, c->touched, maxlist, st);
 }
 
 }  // namespace
@@ -190,6 +212,7 @@ void launch_lb_any(lb_ctx* c) {
 extern "C" {
 
 const char* lb_last_error(void) { return g_last_error.c_str(); }
+void lb_destroy(lb_ctx* ctx);
 
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out) {
   int rc = validate(d);
@@ -202,7 +225,7 @@ int lb_buffer_sizes(const lb_desc* d, lb_sizes* out) {
   out->flags_bytes = align256((size_t)N);
   out->force_bytes = align256(es * 3 * (size_t)N);
   out->beads_bytes = align256(sizeof(double) * 15 * nbs);
-  out->work_bytes = work_layout(N, d->nb).total;
+  out->work_bytes = work_layout(d).total;
   out->state_bytes = align256(es * Q * (size_t)N) + align256(sizeof(double) * 6 * nbs) + 256;
   return LB_OK;
 }
@@ -226,6 +249,15 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
   c->d = *d;
   c->b = *b;
   c->s = (hipStream_t)stream;
+  {
+    hipError_t e1 = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
+    hipError_t e2 = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    hipError_t e3 = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      lb_destroy(c);
+      return fail(LB_ERR_DEVICE, "stream/event creation failed");
+    }
+  }
   c->cur = 0;
   c->dev = d->precision == LB_FP32_DEV;
   c->g = make_geom(d);
@@ -255,7 +287,7 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
   double* beads = (double*)b->beads;
   c->bp.r = beads; c->bp.v = beads + 3 * nbs; c->bp.up = beads + 6 * nbs; c->bp.J = beads + 9 * nbs;
   c->bp.rs = beads + 12 * nbs;
-  c->wl = work_layout(N, d->nb);
+  c->wl = work_layout(d);
   char* w = (char*)b->work;
   c->ctrl = (Ctrl*)(w + c->wl.ctrl);
   c->head = (int*)(w + c->wl.head);
@@ -291,7 +323,7 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
   c->nfluid = (double)nfluid;
 
   hipError_t e = hipMemcpyAsync(b->flags, fl.data(), (size_t)N, hipMemcpyHostToDevice, c->s);
-  if (e != hipSuccess) { delete c; return fail(LB_ERR_DEVICE, "flag upload: %s", hipGetErrorString(e)); }
+  if (e != hipSuccess) { lb_destroy(c); return fail(LB_ERR_DEVICE, "flag upload: %s", hipGetErrorString(e)); }
   if (c->dev) {
     launch_fill_rest<float, true>(b->pops_a, N, c->s);
     launch_fill_rest<float, true>(b->pops_b, N, c->s);
@@ -312,16 +344,20 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
     if (v0_host) acc(hipMemcpyAsync(c->bp.v, v0_host, sizeof(double) * 3 * d->nb, hipMemcpyHostToDevice, c->s));
   }
   e = hipStreamSynchronize(c->s);
-  if (e != hipSuccess) { delete c; return fail(LB_ERR_DEVICE, "init: %s", hipGetErrorString(e)); }
+  if (e != hipSuccess) { lb_destroy(c); return fail(LB_ERR_DEVICE, "init: %s", hipGetErrorString(e)); }
   rc = check_hip("init");
-  if (rc) { delete c; return rc; }
+  if (rc) { lb_destroy(c); return rc; }
   *out = c;
   return LB_OK;
 }
 
 void lb_destroy(lb_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->s2) (void)hipStreamSynchronize(ctx->s2);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->join) (void)hipEventDestroy(ctx->join);
+  if (ctx->s2) (void)hipStreamDestroy(ctx->s2);
   delete ctx;
 }
 
@@ -346,6 +382,7 @@ int lb_profile_stop(lb_ctx* c, double* mean_lb_ms, double* mean_bead_ms, int* ns
   if (!c->prof_on) return fail(LB_ERR_ARG, "profiling not active");
   c->prof_on = false;
   hipError_t r = hipStreamSynchronize(c->s);
+  if (r == hipSuccess) r = hipStreamSynchronize(c->s2);
   if (r != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(r));
   double tl = 0.0, tb = 0.0;
   for (int k = 0; k < c->prof_n; ++k) {
@@ -367,12 +404,13 @@ int lb_profile_stop(lb_ctx* c, double* mean_lb_ms, double* mean_bead_ms, int* ns
 int lb_step(lb_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return fail(LB_ERR_ARG, "bad arguments");
   for (int k = 0; k < nsteps; ++k) {
-    prof_mark(c, 0);
-    prof_mark(c, 1);
-    prof_mark(c, 2);
-    launch_lb_any(c);
-    prof_mark(c, 3);
+    prof_mark(c, 0, c->s);
+    prof_mark(c, 1, c->s);
+    prof_mark(c, 2, c->s);
+    launch_lb_any(c, 0, c->s);
+    prof_mark(c, 3, c->s);
     launch_step_end(0, c->base, c->head, c->touched, (uint8_t*)c->b.flags, c->ctrl, 1, c->s);
+    c->cur ^= 1;
     prof_next(c);
   }
   c->steps += nsteps;
@@ -384,20 +422,34 @@ int md_couple_step(lb_ctx* c, int nsteps) {
   const int nb = c->d.nb;
   uint8_t* flags = (uint8_t*)c->b.flags;
   for (int k = 0; k < nsteps; ++k) {
-    prof_mark(c, 0);
-    if (nb > 0) {
-      launch_bead_prep(c->bp, c->g, nb, c->head, c->next, c->base, c->s);
+    if (nb == 0) {
+      prof_mark(c, 0, c->s);
+      prof_mark(c, 1, c->s);
+      prof_mark(c, 2, c->s);
+      launch_lb_any(c, 0, c->s);
+      prof_mark(c, 3, c->s);
+    } else {
+      // the stencil nodes of r(n) are marked first; the sweep over all other
+      // nodes then runs on the second stream while the beads move
+      prof_mark(c, 0, c->s);
+      launch_bead_prep(c->bp, c->g, nb, c->head, c->next, c->base, flags, c->s);
+      acc(hipEventRecord(c->fork, c->s));
+      acc(hipStreamWaitEvent(c->s2, c->fork, 0));
+      prof_mark(c, 2, c->s2);
+      launch_lb_any(c, 1, c->s2);
+      prof_mark(c, 3, c->s2);
+      acc(hipEventRecord(c->join, c->s2));
       if (c->dev) launch_gather<float, true>(cur_pops(c), flags, c->lp, c->g, c->bp, nb, c->s);
       else launch_gather<double, false>(cur_pops(c), flags, c->lp, c->g, c->bp, nb, c->s);
       launch_md_cycle(c->bp, c->mw, c->mp, c->g, c->ctrl, c->d.n_sub, c->s);
       if (c->dev) launch_spread<float>(c->bp, c->g, nb, c->head, c->next, flags, c->b.force, c->touched, c->ctrl, c->s);
       else launch_spread<double>(c->bp, c->g, nb, c->head, c->next, flags, c->b.force, c->touched, c->ctrl, c->s);
+      launch_lb_forced_any(c, c->s);
+      prof_mark(c, 1, c->s);
+      acc(hipStreamWaitEvent(c->s, c->join, 0));
     }
-    prof_mark(c, 1);
-    prof_mark(c, 2);
-    launch_lb_any(c);
-    prof_mark(c, 3);
     launch_step_end(nb, c->base, c->head, c->touched, flags, c->ctrl, 1, c->s);
+    c->cur ^= 1;
     prof_next(c);
   }
   c->steps += nsteps;
@@ -480,6 +532,7 @@ void* lb_current_pops(lb_ctx* c) { return c ? cur_pops(c) : nullptr; }
 int lb_check(lb_ctx* c) {
   if (!c) return fail(LB_ERR_ARG, "null context");
   hipError_t e = hipStreamSynchronize(c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s2);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(e));
   uint32_t err = 0;
   e = hipMemcpy(&err, &c->ctrl->err, sizeof(err), hipMemcpyDeviceToHost);
@@ -496,5 +549,20 @@ int lb_check(lb_ctx* c) {
 }
 
 int64_t lb_step_count(lb_ctx* c) { return c ? c->steps : -1; }
+
+int lb_diagnostics(lb_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(LB_ERR_ARG, "bad arguments");
+  hipError_t e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(e));
+  Ctrl h;
+  e = hipMemcpy(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(LB_ERR_DEVICE, "diagnostics read: %s", hipGetErrorString(e));
+  out[0] = (int64_t)h.rebuilds;
+  out[1] = (int64_t)h.substeps;
+  out[2] = (int64_t)c->last_touched;
+  out[3] = (int64_t)h.err;
+  out[4] = (int64_t)h.step;
+  return LB_OK;
+}
 
 }  // extern "C"

@@ -52,8 +52,8 @@ struct Ctrl {
   uint32_t err;
   uint32_t touched;          // nodes with the forced bit set this step
   uint64_t step;             // LB steps taken (Philox counter word 0)
-  uint64_t rebuild_at;       // global sub-step index at which lists are rebuilt
-  uint64_t substep;          // global sub-step counter of the MD integrator
+  uint64_t rebuilds;         // neighbour-list rebuilds so far (diagnostic)
+  uint64_t substeps;         // MD sub-steps so far (diagnostic)
   uint32_t pad[56];
 };
 
@@ -86,9 +86,13 @@ __host__ __device__ inline bool site_solid(const Geom& g, int sx, int sy, int sz
   return !pore;
 }
 
-// Wrap an unwrapped coordinate into [0, n).
+// Wrap an unwrapped coordinate into [0, n): w = x - n floor(x / n), reduced
+// once more if rounding lands on n.  For 0 <= x < n - 1 the quotient is
+// certainly in [0, 1) so the result is x itself; that case skips the
+// division and returns the same bits.
 __device__ inline double wrapc(double x, int n) {
   double dn = (double)n;
+  if (x >= 0.0 && x < dn - 1.0) return x;
   double q = floor(x / dn);
   double w = x - dn * q;
   if (w >= dn) w = w - dn;
@@ -193,34 +197,13 @@ __device__ inline void lj_add(const MdParams& P, double d0, double d1, double d2
   F[0] += coef * d0; F[1] += coef * d1; F[2] += coef * d2;
 }
 
+// Minimum image d - n floor(d / n + 1/2).  For |d| < n/4 the floor is 0 and
+// the result is d itself; that case skips the division, same bits.
 __device__ inline double min_image(double d, int n) {
   double dn = (double)n;
+  if (fabs(d) < 0.25 * dn) return d;
   double k = floor(d / dn + 0.5);
   return d - dn * k;
-}
-
-// LJ between bead p (position rp) and every solid site within r_c.  r_c < 2,
-// so the sites at offsets -1..2 from the base node cover all candidates;
-// they are visited z outer, x inner; only the wall plane holds solid sites.
-__device__ inline void wall_add(const MdParams& P, const Geom& g, const double* rp, double F[3]) {
-  if (g.wall_axis < 0) return;
-  double w[3] = {wrapc(rp[0], g.nx), wrapc(rp[1], g.ny), wrapc(rp[2], g.nz)};
-  int b[3] = {(int)floor(w[0]), (int)floor(w[1]), (int)floor(w[2])};
-  int a = g.wall_axis;
-  int na = ext(g, a);
-  // offsets o along the wall axis with (b + o) mod n == wall_pos
-  for (int oz = -1; oz <= 2; ++oz) {
-    if (a == 2) { int s = (b[2] + oz + na) % na; if (s != g.wall_pos) continue; }
-    for (int oy = -1; oy <= 2; ++oy) {
-      if (a == 1) { int s = (b[1] + oy + na) % na; if (s != g.wall_pos) continue; }
-      for (int ox = -1; ox <= 2; ++ox) {
-        if (a == 0) { int s = (b[0] + ox + na) % na; if (s != g.wall_pos) continue; }
-        int sx = b[0] + ox, sy = b[1] + oy, sz = b[2] + oz;
-        if (!site_solid(g, sx, sy, sz)) continue;
-        lj_add(P, w[0] - (double)sx, w[1] - (double)sy, w[2] - (double)sz, F);
-      }
-    }
-  }
 }
 
 // Pore channel: [wall - 1.5, wall + 1.5) along the normal times

@@ -34,11 +34,15 @@ void launch_fill_i32(int* p, long n, int v, hipStream_t s);
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
 template <typename T, bool DEV>
 void launch_lb(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
-               hipStream_t s);
+               int skip_forced, hipStream_t s);
+template <typename T, bool DEV>
+void launch_lb_forced(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
+                      const int* touched, int maxlist, hipStream_t s);
 template <typename T, bool DEV>
 void launch_gather(const void* A, const uint8_t* flags, const LbParams& p, const Geom& g, const BeadPtrs& b, int nb,
                    hipStream_t s);
-void launch_bead_prep(const BeadPtrs& b, const Geom& g, int nb, int* head, int* next, int* base, hipStream_t s);
+void launch_bead_prep(const BeadPtrs& b, const Geom& g, int nb, int* head, int* next, int* base, uint8_t* flags,
+                      hipStream_t s);
 template <typename T>
 void launch_spread(const BeadPtrs& b, const Geom& g, int nb, const int* head, const int* next, uint8_t* flags,
                    void* force, int* touched, Ctrl* ctrl, hipStream_t s);

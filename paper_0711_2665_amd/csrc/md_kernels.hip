@@ -1,8 +1,8 @@
 // md_kernels.hip -- the bead sub-cycle: stochastic position Verlet sub-steps
 // (Sec. 2, Eq. (SPValgo), no constraints) with the fluid velocity at each
-// bead frozen for the whole cycle.  One launch per sub-step, one thread per
-// bead; the positions at which forces are evaluated are double buffered so
-// that every bead reads a consistent snapshot.
+// bead frozen for the whole cycle.  One launch per sub-step; the positions
+// at which forces are evaluated are double buffered so that every bead reads
+// a consistent snapshot.
 //
 // Per sub-step s (h = 1/n_sub, e = exp(-gamma h)):
 //   r_mid = r + h/2 v                      (written by the previous launch)
@@ -15,9 +15,9 @@
 //
 // The LJ sum runs over a Verlet neighbour list (radius r_c + skin) kept in
 // ascending bead order, so it adds exactly the terms of the all-pairs loop
-// in the same order.  A list is rebuilt (by a scan over all beads) in the
-// launch after any bead has moved more than skin/2 since the last build; the
-// flag is carried between launches in three rotating words.
+// in the same order.  A list is rebuilt in the launch after any bead has
+// moved more than skin/2 since the last build; the flag is carried between
+// launches in three rotating words.
 #include "lbmd_kernels.h"
 
 namespace lbmd {
@@ -49,72 +49,251 @@ __global__ void k_md_start(BeadPtrs b, MdWork w, MdParams P) {
   if (d2 > P.halfskin2) w.rb[0] = 1u;
 }
 
-__device__ inline void rebuild_list(const double* __restrict__ rin, const MdParams& P, const Geom& g, int p,
-                                    const double rp[3], int* __restrict__ nbr, int* __restrict__ ncnt,
-                                    Ctrl* __restrict__ ctrl) {
-  int cnt = 0;
-  for (int j = 0; j < P.nb; ++j) {
-    if (j == p) continue;
-    double d0 = min_image(rp[0] - rin[3 * j], g.nx);
-    double d1 = min_image(rp[1] - rin[3 * j + 1], g.ny);
-    double d2 = min_image(rp[2] - rin[3 * j + 2], g.nz);
-    if (d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2) {
-      if (cnt < MAXNBR) nbr[(size_t)p * MAXNBR + cnt] = j;
-      ++cnt;
+// Bending forces of the angles centred at q = q0 .. q0 + nq - 1 (those with
+// 1 <= q <= nb - 2), one angle per thread, into LDS: ang[q - q0][0..2] force
+// on q-1, [3..5] on q, [6..8] on q+1.  Each angle is evaluated once and read
+// by its three beads; the values are those a per-bead evaluation gives.
+__device__ inline void angles_to_lds(const double* __restrict__ rin, const MdParams& P, int q0, int nq,
+                                     double (*ang)[9]) {
+  for (int k = threadIdx.x; k < nq; k += blockDim.x) {
+    int q = q0 + k;
+    if (q < 1 || q > P.nb - 2) continue;
+    const double* ra = &rin[3 * (q - 1)];
+    const double* rb = &rin[3 * q];
+    const double* rc = &rin[3 * (q + 1)];
+    double Fm[3] = {0.0, 0.0, 0.0}, F0[3] = {0.0, 0.0, 0.0}, Fp[3] = {0.0, 0.0, 0.0};
+    angle_add(P, ra, rb, rc, 0, Fm);
+    angle_add(P, ra, rb, rc, 1, F0);
+    angle_add(P, ra, rb, rc, 2, Fp);
+    for (int a = 0; a < 3; ++a) { ang[k][a] = Fm[a]; ang[k][3 + a] = F0[a]; ang[k][6 + a] = Fp[a]; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sub-step kernel.  A workgroup of 64 lanes holds 16 consecutive beads, 4
+// lanes per bead.  The lanes of a bead evaluate its LJ pair forces in
+// parallel (and, on two of them, the wall sites and the noise) into LDS;
+// one lane then adds every contribution in the fixed order of the
+// definition (bonds to p-1 and p+1, the angles centred at p-1, p, p+1, LJ in
+// ascending partner order, wall sites, field), so the sum is the same as a
+// one-thread-per-bead loop.
+// ---------------------------------------------------------------------------
+constexpr int MD_LANES = 4;
+constexpr int MD_BPB = 16;                   // beads per workgroup
+constexpr int MD_WG = MD_LANES * MD_BPB;     // 64
+constexpr int MAXWALL = 16;                  // solid sites within r_c of a bead (4 x 4 window)
+constexpr int NB_PER_LANE = MAXNBR / MD_LANES;
+
+struct MdShared {
+  double ang[MD_BPB + 2][9];                 // angle forces (see angles_to_lds)
+  double pairF[MD_BPB][MAXNBR][3];           // LJ pair force of list entry k
+  uint32_t hit[MD_BPB][MD_LANES];            // lane l, bit m: entry l + 4m is within r_c
+  double wallF[MD_BPB][MAXWALL][3];
+  int nwall[MD_BPB];
+  double xi[MD_BPB][3];
+  int cnt[MD_BPB];
+  int lst[MD_BPB][MAXNBR];                   // the neighbour list in use
+  double tile[MD_WG][3];                     // rebuild: positions of 64 candidates
+  uint32_t tmask[MD_BPB][MD_LANES];          // rebuild: lane l, bit e: candidate 16 l + e is close
+  int over;
+};
+
+// Wall sites of the bead at rp as force vectors (each the truncated-LJ pair
+// force of one solid site within r_c), in the order z outer, x inner over the
+// sites at offsets -1..2 from the base node.  r_c < 2 makes that window
+// cover every candidate.  Solid sites lie in the plane a = wall_pos (minus
+// the pore), so at most one offset along the wall normal can match; the
+// transverse window is then visited with the higher-index axis outer.
+// Wrapping uses compares only (the window is within one period).
+__device__ inline int wall_sites(const MdParams& P, const Geom& g, const double* rp, double out[][3]) {
+  if (g.wall_axis < 0) return 0;
+  const double w0 = wrapc(rp[0], g.nx), w1 = wrapc(rp[1], g.ny), w2 = wrapc(rp[2], g.nz);
+  const int b0 = (int)floor(w0), b1 = (int)floor(w1), b2 = (int)floor(w2);
+  const int a = g.wall_axis;
+  // normal-axis base and extent; transverse axes t0 < t1
+  const int ba = a == 0 ? b0 : (a == 1 ? b1 : b2);
+  const int na = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+  const int bt0 = a == 0 ? b1 : b0, n0 = a == 0 ? g.ny : g.nx;
+  const int bt1 = a == 2 ? b1 : b2, n1 = a == 2 ? g.ny : g.nz;
+  int off = g.wall_pos - ba;                // offset along the normal reaching the plane
+  if (off < -1) off += na;
+  if (off > 2) off -= na;
+  if (off < -1 || off > 2) return 0;
+  const int sa = ba + off;
+  int n = 0;
+  for (int o1 = -1; o1 <= 2; ++o1) {
+    const int u1 = bt1 + o1;
+    const int v1 = u1 < 0 ? u1 + n1 : (u1 >= n1 ? u1 - n1 : u1);
+    const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
+    for (int o0 = -1; o0 <= 2; ++o0) {
+      const int u0 = bt0 + o0;
+      const int v0 = u0 < 0 ? u0 + n0 : (u0 >= n0 ? u0 - n0 : u0);
+      const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
+      if (in0 && in1) continue;             // pore node: fluid
+      const int sx = a == 0 ? sa : u0;
+      const int sy = a == 1 ? sa : (a == 0 ? u0 : u1);
+      const int sz = a == 2 ? sa : u1;
+      const double d0 = w0 - (double)sx, d1 = w1 - (double)sy, d2 = w2 - (double)sz;
+      if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
+      double F[3] = {0.0, 0.0, 0.0};
+      lj_add(P, d0, d1, d2, F);
+      if (n < MAXWALL) { out[n][0] = F[0]; out[n][1] = F[1]; out[n][2] = F[2]; }
+      ++n;
     }
   }
-  if (cnt > MAXNBR) { atomicOr(&ctrl->err, E_NBRLIST); cnt = MAXNBR; }
-  ncnt[p] = cnt;
+  return n;
 }
 
-// Conservative force on bead p at positions rin, in a fixed order: bonds to
-// p-1 and p+1, bending angles centred at p-1, p, p+1, LJ over the neighbour
-// list, wall sites, field.
-__device__ inline void bead_force(const double* __restrict__ rin, const MdParams& P, const Geom& g, int p,
-                                  const double rp[3], const int* __restrict__ nbr, int cnt, double F[3]) {
-  F[0] = 0.0; F[1] = 0.0; F[2] = 0.0;
-  const int nb = P.nb;
-  if (p > 0) bond_add(P, rp, &rin[3 * (p - 1)], F);
-  if (p < nb - 1) bond_add(P, rp, &rin[3 * (p + 1)], F);
-  if (p - 1 >= 1 && p - 1 <= nb - 2) angle_add(P, &rin[3 * (p - 2)], &rin[3 * (p - 1)], rp, 2, F);
-  if (p >= 1 && p <= nb - 2) angle_add(P, &rin[3 * (p - 1)], rp, &rin[3 * (p + 1)], 1, F);
-  if (p + 1 >= 1 && p + 1 <= nb - 2) angle_add(P, rp, &rin[3 * (p + 1)], &rin[3 * (p + 2)], 0, F);
-  for (int k = 0; k < cnt; ++k) {
-    int j = nbr[(size_t)p * MAXNBR + k];
-    double d0 = min_image(rp[0] - rin[3 * j], g.nx);
-    double d1 = min_image(rp[1] - rin[3 * j + 1], g.ny);
-    double d2 = min_image(rp[2] - rin[3 * j + 2], g.nz);
-    lj_add(P, d0, d1, d2, F);
-  }
-  wall_add(P, g, rp, F);
-  if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
-}
-
-__global__ __launch_bounds__(256) void k_md_substep(BeadPtrs b, MdWork w, MdParams P, Geom g,
-                                                    Ctrl* __restrict__ ctrl, int s, int last) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) w.rb[(s + 2) % 3] = 0u;
-  if (p >= P.nb) return;
+__global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdParams P, Geom g,
+                                                      Ctrl* __restrict__ ctrl, int s, int last) {
+  __shared__ MdShared sh;
+  const int t = threadIdx.x;
+  const int slot = t / MD_LANES, lane = t % MD_LANES;
+  const int p0 = blockIdx.x * MD_BPB;
+  const int p = p0 + slot;
+  const bool active = p < P.nb;
   const double* rin = (s & 1) ? w.rmid1 : w.rmid0;
   double* rout = (s & 1) ? w.rmid0 : w.rmid1;
-  double rp[3] = {rin[3 * p], rin[3 * p + 1], rin[3 * p + 2]};
-  if (w.rb[s % 3]) {
-    rebuild_list(rin, P, g, p, rp, w.nbr, w.ncnt, ctrl);
-    w.ref[3 * p] = rp[0]; w.ref[3 * p + 1] = rp[1]; w.ref[3 * p + 2] = rp[2];
+  const uint32_t rebuild = w.rb[s % 3];
+  if (blockIdx.x == 0 && t == 0) {
+    w.rb[(s + 2) % 3] = 0u;
+    ctrl->substeps += 1;
+    if (rebuild) ctrl->rebuilds += 1;
   }
-  double F[3];
-  bead_force(rin, P, g, p, rp, w.nbr, w.ncnt[p], F);
-  double xi[3] = {0.0, 0.0, 0.0};
-  if (P.sig != 0.0) gauss3(P.seed, P.replica, (uint32_t)ctrl->step, (uint32_t)s, (uint32_t)p, xi);
+  double rp[3] = {0.0, 0.0, 0.0};
+  if (active) { rp[0] = rin[3 * p]; rp[1] = rin[3 * p + 1]; rp[2] = rin[3 * p + 2]; }
+  if (t == 0) sh.over = 0;
+  angles_to_lds(rin, P, p0 - 1, MD_BPB + 2, sh.ang);
+
+  // ---- neighbour list: reuse, or rebuild by scanning all beads in tiles of 64
+  if (!rebuild) {
+    if (active && lane == 0) sh.cnt[slot] = w.ncnt[p];
+    __syncthreads();
+    int c = active ? sh.cnt[slot] : 0;
+    for (int k = lane; k < c; k += MD_LANES) sh.lst[slot][k] = w.nbr[(size_t)p * MAXNBR + k];
+  } else {
+    if (lane == 0) sh.cnt[slot] = 0;
+    for (int base = 0; base < P.nb; base += MD_WG) {
+      __syncthreads();
+      int j = base + t;
+      if (j < P.nb) { sh.tile[t][0] = rin[3 * j]; sh.tile[t][1] = rin[3 * j + 1]; sh.tile[t][2] = rin[3 * j + 2]; }
+      __syncthreads();
+      uint32_t m = 0;
+      if (active) {
+        for (int e = 0; e < 16; ++e) {
+          int tt = 16 * lane + e;
+          int jj = base + tt;
+          if (jj >= P.nb || jj == p) continue;
+          double d0 = min_image(rp[0] - sh.tile[tt][0], g.nx);
+          double d1 = min_image(rp[1] - sh.tile[tt][1], g.ny);
+          double d2 = min_image(rp[2] - sh.tile[tt][2], g.nz);
+          if (d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2) m |= 1u << e;
+        }
+      }
+      sh.tmask[slot][lane] = m;
+      __syncthreads();
+      if (active && lane == 0) {
+        uint64_t mm = (uint64_t)sh.tmask[slot][0] | ((uint64_t)sh.tmask[slot][1] << 16) |
+                      ((uint64_t)sh.tmask[slot][2] << 32) | ((uint64_t)sh.tmask[slot][3] << 48);
+        int c = sh.cnt[slot];
+        while (mm) {
+          int tt = __builtin_ctzll(mm);
+          mm &= mm - 1;
+          if (c < MAXNBR) sh.lst[slot][c] = base + tt;
+          else sh.over = 1;
+          ++c;
+        }
+        sh.cnt[slot] = c;
+      }
+    }
+    __syncthreads();
+    if (active && lane == 0) {
+      int c = sh.cnt[slot];
+      if (c > MAXNBR) { c = MAXNBR; sh.cnt[slot] = c; }
+      w.ncnt[p] = c;
+      w.ref[3 * p] = rp[0]; w.ref[3 * p + 1] = rp[1]; w.ref[3 * p + 2] = rp[2];
+    }
+    __syncthreads();
+    int c = active ? sh.cnt[slot] : 0;
+    for (int k = lane; k < c; k += MD_LANES) w.nbr[(size_t)p * MAXNBR + k] = sh.lst[slot][k];
+    if (t == 0 && sh.over) atomicOr(&ctrl->err, E_NBRLIST);
+  }
+  __syncthreads();
+
+  // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
+  const int cnt = active ? sh.cnt[slot] : 0;
+  {
+    int jl[NB_PER_LANE];
+#pragma unroll
+    for (int m = 0; m < NB_PER_LANE; ++m) {
+      int k = lane + MD_LANES * m;
+      jl[m] = (k < cnt) ? sh.lst[slot][k] : -1;
+    }
+    double q[NB_PER_LANE][3];
+#pragma unroll
+    for (int m = 0; m < NB_PER_LANE; ++m) {
+      if (jl[m] >= 0) { q[m][0] = rin[3 * jl[m]]; q[m][1] = rin[3 * jl[m] + 1]; q[m][2] = rin[3 * jl[m] + 2]; }
+      else { q[m][0] = 0.0; q[m][1] = 0.0; q[m][2] = 0.0; }
+    }
+    uint32_t hit = 0;
+#pragma unroll
+    for (int m = 0; m < NB_PER_LANE; ++m) {
+      if (jl[m] < 0) continue;
+      double d0 = min_image(rp[0] - q[m][0], g.nx);
+      double d1 = min_image(rp[1] - q[m][1], g.ny);
+      double d2 = min_image(rp[2] - q[m][2], g.nz);
+      if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
+      double F[3] = {0.0, 0.0, 0.0};
+      lj_add(P, d0, d1, d2, F);
+      int k = lane + MD_LANES * m;
+      sh.pairF[slot][k][0] = F[0]; sh.pairF[slot][k][1] = F[1]; sh.pairF[slot][k][2] = F[2];
+      hit |= 1u << m;
+    }
+    sh.hit[slot][lane] = hit;
+  }
+  // ---- wall sites (lane 1) and noise (lane 2)
+  if (active && lane == 1) sh.nwall[slot] = wall_sites(P, g, rp, sh.wallF[slot]);
+  if (active && lane == 2) {
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (P.sig != 0.0) gauss3(P.seed, P.replica, (uint32_t)ctrl->step, (uint32_t)s, (uint32_t)p, xi);
+    sh.xi[slot][0] = xi[0]; sh.xi[slot][1] = xi[1]; sh.xi[slot][2] = xi[2];
+  }
+  // ---- lane 0: bonds now, then every contribution in the fixed order
+  double F[3] = {0.0, 0.0, 0.0};
+  double vo[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0}, Jo[3] = {0.0, 0.0, 0.0};
+  if (active && lane == 0) {
+    if (p > 0) bond_add(P, rp, &rin[3 * (p - 1)], F);
+    if (p < P.nb - 1) bond_add(P, rp, &rin[3 * (p + 1)], F);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vo[a] = b.v[3 * p + a];
+      Jo[a] = b.J[3 * p + a];
+      u[a] = P.couple ? b.up[3 * p + a] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (!(active && lane == 0)) return;
+  const int q0 = p0 - 1;
+  const int nb = P.nb;
+  if (p - 1 >= 1 && p - 1 <= nb - 2) { const double* A = sh.ang[p - 1 - q0]; F[0] += A[6]; F[1] += A[7]; F[2] += A[8]; }
+  if (p >= 1 && p <= nb - 2) { const double* A = sh.ang[p - q0]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
+  if (p + 1 >= 1 && p + 1 <= nb - 2) { const double* A = sh.ang[p + 1 - q0]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2]; }
+  for (int k = 0; k < cnt; ++k) {
+    if (!((sh.hit[slot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
+    F[0] += sh.pairF[slot][k][0]; F[1] += sh.pairF[slot][k][1]; F[2] += sh.pairF[slot][k][2];
+  }
+  int nw = sh.nwall[slot];
+  if (nw > MAXWALL) { atomicOr(&ctrl->err, E_NBRLIST); nw = MAXWALL; }
+  for (int k = 0; k < nw; ++k) { F[0] += sh.wallF[slot][k][0]; F[1] += sh.wallF[slot][k][1]; F[2] += sh.wallF[slot][k][2]; }
+  if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
+
   double vn[3];
   bool finite = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double u = P.couple ? b.up[3 * p + a] : 0.0;
-    double vold = b.v[3 * p + a];
-    double sx = P.sig * xi[a];
-    vn[a] = P.e * vold + P.cf * (F[a] + P.gamma * u) + sx;
-    b.J[3 * p + a] = b.J[3 * p + a] - P.m * (P.omE * (u - vold) + sx);
+    double sx = P.sig * sh.xi[slot][a];
+    vn[a] = P.e * vo[a] + P.cf * (F[a] + P.gamma * u[a]) + sx;
+    b.J[3 * p + a] = Jo[a] - P.m * (P.omE * (u[a] - vo[a]) + sx);
     b.v[3 * p + a] = vn[a];
     finite = finite && isfinite(vn[a]);
   }
@@ -147,11 +326,11 @@ void launch_md_invalidate(const MdWork& w, hipStream_t s) {
 void launch_md_cycle(const BeadPtrs& b, const MdWork& w, const MdParams& P, const Geom& g, Ctrl* ctrl, int n_sub,
                      hipStream_t s) {
   if (P.nb <= 0 || n_sub <= 0) return;
-  unsigned nblk = (unsigned)((P.nb + 255) / 256);
+  unsigned nblk = (unsigned)((P.nb + MD_BPB - 1) / MD_BPB);
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(1), 0, s, w.rb);
-  hipLaunchKernelGGL(k_md_start, dim3(nblk), dim3(256), 0, s, b, w, P);
+  hipLaunchKernelGGL(k_md_start, dim3((P.nb + 255) / 256), dim3(256), 0, s, b, w, P);
   for (int k = 0; k < n_sub; ++k)
-    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(256), 0, s, b, w, P, g, ctrl, k, k == n_sub - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, b, w, P, g, ctrl, k, k == n_sub - 1 ? 1 : 0);
 }
 
 void launch_zero_v(double* v, int nb, hipStream_t s) {

@@ -83,6 +83,7 @@ def _declare(L):
     L.lb_check.argtypes = [P]
     L.lb_step_count.argtypes = [P]
     L.lb_step_count.restype = C.c_int64
+    L.lb_diagnostics.argtypes = [P, C.POINTER(C.c_int64)]
     L.lb_profile_start.argtypes = [P, C.c_int]
     L.lb_profile_stop.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
 
@@ -165,17 +166,23 @@ class Simulation:
             _raise(lib().lb_init(C.byref(self.desc), C.byref(b), rp, vp, C.c_void_p(self.stream.cuda_stream),
                                  C.byref(ctx)))
         self.ctx = ctx
+        self._destroy = lib().lb_destroy      # kept for teardown at interpreter exit
         self._obs = torch.empty(LB_NOBS, dtype=torch.float64, device=self.device)
 
-    def __del__(self):
+    def close(self):
+        """Synchronise and release the library context (the buffers are freed
+        with this object)."""
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
             try:
                 self.stream.synchronize()
             except Exception:
                 pass
-            lib().lb_destroy(ctx)
+            self._destroy(ctx)
             self.ctx = None
+
+    def __del__(self):
+        self.close()
 
     # -- stepping ------------------------------------------------------------
     def lb_step(self, n=1):
@@ -198,6 +205,11 @@ class Simulation:
         a, b, n = C.c_double(), C.c_double(), C.c_int()
         _raise(lib().lb_profile_stop(self.ctx, C.byref(a), C.byref(b), C.byref(n)))
         return a.value, b.value, n.value
+
+    def diagnostics(self):
+        out = (C.c_int64 * 5)()
+        _raise(lib().lb_diagnostics(self.ctx, out))
+        return dict(zip(("rebuilds", "substeps", "forced_nodes", "watchdog", "steps"), list(out)))
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))
