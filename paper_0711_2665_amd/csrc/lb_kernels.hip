@@ -47,17 +47,35 @@ __device__ inline Nbr make_nbr(const LbParams& p, int x, int y, int z) {
   return n;
 }
 
+// Population store of the sweep: written once per step and read only in the
+// next step, so it bypasses the caches (non-temporal).
+template <typename T>
+__device__ inline void store_pop(T* ptr, T v) {
+  __builtin_nontemporal_store(v, ptr);
+}
+
 // Post-streaming populations at node c: f_i(x) = A_i(x - c_i), or
-// A_opp(i)(x) when x - c_i is solid (halfway bounce-back).
+// A_opp(i)(x) when x - c_i is solid (halfway bounce-back).  Nodes away from
+// walls take a straight run of 19 independent loads; next to a wall the 19
+// upstream flags are loaded first and the addresses selected without
+// branches, so the population loads are again issued together.
 template <typename T>
 __device__ inline void pull(const T* __restrict__ A, const uint8_t* __restrict__ flags, const LbParams& p, int c,
                             uint8_t fl, const Nbr& nb, T f[Q]) {
   const size_t N = (size_t)p.N;
+  if (!(fl & F_NEAR)) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    int src = c + nb.off(-cx(i), -cy(i), -cz(i));
-    bool bb = (fl & F_NEAR) && (flags[src] & F_SOLID);
-    f[i] = bb ? A[(size_t)opp(i) * N + c] : A[(size_t)i * N + src];
+    for (int i = 0; i < Q; ++i) f[i] = A[(size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)))];
+  } else {
+    uint8_t sf[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) sf[i] = flags[c + nb.off(-cx(i), -cy(i), -cz(i))];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      size_t src = (size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)));
+      size_t ref = (size_t)opp(i) * N + (size_t)c;
+      f[i] = A[(sf[i] & F_SOLID) ? ref : src];
+    }
   }
 }
 
@@ -103,19 +121,12 @@ __device__ inline R cdot(int i, R vx, R vy, R vz) {
 // K1: fused stream + collide (Sec. 2, Eq. (lbe2) as a BGK relaxation with the
 // source S_i = 3 w_i F.c_i) of one fluid node c.
 // ---------------------------------------------------------------------------
+// BGK collision with the source term of one fluid node (index c, flags fl)
+// from its post-streaming populations f; writes f* to out.
 template <typename T, bool DEV>
-__device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
-                               const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
-                               uint8_t fl) {
-  int x = c % p.nx;
-  int yz = c / p.nx;
-  int y = yz % p.ny;
-  int z = yz / p.ny;
-  Nbr nb = make_nbr(p, x, y, z);
-  T f[Q];
-  pull<T>(A, flags, p, c, fl, nb, f);
+__device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict__ force, const LbParams& p,
+                                    Ctrl* __restrict__ ctrl, int c, uint8_t fl) {
   const size_t N = (size_t)p.N;
-
   if constexpr (!DEV) {
     // FP64: f* = f - omega (f - f^eq) + 3 w_i (F + g).c_i, f^eq =
     // w_i rho (1 + 3 cu + 4.5 cu^2 - 1.5 u.u)
@@ -134,7 +145,7 @@ __device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const
       double cu = cdot<double>(i, ux, uy, uz);
       double fe = wgt(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
       double src = (3.0 * wgt(i)) * cdot<double>(i, Fx, Fy, Fz);
-      B[(size_t)i * N + c] = (T)(f[i] - p.omega * (f[i] - fe) + src);
+      out[i] = (T)(f[i] - p.omega * (f[i] - fe) + src);
     }
   } else {
     // FP32 deviation storage: g_i = f_i - w_i; drho = sum g, j = sum g c;
@@ -164,11 +175,36 @@ __device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const
       float cu = cdot<float>(i, ux, uy, uz);
       float w = (float)wgt(i);
       float ge = w * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * usq));
-      float out = (float)f[i] - om * ((float)f[i] - ge);
-      if (src_on) out += (3.f * w) * cdot<float>(i, Fx, Fy, Fz);
-      B[(size_t)i * N + c] = (T)out;
+      float o = (float)f[i] - om * ((float)f[i] - ge);
+      if (src_on) o += (3.f * w) * cdot<float>(i, Fx, Fy, Fz);
+      out[i] = (T)o;
     }
   }
+}
+
+// Stream + collide one fluid node at (x, y, z), index c.
+template <typename T, bool DEV>
+__device__ inline void lb_node_xyz(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
+                                   const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
+                                   uint8_t fl, int x, int y, int z) {
+  Nbr nb = make_nbr(p, x, y, z);
+  T f[Q];
+  pull<T>(A, flags, p, c, fl, nb, f);
+  collide_node<T, DEV>(f, f, force, p, ctrl, c, fl);
+  const size_t N = (size_t)p.N;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c], f[i]);
+}
+
+template <typename T, bool DEV>
+__device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
+                               const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
+                               uint8_t fl) {
+  int x = c % p.nx;
+  int yz = c / p.nx;
+  int y = yz % p.ny;
+  int z = yz / p.ny;
+  lb_node_xyz<T, DEV>(A, B, flags, force, p, ctrl, c, fl, x, y, z);
 }
 
 // Sweep over all nodes; solid nodes are skipped, and so are nodes carrying a

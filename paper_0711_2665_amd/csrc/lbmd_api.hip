@@ -53,7 +53,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int NPARTS = 1024;
 
 struct WorkLayout {
-  size_t ctrl, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part;
+  size_t ctrl, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi;
   size_t total;
 };
 
@@ -76,6 +76,7 @@ WorkLayout work_layout(const lb_desc* d) {
   w.rmid1 = take(sizeof(double) * 3 * nbs);
   w.ref = take(sizeof(double) * 3 * nbs);
   w.part = take(sizeof(double) * 4 * NPARTS);
+  w.xi = take(sizeof(double) * 3 * nbs * (size_t)(d->n_sub > 0 ? d->n_sub : 1));
   w.total = o;
   return w;
 }
@@ -301,6 +302,7 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
   c->mw.nbr = (int*)(w + c->wl.nbr);
   c->mw.ncnt = (int*)(w + c->wl.ncnt);
   c->mw.rb = (uint32_t*)(w + c->wl.rb);
+  c->mw.xi = (double*)(w + c->wl.xi);
   c->steps = 0;
 
   // geometry flags on the host (Sec. 4: wall plane with a square pore)

@@ -27,6 +27,7 @@ struct MdWork {
   int* nbr;       // [nb][MAXNBR]
   int* ncnt;      // [nb]
   uint32_t* rb;   // [4] rebuild flags (3-phase) + list-invalid flag
+  double* xi;     // [n_sub][nb][3] noise of the current sub-cycle
 };
 
 template <typename T, bool DEV> void launch_fill_rest(void* pops, long N, hipStream_t s);

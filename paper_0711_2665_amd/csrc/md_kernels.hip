@@ -49,6 +49,19 @@ __global__ void k_md_start(BeadPtrs b, MdWork w, MdParams P) {
   if (d2 > P.halfskin2) w.rb[0] = 1u;
 }
 
+// The noise of a whole sub-cycle at once: xi[(s nb + p) 3 + a] for every
+// sub-step s and bead p (the same counter-based values the sub-step would
+// draw), so the transcendental functions run in one wide launch instead of on
+// the critical path of every sub-step.
+__global__ void k_md_noise(MdParams P, const Ctrl* __restrict__ ctrl, double* __restrict__ xi, int n_sub) {
+  long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long)n_sub * P.nb) return;
+  int sidx = (int)(k / P.nb), p = (int)(k - (long)sidx * P.nb);
+  double x[3];
+  gauss3(P.seed, P.replica, (uint32_t)ctrl->step, (uint32_t)sidx, (uint32_t)p, x);
+  xi[3 * k] = x[0]; xi[3 * k + 1] = x[1]; xi[3 * k + 2] = x[2];
+}
+
 // Bending forces of the angles centred at q = q0 .. q0 + nq - 1 (those with
 // 1 <= q <= nb - 2), one angle per thread, into LDS: ang[q - q0][0..2] force
 // on q-1, [3..5] on q, [6..8] on q+1.  Each angle is evaluated once and read
@@ -90,7 +103,6 @@ struct MdShared {
   uint32_t hit[MD_BPB][MD_LANES];            // lane l, bit m: entry l + 4m is within r_c
   double wallF[MD_BPB][MAXWALL][3];
   int nwall[MD_BPB];
-  double xi[MD_BPB][3];
   int cnt[MD_BPB];
   int lst[MD_BPB][MAXNBR];                   // the neighbour list in use
   double tile[MD_WG][3];                     // rebuild: positions of 64 candidates
@@ -162,12 +174,29 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
   }
   double rp[3] = {0.0, 0.0, 0.0};
   if (active) { rp[0] = rin[3 * p]; rp[1] = rin[3 * p + 1]; rp[2] = rin[3 * p + 2]; }
+  // lane 0 issues every load it needs later before the first barrier
+  const bool lead = active && lane == 0;
+  double vo[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0}, Jo[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
+  double rm[3] = {0.0, 0.0, 0.0}, rq[3] = {0.0, 0.0, 0.0};
+  int ncnt0 = 0;
+  if (lead) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vo[a] = b.v[3 * p + a];
+      Jo[a] = b.J[3 * p + a];
+      u[a] = P.couple ? b.up[3 * p + a] : 0.0;
+      if (P.sig != 0.0) xi[a] = w.xi[(size_t)3 * ((size_t)s * P.nb + p) + a];
+      if (p > 0) rm[a] = rin[3 * (p - 1) + a];
+      if (p < P.nb - 1) rq[a] = rin[3 * (p + 1) + a];
+    }
+    ncnt0 = w.ncnt[p];
+  }
   if (t == 0) sh.over = 0;
   angles_to_lds(rin, P, p0 - 1, MD_BPB + 2, sh.ang);
 
   // ---- neighbour list: reuse, or rebuild by scanning all beads in tiles of 64
   if (!rebuild) {
-    if (active && lane == 0) sh.cnt[slot] = w.ncnt[p];
+    if (lead) sh.cnt[slot] = ncnt0;
     __syncthreads();
     int c = active ? sh.cnt[slot] : 0;
     for (int k = lane; k < c; k += MD_LANES) sh.lst[slot][k] = w.nbr[(size_t)p * MAXNBR + k];
@@ -251,25 +280,13 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
     }
     sh.hit[slot][lane] = hit;
   }
-  // ---- wall sites (lane 1) and noise (lane 2)
+  // ---- wall sites (lane 1)
   if (active && lane == 1) sh.nwall[slot] = wall_sites(P, g, rp, sh.wallF[slot]);
-  if (active && lane == 2) {
-    double xi[3] = {0.0, 0.0, 0.0};
-    if (P.sig != 0.0) gauss3(P.seed, P.replica, (uint32_t)ctrl->step, (uint32_t)s, (uint32_t)p, xi);
-    sh.xi[slot][0] = xi[0]; sh.xi[slot][1] = xi[1]; sh.xi[slot][2] = xi[2];
-  }
   // ---- lane 0: bonds now, then every contribution in the fixed order
   double F[3] = {0.0, 0.0, 0.0};
-  double vo[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0}, Jo[3] = {0.0, 0.0, 0.0};
-  if (active && lane == 0) {
-    if (p > 0) bond_add(P, rp, &rin[3 * (p - 1)], F);
-    if (p < P.nb - 1) bond_add(P, rp, &rin[3 * (p + 1)], F);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      vo[a] = b.v[3 * p + a];
-      Jo[a] = b.J[3 * p + a];
-      u[a] = P.couple ? b.up[3 * p + a] : 0.0;
-    }
+  if (lead) {
+    if (p > 0) bond_add(P, rp, rm, F);
+    if (p < P.nb - 1) bond_add(P, rp, rq, F);
   }
   __syncthreads();
   if (!(active && lane == 0)) return;
@@ -291,7 +308,7 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
   bool finite = true;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double sx = P.sig * sh.xi[slot][a];
+    double sx = P.sig * xi[a];
     vn[a] = P.e * vo[a] + P.cf * (F[a] + P.gamma * u[a]) + sx;
     b.J[3 * p + a] = Jo[a] - P.m * (P.omE * (u[a] - vo[a]) + sx);
     b.v[3 * p + a] = vn[a];
@@ -328,6 +345,10 @@ void launch_md_cycle(const BeadPtrs& b, const MdWork& w, const MdParams& P, cons
   if (P.nb <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)((P.nb + MD_BPB - 1) / MD_BPB);
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(1), 0, s, w.rb);
+  if (P.sig != 0.0) {
+    long nk = (long)n_sub * P.nb;
+    hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, P, ctrl, w.xi, n_sub);
+  }
   hipLaunchKernelGGL(k_md_start, dim3((P.nb + 255) / 256), dim3(256), 0, s, b, w, P);
   for (int k = 0; k < n_sub; ++k)
     hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, b, w, P, g, ctrl, k, k == n_sub - 1 ? 1 : 0);

@@ -58,15 +58,19 @@ def _gpu_pops(sim):
     return sim.pops().double().cpu().numpy()
 
 
-def test_lb_only_fp64_matches_oracle_bitwise(orc):
+@pytest.mark.parametrize("shape,axis,pos", [((12, 10, 16), 2, 8), ((32, 16, 12), 0, 16), ((64, 8, 6), 1, 4)])
+def test_lb_only_fp64_matches_oracle_bitwise(orc, shape, axis, pos):
+    """Shapes cover the per-node sweep (12 x 10 x 16) and the vector sweep
+    (rows of 32 and 64 nodes, walls normal to x and to y)."""
     torch = _torch()
     from paper_0711_2665_amd import lbmd
-    cfg = _cfg((12, 10, 16), wall_axis=2, wall_pos=8, pore_h=3, g=(1e-5, 2e-5, -1e-5), tau=0.8)
+    cfg = _cfg(shape, wall_axis=axis, wall_pos=pos, pore_h=3, g=(1e-5, 2e-5, -1e-5), tau=0.8)
     o = orc.Oracle(cfg)
     s = lbmd.Simulation(cfg)
     rng = np.random.default_rng(1)
     _, w, _ = orc.tables()
-    f0 = w[:, None, None, None] * (1 + 0.05 * rng.standard_normal((19, 16, 10, 12)))
+    nx, ny, nz = shape
+    f0 = w[:, None, None, None] * (1 + 0.05 * rng.standard_normal((19, nz, ny, nx)))
     o.set_pops(f0)
     s.set_state(_state_tensor(s, f0))
     fluid = o.flags() == 0
@@ -223,6 +227,33 @@ def test_single_coupled_step_fp64_bitwise_up_to_libm(orc):
     assert np.array_equal(a, b)
     for k in ("r", "v", "up", "J"):
         assert np.array_equal(sb[k], ob[k]), k
+
+
+@pytest.mark.parametrize("shape,axis,pos", [((12, 10, 16), 2, 8), ((32, 16, 12), 0, 16)])
+def test_lb_only_fp32_deviation_matches_oracle(orc, shape, axis, pos):
+    """FP32 deviation storage against the FP64 oracle over 20 fluid steps from
+    a random perturbation: the deviations agree to a few FP32 ulps of their
+    size (bound measured: well below 1e-6 of max |f - w|)."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = _cfg(shape, wall_axis=axis, wall_pos=pos, pore_h=3, g=(1e-5, 2e-5, -1e-5), tau=0.8)
+    o = orc.Oracle(cfg)
+    s = lbmd.Simulation(cfg, precision=lbmd.LB_FP32_DEV)
+    rng = np.random.default_rng(2)
+    _, w, _ = orc.tables()
+    nx, ny, nz = shape
+    dev = w[:, None, None, None] * 0.05 * rng.standard_normal((19, nz, ny, nx))
+    o.set_pops(w[:, None, None, None] + dev)
+    s.set_state(_state_tensor(s, dev))
+    o.lb_step(20)
+    s.lb_step(20)
+    torch.cuda.synchronize()
+    fluid = o.flags() == 0
+    a = _gpu_pops(s)[:, fluid]
+    b = (o.pops() - w[:, None, None, None])[:, fluid]
+    err = np.abs(a - b).max() / np.abs(b).max()
+    print(f"fp32-dev lb-only {shape}: rel err of deviations {err:.2e}", flush=True)
+    assert err < 1e-5
 
 
 def test_fp32_deviation_rest_state_is_exact():
