@@ -17,13 +17,24 @@
  *     friction gamma (u - v) plus Gaussian noise, and the reaction impulse
  *     spread back onto the 8 surrounding nodes.
  *
+ * A context holds R >= 1 replicas (lb_ensemble_init; lb_init is R = 1):
+ * independent systems, each with its own lattice, wall, chain and noise key,
+ * advanced in lockstep by the same kernel launches.
+ *
  * Conventions (all entry points):
  *   - Ownership: the caller allocates every device buffer (sizes from
- *     lb_buffer_sizes) and keeps it alive until lb_destroy; the library
- *     borrows the pointers and never allocates device memory.
+ *     lb_buffer_sizes / lb_ensemble_sizes) and keeps it alive until
+ *     lb_destroy; the library borrows the pointers and never allocates
+ *     device memory.  It owns host objects only: a second stream, events,
+ *     and the captured graph of lb_ensemble_run.
  *   - Streams: every call enqueues work on the stream given to lb_init and
- *     returns without synchronising, except lb_check, lb_autotune and the
- *     host-copy helpers, which say so.
+ *     returns without synchronising, except where a call says that it
+ *     synchronises.
+ *   - Packing: replica r's nodes start at node offset node_off[r] (a
+ *     multiple of 64) and its beads at slot offset slot_off[r] (a multiple
+ *     of 16), both from lb_ensemble_layout; populations of replica r are
+ *     [19][N_r] from element 19 node_off[r], flags and force ([3][N_r]) use
+ *     the same node offsets, bead arrays the slot offsets.
  *   - Errors: each call returns LB_OK (0) or a negative LB_ERR_* code; the
  *     message of the last failure of the calling thread is returned by
  *     lb_last_error().  No C++ exception crosses this boundary.
@@ -83,15 +94,19 @@ typedef struct lb_desc {
   uint32_t seed, replica; /* Philox key of the bead noise                     */
 } lb_desc;
 
-/* Byte sizes of the caller-allocated device buffers (256-byte aligned). */
+/* Byte sizes of the caller-allocated device buffers (256-byte aligned), and
+ * the packed node and bead-slot counts. */
 typedef struct lb_sizes {
-  size_t pops_bytes;   /* one population array, [19][N] of double or float;
-                          two are needed (pops_a, pops_b)                     */
-  size_t flags_bytes;  /* uint8 per node                                      */
-  size_t force_bytes;  /* bead force density on the lattice, [3][N]          */
-  size_t beads_bytes;  /* bead state, doubles: r, v, u_p, J, r_start, each [nb][3] */
+  size_t pops_bytes;   /* one population array, 19 per packed node, double or
+                          float; two are needed (pops_a, pops_b)            */
+  size_t flags_bytes;  /* uint8 per packed node                               */
+  size_t force_bytes;  /* bead force density on the lattice, 3 per node       */
+  size_t beads_bytes;  /* bead state, doubles: r, v, u_p, J, r_start, each
+                          [bead_slots][3]                                     */
   size_t work_bytes;   /* private scratch: lists, counters, partial sums      */
   size_t state_bytes;  /* size of the buffer lb_get_state writes              */
+  size_t nodes;        /* packed lattice nodes (all replicas, with padding)   */
+  size_t bead_slots;   /* bead slots (all replicas, with padding)             */
 } lb_sizes;
 
 /* Device pointers (hipMalloc'ed or torch CUDA tensors), 256-byte aligned. */
@@ -107,32 +122,48 @@ typedef struct lb_buffers {
 typedef struct lb_ctx lb_ctx;
 
 /* Validates *d and fills *out.  Host only: calls no HIP function.
- * LB_ERR_ARG: extents <= 0 or N > 2^31 - 1, tau <= 0.5, a wall plane outside
- * [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative gamma
- * or kT, rc > 2, or nb > 0 without a positive mass. */
+ * LB_ERR_ARG: extents <= 0 or 19 N > 2^31 - 1, tau <= 0.5, a wall plane
+ * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
+ * gamma or kT, rc outside (0, 2], or nb > 0 without a positive mass. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
 
-/* Creates a context (host memory only) on the current HIP device, builds the
- * solid flags of the geometry on the host and uploads them, fills both
- * population arrays with the rest equilibrium f_i = w_i (zero in
- * LB_FP32_DEV; Sec. 4: unit density, zero velocity) and uploads the bead
- * positions r0_host and velocities v0_host ([nb][3] doubles, host memory;
- * v0_host may be NULL for zero; positions are unwrapped).  stream is a
- * hipStream_t (NULL: the default stream).  The uploads are enqueued on
- * stream from pageable host memory.  LB_ERR_ARG: as lb_buffer_sizes, a NULL
- * or misaligned buffer, or a bead whose base node is solid. */
+/* As lb_buffer_sizes for nrep replicas d[0..nrep-1] in one context.  All
+ * replicas share precision and n_sub; extents, walls, chains, friction,
+ * temperature, field and noise keys may differ.  LB_ERR_ARG also for nrep
+ * outside [1, 1024] or mixed precision / n_sub. */
+int lb_ensemble_sizes(const lb_desc* d, int nrep, lb_sizes* out);
+
+/* Creates a context on the current HIP device, builds the solid flags of the
+ * geometry on the host and uploads them, fills both population arrays with
+ * the rest equilibrium f_i = w_i (zero in LB_FP32_DEV; Sec. 4: unit density,
+ * zero velocity) and uploads the bead positions r0_host and velocities
+ * v0_host ([nb][3] doubles, host memory; v0_host may be NULL for zero;
+ * positions are unwrapped).  stream is a hipStream_t (NULL: the default
+ * stream).  Synchronises the stream before returning.  LB_ERR_ARG: as
+ * lb_buffer_sizes, a NULL or misaligned buffer, or non-finite bead state. */
 int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const double* v0_host,
             void* stream, lb_ctx** out);
+
+/* As lb_init for nrep replicas (the batched ensemble): r0_host / v0_host
+ * hold the chains one after the other, replica 0 first ([sum nb][3]). */
+int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const double* r0_host,
+                     const double* v0_host, void* stream, lb_ctx** out);
+
+/* Host only: writes the node offset and bead-slot offset of every replica
+ * (arrays of nrep). */
+int lb_ensemble_layout(lb_ctx* ctx, int64_t* node_off, int64_t* slot_off);
 
 /* Releases the host-side context; the caller frees its buffers afterwards. */
 void lb_destroy(lb_ctx* ctx);
 
-/* nsteps fluid-only LB steps (Sec. 2, Eq. (lbe2)): pull-stream with halfway
- * bounce-back, BGK collision towards the second-order equilibrium, source
- * 3 w_i g.c_i of the uniform body force.  Beads are not moved. */
+/* nsteps fluid-only LB steps of every replica (Sec. 2, Eq. (lbe2)):
+ * pull-stream with halfway bounce-back, BGK collision towards the
+ * second-order equilibrium, source 3 w_i g.c_i of the uniform body force.
+ * Beads are not moved. */
 int lb_step(lb_ctx* ctx, int nsteps);
 
-/* nsteps coupled steps.  Each step, at the bead positions r(n):
+/* nsteps coupled steps of every replica.  Each step, at the bead positions
+ * r(n):
  *   1. u_p = trilinear interpolation of the fluid velocity (from the pulled
  *      populations of the stored array; u = 0 at solid nodes) (Sec. 2, the
  *      particle-to-grid transfer, here trilinear instead of nearest point);
@@ -147,12 +178,44 @@ int lb_step(lb_ctx* ctx, int nsteps);
  *   4. one LB step with the source 3 w_i (F(x) + g).c_i (Sec. 2, S_i). */
 int md_couple_step(lb_ctx* ctx, int nsteps);
 
+/* As md_couple_step, for the batched ensemble: with use_graph != 0 the
+ * launches of two coupled steps are captured once into a HIP graph
+ * (re-captured after lb_sweep_config / lb_autotune) and the graph is
+ * replayed; an odd step, or a step that brings the populations to the
+ * graph's parity, runs eagerly.  Results are identical to md_couple_step.
+ * While lb_profile_start is active the steps run eagerly. */
+int lb_ensemble_run(lb_ctx* ctx, int nsteps, int use_graph);
+
+/* Synchronises the stream and copies, per replica, the first step count at
+ * which every bead's normal coordinate exceeded the wall plane (the chain
+ * has translocated), or -1 (not yet, or no wall / no chain), to out_host
+ * (nrep int64). */
+int lb_ensemble_translocation(lb_ctx* ctx, int64_t* out_host);
+
+/* Sweep layout: tile_nodes (a multiple of 256) consecutive nodes of one
+ * replica per tile; order 0 lists tiles replica by replica, order 1 deals
+ * them into 8 contiguous chunks interleaved so that neighbouring tiles run on
+ * one XCD; grid 0 launches one workgroup per tile, grid > 0 that many
+ * workgroups striding over the tiles.  Results do not depend on it.
+ * Synchronises the stream (uploads the tile table). */
+int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid);
+
+/* Autotuner of the sweep layout: times `reps` sweeps of every candidate
+ * layout (tile sizes 256..2048, both orders, two persistent grids) with HIP
+ * events, from the current populations into the other array (which the
+ * next step overwrites, so the state is unchanged), keeps the fastest and
+ * caches it for the process by (replica extents and walls, precision).
+ * Writes {tile_nodes, order, grid} to out_cfg[3] and the mean sweep time in
+ * ms to *out_ms (-1 when taken from the cache).  Synchronises the stream. */
+int lb_autotune(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
+
 /* Pre-relaxation of the chain (Sec. 4: the initial walk is relaxed by MD):
  * nsub_total SPV sub-steps with no fluid coupling, no field, no noise and
  * friction gamma_relax; the velocities are zeroed at the end. */
 int md_relax(lb_ctx* ctx, int nsub_total, double gamma_relax);
 
-/* Writes LB_NOBS doubles to out_dev (device memory): [0] fluid mass,
+/* Writes LB_NOBS doubles per replica to out_dev (device memory; replica r
+ * at out_dev + LB_NOBS r): [0] fluid mass,
  * [1..3] fluid momentum (Sec. 3: global momentum reductions), [4] bead
  * temperature m<v^2>/3 (Sec. 2: the monitored bead temperature), [5..7] bead
  * momentum, [8] mean unwrapped normal coordinate, [9] translocated fraction,
@@ -163,10 +226,11 @@ int md_relax(lb_ctx* ctx, int nsub_total, double gamma_relax);
  * Sums are FP64. */
 int lb_observables(lb_ctx* ctx, double* out_dev);
 
-/* Checkpoint: copies the current populations ([19][N], the storage type),
- * r and v ([nb][3] doubles each) and the step counter (uint64) to dst_dev
- * (device, lb_sizes.state_bytes) / restores them from src_dev.  Device to
- * device, enqueued on the stream. */
+/* Checkpoint: copies the current populations (every replica, the storage
+ * type), r and v of every bead slot, the step counter (uint64) and the
+ * translocation steps to dst_dev (device, lb_sizes.state_bytes) / restores
+ * them from src_dev.  Device to device, enqueued on the stream;
+ * lb_set_state synchronises it to read back the step counter. */
 int lb_get_state(lb_ctx* ctx, void* dst_dev);
 int lb_set_state(lb_ctx* ctx, const void* src_dev);
 
@@ -182,10 +246,11 @@ int lb_check(lb_ctx* ctx);
 /* Steps taken so far (host copy). */
 int64_t lb_step_count(lb_ctx* ctx);
 
-/* Kernel timing: from lb_profile_start on, HIP events are recorded on the
- * stream around every LB sweep (phase 0) and every bead phase -- gather, MD
- * sub-cycle and spreading -- (phase 1) of lb_step / md_couple_step, for at
- * most max_steps steps.  lb_profile_stop synchronises the stream, writes the
+/* Kernel timing: from lb_profile_start on, HIP events are recorded around
+ * every LB sweep (phase 0, on the stream the sweep runs on) and every bead
+ * phase -- gather, MD sub-cycle, spreading and the update of the nodes that
+ * carry bead force -- (phase 1) of lb_step / md_couple_step, for at most
+ * max_steps steps.  lb_profile_stop synchronises the stream, writes the
  * mean duration in ms of each phase and the number of steps recorded, and
  * stops recording.  Events are host-side objects; no device memory is
  * allocated by the library.  LB_ERR_ARG: max_steps < 1 or recording already
@@ -194,8 +259,8 @@ int lb_profile_start(lb_ctx* ctx, int max_steps);
 int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* nsteps);
 
 /* Diagnostics: synchronises the stream and writes out[0] = neighbour-list
- * rebuilds, out[1] = MD sub-steps taken, out[2] = nodes carrying bead force
- * in the last step, out[3] = watchdog bits, out[4] = LB steps taken. */
+ * rebuilds (summed over replicas), out[1] = MD sub-step launches, out[2] =
+ * tiles of the sweep, out[3] = watchdog bits, out[4] = LB steps taken. */
 int lb_diagnostics(lb_ctx* ctx, int64_t* out);
 
 /* Message of the last failed call on this thread (never NULL). */

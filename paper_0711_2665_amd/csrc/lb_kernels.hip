@@ -1,7 +1,7 @@
 // lb_kernels.hip -- lattice side of the coupled step: the fused
 // stream + collide sweep, the bead gather (fluid velocity at the beads), the
 // deterministic spreading of the bead reaction onto the lattice, and the
-// fluid reductions.
+// fluid reductions.  All kernels serve every replica of a context.
 #include "lbmd_kernels.h"
 
 namespace lbmd {
@@ -118,11 +118,10 @@ __device__ inline R cdot(int i, R vx, R vy, R vz) {
 }
 
 // ---------------------------------------------------------------------------
-// K1: fused stream + collide (Sec. 2, Eq. (lbe2) as a BGK relaxation with the
-// source S_i = 3 w_i F.c_i) of one fluid node c.
+// BGK collision with the source term (Sec. 2, Eq. (lbe2) read as a relaxation
+// with S_i = 3 w_i F.c_i) of one fluid node (index c, flags fl) from its
+// post-streaming populations f; writes f* to out (may alias f).
 // ---------------------------------------------------------------------------
-// BGK collision with the source term of one fluid node (index c, flags fl)
-// from its post-streaming populations f; writes f* to out.
 template <typename T, bool DEV>
 __device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict__ force, const LbParams& p,
                                     Ctrl* __restrict__ ctrl, int c, uint8_t fl) {
@@ -182,11 +181,16 @@ __device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict_
   }
 }
 
-// Stream + collide one fluid node at (x, y, z), index c.
+// Stream + collide one fluid node c of a replica (pointers already offset to
+// the replica).
 template <typename T, bool DEV>
-__device__ inline void lb_node_xyz(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
-                                   const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
-                                   uint8_t fl, int x, int y, int z) {
+__device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
+                               const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
+                               uint8_t fl) {
+  int x = c % p.nx;
+  int yz = c / p.nx;
+  int y = yz % p.ny;
+  int z = yz / p.ny;
   Nbr nb = make_nbr(p, x, y, z);
   T f[Q];
   pull<T>(A, flags, p, c, fl, nb, f);
@@ -196,45 +200,46 @@ __device__ inline void lb_node_xyz(const T* __restrict__ A, T* __restrict__ B, c
   for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c], f[i]);
 }
 
+// ---------------------------------------------------------------------------
+// K1: the sweep over a table of tiles (each tile_nodes consecutive nodes of
+// one replica); workgroups stride over the table.  Solid nodes are skipped,
+// and so are nodes carrying a bead force when skip_forced is set (they are
+// updated by k_lb_forced once the force is known).
+// ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
-                               const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
-                               uint8_t fl) {
-  int x = c % p.nx;
-  int yz = c / p.nx;
-  int y = yz % p.ny;
-  int z = yz / p.ny;
-  lb_node_xyz<T, DEV>(A, B, flags, force, p, ctrl, c, fl, x, y, z);
-}
-
-// Sweep over all nodes; solid nodes are skipped, and so are nodes carrying a
-// bead force when skip_forced is set (those are updated by k_lb_forced once
-// the force is known).
-template <typename T, bool DEV>
-__global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B,
-                                            const uint8_t* __restrict__ flags, const T* __restrict__ force,
-                                            LbParams p, Ctrl* __restrict__ ctrl, int skip_forced) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p.N) return;
-  uint8_t fl = flags[c];
-  if (fl & F_SOLID) return;
-  if (skip_forced && (fl & F_FORCED)) return;
-  lb_node<T, DEV>(A, B, flags, force, p, ctrl, c, fl);
+__global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B, Dev d, int ntiles,
+                                            int tile_nodes, int skip_forced) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile tl = d.tiles[t];
+    const Rep& R = d.reps[tl.rep];
+    const long no = R.node_off;
+    const T* Ar = A + (size_t)Q * no;
+    T* Br = B + (size_t)Q * no;
+    const uint8_t* fr = d.flags + no;
+    const T* Fr = (const T*)d.force + (size_t)3 * no;
+    const int end = min(tl.start + tile_nodes, R.lp.N);
+    for (int c = tl.start + (int)threadIdx.x; c < end; c += blockDim.x) {
+      uint8_t fl = fr[c];
+      if (fl & F_SOLID) continue;
+      if (skip_forced && (fl & F_FORCED)) continue;
+      lb_node<T, DEV>(Ar, Br, fr, Fr, R.lp, d.ctrl, c, fl);
+    }
+  }
 }
 
 // The nodes that carry a bead force this step (the list written by the
 // spreading kernel).
 template <typename T, bool DEV>
-__global__ __launch_bounds__(64) void k_lb_forced(const T* __restrict__ A, T* __restrict__ B,
-                                                  const uint8_t* __restrict__ flags, const T* __restrict__ force,
-                                                  LbParams p, Ctrl* __restrict__ ctrl,
-                                                  const int* __restrict__ touched, int maxlist) {
+__global__ __launch_bounds__(64) void k_lb_forced(const T* __restrict__ A, T* __restrict__ B, Dev d, int maxlist) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int nt = (int)ctrl->touched;
+  int nt = (int)d.ctrl->touched;
   if (k >= nt || k >= maxlist) return;
-  int c = touched[k];
-  uint8_t fl = flags[c];
-  lb_node<T, DEV>(A, B, flags, force, p, ctrl, c, fl);
+  const int2 e = d.touched[k];
+  const Rep& R = d.reps[e.x];
+  const long no = R.node_off;
+  const uint8_t* fr = d.flags + no;
+  lb_node<T, DEV>(A + (size_t)Q * no, B + (size_t)Q * no, fr, (const T*)d.force + (size_t)3 * no, R.lp, d.ctrl, e.y,
+                  fr[e.y]);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,25 +275,27 @@ __device__ inline void node_velocity(const T* __restrict__ A, const uint8_t* __r
 
 // ---------------------------------------------------------------------------
 // Start of a coupled step: remember r(n), link every bead into the list of
-// its base node, clear J.
+// its base node, clear J, and mark the stencil nodes of r(n) as carrying bead
+// force this step (solid ones are dropped by the spreading; every writer of
+// a node stores the same byte).
 // ---------------------------------------------------------------------------
-__global__ void k_bead_prep(BeadPtrs b, Geom g, int nb, int* __restrict__ head, int* __restrict__ next,
-                            int* __restrict__ base, uint8_t* __restrict__ flags) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nb) return;
-  double rp[3] = {b.r[3 * p], b.r[3 * p + 1], b.r[3 * p + 2]};
-  Stencil st = make_stencil(g, rp);
-  int cell = st.b[0] + g.nx * (st.b[1] + g.ny * st.b[2]);
+__global__ void k_bead_prep(Dev d, int nslots) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const Rep& R = d.reps[d.slot_rep[slot]];
+  if (slot - R.slot_off >= R.mp.nb) return;
+  double rp[3] = {d.r[3 * slot], d.r[3 * slot + 1], d.r[3 * slot + 2]};
+  Stencil st = make_stencil(R.g, rp);
+  int cell = st.b[0] + R.g.nx * (st.b[1] + R.g.ny * st.b[2]);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) { b.rs[3 * p + a] = rp[a]; b.J[3 * p + a] = 0.0; }
-  base[p] = cell;
-  next[p] = atomicExch(&head[cell], p);
-  // the 8 stencil nodes of r(n) receive bead force this step (solid ones are
-  // dropped by the spreading); every writer of a node stores the same byte
+  for (int a = 0; a < 3; ++a) { d.rs[3 * slot + a] = rp[a]; d.J[3 * slot + a] = 0.0; }
+  d.base[slot] = cell;
+  d.next[slot] = atomicExch(&d.head[R.node_off + cell], slot);
+  uint8_t* fr = d.flags + R.node_off;
   for (int k = 0; k < 8; ++k) {
-    int n = (int)corner_node(g, st, k);
-    uint8_t fl = flags[n];
-    if (!(fl & F_SOLID)) flags[n] = fl | F_FORCED;
+    int n = (int)corner_node(R.g, st, k);
+    uint8_t fl = fr[n];
+    if (!(fl & F_SOLID)) fr[n] = fl | F_FORCED;
   }
 }
 
@@ -296,21 +303,24 @@ __global__ void k_bead_prep(BeadPtrs b, Geom g, int nb, int* __restrict__ head, 
 // K2: u_p = sum_k W_k u(node_k) at r(n) (trilinear).
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__global__ void k_gather(const T* __restrict__ A, const uint8_t* __restrict__ flags, LbParams p, Geom g, BeadPtrs b,
-                         int nb) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nb) return;
-  double rp[3] = {b.rs[3 * q], b.rs[3 * q + 1], b.rs[3 * q + 2]};
-  Stencil st = make_stencil(g, rp);
+__global__ void k_gather(const T* __restrict__ A, Dev d, int nslots) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const Rep& R = d.reps[d.slot_rep[slot]];
+  if (slot - R.slot_off >= R.mp.nb) return;
+  const T* Ar = A + (size_t)Q * R.node_off;
+  const uint8_t* fr = d.flags + R.node_off;
+  double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
+  Stencil st = make_stencil(R.g, rp);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < 8; ++k) {
-    int node = (int)corner_node(g, st, k);
+    int node = (int)corner_node(R.g, st, k);
     double W = corner_weight(st, k);
     double u[3];
-    node_velocity<T, DEV>(A, flags, p, node, u);
+    node_velocity<T, DEV>(Ar, fr, R.lp, node, u);
     acc[0] += W * u[0]; acc[1] += W * u[1]; acc[2] += W * u[2];
   }
-  b.up[3 * q] = acc[0]; b.up[3 * q + 1] = acc[1]; b.up[3 * q + 2] = acc[2];
+  d.up[3 * slot] = acc[0]; d.up[3 * slot + 1] = acc[1]; d.up[3 * slot + 2] = acc[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -322,18 +332,22 @@ __global__ void k_gather(const T* __restrict__ A, const uint8_t* __restrict__ fl
 // ascending bead order.  Shares on solid nodes are dropped.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void k_spread(BeadPtrs b, Geom g, int nb, const int* __restrict__ head, const int* __restrict__ next,
-                         uint8_t* __restrict__ flags, T* __restrict__ force, int* __restrict__ touched,
-                         Ctrl* __restrict__ ctrl) {
+__global__ void k_spread(Dev d, int nslots) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= 8 * nb) return;
-  int p = e >> 3, k = e & 7;
-  double rp[3] = {b.rs[3 * p], b.rs[3 * p + 1], b.rs[3 * p + 2]};
+  if (e >= 8 * nslots) return;
+  int slot = e >> 3, k = e & 7;
+  const int rep = d.slot_rep[slot];
+  const Rep& R = d.reps[rep];
+  const int p = slot - R.slot_off;
+  if (p >= R.mp.nb) return;
+  const Geom& g = R.g;
+  const uint8_t* fr = d.flags + R.node_off;
+  double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
   Stencil st = make_stencil(g, rp);
   int n = (int)corner_node(g, st, k);
-  if (flags[n] & F_SOLID) return;
+  if (fr[n] & F_SOLID) return;
   int nz_ = n / g.nxy, rem = n - nz_ * g.nxy, ny_ = rem / g.nx, nx_ = rem - ny_ * g.nx;
-  // contributors as keys q*8 + k'
+  // contributors as keys q*8 + k' (q the chain index)
   int keys[MAXCONTRIB];
   int cnt = 0;
   bool overflow = false;
@@ -342,8 +356,8 @@ __global__ void k_spread(BeadPtrs b, Geom g, int nb, const int* __restrict__ hea
     int by = ny_ - ((k2 >> 1) & 1); if (by < 0) by += g.ny;
     int bz = nz_ - ((k2 >> 2) & 1); if (bz < 0) bz += g.nz;
     int cell = bx + g.nx * (by + g.ny * bz);
-    for (int q = head[cell]; q >= 0; q = next[q]) {
-      int key = q * 8 + k2;
+    for (int q = d.head[R.node_off + cell]; q >= 0; q = d.next[q]) {
+      int key = (q - R.slot_off) * 8 + k2;
       if (cnt < MAXCONTRIB) {
         int j = cnt++;
         while (j > 0 && keys[j - 1] > key) { keys[j] = keys[j - 1]; --j; }
@@ -353,55 +367,82 @@ __global__ void k_spread(BeadPtrs b, Geom g, int nb, const int* __restrict__ hea
       }
     }
   }
-  if (overflow) { atomicOr(&ctrl->err, E_SPREAD); }
+  if (overflow) { atomicOr(&d.ctrl->err, E_SPREAD); }
   if (keys[0] != p * 8 + k) return;   // not the owner of node n
   double F[3] = {0.0, 0.0, 0.0};
   for (int j = 0; j < cnt; ++j) {
-    int q = keys[j] >> 3, k2 = keys[j] & 7;
-    double rq[3] = {b.rs[3 * q], b.rs[3 * q + 1], b.rs[3 * q + 2]};
+    int qs = R.slot_off + (keys[j] >> 3), k2 = keys[j] & 7;
+    double rq[3] = {d.rs[3 * qs], d.rs[3 * qs + 1], d.rs[3 * qs + 2]};
     Stencil sq = make_stencil(g, rq);
     double W = corner_weight(sq, k2);
-    F[0] += W * b.J[3 * q];
-    F[1] += W * b.J[3 * q + 1];
-    F[2] += W * b.J[3 * q + 2];
+    F[0] += W * d.J[3 * qs];
+    F[1] += W * d.J[3 * qs + 1];
+    F[2] += W * d.J[3 * qs + 2];
   }
   const size_t N = (size_t)g.N;
-  force[n] = (T)F[0];
-  force[N + n] = (T)F[1];
-  force[2 * N + n] = (T)F[2];
-  int slot = atomicAdd(&ctrl->touched, 1u);
-  touched[slot] = n;
+  T* Fr = (T*)d.force + (size_t)3 * R.node_off;
+  Fr[n] = (T)F[0];
+  Fr[N + n] = (T)F[1];
+  Fr[2 * N + n] = (T)F[2];
+  int s = atomicAdd(&d.ctrl->touched, 1u);
+  d.touched[s] = make_int2(rep, n);
 }
 
-// End of a coupled step: clear the forced bits, empty the node lists,
-// advance the step counter.
-__global__ void k_step_end(int nb, const int* __restrict__ base, int* __restrict__ head,
-                           const int* __restrict__ touched, uint8_t* __restrict__ flags, Ctrl* __restrict__ ctrl,
-                           int advance) {
+// End of a coupled step: clear the forced bits, empty the node lists, note
+// replicas with a bead still on the cis side of the wall.
+__global__ void k_step_end(Dev d, int nslots, int maxlist) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  int nt = (int)ctrl->touched;
-  if (k < nt) { int n = touched[k]; flags[n] = flags[n] & (uint8_t)~F_FORCED; }
-  if (k < nb) head[base[k]] = -1;
+  int nt = (int)d.ctrl->touched;
+  if (k < nt && k < maxlist) {
+    int2 e = d.touched[k];
+    uint8_t* f = d.flags + d.reps[e.x].node_off + e.y;
+    *f = *f & (uint8_t)~F_FORCED;
+  }
+  if (k < nslots) {
+    const int rep = d.slot_rep[k];
+    const Rep& R = d.reps[rep];
+    if (k - R.slot_off < R.mp.nb) {
+      d.head[R.node_off + d.base[k]] = -1;
+      if (R.g.wall_axis >= 0 && !(d.r[3 * k + R.g.wall_axis] > (double)R.g.wall_pos)) d.notdone[rep] = 1u;
+    }
+  }
 }
-__global__ void k_step_tick(Ctrl* __restrict__ ctrl, int advance) {
-  ctrl->touched = 0u;
-  ctrl->step += (uint64_t)advance;
+// Advance the step counter; record the translocation step of replicas whose
+// whole chain is past the wall plane for the first time.  One block.
+__global__ void k_step_tick(Dev d, int nrep, int with_beads) {
+  const uint64_t next = d.ctrl->step + 1u;
+  for (int r = threadIdx.x; r < nrep && with_beads; r += blockDim.x) {
+    const Rep& R = d.reps[r];
+    if (R.g.wall_axis >= 0 && R.mp.nb > 0 && d.notdone[r] == 0u && d.tX[r] < 0) d.tX[r] = (int64_t)next;
+    d.notdone[r] = 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d.ctrl->touched = 0u;
+    d.ctrl->step = next;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Fluid reductions (mass deviation and momentum) in FP64: block partials,
-// then one block sums the partials in a fixed order.
+// Fluid reductions (mass deviation and momentum) in FP64: one partial per
+// tile, then per replica the partials are summed in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, const uint8_t* __restrict__ flags,
-                                                    long N, double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, Dev d) {
+  constexpr int tile_nodes = OBS_TILE;
   __shared__ double sh[4][256];
+  const Tile tl = d.otiles[blockIdx.x];
+  const Rep& R = d.reps[tl.rep];
+  const size_t N = (size_t)R.lp.N;
+  const T* Ar = A + (size_t)Q * R.node_off;
+  const uint8_t* fr = d.flags + R.node_off;
+  const int end = min(tl.start + tile_nodes, R.lp.N);
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long)gridDim.x * blockDim.x) {
-    if (flags[c] & F_SOLID) continue;
+  for (int c = tl.start + (int)threadIdx.x; c < end; c += blockDim.x) {
+    if (fr[c] & F_SOLID) continue;
     double f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = (double)A[(size_t)i * N + c] - (DEV ? 0.0 : wgt(i));
+    for (int i = 0; i < Q; ++i) f[i] = (double)Ar[(size_t)i * N + c] - (DEV ? 0.0 : wgt(i));
     double m = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) m += f[i];
@@ -417,93 +458,99 @@ __global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, con
       for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < 4) d.part[4 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// Bead observables + final fluid sums (one block of 256 threads).
-__global__ __launch_bounds__(256) void k_observables(const double* __restrict__ part, int nparts, double nfluid,
-                                                     BeadPtrs b, int nb, Geom g, MdParams P,
-                                                     const Ctrl* __restrict__ ctrl, double* __restrict__ out) {
-  __shared__ double sh[16][256];
+// Block-wide sum of 256 values (fixed tree order); every thread gets it.
+__device__ inline double block_sum(double v, double* sh) {
   int t = threadIdx.x;
-  double acc[16];
-  for (int a = 0; a < 16; ++a) acc[a] = 0.0;
-  for (int k = t; k < nparts; k += 256)
-    for (int a = 0; a < 4; ++a) acc[a] += part[4 * k + a];
-  int an = g.wall_axis >= 0 ? g.wall_axis : 2;
-  // pass 1: kinetic, momentum, normal coordinate, counts, work rates, centres
+  __syncthreads();
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Observables of replica blockIdx.x (one block of 256 threads per replica),
+// out[NOBS * r + k] in the order documented in lbmd.h.
+__global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__ out) {
+  __shared__ double sh[256];
+  const int rep = blockIdx.x;
+  const Rep& R = d.reps[rep];
+  const Geom& g = R.g;
+  const MdParams& P = R.mp;
+  const int t = threadIdx.x;
+  const int nb = P.nb;
+  const int so = R.slot_off;
+  double fl[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = R.tile_begin + t; k < R.tile_end; k += 256)
+    for (int a = 0; a < 4; ++a) fl[a] += d.part[4 * (size_t)k + a];
+  double tot[4];
+  for (int a = 0; a < 4; ++a) tot[a] = block_sum(fl[a], sh);
+  const int an = g.wall_axis >= 0 ? g.wall_axis : 2;
+  double acc[12];
+  for (int a = 0; a < 12; ++a) acc[a] = 0.0;
+  // 0 sum v^2, 1-3 momentum, 4 normal coordinate, 5 translocated, 6 in field,
+  // 7 dW_E, 8 dW_H, 9-11 sum of r over translocated beads
   for (int p = t; p < nb; p += 256) {
-    double v0 = b.v[3 * p], v1 = b.v[3 * p + 1], v2 = b.v[3 * p + 2];
-    double rp[3] = {b.r[3 * p], b.r[3 * p + 1], b.r[3 * p + 2]};
-    acc[4] += v0 * v0 + v1 * v1 + v2 * v2;
-    acc[5] += P.m * v0; acc[6] += P.m * v1; acc[7] += P.m * v2;
+    const int s = so + p;
+    double v0 = d.v[3 * s], v1 = d.v[3 * s + 1], v2 = d.v[3 * s + 2];
+    double rp[3] = {d.r[3 * s], d.r[3 * s + 1], d.r[3 * s + 2]};
+    acc[0] += v0 * v0 + v1 * v1 + v2 * v2;
+    acc[1] += P.m * v0; acc[2] += P.m * v1; acc[3] += P.m * v2;
     double zn = rp[an];
-    acc[8] += zn;
+    acc[4] += zn;
     bool tr = g.wall_axis >= 0 && zn > (double)g.wall_pos;
-    acc[9] += tr ? 1.0 : 0.0;
-    bool res = in_field(g, rp);
-    if (res) { acc[10] += 1.0; acc[15] += P.f_drive * b.v[3 * p + an]; }
-    acc[14] += P.gamma * (v0 * b.up[3 * p] + v1 * b.up[3 * p + 1] + v2 * b.up[3 * p + 2]);
-    if (tr) { acc[11] += rp[0]; acc[12] += rp[1]; acc[13] += rp[2]; }
+    if (tr) { acc[5] += 1.0; acc[9] += rp[0]; acc[10] += rp[1]; acc[11] += rp[2]; }
+    if (in_field(g, rp)) { acc[6] += 1.0; acc[7] += P.f_drive * d.v[3 * s + an]; }
+    acc[8] += P.gamma * (v0 * d.up[3 * s] + v1 * d.up[3 * s + 1] + v2 * d.up[3 * s + 2]);
   }
-  for (int a = 0; a < 16; ++a) sh[a][t] = acc[a];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) for (int a = 0; a < 16; ++a) sh[a][t] += sh[a][t + w];
-    __syncthreads();
-  }
-  __shared__ double res[16];
-  if (t < 16) res[t] = sh[t][0];
-  __syncthreads();
-  // centres of the translocated (T) and untranslocated (U) parts
-  double ntr = res[9];
-  double nun = (double)nb - ntr;
-  double ct[3] = {0, 0, 0}, cu[3] = {0, 0, 0};
-  double acc2[3] = {0, 0, 0};
+  double res[12];
+  for (int a = 0; a < 12; ++a) res[a] = block_sum(acc[a], sh);
+  const double ntr = res[5], nun = (double)nb - ntr;
+  double cu_s[3] = {0.0, 0.0, 0.0};
   for (int p = t; p < nb; p += 256) {
-    bool tr = g.wall_axis >= 0 && b.r[3 * p + an] > (double)g.wall_pos;
-    if (!tr) { acc2[0] += b.r[3 * p]; acc2[1] += b.r[3 * p + 1]; acc2[2] += b.r[3 * p + 2]; }
+    const int s = so + p;
+    bool tr = g.wall_axis >= 0 && d.r[3 * s + an] > (double)g.wall_pos;
+    if (!tr) { cu_s[0] += d.r[3 * s]; cu_s[1] += d.r[3 * s + 1]; cu_s[2] += d.r[3 * s + 2]; }
   }
-  __syncthreads();
-  for (int a = 0; a < 3; ++a) sh[a][t] = acc2[a];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) for (int a = 0; a < 3; ++a) sh[a][t] += sh[a][t + w];
-    __syncthreads();
-  }
+  double ct[3], cu[3];
   for (int a = 0; a < 3; ++a) {
-    ct[a] = ntr > 0 ? res[11 + a] / ntr : 0.0;
-    cu[a] = nun > 0 ? sh[a][0] / nun : 0.0;
+    double su = block_sum(cu_s[a], sh);
+    ct[a] = ntr > 0 ? res[9 + a] / ntr : 0.0;
+    cu[a] = nun > 0 ? su / nun : 0.0;
   }
-  __syncthreads();
   double ru = 0.0, rt = 0.0;
   for (int p = t; p < nb; p += 256) {
-    bool tr = g.wall_axis >= 0 && b.r[3 * p + an] > (double)g.wall_pos;
-    double s = 0.0;
-    for (int a = 0; a < 3; ++a) { double d = b.r[3 * p + a] - (tr ? ct[a] : cu[a]); s += d * d; }
-    if (tr) rt += s; else ru += s;
+    const int s = so + p;
+    bool tr = g.wall_axis >= 0 && d.r[3 * s + an] > (double)g.wall_pos;
+    double q = 0.0;
+    for (int a = 0; a < 3; ++a) { double dd = d.r[3 * s + a] - (tr ? ct[a] : cu[a]); q += dd * dd; }
+    if (tr) rt += q; else ru += q;
   }
-  sh[0][t] = ru; sh[1][t] = rt;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) { sh[0][t] += sh[0][t + w]; sh[1][t] += sh[1][t + w]; }
-    __syncthreads();
-  }
+  ru = block_sum(ru, sh);
+  rt = block_sum(rt, sh);
   if (t == 0) {
-    out[0] = nfluid + res[0];
-    out[1] = res[1]; out[2] = res[2]; out[3] = res[3];
-    out[4] = nb > 0 ? P.m * res[4] / (3.0 * nb) : 0.0;
-    out[5] = res[5]; out[6] = res[6]; out[7] = res[7];
-    out[8] = nb > 0 ? res[8] / nb : 0.0;
-    out[9] = nb > 0 ? ntr / nb : 0.0;
-    out[10] = res[10];
-    double RU = nun > 0 ? sqrt(sh[0][0] / nun) : 0.0;
-    double RT = ntr > 0 ? sqrt(sh[1][0] / ntr) : 0.0;
-    out[11] = RU; out[12] = RT;
-    out[13] = pow(pow(RT, 0.6) + pow(RU, 0.6), 1.0 / 0.6);
-    out[14] = res[14]; out[15] = res[15];
-    for (int a = 16; a < 22; ++a) out[a] = __builtin_nan("");
-    out[22] = (double)ctrl->step;
+    double* o = out + (size_t)NOBS * rep;
+    o[0] = R.nfluid + tot[0];
+    o[1] = tot[1]; o[2] = tot[2]; o[3] = tot[3];
+    o[4] = nb > 0 ? P.m * res[0] / (3.0 * nb) : 0.0;
+    o[5] = res[1]; o[6] = res[2]; o[7] = res[3];
+    o[8] = nb > 0 ? res[4] / nb : 0.0;
+    o[9] = nb > 0 ? ntr / nb : 0.0;
+    o[10] = res[6];
+    double RU = nun > 0 ? sqrt(ru / nun) : 0.0;
+    double RT = ntr > 0 ? sqrt(rt / ntr) : 0.0;
+    o[11] = RU; o[12] = RT;
+    o[13] = pow(pow(RT, 0.6) + pow(RU, 0.6), 1.0 / 0.6);
+    o[14] = res[8]; o[15] = res[7];
+    for (int a = 16; a < 22; ++a) o[a] = __builtin_nan("");
+    o[22] = (double)d.ctrl->step;
   }
 }
 
@@ -524,80 +571,58 @@ void launch_fill_f64(double* p, long n, double v, hipStream_t s) {
 }
 
 template <typename T, bool DEV>
-void launch_lb(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
-               int skip_forced, hipStream_t s) {
-  hipLaunchKernelGGL((k_lb<T, DEV>), dim3(blocks_for(p.N, 256)), dim3(256), 0, s, (const T*)A, (T*)B, flags,
-                     (const T*)force, p, ctrl, skip_forced);
+void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int skip_forced,
+               hipStream_t s) {
+  int gsz = (grid > 0 && grid < ntiles) ? grid : ntiles;
+  hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)gsz), dim3(256), 0, s, (const T*)A, (T*)B, d, ntiles, tile_nodes,
+                     skip_forced);
 }
 
 template <typename T, bool DEV>
-void launch_lb_forced(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
-                      const int* touched, int maxlist, hipStream_t s) {
+void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStream_t s) {
   if (maxlist > 0)
-    hipLaunchKernelGGL((k_lb_forced<T, DEV>), dim3(blocks_for(maxlist, 64)), dim3(64), 0, s, (const T*)A, (T*)B,
-                       flags, (const T*)force, p, ctrl, touched, maxlist);
+    hipLaunchKernelGGL((k_lb_forced<T, DEV>), dim3(blocks_for(maxlist, 64)), dim3(64), 0, s, (const T*)A, (T*)B, d,
+                       maxlist);
 }
 
 template <typename T, bool DEV>
-void launch_gather(const void* A, const uint8_t* flags, const LbParams& p, const Geom& g, const BeadPtrs& b, int nb,
-                   hipStream_t s) {
-  if (nb > 0)
-    hipLaunchKernelGGL((k_gather<T, DEV>), dim3(blocks_for(nb, 64)), dim3(64), 0, s, (const T*)A, flags, p, g, b, nb);
+void launch_gather(const void* A, const Dev& d, int nslots, hipStream_t s) {
+  if (nslots > 0)
+    hipLaunchKernelGGL((k_gather<T, DEV>), dim3(blocks_for(nslots, 64)), dim3(64), 0, s, (const T*)A, d, nslots);
 }
 
-void launch_bead_prep(const BeadPtrs& b, const Geom& g, int nb, int* head, int* next, int* base, uint8_t* flags,
-                      hipStream_t s) {
-  if (nb > 0)
-    hipLaunchKernelGGL(k_bead_prep, dim3(blocks_for(nb, 64)), dim3(64), 0, s, b, g, nb, head, next, base, flags);
+void launch_bead_prep(const Dev& d, int nslots, hipStream_t s) {
+  if (nslots > 0) hipLaunchKernelGGL(k_bead_prep, dim3(blocks_for(nslots, 64)), dim3(64), 0, s, d, nslots);
 }
 
 template <typename T>
-void launch_spread(const BeadPtrs& b, const Geom& g, int nb, const int* head, const int* next, uint8_t* flags,
-                   void* force, int* touched, Ctrl* ctrl, hipStream_t s) {
-  if (nb > 0)
-    hipLaunchKernelGGL((k_spread<T>), dim3(blocks_for(8L * nb, 64)), dim3(64), 0, s, b, g, nb, head, next, flags,
-                       (T*)force, touched, ctrl);
+void launch_spread(const Dev& d, int nslots, hipStream_t s) {
+  if (nslots > 0) hipLaunchKernelGGL((k_spread<T>), dim3(blocks_for(8L * nslots, 64)), dim3(64), 0, s, d, nslots);
 }
 
-void launch_step_end(int nb, const int* base, int* head, const int* touched, uint8_t* flags, Ctrl* ctrl, int advance,
-                     hipStream_t s) {
-  if (nb > 0)
-    hipLaunchKernelGGL(k_step_end, dim3(blocks_for(8L * nb, 256)), dim3(256), 0, s, nb, base, head, touched, flags,
-                       ctrl, advance);
-  hipLaunchKernelGGL(k_step_tick, dim3(1), dim3(1), 0, s, ctrl, advance);
+void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_t s) {
+  long n = nslots > maxlist ? nslots : maxlist;
+  if (n > 0) hipLaunchKernelGGL(k_step_end, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, nslots, maxlist);
+  hipLaunchKernelGGL(k_step_tick, dim3(1), dim3(256), 0, s, d, nrep, nslots > 0 ? 1 : 0);
 }
 
 template <typename T, bool DEV>
-void launch_observables(const void* A, const uint8_t* flags, long N, double nfluid, double* part, int nparts,
-                        const BeadPtrs& b, int nb, const Geom& g, const MdParams& P, const Ctrl* ctrl, double* out,
-                        hipStream_t s) {
-  hipLaunchKernelGGL((k_fluid_sums<T, DEV>), dim3(nparts), dim3(256), 0, s, (const T*)A, flags, N, part);
-  hipLaunchKernelGGL(k_observables, dim3(1), dim3(256), 0, s, part, nparts, nfluid, b, nb, g, P, ctrl, out);
+void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_fluid_sums<T, DEV>), dim3((unsigned)n_otiles), dim3(256), 0, s, (const T*)A, d);
+  hipLaunchKernelGGL(k_observables, dim3((unsigned)nrep), dim3(256), 0, s, d, out);
 }
 
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);
 template void launch_fill_rest<float, true>(void*, long, hipStream_t);
-template void launch_lb<double, false>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*,
-                                       int, hipStream_t);
-template void launch_lb<float, true>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*, int,
-                                     hipStream_t);
-template void launch_lb_forced<double, false>(const void*, void*, const uint8_t*, const void*, const LbParams&,
-                                              Ctrl*, const int*, int, hipStream_t);
-template void launch_lb_forced<float, true>(const void*, void*, const uint8_t*, const void*, const LbParams&, Ctrl*,
-                                            const int*, int, hipStream_t);
-template void launch_gather<double, false>(const void*, const uint8_t*, const LbParams&, const Geom&, const BeadPtrs&,
-                                           int, hipStream_t);
-template void launch_gather<float, true>(const void*, const uint8_t*, const LbParams&, const Geom&, const BeadPtrs&,
-                                         int, hipStream_t);
-template void launch_spread<double>(const BeadPtrs&, const Geom&, int, const int*, const int*, uint8_t*, void*, int*,
-                                    Ctrl*, hipStream_t);
-template void launch_spread<float>(const BeadPtrs&, const Geom&, int, const int*, const int*, uint8_t*, void*, int*,
-                                   Ctrl*, hipStream_t);
-template void launch_observables<double, false>(const void*, const uint8_t*, long, double, double*, int,
-                                                const BeadPtrs&, int, const Geom&, const MdParams&, const Ctrl*,
-                                                double*, hipStream_t);
-template void launch_observables<float, true>(const void*, const uint8_t*, long, double, double*, int,
-                                              const BeadPtrs&, int, const Geom&, const MdParams&, const Ctrl*,
-                                              double*, hipStream_t);
+template void launch_lb<double, false>(const void*, void*, const Dev&, int, int, int, int, hipStream_t);
+template void launch_lb<float, true>(const void*, void*, const Dev&, int, int, int, int, hipStream_t);
+template void launch_lb_forced<double, false>(const void*, void*, const Dev&, int, hipStream_t);
+template void launch_lb_forced<float, true>(const void*, void*, const Dev&, int, hipStream_t);
+template void launch_gather<double, false>(const void*, const Dev&, int, hipStream_t);
+template void launch_gather<float, true>(const void*, const Dev&, int, hipStream_t);
+template void launch_spread<double>(const Dev&, int, hipStream_t);
+template void launch_spread<float>(const Dev&, int, hipStream_t);
+template void launch_observables<double, false>(const void*, const Dev&, int, int, double*, hipStream_t);
+template void launch_observables<float, true>(const void*, const Dev&, int, int, double*, hipStream_t);
 
 }  // namespace lbmd

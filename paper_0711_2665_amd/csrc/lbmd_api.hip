@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -49,64 +50,134 @@ int take_acc(const char* where) {
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline long round_up(long x, long m) { return (x + m - 1) / m * m; }
 
-constexpr int NPARTS = 1024;
+constexpr int NODE_ALIGN = 64;      // replica node offsets are multiples of this
+
+// Packing of R replicas into one buffer set (see lbmd_kernels.h).
+struct Packing {
+  std::vector<long> node_off;       // per replica
+  std::vector<int> slot_off;        // per replica
+  long nodes = 0;                   // total packed nodes
+  int slots = 0;                    // total bead slots
+  int slots_alloc = 1;              // slots, at least 1 (array sizing)
+  long sweep_tiles_max = 0;         // tiles of the sweep at TILE_MIN
+  long obs_tiles = 0;
+};
+
+Packing packing(const lb_desc* d, int nrep) {
+  Packing pk;
+  for (int r = 0; r < nrep; ++r) {
+    long N = (long)d[r].nx * d[r].ny * d[r].nz;
+    pk.node_off.push_back(pk.nodes);
+    pk.slot_off.push_back(pk.slots);
+    pk.nodes += round_up(N, NODE_ALIGN);
+    pk.slots += (int)round_up(d[r].nb, MD_BPB);
+    pk.sweep_tiles_max += (N + TILE_MIN - 1) / TILE_MIN;
+    pk.obs_tiles += (N + OBS_TILE - 1) / OBS_TILE;
+  }
+  pk.slots_alloc = pk.slots > 0 ? pk.slots : 1;
+  return pk;
+}
 
 struct WorkLayout {
-  size_t ctrl, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi;
+  size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
+      tX, notdone;
   size_t total;
 };
 
-WorkLayout work_layout(const lb_desc* d) {
-  long N = (long)d->nx * d->ny * d->nz;
-  int nb = d->nb;
+WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   WorkLayout w;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
-  size_t nbs = (size_t)(nb > 0 ? nb : 1);
+  const size_t ns = (size_t)pk.slots_alloc;
+  const size_t R = (size_t)nrep;
   w.ctrl = take(sizeof(Ctrl));
-  w.head = take(sizeof(int) * (size_t)N);
-  w.next = take(sizeof(int) * nbs);
-  w.base = take(sizeof(int) * nbs);
-  w.touched = take(sizeof(int) * 8 * nbs);
-  w.nbr = take(sizeof(int) * MAXNBR * nbs);
-  w.ncnt = take(sizeof(int) * nbs);
-  w.rb = take(sizeof(uint32_t) * 4);
-  w.rmid0 = take(sizeof(double) * 3 * nbs);
-  w.rmid1 = take(sizeof(double) * 3 * nbs);
-  w.ref = take(sizeof(double) * 3 * nbs);
-  w.part = take(sizeof(double) * 4 * NPARTS);
-  w.xi = take(sizeof(double) * 3 * nbs * (size_t)(d->n_sub > 0 ? d->n_sub : 1));
+  w.reps = take(sizeof(Rep) * R);
+  w.tiles = take(sizeof(Tile) * (size_t)pk.sweep_tiles_max);
+  w.otiles = take(sizeof(Tile) * (size_t)pk.obs_tiles);
+  w.slot_rep = take(sizeof(int) * ns);
+  w.head = take(sizeof(int) * (size_t)pk.nodes);
+  w.next = take(sizeof(int) * ns);
+  w.base = take(sizeof(int) * ns);
+  w.touched = take(sizeof(int2) * 8 * ns);
+  w.nbr = take(sizeof(int) * MAXNBR * ns);
+  w.ncnt = take(sizeof(int) * ns);
+  w.rb = take(sizeof(uint32_t) * 4 * R);
+  w.rmid0 = take(sizeof(double) * 3 * ns);
+  w.rmid1 = take(sizeof(double) * 3 * ns);
+  w.ref = take(sizeof(double) * 3 * ns);
+  w.part = take(sizeof(double) * 4 * (size_t)pk.obs_tiles);
+  w.xi = take(sizeof(double) * 3 * ns * (size_t)d[0].n_sub);
+  w.tX = take(sizeof(int64_t) * R);
+  w.notdone = take(sizeof(uint32_t) * R);
   w.total = o;
   return w;
 }
 
-int validate(const lb_desc* d) {
-  if (!d) return fail(LB_ERR_ARG, "null description");
-  if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(LB_ERR_ARG, "extents must be positive");
+size_t elem_size(const lb_desc* d) { return d->precision == LB_FP64 ? sizeof(double) : sizeof(float); }
+
+// Byte layout of the state buffer: populations, then r and v of every slot,
+// then the step counter, then the per-replica translocation steps.
+struct StateLayout {
+  size_t pops, r, v, step, tX, total;
+};
+StateLayout state_layout(const lb_desc* d, int nrep, const Packing& pk) {
+  StateLayout s;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align256(bytes); return at; };
+  s.pops = take(elem_size(d) * Q * (size_t)pk.nodes);
+  s.r = take(sizeof(double) * 3 * (size_t)pk.slots_alloc);
+  s.v = take(sizeof(double) * 3 * (size_t)pk.slots_alloc);
+  s.step = take(sizeof(uint64_t));
+  s.tX = take(sizeof(int64_t) * (size_t)nrep);
+  s.total = o;
+  return s;
+}
+
+int validate_one(const lb_desc* d, int r) {
+  if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return fail(LB_ERR_ARG, "replica %d: extents must be positive", r);
   long N = (long)d->nx * d->ny * d->nz;
-  if (N * (long)Q > 2147483647L) return fail(LB_ERR_ARG, "lattice too large: 19 N must fit in 31 bits");
-  if (d->precision != LB_FP64 && d->precision != LB_FP32_DEV) return fail(LB_ERR_ARG, "unknown precision %d", d->precision);
-  if (!(d->tau > 0.5)) return fail(LB_ERR_ARG, "tau must exceed 1/2 (got %g)", d->tau);
+  if (N * (long)Q > 2147483647L) return fail(LB_ERR_ARG, "replica %d: lattice too large: 19 N must fit in 31 bits", r);
+  if (d->precision != LB_FP64 && d->precision != LB_FP32_DEV)
+    return fail(LB_ERR_ARG, "replica %d: unknown precision %d", r, d->precision);
+  if (!(d->tau > 0.5)) return fail(LB_ERR_ARG, "replica %d: tau must exceed 1/2 (got %g)", r, d->tau);
   for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(d->g[a])) return fail(LB_ERR_ARG, "body force must be finite");
-  if (d->wall_axis < -1 || d->wall_axis > 2) return fail(LB_ERR_ARG, "wall_axis must be -1, 0, 1 or 2");
+    if (!std::isfinite(d->g[a])) return fail(LB_ERR_ARG, "replica %d: body force must be finite", r);
+  if (d->wall_axis < -1 || d->wall_axis > 2) return fail(LB_ERR_ARG, "replica %d: wall_axis must be -1, 0, 1 or 2", r);
   if (d->wall_axis >= 0) {
     int n = d->wall_axis == 0 ? d->nx : (d->wall_axis == 1 ? d->ny : d->nz);
-    if (d->wall_pos < 2 || d->wall_pos > n - 3) return fail(LB_ERR_ARG, "wall plane must lie in [2, n-3]");
+    if (d->wall_pos < 2 || d->wall_pos > n - 3) return fail(LB_ERR_ARG, "replica %d: wall plane must lie in [2, n-3]", r);
     int t0 = d->wall_axis == 0 ? d->ny : d->nx;
     int t1 = d->wall_axis == 2 ? d->ny : d->nz;
-    if (d->pore_h < 0 || d->pore_h > t0 || d->pore_h > t1) return fail(LB_ERR_ARG, "pore wider than the wall");
+    if (d->pore_h < 0 || d->pore_h > t0 || d->pore_h > t1) return fail(LB_ERR_ARG, "replica %d: pore wider than the wall", r);
   }
-  if (d->nb < 0) return fail(LB_ERR_ARG, "negative bead count");
-  if (d->n_sub < 1) return fail(LB_ERR_ARG, "n_sub must be >= 1");
+  if (d->nb < 0) return fail(LB_ERR_ARG, "replica %d: negative bead count", r);
+  if (d->n_sub < 1) return fail(LB_ERR_ARG, "replica %d: n_sub must be >= 1", r);
   if (d->nb > 0) {
-    if (!(d->mass > 0.0)) return fail(LB_ERR_ARG, "bead mass must be positive");
-    if (!(d->gamma >= 0.0) || !(d->kT >= 0.0)) return fail(LB_ERR_ARG, "gamma and kT must be >= 0");
-    if (!(d->rc > 0.0) || d->rc > 2.0) return fail(LB_ERR_ARG, "rc must lie in (0, 2]");
-    if (!(d->sigma > 0.0)) return fail(LB_ERR_ARG, "sigma must be positive");
-    if ((long)d->nb * 8 > 2147483647L / 8) return fail(LB_ERR_ARG, "too many beads");
+    if (!(d->mass > 0.0)) return fail(LB_ERR_ARG, "replica %d: bead mass must be positive", r);
+    if (!(d->gamma >= 0.0) || !(d->kT >= 0.0)) return fail(LB_ERR_ARG, "replica %d: gamma and kT must be >= 0", r);
+    if (!(d->rc > 0.0) || d->rc > 2.0) return fail(LB_ERR_ARG, "replica %d: rc must lie in (0, 2]", r);
+    if (!(d->sigma > 0.0)) return fail(LB_ERR_ARG, "replica %d: sigma must be positive", r);
+    if ((long)d->nb > (1L << 24)) return fail(LB_ERR_ARG, "replica %d: too many beads", r);
   }
+  return LB_OK;
+}
+
+int validate(const lb_desc* d, int nrep) {
+  if (!d) return fail(LB_ERR_ARG, "null description");
+  if (nrep < 1 || nrep > MAX_REPLICAS) return fail(LB_ERR_ARG, "replica count must lie in [1, %d]", MAX_REPLICAS);
+  long nodes = 0, slots = 0;
+  for (int r = 0; r < nrep; ++r) {
+    int rc = validate_one(&d[r], r);
+    if (rc) return rc;
+    if (d[r].precision != d[0].precision) return fail(LB_ERR_ARG, "replica %d: all replicas need one precision", r);
+    if (d[r].n_sub != d[0].n_sub) return fail(LB_ERR_ARG, "replica %d: all replicas need one n_sub", r);
+    nodes += round_up((long)d[r].nx * d[r].ny * d[r].nz, NODE_ALIGN);
+    slots += round_up(d[r].nb, MD_BPB);
+  }
+  if (nodes * (long)Q > 2147483647L * 8L) return fail(LB_ERR_ARG, "ensemble too large");
+  if (slots * 8L > 2147483647L / 8) return fail(LB_ERR_ARG, "too many beads in the ensemble");
   return LB_OK;
 }
 
@@ -140,135 +211,8 @@ void spv_coefficients(MdParams& P, double gamma, double kT, double h) {
   P.sig = kT > 0.0 ? std::sqrt(var) : 0.0;
 }
 
-}  // namespace
-
-struct lb_ctx {
-  lb_desc d;
-  lb_buffers b;
-  hipStream_t s;
-  int cur;          // 0: pops_a holds the current populations
-  Geom g;
-  LbParams lp;
-  MdParams mp;
-  BeadPtrs bp;
-  MdWork mw;
-  WorkLayout wl;
-  Ctrl* ctrl;
-  int* head;
-  int* next;
-  int* base;
-  int* touched;
-  double* part;
-  double nfluid;
-  int64_t steps;
-  int64_t last_touched = 0;
-  bool dev;
-  // second stream for the sweep over the nodes without bead force, which
-  // runs concurrently with the bead phase; fork/join events
-  hipStream_t s2 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
-  // kernel timing (lb_profile_start / lb_profile_stop)
-  std::vector<hipEvent_t> ev;   // 4 per recorded step: bead start/end, LB start/end
-  int prof_max = 0;
-  int prof_n = 0;
-  bool prof_on = false;
-};
-
-namespace {
-
-void* cur_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_a : c->b.pops_b; }
-void* other_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_b : c->b.pops_a; }
-
-// Event slot k of the current recorded step (0, 1: bead phase; 2, 3: sweep),
-// recorded on stream st.
-void prof_mark(lb_ctx* c, int k, hipStream_t st) {
-  if (!c->prof_on || c->prof_n >= c->prof_max) return;
-  acc(hipEventRecord(c->ev[4 * (size_t)c->prof_n + k], st));
-}
-void prof_next(lb_ctx* c) {
-  if (c->prof_on && c->prof_n < c->prof_max) ++c->prof_n;
-}
-
-void launch_lb_any(lb_ctx* c, int skip_forced, hipStream_t st) {
-  if (c->dev)
-    launch_lb<float, true>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl,
-                           skip_forced, st);
-  else
-    launch_lb<double, false>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp, c->ctrl,
-                             skip_forced, st);
-}
-
-void launch_lb_forced_any(lb_ctx* c, hipStream_t st) {
-  int maxlist = 8 * c->d.nb;
-  if (c->dev)
-    launch_lb_forced<float, true>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp,
-                                  c->ctrl, c->touched, maxlist, st);
-  else
-    launch_lb_forced<double, false>(cur_pops(c), other_pops(c), (const uint8_t*)c->b.flags, c->b.force, c->lp,
-                                    c->ctrl, c->touched, maxlist, st);
-}
-
-}  // namespace
-
-extern "C" {
-
-const char* lb_last_error(void) { return g_last_error.c_str(); }
-void lb_destroy(lb_ctx* ctx);
-
-int lb_buffer_sizes(const lb_desc* d, lb_sizes* out) {
-  int rc = validate(d);
-  if (rc) return rc;
-  if (!out) return fail(LB_ERR_ARG, "null output");
-  long N = (long)d->nx * d->ny * d->nz;
-  size_t es = d->precision == LB_FP64 ? sizeof(double) : sizeof(float);
-  size_t nbs = (size_t)(d->nb > 0 ? d->nb : 1);
-  out->pops_bytes = align256(es * Q * (size_t)N);
-  out->flags_bytes = align256((size_t)N);
-  out->force_bytes = align256(es * 3 * (size_t)N);
-  out->beads_bytes = align256(sizeof(double) * 15 * nbs);
-  out->work_bytes = work_layout(d).total;
-  out->state_bytes = align256(es * Q * (size_t)N) + align256(sizeof(double) * 6 * nbs) + 256;
-  return LB_OK;
-}
-
-int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const double* v0_host, void* stream,
-            lb_ctx** out) {
-  int rc = validate(d);
-  if (rc) return rc;
-  if (!b || !out) return fail(LB_ERR_ARG, "null buffers or output");
-  const void* ptrs[6] = {b->pops_a, b->pops_b, b->flags, b->force, b->beads, b->work};
-  for (int k = 0; k < 6; ++k) {
-    if (!ptrs[k]) return fail(LB_ERR_ARG, "buffer %d is NULL", k);
-    if (((uintptr_t)ptrs[k]) & 255) return fail(LB_ERR_ARG, "buffer %d is not 256-byte aligned", k);
-  }
-  if (d->nb > 0 && !r0_host) return fail(LB_ERR_ARG, "bead positions required");
-  for (long k = 0; k < 3L * d->nb; ++k) {
-    if (!std::isfinite(r0_host[k]) || (v0_host && !std::isfinite(v0_host[k])))
-      return fail(LB_ERR_ARG, "non-finite bead state");
-  }
-  lb_ctx* c = new lb_ctx();
-  c->d = *d;
-  c->b = *b;
-  c->s = (hipStream_t)stream;
-  {
-    hipError_t e1 = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
-    hipError_t e2 = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
-    hipError_t e3 = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-      lb_destroy(c);
-      return fail(LB_ERR_DEVICE, "stream/event creation failed");
-    }
-  }
-  c->cur = 0;
-  c->dev = d->precision == LB_FP32_DEV;
-  c->g = make_geom(d);
-  long N = c->g.N;
-  c->lp.nx = d->nx; c->lp.ny = d->ny; c->lp.nz = d->nz; c->lp.nxy = d->nx * d->ny; c->lp.N = (int)N;
-  c->lp.omega = 1.0 / d->tau;
-  for (int a = 0; a < 3; ++a) c->lp.g[a] = d->g[a];
-  c->lp.has_g = (d->g[0] != 0.0 || d->g[1] != 0.0 || d->g[2] != 0.0) ? 1 : 0;
-
-  MdParams& P = c->mp;
+MdParams make_md(const lb_desc* d) {
+  MdParams P;
   std::memset(&P, 0, sizeof(P));
   P.nb = d->nb;
   P.n_sub = d->n_sub;
@@ -283,36 +227,17 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
   P.rlist2 = (d->rc + SKIN) * (d->rc + SKIN);
   P.halfskin2 = (0.5 * SKIN) * (0.5 * SKIN);
   spv_coefficients(P, d->gamma, d->kT, h);
+  return P;
+}
 
-  size_t nbs = (size_t)(d->nb > 0 ? d->nb : 1);
-  double* beads = (double*)b->beads;
-  c->bp.r = beads; c->bp.v = beads + 3 * nbs; c->bp.up = beads + 6 * nbs; c->bp.J = beads + 9 * nbs;
-  c->bp.rs = beads + 12 * nbs;
-  c->wl = work_layout(d);
-  char* w = (char*)b->work;
-  c->ctrl = (Ctrl*)(w + c->wl.ctrl);
-  c->head = (int*)(w + c->wl.head);
-  c->next = (int*)(w + c->wl.next);
-  c->base = (int*)(w + c->wl.base);
-  c->touched = (int*)(w + c->wl.touched);
-  c->part = (double*)(w + c->wl.part);
-  c->mw.rmid0 = (double*)(w + c->wl.rmid0);
-  c->mw.rmid1 = (double*)(w + c->wl.rmid1);
-  c->mw.ref = (double*)(w + c->wl.ref);
-  c->mw.nbr = (int*)(w + c->wl.nbr);
-  c->mw.ncnt = (int*)(w + c->wl.ncnt);
-  c->mw.rb = (uint32_t*)(w + c->wl.rb);
-  c->mw.xi = (double*)(w + c->wl.xi);
-  c->steps = 0;
-
-  // geometry flags on the host (Sec. 4: wall plane with a square pore)
-  std::vector<uint8_t> fl((size_t)N, 0);
-  const Geom& g = c->g;
+// Solid / near-wall flags of one replica (Sec. 4: wall plane with a square
+// pore); returns the number of fluid nodes.
+long build_flags(const Geom& g, uint8_t* fl) {
   long nfluid = 0;
   for (int z = 0; z < g.nz; ++z)
     for (int y = 0; y < g.ny; ++y)
       for (int x = 0; x < g.nx; ++x)
-        if (site_solid(g, x, y, z)) fl[(size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z)] = F_SOLID;
+        fl[(size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z)] = site_solid(g, x, y, z) ? F_SOLID : 0;
   for (int z = 0; z < g.nz; ++z)
     for (int y = 0; y < g.ny; ++y)
       for (int x = 0; x < g.nx; ++x) {
@@ -322,45 +247,402 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
         for (int i = 1; i < Q; ++i)
           if (site_solid(g, x - cx(i), y - cy(i), z - cz(i))) { fl[cidx] |= F_NEAR; break; }
       }
-  c->nfluid = (double)nfluid;
+  return nfluid;
+}
 
-  hipError_t e = hipMemcpyAsync(b->flags, fl.data(), (size_t)N, hipMemcpyHostToDevice, c->s);
-  if (e != hipSuccess) { lb_destroy(c); return fail(LB_ERR_DEVICE, "flag upload: %s", hipGetErrorString(e)); }
-  if (c->dev) {
-    launch_fill_rest<float, true>(b->pops_a, N, c->s);
-    launch_fill_rest<float, true>(b->pops_b, N, c->s);
-  } else {
-    launch_fill_rest<double, false>(b->pops_a, N, c->s);
-    launch_fill_rest<double, false>(b->pops_b, N, c->s);
+}  // namespace
+
+// Sweep configuration: tile size, tile order and grid of the K1 launch.
+struct SweepCfg {
+  int tile_nodes = TILE_MIN;
+  int order = 0;      // 0: replica-major; 1: XCD-chunked (see tile_table)
+  int grid = 0;       // 0: one workgroup per tile; else persistent grid-stride
+};
+
+struct lb_ctx {
+  std::vector<lb_desc> d;
+  int nrep = 1;
+  lb_buffers b;
+  hipStream_t s;
+  int cur;          // 0: pops_a holds the current populations
+  bool dev;
+  int n_sub;
+  Packing pk;
+  WorkLayout wl;
+  StateLayout sl;
+  std::vector<Rep> reps;
+  Dev D;
+  int nslots = 0;
+  int maxlist = 0;
+  bool any_noise = false;
+  SweepCfg sweep;
+  int ntiles = 0;
+  int64_t steps = 0;
+  // second stream for the sweep over the nodes without bead force, which
+  // runs concurrently with the bead phase; fork/join events
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  // graph of two coupled steps, starting at population parity graph_cur
+  hipStream_t scap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_cur = -1;
+  bool capturing = false;
+  // kernel timing (lb_profile_start / lb_profile_stop)
+  std::vector<hipEvent_t> ev;   // 4 per recorded step: bead start/end, LB start/end
+  int prof_max = 0;
+  int prof_n = 0;
+  bool prof_on = false;
+};
+
+namespace {
+
+void* cur_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_a : c->b.pops_b; }
+void* other_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_b : c->b.pops_a; }
+
+// Sweep tiles in launch order.  Order 0 lists each replica's tiles in node
+// order.  Order 1 deals the same list into 8 contiguous chunks and
+// interleaves them, so that workgroup b (which the dispatcher places on XCD
+// b mod 8) takes chunk b mod 8: neighbouring tiles then run on one XCD and
+// share its L2.
+std::vector<Tile> tile_table(const lb_ctx* c, const SweepCfg& sc) {
+  std::vector<Tile> t;
+  for (int r = 0; r < c->nrep; ++r) {
+    int N = c->reps[r].lp.N;
+    for (int st = 0; st < N; st += sc.tile_nodes) t.push_back(Tile{r, st});
   }
-  acc(hipMemsetAsync(b->force, 0, (c->dev ? sizeof(float) : sizeof(double)) * 3 * (size_t)N, c->s));
-  acc(hipMemsetAsync(b->beads, 0, sizeof(double) * 15 * nbs, c->s));
-  acc(hipMemsetAsync(c->ctrl, 0, sizeof(Ctrl), c->s));
-  launch_fill_i32(c->head, N, -1, c->s);
-  launch_fill_f64(c->mw.ref, 3L * (long)nbs, 1e300, c->s);
-  acc(hipMemsetAsync(c->mw.ncnt, 0, sizeof(int) * nbs, c->s));
-  acc(hipMemsetAsync(c->mw.rb, 0, 16, c->s));
-  launch_md_invalidate(c->mw, c->s);
-  if (d->nb > 0) {
-    acc(hipMemcpyAsync(c->bp.r, r0_host, sizeof(double) * 3 * d->nb, hipMemcpyHostToDevice, c->s));
-    if (v0_host) acc(hipMemcpyAsync(c->bp.v, v0_host, sizeof(double) * 3 * d->nb, hipMemcpyHostToDevice, c->s));
+  if (sc.order == 1 && t.size() >= 16) {
+    const size_t n = t.size(), nch = 8, per = (n + nch - 1) / nch;
+    std::vector<Tile> o;
+    o.reserve(n);
+    for (size_t k = 0; k < per; ++k)
+      for (size_t ch = 0; ch < nch; ++ch) {
+        size_t i = ch * per + k;
+        if (i < n) o.push_back(t[i]);
+      }
+    t.swap(o);
   }
-  e = hipStreamSynchronize(c->s);
-  if (e != hipSuccess) { lb_destroy(c); return fail(LB_ERR_DEVICE, "init: %s", hipGetErrorString(e)); }
+  return t;
+}
+
+int upload_tiles(lb_ctx* c, const SweepCfg& sc) {
+  if (sc.tile_nodes < TILE_MIN || sc.tile_nodes % TILE_MIN) return fail(LB_ERR_ARG, "tile size must be a multiple of %d", TILE_MIN);
+  std::vector<Tile> t = tile_table(c, sc);
+  if ((long)t.size() > c->pk.sweep_tiles_max) return fail(LB_ERR_ARG, "tile table overflow");
+  hipError_t e = hipMemcpyAsync((char*)c->b.work + c->wl.tiles, t.data(), sizeof(Tile) * t.size(),
+                                hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);
+  if (e != hipSuccess) return fail(LB_ERR_DEVICE, "tile upload: %s", hipGetErrorString(e));
+  c->sweep = sc;
+  c->ntiles = (int)t.size();
+  return LB_OK;
+}
+
+// Event slot k of the current recorded step (0, 1: bead phase; 2, 3: sweep),
+// recorded on stream st.
+void prof_mark(lb_ctx* c, int k, hipStream_t st) {
+  if (c->capturing || !c->prof_on || c->prof_n >= c->prof_max) return;
+  acc(hipEventRecord(c->ev[4 * (size_t)c->prof_n + k], st));
+}
+void prof_next(lb_ctx* c) {
+  if (!c->capturing && c->prof_on && c->prof_n < c->prof_max) ++c->prof_n;
+}
+
+void sweep(lb_ctx* c, int skip_forced, hipStream_t st) {
+  if (c->dev)
+    launch_lb<float, true>(cur_pops(c), other_pops(c), c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid,
+                           skip_forced, st);
+  else
+    launch_lb<double, false>(cur_pops(c), other_pops(c), c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid,
+                             skip_forced, st);
+}
+
+// One fluid-only step on stream st.
+void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
+  prof_mark(c, 0, st);
+  prof_mark(c, 1, st);
+  prof_mark(c, 2, st);
+  sweep(c, 0, st);
+  prof_mark(c, 3, st);
+  launch_step_end(c->D, 0, 0, c->nrep, st);
+  c->cur ^= 1;
+  prof_next(c);
+}
+
+// One coupled step on stream st: the stencil nodes of r(n) are marked first;
+// the sweep over all other nodes then runs on the second stream while the
+// beads move; the marked nodes are updated once the bead force is spread.
+void enqueue_coupled_step(lb_ctx* c, hipStream_t st) {
+  if (c->nslots == 0) {
+    enqueue_lb_step(c, st);
+    return;
+  }
+  const Dev& D = c->D;
+  prof_mark(c, 0, st);
+  launch_bead_prep(D, c->nslots, st);
+  acc(hipEventRecord(c->fork, st));
+  acc(hipStreamWaitEvent(c->s2, c->fork, 0));
+  prof_mark(c, 2, c->s2);
+  sweep(c, 1, c->s2);
+  prof_mark(c, 3, c->s2);
+  acc(hipEventRecord(c->join, c->s2));
+  if (c->dev) launch_gather<float, true>(cur_pops(c), D, c->nslots, st);
+  else launch_gather<double, false>(cur_pops(c), D, c->nslots, st);
+  MdOverride none{};
+  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, c->any_noise ? 1 : 0, none, st);
+  if (c->dev) launch_spread<float>(D, c->nslots, st);
+  else launch_spread<double>(D, c->nslots, st);
+  if (c->dev) launch_lb_forced<float, true>(cur_pops(c), other_pops(c), D, c->maxlist, st);
+  else launch_lb_forced<double, false>(cur_pops(c), other_pops(c), D, c->maxlist, st);
+  prof_mark(c, 1, st);
+  acc(hipStreamWaitEvent(st, c->join, 0));
+  launch_step_end(D, c->nslots, c->maxlist, c->nrep, st);
+  c->cur ^= 1;
+  prof_next(c);
+}
+
+void drop_graph(lb_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_cur = -1;
+}
+
+// Captures two coupled steps (so that the population parity returns to the
+// start) into a graph.  Every per-step quantity the kernels need (step
+// counter, forced-node count) lives in device memory, and no memset is
+// recorded, so replays are equivalent to eager steps.
+int build_graph(lb_ctx* c) {
+  drop_graph(c);
+  const int cur0 = c->cur;
+  c->capturing = true;
+  hipError_t e = hipStreamBeginCapture(c->scap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->capturing = false;
+    return fail(LB_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+  }
+  enqueue_coupled_step(c, c->scap);
+  enqueue_coupled_step(c, c->scap);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->scap, &g);
+  c->capturing = false;
+  c->cur = cur0;
+  int rc = take_acc("graph capture");
+  if (e2 != hipSuccess || rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : fail(LB_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e2));
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(LB_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  c->graph = g;
+  c->gexec = x;
+  c->graph_cur = cur0;
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_last_error.c_str(); }
+void lb_destroy(lb_ctx* ctx);
+
+int lb_ensemble_sizes(const lb_desc* d, int nrep, lb_sizes* out) {
+  int rc = validate(d, nrep);
+  if (rc) return rc;
+  if (!out) return fail(LB_ERR_ARG, "null output");
+  Packing pk = packing(d, nrep);
+  size_t es = elem_size(d);
+  out->pops_bytes = align256(es * Q * (size_t)pk.nodes);
+  out->flags_bytes = align256((size_t)pk.nodes);
+  out->force_bytes = align256(es * 3 * (size_t)pk.nodes);
+  out->beads_bytes = align256(sizeof(double) * 15 * (size_t)pk.slots_alloc);
+  out->work_bytes = work_layout(d, nrep, pk).total;
+  out->state_bytes = state_layout(d, nrep, pk).total;
+  out->nodes = (size_t)pk.nodes;
+  out->bead_slots = (size_t)pk.slots_alloc;
+  return LB_OK;
+}
+
+int lb_buffer_sizes(const lb_desc* d, lb_sizes* out) { return lb_ensemble_sizes(d, 1, out); }
+
+int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const double* r0_host, const double* v0_host,
+                     void* stream, lb_ctx** out) {
+  int rc = validate(d, nrep);
+  if (rc) return rc;
+  if (!b || !out) return fail(LB_ERR_ARG, "null buffers or output");
+  const void* ptrs[6] = {b->pops_a, b->pops_b, b->flags, b->force, b->beads, b->work};
+  for (int k = 0; k < 6; ++k) {
+    if (!ptrs[k]) return fail(LB_ERR_ARG, "buffer %d is NULL", k);
+    if (((uintptr_t)ptrs[k]) & 255) return fail(LB_ERR_ARG, "buffer %d is not 256-byte aligned", k);
+  }
+  long nb_total = 0;
+  for (int r = 0; r < nrep; ++r) nb_total += d[r].nb;
+  if (nb_total > 0 && !r0_host) return fail(LB_ERR_ARG, "bead positions required");
+  for (long k = 0; k < 3 * nb_total; ++k) {
+    if (!std::isfinite(r0_host[k]) || (v0_host && !std::isfinite(v0_host[k])))
+      return fail(LB_ERR_ARG, "non-finite bead state");
+  }
+  lb_ctx* c = new lb_ctx();
+  c->d.assign(d, d + nrep);
+  c->nrep = nrep;
+  c->b = *b;
+  c->s = (hipStream_t)stream;
+  {
+    hipError_t e1 = hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking);
+    hipError_t e2 = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    hipError_t e3 = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+    hipError_t e4 = hipStreamCreateWithFlags(&c->scap, hipStreamNonBlocking);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+      lb_destroy(c);
+      return fail(LB_ERR_DEVICE, "stream/event creation failed");
+    }
+  }
+  c->cur = 0;
+  c->dev = d[0].precision == LB_FP32_DEV;
+  c->n_sub = d[0].n_sub;
+  c->pk = packing(d, nrep);
+  c->wl = work_layout(d, nrep, c->pk);
+  c->sl = state_layout(d, nrep, c->pk);
+  c->nslots = c->pk.slots;
+  c->maxlist = 8 * c->nslots;
+  const size_t ns = (size_t)c->pk.slots_alloc;
+  const long nodes = c->pk.nodes;
+
+  // replica table, flags, slot map
+  std::vector<uint8_t> fl((size_t)nodes, F_SOLID);   // alignment padding is solid
+  std::vector<int> slot_rep(ns, 0);
+  std::vector<Tile> ot;
+  c->reps.resize(nrep);
+  for (int r = 0; r < nrep; ++r) {
+    Rep& R = c->reps[r];
+    std::memset(&R, 0, sizeof(Rep));
+    R.g = make_geom(&d[r]);
+    R.lp.nx = d[r].nx; R.lp.ny = d[r].ny; R.lp.nz = d[r].nz; R.lp.nxy = d[r].nx * d[r].ny;
+    R.lp.N = (int)R.g.N;
+    R.lp.omega = 1.0 / d[r].tau;
+    for (int a = 0; a < 3; ++a) R.lp.g[a] = d[r].g[a];
+    R.lp.has_g = (d[r].g[0] != 0.0 || d[r].g[1] != 0.0 || d[r].g[2] != 0.0) ? 1 : 0;
+    R.mp = make_md(&d[r]);
+    if (R.mp.nb > 0 && R.mp.sig != 0.0) c->any_noise = true;
+    R.node_off = c->pk.node_off[r];
+    R.slot_off = c->pk.slot_off[r];
+    R.nslot = (int)round_up(d[r].nb, MD_BPB);
+    for (int k = 0; k < R.nslot; ++k) slot_rep[(size_t)R.slot_off + k] = r;
+    R.nfluid = (double)build_flags(R.g, fl.data() + R.node_off);
+    R.tile_begin = (int)ot.size();
+    for (int st = 0; st < R.lp.N; st += OBS_TILE) ot.push_back(Tile{r, st});
+    R.tile_end = (int)ot.size();
+  }
+
+  char* w = (char*)b->work;
+  Dev& D = c->D;
+  std::memset(&D, 0, sizeof(Dev));
+  D.reps = (const Rep*)(w + c->wl.reps);
+  D.tiles = (const Tile*)(w + c->wl.tiles);
+  D.otiles = (const Tile*)(w + c->wl.otiles);
+  D.flags = (uint8_t*)b->flags;
+  D.force = b->force;
+  double* beads = (double*)b->beads;
+  D.r = beads; D.v = beads + 3 * ns; D.up = beads + 6 * ns; D.J = beads + 9 * ns; D.rs = beads + 12 * ns;
+  D.slot_rep = (const int*)(w + c->wl.slot_rep);
+  D.head = (int*)(w + c->wl.head);
+  D.next = (int*)(w + c->wl.next);
+  D.base = (int*)(w + c->wl.base);
+  D.touched = (int2*)(w + c->wl.touched);
+  D.nbr = (int*)(w + c->wl.nbr);
+  D.ncnt = (int*)(w + c->wl.ncnt);
+  D.ref = (double*)(w + c->wl.ref);
+  D.rmid0 = (double*)(w + c->wl.rmid0);
+  D.rmid1 = (double*)(w + c->wl.rmid1);
+  D.rb = (uint32_t*)(w + c->wl.rb);
+  D.xi = (double*)(w + c->wl.xi);
+  D.part = (double*)(w + c->wl.part);
+  D.tX = (int64_t*)(w + c->wl.tX);
+  D.notdone = (uint32_t*)(w + c->wl.notdone);
+  D.ctrl = (Ctrl*)(w + c->wl.ctrl);
+
+  hipStream_t s = c->s;
+  acc(hipMemcpyAsync(b->flags, fl.data(), (size_t)nodes, hipMemcpyHostToDevice, s));
+  acc(hipMemcpyAsync(w + c->wl.reps, c->reps.data(), sizeof(Rep) * nrep, hipMemcpyHostToDevice, s));
+  acc(hipMemcpyAsync(w + c->wl.otiles, ot.data(), sizeof(Tile) * ot.size(), hipMemcpyHostToDevice, s));
+  acc(hipMemcpyAsync(w + c->wl.slot_rep, slot_rep.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+  // rest populations, replica by replica ([19][N_r] from element 19 node_off)
+  for (int r = 0; r < nrep; ++r) {
+    const size_t off = elem_size(d) * Q * (size_t)c->reps[r].node_off;
+    const long N = c->reps[r].lp.N;
+    for (void* p : {b->pops_a, b->pops_b}) {
+      if (c->dev) launch_fill_rest<float, true>((char*)p + off, N, s);
+      else launch_fill_rest<double, false>((char*)p + off, N, s);
+    }
+  }
+  acc(hipMemsetAsync(b->force, 0, elem_size(d) * 3 * (size_t)nodes, s));
+  acc(hipMemsetAsync(b->beads, 0, sizeof(double) * 15 * ns, s));
+  acc(hipMemsetAsync(D.ctrl, 0, sizeof(Ctrl), s));
+  launch_fill_i32(D.head, nodes, -1, s);
+  launch_fill_f64(D.ref, 3L * (long)ns, 1e300, s);
+  acc(hipMemsetAsync(D.ncnt, 0, sizeof(int) * ns, s));
+  acc(hipMemsetAsync(D.rb, 0, sizeof(uint32_t) * 4 * nrep, s));
+  acc(hipMemsetAsync(D.notdone, 0, sizeof(uint32_t) * nrep, s));
+  {
+    std::vector<int64_t> tx((size_t)nrep, -1);
+    acc(hipMemcpyAsync(D.tX, tx.data(), sizeof(int64_t) * nrep, hipMemcpyHostToDevice, s));
+    launch_md_invalidate(D, nrep, s);
+    // bead state, replica by replica into its slots
+    long k = 0;
+    for (int r = 0; r < nrep; ++r) {
+      int nb = d[r].nb;
+      if (nb == 0) continue;
+      acc(hipMemcpyAsync(D.r + 3 * (size_t)c->reps[r].slot_off, r0_host + 3 * k, sizeof(double) * 3 * nb,
+                         hipMemcpyHostToDevice, s));
+      if (v0_host)
+        acc(hipMemcpyAsync(D.v + 3 * (size_t)c->reps[r].slot_off, v0_host + 3 * k, sizeof(double) * 3 * nb,
+                           hipMemcpyHostToDevice, s));
+      k += nb;
+    }
+    hipError_t e = hipStreamSynchronize(s);   // the host vectors above must outlive the copies
+    if (e != hipSuccess) { lb_destroy(c); return fail(LB_ERR_DEVICE, "init: %s", hipGetErrorString(e)); }
+  }
+  rc = take_acc("init");
+  if (rc) { lb_destroy(c); return rc; }
+  rc = upload_tiles(c, SweepCfg{});
+  if (rc) { lb_destroy(c); return rc; }
   rc = check_hip("init");
   if (rc) { lb_destroy(c); return rc; }
   *out = c;
   return LB_OK;
 }
 
+int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const double* v0_host, void* stream,
+            lb_ctx** out) {
+  return lb_ensemble_init(d, 1, b, r0_host, v0_host, stream, out);
+}
+
 void lb_destroy(lb_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->s) (void)hipStreamSynchronize(ctx->s);
   if (ctx->s2) (void)hipStreamSynchronize(ctx->s2);
+  drop_graph(ctx);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
   if (ctx->join) (void)hipEventDestroy(ctx->join);
   if (ctx->s2) (void)hipStreamDestroy(ctx->s2);
+  if (ctx->scap) (void)hipStreamDestroy(ctx->scap);
   delete ctx;
+}
+
+int lb_ensemble_layout(lb_ctx* c, int64_t* node_off, int64_t* slot_off) {
+  if (!c || !node_off || !slot_off) return fail(LB_ERR_ARG, "bad arguments");
+  for (int r = 0; r < c->nrep; ++r) {
+    node_off[r] = c->reps[r].node_off;
+    slot_off[r] = c->reps[r].slot_off;
+  }
+  return LB_OK;
 }
 
 int lb_profile_start(lb_ctx* c, int max_steps) {
@@ -405,124 +687,96 @@ int lb_profile_stop(lb_ctx* c, double* mean_lb_ms, double* mean_bead_ms, int* ns
 
 int lb_step(lb_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return fail(LB_ERR_ARG, "bad arguments");
-  for (int k = 0; k < nsteps; ++k) {
-    prof_mark(c, 0, c->s);
-    prof_mark(c, 1, c->s);
-    prof_mark(c, 2, c->s);
-    launch_lb_any(c, 0, c->s);
-    prof_mark(c, 3, c->s);
-    launch_step_end(0, c->base, c->head, c->touched, (uint8_t*)c->b.flags, c->ctrl, 1, c->s);
-    c->cur ^= 1;
-    prof_next(c);
-  }
+  for (int k = 0; k < nsteps; ++k) enqueue_lb_step(c, c->s);
   c->steps += nsteps;
   return check_hip("lb_step");
 }
 
 int md_couple_step(lb_ctx* c, int nsteps) {
   if (!c || nsteps < 0) return fail(LB_ERR_ARG, "bad arguments");
-  const int nb = c->d.nb;
-  uint8_t* flags = (uint8_t*)c->b.flags;
-  for (int k = 0; k < nsteps; ++k) {
-    if (nb == 0) {
-      prof_mark(c, 0, c->s);
-      prof_mark(c, 1, c->s);
-      prof_mark(c, 2, c->s);
-      launch_lb_any(c, 0, c->s);
-      prof_mark(c, 3, c->s);
-    } else {
-      // the stencil nodes of r(n) are marked first; the sweep over all other
-      // nodes then runs on the second stream while the beads move
-      prof_mark(c, 0, c->s);
-      launch_bead_prep(c->bp, c->g, nb, c->head, c->next, c->base, flags, c->s);
-      acc(hipEventRecord(c->fork, c->s));
-      acc(hipStreamWaitEvent(c->s2, c->fork, 0));
-      prof_mark(c, 2, c->s2);
-      launch_lb_any(c, 1, c->s2);
-      prof_mark(c, 3, c->s2);
-      acc(hipEventRecord(c->join, c->s2));
-      if (c->dev) launch_gather<float, true>(cur_pops(c), flags, c->lp, c->g, c->bp, nb, c->s);
-      else launch_gather<double, false>(cur_pops(c), flags, c->lp, c->g, c->bp, nb, c->s);
-      launch_md_cycle(c->bp, c->mw, c->mp, c->g, c->ctrl, c->d.n_sub, c->s);
-      if (c->dev) launch_spread<float>(c->bp, c->g, nb, c->head, c->next, flags, c->b.force, c->touched, c->ctrl, c->s);
-      else launch_spread<double>(c->bp, c->g, nb, c->head, c->next, flags, c->b.force, c->touched, c->ctrl, c->s);
-      launch_lb_forced_any(c, c->s);
-      prof_mark(c, 1, c->s);
-      acc(hipStreamWaitEvent(c->s, c->join, 0));
-    }
-    launch_step_end(nb, c->base, c->head, c->touched, flags, c->ctrl, 1, c->s);
-    c->cur ^= 1;
-    prof_next(c);
-  }
+  for (int k = 0; k < nsteps; ++k) enqueue_coupled_step(c, c->s);
   c->steps += nsteps;
   return check_hip("md_couple_step");
 }
 
+int lb_ensemble_run(lb_ctx* c, int nsteps, int use_graph) {
+  if (!c || nsteps < 0) return fail(LB_ERR_ARG, "bad arguments");
+  if (!use_graph || c->prof_on) return md_couple_step(c, nsteps);
+  int left = nsteps;
+  if (left >= 2) {
+    if (!c->gexec || (c->graph_cur != c->cur && c->graph_cur != (c->cur ^ 1))) {
+      int rc = build_graph(c);
+      if (rc) return rc;
+    }
+    if (c->graph_cur != c->cur) {   // one eager step to reach the graph's parity
+      enqueue_coupled_step(c, c->s);
+      --left;
+    }
+    for (; left >= 2; left -= 2) acc(hipGraphLaunch(c->gexec, c->s));
+  }
+  for (; left > 0; --left) enqueue_coupled_step(c, c->s);
+  c->steps += nsteps;
+  return check_hip("lb_ensemble_run");
+}
+
 int md_relax(lb_ctx* c, int nsub_total, double gamma_relax) {
   if (!c || nsub_total < 0 || !(gamma_relax >= 0.0)) return fail(LB_ERR_ARG, "bad arguments");
-  if (c->d.nb == 0) return LB_OK;
-  MdParams P = c->mp;
-  P.couple = 0;
-  P.field_on = 0;
-  spv_coefficients(P, gamma_relax, 0.0, 1.0 / (double)c->d.n_sub);
+  if (c->nslots == 0) return LB_OK;
+  MdOverride ov;
+  ov.on = 1;
+  ov.gamma = gamma_relax;
+  const double h = 1.0 / (double)c->n_sub;
+  if (gamma_relax == 0.0) {
+    ov.e = 1.0; ov.omE = 0.0;
+  } else {
+    ov.e = std::exp(-(gamma_relax * h));
+    ov.omE = 1.0 - ov.e;
+  }
+  ov.cf = 0.0;   // per replica: omE / (m gamma), or h / m without friction
   int left = nsub_total;
   while (left > 0) {
-    int n = left < c->d.n_sub ? left : c->d.n_sub;
-    launch_md_cycle(c->bp, c->mw, P, c->g, c->ctrl, n, c->s);
+    int n = left < c->n_sub ? left : c->n_sub;
+    launch_md_cycle(c->D, c->nslots, c->nrep, n, 0, ov, c->s);
     left -= n;
   }
-  launch_zero_v(c->bp.v, c->d.nb, c->s);
+  launch_zero_v(c->D, c->nslots, c->s);
   return check_hip("md_relax");
 }
 
 int lb_observables(lb_ctx* c, double* out_dev) {
   if (!c || !out_dev) return fail(LB_ERR_ARG, "bad arguments");
-  if (c->dev)
-    launch_observables<float, true>(cur_pops(c), (const uint8_t*)c->b.flags, c->g.N, c->nfluid, c->part, NPARTS,
-                                    c->bp, c->d.nb, c->g, c->mp, c->ctrl, out_dev, c->s);
-  else
-    launch_observables<double, false>(cur_pops(c), (const uint8_t*)c->b.flags, c->g.N, c->nfluid, c->part, NPARTS,
-                                      c->bp, c->d.nb, c->g, c->mp, c->ctrl, out_dev, c->s);
+  const int no = (int)c->pk.obs_tiles;
+  if (c->dev) launch_observables<float, true>(cur_pops(c), c->D, no, c->nrep, out_dev, c->s);
+  else launch_observables<double, false>(cur_pops(c), c->D, no, c->nrep, out_dev, c->s);
   return check_hip("lb_observables");
-}
-
-static size_t pops_state_bytes(const lb_ctx* c) {
-  size_t es = c->dev ? sizeof(float) : sizeof(double);
-  return align256(es * Q * (size_t)c->g.N);
 }
 
 int lb_get_state(lb_ctx* c, void* dst) {
   if (!c || !dst) return fail(LB_ERR_ARG, "bad arguments");
-  size_t es = c->dev ? sizeof(float) : sizeof(double);
-  size_t nbs = (size_t)(c->d.nb > 0 ? c->d.nb : 1);
   char* o = (char*)dst;
-  acc(hipMemcpyAsync(o, cur_pops(c), es * Q * (size_t)c->g.N, hipMemcpyDeviceToDevice, c->s));
-  o += pops_state_bytes(c);
-  if (c->d.nb > 0) {
-    acc(hipMemcpyAsync(o, c->bp.r, sizeof(double) * 3 * c->d.nb, hipMemcpyDeviceToDevice, c->s));
-    acc(hipMemcpyAsync(o + sizeof(double) * 3 * nbs, c->bp.v, sizeof(double) * 3 * c->d.nb, hipMemcpyDeviceToDevice, c->s));
-  }
-  o += align256(sizeof(double) * 6 * nbs);
-  acc(hipMemcpyAsync(o, &c->ctrl->step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  acc(hipMemcpyAsync(o + c->sl.pops, cur_pops(c), es * Q * (size_t)c->pk.nodes, hipMemcpyDeviceToDevice, c->s));
+  const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
+  acc(hipMemcpyAsync(o + c->sl.r, c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + c->sl.v, c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + c->sl.step, &c->D.ctrl->step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + c->sl.tX, c->D.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
   return check_hip("lb_get_state");
 }
 
 int lb_set_state(lb_ctx* c, const void* src) {
   if (!c || !src) return fail(LB_ERR_ARG, "bad arguments");
-  size_t es = c->dev ? sizeof(float) : sizeof(double);
-  size_t nbs = (size_t)(c->d.nb > 0 ? c->d.nb : 1);
   const char* o = (const char*)src;
-  acc(hipMemcpyAsync(cur_pops(c), o, es * Q * (size_t)c->g.N, hipMemcpyDeviceToDevice, c->s));
-  o += pops_state_bytes(c);
-  if (c->d.nb > 0) {
-    acc(hipMemcpyAsync(c->bp.r, o, sizeof(double) * 3 * c->d.nb, hipMemcpyDeviceToDevice, c->s));
-    acc(hipMemcpyAsync(c->bp.v, o + sizeof(double) * 3 * nbs, sizeof(double) * 3 * c->d.nb, hipMemcpyDeviceToDevice, c->s));
-  }
-  o += align256(sizeof(double) * 6 * nbs);
-  acc(hipMemcpyAsync(&c->ctrl->step, o, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
-  launch_md_invalidate(c->mw, c->s);
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  acc(hipMemcpyAsync(cur_pops(c), o + c->sl.pops, es * Q * (size_t)c->pk.nodes, hipMemcpyDeviceToDevice, c->s));
+  const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
+  acc(hipMemcpyAsync(c->D.r, o + c->sl.r, nb3, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->D.v, o + c->sl.v, nb3, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(&c->D.ctrl->step, o + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->D.tX, o + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
+  launch_md_invalidate(c->D, c->nrep, c->s);
   uint64_t st = 0;
-  acc(hipMemcpyAsync(&st, o, sizeof(uint64_t), hipMemcpyDeviceToHost, c->s));
+  acc(hipMemcpyAsync(&st, o + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToHost, c->s));
   hipError_t e = hipStreamSynchronize(c->s);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "lb_set_state: %s", hipGetErrorString(e));
   c->steps = (int64_t)st;
@@ -537,7 +791,7 @@ int lb_check(lb_ctx* c) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->s2);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(e));
   uint32_t err = 0;
-  e = hipMemcpy(&err, &c->ctrl->err, sizeof(err), hipMemcpyDeviceToHost);
+  e = hipMemcpy(&err, &c->D.ctrl->err, sizeof(err), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "watchdog read: %s", hipGetErrorString(e));
   if (err) {
     std::string why;
@@ -557,14 +811,90 @@ int lb_diagnostics(lb_ctx* c, int64_t* out) {
   hipError_t e = hipStreamSynchronize(c->s);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(e));
   Ctrl h;
-  e = hipMemcpy(&h, c->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+  e = hipMemcpy(&h, c->D.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "diagnostics read: %s", hipGetErrorString(e));
   out[0] = (int64_t)h.rebuilds;
   out[1] = (int64_t)h.substeps;
-  out[2] = (int64_t)c->last_touched;
+  out[2] = (int64_t)c->ntiles;
   out[3] = (int64_t)h.err;
   out[4] = (int64_t)h.step;
   return LB_OK;
+}
+
+int lb_ensemble_translocation(lb_ctx* c, int64_t* out_host) {
+  if (!c || !out_host) return fail(LB_ERR_ARG, "bad arguments");
+  hipError_t e = hipStreamSynchronize(c->s);
+  if (e == hipSuccess) e = hipMemcpy(out_host, c->D.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(LB_ERR_DEVICE, "translocation read: %s", hipGetErrorString(e));
+  return LB_OK;
+}
+
+int lb_sweep_config(lb_ctx* c, int tile_nodes, int order, int grid) {
+  if (!c || order < 0 || order > 1 || grid < 0) return fail(LB_ERR_ARG, "bad arguments");
+  SweepCfg sc;
+  sc.tile_nodes = tile_nodes;
+  sc.order = order;
+  sc.grid = grid;
+  int rc = upload_tiles(c, sc);
+  if (rc) return rc;
+  drop_graph(c);
+  return LB_OK;
+}
+
+int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
+  if (!c || reps < 1) return fail(LB_ERR_ARG, "bad arguments");
+  // cached per packing (replica extents and walls) and precision
+  static std::map<std::string, SweepCfg> cache;
+  std::string key = c->dev ? "f32:" : "f64:";
+  for (const lb_desc& x : c->d) {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", x.nx, x.ny, x.nz, x.wall_axis, x.wall_pos, x.pore_h);
+    key += buf;
+  }
+  auto it = cache.find(key);
+  SweepCfg best;
+  double best_ms = -1.0;
+  if (it != cache.end()) {
+    best = it->second;
+  } else {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return fail(LB_ERR_DEVICE, "hipEventCreate failed");
+    std::vector<SweepCfg> cand;
+    for (int tn : {256, 512, 1024, 2048})
+      for (int order : {0, 1}) cand.push_back(SweepCfg{tn, order, 0});
+    cand.push_back(SweepCfg{256, 0, 2048});
+    cand.push_back(SweepCfg{256, 0, 8192});
+    int rc = LB_OK;
+    for (const SweepCfg& sc : cand) {
+      rc = upload_tiles(c, sc);
+      if (rc) break;
+      // the sweep from the current populations into the other array: that
+      // array is overwritten by the next step, so the state is unchanged
+      for (int k = 0; k < 2; ++k) sweep(c, 0, c->s);
+      acc(hipEventRecord(e0, c->s));
+      for (int k = 0; k < reps; ++k) sweep(c, 0, c->s);
+      acc(hipEventRecord(e1, c->s));
+      hipError_t e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { rc = fail(LB_ERR_DEVICE, "autotune: %s", hipGetErrorString(e)); break; }
+      double m = ms / reps;
+      if (best_ms < 0.0 || m < best_ms) { best_ms = m; best = sc; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = take_acc("autotune");
+    if (rc) return rc;
+    cache[key] = best;
+  }
+  int rc = upload_tiles(c, best);
+  if (rc) return rc;
+  drop_graph(c);
+  if (out_cfg) { out_cfg[0] = best.tile_nodes; out_cfg[1] = best.order; out_cfg[2] = best.grid; }
+  if (out_ms) *out_ms = best_ms;
+  return check_hip("lb_autotune");
 }
 
 }  // extern "C"

@@ -1,9 +1,30 @@
-// lbmd_kernels.h -- kernel argument blocks and host-side launchers.
+// lbmd_kernels.h -- data layout of a context and the host-side launchers.
+//
+// A context holds R replicas (R = 1 for a single system): independent
+// lattices, each with its own chain, geometry and noise key, advanced in
+// lockstep by the same launches.
+//   - populations: replica r occupies Q * N_r elements at element offset
+//     Q * node_off_r, laid out [Q][N_r] (structure of arrays);
+//   - flags (1 byte / node) and the bead force density ([3][N_r]) follow the
+//     same node offsets;
+//   - beads live in slots; replica r owns slots [slot_off_r, slot_off_r +
+//     nslot_r), nslot_r = nb_r rounded up to the MD workgroup size, so every
+//     MD workgroup holds beads of one chain; chain index p = slot - slot_off_r;
+//   - the sweep runs over a table of tiles (replica, first node), each of
+//     tile_nodes consecutive nodes of one replica, in an order chosen by the
+//     autotuner; the fluid reductions use a fixed table of OBS_TILE-node
+//     tiles, contiguous per replica, so their summation order never changes.
 #pragma once
 
 #include "lbmd_dev.h"
 
 namespace lbmd {
+
+constexpr int MD_BPB = 16;                   // beads per MD workgroup (slot padding)
+constexpr int NOBS = 23;                     // observables per replica
+constexpr int MAX_REPLICAS = 1024;
+constexpr int TILE_MIN = 256;                // smallest sweep tile (nodes)
+constexpr int OBS_TILE = 4096;               // nodes per fluid-reduction tile
 
 struct LbParams {
   int nx, ny, nz, nxy, N;
@@ -12,52 +33,87 @@ struct LbParams {
   int has_g;
 };
 
-struct BeadPtrs {
-  double* r;    // [nb][3] unwrapped positions
-  double* v;    // [nb][3]
-  double* up;   // [nb][3] fluid velocity at the bead (frozen for the sub-cycle)
-  double* J;    // [nb][3] momentum handed to the fluid this step
-  double* rs;   // [nb][3] positions at the start of the step
+// One replica as the kernels see it.
+struct Rep {
+  Geom g;
+  LbParams lp;
+  MdParams mp;
+  long node_off;    // first node in the packed node arrays
+  int slot_off;     // first bead slot
+  int nslot;        // bead slots (multiple of MD_BPB)
+  int tile_begin;   // reduction tiles [tile_begin, tile_end)
+  int tile_end;
+  double nfluid;    // fluid nodes (for the mass observable)
 };
 
-struct MdWork {
-  double* rmid0;  // [nb][3] positions at the force evaluation, double buffered
+struct Tile {
+  int rep;
+  int start;
+};
+
+// Every device array a kernel may touch.
+struct Dev {
+  const Rep* reps;
+  const Tile* tiles;   // sweep tiles
+  const Tile* otiles;  // reduction tiles
+  uint8_t* flags;
+  void* force;
+  // beads, per slot [3] doubles
+  double* r;
+  double* v;
+  double* up;
+  double* J;
+  double* rs;
+  const int* slot_rep;
+  // spreading: bead lists per base node, forced-node list
+  int* head;        // per node, -1 when empty
+  int* next;        // per slot
+  int* base;        // per slot: base node (replica-local index)
+  int2* touched;    // (replica, node) of the nodes carrying bead force
+  // MD sub-cycle
+  int* nbr;         // [slot][MAXNBR] chain indices
+  int* ncnt;        // per slot
+  double* ref;      // per slot [3]: positions at the last list build
+  double* rmid0;    // per slot [3]: force-evaluation positions, double buffered
   double* rmid1;
-  double* ref;    // [nb][3] positions at the last neighbour-list build
-  int* nbr;       // [nb][MAXNBR]
-  int* ncnt;      // [nb]
-  uint32_t* rb;   // [4] rebuild flags (3-phase) + list-invalid flag
-  double* xi;     // [n_sub][nb][3] noise of the current sub-cycle
+  uint32_t* rb;     // [R][4]: rebuild flags (3 rotating) + list-invalid request
+  double* xi;       // [n_sub][slots][3] noise of the current sub-cycle
+  // reductions and per-replica bookkeeping
+  double* part;     // [reduction tiles][4] fluid partial sums
+  int64_t* tX;      // per replica: first step with the whole chain translocated, -1 before
+  uint32_t* notdone;// per replica: some bead still on the cis side this step
+  Ctrl* ctrl;
+};
+
+// MD coefficients that replace the replicas' own during the pre-relaxation
+// (friction gamma, e = exp(-gamma h), 1 - e; the force coefficient follows
+// from each replica's mass).
+struct MdOverride {
+  int on;
+  double gamma, e, omE, cf;
 };
 
 template <typename T, bool DEV> void launch_fill_rest(void* pops, long N, hipStream_t s);
 void launch_fill_i32(int* p, long n, int v, hipStream_t s);
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
 template <typename T, bool DEV>
-void launch_lb(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
-               int skip_forced, hipStream_t s);
+void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int skip_forced,
+               hipStream_t s);
 template <typename T, bool DEV>
-void launch_lb_forced(const void* A, void* B, const uint8_t* flags, const void* force, const LbParams& p, Ctrl* ctrl,
-                      const int* touched, int maxlist, hipStream_t s);
+void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStream_t s);
 template <typename T, bool DEV>
-void launch_gather(const void* A, const uint8_t* flags, const LbParams& p, const Geom& g, const BeadPtrs& b, int nb,
-                   hipStream_t s);
-void launch_bead_prep(const BeadPtrs& b, const Geom& g, int nb, int* head, int* next, int* base, uint8_t* flags,
-                      hipStream_t s);
+void launch_gather(const void* A, const Dev& d, int nslots, hipStream_t s);
+void launch_bead_prep(const Dev& d, int nslots, hipStream_t s);
 template <typename T>
-void launch_spread(const BeadPtrs& b, const Geom& g, int nb, const int* head, const int* next, uint8_t* flags,
-                   void* force, int* touched, Ctrl* ctrl, hipStream_t s);
-void launch_step_end(int nb, const int* base, int* head, const int* touched, uint8_t* flags, Ctrl* ctrl, int advance,
-                     hipStream_t s);
+void launch_spread(const Dev& d, int nslots, hipStream_t s);
+void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_t s);
 template <typename T, bool DEV>
-void launch_observables(const void* A, const uint8_t* flags, long N, double nfluid, double* part, int nparts,
-                        const BeadPtrs& b, int nb, const Geom& g, const MdParams& P, const Ctrl* ctrl, double* out,
-                        hipStream_t s);
+void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s);
 
-// MD sub-cycle: n_sub launches, one per sub-step.
-void launch_md_cycle(const BeadPtrs& b, const MdWork& w, const MdParams& P, const Geom& g, Ctrl* ctrl, int n_sub,
+// MD sub-cycle of all replicas: n_sub launches, one per sub-step.
+void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
                      hipStream_t s);
-void launch_md_invalidate(const MdWork& w, hipStream_t s);
-void launch_zero_v(double* v, int nb, hipStream_t s);
+void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);
+void launch_zero_v(const Dev& d, int nslots, hipStream_t s);
 
 }  // namespace lbmd

@@ -2,7 +2,8 @@
 // (Sec. 2, Eq. (SPValgo), no constraints) with the fluid velocity at each
 // bead frozen for the whole cycle.  One launch per sub-step; the positions
 // at which forces are evaluated are double buffered so that every bead reads
-// a consistent snapshot.
+// a consistent snapshot.  Every replica of a context advances in the same
+// launches; a workgroup never mixes replicas.
 //
 // Per sub-step s (h = 1/n_sub, e = exp(-gamma h)):
 //   r_mid = r + h/2 v                      (written by the previous launch)
@@ -22,50 +23,77 @@
 
 namespace lbmd {
 
-// Reset the rebuild flags; word 3 is the "lists invalid" request from the
-// host (initialisation, restored state).
-__global__ void k_md_begin(uint32_t* rb) {
-  rb[0] = rb[3];
-  rb[1] = 0u;
-  rb[2] = 0u;
-  rb[3] = 0u;
+// Per replica r, rb[4 r + 0..2] are the three rotating rebuild flags and
+// rb[4 r + 3] the "lists invalid" request from the host (initialisation,
+// restored state).
+__global__ void k_md_begin(uint32_t* rb, int nrep) {
+  for (int r = threadIdx.x; r < nrep; r += blockDim.x) {
+    uint32_t* w = rb + 4 * r;
+    w[0] = w[3];
+    w[1] = 0u;
+    w[2] = 0u;
+    w[3] = 0u;
+  }
 }
 
-__global__ void k_md_invalidate(uint32_t* rb) { rb[3] = 1u; }
+__global__ void k_md_invalidate(uint32_t* rb, int nrep) {
+  for (int r = threadIdx.x; r < nrep; r += blockDim.x) rb[4 * r + 3] = 1u;
+}
+
+// Coefficients of the sub-cycle for one replica: its own, or the
+// relaxation's (no coupling, no field, no noise).
+__device__ inline MdParams md_params(const Rep& R, const MdOverride& ov) {
+  MdParams P = R.mp;
+  if (ov.on) {
+    P.gamma = ov.gamma; P.e = ov.e; P.omE = ov.omE;
+    P.cf = ov.gamma == 0.0 ? (2.0 * P.hh) / P.m : ov.omE / (P.m * ov.gamma);
+    P.sig = 0.0; P.couple = 0; P.field_on = 0;
+  }
+  return P;
+}
 
 // r_mid of sub-step 0 and the displacement check that decides whether the
 // first launch rebuilds the lists.
-__global__ void k_md_start(BeadPtrs b, MdWork w, MdParams P) {
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P.nb) return;
+__global__ void k_md_start(Dev d, int nslots, MdOverride ov) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const int rep = d.slot_rep[slot];
+  const Rep& R = d.reps[rep];
+  if (slot - R.slot_off >= R.mp.nb) return;
+  const double hh = R.mp.hh;
   double d2 = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double x = b.r[3 * p + a] + P.hh * b.v[3 * p + a];
-    w.rmid0[3 * p + a] = x;
-    double d = x - w.ref[3 * p + a];
-    d2 += d * d;
+    double x = d.r[3 * slot + a] + hh * d.v[3 * slot + a];
+    d.rmid0[3 * slot + a] = x;
+    double dd = x - d.ref[3 * slot + a];
+    d2 += dd * dd;
   }
-  if (d2 > P.halfskin2) w.rb[0] = 1u;
+  if (d2 > R.mp.halfskin2) d.rb[4 * rep] = 1u;
 }
 
-// The noise of a whole sub-cycle at once: xi[(s nb + p) 3 + a] for every
-// sub-step s and bead p (the same counter-based values the sub-step would
-// draw), so the transcendental functions run in one wide launch instead of on
-// the critical path of every sub-step.
-__global__ void k_md_noise(MdParams P, const Ctrl* __restrict__ ctrl, double* __restrict__ xi, int n_sub) {
+// The noise of a whole sub-cycle at once: xi[(s nslots + slot) 3 + a] for
+// every sub-step s and bead (the same counter-based values the sub-step would
+// draw, keyed by the replica's seed and index and the bead's chain index), so
+// the transcendental functions run in one wide launch instead of on the
+// critical path of every sub-step.
+__global__ void k_md_noise(Dev d, int nslots, int n_sub) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= (long)n_sub * P.nb) return;
-  int sidx = (int)(k / P.nb), p = (int)(k - (long)sidx * P.nb);
+  if (k >= (long)n_sub * nslots) return;
+  int sidx = (int)(k / nslots), slot = (int)(k - (long)sidx * nslots);
+  const Rep& R = d.reps[d.slot_rep[slot]];
+  const int p = slot - R.slot_off;
+  if (p >= R.mp.nb || R.mp.sig == 0.0) return;
   double x[3];
-  gauss3(P.seed, P.replica, (uint32_t)ctrl->step, (uint32_t)sidx, (uint32_t)p, x);
-  xi[3 * k] = x[0]; xi[3 * k + 1] = x[1]; xi[3 * k + 2] = x[2];
+  gauss3(R.mp.seed, R.mp.replica, (uint32_t)d.ctrl->step, (uint32_t)sidx, (uint32_t)p, x);
+  d.xi[3 * k] = x[0]; d.xi[3 * k + 1] = x[1]; d.xi[3 * k + 2] = x[2];
 }
 
-// Bending forces of the angles centred at q = q0 .. q0 + nq - 1 (those with
-// 1 <= q <= nb - 2), one angle per thread, into LDS: ang[q - q0][0..2] force
-// on q-1, [3..5] on q, [6..8] on q+1.  Each angle is evaluated once and read
-// by its three beads; the values are those a per-bead evaluation gives.
+// Bending forces of the angles centred at chain indices q = q0 .. q0 + nq - 1
+// (those with 1 <= q <= nb - 2), one angle per thread, into LDS:
+// ang[q - q0][0..2] force on q-1, [3..5] on q, [6..8] on q+1.  rin points at
+// the chain's first slot.  Each angle is evaluated once and read by its three
+// beads; the values are those a per-bead evaluation gives.
 __device__ inline void angles_to_lds(const double* __restrict__ rin, const MdParams& P, int q0, int nq,
                                      double (*ang)[9]) {
   for (int k = threadIdx.x; k < nq; k += blockDim.x) {
@@ -83,16 +111,15 @@ __device__ inline void angles_to_lds(const double* __restrict__ rin, const MdPar
 }
 
 // ---------------------------------------------------------------------------
-// Sub-step kernel.  A workgroup of 64 lanes holds 16 consecutive beads, 4
-// lanes per bead.  The lanes of a bead evaluate its LJ pair forces in
-// parallel (and, on two of them, the wall sites and the noise) into LDS;
-// one lane then adds every contribution in the fixed order of the
-// definition (bonds to p-1 and p+1, the angles centred at p-1, p, p+1, LJ in
-// ascending partner order, wall sites, field), so the sum is the same as a
+// Sub-step kernel.  A workgroup of 64 lanes holds 16 consecutive bead slots
+// of one replica, 4 lanes per bead.  The lanes of a bead evaluate its LJ pair
+// forces in parallel (and, on a second lane, the wall sites) into LDS; one
+// lane then adds every contribution in the fixed order of the definition
+// (bonds to p-1 and p+1, the angles centred at p-1, p, p+1, LJ in ascending
+// partner order, wall sites, field), so the sum is the same as a
 // one-thread-per-bead loop.
 // ---------------------------------------------------------------------------
 constexpr int MD_LANES = 4;
-constexpr int MD_BPB = 16;                   // beads per workgroup
 constexpr int MD_WG = MD_LANES * MD_BPB;     // 64
 constexpr int MAXWALL = 16;                  // solid sites within r_c of a bead (4 x 4 window)
 constexpr int NB_PER_LANE = MAXNBR / MD_LANES;
@@ -104,7 +131,7 @@ struct MdShared {
   double wallF[MD_BPB][MAXWALL][3];
   int nwall[MD_BPB];
   int cnt[MD_BPB];
-  int lst[MD_BPB][MAXNBR];                   // the neighbour list in use
+  int lst[MD_BPB][MAXNBR];                   // the neighbour list in use (chain indices)
   double tile[MD_WG][3];                     // rebuild: positions of 64 candidates
   uint32_t tmask[MD_BPB][MD_LANES];          // rebuild: lane l, bit e: candidate 16 l + e is close
   int over;
@@ -156,21 +183,30 @@ __device__ inline int wall_sites(const MdParams& P, const Geom& g, const double*
   return n;
 }
 
-__global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdParams P, Geom g,
-                                                      Ctrl* __restrict__ ctrl, int s, int last) {
+__global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int nslots, int s, int last) {
   __shared__ MdShared sh;
   const int t = threadIdx.x;
-  const int slot = t / MD_LANES, lane = t % MD_LANES;
-  const int p0 = blockIdx.x * MD_BPB;
-  const int p = p0 + slot;
+  const int bslot = t / MD_LANES, lane = t % MD_LANES;
+  const int slot0 = blockIdx.x * MD_BPB;
+  const int rep = d.slot_rep[slot0];
+  const Rep& R = d.reps[rep];
+  const MdParams P = md_params(R, ov);
+  const Geom g = R.g;
+  const int so = R.slot_off;
+  const int p0 = slot0 - so;                 // chain index of the first bead here
+  const int p = p0 + bslot;
+  const int slot = slot0 + bslot;
   const bool active = p < P.nb;
-  const double* rin = (s & 1) ? w.rmid1 : w.rmid0;
-  double* rout = (s & 1) ? w.rmid0 : w.rmid1;
-  const uint32_t rebuild = w.rb[s % 3];
-  if (blockIdx.x == 0 && t == 0) {
-    w.rb[(s + 2) % 3] = 0u;
-    ctrl->substeps += 1;
-    if (rebuild) ctrl->rebuilds += 1;
+  const double* rin = ((s & 1) ? d.rmid1 : d.rmid0) + 3 * (size_t)so;   // chain-relative
+  double* rout = (s & 1) ? d.rmid0 : d.rmid1;
+  uint32_t* rbr = d.rb + 4 * rep;
+  const uint32_t rebuild = rbr[s % 3];
+  if (t == 0) {
+    if (p0 == 0) {
+      rbr[(s + 2) % 3] = 0u;
+      if (rebuild) atomicAdd((unsigned long long*)&d.ctrl->rebuilds, 1ull);
+    }
+    if (blockIdx.x == 0) d.ctrl->substeps += 1;
   }
   double rp[3] = {0.0, 0.0, 0.0};
   if (active) { rp[0] = rin[3 * p]; rp[1] = rin[3 * p + 1]; rp[2] = rin[3 * p + 2]; }
@@ -182,26 +218,27 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
   if (lead) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      vo[a] = b.v[3 * p + a];
-      Jo[a] = b.J[3 * p + a];
-      u[a] = P.couple ? b.up[3 * p + a] : 0.0;
-      if (P.sig != 0.0) xi[a] = w.xi[(size_t)3 * ((size_t)s * P.nb + p) + a];
+      vo[a] = d.v[3 * slot + a];
+      Jo[a] = d.J[3 * slot + a];
+      u[a] = P.couple ? d.up[3 * slot + a] : 0.0;
+      if (P.sig != 0.0) xi[a] = d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
       if (p > 0) rm[a] = rin[3 * (p - 1) + a];
       if (p < P.nb - 1) rq[a] = rin[3 * (p + 1) + a];
     }
-    ncnt0 = w.ncnt[p];
+    ncnt0 = d.ncnt[slot];
   }
   if (t == 0) sh.over = 0;
   angles_to_lds(rin, P, p0 - 1, MD_BPB + 2, sh.ang);
 
-  // ---- neighbour list: reuse, or rebuild by scanning all beads in tiles of 64
+  // ---- neighbour list: reuse, or rebuild by scanning the chain in tiles of 64
+  int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
   if (!rebuild) {
-    if (lead) sh.cnt[slot] = ncnt0;
+    if (lead) sh.cnt[bslot] = ncnt0;
     __syncthreads();
-    int c = active ? sh.cnt[slot] : 0;
-    for (int k = lane; k < c; k += MD_LANES) sh.lst[slot][k] = w.nbr[(size_t)p * MAXNBR + k];
+    int c = active ? sh.cnt[bslot] : 0;
+    for (int k = lane; k < c; k += MD_LANES) sh.lst[bslot][k] = nbr_row[k];
   } else {
-    if (lane == 0) sh.cnt[slot] = 0;
+    if (lane == 0) sh.cnt[bslot] = 0;
     for (int base = 0; base < P.nb; base += MD_WG) {
       __syncthreads();
       int j = base + t;
@@ -219,44 +256,44 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
           if (d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2) m |= 1u << e;
         }
       }
-      sh.tmask[slot][lane] = m;
+      sh.tmask[bslot][lane] = m;
       __syncthreads();
       if (active && lane == 0) {
-        uint64_t mm = (uint64_t)sh.tmask[slot][0] | ((uint64_t)sh.tmask[slot][1] << 16) |
-                      ((uint64_t)sh.tmask[slot][2] << 32) | ((uint64_t)sh.tmask[slot][3] << 48);
-        int c = sh.cnt[slot];
+        uint64_t mm = (uint64_t)sh.tmask[bslot][0] | ((uint64_t)sh.tmask[bslot][1] << 16) |
+                      ((uint64_t)sh.tmask[bslot][2] << 32) | ((uint64_t)sh.tmask[bslot][3] << 48);
+        int c = sh.cnt[bslot];
         while (mm) {
           int tt = __builtin_ctzll(mm);
           mm &= mm - 1;
-          if (c < MAXNBR) sh.lst[slot][c] = base + tt;
+          if (c < MAXNBR) sh.lst[bslot][c] = base + tt;
           else sh.over = 1;
           ++c;
         }
-        sh.cnt[slot] = c;
+        sh.cnt[bslot] = c;
       }
     }
     __syncthreads();
     if (active && lane == 0) {
-      int c = sh.cnt[slot];
-      if (c > MAXNBR) { c = MAXNBR; sh.cnt[slot] = c; }
-      w.ncnt[p] = c;
-      w.ref[3 * p] = rp[0]; w.ref[3 * p + 1] = rp[1]; w.ref[3 * p + 2] = rp[2];
+      int c = sh.cnt[bslot];
+      if (c > MAXNBR) { c = MAXNBR; sh.cnt[bslot] = c; }
+      d.ncnt[slot] = c;
+      d.ref[3 * slot] = rp[0]; d.ref[3 * slot + 1] = rp[1]; d.ref[3 * slot + 2] = rp[2];
     }
     __syncthreads();
-    int c = active ? sh.cnt[slot] : 0;
-    for (int k = lane; k < c; k += MD_LANES) w.nbr[(size_t)p * MAXNBR + k] = sh.lst[slot][k];
-    if (t == 0 && sh.over) atomicOr(&ctrl->err, E_NBRLIST);
+    int c = active ? sh.cnt[bslot] : 0;
+    for (int k = lane; k < c; k += MD_LANES) nbr_row[k] = sh.lst[bslot][k];
+    if (t == 0 && sh.over) atomicOr(&d.ctrl->err, E_NBRLIST);
   }
   __syncthreads();
 
   // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
-  const int cnt = active ? sh.cnt[slot] : 0;
+  const int cnt = active ? sh.cnt[bslot] : 0;
   {
     int jl[NB_PER_LANE];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) {
       int k = lane + MD_LANES * m;
-      jl[m] = (k < cnt) ? sh.lst[slot][k] : -1;
+      jl[m] = (k < cnt) ? sh.lst[bslot][k] : -1;
     }
     double q[NB_PER_LANE][3];
 #pragma unroll
@@ -275,13 +312,13 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
       double F[3] = {0.0, 0.0, 0.0};
       lj_add(P, d0, d1, d2, F);
       int k = lane + MD_LANES * m;
-      sh.pairF[slot][k][0] = F[0]; sh.pairF[slot][k][1] = F[1]; sh.pairF[slot][k][2] = F[2];
+      sh.pairF[bslot][k][0] = F[0]; sh.pairF[bslot][k][1] = F[1]; sh.pairF[bslot][k][2] = F[2];
       hit |= 1u << m;
     }
-    sh.hit[slot][lane] = hit;
+    sh.hit[bslot][lane] = hit;
   }
   // ---- wall sites (lane 1)
-  if (active && lane == 1) sh.nwall[slot] = wall_sites(P, g, rp, sh.wallF[slot]);
+  if (active && lane == 1) sh.nwall[bslot] = wall_sites(P, g, rp, sh.wallF[bslot]);
   // ---- lane 0: bonds now, then every contribution in the fixed order
   double F[3] = {0.0, 0.0, 0.0};
   if (lead) {
@@ -289,19 +326,19 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
     if (p < P.nb - 1) bond_add(P, rp, rq, F);
   }
   __syncthreads();
-  if (!(active && lane == 0)) return;
+  if (!lead) return;
   const int q0 = p0 - 1;
   const int nb = P.nb;
   if (p - 1 >= 1 && p - 1 <= nb - 2) { const double* A = sh.ang[p - 1 - q0]; F[0] += A[6]; F[1] += A[7]; F[2] += A[8]; }
   if (p >= 1 && p <= nb - 2) { const double* A = sh.ang[p - q0]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
   if (p + 1 >= 1 && p + 1 <= nb - 2) { const double* A = sh.ang[p + 1 - q0]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2]; }
   for (int k = 0; k < cnt; ++k) {
-    if (!((sh.hit[slot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
-    F[0] += sh.pairF[slot][k][0]; F[1] += sh.pairF[slot][k][1]; F[2] += sh.pairF[slot][k][2];
+    if (!((sh.hit[bslot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
+    F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
   }
-  int nw = sh.nwall[slot];
-  if (nw > MAXWALL) { atomicOr(&ctrl->err, E_NBRLIST); nw = MAXWALL; }
-  for (int k = 0; k < nw; ++k) { F[0] += sh.wallF[slot][k][0]; F[1] += sh.wallF[slot][k][1]; F[2] += sh.wallF[slot][k][2]; }
+  int nw = sh.nwall[bslot];
+  if (nw > MAXWALL) { atomicOr(&d.ctrl->err, E_NBRLIST); nw = MAXWALL; }
+  for (int k = 0; k < nw; ++k) { F[0] += sh.wallF[bslot][k][0]; F[1] += sh.wallF[bslot][k][1]; F[2] += sh.wallF[bslot][k][2]; }
   if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
 
   double vn[3];
@@ -310,24 +347,24 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(BeadPtrs b, MdWork w, MdPa
   for (int a = 0; a < 3; ++a) {
     double sx = P.sig * xi[a];
     vn[a] = P.e * vo[a] + P.cf * (F[a] + P.gamma * u[a]) + sx;
-    b.J[3 * p + a] = Jo[a] - P.m * (P.omE * (u[a] - vo[a]) + sx);
-    b.v[3 * p + a] = vn[a];
+    d.J[3 * slot + a] = Jo[a] - P.m * (P.omE * (u[a] - vo[a]) + sx);
+    d.v[3 * slot + a] = vn[a];
     finite = finite && isfinite(vn[a]);
   }
-  if (!finite) atomicOr(&ctrl->err, E_BEADS);
+  if (!finite) atomicOr(&d.ctrl->err, E_BEADS);
   double re[3] = {rp[0] + P.hh * vn[0], rp[1] + P.hh * vn[1], rp[2] + P.hh * vn[2]};
   if (last) {
-    b.r[3 * p] = re[0]; b.r[3 * p + 1] = re[1]; b.r[3 * p + 2] = re[2];
+    d.r[3 * slot] = re[0]; d.r[3 * slot + 1] = re[1]; d.r[3 * slot + 2] = re[2];
   } else {
     double d2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double x = re[a] + P.hh * vn[a];
-      rout[3 * p + a] = x;
-      double d = x - w.ref[3 * p + a];
-      d2 += d * d;
+      rout[3 * slot + a] = x;
+      double dd = x - d.ref[3 * slot + a];
+      d2 += dd * dd;
     }
-    if (d2 > P.halfskin2) w.rb[(s + 1) % 3] = 1u;
+    if (d2 > P.halfskin2) rbr[(s + 1) % 3] = 1u;
   }
 }
 
@@ -336,26 +373,26 @@ __global__ void k_zero_v(double* v, int n) {
   if (k < n) v[k] = 0.0;
 }
 
-void launch_md_invalidate(const MdWork& w, hipStream_t s) {
-  hipLaunchKernelGGL(k_md_invalidate, dim3(1), dim3(1), 0, s, w.rb);
+void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {
+  hipLaunchKernelGGL(k_md_invalidate, dim3(1), dim3(256), 0, s, d.rb, nrep);
 }
 
-void launch_md_cycle(const BeadPtrs& b, const MdWork& w, const MdParams& P, const Geom& g, Ctrl* ctrl, int n_sub,
+void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
                      hipStream_t s) {
-  if (P.nb <= 0 || n_sub <= 0) return;
-  unsigned nblk = (unsigned)((P.nb + MD_BPB - 1) / MD_BPB);
-  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(1), 0, s, w.rb);
-  if (P.sig != 0.0) {
-    long nk = (long)n_sub * P.nb;
-    hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, P, ctrl, w.xi, n_sub);
+  if (nslots <= 0 || n_sub <= 0) return;
+  unsigned nblk = (unsigned)(nslots / MD_BPB);
+  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, nrep);
+  if (noise && !ov.on) {
+    long nk = (long)n_sub * nslots;
+    hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, d, nslots, n_sub);
   }
-  hipLaunchKernelGGL(k_md_start, dim3((P.nb + 255) / 256), dim3(256), 0, s, b, w, P);
+  hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov);
   for (int k = 0; k < n_sub; ++k)
-    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, b, w, P, g, ctrl, k, k == n_sub - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, d, ov, nslots, k, k == n_sub - 1 ? 1 : 0);
 }
 
-void launch_zero_v(double* v, int nb, hipStream_t s) {
-  if (nb > 0) hipLaunchKernelGGL(k_zero_v, dim3((3 * nb + 255) / 256), dim3(256), 0, s, v, 3 * nb);
+void launch_zero_v(const Dev& d, int nslots, hipStream_t s) {
+  if (nslots > 0) hipLaunchKernelGGL(k_zero_v, dim3((3 * nslots + 255) / 256), dim3(256), 0, s, d.v, 3 * nslots);
 }
 
 }  // namespace lbmd

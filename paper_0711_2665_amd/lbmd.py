@@ -2,8 +2,9 @@
 
 Argument marshalling only: every step of the coupled LB/MD method runs in the
 library's HIP kernels.  PyTorch provides the device memory (uint8 tensors
-sized by lb_buffer_sizes) and the stream (the current torch stream).  The
-binding refuses to run when the library is missing: there is no CPU path.
+sized by lb_buffer_sizes / lb_ensemble_sizes) and the stream (the current
+torch stream).  The binding refuses to run when the library is missing: there
+is no CPU path.
 """
 import ctypes as C
 import os
@@ -37,7 +38,7 @@ class LbDesc(C.Structure):
 
 class LbSizes(C.Structure):
     _fields_ = [(n, C.c_size_t) for n in ("pops_bytes", "flags_bytes", "force_bytes", "beads_bytes",
-                                          "work_bytes", "state_bytes")]
+                                          "work_bytes", "state_bytes", "nodes", "bead_slots")]
 
 
 class LbBuffers(C.Structure):
@@ -67,13 +68,21 @@ def lib():
 
 def _declare(L):
     P = C.c_void_p
+    D = C.POINTER(LbDesc)
     L.lb_last_error.restype = C.c_char_p
-    L.lb_buffer_sizes.argtypes = [C.POINTER(LbDesc), C.POINTER(LbSizes)]
-    L.lb_init.argtypes = [C.POINTER(LbDesc), C.POINTER(LbBuffers), P, P, P, C.POINTER(P)]
+    L.lb_buffer_sizes.argtypes = [D, C.POINTER(LbSizes)]
+    L.lb_ensemble_sizes.argtypes = [D, C.c_int, C.POINTER(LbSizes)]
+    L.lb_init.argtypes = [D, C.POINTER(LbBuffers), P, P, P, C.POINTER(P)]
+    L.lb_ensemble_init.argtypes = [D, C.c_int, C.POINTER(LbBuffers), P, P, P, C.POINTER(P)]
+    L.lb_ensemble_layout.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.lb_destroy.argtypes = [P]
     L.lb_destroy.restype = None
     L.lb_step.argtypes = [P, C.c_int]
     L.md_couple_step.argtypes = [P, C.c_int]
+    L.lb_ensemble_run.argtypes = [P, C.c_int, C.c_int]
+    L.lb_ensemble_translocation.argtypes = [P, C.POINTER(C.c_int64)]
+    L.lb_sweep_config.argtypes = [P, C.c_int, C.c_int, C.c_int]
+    L.lb_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.md_relax.argtypes = [P, C.c_int, C.c_double]
     L.lb_observables.argtypes = [P, P]
     L.lb_get_state.argtypes = [P, P]
@@ -95,6 +104,11 @@ def _raise(code):
 
 def make_desc(cfg, precision=LB_FP64):
     d = LbDesc()
+    _fill_desc(d, cfg, precision)
+    return d
+
+
+def _fill_desc(d, cfg, precision):
     d.nx, d.ny, d.nz = cfg["shape"]
     d.precision = precision
     d.tau = cfg.get("tau", 1.0)
@@ -118,31 +132,50 @@ def make_desc(cfg, precision=LB_FP64):
     d.n_sub = cfg.get("n_sub", 100)
     d.seed = cfg.get("seed", 1234) & 0xFFFFFFFF
     d.replica = cfg.get("replica", 0) & 0xFFFFFFFF
-    return d
+
+
+def make_descs(cfgs, precision=LB_FP64):
+    arr = (LbDesc * len(cfgs))()
+    for k, cfg in enumerate(cfgs):
+        _fill_desc(arr[k], cfg, precision)
+    return arr
+
+
+def _sizes_dict(s):
+    return {n: getattr(s, n) for n, _ in LbSizes._fields_}
 
 
 def buffer_sizes(cfg, precision=LB_FP64):
     d = make_desc(cfg, precision)
     s = LbSizes()
     _raise(lib().lb_buffer_sizes(C.byref(d), C.byref(s)))
-    return {n: getattr(s, n) for n, _ in LbSizes._fields_}
+    return _sizes_dict(s)
 
 
-class Simulation:
-    """One coupled LB/MD system on one GPU (a context of liblbmd)."""
+def ensemble_sizes(cfgs, precision=LB_FP64):
+    arr = make_descs(cfgs, precision)
+    s = LbSizes()
+    _raise(lib().lb_ensemble_sizes(arr, len(cfgs), C.byref(s)))
+    return _sizes_dict(s)
 
-    def __init__(self, cfg, r0=None, v0=None, precision=LB_FP64, device="cuda:0"):
+
+class Context:
+    """R >= 1 coupled LB/MD systems on one GPU, advanced in lockstep (one
+    context of liblbmd).  Replica r has its own lattice, wall, chain and
+    noise key; r0s[r] / v0s[r] are its chain's positions / velocities."""
+
+    def __init__(self, cfgs, r0s=None, v0s=None, precision=LB_FP64, device="cuda:0"):
         import torch
         self.torch = torch
-        self.cfg = dict(cfg)
+        self.cfgs = [dict(c) for c in cfgs]
+        self.nrep = len(self.cfgs)
         self.precision = precision
         self.device = torch.device(device)
-        self.desc = make_desc(cfg, precision)
-        self.nb = self.desc.nb
-        self.shape = tuple(cfg["shape"])
-        nx, ny, nz = self.shape
-        self.N = nx * ny * nz
-        self.sizes = buffer_sizes(cfg, precision)
+        self.descs = make_descs(self.cfgs, precision)
+        self.nbs = [int(c.get("nb", 0)) for c in self.cfgs]
+        self.shapes = [tuple(c["shape"]) for c in self.cfgs]
+        self.Ns = [nx * ny * nz for nx, ny, nz in self.shapes]
+        self.sizes = ensemble_sizes(self.cfgs, precision)
         alloc = lambda n: torch.empty(int(n), dtype=torch.uint8, device=self.device)
         self._bufs = {
             "pops_a": alloc(self.sizes["pops_bytes"]), "pops_b": alloc(self.sizes["pops_bytes"]),
@@ -150,24 +183,34 @@ class Simulation:
             "beads": alloc(self.sizes["beads_bytes"]), "work": alloc(self.sizes["work_bytes"]),
         }
         b = LbBuffers(*[self._bufs[k].data_ptr() for k, _ in LbBuffers._fields_])
-        if self.nb > 0:
-            if r0 is None:
+        nbt = sum(self.nbs)
+        rp = vp = None
+        if nbt > 0:
+            if r0s is None:
                 raise ValueError("bead positions required")
-            r0 = np.ascontiguousarray(r0, dtype=np.float64).reshape(-1)
-            assert r0.size == 3 * self.nb
-        rp = r0.ctypes.data_as(C.c_void_p) if self.nb > 0 else None
-        if v0 is not None:
-            v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1)
-            assert v0.size == 3 * self.nb
-        vp = v0.ctypes.data_as(C.c_void_p) if v0 is not None and self.nb > 0 else None
+            r0 = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.float64).reshape(-1, 3)
+                                                      for r, n in zip(r0s, self.nbs) if n > 0]))
+            assert r0.shape == (nbt, 3)
+            rp = r0.ctypes.data_as(C.c_void_p)
+            if v0s is not None:
+                v0 = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.float64).reshape(-1, 3)
+                                                          for v, n in zip(v0s, self.nbs) if n > 0]))
+                assert v0.shape == (nbt, 3)
+                vp = v0.ctypes.data_as(C.c_void_p)
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             ctx = C.c_void_p()
-            _raise(lib().lb_init(C.byref(self.desc), C.byref(b), rp, vp, C.c_void_p(self.stream.cuda_stream),
-                                 C.byref(ctx)))
+            _raise(lib().lb_ensemble_init(self.descs, self.nrep, C.byref(b), rp, vp,
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
         self.ctx = ctx
         self._destroy = lib().lb_destroy      # kept for teardown at interpreter exit
-        self._obs = torch.empty(LB_NOBS, dtype=torch.float64, device=self.device)
+        no = (C.c_int64 * self.nrep)()
+        so = (C.c_int64 * self.nrep)()
+        _raise(lib().lb_ensemble_layout(self.ctx, no, so))
+        self.node_off = list(no)
+        self.slot_off = list(so)
+        self.slots = int(self.sizes["bead_slots"])
+        self._obs = torch.empty(LB_NOBS * self.nrep, dtype=torch.float64, device=self.device)
 
     def close(self):
         """Synchronise and release the library context (the buffers are freed
@@ -191,11 +234,29 @@ class Simulation:
     def couple_step(self, n=1):
         _raise(lib().md_couple_step(self.ctx, int(n)))
 
+    def run(self, n, graph=True):
+        """n coupled steps, replayed from a captured HIP graph when graph."""
+        _raise(lib().lb_ensemble_run(self.ctx, int(n), 1 if graph else 0))
+
     def relax(self, nsub_total, gamma_relax):
         _raise(lib().md_relax(self.ctx, int(nsub_total), float(gamma_relax)))
 
     def check(self):
         _raise(lib().lb_check(self.ctx))
+
+    def sweep_config(self, tile_nodes, order=0, grid=0):
+        _raise(lib().lb_sweep_config(self.ctx, int(tile_nodes), int(order), int(grid)))
+
+    def autotune(self, reps=5):
+        cfg = (C.c_int * 3)()
+        ms = C.c_double()
+        _raise(lib().lb_autotune(self.ctx, int(reps), cfg, C.byref(ms)))
+        return dict(tile_nodes=cfg[0], order=cfg[1], grid=cfg[2], ms=ms.value)
+
+    def translocation_steps(self):
+        out = (C.c_int64 * self.nrep)()
+        _raise(lib().lb_ensemble_translocation(self.ctx, out))
+        return list(out)
 
     def profile_start(self, max_steps):
         _raise(lib().lb_profile_start(self.ctx, int(max_steps)))
@@ -209,7 +270,7 @@ class Simulation:
     def diagnostics(self):
         out = (C.c_int64 * 5)()
         _raise(lib().lb_diagnostics(self.ctx, out))
-        return dict(zip(("rebuilds", "substeps", "forced_nodes", "watchdog", "steps"), list(out)))
+        return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps"), list(out)))
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))
@@ -219,31 +280,38 @@ class Simulation:
     def dtype(self):
         return self.torch.float64 if self.precision == LB_FP64 else self.torch.float32
 
-    def pops(self):
-        """View of the current populations as [19, nz, ny, nx] (f_i in FP64
-        storage, f_i - w_i in FP32 deviation storage)."""
+    def _cur(self):
         ptr = lib().lb_current_pops(self.ctx)
-        t = self._bufs["pops_a"] if ptr == self._bufs["pops_a"].data_ptr() else self._bufs["pops_b"]
-        nx, ny, nz = self.shape
-        es = 8 if self.precision == LB_FP64 else 4
-        return t[: Q * self.N * es].view(self.dtype).view(Q, nz, ny, nx)
+        return self._bufs["pops_a"] if ptr == self._bufs["pops_a"].data_ptr() else self._bufs["pops_b"]
 
-    def flags(self):
-        nx, ny, nz = self.shape
-        return self._bufs["flags"][: self.N].view(nz, ny, nx)
+    def pops(self, r=0):
+        """View of replica r's current populations as [19, nz, ny, nx] (f_i
+        in FP64 storage, f_i - w_i in FP32 deviation storage)."""
+        nx, ny, nz = self.shapes[r]
+        flat = self._cur().view(self.dtype)
+        o = Q * self.node_off[r]
+        return flat[o: o + Q * self.Ns[r]].view(Q, nz, ny, nx)
 
-    def beads(self):
-        """Views of the bead arrays: r, v, up, J, rs, each (nb, 3) float64."""
-        nbs = max(self.nb, 1)
-        b = self._bufs["beads"][: 15 * nbs * 8].view(self.torch.float64)
+    def flags(self, r=0):
+        nx, ny, nz = self.shapes[r]
+        o = self.node_off[r]
+        return self._bufs["flags"][o: o + self.Ns[r]].view(nz, ny, nx)
+
+    def beads(self, r=0):
+        """Views of replica r's bead arrays: r, v, up, J, rs, each (nb, 3)
+        float64."""
+        ns = self.slots
+        b = self._bufs["beads"][: 15 * ns * 8].view(self.torch.float64)
+        o, nb = self.slot_off[r], self.nbs[r]
         out = {}
         for k, name in enumerate(("r", "v", "up", "J", "rs")):
-            out[name] = b[3 * nbs * k: 3 * nbs * k + 3 * self.nb].view(self.nb, 3)
+            out[name] = b[3 * ns * k + 3 * o: 3 * ns * k + 3 * (o + nb)].view(nb, 3)
         return out
 
     def observables(self):
+        """[nrep, LB_NOBS] float64 on the device (see lb_observables)."""
         _raise(lib().lb_observables(self.ctx, C.c_void_p(self._obs.data_ptr())))
-        return self._obs
+        return self._obs.view(self.nrep, LB_NOBS)
 
     def get_state(self):
         st = self.torch.empty(self.sizes["state_bytes"], dtype=self.torch.uint8, device=self.device)
@@ -252,3 +320,23 @@ class Simulation:
 
     def set_state(self, st):
         _raise(lib().lb_set_state(self.ctx, C.c_void_p(st.data_ptr())))
+
+
+class Simulation(Context):
+    """One coupled LB/MD system (a context with one replica)."""
+
+    def __init__(self, cfg, r0=None, v0=None, precision=LB_FP64, device="cuda:0"):
+        super().__init__([cfg], [r0] if r0 is not None else None, [v0] if v0 is not None else None,
+                         precision=precision, device=device)
+        self.cfg = self.cfgs[0]
+        self.nb = self.nbs[0]
+        self.shape = self.shapes[0]
+        self.N = self.Ns[0]
+
+    def observables(self):
+        return super().observables()[0]
+
+
+class Ensemble(Context):
+    """The batched ensemble: replicas of uneven lattices and chain lengths in
+    one context."""

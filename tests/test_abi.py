@@ -40,7 +40,7 @@ def test_desc_layout_matches_header():
     # the ctypes mirror has the field order and sizes of struct lb_desc
     from paper_0711_2665_amd import lbmd
     assert C.sizeof(lbmd.LbDesc) == 4 * 4 + 8 * 4 + 4 * 4 + 8 * 10 + 4 * 3 + 4  # trailing pad to 8
-    assert C.sizeof(lbmd.LbSizes) == 6 * 8
+    assert C.sizeof(lbmd.LbSizes) == 8 * 8
     assert C.sizeof(lbmd.LbBuffers) == 6 * 8
 
 
@@ -74,6 +74,28 @@ def test_buffer_sizes_are_aligned_and_exact():
     N = 512 * 256 * 256
     assert s["pops_bytes"] == 19 * N * 4
     assert s["flags_bytes"] == N
-    assert all(v % 256 == 0 for v in s.values())
+    assert all(v % 256 == 0 for k, v in s.items() if k.endswith("_bytes"))
+    assert s["nodes"] == N and s["bead_slots"] == 8000
     s64 = lbmd.buffer_sizes(C3, lbmd.LB_FP64)
     assert s64["pops_bytes"] == 19 * N * 8
+
+
+def test_ensemble_sizes_pack_replicas():
+    """Host-only packing of an uneven ensemble: node offsets rounded to 64
+    nodes, bead slots to 16 per chain; mixed n_sub is refused."""
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import C0, scaled
+    cfgs = [scaled(C0, shape=(16, 12, 20), wall_pos=10, nb=12), scaled(C0, shape=(12, 12, 13), wall_axis=-1,
+                                                                          wall_pos=0, pore_h=0, nb=0),
+            scaled(C0, shape=(24, 24, 24), wall_pos=12, nb=33)]
+    s = lbmd.ensemble_sizes(cfgs, lbmd.LB_FP32_DEV)
+    nodes = 3840 + 1920 + 13824
+    assert s["nodes"] == nodes and s["bead_slots"] == 16 + 0 + 48
+    assert s["pops_bytes"] == (19 * nodes * 4 + 255) // 256 * 256
+    with pytest.raises(lbmd.LbError) as e:
+        lbmd.ensemble_sizes([cfgs[0], scaled(cfgs[2], n_sub=50)])
+    assert "n_sub" in str(e.value)
+    with pytest.raises(lbmd.LbError) as e:
+        lbmd.ensemble_sizes([cfgs[0], dict(cfgs[2], tau=0.4)])
+    assert "replica 1" in str(e.value)
+

@@ -1,0 +1,200 @@
+"""Batched ensemble: several replicas of uneven lattice and chain size in one
+context, advanced by the same launches.  Replicas are independent, so every
+replica must equal, bit for bit, the same system run alone (whose parity with
+the oracle the single-system tests establish); one replica with an x-normal
+wall is also held bitwise to the oracle.  Graph replay, the sweep layouts and
+the autotuner must not change any result."""
+import numpy as np
+import pytest
+
+from paper_0711_2665_amd.workloads import C0, initial_chain, scaled
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _cfgs():
+    return [
+        scaled(C0, name="e0", shape=(16, 12, 20), wall_axis=2, wall_pos=10, pore_h=3, nb=12, seed=11, replica=0,
+               init_seed=5, f_drive=0.03),
+        scaled(C0, name="e1", shape=(20, 16, 16), wall_axis=0, wall_pos=10, pore_h=4, nb=20, seed=12, replica=1,
+               init_seed=6, gamma=0.2),
+        scaled(C0, name="e2", shape=(12, 12, 13), wall_axis=-1, wall_pos=0, pore_h=0, nb=0, g=(1e-5, 0.0, 0.0)),
+        scaled(C0, name="e3", shape=(24, 24, 24), wall_axis=2, wall_pos=12, pore_h=3, nb=33, seed=13, replica=3,
+               init_seed=7, kT=0.0),
+    ]
+
+
+def _chains(cfgs):
+    return [initial_chain(c)[0] for c in cfgs]
+
+
+def _snapshot(ctx):
+    out = []
+    for k in range(ctx.nrep):
+        b = ctx.beads(k)
+        out.append(dict(pops=ctx.pops(k).clone(), **{n: b[n].clone() for n in ("r", "v", "up", "J")}))
+    return out
+
+
+def _assert_same(a, b, label):
+    import torch
+    for k, (x, y) in enumerate(zip(a, b)):
+        for n in x:
+            assert torch.equal(x[n], y[n]), (label, k, n)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_each_replica_equals_its_system_run_alone(precision):
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    prec = lbmd.LB_FP64 if precision == "fp64" else lbmd.LB_FP32_DEV
+    cfgs = _cfgs()
+    r0s = _chains(cfgs)
+    ens = lbmd.Ensemble(cfgs, r0s, precision=prec)
+    assert ens.node_off == sorted(ens.node_off) and all(o % 64 == 0 for o in ens.node_off)
+    assert all(o % 16 == 0 for o in ens.slot_off)
+    ens.relax(500, 1.0)
+    ens.couple_step(12)
+    obs = ens.observables().cpu().numpy()
+    torch.cuda.synchronize()
+    ens.check()
+    got = _snapshot(ens)
+    for k, cfg in enumerate(cfgs):
+        s = lbmd.Simulation(cfg, r0s[k] if cfg["nb"] else None, precision=prec)
+        s.relax(500, 1.0)
+        s.couple_step(12)
+        so = s.observables().cpu().numpy()
+        torch.cuda.synchronize()
+        want = _snapshot(s)[0]
+        assert torch.equal(ens.flags(k), s.flags())
+        for n in want:
+            nd = int((got[k][n] != want[n]).sum())
+            print(f"{precision} replica {k} {n}: differing entries {nd}", flush=True)
+            assert nd == 0, (k, n)
+        assert np.array_equal(obs[k][:16], so[:16]) and obs[k][22] == so[22], k
+        s.close()
+
+
+def test_x_wall_replica_matches_oracle_bitwise(orc):
+    """kT = 0 and kappa = 0 remove every transcendental function, so the
+    replica with the wall normal to x must equal the oracle bit for bit."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = [scaled(c, kT=0.0, kappa=0.0) for c in _cfgs()]
+    r0s = _chains(cfgs)
+    o = orc.Oracle(cfgs[1], r0s[1])
+    o.relax(500, 1.0)
+    ob = o.beads()
+    o = orc.Oracle(cfgs[1], ob["r"], np.zeros_like(ob["r"]))
+    r0s[1] = ob["r"]
+    ens = lbmd.Ensemble(cfgs, r0s)
+    o.couple_step(3)
+    ens.couple_step(3)
+    torch.cuda.synchronize()
+    fluid = o.flags() == 0
+    a, b = ens.pops(1).cpu().numpy()[:, fluid], o.pops()[:, fluid]
+    sb = {k: t.cpu().numpy() for k, t in ens.beads(1).items()}
+    ob = o.beads()
+    print("x-wall replica, 3 steps: pops differing", int((a != b).sum()),
+          {k: int((sb[k] != ob[k]).sum()) for k in ("r", "v", "up", "J")}, flush=True)
+    assert np.array_equal(a, b)
+    for k in ("r", "v", "up", "J"):
+        assert np.array_equal(sb[k], ob[k]), k
+
+
+def test_graph_replay_equals_eager_steps():
+    """The captured graph (two coupled steps) replayed several times, with
+    eager work and synchronisations between the replays, gives the eager
+    result at every check."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = _cfgs()
+    r0s = _chains(cfgs)
+    a = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    b = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    for e in (a, b):
+        e.relax(300, 1.0)
+    for n in (5, 6, 1, 4, 7):
+        a.couple_step(n)
+        b.run(n, graph=True)
+        oa = a.observables().cpu().numpy()
+        ob = b.observables().cpu().numpy()
+        torch.cuda.synchronize()
+        _assert_same(_snapshot(a), _snapshot(b), f"after {n}")
+        assert np.array_equal(oa, ob, equal_nan=True)
+        assert a.step_count() == b.step_count()
+        assert a.translocation_steps() == b.translocation_steps()
+    a.check()
+    b.check()
+
+
+def test_sweep_layouts_and_autotuner_leave_results_unchanged():
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = _cfgs()
+    r0s = _chains(cfgs)
+    ref = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    ref.relax(300, 1.0)
+    ref.couple_step(4)
+    torch.cuda.synchronize()
+    want = _snapshot(ref)
+    for tile, order, grid in ((512, 0, 0), (256, 1, 0), (1024, 1, 0), (256, 0, 7), (2048, 1, 3)):
+        e = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+        e.sweep_config(tile, order, grid)
+        e.relax(300, 1.0)
+        e.couple_step(4)
+        torch.cuda.synchronize()
+        _assert_same(_snapshot(e), want, (tile, order, grid))
+        e.close()
+    e = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    e.relax(300, 1.0)
+    e.couple_step(2)
+    before = _snapshot(e)
+    best = e.autotune(reps=2)
+    print("autotune:", best, flush=True)
+    assert best["tile_nodes"] % 256 == 0 and best["order"] in (0, 1) and best["grid"] >= 0
+    _assert_same(_snapshot(e), before, "autotune changed the state")
+    e.couple_step(2)
+    torch.cuda.synchronize()
+    _assert_same(_snapshot(e), want, "after autotune")
+    again = e.autotune(reps=2)       # cached for this layout
+    assert again["ms"] == -1.0 and {k: again[k] for k in ("tile_nodes", "order", "grid")} == \
+        {k: best[k] for k in ("tile_nodes", "order", "grid")}
+
+
+def test_translocation_steps_and_resume():
+    """A chain laid entirely on the trans side is translocated after the first
+    step; a chain on the cis side and a replica without wall stay at -1.  The
+    record is part of the saved state."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = _cfgs()
+    r0s = _chains(cfgs)
+    nb = cfgs[3]["nb"]
+    # an open arc of unit chords in the plane four spacings past the wall
+    R = 1.0 / (2.0 * np.sin(np.pi / 36))
+    th = np.arange(nb) * 2.0 * np.pi / 36
+    trans = np.stack([12.0 + R * np.cos(th), 12.0 + R * np.sin(th), np.full(nb, cfgs[3]["wall_pos"] + 4.0)], 1)
+    r0s[3] = trans
+    ens = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    assert ens.translocation_steps() == [-1, -1, -1, -1]
+    ens.relax(300, 1.0)
+    ens.couple_step(1)
+    t1 = ens.translocation_steps()
+    r3 = ens.beads(3)["r"].cpu().numpy()
+    assert (r3[:, 2] > cfgs[3]["wall_pos"]).all()
+    assert t1 == [-1, -1, -1, 1], t1
+    st = ens.get_state()
+    ens.couple_step(3)
+    assert ens.translocation_steps() == [-1, -1, -1, 1]
+    fresh = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    fresh.set_state(st)
+    assert fresh.step_count() == 1 and fresh.translocation_steps() == [-1, -1, -1, 1]
+    torch.cuda.synchronize()
