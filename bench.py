@@ -8,15 +8,18 @@ every lattice node).  The default workload is the large single run:
 512 x 256 x 256 nodes (33.5 M), wall normal to x at x = 256 with a 7 x 7
 pore, one 8000-bead chain, FP32 deviation storage of the populations.
 Inputs are synthetic (seeded self-avoiding coil, relaxed on the GPU before
-timing) and resident in HBM before the timed region.
+timing) and resident in HBM before the timed region.  The sweep's tile
+layout is chosen by the library's autotuner before timing.
 
 Prints one JSON line: the metric (MLUPS of the whole coupled step), the
 roofline of the dominant kernel (the LB sweep, timed with HIP events inside
-the library on the stream it runs on), the FP64 path on the same workload,
-bead throughput, and the FP64 CPU oracle timed on a bounded sample.
+the library on the stream it runs on), the same steps replayed from a
+captured HIP graph, the FP64 path on the same workload, bead throughput, the
+batched ensemble (64 uneven replicas in one context, graph replay, aggregate
+MLUPS and translocation steps), and the FP64 CPU oracle timed on a bounded
+sample.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,28 +38,22 @@ def lb_bytes_per_update(elem_bytes):
     return 2 * Q * elem_bytes + 1
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("lb_kernels.hip", "lbmd_dev.h", "lbmd_kernels.h"):
-        with open(os.path.join(ROOT, "paper_0711_2665_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def measured_traffic(workload, precision):
+def measured_traffic(workload, precision, layout):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current kernel source with the same sweep
+    layout; else None."""
+    from paper_0711_2665_amd.build import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"lb_sweep_{precision}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("sweep_layout") != layout:
         return None
     return d.get("bytes_per_launch")
 
 
-def run_gpu(cfg, precision_name, steps, warmup):
+def run_gpu(cfg, precision_name, steps, warmup, graph_steps=0):
     import torch
     from paper_0711_2665_amd import lbmd
     from paper_0711_2665_amd.workloads import initial_chain
@@ -65,9 +62,11 @@ def run_gpu(cfg, precision_name, steps, warmup):
     r, v = initial_chain(cfg)
     sim = lbmd.Simulation(cfg, r, v, precision=prec, device="cuda:0")
     sim.relax(cfg["relax_substeps"], cfg["gamma_relax"])
+    tune = sim.autotune(reps=10)
     sim.couple_step(warmup)
     torch.cuda.synchronize()
     sim.check()
+    forced0 = sim.diagnostics()["forced_total"]
     sim.profile_start(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -76,11 +75,73 @@ def run_gpu(cfg, precision_name, steps, warmup):
     t1 = time.perf_counter()
     lb_ms, bead_ms, nrec = sim.profile_stop()
     sim.check()
-    obs = sim.observables().cpu().numpy()
-    nfluid = int(((sim.flags() & 1) == 0).sum().item())
+    out = dict(seconds=t1 - t0, lb_ms=lb_ms, bead_ms=bead_ms, nrec=nrec, tune=tune)
+    out["forced_per_step"] = (sim.diagnostics()["forced_total"] - forced0) / steps
+    if graph_steps:
+        sim.run(2, graph=True)           # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.run(graph_steps, graph=True)
+        torch.cuda.synchronize()
+        out["graph_seconds"] = time.perf_counter() - t0
+        sim.check()
+    out["obs"] = sim.observables().cpu().numpy()
+    out["nfluid"] = int(((sim.flags() & 1) == 0).sum().item())
     del sim
     torch.cuda.empty_cache()
-    return dict(seconds=t1 - t0, lb_ms=lb_ms, bead_ms=bead_ms, nrec=nrec, nfluid=nfluid, obs=obs)
+    return out
+
+
+def run_ensemble(steps, warmup, eager_steps):
+    """The batched ensemble: 64 replicas, cubic edges from {48, 64, 80, 96},
+    chains of {50, 100, 200, 500} beads, pore 3..5, pore force U(0.01, 0.04),
+    own noise key each, FP32 deviation storage, one context; coupled steps
+    replayed from a captured HIP graph."""
+    import torch
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import ensemble_configs, initial_chain
+
+    cfgs = ensemble_configs(64)
+    r0s = [initial_chain(c)[0] for c in cfgs]
+    ens = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV, device="cuda:0")
+    ens.relax(cfgs[0]["relax_substeps"], cfgs[0]["gamma_relax"])
+    tune = ens.autotune(reps=10)
+    ens.couple_step(warmup)
+    torch.cuda.synchronize()
+    ens.check()
+    t0 = time.perf_counter()
+    ens.couple_step(eager_steps)
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+    ens.run(2, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ens.run(steps, graph=True)
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - t0
+    ens.check()
+    tx = ens.translocation_steps()
+    total_steps = ens.step_count()
+    cells = sum(c["shape"][0] * c["shape"][1] * c["shape"][2] for c in cfgs)
+    beads = sum(c["nb"] for c in cfgs)
+    done = sorted(t for t in tx if t >= 0)
+    by_len = {}
+    for c, t in zip(cfgs, tx):
+        by_len.setdefault(c["nb"], []).append(t)
+    res = {
+        "replicas": len(cfgs), "cells": cells, "beads": beads, "steps": steps,
+        "value": round(cells * steps / graph_s / 1e6, 1), "unit": "MLUPS (aggregate)",
+        "ms_per_step": round(1e3 * graph_s / steps, 4),
+        "eager_ms_per_step": round(1e3 * eager_s / eager_steps, 4),
+        "bead_steps_per_s": round(beads * steps / graph_s, 1),
+        "sweep_layout": {k: tune[k] for k in ("tile_nodes", "order", "grid")},
+        "translocation": {"steps_run": total_steps, "translocated": len(done), "censored": len(tx) - len(done),
+                          "steps": done,
+                          "by_chain_length": {str(k): sorted(t for t in v if t >= 0) for k, v in sorted(by_len.items())}},
+    }
+    del ens
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_cpu_baseline(cfg, steps):
@@ -110,6 +171,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -121,13 +184,17 @@ def main():
     nx, ny, nz = cfg["shape"]
     cells = nx * ny * nz
 
-    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, graph_steps=args.steps)
     ms_per_step = 1e3 * main_run["seconds"] / args.steps
     mlups = cells * args.steps / main_run["seconds"] / 1e6
     elem = 4 if args.precision == "fp32dev" else 8
-    alg_bytes = main_run["nfluid"] * lb_bytes_per_update(elem) + (cells - main_run["nfluid"])
+    # the timed sweep skips the nodes carrying bead force (they are updated
+    # after the spreading) and reads only their flag
+    upd = main_run["nfluid"] - main_run["forced_per_step"]
+    alg_bytes = int(round(upd * lb_bytes_per_update(elem) + (cells - upd)))
     achieved = alg_bytes / (main_run["lb_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.precision)
+    layout = {k: main_run["tune"][k] for k in ("tile_nodes", "order", "grid")}
+    traffic = measured_traffic(args.workload, args.precision, layout)
     out = {
         "metric": "LB MLUPS of the coupled LB/MD step (and %HBM roofline of the LB sweep)",
         "value": round(mlups, 1),
@@ -147,6 +214,9 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_lb (fused stream+collide)", "bytes_per_launch": alg_bytes,
                      "mean_launch_ms": round(main_run["lb_ms"], 5)},
+        "sweep_layout": layout,
+        "graph_replay": {"value": round(cells * args.steps / main_run["graph_seconds"] / 1e6, 1), "unit": "MLUPS",
+                         "ms_per_step": round(1e3 * main_run["graph_seconds"] / args.steps, 4)},
         "lb_sweep_mlups": round(cells / (main_run["lb_ms"] * 1e-3) / 1e6, 1),
         "bead_phase_ms": round(main_run["bead_ms"], 4),
         "bead_steps_per_s": round(cfg["nb"] * args.steps / main_run["seconds"], 1),
@@ -154,11 +224,15 @@ def main():
     }
     if not args.no_fp64 and args.precision == "fp32dev":
         k64 = max(20, args.steps // 4)
-        r64 = run_gpu(cfg, "fp64", k64, max(5, args.warmup // 4))
-        ach64 = (r64["nfluid"] * lb_bytes_per_update(8) + (cells - r64["nfluid"])) / (r64["lb_ms"] * 1e-3) / 1e9
+        r64 = run_gpu(cfg, "fp64", k64, max(5, args.warmup // 4), graph_steps=k64)
+        u64 = r64["nfluid"] - r64["forced_per_step"]
+        ach64 = (u64 * lb_bytes_per_update(8) + (cells - u64)) / (r64["lb_ms"] * 1e-3) / 1e9
         out["fp64"] = {"value": round(cells * k64 / r64["seconds"] / 1e6, 1), "unit": "MLUPS", "steps": k64,
                        "ms_per_step": round(1e3 * r64["seconds"] / k64, 4),
+                       "graph_ms_per_step": round(1e3 * r64["graph_seconds"] / k64, 4),
                        "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
+    if not args.no_ensemble and args.workload == "c3":
+        out["ensemble"] = run_ensemble(args.ensemble_steps, 20, 200)
     if not args.no_cpu:
         cb = run_cpu_baseline(cfg, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "MLUPS", "cores": cb["cores"],

@@ -203,8 +203,9 @@ int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid);
 /* Autotuner of the sweep layout: times `reps` sweeps of every candidate
  * layout (tile sizes 256..2048, both orders, two persistent grids) with HIP
  * events, from the current populations into the other array (which the
- * next step overwrites, so the state is unchanged), keeps the fastest and
- * caches it for the process by (replica extents and walls, precision).
+ * next step overwrites, so the state is unchanged), keeps the first
+ * candidate within 1% of the fastest and caches it for the process by
+ * (replica extents and walls, precision).
  * Writes {tile_nodes, order, grid} to out_cfg[3] and the mean sweep time in
  * ms to *out_ms (-1 when taken from the cache).  Synchronises the stream. */
 int lb_autotune(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
@@ -258,9 +259,10 @@ int64_t lb_step_count(lb_ctx* ctx);
 int lb_profile_start(lb_ctx* ctx, int max_steps);
 int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* nsteps);
 
-/* Diagnostics: synchronises the stream and writes out[0] = neighbour-list
- * rebuilds (summed over replicas), out[1] = MD sub-step launches, out[2] =
- * tiles of the sweep, out[3] = watchdog bits, out[4] = LB steps taken. */
+/* Diagnostics: synchronises the stream and writes six int64: out[0] =
+ * neighbour-list rebuilds (summed over replicas), out[1] = MD sub-step
+ * launches, out[2] = tiles of the sweep, out[3] = watchdog bits, out[4] = LB
+ * steps taken, out[5] = nodes that carried bead force, summed over steps. */
 int lb_diagnostics(lb_ctx* ctx, int64_t* out);
 
 /* Message of the last failed call on this thread (never NULL). */

@@ -5,6 +5,7 @@
 Multiply-add contraction is off so that the FP64 path rounds each written
 operation exactly once; packed FP32 instructions are disabled.
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -39,6 +40,16 @@ def build(verbose=False):
     subprocess.check_call(cmd)
     os.replace(LIB + ".tmp", LIB)
     return LIB
+
+
+def kernel_source_hash():
+    """Short hash of the sources that define the lattice sweep; a counter
+    summary taken on other sources no longer describes the kernel."""
+    h = hashlib.sha256()
+    for f in ("lb_kernels.hip", "lbmd_dev.h", "lbmd_kernels.h"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def stale():

@@ -418,6 +418,7 @@ __global__ void k_step_tick(Dev d, int nrep, int with_beads) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    d.ctrl->forced_total += d.ctrl->touched;
     d.ctrl->touched = 0u;
     d.ctrl->step = next;
   }

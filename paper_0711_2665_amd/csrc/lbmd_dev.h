@@ -54,8 +54,10 @@ struct Ctrl {
   uint64_t step;             // LB steps taken (Philox counter word 0)
   uint64_t rebuilds;         // neighbour-list rebuilds so far (diagnostic)
   uint64_t substeps;         // MD sub-steps so far (diagnostic)
-  uint32_t pad[56];
+  uint64_t forced_total;     // nodes carrying bead force, summed over steps (diagnostic)
+  uint32_t pad[54];
 };
+static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 
 // Geometry and lattice extents.
 struct Geom {

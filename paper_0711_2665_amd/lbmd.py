@@ -268,9 +268,9 @@ class Context:
         return a.value, b.value, n.value
 
     def diagnostics(self):
-        out = (C.c_int64 * 5)()
+        out = (C.c_int64 * 6)()
         _raise(lib().lb_diagnostics(self.ctx, out))
-        return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps"), list(out)))
+        return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps", "forced_total"), list(out)))
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))

@@ -1,17 +1,23 @@
-"""Workload driver for rocprofv3 runs of the LB sweep.
+"""Workload driver for rocprofv3 counter runs of the LB sweep.
 
-    python -m paper_0711_2665_amd.profile_run --workload c3 --precision fp32dev --steps 5 --copy-mib 1024
+    python -m paper_0711_2665_amd.profile_run --workload c3 --precision fp32dev --steps 5 \
+        --copy-mib 1024 --meta gpurun_out/lb_sweep_meta.json
 
-Runs `steps` fluid-only sweeps of the workload's lattice (the same kernel the
-coupled step launches for the nodes without bead force) and then a plain
-device-to-device copy of `copy_mib` MiB, whose counter readings calibrate the
-HBM byte counters (FETCH_SIZE, WRITE_SIZE) against a known transfer.
+Builds the workload's lattice without beads, lets the autotuner choose the
+sweep layout (the one the benchmark uses), runs `steps` fluid-only sweeps
+(the kernel the coupled step launches for the nodes without bead force) and
+then a plain device-to-device copy of `copy_mib` MiB, whose counter readings
+calibrate the HBM byte counters (FETCH_SIZE, WRITE_SIZE) against a known
+transfer.  Writes what the summary needs (layout, kernel source hash, node
+counts, algorithmic bytes, copy size) to --meta.
 """
 import argparse
+import json
 
 import torch
 
 from . import lbmd
+from .build import kernel_source_hash
 from .workloads import CONFIGS, scaled
 
 
@@ -21,10 +27,12 @@ def main():
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--meta", default=None)
     a = ap.parse_args()
     cfg = scaled(CONFIGS[a.workload], nb=0)
     prec = lbmd.LB_FP32_DEV if a.precision == "fp32dev" else lbmd.LB_FP64
     sim = lbmd.Simulation(cfg, precision=prec)
+    tune = sim.autotune(reps=10)
     sim.lb_step(a.steps)
     torch.cuda.synchronize()
     sim.check()
@@ -33,7 +41,18 @@ def main():
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(f"profile_run: {a.steps} sweeps of {cfg['shape']} ({a.precision}), copy of {a.copy_mib} MiB", flush=True)
+    nx, ny, nz = cfg["shape"]
+    nfluid = int(((sim.flags() & 1) == 0).sum().item())
+    es = 4 if a.precision == "fp32dev" else 8
+    meta = dict(workload=a.workload, precision=a.precision, shape=[nx, ny, nz], nodes=nx * ny * nz, nfluid=nfluid,
+                algorithmic_bytes_per_launch=nfluid * (2 * 19 * es + 1) + (nx * ny * nz - nfluid),
+                sweep_layout={k: tune[k] for k in ("tile_nodes", "order", "grid")},
+                kernel_source_hash=kernel_source_hash(), copy_bytes=n * 4, sweeps=a.steps)
+    if a.meta:
+        with open(a.meta, "w") as fh:
+            json.dump(meta, fh)
+    print(f"profile_run: {a.steps} sweeps of {cfg['shape']} ({a.precision}), layout {meta['sweep_layout']}, "
+          f"copy of {a.copy_mib} MiB", flush=True)
 
 
 if __name__ == "__main__":

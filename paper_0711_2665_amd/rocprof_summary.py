@@ -1,0 +1,132 @@
+"""Text summaries of rocprofv3 results (the SQLite databases rocprofv3 writes)
+for the profiles folder.
+
+    # kernel table of a --kernel-trace --stats run
+    python -m paper_0711_2665_amd.rocprof_summary trace --db DB --out profiles/X.md \
+        --command "the rocprofv3 command" [--kernel k_lb --last 200]
+
+    # HBM bytes of the sweep from one FETCH_SIZE run and one WRITE_SIZE run
+    python -m paper_0711_2665_amd.rocprof_summary counters --fetch-db DB1 --write-db DB2 \
+        --meta META.json --kernel k_lb --out profiles/lb_sweep_fp32dev_c3 --command "..."
+
+The counters are calibrated against a plain device-to-device copy of known
+size run in the same process after the sweeps: factor = copied bytes /
+counter bytes, for reads and writes separately.
+"""
+import argparse
+import json
+import re
+import sqlite3
+
+
+def short(name):
+    """Kernel name without argument list and return type."""
+    n = re.sub(r"\(.*$", "", name)
+    n = re.sub(r"^void ", "", n)
+    return n
+
+
+def kernel_rows(db):
+    c = sqlite3.connect(db)
+    return c.execute("select name, start, end, duration, grid_x, workgroup_x from kernels order by start").fetchall()
+
+
+def trace(a):
+    rows = kernel_rows(a.db)
+    agg = {}
+    for name, st, en, dur, gx, wx in rows:
+        k = short(name)
+        e = agg.setdefault(k, [0, 0.0, float("inf"), 0.0])
+        e[0] += 1
+        e[1] += dur
+        e[2] = min(e[2], dur)
+        e[3] = max(e[3], dur)
+    total = sum(e[1] for e in agg.values())
+    lines = [f"# rocprofv3 kernel trace: {a.title}", "", "Command (from the repository root):", "",
+             "```", a.command, "```", "",
+             f"Summary: `python -m paper_0711_2665_amd.rocprof_summary trace --db <results.db> ...`", "",
+             "| kernel | calls | avg us | min us | max us | total ms | % of GPU time |",
+             "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, e in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{k}` | {e[0]} | {e[1] / e[0] / 1e3:.2f} | {e[2] / 1e3:.2f} | {e[3] / 1e3:.2f} | "
+                     f"{e[1] / 1e6:.3f} | {100 * e[1] / total:.2f} |")
+    if a.kernel:
+        sel = [r for r in rows if a.kernel in short(r[0])]
+        if a.last:
+            sel = sel[-a.last:]
+        d = [r[3] for r in sel]
+        if d:
+            lines += ["", f"Last {len(d)} dispatches of `{a.kernel}` (the timed region): "
+                      f"mean {sum(d) / len(d) / 1e3:.2f} us, min {min(d) / 1e3:.2f} us, max {max(d) / 1e3:.2f} us, "
+                      f"grid {sel[-1][4]} x workgroup {sel[-1][5]}."]
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counter_rows(db, counter):
+    c = sqlite3.connect(db)
+    return c.execute("select name, start, counter_value from pmc_events where counter_name=? order by start",
+                     (counter,)).fetchall()
+
+
+def counters(a):
+    meta = json.load(open(a.meta))
+    res = {}
+    for counter, db in (("FETCH_SIZE", a.fetch_db), ("WRITE_SIZE", a.write_db)):
+        rows = counter_rows(db, counter)
+        sweep = [(st, v) for n, st, v in rows if a.kernel in short(n)]
+        last = sweep[-1][0]
+        copy = [v for n, st, v in rows if "copyBuffer" in n and st > last]
+        sweep = sweep[-meta["sweeps"]:]
+        kib = sum(v for _, v in sweep) / len(sweep)
+        copy_kib = sum(copy)
+        factor = meta["copy_bytes"] / (copy_kib * 1024.0)
+        res[counter] = dict(kib_per_launch=kib, copy_kib=copy_kib, copy_dispatches=len(copy), factor=factor,
+                            bytes_per_launch=kib * 1024.0 * factor, launches=len(sweep))
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    alg = meta["algorithmic_bytes_per_launch"]
+    out = dict(meta, counters=res, bytes_per_launch=total, traffic_over_algorithmic=total / alg,
+               command=a.command)
+    with open(a.out + "_counters.json", "w") as fh:
+        json.dump(out, fh, indent=1)
+    f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
+    lines = [f"# HBM traffic of the LB sweep: {meta['workload']} {meta['precision']}", "",
+             "Commands (from the repository root):", "", "```", a.command, "```", "",
+             f"Lattice {meta['shape']} ({meta['nodes']} nodes, {meta['nfluid']} fluid), sweep layout "
+             f"{meta['sweep_layout']}, kernel source hash `{meta['kernel_source_hash']}`.", "",
+             "| counter | KiB per launch (raw) | copy calibration (bytes / counter bytes) | bytes per launch |",
+             "|---|---:|---:|---:|",
+             f"| FETCH_SIZE | {f['kib_per_launch']:.1f} | {f['factor']:.4f} ({f['copy_dispatches']} copy dispatches, "
+             f"{meta['copy_bytes']} B) | {f['bytes_per_launch']:.4e} |",
+             f"| WRITE_SIZE | {w['kib_per_launch']:.1f} | {w['factor']:.4f} | {w['bytes_per_launch']:.4e} |", "",
+             f"Measured HBM bytes per launch: {total:.4e}; algorithmic: {alg:.4e} "
+             f"(ratio {total / alg:.4f})."]
+    with open(a.out + "_counters.md", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--db", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--title", default="")
+    t.add_argument("--kernel", default="")
+    t.add_argument("--last", type=int, default=0)
+    c = sub.add_parser("counters")
+    c.add_argument("--fetch-db", required=True)
+    c.add_argument("--write-db", required=True)
+    c.add_argument("--meta", required=True)
+    c.add_argument("--kernel", default="k_lb<")
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
+    a = ap.parse_args()
+    trace(a) if a.mode == "trace" else counters(a)
+
+
+if __name__ == "__main__":
+    main()
