@@ -210,6 +210,45 @@ int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid);
  * ms to *out_ms (-1 when taken from the cache).  Synchronises the stream. */
 int lb_autotune(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
 
+/* Sets the friction rate gamma (>= 0) and the pore force F_drive of
+ * replica rep and recomputes its SPV coefficients (e = exp(-gamma h), the
+ * noise amplitude from the replica's kT).  Synchronises the stream. */
+int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
+
+/*
+ * Adjoint of nsteps coupled steps (reverse-mode derivative; the method's
+ * gradient form).  For a loss L that depends on the bead positions (and
+ * optionally velocities) after the steps, it returns dL/dgamma, dL/dF_drive
+ * and dL/dr at the start, the derivative of the discrete step map itself
+ * (fixed noise sequence: the Philox counters do not depend on the
+ * parameters).  Each step is reversed stage by stage -- LB sweep (the
+ * transposed BGK Jacobian and streaming), spreading, the MD sub-cycle
+ * (sub-steps in reverse; force Jacobians as directional derivatives of the
+ * conservative forces), gathering -- using the populations and bead state of
+ * that step, recomputed segment by segment from checkpoints taken every K
+ * steps of the forward pass.
+ * Supported: one-replica contexts with 1 <= nb <= 256 and gamma > 0
+ * (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either precision.
+ *
+ * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1
+ *   checkpoints of lb_sizes.state_bytes, K population arrays of tape, the
+ *   adjoint fields.  Host only.
+ * lb_adjoint_forward: runs nsteps coupled steps from the current state (as
+ *   md_couple_step does) and records the checkpoints in ws (device, at
+ *   least the size above, 256-byte aligned, owned by the caller, kept until
+ *   the backward call).
+ * lb_adjoint_backward: dLdr_dev (and dLdv_dev, may be NULL for zero): [nb][3]
+ *   doubles on the device, the loss gradient at the final state.  Writes
+ *   grads_dev[0] = dL/dgamma, [1] = dL/dF_drive, [2 ..] = dL/dr_start
+ *   ([nb][3]).  Leaves the context in the final state of the forward pass.
+ * lb_adjoint_run: forward then backward with dLdv = 0.
+ */
+int lb_adjoint_sizes(lb_ctx* ctx, int nsteps, int K, size_t* bytes);
+int lb_adjoint_forward(lb_ctx* ctx, int nsteps, int K, void* ws_dev, size_t ws_bytes);
+int lb_adjoint_backward(lb_ctx* ctx, const double* dLdr_dev, const double* dLdv_dev, double* grads_dev);
+int lb_adjoint_run(lb_ctx* ctx, int nsteps, int K, void* ws_dev, size_t ws_bytes, const double* dLdr_dev,
+                   double* grads_dev);
+
 /* Pre-relaxation of the chain (Sec. 4: the initial walk is relaxed by MD):
  * nsub_total SPV sub-steps with no fluid coupling, no field, no noise and
  * friction gamma_relax; the velocities are zeroed at the end. */

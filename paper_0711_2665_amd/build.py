@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmd.so")
-SOURCES = ["lbmd_api.hip", "lb_kernels.hip", "md_kernels.hip"]
-HEADERS = ["lbmd_dev.h", "lbmd_kernels.h"]
+SOURCES = ["lbmd_api.hip", "lb_kernels.hip", "md_kernels.hip", "adj_kernels.hip"]
+HEADERS = ["lbmd_dev.h", "lbmd_kernels.h", "lbmd_lattice.h"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -46,7 +46,7 @@ def kernel_source_hash():
     """Short hash of the sources that define the lattice sweep; a counter
     summary taken on other sources no longer describes the kernel."""
     h = hashlib.sha256()
-    for f in ("lb_kernels.hip", "lbmd_dev.h", "lbmd_kernels.h"):
+    for f in ("lb_kernels.hip", "lbmd_dev.h", "lbmd_kernels.h", "lbmd_lattice.h"):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -3,6 +3,7 @@
 // deterministic spreading of the bead reaction onto the lattice, and the
 // fluid reductions.  All kernels serve every replica of a context.
 #include "lbmd_kernels.h"
+#include "lbmd_lattice.h"
 
 namespace lbmd {
 
@@ -25,179 +26,6 @@ __global__ void k_fill_i32(int* __restrict__ p, long n, int v) {
 __global__ void k_fill_f64(double* __restrict__ p, long n, double v) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) p[k] = v;
-}
-
-// ---------------------------------------------------------------------------
-// Neighbour offsets of node c = (x, y, z) with periodic wrap.
-// ---------------------------------------------------------------------------
-struct Nbr {
-  int xm, xp, ym, yp, zm, zp;   // index offsets to x-1, x+1, y-1, ...
-  __device__ inline int off(int dx, int dy, int dz) const {
-    return (dx < 0 ? xm : (dx > 0 ? xp : 0)) + (dy < 0 ? ym : (dy > 0 ? yp : 0)) + (dz < 0 ? zm : (dz > 0 ? zp : 0));
-  }
-};
-__device__ inline Nbr make_nbr(const LbParams& p, int x, int y, int z) {
-  Nbr n;
-  n.xm = (x > 0) ? -1 : p.nx - 1;
-  n.xp = (x < p.nx - 1) ? 1 : -(p.nx - 1);
-  n.ym = (y > 0) ? -p.nx : p.nx * (p.ny - 1);
-  n.yp = (y < p.ny - 1) ? p.nx : -p.nx * (p.ny - 1);
-  n.zm = (z > 0) ? -p.nxy : p.nxy * (p.nz - 1);
-  n.zp = (z < p.nz - 1) ? p.nxy : -p.nxy * (p.nz - 1);
-  return n;
-}
-
-// Population store of the sweep: written once per step and read only in the
-// next step, so it bypasses the caches (non-temporal).
-template <typename T>
-__device__ inline void store_pop(T* ptr, T v) {
-  __builtin_nontemporal_store(v, ptr);
-}
-
-// Post-streaming populations at node c: f_i(x) = A_i(x - c_i), or
-// A_opp(i)(x) when x - c_i is solid (halfway bounce-back).  Nodes away from
-// walls take a straight run of 19 independent loads; next to a wall the 19
-// upstream flags are loaded first and the addresses selected without
-// branches, so the population loads are again issued together.
-template <typename T>
-__device__ inline void pull(const T* __restrict__ A, const uint8_t* __restrict__ flags, const LbParams& p, int c,
-                            uint8_t fl, const Nbr& nb, T f[Q]) {
-  const size_t N = (size_t)p.N;
-  if (!(fl & F_NEAR)) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = A[(size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)))];
-  } else {
-    uint8_t sf[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) sf[i] = flags[c + nb.off(-cx(i), -cy(i), -cz(i))];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      size_t src = (size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)));
-      size_t ref = (size_t)opp(i) * N + (size_t)c;
-      f[i] = A[(sf[i] & F_SOLID) ? ref : src];
-    }
-  }
-}
-
-// FP64 moments in the order of the definition: rho = sum_i f_i,
-// j_a = sum_i f_i c_ia (terms with c_ia = 0 add exact zeros and are omitted).
-__device__ inline void moments64(const double f[Q], double& rho, double& ux, double& uy, double& uz) {
-  rho = 0.0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) rho += f[i];
-  double jx = f[1] - f[2] + f[7] - f[8] + f[9] - f[10] + f[11] - f[12] + f[13] - f[14];
-  double jy = f[3] - f[4] + f[7] - f[8] - f[9] + f[10] + f[15] - f[16] + f[17] - f[18];
-  double jz = f[5] - f[6] + f[11] - f[12] - f[13] + f[14] + f[15] - f[16] - f[17] + f[18];
-  ux = jx / rho; uy = jy / rho; uz = jz / rho;
-}
-
-// c_i . v with the zero components omitted, in x, y, z order.
-template <typename R>
-__device__ inline R cdot(int i, R vx, R vy, R vz) {
-  switch (i) {
-    case 0: return (R)0;
-    case 1: return vx;
-    case 2: return -vx;
-    case 3: return vy;
-    case 4: return -vy;
-    case 5: return vz;
-    case 6: return -vz;
-    case 7: return vx + vy;
-    case 8: return -vx - vy;
-    case 9: return vx - vy;
-    case 10: return -vx + vy;
-    case 11: return vx + vz;
-    case 12: return -vx - vz;
-    case 13: return vx - vz;
-    case 14: return -vx + vz;
-    case 15: return vy + vz;
-    case 16: return -vy - vz;
-    case 17: return vy - vz;
-    default: return -vy + vz;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// BGK collision with the source term (Sec. 2, Eq. (lbe2) read as a relaxation
-// with S_i = 3 w_i F.c_i) of one fluid node (index c, flags fl) from its
-// post-streaming populations f; writes f* to out (may alias f).
-// ---------------------------------------------------------------------------
-template <typename T, bool DEV>
-__device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict__ force, const LbParams& p,
-                                    Ctrl* __restrict__ ctrl, int c, uint8_t fl) {
-  const size_t N = (size_t)p.N;
-  if constexpr (!DEV) {
-    // FP64: f* = f - omega (f - f^eq) + 3 w_i (F + g).c_i, f^eq =
-    // w_i rho (1 + 3 cu + 4.5 cu^2 - 1.5 u.u)
-    double rho, ux, uy, uz;
-    moments64(f, rho, ux, uy, uz);
-    if (!(rho > 0.0)) atomicOr(&ctrl->err, E_DENSITY);
-    double usq = ux * ux + uy * uy + uz * uz;
-    double Fx = p.g[0], Fy = p.g[1], Fz = p.g[2];
-    if (fl & F_FORCED) {
-      Fx = (double)force[c] + p.g[0];
-      Fy = (double)force[N + c] + p.g[1];
-      Fz = (double)force[2 * N + c] + p.g[2];
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      double cu = cdot<double>(i, ux, uy, uz);
-      double fe = wgt(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-      double src = (3.0 * wgt(i)) * cdot<double>(i, Fx, Fy, Fz);
-      out[i] = (T)(f[i] - p.omega * (f[i] - fe) + src);
-    }
-  } else {
-    // FP32 deviation storage: g_i = f_i - w_i; drho = sum g, j = sum g c;
-    // g^eq = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u)).
-    float drho = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) drho += (float)f[i];
-    float jx = (float)(f[1] - f[2] + f[7] - f[8] + f[9] - f[10] + f[11] - f[12] + f[13] - f[14]);
-    float jy = (float)(f[3] - f[4] + f[7] - f[8] - f[9] + f[10] + f[15] - f[16] + f[17] - f[18]);
-    float jz = (float)(f[5] - f[6] + f[11] - f[12] - f[13] + f[14] + f[15] - f[16] - f[17] + f[18]);
-    float rho = 1.f + drho;
-    if (!(rho > 0.f)) atomicOr(&ctrl->err, E_DENSITY);
-    float ir = 1.f / rho;
-    float ux = jx * ir, uy = jy * ir, uz = jz * ir;
-    float usq = ux * ux + uy * uy + uz * uz;
-    float om = (float)p.omega;
-    bool forced = (fl & F_FORCED) != 0;
-    float Fx = (float)p.g[0], Fy = (float)p.g[1], Fz = (float)p.g[2];
-    if (forced) {
-      Fx += (float)force[c];
-      Fy += (float)force[N + c];
-      Fz += (float)force[2 * N + c];
-    }
-    bool src_on = forced || p.has_g;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      float cu = cdot<float>(i, ux, uy, uz);
-      float w = (float)wgt(i);
-      float ge = w * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * usq));
-      float o = (float)f[i] - om * ((float)f[i] - ge);
-      if (src_on) o += (3.f * w) * cdot<float>(i, Fx, Fy, Fz);
-      out[i] = (T)o;
-    }
-  }
-}
-
-// Stream + collide one fluid node c of a replica (pointers already offset to
-// the replica).
-template <typename T, bool DEV>
-__device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
-                               const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl, int c,
-                               uint8_t fl) {
-  int x = c % p.nx;
-  int yz = c / p.nx;
-  int y = yz % p.ny;
-  int z = yz / p.ny;
-  Nbr nb = make_nbr(p, x, y, z);
-  T f[Q];
-  pull<T>(A, flags, p, c, fl, nb, f);
-  collide_node<T, DEV>(f, f, force, p, ctrl, c, fl);
-  const size_t N = (size_t)p.N;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c], f[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -240,37 +68,6 @@ __global__ __launch_bounds__(64) void k_lb_forced(const T* __restrict__ A, T* __
   const uint8_t* fr = d.flags + no;
   lb_node<T, DEV>(A + (size_t)Q * no, B + (size_t)Q * no, fr, (const T*)d.force + (size_t)3 * no, R.lp, d.ctrl, e.y,
                   fr[e.y]);
-}
-
-// ---------------------------------------------------------------------------
-// Fluid velocity at node c from the pulled populations (zero at solid nodes),
-// accumulated in FP64.
-// ---------------------------------------------------------------------------
-template <typename T, bool DEV>
-__device__ inline void node_velocity(const T* __restrict__ A, const uint8_t* __restrict__ flags, const LbParams& p,
-                                     int c, double u[3]) {
-  uint8_t fl = flags[c];
-  if (fl & F_SOLID) { u[0] = u[1] = u[2] = 0.0; return; }
-  int x = c % p.nx, yz = c / p.nx, y = yz % p.ny, z = yz / p.ny;
-  Nbr nb = make_nbr(p, x, y, z);
-  T ft[Q];
-  pull<T>(A, flags, p, c, fl, nb, ft);
-  double f[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = (double)ft[i];
-  if constexpr (!DEV) {
-    double rho;
-    moments64(f, rho, u[0], u[1], u[2]);
-  } else {
-    double drho = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) drho += f[i];
-    double jx = f[1] - f[2] + f[7] - f[8] + f[9] - f[10] + f[11] - f[12] + f[13] - f[14];
-    double jy = f[3] - f[4] + f[7] - f[8] - f[9] + f[10] + f[15] - f[16] + f[17] - f[18];
-    double jz = f[5] - f[6] + f[11] - f[12] - f[13] + f[14] + f[15] - f[16] - f[17] + f[18];
-    double rho = 1.0 + drho;
-    u[0] = jx / rho; u[1] = jy / rho; u[2] = jz / rho;
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <string>
@@ -288,6 +289,10 @@ struct lb_ctx {
   hipGraphExec_t gexec = nullptr;
   int graph_cur = -1;
   bool capturing = false;
+  // adjoint: the forward pass recorded by lb_adjoint_forward
+  int adj_n = 0, adj_K = 0;
+  int64_t adj_step0 = 0;
+  char* adj_ws = nullptr;
   // kernel timing (lb_profile_start / lb_profile_stop)
   std::vector<hipEvent_t> ev;   // 4 per recorded step: bead start/end, LB start/end
   int prof_max = 0;
@@ -348,14 +353,13 @@ void prof_next(lb_ctx* c) {
   if (!c->capturing && c->prof_on && c->prof_n < c->prof_max) ++c->prof_n;
 }
 
-void sweep(lb_ctx* c, int skip_forced, hipStream_t st) {
+void sweep_ab(lb_ctx* c, const void* A, void* B, int skip_forced, hipStream_t st) {
   if (c->dev)
-    launch_lb<float, true>(cur_pops(c), other_pops(c), c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid,
-                           skip_forced, st);
+    launch_lb<float, true>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, skip_forced, st);
   else
-    launch_lb<double, false>(cur_pops(c), other_pops(c), c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid,
-                             skip_forced, st);
+    launch_lb<double, false>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, skip_forced, st);
 }
+void sweep(lb_ctx* c, int skip_forced, hipStream_t st) { sweep_ab(c, cur_pops(c), other_pops(c), skip_forced, st); }
 
 // One fluid-only step on stream st.
 void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
@@ -372,33 +376,36 @@ void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
 // One coupled step on stream st: the stencil nodes of r(n) are marked first;
 // the sweep over all other nodes then runs on the second stream while the
 // beads move; the marked nodes are updated once the bead force is spread.
-void enqueue_coupled_step(lb_ctx* c, hipStream_t st) {
-  if (c->nslots == 0) {
-    enqueue_lb_step(c, st);
-    return;
-  }
+void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) {
   const Dev& D = c->D;
   prof_mark(c, 0, st);
   launch_bead_prep(D, c->nslots, st);
   acc(hipEventRecord(c->fork, st));
   acc(hipStreamWaitEvent(c->s2, c->fork, 0));
   prof_mark(c, 2, c->s2);
-  sweep(c, 1, c->s2);
+  sweep_ab(c, A, B, 1, c->s2);
   prof_mark(c, 3, c->s2);
   acc(hipEventRecord(c->join, c->s2));
-  if (c->dev) launch_gather<float, true>(cur_pops(c), D, c->nslots, st);
-  else launch_gather<double, false>(cur_pops(c), D, c->nslots, st);
+  if (c->dev) launch_gather<float, true>(A, D, c->nslots, st);
+  else launch_gather<double, false>(A, D, c->nslots, st);
   MdOverride none{};
   launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, c->any_noise ? 1 : 0, none, st);
   if (c->dev) launch_spread<float>(D, c->nslots, st);
   else launch_spread<double>(D, c->nslots, st);
-  if (c->dev) launch_lb_forced<float, true>(cur_pops(c), other_pops(c), D, c->maxlist, st);
-  else launch_lb_forced<double, false>(cur_pops(c), other_pops(c), D, c->maxlist, st);
+  if (c->dev) launch_lb_forced<float, true>(A, B, D, c->maxlist, st);
+  else launch_lb_forced<double, false>(A, B, D, c->maxlist, st);
   prof_mark(c, 1, st);
   acc(hipStreamWaitEvent(st, c->join, 0));
   launch_step_end(D, c->nslots, c->maxlist, c->nrep, st);
-  c->cur ^= 1;
   prof_next(c);
+}
+void enqueue_coupled_step(lb_ctx* c, hipStream_t st) {
+  if (c->nslots == 0) {
+    enqueue_lb_step(c, st);
+    return;
+  }
+  enqueue_coupled_step_ab(c, cur_pops(c), other_pops(c), st);
+  c->cur ^= 1;
 }
 
 void drop_graph(lb_ctx* c) {
@@ -443,6 +450,59 @@ int build_graph(lb_ctx* c) {
   c->gexec = x;
   c->graph_cur = cur0;
   return LB_OK;
+}
+
+// Workspace of the adjoint: checkpoints every K steps (and the final state),
+// the per-step tape of one segment, adjoint fields.
+struct AdjLayout {
+  size_t ckpt, tape_pops, tape_beads, lamA, lamB, lamu, lbead, mdtape, par, total;
+  size_t pops_slot, bead_arr, md_arr;
+  int nseg;
+};
+
+AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
+  AdjLayout L;
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  L.nseg = (nsteps + K - 1) / K;
+  L.pops_slot = align256(es * Q * (size_t)c->pk.nodes);
+  L.bead_arr = align256(sizeof(double) * 3 * (size_t)c->pk.slots_alloc);
+  L.md_arr = align256(sizeof(double) * 3 * (size_t)c->d[0].nb * (size_t)c->n_sub);
+  size_t o = 0;
+  L.ckpt = o; o += (size_t)(L.nseg + 1) * c->sl.total;
+  L.tape_pops = o; o += (size_t)K * L.pops_slot;
+  L.tape_beads = o; o += (size_t)K * 4 * L.bead_arr;
+  L.lamA = o; o += L.pops_slot;
+  L.lamB = o; o += L.pops_slot;
+  L.lamu = o; o += align256(es * 3 * (size_t)c->pk.nodes);
+  L.lbead = o; o += 5 * L.bead_arr;
+  L.mdtape = o; o += 2 * L.md_arr;
+  L.par = o; o += 256;
+  L.total = o;
+  return L;
+}
+
+int adj_check(const lb_ctx* c, int nsteps, int K) {
+  if (c->nrep != 1) return fail(LB_ERR_UNSUPPORTED, "the adjoint runs on one-replica contexts");
+  const lb_desc& d = c->d[0];
+  if (d.nb < 1 || d.nb > MAX_ADJ_BEADS)
+    return fail(LB_ERR_UNSUPPORTED, "the adjoint needs 1 <= nb <= %d (got %d)", MAX_ADJ_BEADS, d.nb);
+  if (!(c->reps[0].mp.gamma > 0.0)) return fail(LB_ERR_ARG, "the adjoint needs gamma > 0");
+  if (nsteps < 1 || K < 1) return fail(LB_ERR_ARG, "nsteps and K must be >= 1");
+  if (c->prof_on) return fail(LB_ERR_ARG, "profiling is active");
+  return LB_OK;
+}
+
+// Copies a state buffer (lb_get_state layout) into the context: populations
+// to dst_pops, r, v, step counter, translocation steps.
+void restore_state(lb_ctx* c, const char* st, void* dst_pops) {
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  acc(hipMemcpyAsync(dst_pops, st + c->sl.pops, es * Q * (size_t)c->pk.nodes, hipMemcpyDeviceToDevice, c->s));
+  const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
+  acc(hipMemcpyAsync(c->D.r, st + c->sl.r, nb3, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->D.v, st + c->sl.v, nb3, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(&c->D.ctrl->step, st + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->D.tX, st + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
+  launch_md_invalidate(c->D, c->nrep, c->s);
 }
 
 }  // namespace
@@ -902,6 +962,133 @@ int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
   if (out_cfg) { out_cfg[0] = best.tile_nodes; out_cfg[1] = best.order; out_cfg[2] = best.grid; }
   if (out_ms) *out_ms = best_ms;
   return check_hip("lb_autotune");
+}
+
+int lb_set_coupling(lb_ctx* c, int rep, double gamma, double f_drive) {
+  if (!c || rep < 0 || rep >= c->nrep || !(gamma >= 0.0) || !std::isfinite(gamma) || !std::isfinite(f_drive))
+    return fail(LB_ERR_ARG, "bad arguments");
+  Rep& R = c->reps[rep];
+  R.mp.f_drive = f_drive;
+  spv_coefficients(R.mp, gamma, c->d[rep].kT, 1.0 / (double)c->n_sub);
+  c->d[rep].gamma = gamma;
+  c->d[rep].f_drive = f_drive;
+  bool noise = false;
+  for (const Rep& x : c->reps) noise = noise || (x.mp.nb > 0 && x.mp.sig != 0.0);
+  if (noise != c->any_noise) drop_graph(c);
+  c->any_noise = noise;
+  hipError_t e = hipMemcpyAsync((char*)c->b.work + c->wl.reps + sizeof(Rep) * (size_t)rep, &R, sizeof(Rep),
+                                hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s);   // R is read from host memory
+  if (e != hipSuccess) return fail(LB_ERR_DEVICE, "lb_set_coupling: %s", hipGetErrorString(e));
+  return LB_OK;
+}
+
+int lb_adjoint_sizes(lb_ctx* c, int nsteps, int K, size_t* bytes) {
+  if (!c || !bytes) return fail(LB_ERR_ARG, "bad arguments");
+  int rc = adj_check(c, nsteps, K);
+  if (rc) return rc;
+  *bytes = adj_layout(c, nsteps, K).total;
+  return LB_OK;
+}
+
+int lb_adjoint_forward(lb_ctx* c, int nsteps, int K, void* ws, size_t ws_bytes) {
+  if (!c || !ws) return fail(LB_ERR_ARG, "bad arguments");
+  int rc = adj_check(c, nsteps, K);
+  if (rc) return rc;
+  AdjLayout L = adj_layout(c, nsteps, K);
+  if (ws_bytes < L.total) return fail(LB_ERR_ARG, "workspace too small (%zu < %zu bytes)", ws_bytes, L.total);
+  if (((uintptr_t)ws) & 255) return fail(LB_ERR_ARG, "workspace is not 256-byte aligned");
+  char* w = (char*)ws;
+  c->adj_step0 = c->steps;
+  rc = lb_get_state(c, w + L.ckpt);
+  if (rc) return rc;
+  for (int seg = 0; seg < L.nseg; ++seg) {
+    int len = std::min(K, nsteps - seg * K);
+    for (int k = 0; k < len; ++k) enqueue_coupled_step(c, c->s);
+    c->steps += len;
+    rc = lb_get_state(c, w + L.ckpt + (size_t)(seg + 1) * c->sl.total);
+    if (rc) return rc;
+  }
+  c->adj_n = nsteps;
+  c->adj_K = K;
+  c->adj_ws = w;
+  return check_hip("lb_adjoint_forward");
+}
+
+int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, double* grads) {
+  if (!c || !dLdr || !grads) return fail(LB_ERR_ARG, "bad arguments");
+  if (!c->adj_ws) return fail(LB_ERR_ARG, "no recorded forward pass (call lb_adjoint_forward first)");
+  const int nsteps = c->adj_n, K = c->adj_K;
+  int rc = adj_check(c, nsteps, K);
+  if (rc) return rc;
+  AdjLayout L = adj_layout(c, nsteps, K);
+  char* w = c->adj_ws;
+  const int nb = c->d[0].nb;
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  AdjBufs a;
+  a.lr = (double*)(w + L.lbead);
+  a.lv = (double*)(w + L.lbead + L.bead_arr);
+  a.lJ = (double*)(w + L.lbead + 2 * L.bead_arr);
+  a.lup = (double*)(w + L.lbead + 3 * L.bead_arr);
+  a.lrs = (double*)(w + L.lbead + 4 * L.bead_arr);
+  a.rmid = (double*)(w + L.mdtape);
+  a.vold = (double*)(w + L.mdtape + L.md_arr);
+  a.lamu = w + L.lamu;
+  a.par = (double*)(w + L.par);
+  void* lamB = w + L.lamB;   // adjoint of the populations after the step being reversed
+  void* lamA = w + L.lamA;
+  acc(hipMemsetAsync(lamB, 0, L.pops_slot, c->s));
+  acc(hipMemsetAsync(lamA, 0, L.pops_slot, c->s));
+  acc(hipMemsetAsync(a.lamu, 0, es * 3 * (size_t)c->pk.nodes, c->s));
+  launch_adj_init(dLdr, dLdv, a, nb, c->s);
+  auto tape_pops = [&](int j) { return (void*)(w + L.tape_pops + (size_t)j * L.pops_slot); };
+  auto tape_bead = [&](int j, int which) {
+    return (double*)(w + L.tape_beads + ((size_t)j * 4 + which) * L.bead_arr);
+  };
+  const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
+  const double kT = c->d[0].kT;
+  for (int seg = L.nseg - 1; seg >= 0; --seg) {
+    const int n0 = seg * K;
+    const int len = std::min(K, nsteps - n0);
+    // recompute the segment from its checkpoint, writing the tape
+    restore_state(c, w + L.ckpt + (size_t)seg * c->sl.total, tape_pops(0));
+    for (int j = 0; j < len; ++j) {
+      acc(hipMemcpyAsync(tape_bead(j, 0), c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
+      acc(hipMemcpyAsync(tape_bead(j, 1), c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
+      void* B = j + 1 < len ? tape_pops(j + 1) : other_pops(c);
+      enqueue_coupled_step_ab(c, tape_pops(j), B, c->s);
+      acc(hipMemcpyAsync(tape_bead(j, 2), c->D.up, nb3, hipMemcpyDeviceToDevice, c->s));
+      acc(hipMemcpyAsync(tape_bead(j, 3), c->D.J, nb3, hipMemcpyDeviceToDevice, c->s));
+    }
+    // reverse the segment's steps
+    for (int j = len - 1; j >= 0; --j) {
+      Dev da = c->D;
+      da.r = tape_bead(j, 0);
+      Dev ds = da;
+      ds.J = a.lup;
+      ds.force = a.lamu;
+      const uint32_t step = (uint32_t)(c->adj_step0 + n0 + j);
+      if (c->dev)
+        launch_adj_reverse_step<float, true>(tape_pops(j), lamB, lamA, da, ds, a, tape_bead(j, 0), tape_bead(j, 1),
+                                             tape_bead(j, 2), tape_bead(j, 3), step, kT, c->ntiles,
+                                             c->sweep.tile_nodes, c->nslots, nb, c->s);
+      else
+        launch_adj_reverse_step<double, false>(tape_pops(j), lamB, lamA, da, ds, a, tape_bead(j, 0),
+                                               tape_bead(j, 1), tape_bead(j, 2), tape_bead(j, 3), step, kT,
+                                               c->ntiles, c->sweep.tile_nodes, c->nslots, nb, c->s);
+      std::swap(lamA, lamB);
+    }
+  }
+  // the context returns to the state after the forward pass
+  restore_state(c, w + L.ckpt + (size_t)L.nseg * c->sl.total, cur_pops(c));
+  launch_adj_finish(a, grads, nb, c->s);
+  return check_hip("lb_adjoint_backward");
+}
+
+int lb_adjoint_run(lb_ctx* c, int nsteps, int K, void* ws, size_t ws_bytes, const double* dLdr, double* grads) {
+  int rc = lb_adjoint_forward(c, nsteps, K, ws, ws_bytes);
+  if (rc) return rc;
+  return lb_adjoint_backward(c, dLdr, nullptr, grads);
 }
 
 }  // extern "C"

@@ -110,6 +110,27 @@ void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_
 template <typename T, bool DEV>
 void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s);
 
+// Adjoint pass (one replica, chains of at most MAX_ADJ_BEADS beads).
+constexpr int MAX_ADJ_BEADS = 256;
+struct AdjBufs {
+  double* lr;       // [slots][3] adjoint of r
+  double* lv;       // [slots][3] adjoint of v
+  double* lJ;       // [slots][3] adjoint of the impulse J
+  double* lup;      // [slots][3] adjoint of u_p
+  double* lrs;      // [slots][3] position term of the spreading transpose
+  double* rmid;     // [n_sub][nb][3] recomputed force positions of one step
+  double* vold;     // [n_sub][nb][3] velocities at the start of each sub-step
+  void* lamu;       // [3][N] (storage type) adjoint of the gathered node velocity
+  double* par;      // [4]: dL/dgamma, dL/dF_drive accumulators
+};
+void launch_adj_init(const double* dLdr, const double* dLdv, const AdjBufs& a, int nb, hipStream_t s);
+template <typename T, bool DEV>
+void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const Dev& d, const Dev& dspread,
+                             const AdjBufs& a, const double* rt, const double* vt, const double* upt,
+                             const double* Jt, uint32_t step, double kT, int ntiles, int tile_nodes, int nslots,
+                             int nb, hipStream_t s);
+void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
+
 // MD sub-cycle of all replicas: n_sub launches, one per sub-step.
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
                      hipStream_t s);

@@ -84,6 +84,11 @@ def _declare(L):
     L.lb_sweep_config.argtypes = [P, C.c_int, C.c_int, C.c_int]
     L.lb_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.md_relax.argtypes = [P, C.c_int, C.c_double]
+    L.lb_set_coupling.argtypes = [P, C.c_int, C.c_double, C.c_double]
+    L.lb_adjoint_sizes.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.lb_adjoint_forward.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t]
+    L.lb_adjoint_backward.argtypes = [P, P, P, P]
+    L.lb_adjoint_run.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t, P, P]
     L.lb_observables.argtypes = [P, P]
     L.lb_get_state.argtypes = [P, P]
     L.lb_set_state.argtypes = [P, P]
@@ -243,6 +248,40 @@ class Context:
 
     def check(self):
         _raise(lib().lb_check(self.ctx))
+
+    def set_coupling(self, gamma, f_drive, rep=0):
+        _raise(lib().lb_set_coupling(self.ctx, int(rep), float(gamma), float(f_drive)))
+        self.cfgs[rep]["gamma"] = float(gamma)
+        self.cfgs[rep]["f_drive"] = float(f_drive)
+
+    # -- adjoint -------------------------------------------------------------
+    def adjoint_sizes(self, nsteps, K):
+        n = C.c_size_t()
+        _raise(lib().lb_adjoint_sizes(self.ctx, int(nsteps), int(K), C.byref(n)))
+        return n.value
+
+    def adjoint_forward(self, nsteps, K):
+        """nsteps coupled steps with checkpoints every K steps kept in a
+        workspace tensor for adjoint_backward."""
+        n = self.adjoint_sizes(nsteps, K)
+        self._adj_ws = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        _raise(lib().lb_adjoint_forward(self.ctx, int(nsteps), int(K), C.c_void_p(self._adj_ws.data_ptr()), n))
+
+    def adjoint_backward(self, dLdr, dLdv=None):
+        """Gradient [dL/dgamma, dL/dF_drive, dL/dr_start (nb x 3)] (float64,
+        device) of a loss whose gradient at the final bead state is dLdr
+        (and dLdv)."""
+        torch = self.torch
+        nb = self.nbs[0]
+        gr = torch.as_tensor(dLdr, dtype=torch.float64, device=self.device).reshape(nb, 3).contiguous()
+        gv = None
+        if dLdv is not None:
+            gv = torch.as_tensor(dLdv, dtype=torch.float64, device=self.device).reshape(nb, 3).contiguous()
+        out = torch.empty(2 + 3 * nb, dtype=torch.float64, device=self.device)
+        _raise(lib().lb_adjoint_backward(self.ctx, C.c_void_p(gr.data_ptr()),
+                                         C.c_void_p(gv.data_ptr()) if gv is not None else None,
+                                         C.c_void_p(out.data_ptr())))
+        return out
 
     def sweep_config(self, tile_nodes, order=0, grid=0):
         _raise(lib().lb_sweep_config(self.ctx, int(tile_nodes), int(order), int(grid)))
