@@ -16,8 +16,9 @@ roofline of the dominant kernel (the LB sweep, timed with HIP events inside
 the library on the stream it runs on), the same steps replayed from a
 captured HIP graph, the FP64 path on the same workload, bead throughput, the
 batched ensemble (64 uneven replicas in one context, graph replay, aggregate
-MLUPS and translocation steps), and the FP64 CPU oracle timed on a bounded
-sample.
+MLUPS and translocation steps), the adjoint on the 64^3 gradient workload
+(adjoint steps/s in FP64 and FP32, a finite-difference check), and the FP64
+CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -144,6 +145,74 @@ def run_ensemble(steps, warmup, eager_steps):
     return res
 
 
+def run_adjoint(nsteps, K, horizons):
+    """The gradient workload: 64^3, 100-bead chain, pore 3 x 3, loss = mean
+    normal coordinate after the run, gradient w.r.t. gamma, F_drive and the
+    initial positions by the library's adjoint with checkpoints every K
+    steps.  Timed over nsteps coupled steps in FP64 and FP32 deviation
+    storage.  The bead dynamics is chaotic, so the derivative of the discrete
+    map grows with the horizon and finite differences stop resolving it once
+    trajectories cross interpolation kinks inside the difference interval;
+    the check therefore scans short horizons: central difference of dL/dgamma
+    (h = 1e-6, FP64) against the adjoint, and FP32 against FP64."""
+    import numpy as np
+    import torch
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import C4, initial_chain
+
+    cfg = C4
+    r, v = initial_chain(cfg)
+    out = {"workload": cfg["name"], "steps": nsteps, "checkpoint_every": K}
+    dLdr = np.zeros((cfg["nb"], 3))
+    dLdr[:, cfg["wall_axis"]] = 1.0 / cfg["nb"]
+    sims = {}
+    for name, prec in (("fp64", lbmd.LB_FP64), ("fp32dev", lbmd.LB_FP32_DEV)):
+        sim = lbmd.Simulation(cfg, r, v, precision=prec, device="cuda:0")
+        sim.relax(cfg["relax_substeps"], cfg["gamma_relax"])
+        st = sim.get_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.adjoint_forward(nsteps, K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = sim.adjoint_backward(dLdr).cpu().numpy()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sim.check()
+        out[name] = {"adjoint_steps_per_s": round(nsteps / (t2 - t0), 2), "forward_s": round(t1 - t0, 3),
+                     "reverse_s": round(t2 - t1, 3), "dL_dgamma": float(g[0]), "dL_dF_drive": float(g[1])}
+        sims[name] = (sim, st)
+
+    def grad(name, T):
+        sim, st = sims[name]
+        sim.set_state(st)
+        sim.set_coupling(cfg["gamma"], cfg["f_drive"])
+        sim.adjoint_forward(T, K)
+        return sim.adjoint_backward(dLdr).cpu().numpy()
+
+    def loss(T, gamma):
+        sim, st = sims["fp64"]
+        sim.set_state(st)
+        sim.set_coupling(gamma, cfg["f_drive"])
+        sim.couple_step(T)
+        return float(sim.beads()["r"][:, cfg["wall_axis"]].mean())
+
+    h = 1e-6
+    scan = []
+    for T in horizons:
+        g64 = grad("fp64", T)
+        g32 = grad("fp32dev", T)
+        fd = (loss(T, cfg["gamma"] + h) - loss(T, cfg["gamma"] - h)) / (2 * h)
+        scan.append({"steps": T, "dL_dgamma_adjoint": float(g64[0]), "dL_dgamma_fd": fd,
+                     "fd_rel_diff": abs(float(g64[0]) - fd) / max(abs(fd), 1e-300),
+                     "fp32dev_rel_diff": abs(float(g32[0] - g64[0])) / max(abs(float(g64[0])), 1e-300)})
+    out["horizon_scan"] = scan
+    for name in list(sims):
+        del sims[name]
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_cpu_baseline(cfg, steps):
     """The FP64 oracle as it stands, on a bounded sample of the same workload:
     `steps` coupled steps of the full lattice and chain (the chain given a
@@ -173,6 +242,8 @@ def main():
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=5000)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -233,6 +304,8 @@ def main():
                        "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
     if not args.no_ensemble and args.workload == "c3":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 20, 200)
+    if not args.no_adjoint and args.workload == "c3":
+        out["adjoint"] = run_adjoint(args.adjoint_steps, 100, (5, 20, 50, 100))
     if not args.no_cpu:
         cb = run_cpu_baseline(cfg, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "MLUPS", "cores": cb["cores"],

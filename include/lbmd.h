@@ -227,7 +227,7 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * conservative forces), gathering -- using the populations and bead state of
  * that step, recomputed segment by segment from checkpoints taken every K
  * steps of the forward pass.
- * Supported: one-replica contexts with 1 <= nb <= 256 and gamma > 0
+ * Supported: one-replica contexts with 1 <= nb <= 128 and gamma > 0
  * (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either precision.
  *
  * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1

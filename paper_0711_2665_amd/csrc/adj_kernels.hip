@@ -92,34 +92,43 @@ __device__ inline void lj_dd(const MdParams& P, Dd d0, Dd d1, Dd d2, Dd F[3]) {
   F[0] = F[0] + coef * d0; F[1] = F[1] + coef * d1; F[2] = F[2] + coef * d2;
 }
 
-// Minimum image: the shift is a multiple of the period, decided on the value.
-__device__ inline Dd min_image_dd(Dd d, int n) {
-  double dn = (double)n;
-  double k = floor(d.v / dn + 0.5);
-  return Dd{d.v - dn * k, d.d};
-}
-
-// Wall sites within r_c of the bead: every solid site of the 4 x 4 x 4
-// window around the base node (r_c < 2), value-tested on the wrapped
-// position; the derivative of the wrapped position is that of r.
+// Wall sites within r_c of the bead (r_c < 2): the sites of the wall plane
+// in the 4 x 4 window around the base node, minus the pore block; the
+// derivative of the wrapped position is that of r.
 __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, Dd F[3]) {
   if (g.wall_axis < 0) return;
   const double w[3] = {wrapc(rp[0].v, g.nx), wrapc(rp[1].v, g.ny), wrapc(rp[2].v, g.nz)};
   const int b[3] = {(int)floor(w[0]), (int)floor(w[1]), (int)floor(w[2])};
-  for (int oz = -1; oz <= 2; ++oz)
-    for (int oy = -1; oy <= 2; ++oy)
-      for (int ox = -1; ox <= 2; ++ox) {
-        const int sx = b[0] + ox, sy = b[1] + oy, sz = b[2] + oz;
-        if (!site_solid(g, sx, sy, sz)) continue;
-        Dd d0 = Dd{w[0] - (double)sx, rp[0].d}, d1 = Dd{w[1] - (double)sy, rp[1].d}, d2 = Dd{w[2] - (double)sz, rp[2].d};
-        lj_dd(P, d0, d1, d2, F);
-      }
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const int a = g.wall_axis, t0 = g.t0, t1 = g.t1;
+  int off = g.wall_pos - b[a];               // offset along the normal reaching the plane
+  if (off < -1) off += n[a];
+  if (off > 2) off -= n[a];
+  if (off < -1 || off > 2) return;
+  int site[3];
+  site[a] = b[a] + off;
+  for (int o1 = -1; o1 <= 2; ++o1) {
+    const int u1 = b[t1] + o1;
+    const int v1 = u1 < 0 ? u1 + n[t1] : (u1 >= n[t1] ? u1 - n[t1] : u1);
+    const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
+    for (int o0 = -1; o0 <= 2; ++o0) {
+      const int u0 = b[t0] + o0;
+      const int v0 = u0 < 0 ? u0 + n[t0] : (u0 >= n[t0] ? u0 - n[t0] : u0);
+      const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
+      if (in0 && in1) continue;              // pore node: fluid
+      site[t0] = u0;
+      site[t1] = u1;
+      const double e0 = w[0] - (double)site[0], e1 = w[1] - (double)site[1], e2 = w[2] - (double)site[2];
+      if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+      lj_dd(P, Dd{e0, rp[0].d}, Dd{e1, rp[1].d}, Dd{e2, rp[2].d}, F);
+    }
+  }
 }
 
 // Bending forces of the angle centred at q (1 <= q <= nb - 2) at positions
 // pos with direction dir, value and derivative, into LDS rows av[q], ad[q]:
 // [0..2] force on q-1, [3..5] on q, [6..8] on q+1.
-__device__ __noinline__ void angle_to_lds(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int q,
+__device__ inline void angle_to_lds(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int q,
                                     double (*av)[9], double (*ad)[9]) {
   Dd ra[3], rb[3], rc[3];
   for (int a = 0; a < 3; ++a) {
@@ -135,39 +144,59 @@ __device__ __noinline__ void angle_to_lds(const MdParams& P, const double (*pos)
 }
 
 // Conservative force on chain bead p at positions pos with direction dir
-// (nb x 3, LDS), value F and directional derivative dF: bonds, the angle
-// forces from LDS (angles centred at p-1, p, p+1), LJ with every other bead
-// within r_c, wall sites.  The field is added by the caller (constant in r).
-__device__ __noinline__ void bead_force_dd(const MdParams& P, const Geom& g, const double (*pos)[3],
+// (nb x 3, LDS), value and directional derivative, computed by the 4 lanes
+// of the bead: lane l scans the pair partners j = l, l + 4, ... within r_c
+// (distance screen in plain doubles, dual arithmetic only inside r_c); lane
+// 0 adds the bonds, the angle forces from LDS (angles centred at p-1, p,
+// p+1) and the wall sites.  The four partial sums are combined in a fixed
+// order with cross-lane reads, so every lane of the bead ends with F, dF.
+// The field is added by the caller (constant in r).
+__device__ inline void bead_force_dd(const MdParams& P, const Geom& g, const double (*pos)[3],
                                      const double (*dir)[3], const double (*av)[9], const double (*ad)[9], int p,
-                                     double F[3], double dF[3]) {
+                                     int lane, bool on, double F[3], double dF[3]) {
   const int nb = P.nb;
   Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  Dd rp[3] = {Dd{pos[p][0], dir[p][0]}, Dd{pos[p][1], dir[p][1]}, Dd{pos[p][2], dir[p][2]}};
-  if (p > 0) {
-    Dd rq[3] = {Dd{pos[p - 1][0], dir[p - 1][0]}, Dd{pos[p - 1][1], dir[p - 1][1]}, Dd{pos[p - 1][2], dir[p - 1][2]}};
-    bond_dd(P, rp, rq, S);
+  if (on) {
+    for (int j = lane; j < nb; j += 4) {
+      if (j == p) continue;
+      const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
+      const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
+      const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
+      if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+      lj_dd(P, Dd{e0, dir[p][0] - dir[j][0]}, Dd{e1, dir[p][1] - dir[j][1]}, Dd{e2, dir[p][2] - dir[j][2]}, S);
+    }
+    if (lane == 0) {
+      Dd rp[3] = {Dd{pos[p][0], dir[p][0]}, Dd{pos[p][1], dir[p][1]}, Dd{pos[p][2], dir[p][2]}};
+      if (p > 0) {
+        Dd rq[3] = {Dd{pos[p - 1][0], dir[p - 1][0]}, Dd{pos[p - 1][1], dir[p - 1][1]},
+                    Dd{pos[p - 1][2], dir[p - 1][2]}};
+        bond_dd(P, rp, rq, S);
+      }
+      if (p < nb - 1) {
+        Dd rq[3] = {Dd{pos[p + 1][0], dir[p + 1][0]}, Dd{pos[p + 1][1], dir[p + 1][1]},
+                    Dd{pos[p + 1][2], dir[p + 1][2]}};
+        bond_dd(P, rp, rq, S);
+      }
+      if (p - 1 >= 1 && p - 1 <= nb - 2)
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p - 1][6 + a], ad[p - 1][6 + a]};
+      if (p >= 1 && p <= nb - 2)
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p][3 + a], ad[p][3 + a]};
+      if (p + 1 >= 1 && p + 1 <= nb - 2)
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p + 1][a], ad[p + 1][a]};
+      wall_dd(P, g, rp, S);
+    }
   }
-  if (p < nb - 1) {
-    Dd rq[3] = {Dd{pos[p + 1][0], dir[p + 1][0]}, Dd{pos[p + 1][1], dir[p + 1][1]}, Dd{pos[p + 1][2], dir[p + 1][2]}};
-    bond_dd(P, rp, rq, S);
+  // (lane0 + lane1) + (lane2 + lane3), the same on every lane of the bead
+  const int base = (int)(threadIdx.x & 63u) & ~3;
+  for (int a = 0; a < 3; ++a) {
+    double v[4], d[4];
+    for (int l = 0; l < 4; ++l) {
+      v[l] = __shfl(S[a].v, base + l, 64);
+      d[l] = __shfl(S[a].d, base + l, 64);
+    }
+    F[a] = (v[0] + v[1]) + (v[2] + v[3]);
+    dF[a] = (d[0] + d[1]) + (d[2] + d[3]);
   }
-  // angle centred at p-1 acts on its q+1 (= p), at p on q, at p+1 on q-1
-  if (p - 1 >= 1 && p - 1 <= nb - 2)
-    for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p - 1][6 + a], ad[p - 1][6 + a]};
-  if (p >= 1 && p <= nb - 2)
-    for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p][3 + a], ad[p][3 + a]};
-  if (p + 1 >= 1 && p + 1 <= nb - 2)
-    for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p + 1][a], ad[p + 1][a]};
-  for (int j = 0; j < nb; ++j) {
-    if (j == p) continue;
-    Dd d0 = min_image_dd(Dd{pos[p][0] - pos[j][0], dir[p][0] - dir[j][0]}, g.nx);
-    Dd d1 = min_image_dd(Dd{pos[p][1] - pos[j][1], dir[p][1] - dir[j][1]}, g.ny);
-    Dd d2 = min_image_dd(Dd{pos[p][2] - pos[j][2], dir[p][2] - dir[j][2]}, g.nz);
-    lj_dd(P, d0, d1, d2, S);
-  }
-  wall_dd(P, g, rp, S);
-  for (int a = 0; a < 3; ++a) { F[a] = S[a].v; dF[a] = S[a].d; }
 }
 
 // ---------------------------------------------------------------------------
@@ -240,16 +269,18 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 // u_p.  The parameter adjoints are added to par[0] (gamma) and par[1]
 // (F_drive).
 // ---------------------------------------------------------------------------
-constexpr int ADJ_WG = MAX_ADJ_BEADS;
+constexpr int ADJ_LANES = 4;
+constexpr int ADJ_WG = ADJ_LANES * MAX_ADJ_BEADS;
 
 // Forces on every bead at the positions in pos with direction dir: angles
-// into LDS first, then the per-bead sums.
+// into LDS first (one thread per angle), then the per-bead sums.
 __device__ inline void chain_forces(const MdParams& P, const Geom& g, const double (*pos)[3], const double (*dir)[3],
-                                    double (*av)[9], double (*ad)[9], int p, double F[3], double dF[3]) {
+                                    double (*av)[9], double (*ad)[9], int p, int lane, bool on, double F[3],
+                                    double dF[3]) {
   const int nb = P.nb;
-  if (p >= 1 && p <= nb - 2) angle_to_lds(P, pos, dir, p, av, ad);
+  if (lane == 0 && p >= 1 && p <= nb - 2) angle_to_lds(P, pos, dir, p, av, ad);
   __syncthreads();
-  if (p < nb) bead_force_dd(P, g, pos, dir, av, ad, p, F, dF);
+  bead_force_dd(P, g, pos, dir, av, ad, p, lane, on, F, dF);
 }
 
 __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const double* __restrict__ rt,
@@ -264,38 +295,41 @@ __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const doubl
   double(*dir)[3] = (double(*)[3])(lds + 3 * nb);
   double(*av)[9] = (double(*)[9])(lds + 6 * nb);
   double(*ad)[9] = (double(*)[9])(lds + 15 * nb);
-  double* red = lds + 24 * nb;            // 2 ADJ_WG reduction scratch
-  const int p = threadIdx.x;
+  double* red = lds + 24 * nb;            // 2 x (ADJ_WG / ADJ_LANES) reduction scratch
+  const int p = threadIdx.x / ADJ_LANES, lane = threadIdx.x % ADJ_LANES;
   const bool on = p < nb;
+  const bool lead = on && lane == 0;
   double r[3], v[3], u[3];
   for (int c = 0; c < 3; ++c) {
     r[c] = on ? rt[3 * p + c] : 0.0;
     v[c] = on ? vt[3 * p + c] : 0.0;
     u[c] = on ? upt[3 * p + c] : 0.0;
   }
-  // ---- forward recompute
+  // ---- forward recompute (every lane of a bead carries its state)
   for (int s = 0; s < n_sub; ++s) {
     if (on) {
       for (int c = 0; c < 3; ++c) {
         const double x = r[c] + P.hh * v[c];
-        pos[p][c] = x;
-        dir[p][c] = 0.0;
-        a.rmid[((size_t)s * nb + p) * 3 + c] = x;
-        a.vold[((size_t)s * nb + p) * 3 + c] = v[c];
+        if (lane == 0) {
+          pos[p][c] = x;
+          dir[p][c] = 0.0;
+          a.rmid[((size_t)s * nb + p) * 3 + c] = x;
+          a.vold[((size_t)s * nb + p) * 3 + c] = v[c];
+        }
+        r[c] = x;
       }
     }
     __syncthreads();
     double f[3], df[3];
-    chain_forces(P, g, pos, dir, av, ad, p, f, df);
+    chain_forces(P, g, pos, dir, av, ad, p, lane, on, f, df);
     if (on) {
-      const double rp[3] = {pos[p][0], pos[p][1], pos[p][2]};
-      if (P.field_on && in_field(g, rp)) f[g.wall_axis] += P.f_drive;
+      if (P.field_on && in_field(g, r)) f[g.wall_axis] += P.f_drive;
       double xi[3] = {0.0, 0.0, 0.0};
       if (P.sig != 0.0) gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, xi);
       for (int c = 0; c < 3; ++c) {
         const double vn = P.e * v[c] + P.cf * (f[c] + P.gamma * u[c]) + P.sig * xi[c];
         v[c] = vn;
-        r[c] = rp[c] + P.hh * vn;
+        r[c] = r[c] + P.hh * vn;
       }
     }
     __syncthreads();
@@ -315,55 +349,57 @@ __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const doubl
   }
   double acc_g = 0.0, acc_f = 0.0;
   for (int s = n_sub - 1; s >= 0; --s) {
-    double lvt[3];
-    for (int c = 0; c < 3; ++c) lvt[c] = lv[c] + P.hh * lr[c];
-    if (on) {
-      for (int c = 0; c < 3; ++c) {
-        pos[p][c] = a.rmid[((size_t)s * nb + p) * 3 + c];
-        dir[p][c] = P.cf * lvt[c];
-      }
+    double lvt[3], rm[3];
+    for (int c = 0; c < 3; ++c) {
+      lvt[c] = lv[c] + P.hh * lr[c];
+      rm[c] = on ? a.rmid[((size_t)s * nb + p) * 3 + c] : 0.0;
     }
+    if (lead)
+      for (int c = 0; c < 3; ++c) { pos[p][c] = rm[c]; dir[p][c] = P.cf * lvt[c]; }
     __syncthreads();
     double f[3], df[3];
-    chain_forces(P, g, pos, dir, av, ad, p, f, df);
+    chain_forces(P, g, pos, dir, av, ad, p, lane, on, f, df);
     if (on) {
-      const double rp[3] = {pos[p][0], pos[p][1], pos[p][2]};
-      if (P.field_on && in_field(g, rp)) {
-        f[g.wall_axis] += P.f_drive;
-        acc_f += dir[p][g.wall_axis];
-      }
+      const bool field = P.field_on && in_field(g, rm);
+      if (field) f[g.wall_axis] += P.f_drive;
       double xi[3] = {0.0, 0.0, 0.0};
-      if (P.sig != 0.0) gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, xi);
+      if (P.sig != 0.0 && lead) gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, xi);
       for (int c = 0; c < 3; ++c) {
         const double vo = a.vold[((size_t)s * nb + p) * 3 + c];
-        acc_g += lvt[c] * (vo * de + (f[c] + gam * u[c]) * dcf + P.cf * u[c] + xi[c] * dsig);
-        acc_g += lJ[c] * (-P.m) * ((u[c] - vo) * domE + xi[c] * dsig);
+        if (lead) {
+          acc_g += lvt[c] * (vo * de + (f[c] + gam * u[c]) * dcf + P.cf * u[c] + xi[c] * dsig);
+          acc_g += lJ[c] * (-P.m) * ((u[c] - vo) * domE + xi[c] * dsig);
+        }
         lu[c] += P.cf * gam * lvt[c] - P.m * P.omE * lJ[c];
         const double lrm = lr[c] + df[c];
         lr[c] = lrm;
         lv[c] = P.e * lvt[c] + P.m * P.omE * lJ[c] + P.hh * lrm;
       }
+      if (lead && field) acc_f += P.cf * lvt[g.wall_axis];
     }
     __syncthreads();
   }
-  if (on) {
+  if (lead) {
     for (int c = 0; c < 3; ++c) {
       a.lr[3 * p + c] = lr[c];
       a.lv[3 * p + c] = lv[c];
       a.lup[3 * p + c] = lu[c];
     }
   }
-  // parameter adjoints: fixed-order tree over the workgroup
-  red[p] = acc_g;
-  red[ADJ_WG + p] = acc_f;
+  // parameter adjoints: fixed-order tree over the beads (lane-0 values)
+  constexpr int NB_ = ADJ_WG / ADJ_LANES;
+  if (lane == 0) {
+    red[p] = acc_g;
+    red[NB_ + p] = acc_f;
+  }
   __syncthreads();
-  for (int w = ADJ_WG / 2; w > 0; w >>= 1) {
-    if (p < w) { red[p] += red[p + w]; red[ADJ_WG + p] += red[ADJ_WG + p + w]; }
+  for (int w = NB_ / 2; w > 0; w >>= 1) {
+    if (lane == 0 && p < w) { red[p] += red[p + w]; red[NB_ + p] += red[NB_ + p + w]; }
     __syncthreads();
   }
-  if (p == 0) {
+  if (threadIdx.x == 0) {
     a.par[0] += red[0];
-    a.par[1] += red[ADJ_WG];
+    a.par[1] += red[NB_];
   }
 }
 
@@ -504,7 +540,7 @@ void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const 
                              int nb, hipStream_t s) {
   launch_bead_prep(d, nslots, s);
   hipLaunchKernelGGL((k_adj_spread_t<T>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)lamB, d, a, Jt, nb);
-  size_t lds = sizeof(double) * (24 * (size_t)nb + 2 * ADJ_WG);
+  size_t lds = sizeof(double) * (24 * (size_t)nb + 2 * (ADJ_WG / ADJ_LANES));
   hipLaunchKernelGGL(k_adj_md, dim3(1), dim3(ADJ_WG), lds, s, d, a, rt, vt, upt, step, kT);
   hipLaunchKernelGGL((k_adj_gather_t<T, DEV>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)A, d, a, nb);
   launch_spread<T>(dspread, nslots, s);

@@ -83,7 +83,8 @@ Packing packing(const lb_desc* d, int nrep) {
 
 struct WorkLayout {
   size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
-      tX, notdone;
+      tX, notdone, chead, cnext;
+  size_t nbuckets;
   size_t total;
 };
 
@@ -112,6 +113,10 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   w.xi = take(sizeof(double) * 3 * ns * (size_t)d[0].n_sub);
   w.tX = take(sizeof(int64_t) * R);
   w.notdone = take(sizeof(uint32_t) * R);
+  w.nbuckets = 64;
+  while (w.nbuckets < 2 * ns) w.nbuckets *= 2;
+  w.chead = take(sizeof(int) * w.nbuckets);
+  w.cnext = take(sizeof(int) * ns);
   w.total = o;
   return w;
 }
@@ -212,7 +217,7 @@ void spv_coefficients(MdParams& P, double gamma, double kT, double h) {
   P.sig = kT > 0.0 ? std::sqrt(var) : 0.0;
 }
 
-MdParams make_md(const lb_desc* d) {
+MdParams make_md(const lb_desc* d, double skin) {
   MdParams P;
   std::memset(&P, 0, sizeof(P));
   P.nb = d->nb;
@@ -225,8 +230,8 @@ MdParams make_md(const lb_desc* d) {
   P.f_drive = d->f_drive;
   P.couple = 1; P.field_on = 1;
   P.seed = d->seed; P.replica = d->replica;
-  P.rlist2 = (d->rc + SKIN) * (d->rc + SKIN);
-  P.halfskin2 = (0.5 * SKIN) * (0.5 * SKIN);
+  P.rlist2 = (d->rc + skin) * (d->rc + skin);
+  P.halfskin2 = (0.5 * skin) * (0.5 * skin);
   spv_coefficients(P, d->gamma, d->kT, h);
   return P;
 }
@@ -275,14 +280,15 @@ struct lb_ctx {
   Dev D;
   int nslots = 0;
   int maxlist = 0;
+  bool step_lists = false;   // neighbour lists built from a cell list at every coupled step
   bool any_noise = false;
   SweepCfg sweep;
   int ntiles = 0;
   int64_t steps = 0;
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
-  hipStream_t s2 = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t s1 = nullptr, s2 = nullptr;
+  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr;
   // graph of two coupled steps, starting at population parity graph_cur
   hipStream_t scap = nullptr;
   hipGraph_t graph = nullptr;
@@ -376,26 +382,35 @@ void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
 // One coupled step on stream st: the stencil nodes of r(n) are marked first;
 // the sweep over all other nodes then runs on the second stream while the
 // beads move; the marked nodes are updated once the bead force is spread.
+// The bead phase runs on the library's bead stream s1 and the sweep over the
+// nodes without bead force on s2, both forked from and joined back to st, so
+// that the overlap does not depend on the kind of stream the caller uses.
 void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) {
   const Dev& D = c->D;
-  prof_mark(c, 0, st);
-  launch_bead_prep(D, c->nslots, st);
+  hipStream_t sb = c->s1;
   acc(hipEventRecord(c->fork, st));
-  acc(hipStreamWaitEvent(c->s2, c->fork, 0));
+  acc(hipStreamWaitEvent(sb, c->fork, 0));
+  prof_mark(c, 0, sb);
+  launch_bead_prep(D, c->nslots, sb);
+  acc(hipEventRecord(c->prep, sb));
+  acc(hipStreamWaitEvent(c->s2, c->prep, 0));
   prof_mark(c, 2, c->s2);
   sweep_ab(c, A, B, 1, c->s2);
   prof_mark(c, 3, c->s2);
   acc(hipEventRecord(c->join, c->s2));
-  if (c->dev) launch_gather<float, true>(A, D, c->nslots, st);
-  else launch_gather<double, false>(A, D, c->nslots, st);
+  if (c->step_lists) launch_nbr_build(D, c->nslots, sb);
+  if (c->dev) launch_gather<float, true>(A, D, c->nslots, sb);
+  else launch_gather<double, false>(A, D, c->nslots, sb);
   MdOverride none{};
-  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, c->any_noise ? 1 : 0, none, st);
-  if (c->dev) launch_spread<float>(D, c->nslots, st);
-  else launch_spread<double>(D, c->nslots, st);
-  if (c->dev) launch_lb_forced<float, true>(A, B, D, c->maxlist, st);
-  else launch_lb_forced<double, false>(A, B, D, c->maxlist, st);
-  prof_mark(c, 1, st);
+  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, c->any_noise ? 1 : 0, none, sb);
+  if (c->dev) launch_spread<float>(D, c->nslots, sb);
+  else launch_spread<double>(D, c->nslots, sb);
+  if (c->dev) launch_lb_forced<float, true>(A, B, D, c->maxlist, sb);
+  else launch_lb_forced<double, false>(A, B, D, c->maxlist, sb);
+  prof_mark(c, 1, sb);
+  acc(hipEventRecord(c->join1, sb));
   acc(hipStreamWaitEvent(st, c->join, 0));
+  acc(hipStreamWaitEvent(st, c->join1, 0));
   launch_step_end(D, c->nslots, c->maxlist, c->nrep, st);
   prof_next(c);
 }
@@ -558,7 +573,11 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     hipError_t e2 = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     hipError_t e3 = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
     hipError_t e4 = hipStreamCreateWithFlags(&c->scap, hipStreamNonBlocking);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    hipError_t e5 = hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking);
+    hipError_t e6 = hipEventCreateWithFlags(&c->prep, hipEventDisableTiming);
+    hipError_t e7 = hipEventCreateWithFlags(&c->join1, hipEventDisableTiming);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
+        e6 != hipSuccess || e7 != hipSuccess) {
       lb_destroy(c);
       return fail(LB_ERR_DEVICE, "stream/event creation failed");
     }
@@ -571,6 +590,8 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   c->sl = state_layout(d, nrep, c->pk);
   c->nslots = c->pk.slots;
   c->maxlist = 8 * c->nslots;
+  for (int r = 0; r < nrep; ++r) c->step_lists = c->step_lists || d[r].nb >= STEP_LISTS_MIN_BEADS;
+  const double skin = c->step_lists ? SKIN_STEP : SKIN;
   const size_t ns = (size_t)c->pk.slots_alloc;
   const long nodes = c->pk.nodes;
 
@@ -588,13 +609,21 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     R.lp.omega = 1.0 / d[r].tau;
     for (int a = 0; a < 3; ++a) R.lp.g[a] = d[r].g[a];
     R.lp.has_g = (d[r].g[0] != 0.0 || d[r].g[1] != 0.0 || d[r].g[2] != 0.0) ? 1 : 0;
-    R.mp = make_md(&d[r]);
+    R.mp = make_md(&d[r], skin);
     if (R.mp.nb > 0 && R.mp.sig != 0.0) c->any_noise = true;
     R.node_off = c->pk.node_off[r];
     R.slot_off = c->pk.slot_off[r];
     R.nslot = (int)round_up(d[r].nb, MD_BPB);
     for (int k = 0; k < R.nslot; ++k) slot_rep[(size_t)R.slot_off + k] = r;
     R.nfluid = (double)build_flags(R.g, fl.data() + R.node_off);
+    {
+      const int n[3] = {d[r].nx, d[r].ny, d[r].nz};
+      const double side = d[r].rc + skin;
+      for (int a = 0; a < 3; ++a) {
+        int k = (int)std::floor((double)n[a] / side);
+        R.ncell[a] = k < 1 ? 1 : k;
+      }
+    }
     R.tile_begin = (int)ot.size();
     for (int st = 0; st < R.lp.N; st += OBS_TILE) ot.push_back(Tile{r, st});
     R.tile_end = (int)ot.size();
@@ -625,6 +654,9 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   D.part = (double*)(w + c->wl.part);
   D.tX = (int64_t*)(w + c->wl.tX);
   D.notdone = (uint32_t*)(w + c->wl.notdone);
+  D.chead = (int*)(w + c->wl.chead);
+  D.cnext = (int*)(w + c->wl.cnext);
+  D.cmask = (uint32_t)(c->wl.nbuckets - 1);
   D.ctrl = (Ctrl*)(w + c->wl.ctrl);
 
   hipStream_t s = c->s;
@@ -686,11 +718,15 @@ int lb_init(const lb_desc* d, const lb_buffers* b, const double* r0_host, const 
 void lb_destroy(lb_ctx* ctx) {
   if (!ctx) return;
   if (ctx->s) (void)hipStreamSynchronize(ctx->s);
+  if (ctx->s1) (void)hipStreamSynchronize(ctx->s1);
   if (ctx->s2) (void)hipStreamSynchronize(ctx->s2);
   drop_graph(ctx);
   for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
   if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->prep) (void)hipEventDestroy(ctx->prep);
   if (ctx->join) (void)hipEventDestroy(ctx->join);
+  if (ctx->join1) (void)hipEventDestroy(ctx->join1);
+  if (ctx->s1) (void)hipStreamDestroy(ctx->s1);
   if (ctx->s2) (void)hipStreamDestroy(ctx->s2);
   if (ctx->scap) (void)hipStreamDestroy(ctx->scap);
   delete ctx;
@@ -726,6 +762,7 @@ int lb_profile_stop(lb_ctx* c, double* mean_lb_ms, double* mean_bead_ms, int* ns
   if (!c->prof_on) return fail(LB_ERR_ARG, "profiling not active");
   c->prof_on = false;
   hipError_t r = hipStreamSynchronize(c->s);
+  if (r == hipSuccess) r = hipStreamSynchronize(c->s1);
   if (r == hipSuccess) r = hipStreamSynchronize(c->s2);
   if (r != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(r));
   double tl = 0.0, tb = 0.0;
@@ -848,6 +885,7 @@ void* lb_current_pops(lb_ctx* c) { return c ? cur_pops(c) : nullptr; }
 int lb_check(lb_ctx* c) {
   if (!c) return fail(LB_ERR_ARG, "null context");
   hipError_t e = hipStreamSynchronize(c->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->s1);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s2);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "stream: %s", hipGetErrorString(e));
   uint32_t err = 0;

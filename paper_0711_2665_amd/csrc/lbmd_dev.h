@@ -45,7 +45,9 @@ constexpr uint32_t E_SPREAD = 8u;    // too many beads share a node stencil
 
 constexpr int MAXNBR = 48;        // neighbour-list capacity per bead
 constexpr int MAXCONTRIB = 64;    // bead contributions gathered per node
-constexpr double SKIN = 0.4;      // neighbour-list skin
+constexpr double SKIN = 0.4;      // neighbour-list skin (lists rebuilt when a bead moved skin/2)
+constexpr double SKIN_STEP = 0.6; // skin when lists are rebuilt at every coupled step (long chains)
+constexpr int STEP_LISTS_MIN_BEADS = 1024;  // chains this long get per-step cell-list builds
 
 // Control block at the head of the work buffer.
 struct Ctrl {

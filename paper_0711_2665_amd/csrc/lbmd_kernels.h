@@ -44,6 +44,7 @@ struct Rep {
   int tile_begin;   // reduction tiles [tile_begin, tile_end)
   int tile_end;
   double nfluid;    // fluid nodes (for the mass observable)
+  int ncell[3];     // neighbour-search cells per axis (side >= r_c + skin)
 };
 
 struct Tile {
@@ -82,6 +83,9 @@ struct Dev {
   double* part;     // [reduction tiles][4] fluid partial sums
   int64_t* tX;      // per replica: first step with the whole chain translocated, -1 before
   uint32_t* notdone;// per replica: some bead still on the cis side this step
+  int* chead;       // neighbour search: bucket heads of the hashed cell table
+  int* cnext;       // per slot: next bead in the same bucket
+  uint32_t cmask;   // buckets - 1 (a power of two minus one)
   Ctrl* ctrl;
 };
 
@@ -111,7 +115,7 @@ template <typename T, bool DEV>
 void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s);
 
 // Adjoint pass (one replica, chains of at most MAX_ADJ_BEADS beads).
-constexpr int MAX_ADJ_BEADS = 256;
+constexpr int MAX_ADJ_BEADS = 128;
 struct AdjBufs {
   double* lr;       // [slots][3] adjoint of r
   double* lv;       // [slots][3] adjoint of v
@@ -135,6 +139,9 @@ void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
                      hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);
+// Verlet lists of every bead from a hashed cell list of the current
+// positions (once per coupled step); marks the lists valid.
+void launch_nbr_build(const Dev& d, int nslots, hipStream_t s);
 void launch_zero_v(const Dev& d, int nslots, hipStream_t s);
 
 }  // namespace lbmd

@@ -214,7 +214,14 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   const bool lead = active && lane == 0;
   double vo[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0}, Jo[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
   double rm[3] = {0.0, 0.0, 0.0}, rq[3] = {0.0, 0.0, 0.0};
-  int ncnt0 = 0;
+  // every lane: the list length and its share of the list (entries lane,
+  // lane + 4, ...), issued with the other first-level loads; entries past the
+  // length are never used
+  int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
+  const int ncnt0 = active ? d.ncnt[slot] : 0;
+  int pre[NB_PER_LANE];
+#pragma unroll
+  for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = active ? nbr_row[lane + MD_LANES * m] : -1;
   if (lead) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -225,18 +232,17 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
       if (p > 0) rm[a] = rin[3 * (p - 1) + a];
       if (p < P.nb - 1) rq[a] = rin[3 * (p + 1) + a];
     }
-    ncnt0 = d.ncnt[slot];
   }
   if (t == 0) sh.over = 0;
   angles_to_lds(rin, P, p0 - 1, MD_BPB + 2, sh.ang);
 
-  // ---- neighbour list: reuse, or rebuild by scanning the chain in tiles of 64
-  int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
+  // ---- neighbour list: reuse (already in registers), or rebuild by
+  // scanning the chain in tiles of 64
+  int cnt = ncnt0;
+  int jl[NB_PER_LANE];
   if (!rebuild) {
-    if (lead) sh.cnt[bslot] = ncnt0;
-    __syncthreads();
-    int c = active ? sh.cnt[bslot] : 0;
-    for (int k = lane; k < c; k += MD_LANES) sh.lst[bslot][k] = nbr_row[k];
+#pragma unroll
+    for (int m = 0; m < NB_PER_LANE; ++m) jl[m] = (lane + MD_LANES * m < cnt) ? pre[m] : -1;
   } else {
     if (lane == 0) sh.cnt[bslot] = 0;
     for (int base = 0; base < P.nb; base += MD_WG) {
@@ -280,21 +286,18 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
       d.ref[3 * slot] = rp[0]; d.ref[3 * slot + 1] = rp[1]; d.ref[3 * slot + 2] = rp[2];
     }
     __syncthreads();
-    int c = active ? sh.cnt[bslot] : 0;
-    for (int k = lane; k < c; k += MD_LANES) nbr_row[k] = sh.lst[bslot][k];
+    cnt = active ? sh.cnt[bslot] : 0;
+    for (int k = lane; k < cnt; k += MD_LANES) nbr_row[k] = sh.lst[bslot][k];
     if (t == 0 && sh.over) atomicOr(&d.ctrl->err, E_NBRLIST);
-  }
-  __syncthreads();
-
-  // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
-  const int cnt = active ? sh.cnt[bslot] : 0;
-  {
-    int jl[NB_PER_LANE];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) {
       int k = lane + MD_LANES * m;
       jl[m] = (k < cnt) ? sh.lst[bslot][k] : -1;
     }
+  }
+
+  // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
+  {
     double q[NB_PER_LANE][3];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) {
@@ -371,6 +374,105 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
 __global__ void k_zero_v(double* v, int n) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) v[k] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour lists from a hashed cell list, once per coupled step.  Cells of
+// side >= r_c + skin per replica; a cell's beads are linked in one bucket of
+// a power-of-two table (colliding cells share a bucket: their beads fail the
+// distance test or are counted once).  Each bead scans its 27 neighbour
+// cells and keeps every other bead of its chain within r_c + skin in
+// ascending chain order -- the list the in-kernel scan would build.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t cell_bucket(int rep, int cx, int cy, int cz, uint32_t mask) {
+  uint32_t h = ((uint32_t)rep * 73856093u) ^ ((uint32_t)cx * 19349663u) ^ ((uint32_t)cy * 83492791u) ^
+               ((uint32_t)cz * 2654435761u);
+  return h & mask;
+}
+
+__device__ inline void bead_cell(const Rep& R, const double* rp, int c[3]) {
+  const int n[3] = {R.g.nx, R.g.ny, R.g.nz};
+  for (int a = 0; a < 3; ++a) {
+    double w = wrapc(rp[a], n[a]);
+    if (!(w >= 0.0 && w < (double)n[a])) w = 0.0;   // non-finite: still a valid cell
+    int k = (int)(w * (double)R.ncell[a] / (double)n[a]);
+    c[a] = k < R.ncell[a] ? k : R.ncell[a] - 1;
+  }
+}
+
+__global__ void k_cell_clear(int* __restrict__ chead, int nbuckets) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbuckets) chead[k] = -1;
+}
+
+__global__ void k_cell_insert(Dev d, int nslots) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const int rep = d.slot_rep[slot];
+  const Rep& R = d.reps[rep];
+  if (slot - R.slot_off >= R.mp.nb) return;
+  int c[3];
+  bead_cell(R, &d.r[3 * slot], c);
+  d.cnext[slot] = atomicExch(&d.chead[cell_bucket(rep, c[0], c[1], c[2], d.cmask)], slot);
+}
+
+__global__ void k_list_build(Dev d, int nslots) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const int rep = d.slot_rep[slot];
+  const Rep& R = d.reps[rep];
+  const int so = R.slot_off;
+  const int p = slot - so;
+  if (p >= R.mp.nb) return;
+  const Geom& g = R.g;
+  const double rp[3] = {d.r[3 * slot], d.r[3 * slot + 1], d.r[3 * slot + 2]};
+  int c[3];
+  bead_cell(R, rp, c);
+  int lst[MAXNBR];
+  int cnt = 0;
+  bool over = false;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int cx = (c[0] + dx + R.ncell[0]) % R.ncell[0];
+        const int cy = (c[1] + dy + R.ncell[1]) % R.ncell[1];
+        const int cz = (c[2] + dz + R.ncell[2]) % R.ncell[2];
+        for (int q = d.chead[cell_bucket(rep, cx, cy, cz, d.cmask)]; q >= 0; q = d.cnext[q]) {
+          if (d.slot_rep[q] != rep) continue;
+          const int j = q - so;
+          if (j == p) continue;
+          double d0 = min_image(rp[0] - d.r[3 * q], g.nx);
+          double d1 = min_image(rp[1] - d.r[3 * q + 1], g.ny);
+          double d2 = min_image(rp[2] - d.r[3 * q + 2], g.nz);
+          if (!(d0 * d0 + d1 * d1 + d2 * d2 < R.mp.rlist2)) continue;
+          // sorted insert, each bead once, the MAXNBR smallest kept
+          int k = cnt;
+          while (k > 0 && lst[k - 1] > j) --k;
+          if (k > 0 && lst[k - 1] == j) continue;
+          if (cnt == MAXNBR) {
+            over = true;
+            if (k == MAXNBR) continue;
+            --cnt;
+          }
+          for (int m = cnt; m > k; --m) lst[m] = lst[m - 1];
+          lst[k] = j;
+          ++cnt;
+        }
+      }
+  if (over) atomicOr(&d.ctrl->err, E_NBRLIST);
+  int* row = d.nbr + (size_t)slot * MAXNBR;
+  for (int k = 0; k < cnt; ++k) row[k] = lst[k];
+  d.ncnt[slot] = cnt;
+  d.ref[3 * slot] = rp[0]; d.ref[3 * slot + 1] = rp[1]; d.ref[3 * slot + 2] = rp[2];
+  if (p == 0) d.rb[4 * rep + 3] = 0u;      // the lists are valid
+}
+
+void launch_nbr_build(const Dev& d, int nslots, hipStream_t s) {
+  if (nslots <= 0) return;
+  const int nb = (int)d.cmask + 1;
+  hipLaunchKernelGGL(k_cell_clear, dim3((nb + 255) / 256), dim3(256), 0, s, d.chead, nb);
+  hipLaunchKernelGGL(k_cell_insert, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots);
+  hipLaunchKernelGGL(k_list_build, dim3((nslots + 63) / 64), dim3(64), 0, s, d, nslots);
 }
 
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {

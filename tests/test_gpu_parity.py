@@ -260,6 +260,34 @@ def test_single_coupled_step_fp64_bitwise_up_to_libm(orc):
         assert np.array_equal(sb[k], ob[k]), k
 
 
+def test_long_chain_with_per_step_lists_bitwise(orc):
+    """A chain of 1100 beads takes the long-chain path: neighbour lists from
+    a hashed cell list at every coupled step (larger skin).  With kT = 0 and
+    kappa = 0 three coupled steps must equal the oracle bit for bit."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=(40, 40, 40), wall_pos=20, nb=1100, kT=0.0, kappa=0.0, init_seed=9)
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(300, 1.0)
+    ob = o.beads()
+    o = orc.Oracle(cfg, ob["r"], np.zeros_like(ob["r"]))
+    s = lbmd.Simulation(cfg, ob["r"], None)
+    o.couple_step(3)
+    s.couple_step(3)
+    torch.cuda.synchronize()
+    s.check()
+    fluid = o.flags() == 0
+    a, b = _gpu_pops(s)[:, fluid], o.pops()[:, fluid]
+    sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+    ob = o.beads()
+    print("1100 beads, 3 steps: pops differing", int((a != b).sum()),
+          {k: int((sb[k] != ob[k]).sum()) for k in ("r", "v", "up", "J")}, s.diagnostics(), flush=True)
+    assert np.array_equal(a, b)
+    for k in ("r", "v", "up", "J"):
+        assert np.array_equal(sb[k], ob[k]), k
+
+
 @pytest.mark.parametrize("shape,axis,pos", [((12, 10, 16), 2, 8), ((32, 16, 12), 0, 16)])
 def test_lb_only_fp32_deviation_matches_oracle(orc, shape, axis, pos):
     """FP32 deviation storage against the FP64 oracle over 20 fluid steps from
