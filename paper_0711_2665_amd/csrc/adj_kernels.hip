@@ -260,10 +260,10 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 }
 
 // ---------------------------------------------------------------------------
-// MD sub-cycle transpose of one chain, one workgroup, one thread per bead.
-// The sub-cycle is first recomputed from (r_n, v_n, u_p) with the step's
-// noise, recording the force positions r_mid and the velocities at the start
-// of every sub-step; the sub-steps are then reversed.  On entry lr, lv hold
+// MD sub-cycle transpose of one chain, one workgroup, four lanes per bead.
+// The force positions r_mid and the velocities at the start of every
+// sub-step come from the tape the forward sub-cycle wrote while the segment
+// was recomputed; the sub-steps are reversed.  On entry lr, lv hold
 // the adjoint of r, v after the step and lJ that of the impulse J; on exit
 // lr, lv hold the adjoint of r_n, v_n through the sub-cycle and lup that of
 // u_p.  The parameter adjoints are added to par[0] (gamma) and par[1]
@@ -283,9 +283,8 @@ __device__ inline void chain_forces(const MdParams& P, const Geom& g, const doub
   bead_force_dd(P, g, pos, dir, av, ad, p, lane, on, F, dF);
 }
 
-__global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const double* __restrict__ rt,
-                                                   const double* __restrict__ vt, const double* __restrict__ upt,
-                                                   uint32_t step, double kT) {
+__global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const double* __restrict__ mdt,
+                                                   const double* __restrict__ upt, uint32_t step, double kT) {
   extern __shared__ double lds[];
   const Rep& R = d.reps[0];
   const MdParams P = R.mp;
@@ -299,41 +298,10 @@ __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const doubl
   const int p = threadIdx.x / ADJ_LANES, lane = threadIdx.x % ADJ_LANES;
   const bool on = p < nb;
   const bool lead = on && lane == 0;
-  double r[3], v[3], u[3];
-  for (int c = 0; c < 3; ++c) {
-    r[c] = on ? rt[3 * p + c] : 0.0;
-    v[c] = on ? vt[3 * p + c] : 0.0;
-    u[c] = on ? upt[3 * p + c] : 0.0;
-  }
-  // ---- forward recompute (every lane of a bead carries its state)
-  for (int s = 0; s < n_sub; ++s) {
-    if (on) {
-      for (int c = 0; c < 3; ++c) {
-        const double x = r[c] + P.hh * v[c];
-        if (lane == 0) {
-          pos[p][c] = x;
-          dir[p][c] = 0.0;
-          a.rmid[((size_t)s * nb + p) * 3 + c] = x;
-          a.vold[((size_t)s * nb + p) * 3 + c] = v[c];
-        }
-        r[c] = x;
-      }
-    }
-    __syncthreads();
-    double f[3], df[3];
-    chain_forces(P, g, pos, dir, av, ad, p, lane, on, f, df);
-    if (on) {
-      if (P.field_on && in_field(g, r)) f[g.wall_axis] += P.f_drive;
-      double xi[3] = {0.0, 0.0, 0.0};
-      if (P.sig != 0.0) gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, xi);
-      for (int c = 0; c < 3; ++c) {
-        const double vn = P.e * v[c] + P.cf * (f[c] + P.gamma * u[c]) + P.sig * xi[c];
-        v[c] = vn;
-        r[c] = r[c] + P.hh * vn;
-      }
-    }
-    __syncthreads();
-  }
+  double u[3];
+  for (int c = 0; c < 3; ++c) u[c] = on ? upt[3 * p + c] : 0.0;
+  // the forward sub-cycle recorded r_mid and v at the start of every
+  // sub-step: mdt[s][p][0..2] and [3..5]
   // ---- reverse
   const double h = 2.0 * P.hh;
   const double gam = P.gamma;
@@ -352,7 +320,7 @@ __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const doubl
     double lvt[3], rm[3];
     for (int c = 0; c < 3; ++c) {
       lvt[c] = lv[c] + P.hh * lr[c];
-      rm[c] = on ? a.rmid[((size_t)s * nb + p) * 3 + c] : 0.0;
+      rm[c] = on ? mdt[((size_t)s * nb + p) * 6 + c] : 0.0;
     }
     if (lead)
       for (int c = 0; c < 3; ++c) { pos[p][c] = rm[c]; dir[p][c] = P.cf * lvt[c]; }
@@ -365,7 +333,7 @@ __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const doubl
       double xi[3] = {0.0, 0.0, 0.0};
       if (P.sig != 0.0 && lead) gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, xi);
       for (int c = 0; c < 3; ++c) {
-        const double vo = a.vold[((size_t)s * nb + p) * 3 + c];
+        const double vo = mdt[((size_t)s * nb + p) * 6 + 3 + c];
         if (lead) {
           acc_g += lvt[c] * (vo * de + (f[c] + gam * u[c]) * dcf + P.cf * u[c] + xi[c] * dsig);
           acc_g += lJ[c] * (-P.m) * ((u[c] - vo) * domE + xi[c] * dsig);
@@ -535,13 +503,13 @@ void launch_adj_init(const double* dLdr, const double* dLdv, const AdjBufs& a, i
 
 template <typename T, bool DEV>
 void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const Dev& d, const Dev& dspread,
-                             const AdjBufs& a, const double* rt, const double* vt, const double* upt,
+                             const AdjBufs& a, const double* mdt, const double* upt,
                              const double* Jt, uint32_t step, double kT, int ntiles, int tile_nodes, int nslots,
                              int nb, hipStream_t s) {
   launch_bead_prep(d, nslots, s);
   hipLaunchKernelGGL((k_adj_spread_t<T>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)lamB, d, a, Jt, nb);
   size_t lds = sizeof(double) * (24 * (size_t)nb + 2 * (ADJ_WG / ADJ_LANES));
-  hipLaunchKernelGGL(k_adj_md, dim3(1), dim3(ADJ_WG), lds, s, d, a, rt, vt, upt, step, kT);
+  hipLaunchKernelGGL(k_adj_md, dim3(1), dim3(ADJ_WG), lds, s, d, a, mdt, upt, step, kT);
   hipLaunchKernelGGL((k_adj_gather_t<T, DEV>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)A, d, a, nb);
   launch_spread<T>(dspread, nslots, s);
   hipLaunchKernelGGL((k_adj_lb<T, DEV>), dim3((unsigned)ntiles), dim3(256), 0, s, (const T*)A, (const T*)lamB,
@@ -559,9 +527,9 @@ void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s) {
 
 template void launch_adj_reverse_step<double, false>(const void*, const void*, void*, const Dev&, const Dev&,
                                                      const AdjBufs&, const double*, const double*, const double*,
-                                                     const double*, uint32_t, double, int, int, int, int, hipStream_t);
+                                                     uint32_t, double, int, int, int, int, hipStream_t);
 template void launch_adj_reverse_step<float, true>(const void*, const void*, void*, const Dev&, const Dev&,
                                                    const AdjBufs&, const double*, const double*, const double*,
-                                                   const double*, uint32_t, double, int, int, int, int, hipStream_t);
+                                                   uint32_t, double, int, int, int, int, hipStream_t);
 
 }  // namespace lbmd

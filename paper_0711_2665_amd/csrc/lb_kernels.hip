@@ -97,27 +97,38 @@ __global__ void k_bead_prep(Dev d, int nslots) {
 }
 
 // ---------------------------------------------------------------------------
-// K2: u_p = sum_k W_k u(node_k) at r(n) (trilinear).
+// K2: u_p = sum_k W_k u(node_k) at r(n) (trilinear).  Eight consecutive
+// lanes per bead, one corner each; the corner terms are added by the bead's
+// first lane in corner order.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
 __global__ void k_gather(const T* __restrict__ A, Dev d, int nslots) {
-  int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
-  const Rep& R = d.reps[d.slot_rep[slot]];
-  if (slot - R.slot_off >= R.mp.nb) return;
-  const T* Ar = A + (size_t)Q * R.node_off;
-  const uint8_t* fr = d.flags + R.node_off;
-  double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
-  Stencil st = make_stencil(R.g, rp);
-  double acc[3] = {0.0, 0.0, 0.0};
-  for (int k = 0; k < 8; ++k) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = e >> 3, k = e & 7;
+  bool on = slot < nslots;
+  int rep = 0;
+  if (on) {
+    rep = d.slot_rep[slot];
+    on = slot - d.reps[rep].slot_off < d.reps[rep].mp.nb;
+  }
+  double t[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    const Rep& R = d.reps[rep];
+    const T* Ar = A + (size_t)Q * R.node_off;
+    const uint8_t* fr = d.flags + R.node_off;
+    double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
+    Stencil st = make_stencil(R.g, rp);
     int node = (int)corner_node(R.g, st, k);
     double W = corner_weight(st, k);
     double u[3];
     node_velocity<T, DEV>(Ar, fr, R.lp, node, u);
-    acc[0] += W * u[0]; acc[1] += W * u[1]; acc[2] += W * u[2];
+    t[0] = W * u[0]; t[1] = W * u[1]; t[2] = W * u[2];
   }
-  d.up[3 * slot] = acc[0]; d.up[3 * slot + 1] = acc[1]; d.up[3 * slot + 2] = acc[2];
+  const int base = (int)(threadIdx.x & 63u) & ~7;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < 8; ++c)
+    for (int a = 0; a < 3; ++a) acc[a] += __shfl(t[a], base + c, 64);
+  if (on && k == 0) { d.up[3 * slot] = acc[0]; d.up[3 * slot + 1] = acc[1]; d.up[3 * slot + 2] = acc[2]; }
 }
 
 // ---------------------------------------------------------------------------
@@ -386,7 +397,8 @@ void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStre
 template <typename T, bool DEV>
 void launch_gather(const void* A, const Dev& d, int nslots, hipStream_t s) {
   if (nslots > 0)
-    hipLaunchKernelGGL((k_gather<T, DEV>), dim3(blocks_for(nslots, 64)), dim3(64), 0, s, (const T*)A, d, nslots);
+    hipLaunchKernelGGL((k_gather<T, DEV>), dim3(blocks_for(8L * nslots, 64)), dim3(64), 0, s, (const T*)A, d,
+                       nslots);
 }
 
 void launch_bead_prep(const Dev& d, int nslots, hipStream_t s) {

@@ -481,7 +481,7 @@ AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
   L.nseg = (nsteps + K - 1) / K;
   L.pops_slot = align256(es * Q * (size_t)c->pk.nodes);
   L.bead_arr = align256(sizeof(double) * 3 * (size_t)c->pk.slots_alloc);
-  L.md_arr = align256(sizeof(double) * 3 * (size_t)c->d[0].nb * (size_t)c->n_sub);
+  L.md_arr = align256(sizeof(double) * 6 * (size_t)c->d[0].nb * (size_t)c->n_sub);
   size_t o = 0;
   L.ckpt = o; o += (size_t)(L.nseg + 1) * c->sl.total;
   L.tape_pops = o; o += (size_t)K * L.pops_slot;
@@ -490,7 +490,7 @@ AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
   L.lamB = o; o += L.pops_slot;
   L.lamu = o; o += align256(es * 3 * (size_t)c->pk.nodes);
   L.lbead = o; o += 5 * L.bead_arr;
-  L.mdtape = o; o += 2 * L.md_arr;
+  L.mdtape = o; o += (size_t)K * L.md_arr;
   L.par = o; o += 256;
   L.total = o;
   return L;
@@ -1069,8 +1069,6 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
   a.lJ = (double*)(w + L.lbead + 2 * L.bead_arr);
   a.lup = (double*)(w + L.lbead + 3 * L.bead_arr);
   a.lrs = (double*)(w + L.lbead + 4 * L.bead_arr);
-  a.rmid = (double*)(w + L.mdtape);
-  a.vold = (double*)(w + L.mdtape + L.md_arr);
   a.lamu = w + L.lamu;
   a.par = (double*)(w + L.par);
   void* lamB = w + L.lamB;   // adjoint of the populations after the step being reversed
@@ -1094,7 +1092,9 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
       acc(hipMemcpyAsync(tape_bead(j, 0), c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
       acc(hipMemcpyAsync(tape_bead(j, 1), c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
       void* B = j + 1 < len ? tape_pops(j + 1) : other_pops(c);
+      c->D.mdtape = (double*)(w + L.mdtape + (size_t)j * L.md_arr);
       enqueue_coupled_step_ab(c, tape_pops(j), B, c->s);
+      c->D.mdtape = nullptr;
       acc(hipMemcpyAsync(tape_bead(j, 2), c->D.up, nb3, hipMemcpyDeviceToDevice, c->s));
       acc(hipMemcpyAsync(tape_bead(j, 3), c->D.J, nb3, hipMemcpyDeviceToDevice, c->s));
     }
@@ -1106,14 +1106,15 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
       ds.J = a.lup;
       ds.force = a.lamu;
       const uint32_t step = (uint32_t)(c->adj_step0 + n0 + j);
+      const double* mdt = (const double*)(w + L.mdtape + (size_t)j * L.md_arr);
       if (c->dev)
-        launch_adj_reverse_step<float, true>(tape_pops(j), lamB, lamA, da, ds, a, tape_bead(j, 0), tape_bead(j, 1),
-                                             tape_bead(j, 2), tape_bead(j, 3), step, kT, c->ntiles,
-                                             c->sweep.tile_nodes, c->nslots, nb, c->s);
+        launch_adj_reverse_step<float, true>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_bead(j, 2),
+                                             tape_bead(j, 3), step, kT, c->ntiles, c->sweep.tile_nodes, c->nslots,
+                                             nb, c->s);
       else
-        launch_adj_reverse_step<double, false>(tape_pops(j), lamB, lamA, da, ds, a, tape_bead(j, 0),
-                                               tape_bead(j, 1), tape_bead(j, 2), tape_bead(j, 3), step, kT,
-                                               c->ntiles, c->sweep.tile_nodes, c->nslots, nb, c->s);
+        launch_adj_reverse_step<double, false>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_bead(j, 2),
+                                               tape_bead(j, 3), step, kT, c->ntiles, c->sweep.tile_nodes,
+                                               c->nslots, nb, c->s);
       std::swap(lamA, lamB);
     }
   }

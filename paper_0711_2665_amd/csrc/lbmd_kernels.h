@@ -83,6 +83,8 @@ struct Dev {
   double* part;     // [reduction tiles][4] fluid partial sums
   int64_t* tX;      // per replica: first step with the whole chain translocated, -1 before
   uint32_t* notdone;// per replica: some bead still on the cis side this step
+  double* mdtape;   // when set: per sub-step s and bead p, r_mid and v at the start,
+                    // [s][p][2][3] (recorded for the adjoint, one replica)
   int* chead;       // neighbour search: bucket heads of the hashed cell table
   int* cnext;       // per slot: next bead in the same bucket
   uint32_t cmask;   // buckets - 1 (a power of two minus one)
@@ -122,15 +124,14 @@ struct AdjBufs {
   double* lJ;       // [slots][3] adjoint of the impulse J
   double* lup;      // [slots][3] adjoint of u_p
   double* lrs;      // [slots][3] position term of the spreading transpose
-  double* rmid;     // [n_sub][nb][3] recomputed force positions of one step
-  double* vold;     // [n_sub][nb][3] velocities at the start of each sub-step
+
   void* lamu;       // [3][N] (storage type) adjoint of the gathered node velocity
   double* par;      // [4]: dL/dgamma, dL/dF_drive accumulators
 };
 void launch_adj_init(const double* dLdr, const double* dLdv, const AdjBufs& a, int nb, hipStream_t s);
 template <typename T, bool DEV>
 void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const Dev& d, const Dev& dspread,
-                             const AdjBufs& a, const double* rt, const double* vt, const double* upt,
+                             const AdjBufs& a, const double* mdt, const double* upt,
                              const double* Jt, uint32_t step, double kT, int ntiles, int tile_nodes, int nslots,
                              int nb, hipStream_t s);
 void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);

@@ -355,6 +355,11 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
     finite = finite && isfinite(vn[a]);
   }
   if (!finite) atomicOr(&d.ctrl->err, E_BEADS);
+  if (d.mdtape) {
+    double* tp = d.mdtape + ((size_t)s * P.nb + p) * 6;
+    tp[0] = rp[0]; tp[1] = rp[1]; tp[2] = rp[2];
+    tp[3] = vo[0]; tp[4] = vo[1]; tp[5] = vo[2];
+  }
   double re[3] = {rp[0] + P.hh * vn[0], rp[1] + P.hh * vn[1], rp[2] + P.hh * vn[2]};
   if (last) {
     d.r[3 * slot] = re[0]; d.r[3 * slot + 1] = re[1]; d.r[3 * slot + 2] = re[2];
