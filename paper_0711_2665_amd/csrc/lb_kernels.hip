@@ -196,6 +196,67 @@ __global__ void k_spread(Dev d, int nslots) {
   d.touched[s] = make_int2(rep, n);
 }
 
+// Spreading fused with the LB update of the node it writes: the owner of a
+// node (see k_spread) sums its force, stores it, and updates the node at
+// once -- the same operations as k_spread followed by k_lb_forced.
+template <typename T, bool DEV>
+__global__ void k_spread_lb(const T* __restrict__ A, T* __restrict__ B, Dev d, int nslots) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 8 * nslots) return;
+  int slot = e >> 3, k = e & 7;
+  const int rep = d.slot_rep[slot];
+  const Rep& R = d.reps[rep];
+  const int p = slot - R.slot_off;
+  if (p >= R.mp.nb) return;
+  const Geom& g = R.g;
+  const uint8_t* fr = d.flags + R.node_off;
+  double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
+  Stencil st = make_stencil(g, rp);
+  int n = (int)corner_node(g, st, k);
+  if (fr[n] & F_SOLID) return;
+  int nz_ = n / g.nxy, rem = n - nz_ * g.nxy, ny_ = rem / g.nx, nx_ = rem - ny_ * g.nx;
+  int keys[MAXCONTRIB];
+  int cnt = 0;
+  bool overflow = false;
+  for (int k2 = 0; k2 < 8; ++k2) {
+    int bx = nx_ - (k2 & 1); if (bx < 0) bx += g.nx;
+    int by = ny_ - ((k2 >> 1) & 1); if (by < 0) by += g.ny;
+    int bz = nz_ - ((k2 >> 2) & 1); if (bz < 0) bz += g.nz;
+    int cell = bx + g.nx * (by + g.ny * bz);
+    for (int q = d.head[R.node_off + cell]; q >= 0; q = d.next[q]) {
+      int key = (q - R.slot_off) * 8 + k2;
+      if (cnt < MAXCONTRIB) {
+        int j = cnt++;
+        while (j > 0 && keys[j - 1] > key) { keys[j] = keys[j - 1]; --j; }
+        keys[j] = key;
+      } else {
+        overflow = true;
+      }
+    }
+  }
+  if (overflow) { atomicOr(&d.ctrl->err, E_SPREAD); }
+  if (keys[0] != p * 8 + k) return;   // not the owner of node n
+  double F[3] = {0.0, 0.0, 0.0};
+  for (int j = 0; j < cnt; ++j) {
+    int qs = R.slot_off + (keys[j] >> 3), k2 = keys[j] & 7;
+    double rq[3] = {d.rs[3 * qs], d.rs[3 * qs + 1], d.rs[3 * qs + 2]};
+    Stencil sq = make_stencil(g, rq);
+    double W = corner_weight(sq, k2);
+    F[0] += W * d.J[3 * qs];
+    F[1] += W * d.J[3 * qs + 1];
+    F[2] += W * d.J[3 * qs + 2];
+  }
+  const size_t N = (size_t)g.N;
+  T* Fr = (T*)d.force + (size_t)3 * R.node_off;
+  Fr[n] = (T)F[0];
+  Fr[N + n] = (T)F[1];
+  Fr[2 * N + n] = (T)F[2];
+  int s = atomicAdd(&d.ctrl->touched, 1u);
+  d.touched[s] = make_int2(rep, n);
+  const long no = R.node_off;
+  lb_node<T, DEV>(A + (size_t)Q * no, B + (size_t)Q * no, fr, Fr, R.lp, d.ctrl, n, fr[n]);
+}
+
 // End of a coupled step: clear the forced bits, empty the node lists, note
 // replicas with a bead still on the cis side of the wall.
 __global__ void k_step_end(Dev d, int nslots, int maxlist) {
@@ -410,6 +471,13 @@ void launch_spread(const Dev& d, int nslots, hipStream_t s) {
   if (nslots > 0) hipLaunchKernelGGL((k_spread<T>), dim3(blocks_for(8L * nslots, 64)), dim3(64), 0, s, d, nslots);
 }
 
+template <typename T, bool DEV>
+void launch_spread_lb(const void* A, void* B, const Dev& d, int nslots, hipStream_t s) {
+  if (nslots > 0)
+    hipLaunchKernelGGL((k_spread_lb<T, DEV>), dim3(blocks_for(8L * nslots, 64)), dim3(64), 0, s, (const T*)A,
+                       (T*)B, d, nslots);
+}
+
 void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_t s) {
   long n = nslots > maxlist ? nslots : maxlist;
   if (n > 0) hipLaunchKernelGGL(k_step_end, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, nslots, maxlist);
@@ -431,6 +499,8 @@ template void launch_lb_forced<float, true>(const void*, void*, const Dev&, int,
 template void launch_gather<double, false>(const void*, const Dev&, int, hipStream_t);
 template void launch_gather<float, true>(const void*, const Dev&, int, hipStream_t);
 template void launch_spread<double>(const Dev&, int, hipStream_t);
+template void launch_spread_lb<double, false>(const void*, void*, const Dev&, int, hipStream_t);
+template void launch_spread_lb<float, true>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_spread<float>(const Dev&, int, hipStream_t);
 template void launch_observables<double, false>(const void*, const Dev&, int, int, double*, hipStream_t);
 template void launch_observables<float, true>(const void*, const Dev&, int, int, double*, hipStream_t);

@@ -281,6 +281,7 @@ struct lb_ctx {
   int nslots = 0;
   int maxlist = 0;
   bool step_lists = false;   // neighbour lists built from a cell list at every coupled step
+  bool lists_stale = true;   // the positions changed outside a coupled step since the last build
   bool any_noise = false;
   SweepCfg sweep;
   int ntiles = 0;
@@ -288,7 +289,7 @@ struct lb_ctx {
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
   hipStream_t s1 = nullptr, s2 = nullptr;
-  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr;
+  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr, noise = nullptr;
   // graph of two coupled steps, starting at population parity graph_cur
   hipStream_t scap = nullptr;
   hipGraph_t graph = nullptr;
@@ -394,19 +395,33 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   launch_bead_prep(D, c->nslots, sb);
   acc(hipEventRecord(c->prep, sb));
   acc(hipStreamWaitEvent(c->s2, c->prep, 0));
+  // eager steps draw the sub-cycle's noise on the sweep stream, ahead of the
+  // sweep, while the bead stream gathers; a captured graph keeps the noise
+  // pass on the bead stream (no cross-stream dependency inside the step)
+  const bool noise_aside = c->any_noise && !c->capturing;
+  if (noise_aside) {
+    launch_md_noise(D, c->nslots, c->n_sub, c->s2);
+    acc(hipEventRecord(c->noise, c->s2));
+  }
   prof_mark(c, 2, c->s2);
   sweep_ab(c, A, B, 1, c->s2);
   prof_mark(c, 3, c->s2);
   acc(hipEventRecord(c->join, c->s2));
-  if (c->step_lists) launch_nbr_build(D, c->nslots, sb);
+  // long chains: the lists of this step were built at the end of the
+  // previous one (when the sweep is normally done), unless the positions
+  // changed since
+  if (c->step_lists && c->lists_stale) launch_nbr_build(D, c->nslots, sb);
   if (c->dev) launch_gather<float, true>(A, D, c->nslots, sb);
   else launch_gather<double, false>(A, D, c->nslots, sb);
   MdOverride none{};
-  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, c->any_noise ? 1 : 0, none, sb);
-  if (c->dev) launch_spread<float>(D, c->nslots, sb);
-  else launch_spread<double>(D, c->nslots, sb);
-  if (c->dev) launch_lb_forced<float, true>(A, B, D, c->maxlist, sb);
-  else launch_lb_forced<double, false>(A, B, D, c->maxlist, sb);
+  if (noise_aside) acc(hipStreamWaitEvent(sb, c->noise, 0));
+  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, noise_aside ? -1 : (c->any_noise ? 1 : 0), none, sb);
+  if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
+  else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
+  if (c->step_lists) {
+    launch_nbr_build(D, c->nslots, sb);      // from r(n+1), for the next step
+    c->lists_stale = false;
+  }
   prof_mark(c, 1, sb);
   acc(hipEventRecord(c->join1, sb));
   acc(hipStreamWaitEvent(st, c->join, 0));
@@ -518,6 +533,7 @@ void restore_state(lb_ctx* c, const char* st, void* dst_pops) {
   acc(hipMemcpyAsync(&c->D.ctrl->step, st + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(c->D.tX, st + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
   launch_md_invalidate(c->D, c->nrep, c->s);
+  c->lists_stale = true;
 }
 
 }  // namespace
@@ -576,8 +592,9 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     hipError_t e5 = hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking);
     hipError_t e6 = hipEventCreateWithFlags(&c->prep, hipEventDisableTiming);
     hipError_t e7 = hipEventCreateWithFlags(&c->join1, hipEventDisableTiming);
+    hipError_t e8 = hipEventCreateWithFlags(&c->noise, hipEventDisableTiming);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess || e7 != hipSuccess) {
+        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess) {
       lb_destroy(c);
       return fail(LB_ERR_DEVICE, "stream/event creation failed");
     }
@@ -726,6 +743,7 @@ void lb_destroy(lb_ctx* ctx) {
   if (ctx->prep) (void)hipEventDestroy(ctx->prep);
   if (ctx->join) (void)hipEventDestroy(ctx->join);
   if (ctx->join1) (void)hipEventDestroy(ctx->join1);
+  if (ctx->noise) (void)hipEventDestroy(ctx->noise);
   if (ctx->s1) (void)hipStreamDestroy(ctx->s1);
   if (ctx->s2) (void)hipStreamDestroy(ctx->s2);
   if (ctx->scap) (void)hipStreamDestroy(ctx->scap);
@@ -837,6 +855,7 @@ int md_relax(lb_ctx* c, int nsub_total, double gamma_relax) {
     left -= n;
   }
   launch_zero_v(c->D, c->nslots, c->s);
+  c->lists_stale = true;
   return check_hip("md_relax");
 }
 
@@ -872,6 +891,7 @@ int lb_set_state(lb_ctx* c, const void* src) {
   acc(hipMemcpyAsync(&c->D.ctrl->step, o + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(c->D.tX, o + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
   launch_md_invalidate(c->D, c->nrep, c->s);
+  c->lists_stale = true;
   uint64_t st = 0;
   acc(hipMemcpyAsync(&st, o + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToHost, c->s));
   hipError_t e = hipStreamSynchronize(c->s);

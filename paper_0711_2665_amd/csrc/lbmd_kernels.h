@@ -112,6 +112,9 @@ void launch_gather(const void* A, const Dev& d, int nslots, hipStream_t s);
 void launch_bead_prep(const Dev& d, int nslots, hipStream_t s);
 template <typename T>
 void launch_spread(const Dev& d, int nslots, hipStream_t s);
+// Spreading fused with the update of the nodes it writes (forward step).
+template <typename T, bool DEV>
+void launch_spread_lb(const void* A, void* B, const Dev& d, int nslots, hipStream_t s);
 void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_t s);
 template <typename T, bool DEV>
 void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s);
@@ -136,9 +139,11 @@ void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const 
                              int nb, hipStream_t s);
 void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 
-// MD sub-cycle of all replicas: n_sub launches, one per sub-step.
+// MD sub-cycle of all replicas: n_sub launches, one per sub-step.  With
+// noise < 0 the noise pass is left to the caller (launch_md_noise).
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
                      hipStream_t s);
+void launch_md_noise(const Dev& d, int nslots, int n_sub, hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);
 // Verlet lists of every bead from a hashed cell list of the current
 // positions (once per coupled step); marks the lists valid.

@@ -36,9 +36,7 @@ __device__ inline void store_pop(T* ptr, T v) {
 }
 
 // Post-streaming populations at node c: f_i(x) = A_i(x - c_i), or
-// A_opp(i)(x) when x - c_i is solid (halfway bounce-back).  Every element is
-// read once per sweep, so the loads are non-temporal: the stream does not
-// evict the bead data that runs beside it from the caches.  Nodes away from
+// A_opp(i)(x) when x - c_i is solid (halfway bounce-back).  Nodes away from
 // walls take a straight run of 19 independent loads; next to a wall the 19
 // upstream flags are loaded first and the addresses selected without
 // branches, so the population loads are again issued together.
@@ -48,8 +46,7 @@ __device__ inline void pull(const T* __restrict__ A, const uint8_t* __restrict__
   const size_t N = (size_t)p.N;
   if (!(fl & F_NEAR)) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      f[i] = __builtin_nontemporal_load(&A[(size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)))]);
+    for (int i = 0; i < Q; ++i) f[i] = A[(size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)))];
   } else {
     uint8_t sf[Q];
 #pragma unroll
@@ -58,7 +55,7 @@ __device__ inline void pull(const T* __restrict__ A, const uint8_t* __restrict__
     for (int i = 0; i < Q; ++i) {
       size_t src = (size_t)i * N + (size_t)(c + nb.off(-cx(i), -cy(i), -cz(i)));
       size_t ref = (size_t)opp(i) * N + (size_t)c;
-      f[i] = __builtin_nontemporal_load(&A[(sf[i] & F_SOLID) ? ref : src]);
+      f[i] = A[(sf[i] & F_SOLID) ? ref : src];
     }
   }
 }

@@ -489,13 +489,15 @@ void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, c
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, nrep);
-  if (noise && !ov.on) {
-    long nk = (long)n_sub * nslots;
-    hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, d, nslots, n_sub);
-  }
+  if (noise > 0 && !ov.on) launch_md_noise(d, nslots, n_sub, s);
   hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov);
   for (int k = 0; k < n_sub; ++k)
     hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, d, ov, nslots, k, k == n_sub - 1 ? 1 : 0);
+}
+
+void launch_md_noise(const Dev& d, int nslots, int n_sub, hipStream_t s) {
+  long nk = (long)n_sub * nslots;
+  if (nk > 0) hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, d, nslots, n_sub);
 }
 
 void launch_zero_v(const Dev& d, int nslots, hipStream_t s) {

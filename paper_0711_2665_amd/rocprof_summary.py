@@ -52,11 +52,14 @@ def trace(a):
                      f"{e[1] / 1e6:.3f} | {100 * e[1] / total:.2f} |")
     if a.kernel:
         sel = [r for r in rows if a.kernel in short(r[0])]
+        if a.skip_last:
+            sel = sel[:-a.skip_last]
         if a.last:
             sel = sel[-a.last:]
         d = [r[3] for r in sel]
         if d:
-            lines += ["", f"Last {len(d)} dispatches of `{a.kernel}` (the timed region): "
+            lines += ["", f"{len(d)} dispatches of `{a.kernel}` in the timed region"
+                      f"{f' (the last {a.skip_last} dispatches, later in the run, excluded)' if a.skip_last else ''}: "
                       f"mean {sum(d) / len(d) / 1e3:.2f} us, min {min(d) / 1e3:.2f} us, max {max(d) / 1e3:.2f} us, "
                       f"grid {sel[-1][4]} x workgroup {sel[-1][5]}."]
     with open(a.out, "w") as fh:
@@ -117,6 +120,7 @@ def main():
     t.add_argument("--title", default="")
     t.add_argument("--kernel", default="")
     t.add_argument("--last", type=int, default=0)
+    t.add_argument("--skip-last", type=int, default=0)
     c = sub.add_parser("counters")
     c.add_argument("--fetch-db", required=True)
     c.add_argument("--write-db", required=True)
