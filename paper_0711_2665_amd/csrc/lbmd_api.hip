@@ -83,7 +83,7 @@ Packing packing(const lb_desc* d, int nrep) {
 
 struct WorkLayout {
   size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
-      tX, notdone, chead, cnext;
+      tX, notdone, ccount, cbuf;
   size_t nbuckets;
   size_t total;
 };
@@ -115,8 +115,8 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   w.notdone = take(sizeof(uint32_t) * R);
   w.nbuckets = 64;
   while (w.nbuckets < 2 * ns) w.nbuckets *= 2;
-  w.chead = take(sizeof(int) * w.nbuckets);
-  w.cnext = take(sizeof(int) * ns);
+  w.ccount = take(sizeof(int) * w.nbuckets);
+  w.cbuf = take(sizeof(int) * CELL_CAP * w.nbuckets);
   w.total = o;
   return w;
 }
@@ -410,7 +410,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   // long chains: the lists of this step were built at the end of the
   // previous one (when the sweep is normally done), unless the positions
   // changed since
-  if (c->step_lists && c->lists_stale) launch_nbr_build(D, c->nslots, sb);
+  if (c->step_lists && c->lists_stale) launch_nbr_build(D, c->nslots, c->nrep, sb);
   if (c->dev) launch_gather<float, true>(A, D, c->nslots, sb);
   else launch_gather<double, false>(A, D, c->nslots, sb);
   MdOverride none{};
@@ -419,7 +419,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
   if (c->step_lists) {
-    launch_nbr_build(D, c->nslots, sb);      // from r(n+1), for the next step
+    launch_nbr_build(D, c->nslots, c->nrep, sb);      // from r(n+1), for the next step
     c->lists_stale = false;
   }
   prof_mark(c, 1, sb);
@@ -671,8 +671,8 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   D.part = (double*)(w + c->wl.part);
   D.tX = (int64_t*)(w + c->wl.tX);
   D.notdone = (uint32_t*)(w + c->wl.notdone);
-  D.chead = (int*)(w + c->wl.chead);
-  D.cnext = (int*)(w + c->wl.cnext);
+  D.ccount = (int*)(w + c->wl.ccount);
+  D.cbuf = (int*)(w + c->wl.cbuf);
   D.cmask = (uint32_t)(c->wl.nbuckets - 1);
   D.ctrl = (Ctrl*)(w + c->wl.ctrl);
 

@@ -25,6 +25,7 @@ constexpr int NOBS = 23;                     // observables per replica
 constexpr int MAX_REPLICAS = 1024;
 constexpr int TILE_MIN = 256;                // smallest sweep tile (nodes)
 constexpr int OBS_TILE = 4096;               // nodes per fluid-reduction tile
+constexpr int CELL_CAP = 32;                 // beads per bucket of the neighbour-search table
 
 struct LbParams {
   int nx, ny, nz, nxy, N;
@@ -85,8 +86,8 @@ struct Dev {
   uint32_t* notdone;// per replica: some bead still on the cis side this step
   double* mdtape;   // when set: per sub-step s and bead p, r_mid and v at the start,
                     // [s][p][2][3] (recorded for the adjoint, one replica)
-  int* chead;       // neighbour search: bucket heads of the hashed cell table
-  int* cnext;       // per slot: next bead in the same bucket
+  int* ccount;      // neighbour search: beads per bucket of the hashed cell table
+  int* cbuf;        // [buckets][CELL_CAP] bead slots of each bucket
   uint32_t cmask;   // buckets - 1 (a power of two minus one)
   Ctrl* ctrl;
 };
@@ -147,7 +148,7 @@ void launch_md_noise(const Dev& d, int nslots, int n_sub, hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);
 // Verlet lists of every bead from a hashed cell list of the current
 // positions (once per coupled step); marks the lists valid.
-void launch_nbr_build(const Dev& d, int nslots, hipStream_t s);
+void launch_nbr_build(const Dev& d, int nslots, int nrep, hipStream_t s);
 void launch_zero_v(const Dev& d, int nslots, hipStream_t s);
 
 }  // namespace lbmd

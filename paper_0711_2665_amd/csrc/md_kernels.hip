@@ -89,25 +89,16 @@ __global__ void k_md_noise(Dev d, int nslots, int n_sub) {
   d.xi[3 * k] = x[0]; d.xi[3 * k + 1] = x[1]; d.xi[3 * k + 2] = x[2];
 }
 
-// Bending forces of the angles centred at chain indices q = q0 .. q0 + nq - 1
-// (those with 1 <= q <= nb - 2), one angle per thread, into LDS:
-// ang[q - q0][0..2] force on q-1, [3..5] on q, [6..8] on q+1.  rin points at
-// the chain's first slot.  Each angle is evaluated once and read by its three
-// beads; the values are those a per-bead evaluation gives.
-__device__ inline void angles_to_lds(const double* __restrict__ rin, const MdParams& P, int q0, int nq,
-                                     double (*ang)[9]) {
-  for (int k = threadIdx.x; k < nq; k += blockDim.x) {
-    int q = q0 + k;
-    if (q < 1 || q > P.nb - 2) continue;
-    const double* ra = &rin[3 * (q - 1)];
-    const double* rb = &rin[3 * q];
-    const double* rc = &rin[3 * (q + 1)];
-    double Fm[3] = {0.0, 0.0, 0.0}, F0[3] = {0.0, 0.0, 0.0}, Fp[3] = {0.0, 0.0, 0.0};
-    angle_add(P, ra, rb, rc, 0, Fm);
-    angle_add(P, ra, rb, rc, 1, F0);
-    angle_add(P, ra, rb, rc, 2, Fp);
-    for (int a = 0; a < 3; ++a) { ang[k][a] = Fm[a]; ang[k][3 + a] = F0[a]; ang[k][6 + a] = Fp[a]; }
-  }
+// Bending forces of the angle at (ra, rb, rc): out[0..2] the force on the
+// first bead, [3..5] on the centre, [6..8] on the third -- the values a
+// per-bead evaluation gives.
+__device__ inline void angle_forces(const MdParams& P, const double* ra, const double* rb, const double* rc,
+                                    double* out) {
+  double Fm[3] = {0.0, 0.0, 0.0}, F0[3] = {0.0, 0.0, 0.0}, Fp[3] = {0.0, 0.0, 0.0};
+  angle_add(P, ra, rb, rc, 0, Fm);
+  angle_add(P, ra, rb, rc, 1, F0);
+  angle_add(P, ra, rb, rc, 2, Fp);
+  for (int a = 0; a < 3; ++a) { out[a] = Fm[a]; out[3 + a] = F0[a]; out[6 + a] = Fp[a]; }
 }
 
 // ---------------------------------------------------------------------------
@@ -125,7 +116,7 @@ constexpr int MAXWALL = 16;                  // solid sites within r_c of a bead
 constexpr int NB_PER_LANE = MAXNBR / MD_LANES;
 
 struct MdShared {
-  double ang[MD_BPB + 2][9];                 // angle forces (see angles_to_lds)
+  double ang[MD_BPB + 2][9];                 // forces of the angles centred at p0-1 .. p0+16 (angle_forces)
   double pairF[MD_BPB][MAXNBR][3];           // LJ pair force of list entry k
   uint32_t hit[MD_BPB][MD_LANES];            // lane l, bit m: entry l + 4m is within r_c
   double wallF[MD_BPB][MAXWALL][3];
@@ -188,6 +179,43 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   const int t = threadIdx.x;
   const int bslot = t / MD_LANES, lane = t % MD_LANES;
   const int slot0 = blockIdx.x * MD_BPB;
+  const int slot = slot0 + bslot;            // the grid covers the nslots slots exactly
+  const double* rabs = (s & 1) ? d.rmid1 : d.rmid0;
+  double* rout = (s & 1) ? d.rmid0 : d.rmid1;
+
+  // ---- first-level loads, addressed by slot alone so that they are in
+  // flight before the replica's parameters arrive.  Indices are clamped into
+  // the slot range; a value from outside the chain is never used.
+  auto clampslot = [nslots](int q) { return q < 0 ? 0 : (q >= nslots ? nslots - 1 : q); };
+  double rp[3] = {rabs[3 * slot], rabs[3 * slot + 1], rabs[3 * slot + 2]};
+  int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
+  const int ncnt_in = d.ncnt[slot];
+  int pre[NB_PER_LANE];                       // list entries lane, lane + 4, ... (past the length unused)
+#pragma unroll
+  for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = nbr_row[lane + MD_LANES * m];
+  // the bead's own state and its chain neighbours (every lane of the bead
+  // reads them; the lead lane uses them)
+  const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
+  double vo[3], Jo[3], ul[3], xl[3], rm[3], rq[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vo[a] = d.v[3 * slot + a];
+    Jo[a] = d.J[3 * slot + a];
+    ul[a] = d.up[3 * slot + a];
+    xl[a] = ov.on ? 0.0 : d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
+    rm[a] = rabs[3 * sm + a];
+    rq[a] = rabs[3 * sq + a];
+  }
+  // positions of the angle centred at slot slot0 - 1 + t (threads t < 18)
+  double ra[3] = {0.0, 0.0, 0.0}, rb3[3] = {0.0, 0.0, 0.0}, rc[3] = {0.0, 0.0, 0.0};
+  if (t < MD_BPB + 2) {
+    const int c = slot0 - 1 + t;
+    const int ia = clampslot(c - 1), ib = clampslot(c), ic = clampslot(c + 1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { ra[a] = rabs[3 * ia + a]; rb3[a] = rabs[3 * ib + a]; rc[a] = rabs[3 * ic + a]; }
+  }
+
+  // ---- the replica
   const int rep = d.slot_rep[slot0];
   const Rep& R = d.reps[rep];
   const MdParams P = md_params(R, ov);
@@ -195,10 +223,8 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   const int so = R.slot_off;
   const int p0 = slot0 - so;                 // chain index of the first bead here
   const int p = p0 + bslot;
-  const int slot = slot0 + bslot;
   const bool active = p < P.nb;
-  const double* rin = ((s & 1) ? d.rmid1 : d.rmid0) + 3 * (size_t)so;   // chain-relative
-  double* rout = (s & 1) ? d.rmid0 : d.rmid1;
+  const double* rin = rabs + 3 * (size_t)so; // chain-relative
   uint32_t* rbr = d.rb + 4 * rep;
   const uint32_t rebuild = rbr[s % 3];
   if (t == 0) {
@@ -206,35 +232,17 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
       rbr[(s + 2) % 3] = 0u;
       if (rebuild) atomicAdd((unsigned long long*)&d.ctrl->rebuilds, 1ull);
     }
-    if (blockIdx.x == 0) d.ctrl->substeps += 1;
+    if (blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, 1ull);
   }
-  double rp[3] = {0.0, 0.0, 0.0};
-  if (active) { rp[0] = rin[3 * p]; rp[1] = rin[3 * p + 1]; rp[2] = rin[3 * p + 2]; }
-  // lane 0 issues every load it needs later before the first barrier
   const bool lead = active && lane == 0;
-  double vo[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0}, Jo[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
-  double rm[3] = {0.0, 0.0, 0.0}, rq[3] = {0.0, 0.0, 0.0};
-  // every lane: the list length and its share of the list (entries lane,
-  // lane + 4, ...), issued with the other first-level loads; entries past the
-  // length are never used
-  int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
-  const int ncnt0 = active ? d.ncnt[slot] : 0;
-  int pre[NB_PER_LANE];
+  double u[3], xi[3];
 #pragma unroll
-  for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = active ? nbr_row[lane + MD_LANES * m] : -1;
-  if (lead) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      vo[a] = d.v[3 * slot + a];
-      Jo[a] = d.J[3 * slot + a];
-      u[a] = P.couple ? d.up[3 * slot + a] : 0.0;
-      if (P.sig != 0.0) xi[a] = d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
-      if (p > 0) rm[a] = rin[3 * (p - 1) + a];
-      if (p < P.nb - 1) rq[a] = rin[3 * (p + 1) + a];
-    }
+  for (int a = 0; a < 3; ++a) {
+    u[a] = P.couple ? ul[a] : 0.0;
+    xi[a] = P.sig != 0.0 ? xl[a] : 0.0;
   }
   if (t == 0) sh.over = 0;
-  angles_to_lds(rin, P, p0 - 1, MD_BPB + 2, sh.ang);
+  const int ncnt0 = active ? ncnt_in : 0;
 
   // ---- neighbour list: reuse (already in registers), or rebuild by
   // scanning the chain in tiles of 64
@@ -301,8 +309,13 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
     double q[NB_PER_LANE][3];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) {
-      if (jl[m] >= 0) { q[m][0] = rin[3 * jl[m]]; q[m][1] = rin[3 * jl[m] + 1]; q[m][2] = rin[3 * jl[m] + 2]; }
-      else { q[m][0] = 0.0; q[m][1] = 0.0; q[m][2] = 0.0; }
+      const int j = jl[m] >= 0 ? jl[m] : p0;   // an unused entry reads a valid slot
+      q[m][0] = rin[3 * j]; q[m][1] = rin[3 * j + 1]; q[m][2] = rin[3 * j + 2];
+    }
+    // the angles while the partner positions are in flight
+    if (t < MD_BPB + 2) {
+      const int qc = p0 - 1 + t;
+      if (qc >= 1 && qc <= P.nb - 2) angle_forces(P, ra, rb3, rc, sh.ang[t]);
     }
     uint32_t hit = 0;
 #pragma unroll
@@ -382,12 +395,15 @@ __global__ void k_zero_v(double* v, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour lists from a hashed cell list, once per coupled step.  Cells of
-// side >= r_c + skin per replica; a cell's beads are linked in one bucket of
-// a power-of-two table (colliding cells share a bucket: their beads fail the
-// distance test or are counted once).  Each bead scans its 27 neighbour
-// cells and keeps every other bead of its chain within r_c + skin in
-// ascending chain order -- the list the in-kernel scan would build.
+// Neighbour lists from a hashed cell table, once per coupled step.  Cells of
+// side >= r_c + skin per replica; each cell hashes to one bucket of a
+// power-of-two table of fixed-capacity buckets (colliding cells share a
+// bucket: their beads fail the distance test).  Each bead is examined by 32
+// lanes, one per distinct bucket of its 27 neighbour cells; the lanes collect
+// the other beads of its chain within r_c + skin, and one lane sorts them
+// into ascending chain order -- the list the in-kernel scan would build.  A
+// bucket that overflows leaves its replica's lists marked invalid, so the
+// first sub-step rebuilds them in-kernel: the same lists, found slower.
 // ---------------------------------------------------------------------------
 __device__ inline uint32_t cell_bucket(int rep, int cx, int cy, int cz, uint32_t mask) {
   uint32_t h = ((uint32_t)rep * 73856093u) ^ ((uint32_t)cx * 19349663u) ^ ((uint32_t)cy * 83492791u) ^
@@ -405,9 +421,10 @@ __device__ inline void bead_cell(const Rep& R, const double* rp, int c[3]) {
   }
 }
 
-__global__ void k_cell_clear(int* __restrict__ chead, int nbuckets) {
+__global__ void k_cell_clear(int* __restrict__ ccount, int nbuckets, uint32_t* __restrict__ rb, int nrep) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nbuckets) chead[k] = -1;
+  if (k < nbuckets) ccount[k] = 0;
+  if (k < nrep) rb[4 * k + 3] = 0u;          // valid unless a bucket overflows below
 }
 
 __global__ void k_cell_insert(Dev d, int nslots) {
@@ -418,66 +435,94 @@ __global__ void k_cell_insert(Dev d, int nslots) {
   if (slot - R.slot_off >= R.mp.nb) return;
   int c[3];
   bead_cell(R, &d.r[3 * slot], c);
-  d.cnext[slot] = atomicExch(&d.chead[cell_bucket(rep, c[0], c[1], c[2], d.cmask)], slot);
+  const uint32_t b = cell_bucket(rep, c[0], c[1], c[2], d.cmask);
+  const int pos = atomicAdd(&d.ccount[b], 1);
+  if (pos < CELL_CAP) d.cbuf[(size_t)b * CELL_CAP + pos] = slot;
 }
 
-__global__ void k_list_build(Dev d, int nslots) {
-  int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
-  const int rep = d.slot_rep[slot];
-  const Rep& R = d.reps[rep];
-  const int so = R.slot_off;
-  const int p = slot - so;
-  if (p >= R.mp.nb) return;
-  const Geom& g = R.g;
-  const double rp[3] = {d.r[3 * slot], d.r[3 * slot + 1], d.r[3 * slot + 2]};
-  int c[3];
-  bead_cell(R, rp, c);
-  int lst[MAXNBR];
-  int cnt = 0;
-  bool over = false;
-  for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = (c[0] + dx + R.ncell[0]) % R.ncell[0];
-        const int cy = (c[1] + dy + R.ncell[1]) % R.ncell[1];
-        const int cz = (c[2] + dz + R.ncell[2]) % R.ncell[2];
-        for (int q = d.chead[cell_bucket(rep, cx, cy, cz, d.cmask)]; q >= 0; q = d.cnext[q]) {
-          if (d.slot_rep[q] != rep) continue;
-          const int j = q - so;
-          if (j == p) continue;
-          double d0 = min_image(rp[0] - d.r[3 * q], g.nx);
-          double d1 = min_image(rp[1] - d.r[3 * q + 1], g.ny);
-          double d2 = min_image(rp[2] - d.r[3 * q + 2], g.nz);
-          if (!(d0 * d0 + d1 * d1 + d2 * d2 < R.mp.rlist2)) continue;
-          // sorted insert, each bead once, the MAXNBR smallest kept
-          int k = cnt;
-          while (k > 0 && lst[k - 1] > j) --k;
-          if (k > 0 && lst[k - 1] == j) continue;
-          if (cnt == MAXNBR) {
-            over = true;
-            if (k == MAXNBR) continue;
-            --cnt;
-          }
-          for (int m = cnt; m > k; --m) lst[m] = lst[m - 1];
-          lst[k] = j;
-          ++cnt;
-        }
-      }
-  if (over) atomicOr(&d.ctrl->err, E_NBRLIST);
+constexpr int LB_LANES = 32;                 // lanes per bead in the list build (27 cells)
+constexpr int LB_BEADS = 2;                  // beads per 64-lane workgroup
+constexpr int LB_CAND = 96;                  // candidates a bead may collect
+
+__global__ __launch_bounds__(LB_LANES * LB_BEADS) void k_list_build(Dev d, int nslots) {
+  __shared__ int cand[LB_BEADS][LB_CAND];
+  __shared__ int ncand[LB_BEADS];
+  __shared__ uint32_t bkt[LB_BEADS][LB_LANES];
+  const int lb = threadIdx.x / LB_LANES, lane = threadIdx.x % LB_LANES;
+  const int slot = blockIdx.x * LB_BEADS + lb;
+  bool on = slot < nslots;
+  int rep = 0, so = 0, p = 0;
+  if (on) {
+    rep = d.slot_rep[slot];
+    so = d.reps[rep].slot_off;
+    p = slot - so;
+    on = p < d.reps[rep].mp.nb;
+  }
+  double rp[3] = {0.0, 0.0, 0.0};
+  uint32_t b = 0xffffffffu;
+  if (on) {
+    rp[0] = d.r[3 * slot]; rp[1] = d.r[3 * slot + 1]; rp[2] = d.r[3 * slot + 2];
+    if (lane < 27) {
+      const Rep& R = d.reps[rep];
+      int c[3];
+      bead_cell(R, rp, c);
+      const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+      b = cell_bucket(rep, (c[0] + dx + R.ncell[0]) % R.ncell[0], (c[1] + dy + R.ncell[1]) % R.ncell[1],
+                      (c[2] + dz + R.ncell[2]) % R.ncell[2], d.cmask);
+    }
+  }
+  bkt[lb][lane] = b;
+  if (lane == 0) ncand[lb] = 0;
+  __syncthreads();
+  // a bucket reached from several neighbour cells (wrapped small cell counts,
+  // hash collisions) is scanned by its lowest lane only: every candidate once
+  bool scan = b != 0xffffffffu;
+  for (int k = 0; k < lane && scan; ++k) scan = bkt[lb][k] != b;
+  if (scan) {
+    const Geom& g = d.reps[rep].g;
+    const double rl2 = d.reps[rep].mp.rlist2;
+    const int cnt = d.ccount[b];
+    if (cnt > CELL_CAP) d.rb[4 * rep + 3] = 1u;   // incomplete bucket: rebuild in-kernel
+    const int n = min(cnt, CELL_CAP);
+    for (int k = 0; k < n; ++k) {
+      const int q = d.cbuf[(size_t)b * CELL_CAP + k];
+      if (d.slot_rep[q] != rep || q == slot) continue;
+      double d0 = min_image(rp[0] - d.r[3 * q], g.nx);
+      double d1 = min_image(rp[1] - d.r[3 * q + 1], g.ny);
+      double d2 = min_image(rp[2] - d.r[3 * q + 2], g.nz);
+      if (!(d0 * d0 + d1 * d1 + d2 * d2 < rl2)) continue;
+      const int at = atomicAdd(&ncand[lb], 1);
+      if (at < LB_CAND) cand[lb][at] = q - so;
+    }
+  }
+  __syncthreads();
+  if (!on || lane != 0) return;
+  // ascending chain order, the MAXNBR smallest kept
+  int nc = ncand[lb];
+  if (nc > MAXNBR) atomicOr(&d.ctrl->err, E_NBRLIST);
+  if (nc > LB_CAND) nc = LB_CAND;
+  int* c = cand[lb];
+  for (int i = 1; i < nc; ++i) {
+    const int v = c[i];
+    int m = i;
+    while (m > 0 && c[m - 1] > v) { c[m] = c[m - 1]; --m; }
+    c[m] = v;
+  }
+  if (nc > MAXNBR) nc = MAXNBR;
   int* row = d.nbr + (size_t)slot * MAXNBR;
-  for (int k = 0; k < cnt; ++k) row[k] = lst[k];
-  d.ncnt[slot] = cnt;
+  for (int i = 0; i < nc; ++i) row[i] = c[i];
+  d.ncnt[slot] = nc;
   d.ref[3 * slot] = rp[0]; d.ref[3 * slot + 1] = rp[1]; d.ref[3 * slot + 2] = rp[2];
-  if (p == 0) d.rb[4 * rep + 3] = 0u;      // the lists are valid
 }
 
-void launch_nbr_build(const Dev& d, int nslots, hipStream_t s) {
+void launch_nbr_build(const Dev& d, int nslots, int nrep, hipStream_t s) {
   if (nslots <= 0) return;
   const int nb = (int)d.cmask + 1;
-  hipLaunchKernelGGL(k_cell_clear, dim3((nb + 255) / 256), dim3(256), 0, s, d.chead, nb);
+  const int nclr = nb > nrep ? nb : nrep;
+  hipLaunchKernelGGL(k_cell_clear, dim3((nclr + 255) / 256), dim3(256), 0, s, d.ccount, nb, d.rb, nrep);
   hipLaunchKernelGGL(k_cell_insert, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots);
-  hipLaunchKernelGGL(k_list_build, dim3((nslots + 63) / 64), dim3(64), 0, s, d, nslots);
+  hipLaunchKernelGGL(k_list_build, dim3((nslots + LB_BEADS - 1) / LB_BEADS), dim3(LB_LANES * LB_BEADS), 0, s, d,
+                     nslots);
 }
 
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {
