@@ -196,19 +196,43 @@ int lb_ensemble_translocation(lb_ctx* ctx, int64_t* out_host);
  * replica per tile; order 0 lists tiles replica by replica, order 1 deals
  * them into 8 contiguous chunks interleaved so that neighbouring tiles run on
  * one XCD; grid 0 launches one workgroup per tile, grid > 0 that many
- * workgroups striding over the tiles.  Results do not depend on it.
- * Synchronises the stream (uploads the tile table). */
-int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid);
+ * workgroups striding over the tiles.  A thread updates tile_nodes / 256
+ * nodes of a tile (at most 4 per pass, their loads issued together).  cap 0
+ * leaves the occupancy to the hardware; cap in [2, 8] lets at most cap sweep
+ * workgroups share a CU (each reserves LDS it does not use), which leaves
+ * the rest of the CU to the bead phase running beside the sweep.  Results do
+ * not depend on the layout.  Synchronises the stream (uploads the tile
+ * table).  LB_ERR_ARG: order not 0 or 1, grid < 0, cap outside {0, 2..8},
+ * tile_nodes not a positive multiple of 256. */
+int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid, int cap);
 
 /* Autotuner of the sweep layout: times `reps` sweeps of every candidate
- * layout (tile sizes 256..2048, both orders, two persistent grids) with HIP
- * events, from the current populations into the other array (which the
- * next step overwrites, so the state is unchanged), keeps the first
- * candidate within 1% of the fastest and caches it for the process by
- * (replica extents and walls, precision).
- * Writes {tile_nodes, order, grid} to out_cfg[3] and the mean sweep time in
- * ms to *out_ms (-1 when taken from the cache).  Synchronises the stream. */
+ * layout (tile sizes 256..2048 in both orders; persistent grids of 512,
+ * 1024 and 2048 workgroups over tiles of 256 and 512 nodes; tiles of 256,
+ * 512 and 1024 nodes capped at 2, 3 or 4 workgroups per CU) with HIP events,
+ * from the current populations into the other array (which the next step
+ * overwrites, so the state is unchanged), keeps the first candidate within
+ * 1% of the fastest and caches it for the process by (replica extents,
+ * walls and chain lengths, precision).
+ * Writes {tile_nodes, order, grid, cap} to out_cfg[4] and the mean sweep
+ * time in ms to *out_ms (-1 when taken from the cache).  With the
+ * environment variable LBMD_AUTOTUNE_LOG set, every candidate's time is
+ * printed to stderr.  Synchronises the stream.
+ * LB_ERR_ARG: reps < 1; LB_ERR_DEVICE: a HIP call failed. */
 int lb_autotune(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
+
+/* As lb_autotune, choosing the layout by the whole coupled step instead of
+ * the sweep alone (the sweep shares the memory system with the bead phase
+ * that runs beside it): per candidate, 2 ceil(reps / 2) coupled steps
+ * replayed from the two-step graph are timed.  The complete device state
+ * (current populations, beads, work area, force field) is copied to a
+ * temporary device buffer first (hipMalloc'd here, about pops_bytes +
+ * force_bytes + beads_bytes + work_bytes) and restored after every
+ * candidate, with the step count: the state and every later result are
+ * unchanged.  *out_ms is the mean coupled-step time (-1 when cached).
+ * Synchronises the stream.  LB_ERR_ARG: reps < 1; LB_ERR_DEVICE: a HIP call
+ * failed (the state is restored when the snapshot exists). */
+int lb_autotune_step(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
 
 /* Sets the friction rate gamma (>= 0) and the pore force F_drive of
  * replica rep and recomputes its SPV coefficients (e = exp(-gamma h), the
@@ -298,10 +322,12 @@ int64_t lb_step_count(lb_ctx* ctx);
 int lb_profile_start(lb_ctx* ctx, int max_steps);
 int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* nsteps);
 
-/* Diagnostics: synchronises the stream and writes six int64: out[0] =
- * neighbour-list rebuilds (summed over replicas), out[1] = MD sub-step
- * launches, out[2] = tiles of the sweep, out[3] = watchdog bits, out[4] = LB
- * steps taken, out[5] = nodes that carried bead force, summed over steps. */
+/* Diagnostics: synchronises the stream and writes seven int64: out[0] =
+ * neighbour-list rebuilds inside sub-cycles (summed over replicas), out[1] =
+ * MD sub-step launches, out[2] = tiles of the sweep, out[3] = watchdog bits,
+ * out[4] = LB steps taken, out[5] = nodes that carried bead force, summed
+ * over steps, out[6] = the rebuilds of out[0] that searched the cell table
+ * (the others scanned the whole chain). */
 int lb_diagnostics(lb_ctx* ctx, int64_t* out);
 
 /* Message of the last failed call on this thread (never NULL). */

@@ -34,24 +34,52 @@ __global__ void k_fill_f64(double* __restrict__ p, long n, double v) {
 // and so are nodes carrying a bead force when skip_forced is set (they are
 // updated by k_lb_forced once the force is known).
 // ---------------------------------------------------------------------------
-template <typename T, bool DEV>
-__global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B, Dev d, int ntiles,
-                                            int tile_nodes, int skip_forced) {
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const Tile tl = d.tiles[t];
-    const Rep& R = d.reps[tl.rep];
+template <typename T, bool DEV, int U>
+__global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B,
+                                            const Tile* __restrict__ tiles, const Rep* __restrict__ reps,
+                                            const uint8_t* __restrict__ flags, const T* __restrict__ force,
+                                            Ctrl* __restrict__ ctrl, int ntiles, int tile_nodes, int skip_forced) {
+  // The tile and replica tables are read-only arguments that alias nothing
+  // the sweep writes, so their workgroup-uniform reads become scalar loads;
+  // the next tile's record is requested before this tile's work.
+  int t = blockIdx.x;
+  if (t >= ntiles) return;
+  Tile tl = tiles[t];
+  for (;;) {
+    const int tn = t + (int)gridDim.x;
+    const Tile next = tiles[tn < ntiles ? tn : t];
+    const Rep& R = reps[tl.rep];
     const long no = R.node_off;
     const T* Ar = A + (size_t)Q * no;
     T* Br = B + (size_t)Q * no;
-    const uint8_t* fr = d.flags + no;
-    const T* Fr = (const T*)d.force + (size_t)3 * no;
+    const uint8_t* fr = flags + no;
+    const T* Fr = force + (size_t)3 * no;
     const int end = min(tl.start + tile_nodes, R.lp.N);
-    for (int c = tl.start + (int)threadIdx.x; c < end; c += blockDim.x) {
-      uint8_t fl = fr[c];
-      if (fl & F_SOLID) continue;
-      if (skip_forced && (fl & F_FORCED)) continue;
-      lb_node<T, DEV>(Ar, Br, fr, Fr, R.lp, d.ctrl, c, fl);
+    if (tl.near) {
+      // a tile touching the wall: one node per thread and pass, each pull
+      // with bounce-back
+      for (int c = tl.start + (int)threadIdx.x; c < end; c += 256) {
+        const uint8_t fl = fr[c];
+        if ((fl & F_SOLID) || (skip_forced && (fl & F_FORCED))) continue;
+        lb_node<T, DEV>(Ar, Br, fr, Fr, R.lp, ctrl, c, fl);
+      }
+    } else {
+      // U nodes per thread and pass, 256 apart, their loads issued together
+      for (int c0 = tl.start + (int)threadIdx.x; c0 < end; c0 += U * 256) {
+        int c[U];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int cu = c0 + u * 256;
+          in[u] = cu < end;
+          c[u] = in[u] ? cu : c0;           // past the tile: pull a valid node, store nothing
+        }
+        lb_nodes_bulk<T, DEV, U>(Ar, Br, fr, Fr, R.lp, ctrl, c, in, skip_forced);
+      }
     }
+    if (tn >= ntiles) break;
+    t = tn;
+    tl = next;
   }
 }
 
@@ -441,11 +469,22 @@ void launch_fill_f64(double* p, long n, double v, hipStream_t s) {
 }
 
 template <typename T, bool DEV>
-void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int skip_forced,
+void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int cap, int skip_forced,
                hipStream_t s) {
   int gsz = (grid > 0 && grid < ntiles) ? grid : ntiles;
-  hipLaunchKernelGGL((k_lb<T, DEV>), dim3((unsigned)gsz), dim3(256), 0, s, (const T*)A, (T*)B, d, ntiles, tile_nodes,
-                     skip_forced);
+  const int per = tile_nodes / 256;         // nodes per thread and tile
+  // LDS the kernel does not use, reserved so that at most `cap` sweep
+  // workgroups share a CU
+  const size_t lds = cap > 0 ? (size_t)((LDS_PER_CU - LDS_KEEP) / cap) & ~(size_t)1023 : 0;
+  if (per >= 4)
+    hipLaunchKernelGGL((k_lb<T, DEV, 4>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles, d.reps,
+                       d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
+  else if (per >= 2)
+    hipLaunchKernelGGL((k_lb<T, DEV, 2>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles, d.reps,
+                       d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
+  else
+    hipLaunchKernelGGL((k_lb<T, DEV, 1>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles, d.reps,
+                       d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
 }
 
 template <typename T, bool DEV>
@@ -492,8 +531,8 @@ void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, dou
 
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);
 template void launch_fill_rest<float, true>(void*, long, hipStream_t);
-template void launch_lb<double, false>(const void*, void*, const Dev&, int, int, int, int, hipStream_t);
-template void launch_lb<float, true>(const void*, void*, const Dev&, int, int, int, int, hipStream_t);
+template void launch_lb<double, false>(const void*, void*, const Dev&, int, int, int, int, int, hipStream_t);
+template void launch_lb<float, true>(const void*, void*, const Dev&, int, int, int, int, int, hipStream_t);
 template void launch_lb_forced<double, false>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_lb_forced<float, true>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_gather<double, false>(const void*, const Dev&, int, hipStream_t);

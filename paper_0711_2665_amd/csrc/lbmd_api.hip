@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -83,7 +84,7 @@ Packing packing(const lb_desc* d, int nrep) {
 
 struct WorkLayout {
   size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
-      tX, notdone, ccount, cbuf;
+      tX, notdone, ccount, cbuf, rbin, cst;
   size_t nbuckets;
   size_t total;
 };
@@ -117,6 +118,8 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   while (w.nbuckets < 2 * ns) w.nbuckets *= 2;
   w.ccount = take(sizeof(int) * w.nbuckets);
   w.cbuf = take(sizeof(int) * CELL_CAP * w.nbuckets);
+  w.rbin = take(sizeof(double) * 3 * ns);
+  w.cst = take(sizeof(uint32_t) * 4 * R);
   w.total = o;
   return w;
 }
@@ -263,6 +266,7 @@ struct SweepCfg {
   int tile_nodes = TILE_MIN;
   int order = 0;      // 0: replica-major; 1: XCD-chunked (see tile_table)
   int grid = 0;       // 0: one workgroup per tile; else persistent grid-stride
+  int cap = 0;        // 0, or at most this many sweep workgroups per CU (LDS reserved)
 };
 
 struct lb_ctx {
@@ -285,6 +289,7 @@ struct lb_ctx {
   bool any_noise = false;
   SweepCfg sweep;
   int ntiles = 0;
+  std::vector<std::vector<uint8_t>> near_blocks;   // per replica and TILE_MIN nodes: solid or wall-adjacent
   int64_t steps = 0;
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
@@ -320,8 +325,13 @@ void* other_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_b : c->b.pops_a; }
 std::vector<Tile> tile_table(const lb_ctx* c, const SweepCfg& sc) {
   std::vector<Tile> t;
   for (int r = 0; r < c->nrep; ++r) {
-    int N = c->reps[r].lp.N;
-    for (int st = 0; st < N; st += sc.tile_nodes) t.push_back(Tile{r, st});
+    const int N = c->reps[r].lp.N;
+    const std::vector<uint8_t>& nb = c->near_blocks[r];
+    for (int st = 0; st < N; st += sc.tile_nodes) {
+      int near = 0;
+      for (int b = st / TILE_MIN; b < (st + sc.tile_nodes) / TILE_MIN && b < (int)nb.size(); ++b) near |= nb[b];
+      t.push_back(Tile{r, st, near});
+    }
   }
   if (sc.order == 1 && t.size() >= 16) {
     const size_t n = t.size(), nch = 8, per = (n + nch - 1) / nch;
@@ -362,9 +372,9 @@ void prof_next(lb_ctx* c) {
 
 void sweep_ab(lb_ctx* c, const void* A, void* B, int skip_forced, hipStream_t st) {
   if (c->dev)
-    launch_lb<float, true>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, skip_forced, st);
+    launch_lb<float, true>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, c->sweep.cap, skip_forced, st);
   else
-    launch_lb<double, false>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, skip_forced, st);
+    launch_lb<double, false>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, c->sweep.cap, skip_forced, st);
 }
 void sweep(lb_ctx* c, int skip_forced, hipStream_t st) { sweep_ab(c, cur_pops(c), other_pops(c), skip_forced, st); }
 
@@ -617,6 +627,7 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   std::vector<int> slot_rep(ns, 0);
   std::vector<Tile> ot;
   c->reps.resize(nrep);
+  c->near_blocks.resize(nrep);
   for (int r = 0; r < nrep; ++r) {
     Rep& R = c->reps[r];
     std::memset(&R, 0, sizeof(Rep));
@@ -635,14 +646,19 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     R.nfluid = (double)build_flags(R.g, fl.data() + R.node_off);
     {
       const int n[3] = {d[r].nx, d[r].ny, d[r].nz};
-      const double side = d[r].rc + skin;
+      const double side = d[r].rc + skin + CELL_MARGIN;
       for (int a = 0; a < 3; ++a) {
         int k = (int)std::floor((double)n[a] / side);
         R.ncell[a] = k < 1 ? 1 : k;
       }
     }
     R.tile_begin = (int)ot.size();
-    for (int st = 0; st < R.lp.N; st += OBS_TILE) ot.push_back(Tile{r, st});
+    for (int st = 0; st < R.lp.N; st += OBS_TILE) ot.push_back(Tile{r, st, 0});
+    // per TILE_MIN nodes: whether any is solid or next to a solid node
+    std::vector<uint8_t>& nbk = c->near_blocks[r];
+    nbk.assign((size_t)((R.lp.N + TILE_MIN - 1) / TILE_MIN), 0);
+    for (long k = 0; k < R.lp.N; ++k)
+      if (fl[(size_t)(R.node_off + k)] & (F_SOLID | F_NEAR)) nbk[(size_t)(k / TILE_MIN)] = 1;
     R.tile_end = (int)ot.size();
   }
 
@@ -673,6 +689,8 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   D.notdone = (uint32_t*)(w + c->wl.notdone);
   D.ccount = (int*)(w + c->wl.ccount);
   D.cbuf = (int*)(w + c->wl.cbuf);
+  D.rbin = (double*)(w + c->wl.rbin);
+  D.cst = (uint32_t*)(w + c->wl.cst);
   D.cmask = (uint32_t)(c->wl.nbuckets - 1);
   D.ctrl = (Ctrl*)(w + c->wl.ctrl);
 
@@ -695,6 +713,8 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   acc(hipMemsetAsync(D.ctrl, 0, sizeof(Ctrl), s));
   launch_fill_i32(D.head, nodes, -1, s);
   launch_fill_f64(D.ref, 3L * (long)ns, 1e300, s);
+  launch_fill_f64(D.rbin, 3L * (long)ns, 1e300, s);
+  acc(hipMemsetAsync(D.cst, 0, sizeof(uint32_t) * 4 * nrep, s));
   acc(hipMemsetAsync(D.ncnt, 0, sizeof(int) * ns, s));
   acc(hipMemsetAsync(D.rb, 0, sizeof(uint32_t) * 4 * nrep, s));
   acc(hipMemsetAsync(D.notdone, 0, sizeof(uint32_t) * nrep, s));
@@ -937,6 +957,7 @@ int lb_diagnostics(lb_ctx* c, int64_t* out) {
   out[3] = (int64_t)h.err;
   out[4] = (int64_t)h.step;
   out[5] = (int64_t)h.forced_total;
+  out[6] = (int64_t)h.cell_rebuilds;
   return LB_OK;
 }
 
@@ -948,26 +969,98 @@ int lb_ensemble_translocation(lb_ctx* c, int64_t* out_host) {
   return LB_OK;
 }
 
-int lb_sweep_config(lb_ctx* c, int tile_nodes, int order, int grid) {
-  if (!c || order < 0 || order > 1 || grid < 0) return fail(LB_ERR_ARG, "bad arguments");
+int lb_sweep_config(lb_ctx* c, int tile_nodes, int order, int grid, int cap) {
+  if (!c || order < 0 || order > 1 || grid < 0 || !(cap == 0 || (cap >= SWEEP_CAP_MIN && cap <= SWEEP_CAP_MAX)))
+    return fail(LB_ERR_ARG, "bad arguments");
   SweepCfg sc;
   sc.tile_nodes = tile_nodes;
   sc.order = order;
   sc.grid = grid;
+  sc.cap = cap;
   int rc = upload_tiles(c, sc);
   if (rc) return rc;
   drop_graph(c);
   return LB_OK;
 }
 
-int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
+}  // extern "C"
+
+namespace {
+
+// Candidate sweep layouts: tile sizes 256..2048 in both orders; persistent
+// grids of 512..2048 workgroups over tiles of 256 and 512 nodes; and one
+// workgroup per tile of 256..1024 nodes with at most 2, 3 or 4 sweep
+// workgroups per CU.
+std::vector<SweepCfg> sweep_candidates() {
+  std::vector<SweepCfg> cand;
+  for (int tn : {256, 512, 1024, 2048})
+    for (int order : {0, 1}) cand.push_back(SweepCfg{tn, order, 0, 0});
+  for (int tn : {256, 512})
+    for (int g : {512, 1024, 2048}) cand.push_back(SweepCfg{tn, 0, g, 0});
+  for (int tn : {256, 512, 1024})
+    for (int cap : {2, 3, 4}) cand.push_back(SweepCfg{tn, 0, 0, cap});
+  return cand;
+}
+
+// Device copy of everything a coupled step reads or writes (current
+// populations, beads, work area, force field) and the host fields that
+// follow it, so that timed trial steps leave no trace.
+struct Snapshot {
+  char* mem = nullptr;
+  size_t pops = 0, beads = 0, work = 0, force = 0;
+  int cur = 0;
+  int64_t steps = 0;
+  bool lists_stale = true;
+};
+
+int snapshot_take(lb_ctx* c, Snapshot& S) {
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  S.pops = align256(es * Q * (size_t)c->pk.nodes);
+  S.beads = align256(sizeof(double) * 15 * (size_t)c->pk.slots_alloc);
+  S.work = align256(c->wl.total);
+  S.force = align256(es * 3 * (size_t)c->pk.nodes);
+  hipError_t e = hipMalloc((void**)&S.mem, S.pops + S.beads + S.work + S.force);
+  if (e != hipSuccess) { S.mem = nullptr; return fail(LB_ERR_DEVICE, "snapshot: %s", hipGetErrorString(e)); }
+  char* o = S.mem;
+  acc(hipMemcpyAsync(o, cur_pops(c), S.pops, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + S.pops, c->b.beads, S.beads, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + S.pops + S.beads, c->b.work, c->wl.total, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + S.pops + S.beads + S.work, c->b.force, es * 3 * (size_t)c->pk.nodes,
+                     hipMemcpyDeviceToDevice, c->s));
+  S.cur = c->cur;
+  S.steps = c->steps;
+  S.lists_stale = c->lists_stale;
+  return take_acc("snapshot");
+}
+
+void snapshot_restore(lb_ctx* c, const Snapshot& S) {
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  c->cur = S.cur;
+  c->steps = S.steps;
+  c->lists_stale = S.lists_stale;
+  const char* o = S.mem;
+  acc(hipMemcpyAsync(cur_pops(c), o, es * Q * (size_t)c->pk.nodes, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->b.beads, o + S.pops, sizeof(double) * 15 * (size_t)c->pk.slots_alloc,
+                     hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->b.work, o + S.pops + S.beads, c->wl.total, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->b.force, o + S.pops + S.beads + S.work, es * 3 * (size_t)c->pk.nodes,
+                     hipMemcpyDeviceToDevice, c->s));
+}
+
+// Times every candidate layout: `reps` sweeps from the current populations
+// into the other array, or (coupled) `reps` coupled steps replayed from the
+// two-step graph, from a snapshot restored after each candidate.  Keeps the
+// first candidate within 1% of the fastest (timing noise then does not flip
+// the choice between layouts that perform alike) and caches it per packing,
+// precision and mode.
+int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms) {
   if (!c || reps < 1) return fail(LB_ERR_ARG, "bad arguments");
-  // cached per packing (replica extents and walls) and precision
   static std::map<std::string, SweepCfg> cache;
-  std::string key = c->dev ? "f32:" : "f64:";
+  std::string key = coupled ? "step:" : "sweep:";
+  key += c->dev ? "f32:" : "f64:";
   for (const lb_desc& x : c->d) {
     char buf[96];
-    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d;", x.nx, x.ny, x.nz, x.wall_axis, x.wall_pos, x.pore_h);
+    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d;", x.nx, x.ny, x.nz, x.wall_axis, x.wall_pos, x.pore_h, x.nb);
     key += buf;
   }
   auto it = cache.find(key);
@@ -976,38 +1069,60 @@ int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
   if (it != cache.end()) {
     best = it->second;
   } else {
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
       return fail(LB_ERR_DEVICE, "hipEventCreate failed");
-    std::vector<SweepCfg> cand;
-    for (int tn : {256, 512, 1024, 2048})
-      for (int order : {0, 1}) cand.push_back(SweepCfg{tn, order, 0});
-    cand.push_back(SweepCfg{256, 0, 2048});
-    cand.push_back(SweepCfg{256, 0, 8192});
-    int rc = LB_OK;
+    }
+    const std::vector<SweepCfg> cand = sweep_candidates();
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    Snapshot S;
+    int rc = coupled ? snapshot_take(c, S) : LB_OK;
     std::vector<double> times;
-    for (const SweepCfg& sc : cand) {
-      rc = upload_tiles(c, sc);
+    for (size_t k = 0; k < cand.size() && !rc; ++k) {
+      rc = upload_tiles(c, cand[k]);
       if (rc) break;
-      // the sweep from the current populations into the other array: that
-      // array is overwritten by the next step, so the state is unchanged
-      for (int k = 0; k < 2; ++k) sweep(c, 0, c->s);
-      acc(hipEventRecord(e0, c->s));
-      for (int k = 0; k < reps; ++k) sweep(c, 0, c->s);
-      acc(hipEventRecord(e1, c->s));
+      drop_graph(c);
+      if (coupled) {
+        rc = lb_ensemble_run(c, 2, 1);   // capture and a first replay
+        if (rc) break;
+        acc(hipEventRecord(e0, c->s));
+        rc = lb_ensemble_run(c, 2 * ((reps + 1) / 2), 1);
+        if (rc) break;
+        acc(hipEventRecord(e1, c->s));
+      } else {
+        // into the other array, which the next step overwrites: the state
+        // is unchanged
+        for (int j = 0; j < 2; ++j) sweep(c, 0, c->s);
+        acc(hipEventRecord(e0, c->s));
+        for (int j = 0; j < reps; ++j) sweep(c, 0, c->s);
+        acc(hipEventRecord(e1, c->s));
+      }
       hipError_t e = hipEventSynchronize(e1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
       if (e != hipSuccess) { rc = fail(LB_ERR_DEVICE, "autotune: %s", hipGetErrorString(e)); break; }
-      times.push_back(ms / reps);
+      times.push_back(ms / (coupled ? 2 * ((reps + 1) / 2) : reps));
+      if (coupled) snapshot_restore(c, S);
     }
+    if (S.mem) {
+      if (rc) snapshot_restore(c, S);
+      hipError_t e = hipStreamSynchronize(c->s);
+      (void)hipFree(S.mem);
+      if (!rc && e != hipSuccess) rc = fail(LB_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
+    }
+    drop_graph(c);
+    c->prof_on = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     rc = take_acc("autotune");
     if (rc) return rc;
-    // the first candidate within 1% of the fastest: timing noise does not
-    // flip the choice between layouts that perform alike
+    if (std::getenv("LBMD_AUTOTUNE_LOG"))
+      for (size_t k = 0; k < cand.size(); ++k)
+        fprintf(stderr, "lb_autotune %s: tile %d order %d grid %d cap %d: %.4f ms\n", coupled ? "step" : "sweep",
+                cand[k].tile_nodes, cand[k].order, cand[k].grid, cand[k].cap, times[k]);
     double tmin = times[0];
     for (double t : times) tmin = t < tmin ? t : tmin;
     for (size_t k = 0; k < cand.size(); ++k)
@@ -1017,9 +1132,21 @@ int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
   int rc = upload_tiles(c, best);
   if (rc) return rc;
   drop_graph(c);
-  if (out_cfg) { out_cfg[0] = best.tile_nodes; out_cfg[1] = best.order; out_cfg[2] = best.grid; }
+  if (out_cfg) { out_cfg[0] = best.tile_nodes; out_cfg[1] = best.order; out_cfg[2] = best.grid; out_cfg[3] = best.cap; }
   if (out_ms) *out_ms = best_ms;
   return check_hip("lb_autotune");
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
+  return tune_layout(c, reps, false, out_cfg, out_ms);
+}
+
+int lb_autotune_step(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
+  return tune_layout(c, reps, true, out_cfg, out_ms);
 }
 
 int lb_set_coupling(lb_ctx* c, int rep, double gamma, double f_drive) {

@@ -48,6 +48,10 @@ constexpr int MAXCONTRIB = 64;    // bead contributions gathered per node
 constexpr double SKIN = 0.4;      // neighbour-list skin (lists rebuilt when a bead moved skin/2)
 constexpr double SKIN_STEP = 0.6; // skin when lists are rebuilt at every coupled step (long chains)
 constexpr int STEP_LISTS_MIN_BEADS = 1024;  // chains this long get per-step cell-list builds
+// Cells of the neighbour-search table are at least r_c + skin + CELL_MARGIN
+// wide, so the table stays usable for a rebuild inside a sub-cycle while no
+// bead has moved more than CELL_MARGIN from where it was binned.
+constexpr double CELL_MARGIN = 0.5;
 
 // Control block at the head of the work buffer.
 struct Ctrl {
@@ -57,7 +61,8 @@ struct Ctrl {
   uint64_t rebuilds;         // neighbour-list rebuilds so far (diagnostic)
   uint64_t substeps;         // MD sub-steps so far (diagnostic)
   uint64_t forced_total;     // nodes carrying bead force, summed over steps (diagnostic)
-  uint32_t pad[54];
+  uint64_t cell_rebuilds;    // of the rebuilds, those that used the cell table (diagnostic)
+  uint32_t pad[52];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 

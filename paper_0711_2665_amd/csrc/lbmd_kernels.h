@@ -26,6 +26,11 @@ constexpr int MAX_REPLICAS = 1024;
 constexpr int TILE_MIN = 256;                // smallest sweep tile (nodes)
 constexpr int OBS_TILE = 4096;               // nodes per fluid-reduction tile
 constexpr int CELL_CAP = 32;                 // beads per bucket of the neighbour-search table
+// Sweep occupancy cap: a capped sweep workgroup reserves (LDS per CU - what
+// two bead sub-step workgroups need) / cap bytes of LDS it does not use
+constexpr int LDS_PER_CU = 160 * 1024;
+constexpr int LDS_KEEP = 64 * 1024;
+constexpr int SWEEP_CAP_MIN = 2, SWEEP_CAP_MAX = 8;
 
 struct LbParams {
   int nx, ny, nz, nxy, N;
@@ -51,6 +56,7 @@ struct Rep {
 struct Tile {
   int rep;
   int start;
+  int near;         // sweep tiles: some node of the tile is solid or next to a solid node
 };
 
 // Every device array a kernel may touch.
@@ -88,6 +94,9 @@ struct Dev {
                     // [s][p][2][3] (recorded for the adjoint, one replica)
   int* ccount;      // neighbour search: beads per bucket of the hashed cell table
   int* cbuf;        // [buckets][CELL_CAP] bead slots of each bucket
+  double* rbin;     // per slot: the position the table binned (1e300 before any build)
+  uint32_t* cst;    // per replica, 3 rotating words: some bead is farther than CELL_MARGIN
+                    // from its binned position at that sub-step (the table is not usable)
   uint32_t cmask;   // buckets - 1 (a power of two minus one)
   Ctrl* ctrl;
 };
@@ -104,7 +113,7 @@ template <typename T, bool DEV> void launch_fill_rest(void* pops, long N, hipStr
 void launch_fill_i32(int* p, long n, int v, hipStream_t s);
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
 template <typename T, bool DEV>
-void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int skip_forced,
+void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int cap, int skip_forced,
                hipStream_t s);
 template <typename T, bool DEV>
 void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStream_t s);

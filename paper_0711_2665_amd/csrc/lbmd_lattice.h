@@ -181,6 +181,37 @@ __device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const
   for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c], f[i]);
 }
 
+// Stream + collide U nodes c[u] of one replica, none of them next to a solid
+// node: the flags and straight pulls of all U nodes are issued together.
+// Nodes with in[u] false (c[u] must still be a valid node), solid nodes and,
+// with skip_forced, nodes carrying bead force are neither collided nor
+// stored.
+template <typename T, bool DEV, int U>
+__device__ inline void lb_nodes_bulk(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
+                                     const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl,
+                                     const int c[U], const bool in[U], int skip_forced) {
+  const size_t N = (size_t)p.N;
+  uint8_t fl[U];
+  T f[U][Q];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    fl[u] = flags[c[u]];
+    int x = c[u] % p.nx;
+    int yz = c[u] / p.nx;
+    const Nbr nb = make_nbr(p, x, yz % p.ny, yz / p.ny);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      f[u][i] = A[(size_t)i * N + (size_t)(c[u] + nb.off(-cx(i), -cy(i), -cz(i)))];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (!in[u] || (fl[u] & F_SOLID) || (skip_forced && (fl[u] & F_FORCED))) continue;
+    collide_node<T, DEV>(f[u], f[u], force, p, ctrl, c[u], fl[u]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c[u]], f[u][i]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fluid velocity at node c from the pulled populations (zero at solid nodes),
 // accumulated in FP64.

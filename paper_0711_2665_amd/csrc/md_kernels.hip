@@ -26,13 +26,16 @@ namespace lbmd {
 // Per replica r, rb[4 r + 0..2] are the three rotating rebuild flags and
 // rb[4 r + 3] the "lists invalid" request from the host (initialisation,
 // restored state).
-__global__ void k_md_begin(uint32_t* rb, int nrep) {
+__global__ void k_md_begin(uint32_t* rb, uint32_t* cst, int nrep) {
   for (int r = threadIdx.x; r < nrep; r += blockDim.x) {
     uint32_t* w = rb + 4 * r;
     w[0] = w[3];
     w[1] = 0u;
     w[2] = 0u;
     w[3] = 0u;
+    cst[4 * r] = 0u;
+    cst[4 * r + 1] = 0u;
+    cst[4 * r + 2] = 0u;
   }
 }
 
@@ -52,6 +55,25 @@ __device__ inline MdParams md_params(const Rep& R, const MdOverride& ov) {
   return P;
 }
 
+// Neighbour-search cells: side >= r_c + skin + CELL_MARGIN per replica; each
+// cell hashes to one bucket of a power-of-two table of fixed-capacity buckets
+// (colliding cells share a bucket: their beads fail the distance test).
+__device__ inline uint32_t cell_bucket(int rep, int cx, int cy, int cz, uint32_t mask) {
+  uint32_t h = ((uint32_t)rep * 73856093u) ^ ((uint32_t)cx * 19349663u) ^ ((uint32_t)cy * 83492791u) ^
+               ((uint32_t)cz * 2654435761u);
+  return h & mask;
+}
+
+__device__ inline void bead_cell(const Rep& R, const double* rp, int c[3]) {
+  const int n[3] = {R.g.nx, R.g.ny, R.g.nz};
+  for (int a = 0; a < 3; ++a) {
+    double w = wrapc(rp[a], n[a]);
+    if (!(w >= 0.0 && w < (double)n[a])) w = 0.0;   // non-finite: still a valid cell
+    int k = (int)(w * (double)R.ncell[a] / (double)n[a]);
+    c[a] = k < R.ncell[a] ? k : R.ncell[a] - 1;
+  }
+}
+
 // r_mid of sub-step 0 and the displacement check that decides whether the
 // first launch rebuilds the lists.
 __global__ void k_md_start(Dev d, int nslots, MdOverride ov) {
@@ -61,15 +83,18 @@ __global__ void k_md_start(Dev d, int nslots, MdOverride ov) {
   const Rep& R = d.reps[rep];
   if (slot - R.slot_off >= R.mp.nb) return;
   const double hh = R.mp.hh;
-  double d2 = 0.0;
+  double d2 = 0.0, b2 = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double x = d.r[3 * slot + a] + hh * d.v[3 * slot + a];
     d.rmid0[3 * slot + a] = x;
     double dd = x - d.ref[3 * slot + a];
     d2 += dd * dd;
+    double db = x - d.rbin[3 * slot + a];
+    b2 += db * db;
   }
   if (d2 > R.mp.halfskin2) d.rb[4 * rep] = 1u;
+  if (!(b2 <= CELL_MARGIN * CELL_MARGIN)) d.cst[4 * rep] = 1u;
 }
 
 // The noise of a whole sub-cycle at once: xi[(s nslots + slot) 3 + a] for
@@ -125,6 +150,7 @@ struct MdShared {
   int lst[MD_BPB][MAXNBR];                   // the neighbour list in use (chain indices)
   double tile[MD_WG][3];                     // rebuild: positions of 64 candidates
   uint32_t tmask[MD_BPB][MD_LANES];          // rebuild: lane l, bit e: candidate 16 l + e is close
+  uint32_t bk[MD_BPB][28];                   // rebuild from the cell table: the 27 buckets around a bead
   int over;
 };
 
@@ -196,9 +222,10 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   // the bead's own state and its chain neighbours (every lane of the bead
   // reads them; the lead lane uses them)
   const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
-  double vo[3], Jo[3], ul[3], xl[3], rm[3], rq[3];
+  double vo[3], Jo[3], ul[3], xl[3], rm[3], rq[3], rbl[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
+    rbl[a] = d.rbin[3 * slot + a];
     vo[a] = d.v[3 * slot + a];
     Jo[a] = d.J[3 * slot + a];
     ul[a] = d.up[3 * slot + a];
@@ -230,7 +257,9 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   if (t == 0) {
     if (p0 == 0) {
       rbr[(s + 2) % 3] = 0u;
+      d.cst[4 * rep + (s + 2) % 3] = 0u;
       if (rebuild) atomicAdd((unsigned long long*)&d.ctrl->rebuilds, 1ull);
+      if (rebuild && !d.cst[4 * rep + s % 3]) atomicAdd((unsigned long long*)&d.ctrl->cell_rebuilds, 1ull);
     }
     if (blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, 1ull);
   }
@@ -244,8 +273,9 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   if (t == 0) sh.over = 0;
   const int ncnt0 = active ? ncnt_in : 0;
 
-  // ---- neighbour list: reuse (already in registers), or rebuild by
-  // scanning the chain in tiles of 64
+  // ---- neighbour list: reuse (already in registers), or rebuild -- from
+  // the cell table while every bead of the chain is within CELL_MARGIN of
+  // where the table binned it, else by scanning the chain in tiles of 64
   int cnt = ncnt0;
   int jl[NB_PER_LANE];
   if (!rebuild) {
@@ -253,37 +283,86 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
     for (int m = 0; m < NB_PER_LANE; ++m) jl[m] = (lane + MD_LANES * m < cnt) ? pre[m] : -1;
   } else {
     if (lane == 0) sh.cnt[bslot] = 0;
-    for (int base = 0; base < P.nb; base += MD_WG) {
-      __syncthreads();
-      int j = base + t;
-      if (j < P.nb) { sh.tile[t][0] = rin[3 * j]; sh.tile[t][1] = rin[3 * j + 1]; sh.tile[t][2] = rin[3 * j + 2]; }
-      __syncthreads();
-      uint32_t m = 0;
+    if (!d.cst[4 * rep + s % 3]) {
+      // lane l scans the distinct buckets l, l + 4, ... of the 27 cells
+      // around the bead (a candidate binned within CELL_MARGIN of its
+      // position lies in one of them); the lead lane then sorts
       if (active) {
-        for (int e = 0; e < 16; ++e) {
-          int tt = 16 * lane + e;
-          int jj = base + tt;
-          if (jj >= P.nb || jj == p) continue;
-          double d0 = min_image(rp[0] - sh.tile[tt][0], g.nx);
-          double d1 = min_image(rp[1] - sh.tile[tt][1], g.ny);
-          double d2 = min_image(rp[2] - sh.tile[tt][2], g.nz);
-          if (d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2) m |= 1u << e;
+        int c[3];
+        bead_cell(R, rp, c);
+        for (int k = lane; k < 27; k += MD_LANES) {
+          const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+          sh.bk[bslot][k] = cell_bucket(rep, (c[0] + dx + R.ncell[0]) % R.ncell[0],
+                                        (c[1] + dy + R.ncell[1]) % R.ncell[1], (c[2] + dz + R.ncell[2]) % R.ncell[2],
+                                        d.cmask);
         }
       }
-      sh.tmask[bslot][lane] = m;
+      __syncthreads();
+      if (active) {
+        for (int k = lane; k < 27; k += MD_LANES) {
+          const uint32_t b = sh.bk[bslot][k];
+          bool dup = false;
+          for (int k2 = 0; k2 < k; ++k2) dup = dup || sh.bk[bslot][k2] == b;
+          if (dup) continue;
+          const int n = min(d.ccount[b], CELL_CAP);
+          for (int e = 0; e < n; ++e) {
+            const int q = d.cbuf[(size_t)b * CELL_CAP + e];
+            if (d.slot_rep[q] != rep || q == slot) continue;
+            const int jj = q - so;
+            double d0 = min_image(rp[0] - rin[3 * jj], g.nx);
+            double d1 = min_image(rp[1] - rin[3 * jj + 1], g.ny);
+            double d2 = min_image(rp[2] - rin[3 * jj + 2], g.nz);
+            if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2)) continue;
+            const int at = atomicAdd(&sh.cnt[bslot], 1);
+            if (at < MAXNBR) sh.lst[bslot][at] = jj;
+            else sh.over = 1;
+          }
+        }
+      }
       __syncthreads();
       if (active && lane == 0) {
-        uint64_t mm = (uint64_t)sh.tmask[bslot][0] | ((uint64_t)sh.tmask[bslot][1] << 16) |
-                      ((uint64_t)sh.tmask[bslot][2] << 32) | ((uint64_t)sh.tmask[bslot][3] << 48);
-        int c = sh.cnt[bslot];
-        while (mm) {
-          int tt = __builtin_ctzll(mm);
-          mm &= mm - 1;
-          if (c < MAXNBR) sh.lst[bslot][c] = base + tt;
-          else sh.over = 1;
-          ++c;
+        const int c = min(sh.cnt[bslot], MAXNBR);
+        int* L = sh.lst[bslot];
+        for (int i = 1; i < c; ++i) {
+          const int v = L[i];
+          int m = i;
+          while (m > 0 && L[m - 1] > v) { L[m] = L[m - 1]; --m; }
+          L[m] = v;
         }
-        sh.cnt[bslot] = c;
+      }
+    } else {
+      for (int base = 0; base < P.nb; base += MD_WG) {
+        __syncthreads();
+        int j = base + t;
+        if (j < P.nb) { sh.tile[t][0] = rin[3 * j]; sh.tile[t][1] = rin[3 * j + 1]; sh.tile[t][2] = rin[3 * j + 2]; }
+        __syncthreads();
+        uint32_t m = 0;
+        if (active) {
+          for (int e = 0; e < 16; ++e) {
+            int tt = 16 * lane + e;
+            int jj = base + tt;
+            if (jj >= P.nb || jj == p) continue;
+            double d0 = min_image(rp[0] - sh.tile[tt][0], g.nx);
+            double d1 = min_image(rp[1] - sh.tile[tt][1], g.ny);
+            double d2 = min_image(rp[2] - sh.tile[tt][2], g.nz);
+            if (d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2) m |= 1u << e;
+          }
+        }
+        sh.tmask[bslot][lane] = m;
+        __syncthreads();
+        if (active && lane == 0) {
+          uint64_t mm = (uint64_t)sh.tmask[bslot][0] | ((uint64_t)sh.tmask[bslot][1] << 16) |
+                        ((uint64_t)sh.tmask[bslot][2] << 32) | ((uint64_t)sh.tmask[bslot][3] << 48);
+          int c = sh.cnt[bslot];
+          while (mm) {
+            int tt = __builtin_ctzll(mm);
+            mm &= mm - 1;
+            if (c < MAXNBR) sh.lst[bslot][c] = base + tt;
+            else sh.over = 1;
+            ++c;
+          }
+          sh.cnt[bslot] = c;
+        }
       }
     }
     __syncthreads();
@@ -377,15 +456,18 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   if (last) {
     d.r[3 * slot] = re[0]; d.r[3 * slot + 1] = re[1]; d.r[3 * slot + 2] = re[2];
   } else {
-    double d2 = 0.0;
+    double d2 = 0.0, b2 = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       double x = re[a] + P.hh * vn[a];
       rout[3 * slot + a] = x;
       double dd = x - d.ref[3 * slot + a];
       d2 += dd * dd;
+      double db = x - rbl[a];
+      b2 += db * db;
     }
     if (d2 > P.halfskin2) rbr[(s + 1) % 3] = 1u;
+    if (!(b2 <= CELL_MARGIN * CELL_MARGIN)) d.cst[4 * rep + (s + 1) % 3] = 1u;
   }
 }
 
@@ -395,32 +477,14 @@ __global__ void k_zero_v(double* v, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour lists from a hashed cell table, once per coupled step.  Cells of
-// side >= r_c + skin per replica; each cell hashes to one bucket of a
-// power-of-two table of fixed-capacity buckets (colliding cells share a
-// bucket: their beads fail the distance test).  Each bead is examined by 32
-// lanes, one per distinct bucket of its 27 neighbour cells; the lanes collect
-// the other beads of its chain within r_c + skin, and one lane sorts them
-// into ascending chain order -- the list the in-kernel scan would build.  A
-// bucket that overflows leaves its replica's lists marked invalid, so the
-// first sub-step rebuilds them in-kernel: the same lists, found slower.
+// Neighbour lists from the hashed cell table, once per coupled step.  Each
+// bead is examined by 32 lanes, one per distinct bucket of its 27 neighbour
+// cells; the lanes collect the other beads of its chain within r_c + skin,
+// and one lane sorts them into ascending chain order -- the list the
+// in-kernel scan would build.  A bucket that overflows leaves its replica's
+// lists marked invalid (and the table unusable), so the first sub-step
+// rebuilds them by the full scan: the same lists, found slower.
 // ---------------------------------------------------------------------------
-__device__ inline uint32_t cell_bucket(int rep, int cx, int cy, int cz, uint32_t mask) {
-  uint32_t h = ((uint32_t)rep * 73856093u) ^ ((uint32_t)cx * 19349663u) ^ ((uint32_t)cy * 83492791u) ^
-               ((uint32_t)cz * 2654435761u);
-  return h & mask;
-}
-
-__device__ inline void bead_cell(const Rep& R, const double* rp, int c[3]) {
-  const int n[3] = {R.g.nx, R.g.ny, R.g.nz};
-  for (int a = 0; a < 3; ++a) {
-    double w = wrapc(rp[a], n[a]);
-    if (!(w >= 0.0 && w < (double)n[a])) w = 0.0;   // non-finite: still a valid cell
-    int k = (int)(w * (double)R.ncell[a] / (double)n[a]);
-    c[a] = k < R.ncell[a] ? k : R.ncell[a] - 1;
-  }
-}
-
 __global__ void k_cell_clear(int* __restrict__ ccount, int nbuckets, uint32_t* __restrict__ rb, int nrep) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < nbuckets) ccount[k] = 0;
@@ -438,6 +502,10 @@ __global__ void k_cell_insert(Dev d, int nslots) {
   const uint32_t b = cell_bucket(rep, c[0], c[1], c[2], d.cmask);
   const int pos = atomicAdd(&d.ccount[b], 1);
   if (pos < CELL_CAP) d.cbuf[(size_t)b * CELL_CAP + pos] = slot;
+  // a bead left out of a full bucket is "far from its binned position", so
+  // the table is not used inside the sub-cycle
+#pragma unroll
+  for (int a = 0; a < 3; ++a) d.rbin[3 * slot + a] = pos < CELL_CAP ? d.r[3 * slot + a] : 1e300;
 }
 
 constexpr int LB_LANES = 32;                 // lanes per bead in the list build (27 cells)
@@ -533,7 +601,7 @@ void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, c
                      hipStream_t s) {
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
-  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, nrep);
+  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
   if (noise > 0 && !ov.on) launch_md_noise(d, nslots, n_sub, s);
   hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov);
   for (int k = 0; k < n_sub; ++k)

@@ -81,8 +81,9 @@ def _declare(L):
     L.md_couple_step.argtypes = [P, C.c_int]
     L.lb_ensemble_run.argtypes = [P, C.c_int, C.c_int]
     L.lb_ensemble_translocation.argtypes = [P, C.POINTER(C.c_int64)]
-    L.lb_sweep_config.argtypes = [P, C.c_int, C.c_int, C.c_int]
+    L.lb_sweep_config.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
     L.lb_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.lb_autotune_step.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.md_relax.argtypes = [P, C.c_int, C.c_double]
     L.lb_set_coupling.argtypes = [P, C.c_int, C.c_double, C.c_double]
     L.lb_adjoint_sizes.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
@@ -283,14 +284,18 @@ class Context:
                                          C.c_void_p(out.data_ptr())))
         return out
 
-    def sweep_config(self, tile_nodes, order=0, grid=0):
-        _raise(lib().lb_sweep_config(self.ctx, int(tile_nodes), int(order), int(grid)))
+    def sweep_config(self, tile_nodes, order=0, grid=0, cap=0):
+        _raise(lib().lb_sweep_config(self.ctx, int(tile_nodes), int(order), int(grid), int(cap)))
 
-    def autotune(self, reps=5):
-        cfg = (C.c_int * 3)()
+    def autotune(self, reps=5, coupled=False):
+        """Chooses the sweep layout by timing the sweep alone, or with
+        coupled=True the whole coupled step (graph-replayed, from a snapshot
+        of the state that is restored afterwards)."""
+        cfg = (C.c_int * 4)()
         ms = C.c_double()
-        _raise(lib().lb_autotune(self.ctx, int(reps), cfg, C.byref(ms)))
-        return dict(tile_nodes=cfg[0], order=cfg[1], grid=cfg[2], ms=ms.value)
+        fn = lib().lb_autotune_step if coupled else lib().lb_autotune
+        _raise(fn(self.ctx, int(reps), cfg, C.byref(ms)))
+        return dict(tile_nodes=cfg[0], order=cfg[1], grid=cfg[2], cap=cfg[3], ms=ms.value)
 
     def translocation_steps(self):
         out = (C.c_int64 * self.nrep)()
@@ -307,9 +312,10 @@ class Context:
         return a.value, b.value, n.value
 
     def diagnostics(self):
-        out = (C.c_int64 * 6)()
+        out = (C.c_int64 * 7)()
         _raise(lib().lb_diagnostics(self.ctx, out))
-        return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps", "forced_total"), list(out)))
+        return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps", "forced_total",
+                         "cell_rebuilds"), list(out)))
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))

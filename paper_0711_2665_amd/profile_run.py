@@ -3,13 +3,13 @@
     python -m paper_0711_2665_amd.profile_run --workload c3 --precision fp32dev --steps 5 \
         --copy-mib 1024 --meta gpurun_out/lb_sweep_meta.json
 
-Builds the workload's lattice without beads, lets the autotuner choose the
-sweep layout (the one the benchmark uses), runs `steps` fluid-only sweeps
-(the kernel the coupled step launches for the nodes without bead force) and
-then a plain device-to-device copy of `copy_mib` MiB, whose counter readings
-calibrate the HBM byte counters (FETCH_SIZE, WRITE_SIZE) against a known
-transfer.  Writes what the summary needs (layout, kernel source hash, node
-counts, algorithmic bytes, copy size) to --meta.
+Builds the workload's lattice without beads and, for every sweep layout the
+autotuner chooses from, runs `steps` fluid-only sweeps (the kernel the
+coupled step launches for the nodes without bead force); then a plain
+device-to-device copy of `copy_mib` MiB, whose counter readings calibrate
+the HBM byte counters (FETCH_SIZE, WRITE_SIZE) against a known transfer.
+Writes what the summary needs (layouts in launch order, kernel source hash,
+node counts, algorithmic bytes, copy size) to --meta.
 """
 import argparse
 import json
@@ -19,6 +19,11 @@ import torch
 from . import lbmd
 from .build import kernel_source_hash
 from .workloads import CONFIGS, scaled
+
+# the autotuner's candidates (tile nodes, order, grid, cap)
+LAYOUTS = [(t, o, 0, 0) for t in (256, 512, 1024, 2048) for o in (0, 1)] + \
+    [(t, 0, g, 0) for t in (256, 512) for g in (512, 1024, 2048)] + \
+    [(t, 0, 0, k) for t in (256, 512, 1024) for k in (2, 3, 4)]
 
 
 def main():
@@ -32,8 +37,9 @@ def main():
     cfg = scaled(CONFIGS[a.workload], nb=0)
     prec = lbmd.LB_FP32_DEV if a.precision == "fp32dev" else lbmd.LB_FP64
     sim = lbmd.Simulation(cfg, precision=prec)
-    tune = sim.autotune(reps=10)
-    sim.lb_step(a.steps)
+    for lay in LAYOUTS:
+        sim.sweep_config(*lay)
+        sim.lb_step(a.steps)
     torch.cuda.synchronize()
     sim.check()
     n = a.copy_mib * 2 ** 20 // 4
@@ -46,12 +52,12 @@ def main():
     es = 4 if a.precision == "fp32dev" else 8
     meta = dict(workload=a.workload, precision=a.precision, shape=[nx, ny, nz], nodes=nx * ny * nz, nfluid=nfluid,
                 algorithmic_bytes_per_launch=nfluid * (2 * 19 * es + 1) + (nx * ny * nz - nfluid),
-                sweep_layout={k: tune[k] for k in ("tile_nodes", "order", "grid")},
+                layouts=[dict(tile_nodes=t, order=o, grid=g, cap=k) for t, o, g, k in LAYOUTS],
                 kernel_source_hash=kernel_source_hash(), copy_bytes=n * 4, sweeps=a.steps)
     if a.meta:
         with open(a.meta, "w") as fh:
             json.dump(meta, fh)
-    print(f"profile_run: {a.steps} sweeps of {cfg['shape']} ({a.precision}), layout {meta['sweep_layout']}, "
+    print(f"profile_run: {a.steps} sweeps of {cfg['shape']} ({a.precision}) in each of {len(LAYOUTS)} layouts, "
           f"copy of {a.copy_mib} MiB", flush=True)
 
 

@@ -75,36 +75,46 @@ def counter_rows(db, counter):
 
 def counters(a):
     meta = json.load(open(a.meta))
+    layouts, n = meta["layouts"], meta["sweeps"]
+    per = [dict(layout=l) for l in layouts]
     res = {}
     for counter, db in (("FETCH_SIZE", a.fetch_db), ("WRITE_SIZE", a.write_db)):
         rows = counter_rows(db, counter)
-        sweep = [(st, v) for n, st, v in rows if a.kernel in short(n)]
+        sweep = [(st, v) for nm, st, v in rows if a.kernel in short(nm)]
         last = sweep[-1][0]
-        copy = [v for n, st, v in rows if "copyBuffer" in n and st > last]
-        sweep = sweep[-meta["sweeps"]:]
-        kib = sum(v for _, v in sweep) / len(sweep)
+        copy = [v for nm, st, v in rows if "copyBuffer" in nm and st > last]
+        sweep = sweep[-len(layouts) * n:]
         copy_kib = sum(copy)
         factor = meta["copy_bytes"] / (copy_kib * 1024.0)
-        res[counter] = dict(kib_per_launch=kib, copy_kib=copy_kib, copy_dispatches=len(copy), factor=factor,
-                            bytes_per_launch=kib * 1024.0 * factor, launches=len(sweep))
-    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+        res[counter] = dict(copy_kib=copy_kib, copy_dispatches=len(copy), factor=factor)
+        for k, e in enumerate(per):
+            kib = sum(v for _, v in sweep[k * n:(k + 1) * n]) / n
+            e[counter] = dict(kib_per_launch=kib, bytes_per_launch=kib * 1024.0 * factor)
     alg = meta["algorithmic_bytes_per_launch"]
-    out = dict(meta, counters=res, bytes_per_launch=total, traffic_over_algorithmic=total / alg,
-               command=a.command)
+    for e in per:
+        e["bytes_per_launch"] = e["FETCH_SIZE"]["bytes_per_launch"] + e["WRITE_SIZE"]["bytes_per_launch"]
+        e["traffic_over_algorithmic"] = e["bytes_per_launch"] / alg
+    out = dict(meta, counters=res, per_layout=per, command=a.command)
     with open(a.out + "_counters.json", "w") as fh:
         json.dump(out, fh, indent=1)
     f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
     lines = [f"# HBM traffic of the LB sweep: {meta['workload']} {meta['precision']}", "",
              "Commands (from the repository root):", "", "```", a.command, "```", "",
-             f"Lattice {meta['shape']} ({meta['nodes']} nodes, {meta['nfluid']} fluid), sweep layout "
-             f"{meta['sweep_layout']}, kernel source hash `{meta['kernel_source_hash']}`.", "",
-             "| counter | KiB per launch (raw) | copy calibration (bytes / counter bytes) | bytes per launch |",
-             "|---|---:|---:|---:|",
-             f"| FETCH_SIZE | {f['kib_per_launch']:.1f} | {f['factor']:.4f} ({f['copy_dispatches']} copy dispatches, "
-             f"{meta['copy_bytes']} B) | {f['bytes_per_launch']:.4e} |",
-             f"| WRITE_SIZE | {w['kib_per_launch']:.1f} | {w['factor']:.4f} | {w['bytes_per_launch']:.4e} |", "",
-             f"Measured HBM bytes per launch: {total:.4e}; algorithmic: {alg:.4e} "
-             f"(ratio {total / alg:.4f})."]
+             f"Lattice {meta['shape']} ({meta['nodes']} nodes, {meta['nfluid']} fluid), kernel source hash "
+             f"`{meta['kernel_source_hash']}`, {n} sweeps per layout.  Counters are calibrated against a "
+             f"device-to-device copy of {meta['copy_bytes']} B: factor (bytes / counter bytes) "
+             f"{f['factor']:.4f} for FETCH_SIZE ({f['copy_dispatches']} copy dispatches), {w['factor']:.4f} "
+             f"for WRITE_SIZE.", "",
+             f"Algorithmic bytes per launch: {alg:.4e}.", "",
+             "| tile nodes | order | grid | cap | FETCH_SIZE KiB/launch (raw) | WRITE_SIZE KiB/launch (raw) | "
+             "HBM bytes per launch | / algorithmic |",
+             "|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for e in per:
+        l = e["layout"]
+        lines.append(f"| {l['tile_nodes']} | {l['order']} | {l['grid']} | {l['cap']} | "
+                     f"{e['FETCH_SIZE']['kib_per_launch']:.1f} | "
+                     f"{e['WRITE_SIZE']['kib_per_launch']:.1f} | {e['bytes_per_launch']:.4e} | "
+                     f"{e['traffic_over_algorithmic']:.4f} |")
     with open(a.out + "_counters.md", "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))

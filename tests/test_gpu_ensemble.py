@@ -145,13 +145,14 @@ def test_sweep_layouts_and_autotuner_leave_results_unchanged():
     ref.couple_step(4)
     torch.cuda.synchronize()
     want = _snapshot(ref)
-    for tile, order, grid in ((512, 0, 0), (256, 1, 0), (1024, 1, 0), (256, 0, 7), (2048, 1, 3)):
+    for tile, order, grid, cap in ((512, 0, 0, 0), (256, 1, 0, 0), (1024, 1, 0, 0), (256, 0, 7, 0), (2048, 1, 3, 0),
+                                   (768, 0, 5, 0), (512, 0, 0, 2), (1024, 0, 0, 3), (256, 1, 0, 8)):
         e = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
-        e.sweep_config(tile, order, grid)
+        e.sweep_config(tile, order, grid, cap)
         e.relax(300, 1.0)
         e.couple_step(4)
         torch.cuda.synchronize()
-        _assert_same(_snapshot(e), want, (tile, order, grid))
+        _assert_same(_snapshot(e), want, (tile, order, grid, cap))
         e.close()
     e = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
     e.relax(300, 1.0)
@@ -159,14 +160,14 @@ def test_sweep_layouts_and_autotuner_leave_results_unchanged():
     before = _snapshot(e)
     best = e.autotune(reps=2)
     print("autotune:", best, flush=True)
-    assert best["tile_nodes"] % 256 == 0 and best["order"] in (0, 1) and best["grid"] >= 0
+    assert best["tile_nodes"] % 256 == 0 and best["order"] in (0, 1) and best["grid"] >= 0 and best["cap"] in (0, 2, 3, 4)
     _assert_same(_snapshot(e), before, "autotune changed the state")
     e.couple_step(2)
     torch.cuda.synchronize()
     _assert_same(_snapshot(e), want, "after autotune")
     again = e.autotune(reps=2)       # cached for this layout
-    assert again["ms"] == -1.0 and {k: again[k] for k in ("tile_nodes", "order", "grid")} == \
-        {k: best[k] for k in ("tile_nodes", "order", "grid")}
+    assert again["ms"] == -1.0 and {k: again[k] for k in ("tile_nodes", "order", "grid", "cap")} == \
+        {k: best[k] for k in ("tile_nodes", "order", "grid", "cap")}
 
 
 def test_translocation_steps_and_resume():
@@ -198,3 +199,36 @@ def test_translocation_steps_and_resume():
     fresh.set_state(st)
     assert fresh.step_count() == 1 and fresh.translocation_steps() == [-1, -1, -1, 1]
     torch.cuda.synchronize()
+
+
+def test_coupled_step_autotuner_restores_the_state():
+    """The autotuner that times whole coupled steps runs trial steps from a
+    snapshot: afterwards the state, the step count, the translocation record
+    and the diagnostic counters are those from before, and later steps give
+    the reference results."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = _cfgs()
+    r0s = _chains(cfgs)
+    ref = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    ref.relax(300, 1.0)
+    ref.couple_step(5)
+    torch.cuda.synchronize()
+    want = _snapshot(ref)
+    e = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    e.relax(300, 1.0)
+    e.couple_step(3)
+    torch.cuda.synchronize()
+    before, diag, steps, tx = _snapshot(e), e.diagnostics(), e.step_count(), e.translocation_steps()
+    best = e.autotune(reps=3, coupled=True)
+    print("coupled autotune:", best, flush=True)
+    assert best["ms"] > 0.0 and best["tile_nodes"] % 256 == 0
+    torch.cuda.synchronize()
+    _assert_same(_snapshot(e), before, "autotune changed the state")
+    assert e.diagnostics() == diag and e.step_count() == steps and e.translocation_steps() == tx
+    e.run(2, graph=True)
+    torch.cuda.synchronize()
+    _assert_same(_snapshot(e), want, "after the coupled autotune")
+    again = e.autotune(reps=3, coupled=True)
+    assert again["ms"] == -1.0 and again["tile_nodes"] == best["tile_nodes"]
+    e.check()

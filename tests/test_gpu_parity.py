@@ -288,6 +288,41 @@ def test_long_chain_with_per_step_lists_bitwise(orc):
         assert np.array_equal(sb[k], ob[k]), k
 
 
+def test_long_chain_rebuilds_inside_the_cycle_bitwise(orc):
+    """The 1100-bead chain with a uniform drift of 0.45 per step parallel to
+    the wall: beads pass half the skin inside a sub-cycle, so lists are
+    rebuilt there -- from the cell table while every bead is within its
+    margin of where it was binned, else by the full scan.  Three coupled
+    steps (kT = 0, kappa = 0) must equal the oracle bit for bit, and the
+    table must have served some of the rebuilds."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=(40, 40, 40), wall_pos=20, nb=1100, kT=0.0, kappa=0.0, init_seed=9)
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(300, 1.0)
+    r0 = o.beads()["r"]
+    v0 = np.zeros_like(r0)
+    v0[:, 0] = 0.45
+    o = orc.Oracle(cfg, r0, v0)
+    s = lbmd.Simulation(cfg, r0, v0)
+    o.couple_step(3)
+    s.couple_step(3)
+    torch.cuda.synchronize()
+    s.check()
+    diag = s.diagnostics()
+    fluid = o.flags() == 0
+    a, b = _gpu_pops(s)[:, fluid], o.pops()[:, fluid]
+    sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+    ob = o.beads()
+    print("1100 beads drifting, 3 steps: pops differing", int((a != b).sum()),
+          {k: int((sb[k] != ob[k]).sum()) for k in ("r", "v", "up", "J")}, diag, flush=True)
+    assert np.array_equal(a, b)
+    for k in ("r", "v", "up", "J"):
+        assert np.array_equal(sb[k], ob[k]), k
+    assert diag["cell_rebuilds"] >= 1 and diag["rebuilds"] >= diag["cell_rebuilds"]
+
+
 @pytest.mark.parametrize("shape,axis,pos", [((12, 10, 16), 2, 8), ((32, 16, 12), 0, 16)])
 def test_lb_only_fp32_deviation_matches_oracle(orc, shape, axis, pos):
     """FP32 deviation storage against the FP64 oracle over 20 fluid steps from
