@@ -59,8 +59,21 @@ def measured_traffic(workload, precision, layout):
     return None
 
 
+def sweep_alone(run, cells, elem):
+    """Roofline of the sweep run alone over every fluid node in the layout
+    the sweep-only autotuner picks (in the coupled step the layout is picked
+    for the whole step, and the sweep shares the memory system with the bead
+    phase)."""
+    a = run["alone"]
+    nbytes = run["nfluid"] * lb_bytes_per_update(elem) + (cells - run["nfluid"])
+    gbs = nbytes / (a["ms"] * 1e-3) / 1e9
+    return {"layout": {k: a[k] for k in ("tile_nodes", "order", "grid", "cap")}, "mean_launch_ms": round(a["ms"], 5),
+            "bytes_per_launch": int(nbytes), "achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def run_gpu(cfg, precision_name, steps, warmup):
-    """Relax, choose the sweep layout by timing whole coupled steps, then:
+    """Relax, time the sweep alone (autotuner, sweep-only mode), choose the
+    sweep layout by timing whole coupled steps, then:
     `steps` coupled steps replayed from the captured two-step HIP graph (the
     timed region of the headline figure), and `steps` eager steps with the
     library's per-step HIP events around the sweep and the bead phase (the
@@ -73,6 +86,9 @@ def run_gpu(cfg, precision_name, steps, warmup):
     r, v = initial_chain(cfg)
     sim = lbmd.Simulation(cfg, r, v, precision=prec, device="cuda:0")
     sim.relax(cfg["relax_substeps"], cfg["gamma_relax"])
+    # the sweep alone (every fluid node, nothing beside it), in the layout
+    # that is fastest for it, timed by the autotuner with HIP events
+    alone = sim.autotune(reps=10)
     tune = sim.autotune(reps=10, coupled=True)
     sim.run(warmup + (warmup & 1), graph=True)          # capture, warm replays
     torch.cuda.synchronize()
@@ -82,7 +98,7 @@ def run_gpu(cfg, precision_name, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.check()
-    out = dict(seconds=t1 - t0, tune=tune)
+    out = dict(seconds=t1 - t0, tune=tune, alone=alone)
     diag0 = sim.diagnostics()
     sim.profile_start(steps)
     torch.cuda.synchronize()
@@ -296,6 +312,7 @@ def main():
                      "kernel": "k_lb (fused stream+collide)", "bytes_per_launch": alg_bytes,
                      "mean_launch_ms": round(main_run["lb_ms"], 5)},
         "sweep_layout": layout,
+        "sweep_alone": sweep_alone(main_run, cells, elem),
         "timing": "graph replay of the coupled step; roofline from the same kernels in eager steps",
         "eager": {"value": round(cells * args.steps / main_run["eager_seconds"] / 1e6, 1), "unit": "MLUPS",
                   "ms_per_step": round(1e3 * main_run["eager_seconds"] / args.steps, 4)},
@@ -314,6 +331,7 @@ def main():
         out["fp64"] = {"value": round(cells * k64 / r64["seconds"] / 1e6, 1), "unit": "MLUPS", "steps": k64,
                        "ms_per_step": round(1e3 * r64["seconds"] / k64, 4),
                        "eager_ms_per_step": round(1e3 * r64["eager_seconds"] / k64, 4),
+                       "sweep_alone": sweep_alone(r64, cells, 8),
                        "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
     if not args.no_ensemble and args.workload == "c3":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 20, 200)

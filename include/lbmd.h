@@ -207,11 +207,12 @@ int lb_ensemble_translocation(lb_ctx* ctx, int64_t* out_host);
 int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid, int cap);
 
 /* Autotuner of the sweep layout: times `reps` sweeps of every candidate
- * layout (tile sizes 256..2048 in both orders; persistent grids of 512,
- * 1024 and 2048 workgroups over tiles of 256 and 512 nodes; tiles of 256,
- * 512 and 1024 nodes capped at 2, 3 or 4 workgroups per CU) with HIP events,
- * from the current populations into the other array (which the next step
- * overwrites, so the state is unchanged), keeps the first candidate within
+ * layout (tile sizes 256..2048 in both orders; persistent grids of 256,
+ * 384, 512, 768, 1024 and 2048 workgroups over tiles of 256 and 512 nodes;
+ * tiles of 256, 512 and 1024 nodes capped at 2, 3 or 4 workgroups per CU)
+ * with HIP events, from the current populations into the other array (which
+ * the next step overwrites, so the state is unchanged), keeps the first
+ * candidate within
  * 1% of the fastest and caches it for the process by (replica extents,
  * walls and chain lengths, precision).
  * Writes {tile_nodes, order, grid, cap} to out_cfg[4] and the mean sweep

@@ -111,7 +111,7 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   w.rmid1 = take(sizeof(double) * 3 * ns);
   w.ref = take(sizeof(double) * 3 * ns);
   w.part = take(sizeof(double) * 4 * (size_t)pk.obs_tiles);
-  w.xi = take(sizeof(double) * 3 * ns * (size_t)d[0].n_sub);
+  w.xi = take(sizeof(double) * 3 * ns * (size_t)d[0].n_sub * 2);   // two sub-cycles: this step's and the next
   w.tX = take(sizeof(int64_t) * R);
   w.notdone = take(sizeof(uint32_t) * R);
   w.nbuckets = 64;
@@ -287,6 +287,7 @@ struct lb_ctx {
   bool step_lists = false;   // neighbour lists built from a cell list at every coupled step
   bool lists_stale = true;   // the positions changed outside a coupled step since the last build
   bool any_noise = false;
+  bool noise_ready = false;  // the noise slot of the current population parity holds this step's noise
   SweepCfg sweep;
   int ntiles = 0;
   std::vector<std::vector<uint8_t>> near_blocks;   // per replica and TILE_MIN nodes: solid or wall-adjacent
@@ -294,7 +295,7 @@ struct lb_ctx {
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
   hipStream_t s1 = nullptr, s2 = nullptr;
-  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr, noise = nullptr;
+  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr;
   // graph of two coupled steps, starting at population parity graph_cur
   hipStream_t scap = nullptr;
   hipGraph_t graph = nullptr;
@@ -378,8 +379,33 @@ void sweep_ab(lb_ctx* c, const void* A, void* B, int skip_forced, hipStream_t st
 }
 void sweep(lb_ctx* c, int skip_forced, hipStream_t st) { sweep_ab(c, cur_pops(c), other_pops(c), skip_forced, st); }
 
+// The device view with d.xi at noise slot k (two sub-cycles of noise, one
+// per population parity).
+Dev with_noise_slot(const lb_ctx* c, int k) {
+  Dev D = c->D;
+  D.xi = c->D.xi + (size_t)k * 3 * (size_t)c->pk.slots_alloc * (size_t)c->n_sub;
+  return D;
+}
+
+// Draws the current step's noise on st unless it was drawn during the
+// previous coupled step.
+void ensure_noise(lb_ctx* c, hipStream_t st) {
+  if (!c->any_noise || c->noise_ready || c->nslots == 0) return;
+  launch_md_noise(with_noise_slot(c, c->cur), c->nslots, c->n_sub, 0, st);
+  c->noise_ready = true;
+}
+
+// Builds the neighbour lists of long chains on st if the positions changed
+// outside a coupled step (a step would otherwise build them first).
+void ensure_lists(lb_ctx* c, hipStream_t st) {
+  if (!c->step_lists || !c->lists_stale) return;
+  launch_nbr_build(c->D, c->nslots, c->nrep, st);
+  c->lists_stale = false;
+}
+
 // One fluid-only step on stream st.
 void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
+  c->noise_ready = false;
   prof_mark(c, 0, st);
   prof_mark(c, 1, st);
   prof_mark(c, 2, st);
@@ -397,7 +423,8 @@ void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
 // nodes without bead force on s2, both forked from and joined back to st, so
 // that the overlap does not depend on the kind of stream the caller uses.
 void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) {
-  const Dev& D = c->D;
+  ensure_noise(c, st);
+  const Dev D = with_noise_slot(c, c->cur);
   hipStream_t sb = c->s1;
   acc(hipEventRecord(c->fork, st));
   acc(hipStreamWaitEvent(sb, c->fork, 0));
@@ -405,17 +432,12 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   launch_bead_prep(D, c->nslots, sb);
   acc(hipEventRecord(c->prep, sb));
   acc(hipStreamWaitEvent(c->s2, c->prep, 0));
-  // eager steps draw the sub-cycle's noise on the sweep stream, ahead of the
-  // sweep, while the bead stream gathers; a captured graph keeps the noise
-  // pass on the bead stream (no cross-stream dependency inside the step)
-  const bool noise_aside = c->any_noise && !c->capturing;
-  if (noise_aside) {
-    launch_md_noise(D, c->nslots, c->n_sub, c->s2);
-    acc(hipEventRecord(c->noise, c->s2));
-  }
   prof_mark(c, 2, c->s2);
   sweep_ab(c, A, B, 1, c->s2);
   prof_mark(c, 3, c->s2);
+  // the next step's noise, into the other slot, after the sweep: off the
+  // bead stream's path
+  if (c->any_noise) launch_md_noise(with_noise_slot(c, c->cur ^ 1), c->nslots, c->n_sub, 1, c->s2);
   acc(hipEventRecord(c->join, c->s2));
   // long chains: the lists of this step were built at the end of the
   // previous one (when the sweep is normally done), unless the positions
@@ -424,8 +446,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   if (c->dev) launch_gather<float, true>(A, D, c->nslots, sb);
   else launch_gather<double, false>(A, D, c->nslots, sb);
   MdOverride none{};
-  if (noise_aside) acc(hipStreamWaitEvent(sb, c->noise, 0));
-  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, noise_aside ? -1 : (c->any_noise ? 1 : 0), none, sb);
+  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb);
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
   if (c->step_lists) {
@@ -437,6 +458,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   acc(hipStreamWaitEvent(st, c->join, 0));
   acc(hipStreamWaitEvent(st, c->join1, 0));
   launch_step_end(D, c->nslots, c->maxlist, c->nrep, st);
+  c->noise_ready = c->any_noise;
   prof_next(c);
 }
 void enqueue_coupled_step(lb_ctx* c, hipStream_t st) {
@@ -462,6 +484,9 @@ void drop_graph(lb_ctx* c) {
 // recorded, so replays are equivalent to eager steps.
 int build_graph(lb_ctx* c) {
   drop_graph(c);
+  // the graph starts from a step whose noise is drawn and whose lists are built
+  ensure_noise(c, c->s);
+  ensure_lists(c, c->s);
   const int cur0 = c->cur;
   c->capturing = true;
   hipError_t e = hipStreamBeginCapture(c->scap, hipStreamCaptureModeThreadLocal);
@@ -544,6 +569,7 @@ void restore_state(lb_ctx* c, const char* st, void* dst_pops) {
   acc(hipMemcpyAsync(c->D.tX, st + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
   launch_md_invalidate(c->D, c->nrep, c->s);
   c->lists_stale = true;
+  c->noise_ready = false;
 }
 
 }  // namespace
@@ -602,9 +628,8 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     hipError_t e5 = hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking);
     hipError_t e6 = hipEventCreateWithFlags(&c->prep, hipEventDisableTiming);
     hipError_t e7 = hipEventCreateWithFlags(&c->join1, hipEventDisableTiming);
-    hipError_t e8 = hipEventCreateWithFlags(&c->noise, hipEventDisableTiming);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess) {
+        e6 != hipSuccess || e7 != hipSuccess) {
       lb_destroy(c);
       return fail(LB_ERR_DEVICE, "stream/event creation failed");
     }
@@ -763,7 +788,6 @@ void lb_destroy(lb_ctx* ctx) {
   if (ctx->prep) (void)hipEventDestroy(ctx->prep);
   if (ctx->join) (void)hipEventDestroy(ctx->join);
   if (ctx->join1) (void)hipEventDestroy(ctx->join1);
-  if (ctx->noise) (void)hipEventDestroy(ctx->noise);
   if (ctx->s1) (void)hipStreamDestroy(ctx->s1);
   if (ctx->s2) (void)hipStreamDestroy(ctx->s2);
   if (ctx->scap) (void)hipStreamDestroy(ctx->scap);
@@ -847,6 +871,10 @@ int lb_ensemble_run(lb_ctx* c, int nsteps, int use_graph) {
       enqueue_coupled_step(c, c->s);
       --left;
     }
+    if (left >= 2) {
+      ensure_noise(c, c->s);
+      ensure_lists(c, c->s);
+    }
     for (; left >= 2; left -= 2) acc(hipGraphLaunch(c->gexec, c->s));
   }
   for (; left > 0; --left) enqueue_coupled_step(c, c->s);
@@ -871,7 +899,7 @@ int md_relax(lb_ctx* c, int nsub_total, double gamma_relax) {
   int left = nsub_total;
   while (left > 0) {
     int n = left < c->n_sub ? left : c->n_sub;
-    launch_md_cycle(c->D, c->nslots, c->nrep, n, 0, ov, c->s);
+    launch_md_cycle(c->D, c->nslots, c->nrep, n, ov, c->s);
     left -= n;
   }
   launch_zero_v(c->D, c->nslots, c->s);
@@ -912,6 +940,7 @@ int lb_set_state(lb_ctx* c, const void* src) {
   acc(hipMemcpyAsync(c->D.tX, o + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
   launch_md_invalidate(c->D, c->nrep, c->s);
   c->lists_stale = true;
+  c->noise_ready = false;
   uint64_t st = 0;
   acc(hipMemcpyAsync(&st, o + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToHost, c->s));
   hipError_t e = hipStreamSynchronize(c->s);
@@ -988,7 +1017,7 @@ int lb_sweep_config(lb_ctx* c, int tile_nodes, int order, int grid, int cap) {
 namespace {
 
 // Candidate sweep layouts: tile sizes 256..2048 in both orders; persistent
-// grids of 512..2048 workgroups over tiles of 256 and 512 nodes; and one
+// grids of 256..2048 workgroups over tiles of 256 and 512 nodes; and one
 // workgroup per tile of 256..1024 nodes with at most 2, 3 or 4 sweep
 // workgroups per CU.
 std::vector<SweepCfg> sweep_candidates() {
@@ -996,7 +1025,7 @@ std::vector<SweepCfg> sweep_candidates() {
   for (int tn : {256, 512, 1024, 2048})
     for (int order : {0, 1}) cand.push_back(SweepCfg{tn, order, 0, 0});
   for (int tn : {256, 512})
-    for (int g : {512, 1024, 2048}) cand.push_back(SweepCfg{tn, 0, g, 0});
+    for (int g : {256, 384, 512, 768, 1024, 2048}) cand.push_back(SweepCfg{tn, 0, g, 0});
   for (int tn : {256, 512, 1024})
     for (int cap : {2, 3, 4}) cand.push_back(SweepCfg{tn, 0, 0, cap});
   return cand;
@@ -1011,6 +1040,7 @@ struct Snapshot {
   int cur = 0;
   int64_t steps = 0;
   bool lists_stale = true;
+  bool noise_ready = false;
 };
 
 int snapshot_take(lb_ctx* c, Snapshot& S) {
@@ -1030,6 +1060,7 @@ int snapshot_take(lb_ctx* c, Snapshot& S) {
   S.cur = c->cur;
   S.steps = c->steps;
   S.lists_stale = c->lists_stale;
+  S.noise_ready = c->noise_ready;
   return take_acc("snapshot");
 }
 
@@ -1038,6 +1069,7 @@ void snapshot_restore(lb_ctx* c, const Snapshot& S) {
   c->cur = S.cur;
   c->steps = S.steps;
   c->lists_stale = S.lists_stale;
+  c->noise_ready = S.noise_ready;
   const char* o = S.mem;
   acc(hipMemcpyAsync(cur_pops(c), o, es * Q * (size_t)c->pk.nodes, hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(c->b.beads, o + S.pops, sizeof(double) * 15 * (size_t)c->pk.slots_alloc,
@@ -1161,6 +1193,7 @@ int lb_set_coupling(lb_ctx* c, int rep, double gamma, double f_drive) {
   for (const Rep& x : c->reps) noise = noise || (x.mp.nb > 0 && x.mp.sig != 0.0);
   if (noise != c->any_noise) drop_graph(c);
   c->any_noise = noise;
+  c->noise_ready = false;
   hipError_t e = hipMemcpyAsync((char*)c->b.work + c->wl.reps + sizeof(Rep) * (size_t)rep, &R, sizeof(Rep),
                                 hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);   // R is read from host memory
@@ -1240,6 +1273,9 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
       acc(hipMemcpyAsync(tape_bead(j, 1), c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
       void* B = j + 1 < len ? tape_pops(j + 1) : other_pops(c);
       c->D.mdtape = (double*)(w + L.mdtape + (size_t)j * L.md_arr);
+      // these steps keep the population parity, so the noise slot does not
+      // alternate: every step draws its own noise
+      c->noise_ready = false;
       enqueue_coupled_step_ab(c, tape_pops(j), B, c->s);
       c->D.mdtape = nullptr;
       acc(hipMemcpyAsync(tape_bead(j, 2), c->D.up, nb3, hipMemcpyDeviceToDevice, c->s));

@@ -149,11 +149,12 @@ void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const 
                              int nb, hipStream_t s);
 void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 
-// MD sub-cycle of all replicas: n_sub launches, one per sub-step.  With
-// noise < 0 the noise pass is left to the caller (launch_md_noise).
-void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
-                     hipStream_t s);
-void launch_md_noise(const Dev& d, int nslots, int n_sub, hipStream_t s);
+// MD sub-cycle of all replicas: n_sub launches, one per sub-step, reading
+// the noise from d.xi (drawn beforehand by launch_md_noise; unused by
+// replicas without noise and by the relaxation).
+void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s);
+// Noise of one sub-cycle into d.xi, for the step counter + step_offset.
+void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);
 // Verlet lists of every bead from a hashed cell list of the current
 // positions (once per coupled step); marks the lists valid.

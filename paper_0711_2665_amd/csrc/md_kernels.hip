@@ -101,8 +101,9 @@ __global__ void k_md_start(Dev d, int nslots, MdOverride ov) {
 // every sub-step s and bead (the same counter-based values the sub-step would
 // draw, keyed by the replica's seed and index and the bead's chain index), so
 // the transcendental functions run in one wide launch instead of on the
-// critical path of every sub-step.
-__global__ void k_md_noise(Dev d, int nslots, int n_sub) {
+// critical path of every sub-step.  The step counter word is the control
+// block's step plus step_offset (1: the sub-cycle of the next step).
+__global__ void k_md_noise(Dev d, int nslots, int n_sub, int step_offset) {
   long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (long)n_sub * nslots) return;
   int sidx = (int)(k / nslots), slot = (int)(k - (long)sidx * nslots);
@@ -110,7 +111,7 @@ __global__ void k_md_noise(Dev d, int nslots, int n_sub) {
   const int p = slot - R.slot_off;
   if (p >= R.mp.nb || R.mp.sig == 0.0) return;
   double x[3];
-  gauss3(R.mp.seed, R.mp.replica, (uint32_t)d.ctrl->step, (uint32_t)sidx, (uint32_t)p, x);
+  gauss3(R.mp.seed, R.mp.replica, (uint32_t)(d.ctrl->step + (uint64_t)step_offset), (uint32_t)sidx, (uint32_t)p, x);
   d.xi[3 * k] = x[0]; d.xi[3 * k + 1] = x[1]; d.xi[3 * k + 2] = x[2];
 }
 
@@ -597,20 +598,20 @@ void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {
   hipLaunchKernelGGL(k_md_invalidate, dim3(1), dim3(256), 0, s, d.rb, nrep);
 }
 
-void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, int noise, const MdOverride& ov,
-                     hipStream_t s) {
+void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s) {
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
-  if (noise > 0 && !ov.on) launch_md_noise(d, nslots, n_sub, s);
   hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov);
   for (int k = 0; k < n_sub; ++k)
     hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, d, ov, nslots, k, k == n_sub - 1 ? 1 : 0);
 }
 
-void launch_md_noise(const Dev& d, int nslots, int n_sub, hipStream_t s) {
+void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s) {
   long nk = (long)n_sub * nslots;
-  if (nk > 0) hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, d, nslots, n_sub);
+  if (nk > 0)
+    hipLaunchKernelGGL(k_md_noise, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, s, d, nslots, n_sub,
+                       step_offset);
 }
 
 void launch_zero_v(const Dev& d, int nslots, hipStream_t s) {

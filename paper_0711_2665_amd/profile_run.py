@@ -22,7 +22,7 @@ from .workloads import CONFIGS, scaled
 
 # the autotuner's candidates (tile nodes, order, grid, cap)
 LAYOUTS = [(t, o, 0, 0) for t in (256, 512, 1024, 2048) for o in (0, 1)] + \
-    [(t, 0, g, 0) for t in (256, 512) for g in (512, 1024, 2048)] + \
+    [(t, 0, g, 0) for t in (256, 512) for g in (256, 384, 512, 768, 1024, 2048)] + \
     [(t, 0, 0, k) for t in (256, 512, 1024) for k in (2, 3, 4)]
 
 

@@ -5,6 +5,11 @@ for the profiles folder.
     python -m paper_0711_2665_amd.rocprof_summary trace --db DB --out profiles/X.md \
         --command "the rocprofv3 command" [--kernel k_lb --last 200]
 
+    # one coupled step as a timeline (kernel starts relative to the end of the
+    # previous step, sub-step durations summarised)
+    python -m paper_0711_2665_amd.rocprof_summary timeline --db DB --out profiles/X.md \
+        --command "the rocprofv3 command" --step -5
+
     # HBM bytes of the sweep from one FETCH_SIZE run and one WRITE_SIZE run
     python -m paper_0711_2665_amd.rocprof_summary counters --fetch-db DB1 --write-db DB2 \
         --meta META.json --kernel k_lb --out profiles/lb_sweep_fp32dev_c3 --command "..."
@@ -62,6 +67,42 @@ def trace(a):
                       f"{f' (the last {a.skip_last} dispatches, later in the run, excluded)' if a.skip_last else ''}: "
                       f"mean {sum(d) / len(d) / 1e3:.2f} us, min {min(d) / 1e3:.2f} us, max {max(d) / 1e3:.2f} us, "
                       f"grid {sel[-1][4]} x workgroup {sel[-1][5]}."]
+    with open(a.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def timeline(a):
+    """Kernels of one coupled step (between two k_step_end dispatches), in
+    start order, with start and end relative to the end of the previous step;
+    the MD sub-step launches are summarised (count, median, while the sweep
+    runs and after it)."""
+    rows = kernel_rows(a.db)
+    ends = [i for i, r in enumerate(rows) if short(r[0]).endswith("k_step_end")]
+    i0, i1 = ends[a.step - 1], ends[a.step]
+    t0 = rows[i0][2]
+    lines = [f"# rocprofv3 timeline of one coupled step: {a.title}", "", "Command (from the repository root):", "",
+             "```", a.command, "```", "",
+             f"Summary: `python -m paper_0711_2665_amd.rocprof_summary timeline --db <results.db> --step {a.step}`", "",
+             "| kernel | start us | end us | duration us |", "|---|---:|---:|---:|"]
+    md, sweep_end = [], None
+    for name, st, en, dur, gx, wx in rows[i0 + 1:i1 + 1]:
+        k = short(name)
+        if k.endswith("k_md_substep"):
+            md.append((st - t0, en - t0, dur))
+            continue
+        if "k_lb<" in k:
+            sweep_end = en - t0
+        lines.append(f"| `{k}` | {(st - t0) / 1e3:.1f} | {(en - t0) / 1e3:.1f} | {dur / 1e3:.1f} |")
+    if md:
+        d = sorted(x[2] for x in md)
+        during = [x[2] for x in md if sweep_end is not None and x[1] <= sweep_end]
+        after = [x[2] for x in md if sweep_end is not None and x[0] >= sweep_end]
+        med = lambda v: sorted(v)[len(v) // 2] / 1e3 if v else float("nan")
+        lines += ["", f"{len(md)} MD sub-step launches from {md[0][0] / 1e3:.1f} us to {md[-1][1] / 1e3:.1f} us: "
+                  f"median {med(d):.2f} us, max {d[-1] / 1e3:.1f} us; median {med(during):.2f} us over the "
+                  f"{len(during)} that ran beside the sweep, {med(after):.2f} us over the {len(after)} after it."]
+    lines += ["", f"Step span: {(rows[i1][2] - t0) / 1e3:.1f} us."]
     with open(a.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -131,6 +172,12 @@ def main():
     t.add_argument("--kernel", default="")
     t.add_argument("--last", type=int, default=0)
     t.add_argument("--skip-last", type=int, default=0)
+    tl = sub.add_parser("timeline")
+    tl.add_argument("--db", required=True)
+    tl.add_argument("--out", required=True)
+    tl.add_argument("--command", required=True)
+    tl.add_argument("--title", default="")
+    tl.add_argument("--step", type=int, default=-5)
     c = sub.add_parser("counters")
     c.add_argument("--fetch-db", required=True)
     c.add_argument("--write-db", required=True)
@@ -139,7 +186,7 @@ def main():
     c.add_argument("--out", required=True)
     c.add_argument("--command", required=True)
     a = ap.parse_args()
-    trace(a) if a.mode == "trace" else counters(a)
+    {"trace": trace, "timeline": timeline, "counters": counters}[a.mode](a)
 
 
 if __name__ == "__main__":
