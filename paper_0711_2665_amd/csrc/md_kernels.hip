@@ -115,38 +115,57 @@ __global__ void k_md_noise(Dev d, int nslots, int n_sub, int step_offset) {
   d.xi[3 * k] = x[0]; d.xi[3 * k + 1] = x[1]; d.xi[3 * k + 2] = x[2];
 }
 
-// Bending forces of the angle at (ra, rb, rc): out[0..2] the force on the
-// first bead, [3..5] on the centre, [6..8] on the third -- the values a
-// per-bead evaluation gives.
-__device__ inline void angle_forces(const MdParams& P, const double* ra, const double* rb, const double* rc,
-                                    double* out) {
-  double Fm[3] = {0.0, 0.0, 0.0}, F0[3] = {0.0, 0.0, 0.0}, Fp[3] = {0.0, 0.0, 0.0};
-  angle_add(P, ra, rb, rc, 0, Fm);
-  angle_add(P, ra, rb, rc, 1, F0);
-  angle_add(P, ra, rb, rc, 2, Fp);
-  for (int a = 0; a < 3; ++a) { out[a] = Fm[a]; out[3 + a] = F0[a]; out[6 + a] = Fp[a]; }
+// Component a of the bending forces of the angle at (ra, rb, rc): out[0] on
+// the first bead, out[1] on the centre, out[2] on the third -- the operations
+// of angle_add for that component, so the values a per-bead evaluation gives.
+__device__ inline void angle_component(const MdParams& P, const double* ra, const double* rb, const double* rc,
+                                       int a, double out[3]) {
+  double b1[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
+  double b2[3] = {rc[0] - rb[0], rc[1] - rb[1], rc[2] - rb[2]};
+  double n[3] = {b1[1] * b2[2] - b1[2] * b2[1], b1[2] * b2[0] - b1[0] * b2[2], b1[0] * b2[1] - b1[1] * b2[0]};
+  double s = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  double c = b1[0] * b2[0] + b1[1] * b2[1] + b1[2] * b2[2];
+  if (s == 0.0) {
+    // straight or folded: the contribution is exactly 0 (as in angle_add)
+    out[0] = 0.0; out[1] = 0.0; out[2] = 0.0;
+    return;
+  }
+  double phi = atan2(s, c);
+  double den = s * s + c * c;
+  const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+  double g1 = b2[a1] * n[a2] - b2[a2] * n[a1];
+  double g2 = n[a1] * b1[a2] - n[a2] * b1[a1];
+  double kp = P.kappa * phi;
+  double d1 = (c * g1 / s - s * b2[a]) / den;
+  double d2 = (c * g2 / s - s * b1[a]) / den;
+  out[0] = 0.0 + kp * d1;
+  out[1] = 0.0 + -(kp * (d1 - d2));
+  out[2] = 0.0 + -(kp * d2);
 }
 
 // ---------------------------------------------------------------------------
-// Sub-step kernel.  A workgroup of 64 lanes holds 16 consecutive bead slots
-// of one replica, 4 lanes per bead.  The lanes of a bead evaluate its LJ pair
-// forces in parallel (and, on a second lane, the wall sites) into LDS; one
-// lane then adds every contribution in the fixed order of the definition
-// (bonds to p-1 and p+1, the angles centred at p-1, p, p+1, LJ in ascending
-// partner order, wall sites, field), so the sum is the same as a
+// Sub-step kernel.  A workgroup holds 16 consecutive bead slots of one
+// replica in three waves that work side by side: in the first, 4 lanes per
+// bead evaluate its LJ pair forces; the second evaluates the bending of the
+// 18 angles that touch the 16 beads, one lane per angle and component; the
+// third the wall sites, one lane per bead and window row.  All go to LDS.
+// One lane per bead then adds every contribution in the fixed order of the
+// definition (bonds to p-1 and p+1, the angles centred at p-1, p, p+1, LJ in
+// ascending partner order, wall sites, field), so the sum is the same as a
 // one-thread-per-bead loop.
 // ---------------------------------------------------------------------------
 constexpr int MD_LANES = 4;
 constexpr int MD_WG = MD_LANES * MD_BPB;     // 64
-constexpr int MAXWALL = 16;                  // solid sites within r_c of a bead (4 x 4 window)
+constexpr int MAXWALL = 16;                  // the 4 x 4 window of wall sites around a bead
 constexpr int NB_PER_LANE = MAXNBR / MD_LANES;
 
 struct MdShared {
-  double ang[MD_BPB + 2][9];                 // forces of the angles centred at p0-1 .. p0+16 (angle_forces)
+  double ang[MD_BPB + 2][9];                 // forces of the angles centred at p0-1 .. p0+16: [0..2] on
+                                             // q-1, [3..5] on q, [6..8] on q+1
   double pairF[MD_BPB][MAXNBR][3];           // LJ pair force of list entry k
   uint32_t hit[MD_BPB][MD_LANES];            // lane l, bit m: entry l + 4m is within r_c
-  double wallF[MD_BPB][MAXWALL][3];
-  int nwall[MD_BPB];
+  double wallF[MD_BPB][MAXWALL][3];         // wall site (o1 + 1) * 4 + (o0 + 1) of each bead
+  uint32_t wmask[MD_BPB][MD_LANES];          // lane l: which sites of row o1 = l - 1 are set
   int cnt[MD_BPB];
   int lst[MD_BPB][MAXNBR];                   // the neighbour list in use (chain indices)
   double tile[MD_WG][3];                     // rebuild: positions of 64 candidates
@@ -155,15 +174,18 @@ struct MdShared {
   int over;
 };
 
-// Wall sites of the bead at rp as force vectors (each the truncated-LJ pair
-// force of one solid site within r_c), in the order z outer, x inner over the
-// sites at offsets -1..2 from the base node.  r_c < 2 makes that window
-// cover every candidate.  Solid sites lie in the plane a = wall_pos (minus
-// the pore), so at most one offset along the wall normal can match; the
-// transverse window is then visited with the higher-index axis outer.
-// Wrapping uses compares only (the window is within one period).
-__device__ inline int wall_sites(const MdParams& P, const Geom& g, const double* rp, double out[][3]) {
-  if (g.wall_axis < 0) return 0;
+// Wall sites of the bead at rp, one row of the window at a time: the sites
+// at offsets -1..2 from the base node along the lower transverse axis (o0),
+// for offset o1 along the higher one.  Each is the truncated-LJ pair force of
+// one solid site within r_c; the force of offset o0 goes to out[o0 + 1] and
+// the returned mask has bit o0 + 1 set.  r_c < 2 makes the window cover
+// every candidate.  Solid sites lie in the plane a = wall_pos (minus the
+// pore), so at most one offset along the wall normal can match.  Rows
+// o1 = -1..2, each in o0 order, visit the sites in the order of the
+// definition's sum (higher transverse axis outer).  Wrapping uses compares
+// only (the window is within one period).
+__device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const double* rp, int o1, double out[4][3]) {
+  if (g.wall_axis < 0) return 0u;
   const double w0 = wrapc(rp[0], g.nx), w1 = wrapc(rp[1], g.ny), w2 = wrapc(rp[2], g.nz);
   const int b0 = (int)floor(w0), b1 = (int)floor(w1), b2 = (int)floor(w2);
   const int a = g.wall_axis;
@@ -175,72 +197,82 @@ __device__ inline int wall_sites(const MdParams& P, const Geom& g, const double*
   int off = g.wall_pos - ba;                // offset along the normal reaching the plane
   if (off < -1) off += na;
   if (off > 2) off -= na;
-  if (off < -1 || off > 2) return 0;
+  if (off < -1 || off > 2) return 0u;
   const int sa = ba + off;
-  int n = 0;
-  for (int o1 = -1; o1 <= 2; ++o1) {
-    const int u1 = bt1 + o1;
-    const int v1 = u1 < 0 ? u1 + n1 : (u1 >= n1 ? u1 - n1 : u1);
-    const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
-    for (int o0 = -1; o0 <= 2; ++o0) {
-      const int u0 = bt0 + o0;
-      const int v0 = u0 < 0 ? u0 + n0 : (u0 >= n0 ? u0 - n0 : u0);
-      const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
-      if (in0 && in1) continue;             // pore node: fluid
-      const int sx = a == 0 ? sa : u0;
-      const int sy = a == 1 ? sa : (a == 0 ? u0 : u1);
-      const int sz = a == 2 ? sa : u1;
-      const double d0 = w0 - (double)sx, d1 = w1 - (double)sy, d2 = w2 - (double)sz;
-      if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
-      double F[3] = {0.0, 0.0, 0.0};
-      lj_add(P, d0, d1, d2, F);
-      if (n < MAXWALL) { out[n][0] = F[0]; out[n][1] = F[1]; out[n][2] = F[2]; }
-      ++n;
-    }
+  const int u1 = bt1 + o1;
+  const int v1 = u1 < 0 ? u1 + n1 : (u1 >= n1 ? u1 - n1 : u1);
+  const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
+  uint32_t mask = 0u;
+  for (int o0 = -1; o0 <= 2; ++o0) {
+    const int u0 = bt0 + o0;
+    const int v0 = u0 < 0 ? u0 + n0 : (u0 >= n0 ? u0 - n0 : u0);
+    const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
+    if (in0 && in1) continue;               // pore node: fluid
+    const int sx = a == 0 ? sa : u0;
+    const int sy = a == 1 ? sa : (a == 0 ? u0 : u1);
+    const int sz = a == 2 ? sa : u1;
+    const double d0 = w0 - (double)sx, d1 = w1 - (double)sy, d2 = w2 - (double)sz;
+    if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
+    double F[3] = {0.0, 0.0, 0.0};
+    lj_add(P, d0, d1, d2, F);
+    out[o0 + 1][0] = F[0]; out[o0 + 1][1] = F[1]; out[o0 + 1][2] = F[2];
+    mask |= 1u << (o0 + 1);
   }
-  return n;
+  return mask;
 }
 
-__global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int nslots, int s, int last) {
+__global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, int nslots, int s, int last) {
   __shared__ MdShared sh;
   const int t = threadIdx.x;
-  const int bslot = t / MD_LANES, lane = t % MD_LANES;
+  // wave 0 holds the beads (4 lanes each), wave 1 evaluates the angles and
+  // wave 2 the wall sites.  Every wave takes every barrier: the branches
+  // around barriers are uniform in the workgroup.
+  const int wave = __builtin_amdgcn_readfirstlane(t) / MD_WG;
+  const int tb = t - wave * MD_WG;           // lane within the wave
+  const int bslot = tb / MD_LANES, lane = tb % MD_LANES;
   const int slot0 = blockIdx.x * MD_BPB;
   const int slot = slot0 + bslot;            // the grid covers the nslots slots exactly
   const double* rabs = (s & 1) ? d.rmid1 : d.rmid0;
   double* rout = (s & 1) ? d.rmid0 : d.rmid1;
+  auto clampslot = [nslots](int q) { return q < 0 ? 0 : (q >= nslots ? nslots - 1 : q); };
 
   // ---- first-level loads, addressed by slot alone so that they are in
   // flight before the replica's parameters arrive.  Indices are clamped into
   // the slot range; a value from outside the chain is never used.
-  auto clampslot = [nslots](int q) { return q < 0 ? 0 : (q >= nslots ? nslots - 1 : q); };
-  double rp[3] = {rabs[3 * slot], rabs[3 * slot + 1], rabs[3 * slot + 2]};
+  double rp[3] = {0.0, 0.0, 0.0};
   int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
-  const int ncnt_in = d.ncnt[slot];
+  int ncnt_in = 0;
   int pre[NB_PER_LANE];                       // list entries lane, lane + 4, ... (past the length unused)
-#pragma unroll
-  for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = nbr_row[lane + MD_LANES * m];
-  // the bead's own state and its chain neighbours (every lane of the bead
-  // reads them; the lead lane uses them)
-  const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
   double vo[3], Jo[3], ul[3], xl[3], rm[3], rq[3], rbl[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    rbl[a] = d.rbin[3 * slot + a];
-    vo[a] = d.v[3 * slot + a];
-    Jo[a] = d.J[3 * slot + a];
-    ul[a] = d.up[3 * slot + a];
-    xl[a] = ov.on ? 0.0 : d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
-    rm[a] = rabs[3 * sm + a];
-    rq[a] = rabs[3 * sq + a];
-  }
-  // positions of the angle centred at slot slot0 - 1 + t (threads t < 18)
   double ra[3] = {0.0, 0.0, 0.0}, rb3[3] = {0.0, 0.0, 0.0}, rc[3] = {0.0, 0.0, 0.0};
-  if (t < MD_BPB + 2) {
-    const int c = slot0 - 1 + t;
-    const int ia = clampslot(c - 1), ib = clampslot(c), ic = clampslot(c + 1);
+  if (wave == 0) {
+    rp[0] = rabs[3 * slot]; rp[1] = rabs[3 * slot + 1]; rp[2] = rabs[3 * slot + 2];
+    ncnt_in = d.ncnt[slot];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) { ra[a] = rabs[3 * ia + a]; rb3[a] = rabs[3 * ib + a]; rc[a] = rabs[3 * ic + a]; }
+    for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = nbr_row[lane + MD_LANES * m];
+    // the bead's own state and its chain neighbours (every lane of the bead
+    // reads them; the lead lane uses them)
+    const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rbl[a] = d.rbin[3 * slot + a];
+      vo[a] = d.v[3 * slot + a];
+      Jo[a] = d.J[3 * slot + a];
+      ul[a] = d.up[3 * slot + a];
+      xl[a] = ov.on ? 0.0 : d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
+      rm[a] = rabs[3 * sm + a];
+      rq[a] = rabs[3 * sq + a];
+    }
+  } else if (wave == 1) {
+    if (tb < 3 * (MD_BPB + 2)) {
+      // positions of the angle centred at slot slot0 - 1 + tb / 3
+      const int c = slot0 - 1 + tb / 3;
+      const int ia = clampslot(c - 1), ib = clampslot(c), ic = clampslot(c + 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { ra[a] = rabs[3 * ia + a]; rb3[a] = rabs[3 * ib + a]; rc[a] = rabs[3 * ic + a]; }
+    }
+  } else {
+    rp[0] = rabs[3 * slot]; rp[1] = rabs[3 * slot + 1]; rp[2] = rabs[3 * slot + 2];
   }
 
   // ---- the replica
@@ -251,27 +283,22 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
   const int so = R.slot_off;
   const int p0 = slot0 - so;                 // chain index of the first bead here
   const int p = p0 + bslot;
-  const bool active = p < P.nb;
+  const bool active = wave == 0 && p < P.nb;
   const double* rin = rabs + 3 * (size_t)so; // chain-relative
   uint32_t* rbr = d.rb + 4 * rep;
   const uint32_t rebuild = rbr[s % 3];
+  const uint32_t table_stale = d.cst[4 * rep + s % 3];
   if (t == 0) {
     if (p0 == 0) {
       rbr[(s + 2) % 3] = 0u;
       d.cst[4 * rep + (s + 2) % 3] = 0u;
       if (rebuild) atomicAdd((unsigned long long*)&d.ctrl->rebuilds, 1ull);
-      if (rebuild && !d.cst[4 * rep + s % 3]) atomicAdd((unsigned long long*)&d.ctrl->cell_rebuilds, 1ull);
+      if (rebuild && !table_stale) atomicAdd((unsigned long long*)&d.ctrl->cell_rebuilds, 1ull);
     }
     if (blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, 1ull);
+    sh.over = 0;
   }
   const bool lead = active && lane == 0;
-  double u[3], xi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    u[a] = P.couple ? ul[a] : 0.0;
-    xi[a] = P.sig != 0.0 ? xl[a] : 0.0;
-  }
-  if (t == 0) sh.over = 0;
   const int ncnt0 = active ? ncnt_in : 0;
 
   // ---- neighbour list: reuse (already in registers), or rebuild -- from
@@ -283,8 +310,8 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) jl[m] = (lane + MD_LANES * m < cnt) ? pre[m] : -1;
   } else {
-    if (lane == 0) sh.cnt[bslot] = 0;
-    if (!d.cst[4 * rep + s % 3]) {
+    if (wave == 0 && lane == 0) sh.cnt[bslot] = 0;
+    if (!table_stale) {
       // lane l scans the distinct buckets l, l + 4, ... of the 27 cells
       // around the bead (a candidate binned within CELL_MARGIN of its
       // position lies in one of them); the lead lane then sorts
@@ -334,8 +361,10 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
     } else {
       for (int base = 0; base < P.nb; base += MD_WG) {
         __syncthreads();
-        int j = base + t;
-        if (j < P.nb) { sh.tile[t][0] = rin[3 * j]; sh.tile[t][1] = rin[3 * j + 1]; sh.tile[t][2] = rin[3 * j + 2]; }
+        const int j = base + tb;
+        if (wave == 0 && j < P.nb) {
+          sh.tile[tb][0] = rin[3 * j]; sh.tile[tb][1] = rin[3 * j + 1]; sh.tile[tb][2] = rin[3 * j + 2];
+        }
         __syncthreads();
         uint32_t m = 0;
         if (active) {
@@ -349,7 +378,7 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
             if (d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2) m |= 1u << e;
           }
         }
-        sh.tmask[bslot][lane] = m;
+        if (wave == 0) sh.tmask[bslot][lane] = m;
         __syncthreads();
         if (active && lane == 0) {
           uint64_t mm = (uint64_t)sh.tmask[bslot][0] | ((uint64_t)sh.tmask[bslot][1] << 16) |
@@ -384,18 +413,29 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
     }
   }
 
-  // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
-  {
+  double F[3] = {0.0, 0.0, 0.0};
+  if (wave == 1) {
+    // ---- the angles centred at p0 - 1 .. p0 + 16: lane 3 k + a takes
+    // component a of angle k
+    if (tb < 3 * (MD_BPB + 2)) {
+      const int k = tb / 3, a = tb % 3;
+      const int qc = p0 - 1 + k;
+      if (qc >= 1 && qc <= P.nb - 2) {
+        double f[3];
+        angle_component(P, ra, rb3, rc, a, f);
+        sh.ang[k][a] = f[0]; sh.ang[k][3 + a] = f[1]; sh.ang[k][6 + a] = f[2];
+      }
+    }
+  } else if (wave == 2) {
+    // ---- wall sites: lane l of a bead takes row o1 = l - 1 of the window
+    sh.wmask[bslot][lane] = p < P.nb ? wall_row(P, g, rp, lane - 1, &sh.wallF[bslot][4 * lane]) : 0u;
+  } else {
+    // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
     double q[NB_PER_LANE][3];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) {
       const int j = jl[m] >= 0 ? jl[m] : p0;   // an unused entry reads a valid slot
       q[m][0] = rin[3 * j]; q[m][1] = rin[3 * j + 1]; q[m][2] = rin[3 * j + 2];
-    }
-    // the angles while the partner positions are in flight
-    if (t < MD_BPB + 2) {
-      const int qc = p0 - 1 + t;
-      if (qc >= 1 && qc <= P.nb - 2) angle_forces(P, ra, rb3, rc, sh.ang[t]);
     }
     uint32_t hit = 0;
 #pragma unroll
@@ -405,21 +445,18 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
       double d1 = min_image(rp[1] - q[m][1], g.ny);
       double d2 = min_image(rp[2] - q[m][2], g.nz);
       if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
-      double F[3] = {0.0, 0.0, 0.0};
-      lj_add(P, d0, d1, d2, F);
+      double Fp[3] = {0.0, 0.0, 0.0};
+      lj_add(P, d0, d1, d2, Fp);
       int k = lane + MD_LANES * m;
-      sh.pairF[bslot][k][0] = F[0]; sh.pairF[bslot][k][1] = F[1]; sh.pairF[bslot][k][2] = F[2];
+      sh.pairF[bslot][k][0] = Fp[0]; sh.pairF[bslot][k][1] = Fp[1]; sh.pairF[bslot][k][2] = Fp[2];
       hit |= 1u << m;
     }
     sh.hit[bslot][lane] = hit;
-  }
-  // ---- wall sites (lane 1)
-  if (active && lane == 1) sh.nwall[bslot] = wall_sites(P, g, rp, sh.wallF[bslot]);
-  // ---- lane 0: bonds now, then every contribution in the fixed order
-  double F[3] = {0.0, 0.0, 0.0};
-  if (lead) {
-    if (p > 0) bond_add(P, rp, rm, F);
-    if (p < P.nb - 1) bond_add(P, rp, rq, F);
+    // ---- lane 0: bonds now, then every contribution in the fixed order
+    if (lead) {
+      if (p > 0) bond_add(P, rp, rm, F);
+      if (p < P.nb - 1) bond_add(P, rp, rq, F);
+    }
   }
   __syncthreads();
   if (!lead) return;
@@ -432,11 +469,18 @@ __global__ __launch_bounds__(MD_WG) void k_md_substep(Dev d, MdOverride ov, int 
     if (!((sh.hit[bslot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
     F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
   }
-  int nw = sh.nwall[bslot];
-  if (nw > MAXWALL) { atomicOr(&d.ctrl->err, E_NBRLIST); nw = MAXWALL; }
-  for (int k = 0; k < nw; ++k) { F[0] += sh.wallF[bslot][k][0]; F[1] += sh.wallF[bslot][k][1]; F[2] += sh.wallF[bslot][k][2]; }
+  for (int k = 0; k < MAXWALL; ++k) {
+    if (!((sh.wmask[bslot][k / 4] >> (k % 4)) & 1u)) continue;
+    F[0] += sh.wallF[bslot][k][0]; F[1] += sh.wallF[bslot][k][1]; F[2] += sh.wallF[bslot][k][2];
+  }
   if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
 
+  double u[3], xi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = P.couple ? ul[a] : 0.0;
+    xi[a] = P.sig != 0.0 ? xl[a] : 0.0;
+  }
   double vn[3];
   bool finite = true;
 #pragma unroll
@@ -604,7 +648,7 @@ void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOver
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
   hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov);
   for (int k = 0; k < n_sub; ++k)
-    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(MD_WG), 0, s, d, ov, nslots, k, k == n_sub - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(3 * MD_WG), 0, s, d, ov, nslots, k, k == n_sub - 1 ? 1 : 0);
 }
 
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s) {
