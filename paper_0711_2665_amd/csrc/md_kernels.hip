@@ -148,11 +148,13 @@ __device__ inline void angle_component(const MdParams& P, const double* ra, cons
 // replica in three waves that work side by side: in the first, 4 lanes per
 // bead evaluate its LJ pair forces; the second evaluates the bending of the
 // 18 angles that touch the 16 beads, one lane per angle and component; the
-// third the wall sites, one lane per bead and window row.  All go to LDS.
-// One lane per bead then adds every contribution in the fixed order of the
-// definition (bonds to p-1 and p+1, the angles centred at p-1, p, p+1, LJ in
-// ascending partner order, wall sites, field), so the sum is the same as a
-// one-thread-per-bead loop.
+// third the wall sites, one lane per bead and window row, and the bonds.  All
+// go to LDS.  One lane per bead of the third wave then adds every
+// contribution in the fixed order of the definition (bonds to p-1 and p+1,
+// the angles centred at p-1, p, p+1, LJ in ascending partner order, wall
+// sites, field), so the sum is the same as a one-thread-per-bead loop, and
+// moves the bead.  Spreading the work keeps each wave's registers few, so
+// that the workgroups fit on CUs beside the lattice sweep.
 // ---------------------------------------------------------------------------
 constexpr int MD_LANES = 4;
 constexpr int MD_WG = MD_LANES * MD_BPB;     // 64
@@ -224,9 +226,10 @@ __device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const doub
 __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, int nslots, int s, int last) {
   __shared__ MdShared sh;
   const int t = threadIdx.x;
-  // wave 0 holds the beads (4 lanes each), wave 1 evaluates the angles and
-  // wave 2 the wall sites.  Every wave takes every barrier: the branches
-  // around barriers are uniform in the workgroup.
+  // wave 0 holds the neighbour lists and LJ pairs (4 lanes per bead), wave 1
+  // evaluates the angles, wave 2 the wall sites and bonds and then moves the
+  // beads.  Every wave takes every barrier: the branches around barriers are
+  // uniform in the workgroup.
   const int wave = __builtin_amdgcn_readfirstlane(t) / MD_WG;
   const int tb = t - wave * MD_WG;           // lane within the wave
   const int bslot = tb / MD_LANES, lane = tb % MD_LANES;
@@ -243,26 +246,13 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
   int* nbr_row = d.nbr + (size_t)slot * MAXNBR;
   int ncnt_in = 0;
   int pre[NB_PER_LANE];                       // list entries lane, lane + 4, ... (past the length unused)
-  double vo[3], Jo[3], ul[3], xl[3], rm[3], rq[3], rbl[3];
+  double vo[3], Jo[3], ul[3], xl[3], rm[3], rq[3], rbl[3], rfl[3];
   double ra[3] = {0.0, 0.0, 0.0}, rb3[3] = {0.0, 0.0, 0.0}, rc[3] = {0.0, 0.0, 0.0};
   if (wave == 0) {
     rp[0] = rabs[3 * slot]; rp[1] = rabs[3 * slot + 1]; rp[2] = rabs[3 * slot + 2];
     ncnt_in = d.ncnt[slot];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = nbr_row[lane + MD_LANES * m];
-    // the bead's own state and its chain neighbours (every lane of the bead
-    // reads them; the lead lane uses them)
-    const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      rbl[a] = d.rbin[3 * slot + a];
-      vo[a] = d.v[3 * slot + a];
-      Jo[a] = d.J[3 * slot + a];
-      ul[a] = d.up[3 * slot + a];
-      xl[a] = ov.on ? 0.0 : d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
-      rm[a] = rabs[3 * sm + a];
-      rq[a] = rabs[3 * sq + a];
-    }
   } else if (wave == 1) {
     if (tb < 3 * (MD_BPB + 2)) {
       // positions of the angle centred at slot slot0 - 1 + tb / 3
@@ -298,7 +288,8 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     if (blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, 1ull);
     sh.over = 0;
   }
-  const bool lead = active && lane == 0;
+  // lane 0 of each bead in wave 2 adds the contributions and moves the bead
+  const bool lead = wave == 2 && lane == 0 && p < P.nb;
   const int ncnt0 = active ? ncnt_in : 0;
 
   // ---- neighbour list: reuse (already in registers), or rebuild -- from
@@ -427,8 +418,31 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
       }
     }
   } else if (wave == 2) {
+    // the bead's own state, its chain neighbours and its list references
+    // (every lane of the bead reads them; lane 0 uses them).  Loaded here,
+    // not with the first loads, so that they hold no registers while the
+    // other waves work; they are needed only at the end.
+    {
+      const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        rbl[a] = d.rbin[3 * slot + a];
+        rfl[a] = d.ref[3 * slot + a];
+        vo[a] = d.v[3 * slot + a];
+        Jo[a] = d.J[3 * slot + a];
+        ul[a] = d.up[3 * slot + a];
+        xl[a] = ov.on ? 0.0 : d.xi[(size_t)3 * ((size_t)s * nslots + slot) + a];
+        rm[a] = rabs[3 * sm + a];
+        rq[a] = rabs[3 * sq + a];
+      }
+    }
     // ---- wall sites: lane l of a bead takes row o1 = l - 1 of the window
     sh.wmask[bslot][lane] = p < P.nb ? wall_row(P, g, rp, lane - 1, &sh.wallF[bslot][4 * lane]) : 0u;
+    // ---- lane 0: bonds now, the rest after the barrier
+    if (lead) {
+      if (p > 0) bond_add(P, rp, rm, F);
+      if (p < P.nb - 1) bond_add(P, rp, rq, F);
+    }
   } else {
     // ---- LJ pair forces: lane l handles list entries l, l + 4, l + 8, ...
     double q[NB_PER_LANE][3];
@@ -452,20 +466,18 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
       hit |= 1u << m;
     }
     sh.hit[bslot][lane] = hit;
-    // ---- lane 0: bonds now, then every contribution in the fixed order
-    if (lead) {
-      if (p > 0) bond_add(P, rp, rm, F);
-      if (p < P.nb - 1) bond_add(P, rp, rq, F);
-    }
+    if (lane == 0) sh.cnt[bslot] = cnt;
   }
   __syncthreads();
   if (!lead) return;
+  // every contribution in the fixed order
+  const int cnt_b = sh.cnt[bslot];
   const int q0 = p0 - 1;
   const int nb = P.nb;
   if (p - 1 >= 1 && p - 1 <= nb - 2) { const double* A = sh.ang[p - 1 - q0]; F[0] += A[6]; F[1] += A[7]; F[2] += A[8]; }
   if (p >= 1 && p <= nb - 2) { const double* A = sh.ang[p - q0]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
   if (p + 1 >= 1 && p + 1 <= nb - 2) { const double* A = sh.ang[p + 1 - q0]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2]; }
-  for (int k = 0; k < cnt; ++k) {
+  for (int k = 0; k < cnt_b; ++k) {
     if (!((sh.hit[bslot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
     F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
   }
@@ -506,7 +518,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     for (int a = 0; a < 3; ++a) {
       double x = re[a] + P.hh * vn[a];
       rout[3 * slot + a] = x;
-      double dd = x - d.ref[3 * slot + a];
+      double dd = x - (rebuild ? rp[a] : rfl[a]);   // a rebuild this sub-step set ref = r_mid
       d2 += dd * dd;
       double db = x - rbl[a];
       b2 += db * db;

@@ -225,7 +225,11 @@ def test_coupled_step_autotuner_restores_the_state():
     assert best["ms"] > 0.0 and best["tile_nodes"] % 256 == 0
     torch.cuda.synchronize()
     _assert_same(_snapshot(e), before, "autotune changed the state")
-    assert e.diagnostics() == diag and e.step_count() == steps and e.translocation_steps() == tx
+    after = e.diagnostics()
+    for k in ("sweep_tiles",):   # the layout, which the autotuner sets
+        after.pop(k)
+        diag.pop(k)
+    assert after == diag and e.step_count() == steps and e.translocation_steps() == tx
     e.run(2, graph=True)
     torch.cuda.synchronize()
     _assert_same(_snapshot(e), want, "after the coupled autotune")
