@@ -55,27 +55,17 @@ __global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restri
     const uint8_t* fr = flags + no;
     const T* Fr = force + (size_t)3 * no;
     const int end = min(tl.start + tile_nodes, R.lp.N);
-    if (tl.near) {
-      // a tile touching the wall: one node per thread and pass, each pull
-      // with bounce-back
-      for (int c = tl.start + (int)threadIdx.x; c < end; c += 256) {
-        const uint8_t fl = fr[c];
-        if ((fl & F_SOLID) || (skip_forced && (fl & F_FORCED))) continue;
-        lb_node<T, DEV>(Ar, Br, fr, Fr, R.lp, ctrl, c, fl);
-      }
-    } else {
-      // U nodes per thread and pass, 256 apart, their loads issued together
-      for (int c0 = tl.start + (int)threadIdx.x; c0 < end; c0 += U * 256) {
-        int c[U];
-        bool in[U];
+    // U nodes per thread and pass, 256 apart, their loads issued together
+    for (int c0 = tl.start + (int)threadIdx.x; c0 < end; c0 += U * 256) {
+      int c[U];
+      bool in[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int cu = c0 + u * 256;
-          in[u] = cu < end;
-          c[u] = in[u] ? cu : c0;           // past the tile: pull a valid node, store nothing
-        }
-        lb_nodes_bulk<T, DEV, U>(Ar, Br, fr, Fr, R.lp, ctrl, c, in, skip_forced);
+      for (int u = 0; u < U; ++u) {
+        const int cu = c0 + u * 256;
+        in[u] = cu < end;
+        c[u] = in[u] ? cu : c0;             // past the tile: pull a valid node, store nothing
       }
+      lb_nodes<T, DEV, U>(Ar, Br, fr, Fr, R.lp, ctrl, c, in, skip_forced);
     }
     if (tn >= ntiles) break;
     t = tn;

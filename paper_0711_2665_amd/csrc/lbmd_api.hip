@@ -290,7 +290,6 @@ struct lb_ctx {
   bool noise_ready = false;  // the noise slot of the current population parity holds this step's noise
   SweepCfg sweep;
   int ntiles = 0;
-  std::vector<std::vector<uint8_t>> near_blocks;   // per replica and TILE_MIN nodes: solid or wall-adjacent
   int64_t steps = 0;
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
@@ -327,12 +326,7 @@ std::vector<Tile> tile_table(const lb_ctx* c, const SweepCfg& sc) {
   std::vector<Tile> t;
   for (int r = 0; r < c->nrep; ++r) {
     const int N = c->reps[r].lp.N;
-    const std::vector<uint8_t>& nb = c->near_blocks[r];
-    for (int st = 0; st < N; st += sc.tile_nodes) {
-      int near = 0;
-      for (int b = st / TILE_MIN; b < (st + sc.tile_nodes) / TILE_MIN && b < (int)nb.size(); ++b) near |= nb[b];
-      t.push_back(Tile{r, st, near});
-    }
+    for (int st = 0; st < N; st += sc.tile_nodes) t.push_back(Tile{r, st});
   }
   if (sc.order == 1 && t.size() >= 16) {
     const size_t n = t.size(), nch = 8, per = (n + nch - 1) / nch;
@@ -652,7 +646,6 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   std::vector<int> slot_rep(ns, 0);
   std::vector<Tile> ot;
   c->reps.resize(nrep);
-  c->near_blocks.resize(nrep);
   for (int r = 0; r < nrep; ++r) {
     Rep& R = c->reps[r];
     std::memset(&R, 0, sizeof(Rep));
@@ -678,12 +671,7 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
       }
     }
     R.tile_begin = (int)ot.size();
-    for (int st = 0; st < R.lp.N; st += OBS_TILE) ot.push_back(Tile{r, st, 0});
-    // per TILE_MIN nodes: whether any is solid or next to a solid node
-    std::vector<uint8_t>& nbk = c->near_blocks[r];
-    nbk.assign((size_t)((R.lp.N + TILE_MIN - 1) / TILE_MIN), 0);
-    for (long k = 0; k < R.lp.N; ++k)
-      if (fl[(size_t)(R.node_off + k)] & (F_SOLID | F_NEAR)) nbk[(size_t)(k / TILE_MIN)] = 1;
+    for (int st = 0; st < R.lp.N; st += OBS_TILE) ot.push_back(Tile{r, st});
     R.tile_end = (int)ot.size();
   }
 

@@ -56,7 +56,6 @@ struct Rep {
 struct Tile {
   int rep;
   int start;
-  int near;         // sweep tiles: some node of the tile is solid or next to a solid node
 };
 
 // Every device array a kernel may touch.

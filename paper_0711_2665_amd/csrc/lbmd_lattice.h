@@ -181,15 +181,39 @@ __device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const
   for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c], f[i]);
 }
 
-// Stream + collide U nodes c[u] of one replica, none of them next to a solid
-// node: the flags and straight pulls of all U nodes are issued together.
-// Nodes with in[u] false (c[u] must still be a valid node), solid nodes and,
-// with skip_forced, nodes carrying bead force are neither collided nor
-// stored.
+// Halfway bounce-back at a node next to a wall, after a straight pull: the
+// populations pulled from solid upstream nodes are replaced by the node's own
+// opposite populations -- the values pull gives.  The replacements arrive
+// before it returns, so no load of it is outstanding in the caller.
+template <typename T>
+__device__ inline void bounce_back(const T* __restrict__ A, const uint8_t* __restrict__ flags, const LbParams& p,
+                                   int c, T f[Q]) {
+  const size_t N = (size_t)p.N;
+  int x = c % p.nx;
+  int yz = c / p.nx;
+  const Nbr nb = make_nbr(p, x, yz % p.ny, yz / p.ny);
+  uint8_t sf[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) sf[i] = flags[c + nb.off(-cx(i), -cy(i), -cz(i))];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const T r = A[(size_t)opp(i) * N + (size_t)c];
+    f[i] = (sf[i] & F_SOLID) ? r : f[i];
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) asm volatile("" ::"v"(f[i]));
+}
+
+// Stream + collide U nodes c[u] of one replica (c[u] must be a valid node
+// also where in[u] is false).  The flags and the straight pulls f_i =
+// A_i(x - c_i) of all U nodes are issued together (a straight pull is a valid
+// read at any node); a node next to a wall then replaces what came from solid
+// nodes.  Nodes with in[u] false, solid nodes and, with skip_forced, nodes
+// carrying bead force are neither collided nor stored.
 template <typename T, bool DEV, int U>
-__device__ inline void lb_nodes_bulk(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
-                                     const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl,
-                                     const int c[U], const bool in[U], int skip_forced) {
+__device__ inline void lb_nodes(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
+                                const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl,
+                                const int c[U], const bool in[U], int skip_forced) {
   const size_t N = (size_t)p.N;
   uint8_t fl[U];
   T f[U][Q];
@@ -203,6 +227,14 @@ __device__ inline void lb_nodes_bulk(const T* __restrict__ A, T* __restrict__ B,
     for (int i = 0; i < Q; ++i)
       f[u][i] = A[(size_t)i * N + (size_t)(c[u] + nb.off(-cx(i), -cy(i), -cz(i)))];
   }
+  // every pull is taken here, so none is deferred behind the flag tests
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) asm volatile("" ::"v"(f[u][i]));
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (fl[u] & F_NEAR) bounce_back<T>(A, flags, p, c[u], f[u]);
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (!in[u] || (fl[u] & F_SOLID) || (skip_forced && (fl[u] & F_FORCED))) continue;
