@@ -135,6 +135,81 @@ void gauss3(uint32_t seed, uint32_t rep, uint32_t n, uint32_t s, uint32_t p, dou
   xi[2] = rb * std::cos(two_pi * u3);
 }
 
+// ---------------------------------------------------------------------------
+// Fluctuating lattice Boltzmann (Sec. 2, the stochastic term F_i: a noisy
+// stress on the five shear/bulk stress modes plus noise on the ghost modes,
+// in the mode formulation of Adhikari et al. the paper refers to).  Reading:
+// the 19 populations are mapped to 19 moments m_k = sum_i e_ki f_i of a basis
+// orthogonal under the weights, sum_i w_i e_ki e_li = b_k delta_kl; the BGK
+// collision relaxes every non-conserved mode by the same factor 1 - omega;
+// fluctuation-dissipation then fixes the noise on each non-conserved mode k
+// as sqrt(mu b_k (1 - (1 - omega)^2)) r_k with mu = rho kT / c_s^2 and r_k
+// standard normal, mapped back by f_i += w_i sum_k e_ki noise_k / b_k.
+// The basis, in powers of the lattice velocity c:
+//   k = 0: 1;  1..3: c_x, c_y, c_z;  4: c^2 - 1;  5: 3 c_x^2 - c^2;
+//   6: c_y^2 - c_z^2;  7..9: c_x c_y, c_y c_z, c_z c_x;
+//   10..12: (3 c^2 - 5) c_x, (3 c^2 - 5) c_y, (3 c^2 - 5) c_z;
+//   13..15: (c_y^2 - c_z^2) c_x, (c_z^2 - c_x^2) c_y, (c_x^2 - c_y^2) c_z;
+//   16: 3 c^4 - 6 c^2 + 1;  17: (2 c^2 - 3)(3 c_x^2 - c^2);
+//   18: (2 c^2 - 3)(c_y^2 - c_z^2).
+// Modes 0..3 (mass, momentum) are conserved and get no noise.
+// ---------------------------------------------------------------------------
+inline double mode_poly(int k, int i) {
+  const double x = CV[i][0], y = CV[i][1], z = CV[i][2];
+  const double c2 = x * x + y * y + z * z;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return y;
+    case 3: return z;
+    case 4: return c2 - 1.0;
+    case 5: return 3.0 * x * x - c2;
+    case 6: return y * y - z * z;
+    case 7: return x * y;
+    case 8: return y * z;
+    case 9: return z * x;
+    case 10: return (3.0 * c2 - 5.0) * x;
+    case 11: return (3.0 * c2 - 5.0) * y;
+    case 12: return (3.0 * c2 - 5.0) * z;
+    case 13: return (y * y - z * z) * x;
+    case 14: return (z * z - x * x) * y;
+    case 15: return (x * x - y * y) * z;
+    case 16: return 3.0 * c2 * c2 - 6.0 * c2 + 1.0;
+    case 17: return (2.0 * c2 - 3.0) * (3.0 * x * x - c2);
+    default: return (2.0 * c2 - 3.0) * (y * y - z * z);
+  }
+}
+
+// Norm b_k = sum_i w_i e_ki^2 of a basis vector.
+inline double mode_norm(int k) {
+  double b = 0.0;
+  for (int i = 0; i < Q; ++i) b += weight(i) * mode_poly(k, i) * mode_poly(k, i);
+  return b;
+}
+
+// Sixteen standard normals for fluid node `node` of replica `rep` at LB step
+// n: four Philox blocks with key (seed, replica) and counter (n, node, k, 1),
+// k = 0..3 (the bead noise uses counter word 3 = 0), uniforms (x + 1/2) 2^-32,
+// Box-Muller on (u0,u1) and (u2,u3) of each block, cosine then sine.
+void fluid_normals(uint32_t seed, uint32_t rep, uint32_t n, uint32_t node, double r[16]) {
+  const double two32inv = 1.0 / 4294967296.0;
+  const double two_pi = 6.283185307179586;
+  uint32_t key[2] = {seed, rep};
+  for (uint32_t k = 0; k < 4; ++k) {
+    uint32_t ctr[4] = {n, node, k, 1u};
+    uint32_t x[4];
+    philox4x32_10(ctr, key, x);
+    double u[4];
+    for (int j = 0; j < 4; ++j) u[j] = ((double)x[j] + 0.5) * two32inv;
+    double ra = std::sqrt(-2.0 * std::log(u[0]));
+    double rb = std::sqrt(-2.0 * std::log(u[2]));
+    r[4 * k + 0] = ra * std::cos(two_pi * u[1]);
+    r[4 * k + 1] = ra * std::sin(two_pi * u[1]);
+    r[4 * k + 2] = rb * std::cos(two_pi * u[3]);
+    r[4 * k + 3] = rb * std::sin(two_pi * u[3]);
+  }
+}
+
 }  // namespace orc
 
 // ---------------------------------------------------------------------------
@@ -153,6 +228,7 @@ typedef struct {
   double gamma, kT, f_drive;
   int n_sub;           // MD sub-steps per LB step
   uint32_t seed, replica;
+  double fluid_kT;     // thermal energy of the fluid noise (0: athermal BGK fluid)
 } or_desc;
 }
 
@@ -303,6 +379,26 @@ struct Sim {
     }
   }
 
+  // The stochastic term of the fluctuating fluid at node c (see
+  // fluid_normals and mode_poly): with rho from the pulled populations f,
+  // noise_k = sqrt(3 rho kT (1 - (1 - omega)^2) / b_k) r_{k-4} on modes
+  // k = 4..18, added as out_i += w_i sum_k e_ki noise_k in ascending k.
+  void fluctuate(long c, const R f[Q], R out[Q]) const {
+    double r[16];
+    fluid_normals(d.seed, d.replica, (uint32_t)step, (uint32_t)c, r);
+    R rho = R(0.0);
+    for (int i = 0; i < Q; ++i) rho += f[i];
+    const double g2 = (1.0 - omega) * (1.0 - omega);
+    R noise[Q];
+    for (int k = 4; k < Q; ++k)
+      noise[k] = dsqrt(R(3.0 * d.fluid_kT * (1.0 - g2) / mode_norm(k)) * rho) * R(r[k - 4]);
+    for (int i = 0; i < Q; ++i) {
+      R s = R(0.0);
+      for (int k = 4; k < Q; ++k) s += R(mode_poly(k, i)) * noise[k];
+      out[i] = out[i] + R(weight(i)) * s;
+    }
+  }
+
   // One LB time step: stream (pull) + collide every fluid node, A -> B, then
   // swap.  Solid nodes are never written.  The bounce-back momentum given to
   // the wall is recorded in ledger_bb.
@@ -321,6 +417,7 @@ struct Sim {
           for (int i = 0; i < Q; ++i) f[i] = pulled(A, x, y, z, i);
           for (int a = 0; a < 3; ++a) Fx[a] = F[(size_t)a * N + c] + R(d.g[a]);
           collide(f, Fx, out);
+          if (d.fluid_kT > 0.0) fluctuate(c, f, out);
           for (int i = 0; i < Q; ++i) B[(size_t)i * N + c] = out[i];
           for (int i = 1; i < Q; ++i) {
             long src = idx(wrapi(x - CV[i][0], nx), wrapi(y - CV[i][1], ny), wrapi(z - CV[i][2], nz));
@@ -834,6 +931,10 @@ void or_feq(double rho, const double* u, double* out) {
 }
 void or_collide(void* h, const double* f, const double* F, double* out) { ((SimD*)h)->collide(f, F, out); }
 void or_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { orc::philox4x32_10(ctr, key, out); }
+double or_mode_poly(int k, int i) { return orc::mode_poly(k, i); }
+void or_fluid_normals(uint32_t seed, uint32_t rep, uint32_t n, uint32_t node, double* out) {
+  orc::fluid_normals(seed, rep, n, node, out);
+}
 void or_gauss3(uint32_t seed, uint32_t rep, uint32_t n, uint32_t s, uint32_t p, double* out) {
   orc::gauss3(seed, rep, n, s, p, out);
 }

@@ -28,6 +28,7 @@ class OrDesc(C.Structure):
         ("kappa", C.c_double), ("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double),
         ("gamma", C.c_double), ("kT", C.c_double), ("f_drive", C.c_double),
         ("n_sub", C.c_int), ("seed", C.c_uint32), ("replica", C.c_uint32),
+        ("fluid_kT", C.c_double),
     ]
 
 
@@ -60,6 +61,9 @@ def _declare(L):
     L.or_collide.argtypes = [_P, _DP, _DP, _DP]
     L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
     L.or_gauss3.argtypes = [C.c_uint32] * 5 + [_DP]
+    L.or_mode_poly.restype = C.c_double
+    L.or_mode_poly.argtypes = [C.c_int, C.c_int]
+    L.or_fluid_normals.argtypes = [C.c_uint32] * 4 + [_DP]
     L.or_stencil.argtypes = [_P, _DP, C.POINTER(C.c_longlong), _DP]
     L.or_gather.argtypes = [_P, _DP]
     L.or_spread.argtypes = [_P, _DP, _DP]
@@ -108,6 +112,7 @@ def make_desc(cfg):
     d.n_sub = cfg.get("n_sub", 100)
     d.seed = cfg.get("seed", 1234) & 0xFFFFFFFF
     d.replica = cfg.get("replica", 0) & 0xFFFFFFFF
+    d.fluid_kT = cfg.get("fluid_kT", 0.0)
     return d
 
 
@@ -276,6 +281,18 @@ def philox(ctr, key):
 def gauss3(seed, rep, n, s, p):
     out = np.empty(3)
     lib().or_gauss3(seed, rep, n, s, p, _dp(out))
+    return out
+
+
+def mode_basis():
+    """The oracle's 19 x 19 mode matrix e[k][i] of the fluctuating fluid."""
+    L = lib()
+    return np.array([[L.or_mode_poly(k, i) for i in range(19)] for k in range(19)])
+
+
+def fluid_normals(seed, rep, n, node):
+    out = np.empty(16)
+    lib().or_fluid_normals(seed, rep, n, node, _dp(out))
     return out
 
 
