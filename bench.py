@@ -19,8 +19,9 @@ the library on the stream it runs on, over the same number of eager steps),
 the eager steps' rate, the FP64 path on the same workload, bead throughput, the
 batched ensemble (64 uneven replicas in one context, graph replay, aggregate
 MLUPS and translocation steps), the adjoint on the 64^3 gradient workload
-(adjoint steps/s in FP64 and FP32, a finite-difference check), and the FP64
-CPU oracle timed on a bounded sample.
+(adjoint steps/s in FP64 and FP32, a finite-difference check), the same
+workload with a fluctuating fluid (noise on the non-conserved modes drawn in
+the sweep), and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -270,6 +271,7 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=5000)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--no-thermal", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -333,6 +335,20 @@ def main():
                        "eager_ms_per_step": round(1e3 * r64["eager_seconds"] / k64, 4),
                        "sweep_alone": sweep_alone(r64, cells, 8),
                        "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
+    if not args.no_thermal:
+        # the same workload with a fluctuating fluid at the beads' temperature
+        from paper_0711_2665_amd.workloads import scaled
+        kth = max(20, args.steps // 2)
+        rt = run_gpu(scaled(cfg, fluid_kT=cfg["kT"]), args.precision, kth, args.warmup)
+        ut = rt["nfluid"] - rt["forced_per_step"]
+        acht = (ut * lb_bytes_per_update(elem) + (cells - ut)) / (rt["lb_ms"] * 1e-3) / 1e9
+        out["thermal_fluid"] = {"value": round(cells * kth / rt["seconds"] / 1e6, 1), "unit": "MLUPS",
+                                "steps": kth, "fluid_kT": cfg["kT"],
+                                "ms_per_step": round(1e3 * rt["seconds"] / kth, 4),
+                                "sweep_layout": {k: rt["tune"][k] for k in ("tile_nodes", "order", "grid", "cap")},
+                                "sweep_alone": sweep_alone(rt, cells, elem),
+                                "lb_sweep_gbs": round(acht, 1), "lb_sweep_frac": round(acht / PEAK_HBM_GBS, 4),
+                                "lb_sweep_mean_launch_ms": round(rt["lb_ms"], 5)}
     if not args.no_ensemble and args.workload == "c3":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 20, 200)
     if not args.no_adjoint and args.workload == "c3":

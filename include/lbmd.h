@@ -91,7 +91,13 @@ typedef struct lb_desc {
   double gamma, kT;       /* friction rate and thermal energy of the beads   */
   double f_drive;         /* force along +normal on beads in the pore channel */
   int32_t n_sub;          /* MD sub-steps per LB step                        */
-  uint32_t seed, replica; /* Philox key of the bead noise                     */
+  uint32_t seed, replica; /* Philox key of the bead and the fluid noise       */
+  double fluid_kT;        /* thermal energy of the fluctuating fluid (Sec. 2,
+                             the stochastic term F_i, read as noise on the 15
+                             non-conserved D3Q19 modes with the amplitudes of
+                             fluctuation-dissipation); 0: athermal BGK fluid.
+                             Node c of a replica draws, at LB step n, Philox-
+                             4x32-10 of counters (n, c, k, 1), k = 0..3       */
 } lb_desc;
 
 /* Byte sizes of the caller-allocated device buffers (256-byte aligned), and
@@ -124,7 +130,8 @@ typedef struct lb_ctx lb_ctx;
 /* Validates *d and fills *out.  Host only: calls no HIP function.
  * LB_ERR_ARG: extents <= 0 or 19 N > 2^31 - 1, tau <= 0.5, a wall plane
  * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
- * gamma or kT, rc outside (0, 2], or nb > 0 without a positive mass. */
+ * gamma, kT or fluid_kT, rc outside (0, 2], or nb > 0 without a positive
+ * mass. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
 
 /* As lb_buffer_sizes for nrep replicas d[0..nrep-1] in one context.  All
@@ -214,9 +221,9 @@ int lb_sweep_config(lb_ctx* ctx, int tile_nodes, int order, int grid, int cap);
  * the next step overwrites, so the state is unchanged), keeps the first
  * candidate within
  * 1% of the fastest and caches it for the process by (replica extents,
- * walls and chain lengths, precision).
+ * walls and chain lengths, precision, athermal or fluctuating fluid).
  * Writes {tile_nodes, order, grid, cap} to out_cfg[4] and the mean sweep
- * time in ms to *out_ms (-1 when taken from the cache).  With the
+ * time in ms to *out_ms (the time measured when the entry was cached).  With the
  * environment variable LBMD_AUTOTUNE_LOG set, every candidate's time is
  * printed to stderr.  Synchronises the stream.
  * LB_ERR_ARG: reps < 1; LB_ERR_DEVICE: a HIP call failed. */
@@ -230,7 +237,8 @@ int lb_autotune(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
  * temporary device buffer first (hipMalloc'd here, about pops_bytes +
  * force_bytes + beads_bytes + work_bytes) and restored after every
  * candidate, with the step count: the state and every later result are
- * unchanged.  *out_ms is the mean coupled-step time (-1 when cached).
+ * unchanged.  *out_ms is the mean coupled-step time (as measured when the
+ * entry was cached).
  * Synchronises the stream.  LB_ERR_ARG: reps < 1; LB_ERR_DEVICE: a HIP call
  * failed (the state is restored when the snapshot exists). */
 int lb_autotune_step(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
@@ -252,8 +260,9 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * conservative forces), gathering -- using the populations and bead state of
  * that step, recomputed segment by segment from checkpoints taken every K
  * steps of the forward pass.
- * Supported: one-replica contexts with 1 <= nb <= 128 and gamma > 0
- * (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either precision.
+ * Supported: one-replica contexts with 1 <= nb <= 128, gamma > 0 and an
+ * athermal fluid, fluid_kT = 0 (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise);
+ * either precision.
  *
  * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1
  *   checkpoints of lb_sizes.state_bytes, K population arrays of tape, the

@@ -34,7 +34,7 @@ __global__ void k_fill_f64(double* __restrict__ p, long n, double v) {
 // and so are nodes carrying a bead force when skip_forced is set (they are
 // updated by k_lb_forced once the force is known).
 // ---------------------------------------------------------------------------
-template <typename T, bool DEV, int U>
+template <typename T, bool DEV, int U, bool FL>
 __global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restrict__ B,
                                             const Tile* __restrict__ tiles, const Rep* __restrict__ reps,
                                             const uint8_t* __restrict__ flags, const T* __restrict__ force,
@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restri
   // the next tile's record is requested before this tile's work.
   int t = blockIdx.x;
   if (t >= ntiles) return;
+  const uint32_t n = FL ? (uint32_t)ctrl->step : 0u;   // LB step: counter word 0 of the fluid noise
   Tile tl = tiles[t];
   for (;;) {
     const int tn = t + (int)gridDim.x;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void k_lb(const T* __restrict__ A, T* __restri
         in[u] = cu < end;
         c[u] = in[u] ? cu : c0;             // past the tile: pull a valid node, store nothing
       }
-      lb_nodes<T, DEV, U>(Ar, Br, fr, Fr, R.lp, ctrl, c, in, skip_forced);
+      lb_nodes<T, DEV, U, FL>(Ar, Br, fr, Fr, R.lp, ctrl, c, in, skip_forced, n);
     }
     if (tn >= ntiles) break;
     t = tn;
@@ -458,23 +459,30 @@ void launch_fill_f64(double* p, long n, double v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
+template <typename T, bool DEV, bool FL>
+static void launch_lb_u(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int gsz, size_t lds,
+                        int skip_forced, hipStream_t s) {
+  const int per = tile_nodes / 256;         // nodes per thread and tile
+  if (per >= 4)
+    hipLaunchKernelGGL((k_lb<T, DEV, 4, FL>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles,
+                       d.reps, d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
+  else if (per >= 2)
+    hipLaunchKernelGGL((k_lb<T, DEV, 2, FL>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles,
+                       d.reps, d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
+  else
+    hipLaunchKernelGGL((k_lb<T, DEV, 1, FL>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles,
+                       d.reps, d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
+}
+
 template <typename T, bool DEV>
 void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int cap, int skip_forced,
-               hipStream_t s) {
+               bool fluct, hipStream_t s) {
   int gsz = (grid > 0 && grid < ntiles) ? grid : ntiles;
-  const int per = tile_nodes / 256;         // nodes per thread and tile
   // LDS the kernel does not use, reserved so that at most `cap` sweep
   // workgroups share a CU
   const size_t lds = cap > 0 ? (size_t)((LDS_PER_CU - LDS_KEEP) / cap) & ~(size_t)1023 : 0;
-  if (per >= 4)
-    hipLaunchKernelGGL((k_lb<T, DEV, 4>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles, d.reps,
-                       d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
-  else if (per >= 2)
-    hipLaunchKernelGGL((k_lb<T, DEV, 2>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles, d.reps,
-                       d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
-  else
-    hipLaunchKernelGGL((k_lb<T, DEV, 1>), dim3((unsigned)gsz), dim3(256), lds, s, (const T*)A, (T*)B, d.tiles, d.reps,
-                       d.flags, (const T*)d.force, d.ctrl, ntiles, tile_nodes, skip_forced);
+  if (fluct) launch_lb_u<T, DEV, true>(A, B, d, ntiles, tile_nodes, gsz, lds, skip_forced, s);
+  else launch_lb_u<T, DEV, false>(A, B, d, ntiles, tile_nodes, gsz, lds, skip_forced, s);
 }
 
 template <typename T, bool DEV>
@@ -521,8 +529,8 @@ void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, dou
 
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);
 template void launch_fill_rest<float, true>(void*, long, hipStream_t);
-template void launch_lb<double, false>(const void*, void*, const Dev&, int, int, int, int, int, hipStream_t);
-template void launch_lb<float, true>(const void*, void*, const Dev&, int, int, int, int, int, hipStream_t);
+template void launch_lb<double, false>(const void*, void*, const Dev&, int, int, int, int, int, bool, hipStream_t);
+template void launch_lb<float, true>(const void*, void*, const Dev&, int, int, int, int, int, bool, hipStream_t);
 template void launch_lb_forced<double, false>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_lb_forced<float, true>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_gather<double, false>(const void*, const Dev&, int, hipStream_t);

@@ -161,6 +161,8 @@ int validate_one(const lb_desc* d, int r) {
     int t1 = d->wall_axis == 2 ? d->ny : d->nz;
     if (d->pore_h < 0 || d->pore_h > t0 || d->pore_h > t1) return fail(LB_ERR_ARG, "replica %d: pore wider than the wall", r);
   }
+  if (!(d->fluid_kT >= 0.0) || !std::isfinite(d->fluid_kT))
+    return fail(LB_ERR_ARG, "replica %d: fluid_kT must be finite and >= 0", r);
   if (d->nb < 0) return fail(LB_ERR_ARG, "replica %d: negative bead count", r);
   if (d->n_sub < 1) return fail(LB_ERR_ARG, "replica %d: n_sub must be >= 1", r);
   if (d->nb > 0) {
@@ -239,6 +241,24 @@ MdParams make_md(const lb_desc* d, double skin) {
   return P;
 }
 
+// Noise amplitudes of the fluctuating fluid: mode k (4..18) receives
+// sqrt(rho mu_k) r with mu_k = 3 kT (1 - (1 - omega)^2) / b_k, b_k =
+// sum_i w_i e_ki^2 (fluctuation-dissipation for a mode relaxed by the
+// factor 1 - omega each step, at c_s^2 = 1/3).
+void fluid_noise_params(LbParams& lp, const lb_desc& d) {
+  lp.fluct = d.fluid_kT > 0.0 ? 1 : 0;
+  lp.fseed = d.seed;
+  lp.frep = d.replica;
+  const double keep = 1.0 - lp.omega;
+  for (int k = 4; k < Q; ++k) {
+    double b = 0.0;
+    for (int i = 0; i < Q; ++i) b += wgt(i) * (double)(mode_coef(k, i) * mode_coef(k, i));
+    const double a = lp.fluct ? std::sqrt(3.0 * d.fluid_kT * (1.0 - keep * keep) / b) : 0.0;
+    lp.famp[k - 4] = a;
+    lp.famp32[k - 4] = (float)a;
+  }
+}
+
 // Solid / near-wall flags of one replica (Sec. 4: wall plane with a square
 // pore); returns the number of fluid nodes.
 long build_flags(const Geom& g, uint8_t* fl) {
@@ -287,6 +307,7 @@ struct lb_ctx {
   bool step_lists = false;   // neighbour lists built from a cell list at every coupled step
   bool lists_stale = true;   // the positions changed outside a coupled step since the last build
   bool any_noise = false;
+  bool any_fluct = false;    // some replica has a fluctuating fluid
   bool noise_ready = false;  // the noise slot of the current population parity holds this step's noise
   SweepCfg sweep;
   int ntiles = 0;
@@ -366,10 +387,11 @@ void prof_next(lb_ctx* c) {
 }
 
 void sweep_ab(lb_ctx* c, const void* A, void* B, int skip_forced, hipStream_t st) {
+  const SweepCfg& w = c->sweep;
   if (c->dev)
-    launch_lb<float, true>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, c->sweep.cap, skip_forced, st);
+    launch_lb<float, true>(A, B, c->D, c->ntiles, w.tile_nodes, w.grid, w.cap, skip_forced, c->any_fluct, st);
   else
-    launch_lb<double, false>(A, B, c->D, c->ntiles, c->sweep.tile_nodes, c->sweep.grid, c->sweep.cap, skip_forced, st);
+    launch_lb<double, false>(A, B, c->D, c->ntiles, w.tile_nodes, w.grid, w.cap, skip_forced, c->any_fluct, st);
 }
 void sweep(lb_ctx* c, int skip_forced, hipStream_t st) { sweep_ab(c, cur_pops(c), other_pops(c), skip_forced, st); }
 
@@ -546,6 +568,7 @@ int adj_check(const lb_ctx* c, int nsteps, int K) {
   if (d.nb < 1 || d.nb > MAX_ADJ_BEADS)
     return fail(LB_ERR_UNSUPPORTED, "the adjoint needs 1 <= nb <= %d (got %d)", MAX_ADJ_BEADS, d.nb);
   if (!(c->reps[0].mp.gamma > 0.0)) return fail(LB_ERR_ARG, "the adjoint needs gamma > 0");
+  if (c->reps[0].lp.fluct) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs an athermal fluid (fluid_kT = 0)");
   if (nsteps < 1 || K < 1) return fail(LB_ERR_ARG, "nsteps and K must be >= 1");
   if (c->prof_on) return fail(LB_ERR_ARG, "profiling is active");
   return LB_OK;
@@ -655,8 +678,10 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     R.lp.omega = 1.0 / d[r].tau;
     for (int a = 0; a < 3; ++a) R.lp.g[a] = d[r].g[a];
     R.lp.has_g = (d[r].g[0] != 0.0 || d[r].g[1] != 0.0 || d[r].g[2] != 0.0) ? 1 : 0;
+    fluid_noise_params(R.lp, d[r]);
     R.mp = make_md(&d[r], skin);
     if (R.mp.nb > 0 && R.mp.sig != 0.0) c->any_noise = true;
+    if (R.lp.fluct) c->any_fluct = true;
     R.node_off = c->pk.node_off[r];
     R.slot_off = c->pk.slot_off[r];
     R.nslot = (int)round_up(d[r].nb, MD_BPB);
@@ -1071,13 +1096,15 @@ void snapshot_restore(lb_ctx* c, const Snapshot& S) {
 // into the other array, or (coupled) `reps` coupled steps replayed from the
 // two-step graph, from a snapshot restored after each candidate.  Keeps the
 // first candidate within 1% of the fastest (timing noise then does not flip
-// the choice between layouts that perform alike) and caches it per packing,
-// precision and mode.
+// the choice between layouts that perform alike) and caches it, with its
+// time, per packing, precision, sweep variant (athermal or fluctuating fluid)
+// and mode.
 int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms) {
   if (!c || reps < 1) return fail(LB_ERR_ARG, "bad arguments");
-  static std::map<std::string, SweepCfg> cache;
+  static std::map<std::string, std::pair<SweepCfg, double>> cache;
   std::string key = coupled ? "step:" : "sweep:";
   key += c->dev ? "f32:" : "f64:";
+  key += c->any_fluct ? "thermal:" : "athermal:";
   for (const lb_desc& x : c->d) {
     char buf[96];
     snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d;", x.nx, x.ny, x.nz, x.wall_axis, x.wall_pos, x.pore_h, x.nb);
@@ -1087,7 +1114,8 @@ int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms)
   SweepCfg best;
   double best_ms = -1.0;
   if (it != cache.end()) {
-    best = it->second;
+    best = it->second.first;
+    best_ms = it->second.second;
   } else {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -1147,7 +1175,7 @@ int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms)
     for (double t : times) tmin = t < tmin ? t : tmin;
     for (size_t k = 0; k < cand.size(); ++k)
       if (times[k] <= 1.01 * tmin) { best = cand[k]; best_ms = times[k]; break; }
-    cache[key] = best;
+    cache[key] = std::make_pair(best, best_ms);
   }
   int rc = upload_tiles(c, best);
   if (rc) return rc;

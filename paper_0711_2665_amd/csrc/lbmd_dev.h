@@ -32,6 +32,45 @@ __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i 
 // weights 1/3, 1/18, 1/36 (rest, axis, diagonal)
 __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
+// Modes of the fluctuating fluid: coefficient e_ki of population i in the
+// non-conserved mode k = 4..18 (modes 0..3 are the density and the momentum,
+// which take no noise).  Polynomials in the velocity c of population i,
+// mutually orthogonal under the weights and orthogonal to 1 and c:
+// k = 4 bulk stress c^2 - 1; 5, 6 normal-stress differences 3 c_x^2 - c^2,
+// c_y^2 - c_z^2; 7..9 shear stresses c_x c_y, c_y c_z, c_z c_x; 10..12 the
+// ghost vector (3 c^2 - 5) c; 13..15 the ghost vector (c_y^2 - c_z^2) c_x,
+// (c_z^2 - c_x^2) c_y, (c_x^2 - c_y^2) c_z; 16 the ghost scalar
+// 3 c^4 - 6 c^2 + 1; 17, 18 (2 c^2 - 3) times the modes 5 and 6.
+__host__ __device__ constexpr int mode_coef(int k, int i) {
+  const int x = cx(i), y = cy(i), z = cz(i);
+  const int xx = x * x, yy = y * y, zz = z * z, q = xx + yy + zz;
+  const int ax[3] = {x, y, z};
+  if (k == 4) return q - 1;
+  if (k == 5) return 3 * xx - q;
+  if (k == 6) return yy - zz;
+  if (k >= 7 && k <= 9) return ax[k - 7] * ax[(k - 6) % 3];
+  if (k >= 10 && k <= 12) return (3 * q - 5) * ax[k - 10];
+  if (k == 13) return (yy - zz) * x;
+  if (k == 14) return (zz - xx) * y;
+  if (k == 15) return (xx - yy) * z;
+  if (k == 16) return 3 * q * q - 6 * q + 1;
+  if (k == 17) return (2 * q - 3) * (3 * xx - q);
+  return (2 * q - 3) * (yy - zz);
+}
+constexpr int NMODE_NOISE = 15;   // modes 4..18
+// Parity of mode k under c -> -c: the ghost vectors 10..15 are odd, every
+// other non-conserved mode is even.
+__host__ __device__ constexpr bool mode_odd(int k) { return k >= 10 && k <= 15; }
+__host__ __device__ constexpr bool mode_parity_holds() {
+  for (int k = 4; k < Q; ++k)
+    for (int i = 0; i < Q; ++i) {
+      const int j = i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1);   // the opposite velocity
+      if (mode_coef(k, j) != (mode_odd(k) ? -1 : 1) * mode_coef(k, i)) return false;
+    }
+  return true;
+}
+static_assert(mode_parity_holds(), "mode parity table");
+
 // node flags
 constexpr uint8_t F_SOLID = 1;   // wall node: never updated; reflects links
 constexpr uint8_t F_NEAR = 2;    // some upstream neighbour x - c_i is solid
@@ -129,10 +168,12 @@ struct MdParams {
 __device__ inline void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    // full 64-bit products: one v_mad_u64_u32 gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    // three-input XOR in one v_bitop3_b32 (truth table 0x96)
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
   }
 }

@@ -37,6 +37,13 @@ struct LbParams {
   double omega;     // 1 / tau
   double g[3];      // body-force density
   int has_g;
+  // fluctuating fluid (fluct = 0: athermal): Philox key (fseed, frep); the
+  // noise on mode k is sqrt(rho) famp[k-4] r, famp = sqrt(3 kT (1 - (1 -
+  // omega)^2) / b_k), b_k the norm of mode k; famp32 the same in FP32
+  int fluct;
+  uint32_t fseed, frep;
+  double famp[NMODE_NOISE];
+  float famp32[NMODE_NOISE];
 };
 
 // One replica as the kernels see it.
@@ -111,9 +118,11 @@ struct MdOverride {
 template <typename T, bool DEV> void launch_fill_rest(void* pops, long N, hipStream_t s);
 void launch_fill_i32(int* p, long n, int v, hipStream_t s);
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
+// fluct: some replica has a fluctuating fluid (selects the sweep variant
+// that draws the fluid noise; replicas without it skip the draw)
 template <typename T, bool DEV>
 void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes, int grid, int cap, int skip_forced,
-               hipStream_t s);
+               bool fluct, hipStream_t s);
 template <typename T, bool DEV>
 void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStream_t s);
 template <typename T, bool DEV>

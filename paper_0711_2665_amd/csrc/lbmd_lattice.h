@@ -101,10 +101,11 @@ __device__ inline R cdot(int i, R vx, R vy, R vz) {
 // ---------------------------------------------------------------------------
 // BGK collision with the source term (Sec. 2, Eq. (lbe2) read as a relaxation
 // with S_i = 3 w_i F.c_i) of one fluid node (index c, flags fl) from its
-// post-streaming populations f; writes f* to out (may alias f).
+// post-streaming populations f; writes f* to out (may alias f) and returns
+// the node's density.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict__ force, const LbParams& p,
+__device__ inline auto collide_node(const T f[Q], T out[Q], const T* __restrict__ force, const LbParams& p,
                                     Ctrl* __restrict__ ctrl, int c, uint8_t fl) {
   const size_t N = (size_t)p.N;
   if constexpr (!DEV) {
@@ -127,6 +128,7 @@ __device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict_
       double src = (3.0 * wgt(i)) * cdot<double>(i, Fx, Fy, Fz);
       out[i] = (T)(f[i] - p.omega * (f[i] - fe) + src);
     }
+    return rho;
   } else {
     // FP32 deviation storage: g_i = f_i - w_i; drho = sum g, j = sum g c;
     // g^eq = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u.u)).
@@ -159,6 +161,88 @@ __device__ inline void collide_node(const T f[Q], T out[Q], const T* __restrict_
       if (src_on) o += (3.f * w) * cdot<float>(i, Fx, Fy, Fz);
       out[i] = (T)o;
     }
+    return rho;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stochastic term of the fluctuating fluid (Sec. 2, F_i; read in the mode
+// formulation of Adhikari et al.): after the collision of node c at LB step
+// n, every non-conserved mode k = 4..18 receives sqrt(rho) famp[k-4] r_k and
+// the populations f_i += w_i sum_k e_ki (that noise), so mass and momentum
+// stay as they are.  The 15 normals r_k come from four Philox-4x32-10 blocks
+// with key (fseed, frep) and counters (n, c, b, 1), b = 0..3: uniforms
+// (x + 1/2) 2^-32, Box-Muller on the pairs (u0, u1) and (u2, u3), cosine then
+// sine.  FP64: double log, sincos and sqrt.  FP32 deviation storage: the
+// hardware log2, sqrt and sin/cos of a fraction of a turn.
+// ---------------------------------------------------------------------------
+template <typename T, bool DEV, typename R>
+__device__ inline void fluid_noise(const LbParams& p, uint32_t n, int c, R rho, T f[Q]) {
+  // s[k-4] = famp[k-4] r_k
+  R s[NMODE_NOISE];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    uint32_t x0 = n, x1 = (uint32_t)c, x2 = (uint32_t)b, x3 = 1u;
+    philox10(x0, x1, x2, x3, p.fseed, p.frep);
+    R r[4];
+    if constexpr (DEV) {
+      const float s32 = 2.3283064365386963e-10f;   // 2^-32
+      const float u0 = fmaf((float)x0, s32, 0.5f * s32), u1 = fmaf((float)x1, s32, 0.5f * s32);
+      const float u2 = fmaf((float)x2, s32, 0.5f * s32), u3 = fmaf((float)x3, s32, 0.5f * s32);
+      const float m2ln2 = -1.3862943611198906f;     // -2 ln 2: -2 ln u = -2 ln 2 log2 u
+      const float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+      const float rb = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+      r[0] = ra * __builtin_amdgcn_cosf(u1);
+      r[1] = ra * __builtin_amdgcn_sinf(u1);
+      r[2] = rb * __builtin_amdgcn_cosf(u3);
+      r[3] = rb * __builtin_amdgcn_sinf(u3);
+    } else {
+      const double inv32 = 1.0 / 4294967296.0;
+      const double two_pi = 6.283185307179586;
+      const double ra = sqrt(-2.0 * log(((double)x0 + 0.5) * inv32));
+      const double rb = sqrt(-2.0 * log(((double)x2 + 0.5) * inv32));
+      double sa, ca, sb, cb;
+      sincos(two_pi * (((double)x1 + 0.5) * inv32), &sa, &ca);
+      sincos(two_pi * (((double)x3 + 0.5) * inv32), &sb, &cb);
+      r[0] = ra * ca; r[1] = ra * sa; r[2] = rb * cb; r[3] = rb * sb;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * b + j < NMODE_NOISE) {
+        if constexpr (DEV) s[4 * b + j] = p.famp32[4 * b + j] * r[j];
+        else s[4 * b + j] = p.famp[4 * b + j] * r[j];
+      }
+  }
+  // back to populations, f_i += sqrt(rho) w_i sum_k e_ki s_k, a velocity and
+  // its opposite together: the even modes add to both, the odd ones with
+  // opposite signs
+  R sr;
+  if constexpr (DEV) sr = __builtin_amdgcn_sqrtf(rho);
+  else sr = sqrt(rho);
+  const R a0 = sr * (R)wgt(0), a1 = sr * (R)wgt(1), a2 = sr * (R)wgt(7);
+  // h = 0: the rest population; h = 1..9: the pair (2h - 1, 2h)
+#pragma unroll
+  for (int h = 0; h < 10; ++h) {
+    const int i = h == 0 ? 0 : 2 * h - 1;
+    R ev = (R)0, od = (R)0;
+#pragma unroll
+    for (int k = 0; k < NMODE_NOISE; ++k) {
+      const int e = mode_coef(k + 4, i);
+      R& acc = mode_odd(k + 4) ? od : ev;
+      if (e == 1) acc += s[k];
+      else if (e == -1) acc -= s[k];
+      else if (e != 0) {
+        if constexpr (DEV) acc = fmaf((float)e, s[k], acc);
+        else acc += (R)e * s[k];
+      }
+    }
+    if (h == 0) {
+      f[0] = (T)((R)f[0] + a0 * ev);
+    } else {
+      const R a = i < 7 ? a1 : a2;
+      f[i] = (T)((R)f[i] + a * (ev + od));
+      f[i + 1] = (T)((R)f[i + 1] + a * (ev - od));
+    }
   }
 }
 
@@ -175,7 +259,8 @@ __device__ inline void lb_node(const T* __restrict__ A, T* __restrict__ B, const
   Nbr nb = make_nbr(p, x, y, z);
   T f[Q];
   pull<T>(A, flags, p, c, fl, nb, f);
-  collide_node<T, DEV>(f, f, force, p, ctrl, c, fl);
+  const auto rho = collide_node<T, DEV>(f, f, force, p, ctrl, c, fl);
+  if (p.fluct) fluid_noise<T, DEV>(p, (uint32_t)ctrl->step, c, rho, f);
   const size_t N = (size_t)p.N;
 #pragma unroll
   for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c], f[i]);
@@ -209,11 +294,12 @@ __device__ inline void bounce_back(const T* __restrict__ A, const uint8_t* __res
 // A_i(x - c_i) of all U nodes are issued together (a straight pull is a valid
 // read at any node); a node next to a wall then replaces what came from solid
 // nodes.  Nodes with in[u] false, solid nodes and, with skip_forced, nodes
-// carrying bead force are neither collided nor stored.
-template <typename T, bool DEV, int U>
+// carrying bead force are neither collided nor stored.  FL: replicas with a
+// fluctuating fluid add its noise for LB step n.
+template <typename T, bool DEV, int U, bool FL>
 __device__ inline void lb_nodes(const T* __restrict__ A, T* __restrict__ B, const uint8_t* __restrict__ flags,
                                 const T* __restrict__ force, const LbParams& p, Ctrl* __restrict__ ctrl,
-                                const int c[U], const bool in[U], int skip_forced) {
+                                const int c[U], const bool in[U], int skip_forced, uint32_t n) {
   const size_t N = (size_t)p.N;
   uint8_t fl[U];
   T f[U][Q];
@@ -238,7 +324,9 @@ __device__ inline void lb_nodes(const T* __restrict__ A, T* __restrict__ B, cons
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     if (!in[u] || (fl[u] & F_SOLID) || (skip_forced && (fl[u] & F_FORCED))) continue;
-    collide_node<T, DEV>(f[u], f[u], force, p, ctrl, c[u], fl[u]);
+    const auto rho = collide_node<T, DEV>(f[u], f[u], force, p, ctrl, c[u], fl[u]);
+    if constexpr (FL)
+      if (p.fluct) fluid_noise<T, DEV>(p, n, c[u], rho, f[u]);
 #pragma unroll
     for (int i = 0; i < Q; ++i) store_pop(&B[(size_t)i * N + c[u]], f[u][i]);
   }

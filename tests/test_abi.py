@@ -36,12 +36,31 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_desc_layout_matches_header():
-    # the ctypes mirror has the field order and sizes of struct lb_desc
+def test_desc_layout_matches_header(tmp_path):
+    # the ctypes mirrors have the size and the field offsets the C compiler
+    # gives the structs of include/lbmd.h
     from paper_0711_2665_amd import lbmd
-    assert C.sizeof(lbmd.LbDesc) == 4 * 4 + 8 * 4 + 4 * 4 + 8 * 10 + 4 * 3 + 4  # trailing pad to 8
-    assert C.sizeof(lbmd.LbSizes) == 8 * 8
-    assert C.sizeof(lbmd.LbBuffers) == 6 * 8
+    structs = {"lb_desc": lbmd.LbDesc, "lb_sizes": lbmd.LbSizes, "lb_buffers": lbmd.LbBuffers}
+    lines = ['#include <stdio.h>', '#include "lbmd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)], text=True).splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+    assert {f[0] for f in lbmd.LbDesc._fields_} >= {"fluid_kT", "seed", "replica"}
 
 
 @pytest.mark.parametrize("bad,msg", [
@@ -54,6 +73,7 @@ def test_desc_layout_matches_header():
     (dict(nb=3, mass=0.0), "mass"),
     (dict(nb=3, rc=2.5), "rc"),
     (dict(shape=(1024, 1024, 128)), "too large"),
+    (dict(fluid_kT=-1e-4), "fluid_kT"),
 ])
 def test_host_validation(bad, msg):
     from paper_0711_2665_amd import lbmd
