@@ -42,12 +42,14 @@ def lb_bytes_per_update(elem_bytes):
     return 2 * Q * elem_bytes + 1
 
 
-def measured_traffic(workload, precision, layout):
+def measured_traffic(workload, precision, layout, thermal=False):
     """HBM bytes per sweep launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and holds the
-    sweep layout in use; else None."""
+    summary (of the athermal sweep, or with thermal of the sweep that draws
+    the fluid noise), if it was taken on the current kernel source and holds
+    the sweep layout in use; else None."""
     from paper_0711_2665_amd.build import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", f"lb_sweep_{precision}_{workload}_counters.json")
+    tag = f"{precision}_thermal" if thermal else precision
+    path = os.path.join(ROOT, "profiles", f"lb_sweep_{tag}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -342,10 +344,12 @@ def main():
         rt = run_gpu(scaled(cfg, fluid_kT=cfg["kT"]), args.precision, kth, args.warmup)
         ut = rt["nfluid"] - rt["forced_per_step"]
         acht = (ut * lb_bytes_per_update(elem) + (cells - ut)) / (rt["lb_ms"] * 1e-3) / 1e9
+        lay_t = {k: rt["tune"][k] for k in ("tile_nodes", "order", "grid", "cap")}
         out["thermal_fluid"] = {"value": round(cells * kth / rt["seconds"] / 1e6, 1), "unit": "MLUPS",
                                 "steps": kth, "fluid_kT": cfg["kT"],
                                 "ms_per_step": round(1e3 * rt["seconds"] / kth, 4),
-                                "sweep_layout": {k: rt["tune"][k] for k in ("tile_nodes", "order", "grid", "cap")},
+                                "sweep_layout": lay_t,
+                                "lb_sweep_traffic": measured_traffic(args.workload, args.precision, lay_t, True),
                                 "sweep_alone": sweep_alone(rt, cells, elem),
                                 "lb_sweep_gbs": round(acht, 1), "lb_sweep_frac": round(acht / PEAK_HBM_GBS, 4),
                                 "lb_sweep_mean_launch_ms": round(rt["lb_ms"], 5)}

@@ -3,8 +3,9 @@
     python -m paper_0711_2665_amd.profile_run --workload c3 --precision fp32dev --steps 5 \
         --copy-mib 1024 --meta gpurun_out/lb_sweep_meta.json
 
-Builds the workload's lattice without beads and, for every sweep layout the
-autotuner chooses from, runs `steps` fluid-only sweeps (the kernel the
+Builds the workload's lattice without beads (with --fluid-kT, a fluctuating
+fluid: the sweep variant that draws the fluid noise) and, for every sweep
+layout the autotuner chooses from, runs `steps` fluid-only sweeps (the kernel the
 coupled step launches for the nodes without bead force); then a plain
 device-to-device copy of `copy_mib` MiB, whose counter readings calibrate
 the HBM byte counters (FETCH_SIZE, WRITE_SIZE) against a known transfer.
@@ -33,8 +34,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--meta", default=None)
+    ap.add_argument("--fluid-kT", type=float, default=0.0,
+                    help="thermal energy of a fluctuating fluid (selects the sweep that draws its noise)")
     a = ap.parse_args()
-    cfg = scaled(CONFIGS[a.workload], nb=0)
+    cfg = scaled(CONFIGS[a.workload], nb=0, fluid_kT=a.fluid_kT)
     prec = lbmd.LB_FP32_DEV if a.precision == "fp32dev" else lbmd.LB_FP64
     sim = lbmd.Simulation(cfg, precision=prec)
     for lay in LAYOUTS:
@@ -53,7 +56,7 @@ def main():
     meta = dict(workload=a.workload, precision=a.precision, shape=[nx, ny, nz], nodes=nx * ny * nz, nfluid=nfluid,
                 algorithmic_bytes_per_launch=nfluid * (2 * 19 * es + 1) + (nx * ny * nz - nfluid),
                 layouts=[dict(tile_nodes=t, order=o, grid=g, cap=k) for t, o, g, k in LAYOUTS],
-                kernel_source_hash=kernel_source_hash(), copy_bytes=n * 4, sweeps=a.steps)
+                kernel_source_hash=kernel_source_hash(), copy_bytes=n * 4, sweeps=a.steps, fluid_kT=a.fluid_kT)
     if a.meta:
         with open(a.meta, "w") as fh:
             json.dump(meta, fh)

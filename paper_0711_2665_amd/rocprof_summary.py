@@ -139,7 +139,8 @@ def counters(a):
     with open(a.out + "_counters.json", "w") as fh:
         json.dump(out, fh, indent=1)
     f, w = res["FETCH_SIZE"], res["WRITE_SIZE"]
-    lines = [f"# HBM traffic of the LB sweep: {meta['workload']} {meta['precision']}", "",
+    variant = f", fluctuating fluid (kT = {meta['fluid_kT']:g})" if meta.get("fluid_kT", 0.0) > 0 else ""
+    lines = [f"# HBM traffic of the LB sweep: {meta['workload']} {meta['precision']}{variant}", "",
              "Commands (from the repository root):", "", "```", a.command, "```", "",
              f"Lattice {meta['shape']} ({meta['nodes']} nodes, {meta['nfluid']} fluid), kernel source hash "
              f"`{meta['kernel_source_hash']}`, {n} sweeps per layout.  Counters are calibrated against a "
