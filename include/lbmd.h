@@ -87,7 +87,8 @@ typedef struct lb_desc {
   double mass;            /* bead mass                                        */
   double k_bond, r0;      /* harmonic bond constant and rest length          */
   double kappa;           /* bending constant, V = kappa phi^2 / 2           */
-  double eps, sigma, rc;  /* truncated LJ (bead-bead and bead-wall site)     */
+  double eps, sigma, rc;  /* truncated LJ (bead-bead and bead-wall site),
+                             0 < rc <= 3                                     */
   double gamma, kT;       /* friction rate and thermal energy of the beads   */
   double f_drive;         /* force along +normal on beads in the pore channel */
   int32_t n_sub;          /* MD sub-steps per LB step                        */
@@ -130,8 +131,8 @@ typedef struct lb_ctx lb_ctx;
 /* Validates *d and fills *out.  Host only: calls no HIP function.
  * LB_ERR_ARG: extents <= 0 or 19 N > 2^31 - 1, tau <= 0.5, a wall plane
  * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
- * gamma, kT or fluid_kT, rc outside (0, 2], or nb > 0 without a positive
- * mass. */
+ * gamma, kT or fluid_kT, rc outside (0, 3], nb > 0 without a positive
+ * mass, or nb > 0 with a wall on a lattice with an extent below 6. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
 
 /* As lb_buffer_sizes for nrep replicas d[0..nrep-1] in one context.  All

@@ -579,7 +579,7 @@ struct Sim {
     }
   }
   // Wall repulsion: the same truncated LJ between a bead and every solid node
-  // site within r_c.  r_c < 2, so the sites at offsets -1..2 from the bead's
+  // site within r_c.  r_c <= 3, so the sites at offsets -2..3 from the bead's
   // base node on each axis cover every candidate (z outer, x inner).
   void wall_on_bead(const std::vector<R>& pos, int p, R Fp[3]) const {
     if (d.wall_axis < 0) return;
@@ -589,9 +589,9 @@ struct Sim {
       w[a] = wrapc(pos[3 * p + a], ext(a));
       b[a] = (int)std::floor(val(w[a]));
     }
-    for (int oz = -1; oz <= 2; ++oz)
-      for (int oy = -1; oy <= 2; ++oy)
-        for (int ox = -1; ox <= 2; ++ox) {
+    for (int oz = -2; oz <= 3; ++oz)
+      for (int oy = -2; oy <= 3; ++oy)
+        for (int ox = -2; ox <= 3; ++ox) {
           int sx = b[0] + ox, sy = b[1] + oy, sz = b[2] + oz;
           if (!solid[idx(wrapi(sx, nx), wrapi(sy, ny), wrapi(sz, nz))]) continue;
           R dd[3] = {w[0] - R((double)sx), w[1] - R((double)sy), w[2] - R((double)sz)};
@@ -711,9 +711,9 @@ struct Sim {
         double w[3];
         int b[3];
         for (int a = 0; a < 3; ++a) { w[a] = val(wrapc(pos[3 * p + a], ext(a))); b[a] = (int)std::floor(w[a]); }
-        for (int oz = -1; oz <= 2; ++oz)
-          for (int oy = -1; oy <= 2; ++oy)
-            for (int ox = -1; ox <= 2; ++ox) {
+        for (int oz = -2; oz <= 3; ++oz)
+          for (int oy = -2; oy <= 3; ++oy)
+            for (int ox = -2; ox <= 3; ++ox) {
               int sx = b[0] + ox, sy = b[1] + oy, sz = b[2] + oz;
               if (!solid[idx(wrapi(sx, nx), wrapi(sy, ny), wrapi(sz, nz))]) continue;
               double dx = w[0] - sx, dy = w[1] - sy, dz = w[2] - sz;

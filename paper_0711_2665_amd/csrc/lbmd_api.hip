@@ -168,9 +168,11 @@ int validate_one(const lb_desc* d, int r) {
   if (d->nb > 0) {
     if (!(d->mass > 0.0)) return fail(LB_ERR_ARG, "replica %d: bead mass must be positive", r);
     if (!(d->gamma >= 0.0) || !(d->kT >= 0.0)) return fail(LB_ERR_ARG, "replica %d: gamma and kT must be >= 0", r);
-    if (!(d->rc > 0.0) || d->rc > 2.0) return fail(LB_ERR_ARG, "replica %d: rc must lie in (0, 2]", r);
+    if (!(d->rc > 0.0) || d->rc > 3.0) return fail(LB_ERR_ARG, "replica %d: rc must lie in (0, 3]", r);
     if (!(d->sigma > 0.0)) return fail(LB_ERR_ARG, "replica %d: sigma must be positive", r);
     if ((long)d->nb > (1L << 24)) return fail(LB_ERR_ARG, "replica %d: too many beads", r);
+    if (d->wall_axis >= 0 && (d->nx < 6 || d->ny < 6 || d->nz < 6))
+      return fail(LB_ERR_ARG, "replica %d: a wall with beads needs extents >= 6", r);
   }
   return LB_OK;
 }

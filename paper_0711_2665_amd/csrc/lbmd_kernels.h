@@ -29,7 +29,7 @@ constexpr int CELL_CAP = 32;                 // beads per bucket of the neighbou
 // Sweep occupancy cap: a capped sweep workgroup reserves (LDS per CU - what
 // two bead sub-step workgroups need) / cap bytes of LDS it does not use
 constexpr int LDS_PER_CU = 160 * 1024;
-constexpr int LDS_KEEP = 64 * 1024;
+constexpr int LDS_KEEP = 76 * 1024;
 constexpr int SWEEP_CAP_MIN = 2, SWEEP_CAP_MAX = 8;
 
 struct LbParams {

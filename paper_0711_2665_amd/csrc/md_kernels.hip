@@ -158,7 +158,9 @@ __device__ inline void angle_component(const MdParams& P, const double* ra, cons
 // ---------------------------------------------------------------------------
 constexpr int MD_LANES = 4;
 constexpr int MD_WG = MD_LANES * MD_BPB;     // 64
-constexpr int MAXWALL = 16;                  // the 4 x 4 window of wall sites around a bead
+constexpr int WLO = -2, WHI = 3;             // wall-site window: offsets -2..3 from the base node (r_c <= 3)
+constexpr int WSPAN = WHI - WLO + 1;         // 6
+constexpr int MAXWALL = WSPAN * WSPAN;       // the 6 x 6 window of wall sites in the wall plane
 constexpr int NB_PER_LANE = MAXNBR / MD_LANES;
 
 struct MdShared {
@@ -166,27 +168,34 @@ struct MdShared {
                                              // q-1, [3..5] on q, [6..8] on q+1
   double pairF[MD_BPB][MAXNBR][3];           // LJ pair force of list entry k
   uint32_t hit[MD_BPB][MD_LANES];            // lane l, bit m: entry l + 4m is within r_c
-  double wallF[MD_BPB][MAXWALL][3];         // wall site (o1 + 1) * 4 + (o0 + 1) of each bead
-  uint32_t wmask[MD_BPB][MD_LANES];          // lane l: which sites of row o1 = l - 1 are set
+  uint32_t wmask[MD_BPB][WSPAN];             // row o1 - WLO: which sites o0 - WLO of the row are set
   int cnt[MD_BPB];
   int lst[MD_BPB][MAXNBR];                   // the neighbour list in use (chain indices)
-  double tile[MD_WG][3];                     // rebuild: positions of 64 candidates
-  uint32_t tmask[MD_BPB][MD_LANES];          // rebuild: lane l, bit e: candidate 16 l + e is close
-  uint32_t bk[MD_BPB][28];                   // rebuild from the cell table: the 27 buckets around a bead
+  // the list rebuild's scratch is dead before the wall sites are written
+  union {
+    struct {
+      double tile[MD_WG][3];                 // rebuild: positions of 64 candidates
+      uint32_t tmask[MD_BPB][MD_LANES];      // rebuild: lane l, bit e: candidate 16 l + e is close
+      uint32_t bk[MD_BPB][28];               // rebuild from the cell table: the 27 buckets around a bead
+    };
+    double wallF[MD_BPB][MAXWALL][3];        // wall site (o1 - WLO) * WSPAN + (o0 - WLO) of each bead
+  };
   int over;
 };
+static_assert(2 * sizeof(MdShared) <= (size_t)LDS_KEEP, "two sub-step workgroups fit in the LDS a capped sweep leaves");
 
 // Wall sites of the bead at rp, one row of the window at a time: the sites
-// at offsets -1..2 from the base node along the lower transverse axis (o0),
+// at offsets -2..3 from the base node along the lower transverse axis (o0),
 // for offset o1 along the higher one.  Each is the truncated-LJ pair force of
-// one solid site within r_c; the force of offset o0 goes to out[o0 + 1] and
-// the returned mask has bit o0 + 1 set.  r_c < 2 makes the window cover
+// one solid site within r_c; the force of offset o0 goes to out[o0 - WLO] and
+// the returned mask has bit o0 - WLO set.  r_c <= 3 makes the window cover
 // every candidate.  Solid sites lie in the plane a = wall_pos (minus the
 // pore), so at most one offset along the wall normal can match.  Rows
-// o1 = -1..2, each in o0 order, visit the sites in the order of the
+// o1 = -2..3, each in o0 order, visit the sites in the order of the
 // definition's sum (higher transverse axis outer).  Wrapping uses compares
-// only (the window is within one period).
-__device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const double* rp, int o1, double out[4][3]) {
+// only (the window is within one period: extents are at least 6).
+__device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const double* rp, int o1,
+                                    double out[WSPAN][3]) {
   if (g.wall_axis < 0) return 0u;
   const double w0 = wrapc(rp[0], g.nx), w1 = wrapc(rp[1], g.ny), w2 = wrapc(rp[2], g.nz);
   const int b0 = (int)floor(w0), b1 = (int)floor(w1), b2 = (int)floor(w2);
@@ -197,15 +206,15 @@ __device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const doub
   const int bt0 = a == 0 ? b1 : b0, n0 = a == 0 ? g.ny : g.nx;
   const int bt1 = a == 2 ? b1 : b2, n1 = a == 2 ? g.ny : g.nz;
   int off = g.wall_pos - ba;                // offset along the normal reaching the plane
-  if (off < -1) off += na;
-  if (off > 2) off -= na;
-  if (off < -1 || off > 2) return 0u;
+  if (off < WLO) off += na;
+  if (off > WHI) off -= na;
+  if (off < WLO || off > WHI) return 0u;
   const int sa = ba + off;
   const int u1 = bt1 + o1;
   const int v1 = u1 < 0 ? u1 + n1 : (u1 >= n1 ? u1 - n1 : u1);
   const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
   uint32_t mask = 0u;
-  for (int o0 = -1; o0 <= 2; ++o0) {
+  for (int o0 = WLO; o0 <= WHI; ++o0) {
     const int u0 = bt0 + o0;
     const int v0 = u0 < 0 ? u0 + n0 : (u0 >= n0 ? u0 - n0 : u0);
     const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
@@ -217,8 +226,8 @@ __device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const doub
     if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
     double F[3] = {0.0, 0.0, 0.0};
     lj_add(P, d0, d1, d2, F);
-    out[o0 + 1][0] = F[0]; out[o0 + 1][1] = F[1]; out[o0 + 1][2] = F[2];
-    mask |= 1u << (o0 + 1);
+    out[o0 - WLO][0] = F[0]; out[o0 - WLO][1] = F[1]; out[o0 - WLO][2] = F[2];
+    mask |= 1u << (o0 - WLO);
   }
   return mask;
 }
@@ -436,8 +445,10 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
         rq[a] = rabs[3 * sq + a];
       }
     }
-    // ---- wall sites: lane l of a bead takes row o1 = l - 1 of the window
-    sh.wmask[bslot][lane] = p < P.nb ? wall_row(P, g, rp, lane - 1, &sh.wallF[bslot][4 * lane]) : 0u;
+    // ---- wall sites: lane l of a bead takes the rows o1 = WLO + l and
+    // WLO + l + 4 of the window (the second only for l < 2)
+    for (int row = lane; row < WSPAN; row += MD_LANES)
+      sh.wmask[bslot][row] = p < P.nb ? wall_row(P, g, rp, WLO + row, &sh.wallF[bslot][WSPAN * row]) : 0u;
     // ---- lane 0: bonds now, the rest after the barrier
     if (lead) {
       if (p > 0) bond_add(P, rp, rm, F);
@@ -482,7 +493,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
   }
   for (int k = 0; k < MAXWALL; ++k) {
-    if (!((sh.wmask[bslot][k / 4] >> (k % 4)) & 1u)) continue;
+    if (!((sh.wmask[bslot][k / WSPAN] >> (k % WSPAN)) & 1u)) continue;
     F[0] += sh.wallF[bslot][k][0]; F[1] += sh.wallF[bslot][k][1]; F[2] += sh.wallF[bslot][k][2];
   }
   if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;

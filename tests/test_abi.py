@@ -71,7 +71,8 @@ def test_desc_layout_matches_header(tmp_path):
     (dict(n_sub=0), "n_sub"),
     (dict(nb=-1), "negative"),
     (dict(nb=3, mass=0.0), "mass"),
-    (dict(nb=3, rc=2.5), "rc"),
+    (dict(nb=3, rc=3.5), "rc"),
+    (dict(nb=3, wall_axis=2, wall_pos=2, shape=(16, 5, 8)), "extents >= 6"),
     (dict(shape=(1024, 1024, 128)), "too large"),
     (dict(fluid_kT=-1e-4), "fluid_kT"),
 ])

@@ -62,21 +62,28 @@ def _adjoint(sim, st, cfg, nsteps, K):
     return g[0], g[1], g[2:].reshape(-1, 3)
 
 
-def test_adjoint_fp64_matches_oracle_jvp(orc):
+# the paper's soft bead-bead and wall LJ (sigma = 1.8, eps = 1e-4): r_c =
+# 2^(1/6) 1.8 > 2 reaches wall sites two nodes from the base node
+CFG_SOFT = scaled(CFG, sigma=1.8, eps=1e-4, rc=2.0 ** (1.0 / 6.0) * 1.8)
+
+
+@pytest.mark.parametrize("lj", ["wca", "paper_soft"])
+def test_adjoint_fp64_matches_oracle_jvp(orc, lj):
     torch = _torch()
     from paper_0711_2665_amd import lbmd
-    r0 = _start(orc, CFG)
+    cfg = CFG if lj == "wca" else CFG_SOFT
+    r0 = _start(orc, cfg)
     v0 = np.zeros_like(r0)
-    sim = lbmd.Simulation(CFG, r0)
+    sim = lbmd.Simulation(cfg, r0)
     st = sim.get_state()
-    gg, gf, gr = _adjoint(sim, st, CFG, NSTEPS, 5)
+    gg, gf, gr = _adjoint(sim, st, cfg, NSTEPS, 5)
     torch.cuda.synchronize()
     L_gpu = float(sim.beads()["r"][:, 2].mean())
-    L, dg = orc.jvp(CFG, r0, v0, NSTEPS, dgamma=1.0)
-    _, df = orc.jvp(CFG, r0, v0, NSTEPS, dfdrive=1.0)
+    L, dg = orc.jvp(cfg, r0, v0, NSTEPS, dgamma=1.0)
+    _, df = orc.jvp(cfg, r0, v0, NSTEPS, dfdrive=1.0)
     rng = np.random.default_rng(3)
     dirs = [rng.standard_normal(r0.shape) for _ in range(3)]
-    dr = [orc.jvp(CFG, r0, v0, NSTEPS, dr0=d)[1] for d in dirs]
+    dr = [orc.jvp(cfg, r0, v0, NSTEPS, dr0=d)[1] for d in dirs]
     print(f"L gpu {L_gpu:.15g} oracle {L:.15g}; dL/dgamma {gg:.12e} / {dg:.12e}; dL/dF {gf:.12e} / {df:.12e}",
           flush=True)
     assert abs(L_gpu - L) <= 1e-12 * abs(L)

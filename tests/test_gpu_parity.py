@@ -323,6 +323,28 @@ def test_long_chain_rebuilds_inside_the_cycle_bitwise(orc):
     assert diag["cell_rebuilds"] >= 1 and diag["rebuilds"] >= diag["cell_rebuilds"]
 
 
+def test_paper_soft_lj_coupled_steps_bitwise(orc):
+    """The paper's bead LJ (sigma = 1.8, eps = 1e-4, r_c = 2^(1/6) 1.8 > 2,
+    so wall sites two nodes from a bead's base node count), without noise and
+    bending: five coupled steps equal the oracle bit for bit."""
+    torch = _torch()
+    cfg = scaled(C0, kT=0.0, kappa=0.0, sigma=1.8, eps=1e-4, rc=2.0 ** (1.0 / 6.0) * 1.8)
+    o, s = _c0_common_start(orc, cfg)
+    o.couple_step(5)
+    s.couple_step(5)
+    torch.cuda.synchronize()
+    fluid = o.flags() == 0
+    a, b = _gpu_pops(s)[:, fluid], o.pops()[:, fluid]
+    sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+    ob = o.beads()
+    print("soft LJ, 5 steps: pops differing", int((a != b).sum()),
+          {k: int((sb[k] != ob[k]).sum()) for k in ("r", "v", "up", "J")}, flush=True)
+    assert np.array_equal(a, b)
+    for k in ("r", "v", "up", "J"):
+        assert np.array_equal(sb[k], ob[k]), k
+    s.check()
+
+
 @pytest.mark.parametrize("shape,axis,pos", [((12, 10, 16), 2, 8), ((32, 16, 12), 0, 16)])
 def test_lb_only_fp32_deviation_matches_oracle(orc, shape, axis, pos):
     """FP32 deviation storage against the FP64 oracle over 20 fluid steps from

@@ -185,6 +185,38 @@ def test_field_region_reading(orc):
         assert not o.in_field(np.array(p, dtype=float)), p
 
 
+# -- wall repulsion: the truncated LJ of every solid site within r_c,
+#    against a brute-force sum over all solid sites of the lattice (minimum
+#    image), for cut-offs up to the largest the library accepts (r_c <= 3:
+#    the paper's sigma = 1.8 gives r_c = 2^(1/6) 1.8 > 2)
+
+@pytest.mark.parametrize("sigma", [1.0, 1.8, 2.6])
+def test_wall_force_equals_brute_force_over_every_site(orc, sigma):
+    rc = 2.0 ** (1.0 / 6.0) * sigma
+    eps = 1e-4 if sigma > 1.0 else 1.0
+    cfg = scaled(C0, shape=(24, 20, 22), wall_axis=1, wall_pos=10, pore_h=3, nb=1, sigma=sigma, rc=rc, eps=eps)
+    o = orc.Oracle(cfg, np.zeros((1, 3)))
+    solid = np.argwhere(o.flags() == 1)[:, ::-1].astype(float)      # (x, y, z) of every solid node
+    ext = np.array([24.0, 20.0, 22.0])
+    rng = np.random.default_rng(int(10 * sigma))
+    pts = [np.array([12.3, 10 + dy, 11.7]) for dy in (-2.9, -2.2, -1.5, -0.6, 0.4, 1.1, 2.5, 3.3)]
+    # beads inside the pore, near the wall plane: the nearest solid sites lie
+    # two nodes below the base node along x or z, just inside r_c = 2.02
+    pts += [np.array([12.005, 10.1, 11.0]), np.array([12.0, 9.9, 10.003])]
+    pts += [np.array([10.6 + rng.random() * 3, 8.0 + rng.random() * 4, 9.6 + rng.random() * 3]) for _ in range(12)]
+    for rp in pts:
+        o.set_beads(rp[None, :], np.zeros((1, 3)))
+        got = o.forces(field_on=False)[0]
+        d = rp[None, :] - solid
+        d -= ext * np.round(d / ext)
+        r2 = (d * d).sum(1)
+        near = r2 < rc * rc
+        sr6 = (sigma ** 2 / r2[near]) ** 3
+        want = ((24 * eps * (2 * sr6 * sr6 - sr6) / r2[near])[:, None] * d[near]).sum(0)
+        scale = max(1.0, np.abs(want).max())
+        assert np.abs(got - want).max() <= 1e-12 * scale, (rp, got, want, int(near.sum()))
+
+
 # -- P8: momentum ledger.  In a periodic box without walls the fluid + bead
 #    momentum is conserved; with walls (field off, beads away from them) the
 #    bounce-back ledger closes the balance (halfway bounce-back hands the
