@@ -229,6 +229,7 @@ typedef struct {
   int n_sub;           // MD sub-steps per LB step
   uint32_t seed, replica;
   double fluid_kT;     // thermal energy of the fluid noise (0: athermal BGK fluid)
+  int mts_outer;       // 0: n_sub uniform sub-steps; M > 0: the multiple-time-step cycle with M outer steps
 } or_desc;
 }
 
@@ -676,6 +677,37 @@ struct Sim {
     }
   }
 
+  // The two force groups of the multiple-time-step cycle, each summed in the
+  // order of forces(): the bonded forces (bonds to p-1 and p+1, the angles
+  // centred at p-1, p, p+1) and the slow forces (bead LJ in ascending
+  // partner order, wall sites, field).
+  void fast_forces(const std::vector<R>& pos, std::vector<R>& Fb) const {
+    for (int p = 0; p < nb; ++p) {
+      R Fp[3] = {R(0.0), R(0.0), R(0.0)};
+      if (p > 0) bond_force(pos, p, p - 1, Fp);
+      if (p < nb - 1) bond_force(pos, p, p + 1, Fp);
+      for (int q = p - 1; q <= p + 1; ++q) {
+        if (q < 1 || q > nb - 2) continue;
+        R Fm[3], F0[3], Fq[3];
+        angle_forces(pos, q, Fm, F0, Fq);
+        const R* mine = (q == p + 1) ? Fm : (q == p ? F0 : Fq);
+        for (int a = 0; a < 3; ++a) Fp[a] += mine[a];
+      }
+      for (int a = 0; a < 3; ++a) Fb[3 * p + a] = Fp[a];
+    }
+  }
+  void slow_forces(const std::vector<R>& pos, std::vector<R>& Fs, bool field_on) const {
+    std::vector<std::vector<int>> cand;
+    if (use_cells) build_candidates(pos, cand);
+    for (int p = 0; p < nb; ++p) {
+      R Fp[3] = {R(0.0), R(0.0), R(0.0)};
+      lj_on_bead(pos, p, use_cells ? &cand[p] : nullptr, Fp);
+      wall_on_bead(pos, p, Fp);
+      if (field_on && in_field(&pos[3 * p])) Fp[d.wall_axis] += fdrive;
+      for (int a = 0; a < 3; ++a) Fs[3 * p + a] = Fp[a];
+    }
+  }
+
   // Potential energy of the conservative forces except the field (the field
   // is a step in space and has no potential): used by finite-difference pins.
   double energy(const std::vector<R>& pos) const {
@@ -731,7 +763,11 @@ struct Sim {
   // F^c includes the field.  The noise enters only through sig xi.  The
   // friction + noise impulse m[(1-e)(u_p - v_old) + sig xi] is the momentum
   // the bead takes from the fluid; J collects minus its sum.
-  void md_subcycle(bool couple, bool field_on, uint32_t n_counter) {
+  void md_subcycle(bool couple, bool field_on, uint32_t n_counter, bool allow_mts = true) {
+    if (allow_mts && d.mts_outer > 0) {
+      md_subcycle_mts(couple, field_on, n_counter);
+      return;
+    }
     std::vector<R> Fc((size_t)3 * nb);
     for (int s = 0; s < d.n_sub; ++s) {
       for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
@@ -748,6 +784,44 @@ struct Sim {
         }
       }
       for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
+    }
+  }
+
+  // ---- multiple-time-step sub-cycle (Sec. 2, the nested cycle over the
+  // bonds; read as a RESPA split, the printed inner loop moving no position):
+  // M outer steps of dt = 1/M.  Each opens and closes with a half kick of the
+  // slow forces, v += (dt/2)/m F_s(r), around M_b = n_sub/M SPV sub-steps of
+  // h = 1/n_sub with the bonded forces only:
+  //   r += h/2 v;  v = e v + (1-e)/(m gamma) (F_b(r) + gamma u_p) + sig xi;  r += h/2 v
+  // Sub-step i of outer step o draws the noise of sub-step index o M_b + i;
+  // J collects the friction + noise impulse of every sub-step as in the
+  // uniform cycle.
+  void md_subcycle_mts(bool couple, bool field_on, uint32_t n_counter) {
+    const int M = d.mts_outer, Mb = d.n_sub / M;
+    const R kick = R(0.5 * (1.0 / (double)M) / m);
+    std::vector<R> Fs((size_t)3 * nb), Fb((size_t)3 * nb);
+    for (int o = 0; o < M; ++o) {
+      slow_forces(r, Fs, field_on);
+      for (int k = 0; k < 3 * nb; ++k) v[k] = v[k] + kick * Fs[k];
+      for (int i = 0; i < Mb; ++i) {
+        const int s = o * Mb + i;
+        for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
+        fast_forces(r, Fb);
+        for (int p = 0; p < nb; ++p) {
+          double xi[3] = {0.0, 0.0, 0.0};
+          if (val(sig) != 0.0) gauss3(d.seed, d.replica, n_counter, (uint32_t)s, (uint32_t)p, xi);
+          for (int a = 0; a < 3; ++a) {
+            R u = couple ? up[3 * p + a] : R(0.0);
+            R vold = v[3 * p + a];
+            R sx = sig * R(xi[a]);
+            v[3 * p + a] = e * vold + cf * (Fb[3 * p + a] + gamma * u) + sx;
+            J[3 * p + a] = J[3 * p + a] - R(m) * (omE * (u - vold) + sx);
+          }
+        }
+        for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
+      }
+      slow_forces(r, Fs, field_on);
+      for (int k = 0; k < 3 * nb; ++k) v[k] = v[k] + kick * Fs[k];
     }
   }
 
@@ -781,7 +855,7 @@ struct Sim {
     int left = nsub_total;
     while (left > 0) {
       d.n_sub = std::min(left, save_nsub);
-      md_subcycle(false, false, 0u);
+      md_subcycle(false, false, 0u, false);
       left -= d.n_sub;
     }
     d.n_sub = save_nsub;
@@ -874,6 +948,7 @@ typedef Sim<double> SimD;
 
 void* or_create(const or_desc* d, const double* r0, const double* v0) {
   if (!d || d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || !(d->tau > 0.5) || d->n_sub <= 0) return nullptr;
+  if (d->mts_outer < 0 || (d->mts_outer > 0 && d->n_sub % d->mts_outer != 0)) return nullptr;
   SimD* s = new SimD();
   s->init(*d, r0, v0);
   return s;
