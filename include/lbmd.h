@@ -99,6 +99,16 @@ typedef struct lb_desc {
                              fluctuation-dissipation); 0: athermal BGK fluid.
                              Node c of a replica draws, at LB step n, Philox-
                              4x32-10 of counters (n, c, k, 1), k = 0..3       */
+  int32_t mts_outer;      /* 0: the MD sub-cycle is n_sub uniform SPV sub-steps
+                             with every force.  M > 0: the multiple-time-step
+                             cycle (Sec. 2, the nested cycle over the bonds,
+                             read as a RESPA split): M outer steps of 1/M, each
+                             a half kick of the slow forces (bead LJ, wall,
+                             field), n_sub / M SPV sub-steps with the bonds and
+                             bending, friction and noise, and another half
+                             kick.  n_sub / M must be a whole number <= 40; all
+                             replicas share M; the pre-relaxation always uses
+                             uniform sub-steps                               */
 } lb_desc;
 
 /* Byte sizes of the caller-allocated device buffers (256-byte aligned), and
@@ -132,13 +142,14 @@ typedef struct lb_ctx lb_ctx;
  * LB_ERR_ARG: extents <= 0 or 19 N > 2^31 - 1, tau <= 0.5, a wall plane
  * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
  * gamma, kT or fluid_kT, rc outside (0, 3], nb > 0 without a positive
- * mass, or nb > 0 with a wall on a lattice with an extent below 6. */
+ * mass, nb > 0 with a wall on a lattice with an extent below 6, or an
+ * mts_outer that is negative or does not divide n_sub into at most 40. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
 
 /* As lb_buffer_sizes for nrep replicas d[0..nrep-1] in one context.  All
- * replicas share precision and n_sub; extents, walls, chains, friction,
+ * replicas share precision, n_sub and mts_outer; extents, walls, chains, friction,
  * temperature, field and noise keys may differ.  LB_ERR_ARG also for nrep
- * outside [1, 1024] or mixed precision / n_sub. */
+ * outside [1, 1024] or mixed precision / n_sub / mts_outer. */
 int lb_ensemble_sizes(const lb_desc* d, int nrep, lb_sizes* out);
 
 /* Creates a context on the current HIP device, builds the solid flags of the
@@ -261,9 +272,9 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * conservative forces), gathering -- using the populations and bead state of
  * that step, recomputed segment by segment from checkpoints taken every K
  * steps of the forward pass.
- * Supported: one-replica contexts with 1 <= nb <= 128, gamma > 0 and an
- * athermal fluid, fluid_kT = 0 (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise);
- * either precision.
+ * Supported: one-replica contexts with 1 <= nb <= 128, gamma > 0, an
+ * athermal fluid (fluid_kT = 0) and the uniform sub-cycle (mts_outer = 0)
+ * (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either precision.
  *
  * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1
  *   checkpoints of lb_sizes.state_bytes, K population arrays of tape, the

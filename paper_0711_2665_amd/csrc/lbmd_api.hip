@@ -165,6 +165,10 @@ int validate_one(const lb_desc* d, int r) {
     return fail(LB_ERR_ARG, "replica %d: fluid_kT must be finite and >= 0", r);
   if (d->nb < 0) return fail(LB_ERR_ARG, "replica %d: negative bead count", r);
   if (d->n_sub < 1) return fail(LB_ERR_ARG, "replica %d: n_sub must be >= 1", r);
+  if (d->mts_outer < 0) return fail(LB_ERR_ARG, "replica %d: mts_outer must be >= 0", r);
+  if (d->mts_outer > 0 && (d->n_sub % d->mts_outer != 0 || d->n_sub / d->mts_outer > MTS_MAX_INNER))
+    return fail(LB_ERR_ARG, "replica %d: mts_outer must divide n_sub into at most %d sub-steps per outer step", r,
+                MTS_MAX_INNER);
   if (d->nb > 0) {
     if (!(d->mass > 0.0)) return fail(LB_ERR_ARG, "replica %d: bead mass must be positive", r);
     if (!(d->gamma >= 0.0) || !(d->kT >= 0.0)) return fail(LB_ERR_ARG, "replica %d: gamma and kT must be >= 0", r);
@@ -186,6 +190,7 @@ int validate(const lb_desc* d, int nrep) {
     if (rc) return rc;
     if (d[r].precision != d[0].precision) return fail(LB_ERR_ARG, "replica %d: all replicas need one precision", r);
     if (d[r].n_sub != d[0].n_sub) return fail(LB_ERR_ARG, "replica %d: all replicas need one n_sub", r);
+    if (d[r].mts_outer != d[0].mts_outer) return fail(LB_ERR_ARG, "replica %d: all replicas need one mts_outer", r);
     nodes += round_up((long)d[r].nx * d[r].ny * d[r].nz, NODE_ALIGN);
     slots += round_up(d[r].nb, MD_BPB);
   }
@@ -240,6 +245,7 @@ MdParams make_md(const lb_desc* d, double skin) {
   P.rlist2 = (d->rc + skin) * (d->rc + skin);
   P.halfskin2 = (0.5 * skin) * (0.5 * skin);
   spv_coefficients(P, d->gamma, d->kT, h);
+  P.kick = d->mts_outer > 0 ? 0.5 * (1.0 / (double)d->mts_outer) / P.m : 0.0;
   return P;
 }
 
@@ -310,6 +316,7 @@ struct lb_ctx {
   bool lists_stale = true;   // the positions changed outside a coupled step since the last build
   bool any_noise = false;
   bool any_fluct = false;    // some replica has a fluctuating fluid
+  int mts = 0;               // outer steps of the multiple-time-step sub-cycle (0: uniform sub-steps)
   bool noise_ready = false;  // the noise slot of the current population parity holds this step's noise
   SweepCfg sweep;
   int ntiles = 0;
@@ -464,7 +471,8 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   if (c->dev) launch_gather<float, true>(A, D, c->nslots, sb);
   else launch_gather<double, false>(A, D, c->nslots, sb);
   MdOverride none{};
-  launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb);
+  if (c->mts > 0) launch_md_cycle_mts(D, c->nslots, c->nrep, c->n_sub, c->mts, sb);
+  else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb);
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
   if (c->step_lists) {
@@ -571,6 +579,7 @@ int adj_check(const lb_ctx* c, int nsteps, int K) {
     return fail(LB_ERR_UNSUPPORTED, "the adjoint needs 1 <= nb <= %d (got %d)", MAX_ADJ_BEADS, d.nb);
   if (!(c->reps[0].mp.gamma > 0.0)) return fail(LB_ERR_ARG, "the adjoint needs gamma > 0");
   if (c->reps[0].lp.fluct) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs an athermal fluid (fluid_kT = 0)");
+  if (c->mts > 0) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs the uniform sub-cycle (mts_outer = 0)");
   if (nsteps < 1 || K < 1) return fail(LB_ERR_ARG, "nsteps and K must be >= 1");
   if (c->prof_on) return fail(LB_ERR_ARG, "profiling is active");
   return LB_OK;
@@ -656,6 +665,7 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   c->cur = 0;
   c->dev = d[0].precision == LB_FP32_DEV;
   c->n_sub = d[0].n_sub;
+  c->mts = d[0].mts_outer;
   c->pk = packing(d, nrep);
   c->wl = work_layout(d, nrep, c->pk);
   c->sl = state_layout(d, nrep, c->pk);

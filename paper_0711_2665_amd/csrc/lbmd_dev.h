@@ -162,6 +162,7 @@ struct MdParams {
   uint32_t seed, replica;
   double rlist2;        // (rc + skin)^2
   double halfskin2;     // (skin/2)^2
+  double kick;          // multiple-time-step cycle: (dt/2)/m with dt = 1/M (0 without it)
 };
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) and Box-Muller ------------------

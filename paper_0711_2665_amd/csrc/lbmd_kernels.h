@@ -161,6 +161,11 @@ void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 // the noise from d.xi (drawn beforehand by launch_md_noise; unused by
 // replicas without noise and by the relaxation).
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s);
+// The multiple-time-step sub-cycle of a coupled step: M outer steps of
+// n_sub / M SPV sub-steps with the bonded forces, between kicks of the slow
+// forces (bead LJ, wall, field); noise from d.xi as in launch_md_cycle.
+constexpr int MTS_MAX_INNER = 40;   // inner sub-steps per outer step (the inner kernel's halo is 2 per sub-step)
+void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s);
 // Noise of one sub-cycle into d.xi, for the step counter + step_offset.
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);

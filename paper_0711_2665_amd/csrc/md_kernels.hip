@@ -74,9 +74,10 @@ __device__ inline void bead_cell(const Rep& R, const double* rp, int c[3]) {
   }
 }
 
-// r_mid of sub-step 0 and the displacement check that decides whether the
+// r_mid of sub-step 0 (with mts: r itself, where the first slow kick
+// evaluates its forces) and the displacement check that decides whether the
 // first launch rebuilds the lists.
-__global__ void k_md_start(Dev d, int nslots, MdOverride ov) {
+__global__ void k_md_start(Dev d, int nslots, MdOverride ov, int mts) {
   int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= nslots) return;
   const int rep = d.slot_rep[slot];
@@ -86,7 +87,7 @@ __global__ void k_md_start(Dev d, int nslots, MdOverride ov) {
   double d2 = 0.0, b2 = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double x = d.r[3 * slot + a] + hh * d.v[3 * slot + a];
+    double x = mts ? d.r[3 * slot + a] : d.r[3 * slot + a] + hh * d.v[3 * slot + a];
     d.rmid0[3 * slot + a] = x;
     double dd = x - d.ref[3 * slot + a];
     d2 += dd * dd;
@@ -232,6 +233,12 @@ __device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const doub
   return mask;
 }
 
+// SLOW: a kick of the multiple-time-step cycle instead of a sub-step.  The
+// slow forces (bead LJ, wall sites, field) are evaluated at r, which does not
+// change, and `last` half kicks v += kick F are applied one after the other
+// (2 between two outer steps, 1 at the ends); s is the kick's index in the
+// cycle (0..M), which selects the rotating rebuild words.
+template <bool SLOW>
 __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, int nslots, int s, int last) {
   __shared__ MdShared sh;
   const int t = threadIdx.x;
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
   const int bslot = tb / MD_LANES, lane = tb % MD_LANES;
   const int slot0 = blockIdx.x * MD_BPB;
   const int slot = slot0 + bslot;            // the grid covers the nslots slots exactly
-  const double* rabs = (s & 1) ? d.rmid1 : d.rmid0;
+  const double* rabs = SLOW ? d.r : ((s & 1) ? d.rmid1 : d.rmid0);
   double* rout = (s & 1) ? d.rmid0 : d.rmid1;
   auto clampslot = [nslots](int q) { return q < 0 ? 0 : (q >= nslots ? nslots - 1 : q); };
 
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) pre[m] = nbr_row[lane + MD_LANES * m];
   } else if (wave == 1) {
-    if (tb < 3 * (MD_BPB + 2)) {
+    if (!SLOW && tb < 3 * (MD_BPB + 2)) {
       // positions of the angle centred at slot slot0 - 1 + tb / 3
       const int c = slot0 - 1 + tb / 3;
       const int ia = clampslot(c - 1), ib = clampslot(c), ic = clampslot(c + 1);
@@ -294,7 +301,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
       if (rebuild) atomicAdd((unsigned long long*)&d.ctrl->rebuilds, 1ull);
       if (rebuild && !table_stale) atomicAdd((unsigned long long*)&d.ctrl->cell_rebuilds, 1ull);
     }
-    if (blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, 1ull);
+    if (!SLOW && blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, 1ull);
     sh.over = 0;
   }
   // lane 0 of each bead in wave 2 adds the contributions and moves the bead
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
   if (wave == 1) {
     // ---- the angles centred at p0 - 1 .. p0 + 16: lane 3 k + a takes
     // component a of angle k
-    if (tb < 3 * (MD_BPB + 2)) {
+    if (!SLOW && tb < 3 * (MD_BPB + 2)) {
       const int k = tb / 3, a = tb % 3;
       const int qc = p0 - 1 + k;
       if (qc >= 1 && qc <= P.nb - 2) {
@@ -431,7 +438,10 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     // (every lane of the bead reads them; lane 0 uses them).  Loaded here,
     // not with the first loads, so that they hold no registers while the
     // other waves work; they are needed only at the end.
-    {
+    if (SLOW) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) vo[a] = d.v[3 * slot + a];
+    } else {
       const int sm = clampslot(slot - 1), sq = clampslot(slot + 1);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -450,7 +460,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     for (int row = lane; row < WSPAN; row += MD_LANES)
       sh.wmask[bslot][row] = p < P.nb ? wall_row(P, g, rp, WLO + row, &sh.wallF[bslot][WSPAN * row]) : 0u;
     // ---- lane 0: bonds now, the rest after the barrier
-    if (lead) {
+    if (!SLOW && lead) {
       if (p > 0) bond_add(P, rp, rm, F);
       if (p < P.nb - 1) bond_add(P, rp, rq, F);
     }
@@ -485,9 +495,11 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
   const int cnt_b = sh.cnt[bslot];
   const int q0 = p0 - 1;
   const int nb = P.nb;
-  if (p - 1 >= 1 && p - 1 <= nb - 2) { const double* A = sh.ang[p - 1 - q0]; F[0] += A[6]; F[1] += A[7]; F[2] += A[8]; }
-  if (p >= 1 && p <= nb - 2) { const double* A = sh.ang[p - q0]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
-  if (p + 1 >= 1 && p + 1 <= nb - 2) { const double* A = sh.ang[p + 1 - q0]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2]; }
+  if (!SLOW) {
+    if (p - 1 >= 1 && p - 1 <= nb - 2) { const double* A = sh.ang[p - 1 - q0]; F[0] += A[6]; F[1] += A[7]; F[2] += A[8]; }
+    if (p >= 1 && p <= nb - 2) { const double* A = sh.ang[p - q0]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
+    if (p + 1 >= 1 && p + 1 <= nb - 2) { const double* A = sh.ang[p + 1 - q0]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2]; }
+  }
   for (int k = 0; k < cnt_b; ++k) {
     if (!((sh.hit[bslot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
     F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
@@ -497,6 +509,19 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     F[0] += sh.wallF[bslot][k][0]; F[1] += sh.wallF[bslot][k][1]; F[2] += sh.wallF[bslot][k][2];
   }
   if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
+
+  if (SLOW) {
+    bool fin = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double vn = vo[a] + P.kick * F[a];
+      if (last == 2) vn = vn + P.kick * F[a];
+      d.v[3 * slot + a] = vn;
+      fin = fin && isfinite(vn);
+    }
+    if (!fin) atomicOr(&d.ctrl->err, E_BEADS);
+    return;
+  }
 
   double u[3], xi[3];
 #pragma unroll
@@ -542,6 +567,101 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
 __global__ void k_zero_v(double* v, int n) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) v[k] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Inner cycle of outer step o of the multiple-time-step scheme: M_b SPV
+// sub-steps with the bonded forces only (bonds, bending), the friction
+// towards the frozen u_p and the noise of sub-step index o M_b + i, all in
+// one launch.  The bonded force on a bead depends on the chain neighbours
+// p-2 .. p+2 only, so a workgroup advances a segment of IN_WG consecutive
+// slots through the whole inner cycle with its positions in LDS and one
+// barrier per sub-step; the 2 M_b slots at each end are a halo computed again
+// by the neighbouring workgroup (after i sub-steps the missing neighbours
+// beyond the segment have corrupted at most 2 i slots at each end), so each
+// workgroup stores only the IN_WG - 4 M_b slots in the middle.  Sums follow
+// the definition's order: bonds to p-1 and p+1, then the angles centred at
+// p-1, p, p+1.  The last lane state also gives the displacement checks of the
+// slow kick that follows (index o + 1).
+// ---------------------------------------------------------------------------
+constexpr int IN_WG = 256;
+
+__global__ __launch_bounds__(IN_WG) void k_md_inner(Dev d, int nslots, int o, int Mb) {
+  __shared__ double pos[2][IN_WG][3];
+  const int j = threadIdx.x;
+  const int H = 2 * Mb, own = IN_WG - 2 * H;
+  const int gslot = (int)blockIdx.x * own - H + j;
+  const bool valid = gslot >= 0 && gslot < nslots;
+  const int slot = valid ? gslot : 0;
+  const int rep = d.slot_rep[slot];
+  const Rep& R = d.reps[rep];
+  const int p = slot - R.slot_off;
+  const int nb = R.mp.nb;
+  const bool active = valid && p < nb;
+  const double hh = R.mp.hh, e = R.mp.e, cf = R.mp.cf, gam = R.mp.gamma, omE = R.mp.omE, sig = R.mp.sig;
+  const double m = R.mp.m;
+  double r[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0}, J[3] = {0.0, 0.0, 0.0}, u[3] = {0.0, 0.0, 0.0};
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r[a] = d.r[3 * slot + a];
+      v[a] = d.v[3 * slot + a];
+      J[a] = d.J[3 * slot + a];
+      u[a] = R.mp.couple ? d.up[3 * slot + a] : 0.0;
+    }
+  }
+  // chain neighbour p + k is in the chain and in this segment
+  auto has = [&](int k) { return p + k >= 0 && p + k < nb && j + k >= 0 && j + k < IN_WG; };
+  for (int i = 0; i < Mb; ++i) {
+    const int sidx = o * Mb + i;
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (active && sig != 0.0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xi[a] = d.xi[(size_t)3 * ((size_t)sidx * nslots + slot) + a];
+    }
+    double rh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rh[a] = r[a] + hh * v[a];
+      pos[i & 1][j][a] = rh[a];
+    }
+    __syncthreads();
+    if (active) {
+      const double(*q)[3] = pos[i & 1];
+      double F[3] = {0.0, 0.0, 0.0};
+      if (p > 0 && has(-1)) bond_add(R.mp, rh, q[j - 1], F);
+      if (p < nb - 1 && has(1)) bond_add(R.mp, rh, q[j + 1], F);
+      if (p - 1 >= 1 && p - 1 <= nb - 2 && has(-2)) angle_add(R.mp, q[j - 2], q[j - 1], rh, 2, F);
+      if (p >= 1 && p <= nb - 2 && has(-1) && has(1)) angle_add(R.mp, q[j - 1], rh, q[j + 1], 1, F);
+      if (p + 1 >= 1 && p + 1 <= nb - 2 && has(2)) angle_add(R.mp, rh, q[j + 1], q[j + 2], 0, F);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double sx = sig * xi[a];
+        const double vn = e * v[a] + cf * (F[a] + gam * u[a]) + sx;
+        J[a] = J[a] - m * (omE * (u[a] - v[a]) + sx);
+        v[a] = vn;
+        r[a] = rh[a] + hh * vn;
+      }
+    }
+  }
+  if (j == 0 && blockIdx.x == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, (unsigned long long)Mb);
+  if (!active || j < H || j >= IN_WG - H) return;
+  bool fin = true;
+  double d2 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d.r[3 * slot + a] = r[a];
+    d.v[3 * slot + a] = v[a];
+    d.J[3 * slot + a] = J[a];
+    fin = fin && isfinite(v[a]) && isfinite(r[a]);
+    const double dd = r[a] - d.ref[3 * slot + a];
+    d2 += dd * dd;
+    const double db = r[a] - d.rbin[3 * slot + a];
+    b2 += db * db;
+  }
+  if (!fin) atomicOr(&d.ctrl->err, E_BEADS);
+  if (d2 > R.mp.halfskin2) d.rb[4 * rep + (o + 1) % 3] = 1u;
+  if (!(b2 <= CELL_MARGIN * CELL_MARGIN)) d.cst[4 * rep + (o + 1) % 3] = 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -669,9 +789,26 @@ void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOver
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
-  hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov);
+  hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov, 0);
   for (int k = 0; k < n_sub; ++k)
-    hipLaunchKernelGGL(k_md_substep, dim3(nblk), dim3(3 * MD_WG), 0, s, d, ov, nslots, k, k == n_sub - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_md_substep<false>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, ov, nslots, k,
+                       k == n_sub - 1 ? 1 : 0);
+}
+
+void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s) {
+  if (nslots <= 0 || n_sub <= 0 || M <= 0) return;
+  const int Mb = n_sub / M;
+  const unsigned nblk = (unsigned)(nslots / MD_BPB);
+  const int own = IN_WG - 4 * Mb;
+  const unsigned nin = (unsigned)((nslots + own - 1) / own);
+  MdOverride none{};
+  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+  hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, none, 1);
+  for (int o = 0; o < M; ++o) {
+    hipLaunchKernelGGL(k_md_substep<true>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, none, nslots, o, o == 0 ? 1 : 2);
+    hipLaunchKernelGGL(k_md_inner, dim3(nin), dim3(IN_WG), 0, s, d, nslots, o, Mb);
+  }
+  hipLaunchKernelGGL(k_md_substep<true>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, none, nslots, M, 1);
 }
 
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s) {

@@ -46,7 +46,15 @@ C3 = _cfg(name="large_512x256x256_8000beads", shape=(512, 256, 256), wall_axis=0
 C4 = _cfg(name="adjoint_64cube_100beads", shape=(64, 64, 64), wall_axis=2, wall_pos=32,
           pore_h=3, nb=100, steps=2000, init_seed=14, checkpoint_every=100)
 
-CONFIGS = {"c0": C0, "c1": C1, "c3": C3, "c4": C4}
+# The paper's bead LJ (Sec. 2: sigma = 1.8, eps = 1e-4, cut-off 2^(1/6) sigma)
+# with the bond rest length at the cut-off (the paper gives none), so the
+# truncated LJ does not act along a bond at rest; and the multiple-time-step
+# sub-cycle with M = 5 outer steps of 20 sub-steps (Sec. 2).
+PAPER_LJ = dict(sigma=1.8, eps=1e-4, rc=2.0 ** (1.0 / 6.0) * 1.8, r0=2.0 ** (1.0 / 6.0) * 1.8)
+C3M = _cfg(name="large_512x256x256_8000beads_paper_lj_mts5x20", shape=(512, 256, 256), wall_axis=0,
+           wall_pos=256, pore_h=7, nb=8000, steps=2000, init_seed=13, mts_outer=5, **PAPER_LJ)
+
+CONFIGS = {"c0": C0, "c1": C1, "c3": C3, "c4": C4, "c3m": C3M}
 
 
 def ensemble_configs(n_replicas=64, seed=15, steps=5000):
@@ -179,5 +187,5 @@ def mlups(cfg, seconds_per_step):
     return cells(cfg) / seconds_per_step / 1e6
 
 
-__all__ = ["BASE", "C0", "C1", "C3", "C4", "CONFIGS", "ensemble_configs", "initial_chain",
+__all__ = ["BASE", "C0", "C1", "C3", "C4", "C3M", "PAPER_LJ", "CONFIGS", "ensemble_configs", "initial_chain",
            "pore_bounds", "scaled", "cells", "mlups", "geometry_summary", "math"]

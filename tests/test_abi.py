@@ -75,6 +75,9 @@ def test_desc_layout_matches_header(tmp_path):
     (dict(nb=3, wall_axis=2, wall_pos=2, shape=(16, 5, 8)), "extents >= 6"),
     (dict(shape=(1024, 1024, 128)), "too large"),
     (dict(fluid_kT=-1e-4), "fluid_kT"),
+    (dict(mts_outer=3), "mts_outer"),
+    (dict(mts_outer=1), "mts_outer"),
+    (dict(mts_outer=-1), "mts_outer"),
 ])
 def test_host_validation(bad, msg):
     from paper_0711_2665_amd import lbmd

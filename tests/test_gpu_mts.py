@@ -1,0 +1,204 @@
+"""GPU parity of the multiple-time-step bead cycle (M outer steps: kicks of
+the slow forces, a fused launch of n_sub/M SPV sub-steps with the bonded
+forces) against the FP64 oracle, through the C ABI: bitwise without
+transcendental functions, within 1e-12 or the chaos envelope with noise and
+bending, FP32 deviation storage within its bound, chains longer than one
+segment of the fused inner launch, the ensemble and graph paths against
+single eager runs."""
+import numpy as np
+import pytest
+
+from paper_0711_2665_amd.workloads import C0, PAPER_LJ, initial_chain, scaled
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def _start(orc, cfg, precision=None, relax=None):
+    """The oracle relaxes the seeded chain; both sides start from its relaxed
+    positions with v = 0 and the fluid at rest."""
+    from paper_0711_2665_amd import lbmd
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(cfg["relax_substeps"] if relax is None else relax, cfg["gamma_relax"])
+    rr = o.beads()["r"]
+    o = orc.Oracle(cfg, rr, np.zeros_like(rr))
+    s = lbmd.Simulation(cfg, rr, None, precision=lbmd.LB_FP64 if precision is None else precision)
+    return o, s
+
+
+def _same(o, s, label):
+    fluid = o.flags() == 0
+    a, b = s.pops().double().cpu().numpy()[:, fluid], o.pops()[:, fluid]
+    sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+    ob = o.beads()
+    diff = {k: int((sb[k] != ob[k]).sum()) for k in ("r", "v", "up", "J")}
+    print(f"{label}: pops differing {int((a != b).sum())}, beads {diff}", flush=True)
+    assert np.array_equal(a, b)
+    for k in ("r", "v", "up", "J"):
+        assert np.array_equal(sb[k], ob[k]), k
+
+
+@pytest.mark.parametrize("M,n_sub", [(5, 100), (2, 80), (1, 20)])
+def test_mts_coupled_steps_bitwise(orc, M, n_sub):
+    """The 32^3 system with the paper's LJ, no noise and no bending: every
+    field equals the oracle bit for bit after 5 coupled steps (M_b = 20, the
+    largest inner cycle 40, and a single outer step)."""
+    torch = _torch()
+    cfg = scaled(C0, kT=0.0, kappa=0.0, mts_outer=M, n_sub=n_sub, **PAPER_LJ)
+    o, s = _start(orc, cfg)
+    o.couple_step(5)
+    s.couple_step(5)
+    torch.cuda.synchronize()
+    s.check()
+    _same(o, s, f"mts M={M} n_sub={n_sub}, 5 steps")
+    d = s.diagnostics()
+    assert d["substeps"] == 5 * n_sub
+
+
+def test_mts_long_chain_across_segments_bitwise(orc):
+    """A 1100-bead chain (per-step neighbour lists from the cell table; the
+    fused inner launch splits it into segments of 176 slots with 40-slot
+    halos) drifting across the box so that lists are rebuilt inside the
+    cycle: three coupled steps equal the oracle bit for bit."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=(48, 48, 48), wall_pos=24, nb=1100, kT=0.0, kappa=0.0, init_seed=9, mts_outer=5,
+                 **PAPER_LJ)
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(300, 1.0)
+    r0 = o.beads()["r"]
+    v0 = np.zeros_like(r0)
+    v0[:, 0] = 0.45
+    o = orc.Oracle(cfg, r0, v0)
+    s = lbmd.Simulation(cfg, r0, v0)
+    o.couple_step(3)
+    s.couple_step(3)
+    torch.cuda.synchronize()
+    s.check()
+    _same(o, s, "mts 1100 beads drifting, 3 steps")
+    d = s.diagnostics()
+    print(d, flush=True)
+    assert d["rebuilds"] >= 1
+
+
+def test_mts_coupled_with_noise_and_bending_fp64(orc):
+    """Noise and bending on (the GPU's and the host's log, sin, cos, atan2 may
+    differ in the last bit): after one step every field agrees to 1e-12;
+    after 10 and 30, within 1e-12 or 100x the oracle's own divergence from a
+    copy whose initial positions moved by one ulp."""
+    torch = _torch()
+    cfg = scaled(C0, mts_outer=5, **PAPER_LJ)
+    o, s = _start(orc, cfg)
+    r0 = o.beads()["r"]
+    o2 = orc.Oracle(cfg, np.nextafter(r0, np.inf), np.zeros_like(r0))
+    fluid = o.flags() == 0
+    done = 0
+    for target in (1, 10, 30):
+        o.couple_step(target - done)
+        o2.couple_step(target - done)
+        s.couple_step(target - done)
+        done = target
+        torch.cuda.synchronize()
+        ob, ob2 = o.beads(), o2.beads()
+        sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+        rows = {"pops": (_rel(s.pops().double().cpu().numpy()[:, fluid], o.pops()[:, fluid]),
+                         _rel(o2.pops()[:, fluid], o.pops()[:, fluid]))}
+        for k in ("r", "v", "up", "J"):
+            rows[k] = (_rel(sb[k], ob[k]), _rel(ob2[k], ob[k]))
+        print(f"mts c0 step {target}: " + ", ".join(f"{k} gpu {g:.1e} / envelope {e:.1e}"
+                                                   for k, (g, e) in rows.items()), flush=True)
+        for k, (g, e) in rows.items():
+            bound = TOL64 if target == 1 else max(TOL64, 100 * e)
+            assert g <= bound, (target, k, g, e)
+    s.check()
+
+
+def test_mts_fp32_deviation_error(orc):
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, mts_outer=5, **PAPER_LJ)
+    o, s = _start(orc, cfg, precision=lbmd.LB_FP32_DEV)
+    fluid = o.flags() == 0
+    _, w, _ = orc.tables()
+    o.couple_step(30)
+    s.couple_step(30)
+    torch.cuda.synchronize()
+    fo = o.pops()[:, fluid] - w[:, None]
+    fs = s.pops().double().cpu().numpy()[:, fluid]
+    err_f = np.abs(fs - fo).max()
+    rg, ro = s.beads()["r"].cpu().numpy(), o.beads()["r"]
+    print(f"fp32-dev mts c0 30 steps: |f - f64|_max {err_f:.3e} (max |f - w| {np.abs(fo).max():.3e}), "
+          f"|r - r64|_max {np.abs(rg - ro).max():.3e}", flush=True)
+    assert err_f < 1e-6
+    assert np.abs(rg - ro).max() < 1e-4
+
+
+def _ens_cfgs():
+    base = scaled(C0, mts_outer=5, **PAPER_LJ)
+    return [
+        scaled(base, name="m0", shape=(16, 12, 20), wall_axis=2, wall_pos=10, pore_h=3, nb=12, seed=11, replica=0,
+               init_seed=5),
+        scaled(base, name="m1", shape=(40, 32, 32), wall_axis=0, wall_pos=20, pore_h=4, nb=300, seed=12, replica=1,
+               init_seed=6, gamma=0.2),
+        scaled(base, name="m2", shape=(12, 12, 13), wall_axis=-1, wall_pos=0, pore_h=0, nb=0),
+        scaled(base, name="m3", shape=(24, 24, 24), wall_axis=2, wall_pos=12, pore_h=3, nb=33, seed=13, replica=3,
+               init_seed=7, kT=0.0, fluid_kT=1e-4),
+    ]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_mts_ensemble_graph_equals_replicas_run_alone(precision):
+    """An ensemble whose replicas sit side by side in the fused inner launch
+    (a segment may hold the end of one chain and the start of the next),
+    stepped by graph replays with eager work between them: every replica
+    equals the same system run alone with eager steps, bit for bit."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    prec = lbmd.LB_FP64 if precision == "fp64" else lbmd.LB_FP32_DEV
+    cfgs = _ens_cfgs()
+    r0s = [initial_chain(c)[0] for c in cfgs]
+    ens = lbmd.Ensemble(cfgs, r0s, precision=prec)
+    ens.relax(300, 1.0)
+    for n in (3, 4, 2):
+        ens.run(n, graph=True)
+        ens.observables()
+    torch.cuda.synchronize()
+    ens.check()
+    for k, cfg in enumerate(cfgs):
+        s = lbmd.Simulation(cfg, r0s[k] if cfg["nb"] else None, precision=prec)
+        s.relax(300, 1.0)
+        s.couple_step(9)
+        torch.cuda.synchronize()
+        nd = int((ens.pops(k) != s.pops()).sum())
+        bd = {n: int((ens.beads(k)[n] != s.beads()[n]).sum()) for n in ("r", "v", "J")} if cfg["nb"] else {}
+        print(f"{precision} mts ensemble replica {k}: pops differing {nd}, beads {bd}", flush=True)
+        assert nd == 0 and all(v == 0 for v in bd.values()), (k, nd, bd)
+        s.close()
+
+
+def test_adjoint_rejects_the_mts_cycle():
+    _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=(16, 16, 16), wall_pos=8, nb=8, mts_outer=5, **PAPER_LJ)
+    r, _ = initial_chain(cfg)
+    s = lbmd.Simulation(cfg, r)
+    with pytest.raises(lbmd.LbError) as e:
+        s.adjoint_sizes(4, 2)
+    assert e.value.code == lbmd.LB_ERR_UNSUPPORTED
