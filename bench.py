@@ -21,7 +21,9 @@ batched ensemble (64 uneven replicas in one context, graph replay, aggregate
 MLUPS and translocation steps), the adjoint on the 64^3 gradient workload
 (adjoint steps/s in FP64 and FP32, a finite-difference check), the same
 workload with a fluctuating fluid (noise on the non-conserved modes drawn in
-the sweep), and the FP64 CPU oracle timed on a bounded sample.
+the sweep), the same lattice and chain with the paper's soft bead LJ under
+the multiple-time-step cycle and under uniform sub-steps, and the FP64 CPU
+oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -274,6 +276,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--no-thermal", action="store_true")
+    ap.add_argument("--no-mts", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -353,6 +356,25 @@ def main():
                                 "sweep_alone": sweep_alone(rt, cells, elem),
                                 "lb_sweep_gbs": round(acht, 1), "lb_sweep_frac": round(acht / PEAK_HBM_GBS, 4),
                                 "lb_sweep_mean_launch_ms": round(rt["lb_ms"], 5)}
+    if not args.no_mts and args.workload == "c3":
+        # the paper's bead LJ on the same lattice and chain, with the
+        # multiple-time-step cycle (5 outer x 20 sub-steps) and, for
+        # comparison, with 100 uniform sub-steps
+        from paper_0711_2665_amd.workloads import C3M, scaled
+        km = max(20, args.steps // 2)
+        rm = run_gpu(C3M, args.precision, km, args.warmup)
+        ru = run_gpu(scaled(C3M, mts_outer=0), args.precision, km, args.warmup)
+        um = rm["nfluid"] - rm["forced_per_step"]
+        achm = (um * lb_bytes_per_update(elem) + (cells - um)) / (rm["lb_ms"] * 1e-3) / 1e9
+        out["paper_lj_mts"] = {
+            "workload": C3M["name"], "value": round(cells * km / rm["seconds"] / 1e6, 1), "unit": "MLUPS",
+            "steps": km, "ms_per_step": round(1e3 * rm["seconds"] / km, 4),
+            "bead_phase_ms": round(rm["bead_ms"], 4), "lb_sweep_mean_launch_ms": round(rm["lb_ms"], 5),
+            "lb_sweep_gbs": round(achm, 1), "lb_sweep_frac": round(achm / PEAK_HBM_GBS, 4),
+            "sweep_layout": {k: rm["tune"][k] for k in ("tile_nodes", "order", "grid", "cap")},
+            "uniform_100_substeps": {"value": round(cells * km / ru["seconds"] / 1e6, 1), "unit": "MLUPS",
+                                     "ms_per_step": round(1e3 * ru["seconds"] / km, 4),
+                                     "bead_phase_ms": round(ru["bead_ms"], 4)}}
     if not args.no_ensemble and args.workload == "c3":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 20, 200)
     if not args.no_adjoint and args.workload == "c3":

@@ -246,6 +246,9 @@ MdParams make_md(const lb_desc* d, double skin) {
   P.halfskin2 = (0.5 * skin) * (0.5 * skin);
   spv_coefficients(P, d->gamma, d->kT, h);
   P.kick = d->mts_outer > 0 ? 0.5 * (1.0 / (double)d->mts_outer) / P.m : 0.0;
+  const int cr = d->rc > 2.0 ? 3 : 2;       // ceil(rc) for 1 < rc <= 3 (rc <= 1: the 2-window still covers it)
+  P.wlo = 1 - cr;
+  P.whi = cr;
   return P;
 }
 
@@ -1118,8 +1121,9 @@ int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms)
   key += c->dev ? "f32:" : "f64:";
   key += c->any_fluct ? "thermal:" : "athermal:";
   for (const lb_desc& x : c->d) {
-    char buf[96];
-    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d;", x.nx, x.ny, x.nz, x.wall_axis, x.wall_pos, x.pore_h, x.nb);
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%d,%d,%d,%d,%d,%d,%d,%d,%d,%.17g;", x.nx, x.ny, x.nz, x.wall_axis, x.wall_pos,
+             x.pore_h, x.nb, x.n_sub, x.mts_outer, x.rc);
     key += buf;
   }
   auto it = cache.find(key);

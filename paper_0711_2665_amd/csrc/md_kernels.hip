@@ -186,8 +186,10 @@ struct MdShared {
 static_assert(2 * sizeof(MdShared) <= (size_t)LDS_KEEP, "two sub-step workgroups fit in the LDS a capped sweep leaves");
 
 // Wall sites of the bead at rp, one row of the window at a time: the sites
-// at offsets -2..3 from the base node along the lower transverse axis (o0),
-// for offset o1 along the higher one.  Each is the truncated-LJ pair force of
+// at offsets P.wlo..P.whi (within -2..3) from the base node along the lower
+// transverse axis (o0), for offset o1 along the higher one; offsets outside
+// 1 - ceil(r_c) .. ceil(r_c) cannot reach r_c, so the window shrinks to
+// -1..2 for r_c <= 2.  Each is the truncated-LJ pair force of
 // one solid site within r_c; the force of offset o0 goes to out[o0 - WLO] and
 // the returned mask has bit o0 - WLO set.  r_c <= 3 makes the window cover
 // every candidate.  Solid sites lie in the plane a = wall_pos (minus the
@@ -209,13 +211,13 @@ __device__ inline uint32_t wall_row(const MdParams& P, const Geom& g, const doub
   int off = g.wall_pos - ba;                // offset along the normal reaching the plane
   if (off < WLO) off += na;
   if (off > WHI) off -= na;
-  if (off < WLO || off > WHI) return 0u;
+  if (off < P.wlo || off > P.whi) return 0u;
   const int sa = ba + off;
   const int u1 = bt1 + o1;
   const int v1 = u1 < 0 ? u1 + n1 : (u1 >= n1 ? u1 - n1 : u1);
   const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
   uint32_t mask = 0u;
-  for (int o0 = WLO; o0 <= WHI; ++o0) {
+  for (int o0 = P.wlo; o0 <= P.whi; ++o0) {
     const int u0 = bt0 + o0;
     const int v0 = u0 < 0 ? u0 + n0 : (u0 >= n0 ? u0 - n0 : u0);
     const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
@@ -455,10 +457,13 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
         rq[a] = rabs[3 * sq + a];
       }
     }
-    // ---- wall sites: lane l of a bead takes the rows o1 = WLO + l and
-    // WLO + l + 4 of the window (the second only for l < 2)
-    for (int row = lane; row < WSPAN; row += MD_LANES)
-      sh.wmask[bslot][row] = p < P.nb ? wall_row(P, g, rp, WLO + row, &sh.wallF[bslot][WSPAN * row]) : 0u;
+    // ---- wall sites: rows outside wlo..whi hold no site within r_c and
+    // stay empty; lane l takes the rows o1 = wlo + l, wlo + l + 4, ... (for
+    // r_c <= 2 one row per lane, all lanes at once).  The clearing stores
+    // precede the row stores of the same wave.
+    for (int row = lane; row < WSPAN; row += MD_LANES) sh.wmask[bslot][row] = 0u;
+    for (int o1 = P.wlo + lane; o1 <= P.whi; o1 += MD_LANES)
+      sh.wmask[bslot][o1 - WLO] = p < P.nb ? wall_row(P, g, rp, o1, &sh.wallF[bslot][WSPAN * (o1 - WLO)]) : 0u;
     // ---- lane 0: bonds now, the rest after the barrier
     if (!SLOW && lead) {
       if (p > 0) bond_add(P, rp, rm, F);
@@ -504,8 +509,14 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     if (!((sh.hit[bslot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
     F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
   }
-  for (int k = 0; k < MAXWALL; ++k) {
-    if (!((sh.wmask[bslot][k / WSPAN] >> (k % WSPAN)) & 1u)) continue;
+  // the wall sites within r_c, in ascending site order (set bits only: most
+  // beads have none)
+  uint64_t wm = 0;
+#pragma unroll
+  for (int row = 0; row < WSPAN; ++row) wm |= (uint64_t)sh.wmask[bslot][row] << (WSPAN * row);
+  while (wm) {
+    const int k = __builtin_ctzll(wm);
+    wm &= wm - 1;
     F[0] += sh.wallF[bslot][k][0]; F[1] += sh.wallF[bslot][k][1]; F[2] += sh.wallF[bslot][k][2];
   }
   if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;

@@ -88,7 +88,7 @@ def timeline(a):
     md, sweep_end = [], None
     for name, st, en, dur, gx, wx in rows[i0 + 1:i1 + 1]:
         k = short(name)
-        if k.endswith("k_md_substep"):
+        if k.endswith("k_md_substep") or k.endswith("k_md_substep<false>"):   # uniform sub-steps
             md.append((st - t0, en - t0, dur))
             continue
         if "k_lb<" in k:
