@@ -121,7 +121,7 @@ __global__ void k_bead_prep(Dev d, int nslots) {
 // first lane in corner order.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__global__ void k_gather(const T* __restrict__ A, Dev d, int nslots) {
+__global__ void k_gather(const T* __restrict__ A, Dev d, int nslots, int start) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int slot = e >> 3, k = e & 7;
   bool on = slot < nslots;
@@ -147,7 +147,28 @@ __global__ void k_gather(const T* __restrict__ A, Dev d, int nslots) {
   double acc[3] = {0.0, 0.0, 0.0};
   for (int c = 0; c < 8; ++c)
     for (int a = 0; a < 3; ++a) acc[a] += __shfl(t[a], base + c, 64);
-  if (on && k == 0) { d.up[3 * slot] = acc[0]; d.up[3 * slot + 1] = acc[1]; d.up[3 * slot + 2] = acc[2]; }
+  if (on && k == 0) {
+    d.up[3 * slot] = acc[0]; d.up[3 * slot + 1] = acc[1]; d.up[3 * slot + 2] = acc[2];
+    if (start) {
+      // the opening of the MD sub-cycle: r_mid of sub-step 0 (start = 1;
+      // with the multiple-time-step cycle, start = 2, r itself) and the
+      // displacement checks that decide whether its first launch rebuilds
+      // the neighbour lists
+      const Rep& R = d.reps[rep];
+      double d2 = 0.0, b2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double x = start == 2 ? d.r[3 * slot + a] : d.r[3 * slot + a] + R.mp.hh * d.v[3 * slot + a];
+        d.rmid0[3 * slot + a] = x;
+        const double dd = x - d.ref[3 * slot + a];
+        d2 += dd * dd;
+        const double db = x - d.rbin[3 * slot + a];
+        b2 += db * db;
+      }
+      if (d2 > R.mp.halfskin2) d.rb[4 * rep] = 1u;
+      if (!(b2 <= CELL_MARGIN * CELL_MARGIN)) d.cst[4 * rep] = 1u;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -493,10 +514,10 @@ void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStre
 }
 
 template <typename T, bool DEV>
-void launch_gather(const void* A, const Dev& d, int nslots, hipStream_t s) {
+void launch_gather(const void* A, const Dev& d, int nslots, int start, hipStream_t s) {
   if (nslots > 0)
     hipLaunchKernelGGL((k_gather<T, DEV>), dim3(blocks_for(8L * nslots, 64)), dim3(64), 0, s, (const T*)A, d,
-                       nslots);
+                       nslots, start);
 }
 
 void launch_bead_prep(const Dev& d, int nslots, hipStream_t s) {
@@ -533,8 +554,8 @@ template void launch_lb<double, false>(const void*, void*, const Dev&, int, int,
 template void launch_lb<float, true>(const void*, void*, const Dev&, int, int, int, int, int, bool, hipStream_t);
 template void launch_lb_forced<double, false>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_lb_forced<float, true>(const void*, void*, const Dev&, int, hipStream_t);
-template void launch_gather<double, false>(const void*, const Dev&, int, hipStream_t);
-template void launch_gather<float, true>(const void*, const Dev&, int, hipStream_t);
+template void launch_gather<double, false>(const void*, const Dev&, int, int, hipStream_t);
+template void launch_gather<float, true>(const void*, const Dev&, int, int, hipStream_t);
 template void launch_spread<double>(const Dev&, int, hipStream_t);
 template void launch_spread_lb<double, false>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_spread_lb<float, true>(const void*, void*, const Dev&, int, hipStream_t);

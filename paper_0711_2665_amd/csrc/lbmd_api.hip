@@ -327,7 +327,7 @@ struct lb_ctx {
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
   hipStream_t s1 = nullptr, s2 = nullptr;
-  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr;
+  hipEvent_t fork = nullptr, prep = nullptr, join = nullptr, join1 = nullptr, mdone = nullptr;
   // graph of two coupled steps, starting at population parity graph_cur
   hipStream_t scap = nullptr;
   hipGraph_t graph = nullptr;
@@ -466,23 +466,30 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   // the next step's noise, into the other slot, after the sweep: off the
   // bead stream's path
   if (c->any_noise) launch_md_noise(with_noise_slot(c, c->cur ^ 1), c->nslots, c->n_sub, 1, c->s2);
-  acc(hipEventRecord(c->join, c->s2));
   // long chains: the lists of this step were built at the end of the
-  // previous one (when the sweep is normally done), unless the positions
-  // changed since
+  // previous one (beside the spreading), unless the positions changed since
   if (c->step_lists && c->lists_stale) launch_nbr_build(D, c->nslots, c->nrep, sb);
-  if (c->dev) launch_gather<float, true>(A, D, c->nslots, sb);
-  else launch_gather<double, false>(A, D, c->nslots, sb);
+  // the gather also opens the sub-cycle (after its flag reset)
+  launch_md_begin(D, c->nrep, sb);
+  const int start = c->mts > 0 ? 2 : 1;
+  if (c->dev) launch_gather<float, true>(A, D, c->nslots, start, sb);
+  else launch_gather<double, false>(A, D, c->nslots, start, sb);
   MdOverride none{};
-  if (c->mts > 0) launch_md_cycle_mts(D, c->nslots, c->nrep, c->n_sub, c->mts, sb);
-  else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb);
+  if (c->mts > 0) launch_md_cycle_mts(D, c->nslots, c->nrep, c->n_sub, c->mts, sb, false);
+  else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb, false);
+  if (c->step_lists) acc(hipEventRecord(c->mdone, sb));
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
+  prof_mark(c, 1, sb);
   if (c->step_lists) {
-    launch_nbr_build(D, c->nslots, c->nrep, sb);      // from r(n+1), for the next step
+    // the next step's lists from r(n+1), on the sweep stream (done by now)
+    // beside the spreading, which touches none of their arrays; enqueued
+    // after the spreading so that a replayed graph issues that first
+    acc(hipStreamWaitEvent(c->s2, c->mdone, 0));
+    launch_nbr_build(D, c->nslots, c->nrep, c->s2);
     c->lists_stale = false;
   }
-  prof_mark(c, 1, sb);
+  acc(hipEventRecord(c->join, c->s2));
   acc(hipEventRecord(c->join1, sb));
   acc(hipStreamWaitEvent(st, c->join, 0));
   acc(hipStreamWaitEvent(st, c->join1, 0));
@@ -659,8 +666,9 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     hipError_t e5 = hipStreamCreateWithFlags(&c->s1, hipStreamNonBlocking);
     hipError_t e6 = hipEventCreateWithFlags(&c->prep, hipEventDisableTiming);
     hipError_t e7 = hipEventCreateWithFlags(&c->join1, hipEventDisableTiming);
+    hipError_t e8 = hipEventCreateWithFlags(&c->mdone, hipEventDisableTiming);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
-        e6 != hipSuccess || e7 != hipSuccess) {
+        e6 != hipSuccess || e7 != hipSuccess || e8 != hipSuccess) {
       lb_destroy(c);
       return fail(LB_ERR_DEVICE, "stream/event creation failed");
     }
@@ -816,6 +824,7 @@ void lb_destroy(lb_ctx* ctx) {
   if (ctx->prep) (void)hipEventDestroy(ctx->prep);
   if (ctx->join) (void)hipEventDestroy(ctx->join);
   if (ctx->join1) (void)hipEventDestroy(ctx->join1);
+  if (ctx->mdone) (void)hipEventDestroy(ctx->mdone);
   if (ctx->s1) (void)hipStreamDestroy(ctx->s1);
   if (ctx->s2) (void)hipStreamDestroy(ctx->s2);
   if (ctx->scap) (void)hipStreamDestroy(ctx->scap);

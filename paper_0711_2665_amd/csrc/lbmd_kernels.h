@@ -125,8 +125,10 @@ void launch_lb(const void* A, void* B, const Dev& d, int ntiles, int tile_nodes,
                bool fluct, hipStream_t s);
 template <typename T, bool DEV>
 void launch_lb_forced(const void* A, void* B, const Dev& d, int maxlist, hipStream_t s);
+// start: 0, or also open the MD sub-cycle (what k_md_start does: 1 for
+// uniform sub-steps, 2 for the multiple-time-step cycle) after launch_md_begin
 template <typename T, bool DEV>
-void launch_gather(const void* A, const Dev& d, int nslots, hipStream_t s);
+void launch_gather(const void* A, const Dev& d, int nslots, int start, hipStream_t s);
 void launch_bead_prep(const Dev& d, int nslots, hipStream_t s);
 template <typename T>
 void launch_spread(const Dev& d, int nslots, hipStream_t s);
@@ -160,12 +162,16 @@ void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 // MD sub-cycle of all replicas: n_sub launches, one per sub-step, reading
 // the noise from d.xi (drawn beforehand by launch_md_noise; unused by
 // replicas without noise and by the relaxation).
-void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s);
+// prologue = false: the cycle's opening (launch_md_begin and the start of the
+// sub-cycle) was done already, by launch_md_begin and launch_gather
+void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s,
+                     bool prologue = true);
+void launch_md_begin(const Dev& d, int nrep, hipStream_t s);
 // The multiple-time-step sub-cycle of a coupled step: M outer steps of
 // n_sub / M SPV sub-steps with the bonded forces, between kicks of the slow
 // forces (bead LJ, wall, field); noise from d.xi as in launch_md_cycle.
 constexpr int MTS_MAX_INNER = 40;   // inner sub-steps per outer step (the inner kernel's halo is 2 per sub-step)
-void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s);
+void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s, bool prologue = true);
 // Noise of one sub-cycle into d.xi, for the step counter + step_offset.
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);

@@ -293,7 +293,9 @@ __device__ inline void bounce_back(const T* __restrict__ A, const uint8_t* __res
 // also where in[u] is false).  The flags and the straight pulls f_i =
 // A_i(x - c_i) of all U nodes are issued together (a straight pull is a valid
 // read at any node); a node next to a wall then replaces what came from solid
-// nodes.  Nodes with in[u] false, solid nodes and, with skip_forced, nodes
+// nodes.  Flags and pulls are non-temporal loads: the streamed lattice then
+// does not push the bead phase's working set out of the caches while the two
+// run side by side.  Nodes with in[u] false, solid nodes and, with skip_forced, nodes
 // carrying bead force are neither collided nor stored.  FL: replicas with a
 // fluctuating fluid add its noise for LB step n.
 template <typename T, bool DEV, int U, bool FL>
@@ -305,13 +307,13 @@ __device__ inline void lb_nodes(const T* __restrict__ A, T* __restrict__ B, cons
   T f[U][Q];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    fl[u] = flags[c[u]];
+    fl[u] = __builtin_nontemporal_load(&flags[c[u]]);
     int x = c[u] % p.nx;
     int yz = c[u] / p.nx;
     const Nbr nb = make_nbr(p, x, yz % p.ny, yz / p.ny);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      f[u][i] = A[(size_t)i * N + (size_t)(c[u] + nb.off(-cx(i), -cy(i), -cz(i)))];
+      f[u][i] = __builtin_nontemporal_load(&A[(size_t)i * N + (size_t)(c[u] + nb.off(-cx(i), -cy(i), -cz(i)))]);
   }
   // every pull is taken here, so none is deferred behind the flag tests
 #pragma unroll

@@ -796,25 +796,34 @@ void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {
   hipLaunchKernelGGL(k_md_invalidate, dim3(1), dim3(256), 0, s, d.rb, nrep);
 }
 
-void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s) {
+void launch_md_begin(const Dev& d, int nrep, hipStream_t s) {
+  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+}
+
+void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s,
+                     bool prologue) {
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
-  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
-  hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov, 0);
+  if (prologue) {
+    hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+    hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov, 0);
+  }
   for (int k = 0; k < n_sub; ++k)
     hipLaunchKernelGGL(k_md_substep<false>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, ov, nslots, k,
                        k == n_sub - 1 ? 1 : 0);
 }
 
-void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s) {
+void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s, bool prologue) {
   if (nslots <= 0 || n_sub <= 0 || M <= 0) return;
   const int Mb = n_sub / M;
   const unsigned nblk = (unsigned)(nslots / MD_BPB);
   const int own = IN_WG - 4 * Mb;
   const unsigned nin = (unsigned)((nslots + own - 1) / own);
   MdOverride none{};
-  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
-  hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, none, 1);
+  if (prologue) {
+    hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+    hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, none, 1);
+  }
   for (int o = 0; o < M; ++o) {
     hipLaunchKernelGGL(k_md_substep<true>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, none, nslots, o, o == 0 ? 1 : 2);
     hipLaunchKernelGGL(k_md_inner, dim3(nin), dim3(IN_WG), 0, s, d, nslots, o, Mb);

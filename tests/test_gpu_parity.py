@@ -323,6 +323,30 @@ def test_long_chain_rebuilds_inside_the_cycle_bitwise(orc):
     assert diag["cell_rebuilds"] >= 1 and diag["rebuilds"] >= diag["cell_rebuilds"]
 
 
+def test_long_chain_graph_replay_equals_eager_steps(orc):
+    """The long-chain path builds the next step's lists on the sweep stream
+    beside the spreading: steps replayed from the captured graph, with eager
+    work between the replays, equal eager steps bit for bit."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=(40, 40, 40), wall_pos=20, nb=1100, init_seed=9)
+    r, _ = initial_chain(cfg)
+    a = lbmd.Simulation(cfg, r)
+    b = lbmd.Simulation(cfg, r)
+    for e in (a, b):
+        e.relax(300, 1.0)
+    for n in (2, 3, 1, 4):
+        a.couple_step(n)
+        b.run(n, graph=True)
+        b.observables()
+        torch.cuda.synchronize()
+        assert torch.equal(a.pops(), b.pops()), n
+        for k in ("r", "v", "up", "J"):
+            assert torch.equal(a.beads()[k], b.beads()[k]), (n, k)
+    a.check()
+    b.check()
+
+
 def test_paper_soft_lj_coupled_steps_bitwise(orc):
     """The paper's bead LJ (sigma = 1.8, eps = 1e-4, r_c = 2^(1/6) 1.8 > 2,
     so wall sites two nodes from a bead's base node count), without noise and
