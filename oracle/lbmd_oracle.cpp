@@ -230,6 +230,7 @@ typedef struct {
   uint32_t seed, replica;
   double fluid_kT;     // thermal energy of the fluid noise (0: athermal BGK fluid)
   int mts_outer;       // 0: n_sub uniform sub-steps; M > 0: the multiple-time-step cycle with M outer steps
+  int coupling;        // bead <-> lattice transfer: 0 trilinear, 1 nearest grid point
 } or_desc;
 }
 
@@ -450,8 +451,13 @@ struct Sim {
     if (val(w) >= (double)n) w = w - R((double)n);
     return w;
   }
-  // Trilinear stencil of bead p at position rp: base node b, the 8 corner
-  // nodes (corner k has offsets (k&1, k>>1&1, k>>2&1)) and their weights.
+  // Stencil of bead p at position rp: base node b, the 8 corner nodes
+  // (corner k has offsets (k&1, k>>1&1, k>>2&1)) and their weights --
+  // trilinear, or with the nearest-grid-point transfer (Sec. 2, the
+  // particle/grid paragraph: the fluid velocity is taken at the nearest node
+  // and the forces go back to it) weight 1 at the nearest corner, which is
+  // the upper one along an axis where the fraction is at least 1/2, and 0 at
+  // the others.
   void stencil(const R* rp, long node[8], R W[8]) const {
     int b[3];
     R del[3];
@@ -459,6 +465,7 @@ struct Sim {
       R w = wrapc(rp[a], ext(a));
       b[a] = (int)std::floor(val(w));
       del[a] = w - R((double)b[a]);
+      if (d.coupling == 1) del[a] = val(del[a]) >= 0.5 ? R(1.0) : R(0.0);
     }
     for (int k = 0; k < 8; ++k) {
       int o[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
@@ -949,6 +956,7 @@ typedef Sim<double> SimD;
 void* or_create(const or_desc* d, const double* r0, const double* v0) {
   if (!d || d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || !(d->tau > 0.5) || d->n_sub <= 0) return nullptr;
   if (d->mts_outer < 0 || (d->mts_outer > 0 && d->n_sub % d->mts_outer != 0)) return nullptr;
+  if (d->coupling != 0 && d->coupling != 1) return nullptr;
   SimD* s = new SimD();
   s->init(*d, r0, v0);
   return s;

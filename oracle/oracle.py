@@ -28,7 +28,7 @@ class OrDesc(C.Structure):
         ("kappa", C.c_double), ("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double),
         ("gamma", C.c_double), ("kT", C.c_double), ("f_drive", C.c_double),
         ("n_sub", C.c_int), ("seed", C.c_uint32), ("replica", C.c_uint32),
-        ("fluid_kT", C.c_double), ("mts_outer", C.c_int),
+        ("fluid_kT", C.c_double), ("mts_outer", C.c_int), ("coupling", C.c_int),
     ]
 
 
@@ -114,6 +114,7 @@ def make_desc(cfg):
     d.replica = cfg.get("replica", 0) & 0xFFFFFFFF
     d.fluid_kT = cfg.get("fluid_kT", 0.0)
     d.mts_outer = cfg.get("mts_outer", 0)
+    d.coupling = cfg.get("coupling", 0)
     return d
 
 

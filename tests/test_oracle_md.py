@@ -114,6 +114,58 @@ def test_gather_is_transpose_of_spread(orc):
     assert abs(lhs - rhs) < 1e-14 * (abs(lhs) + 1e-3)
 
 
+# -- nearest-grid-point transfer (Sec. 2, the particle/grid paragraph): u_p
+#    is the fluid velocity at the node nearest to the bead (round half up,
+#    periodic), and J goes back to that node alone; momentum is conserved
+
+def _nearest_node(rp, L):
+    w = rp - L * np.floor(rp / L)
+    n = np.floor(w + 0.5).astype(int) % L
+    return n[0] + L[0] * (n[1] + L[1] * n[2])
+
+
+def test_ngp_gather_takes_the_nearest_node(orc):
+    cfg = scaled(C0, shape=(12, 10, 14), wall_pos=7, nb=1, coupling=1)
+    o = orc.Oracle(cfg, np.zeros((1, 3)))
+    L = np.array([12, 10, 14])
+    rng = np.random.default_rng(8)
+    _, w, _ = orc.tables()
+    o.set_pops(w[:, None] * (1 + 0.05 * rng.standard_normal((19, o.N))))
+    U = o.node_velocity_field().reshape(3, -1)
+    pts = [rng.uniform(-30, 30, 3) for _ in range(40)]
+    pts += [np.array([3.5, 2.5, 6.5]), np.array([11.7, 9.6, 13.5]), np.array([-0.5, 4.49999, 7.0])]
+    for rp in pts:
+        o.set_beads(rp[None, :], np.zeros((1, 3)))
+        up = o.gather()[0]
+        assert np.array_equal(up, U[:, _nearest_node(rp, L)]), rp
+
+
+def test_ngp_spread_is_the_transpose_and_conserves_momentum(orc):
+    cfg = scaled(C0, shape=(12, 10, 14), wall_pos=7, nb=9, coupling=1)
+    r, _ = initial_chain(cfg)
+    o = orc.Oracle(cfg, r)
+    rng = np.random.default_rng(9)
+    J = rng.standard_normal((cfg["nb"], 3))
+    F = o.spread(J).reshape(3, -1)
+    want = np.zeros_like(F)
+    L = np.array([12, 10, 14])
+    solid = o.flags().reshape(-1) == 1
+    for p in range(cfg["nb"]):
+        n = _nearest_node(r[p], L)
+        if not solid[n]:
+            want[:, n] += J[p]
+    assert np.allclose(F, want, rtol=0, atol=1e-15)
+    # a coupled run in a periodic box conserves fluid + bead momentum
+    cfg2 = scaled(C0, shape=(16, 16, 16), wall_axis=-1, nb=10, n_sub=50, kT=1e-3, coupling=1)
+    r2, _ = initial_chain(scaled(C0, shape=(16, 16, 16), wall_pos=8, nb=10))
+    o2 = orc.Oracle(cfg2, r2, 0.02 * rng.standard_normal(r2.shape))
+    P0 = o2.observables()
+    o2.couple_step(20)
+    P1 = o2.observables()
+    assert np.abs(P1[5:8] - P0[5:8]).max() > 1e-3
+    assert np.abs((P1[1:4] + P1[5:8]) - (P0[1:4] + P0[5:8])).max() < 1e-12
+
+
 # -- P12: force laws.  Cell list and all-pairs give the same LJ sums bitwise;
 #    internal forces sum to zero; every force is minus the gradient of its
 #    energy (central differences).
