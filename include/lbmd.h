@@ -75,6 +75,8 @@ enum {
  * pore_h - 1] on each), periodic on all three axes.  wall_axis = -1 means no
  * wall (and no driving field).
  */
+enum { LB_COUPLING_TRILINEAR = 0, LB_COUPLING_NGP = 1 };
+
 typedef struct lb_desc {
   int32_t nx, ny, nz;
   int32_t precision;      /* LB_FP64 or LB_FP32_DEV                          */
@@ -109,6 +111,12 @@ typedef struct lb_desc {
                              kick.  n_sub / M must be a whole number <= 40; all
                              replicas share M; the pre-relaxation always uses
                              uniform sub-steps                               */
+  int32_t coupling;       /* bead <-> lattice transfer of u_p and the impulse
+                             (Sec. 2, the particle/grid paragraph):
+                             LB_COUPLING_TRILINEAR (the 8 nodes around the
+                             bead, trilinear weights) or LB_COUPLING_NGP (the
+                             paper's: the nearest node, the upper one along an
+                             axis where the fraction is 1/2)                 */
 } lb_desc;
 
 /* Byte sizes of the caller-allocated device buffers (256-byte aligned), and
@@ -143,7 +151,8 @@ typedef struct lb_ctx lb_ctx;
  * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
  * gamma, kT or fluid_kT, rc outside (0, 3], nb > 0 without a positive
  * mass, nb > 0 with a wall on a lattice with an extent below 6, or an
- * mts_outer that is negative or does not divide n_sub into at most 40. */
+ * mts_outer that is negative or does not divide n_sub into at most 40, or
+ * an unknown coupling. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
 
 /* As lb_buffer_sizes for nrep replicas d[0..nrep-1] in one context.  All
@@ -273,8 +282,9 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * that step, recomputed segment by segment from checkpoints taken every K
  * steps of the forward pass.
  * Supported: one-replica contexts with 1 <= nb <= 128, gamma > 0, an
- * athermal fluid (fluid_kT = 0) and the uniform sub-cycle (mts_outer = 0)
- * (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either precision.
+ * athermal fluid (fluid_kT = 0), the uniform sub-cycle (mts_outer = 0) and
+ * the trilinear transfer (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either
+ * precision.
  *
  * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1
  *   checkpoints of lb_sizes.state_bytes, K population arrays of tape, the

@@ -109,6 +109,7 @@ __global__ void k_bead_prep(Dev d, int nslots) {
   d.next[slot] = atomicExch(&d.head[R.node_off + cell], slot);
   uint8_t* fr = d.flags + R.node_off;
   for (int k = 0; k < 8; ++k) {
+    if (!corner_used(R.g, st, k)) continue;
     int n = (int)corner_node(R.g, st, k);
     uint8_t fl = fr[n];
     if (!(fl & F_SOLID)) fr[n] = fl | F_FORCED;
@@ -192,6 +193,7 @@ __global__ void k_spread(Dev d, int nslots) {
   const uint8_t* fr = d.flags + R.node_off;
   double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
   Stencil st = make_stencil(g, rp);
+  if (!corner_used(g, st, k)) return;
   int n = (int)corner_node(g, st, k);
   if (fr[n] & F_SOLID) return;
   int nz_ = n / g.nxy, rem = n - nz_ * g.nxy, ny_ = rem / g.nx, nx_ = rem - ny_ * g.nx;
@@ -205,6 +207,11 @@ __global__ void k_spread(Dev d, int nslots) {
     int bz = nz_ - ((k2 >> 2) & 1); if (bz < 0) bz += g.nz;
     int cell = bx + g.nx * (by + g.ny * bz);
     for (int q = d.head[R.node_off + cell]; q >= 0; q = d.next[q]) {
+      if (g.ngp) {
+        // with the nearest-grid-point transfer only q's nearest node counts
+        const Stencil sq = make_stencil(g, &d.rs[3 * q]);
+        if (!corner_used(g, sq, k2)) continue;
+      }
       int key = (q - R.slot_off) * 8 + k2;
       if (cnt < MAXCONTRIB) {
         int j = cnt++;
@@ -252,6 +259,7 @@ __global__ void k_spread_lb(const T* __restrict__ A, T* __restrict__ B, Dev d, i
   const uint8_t* fr = d.flags + R.node_off;
   double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
   Stencil st = make_stencil(g, rp);
+  if (!corner_used(g, st, k)) return;
   int n = (int)corner_node(g, st, k);
   if (fr[n] & F_SOLID) return;
   int nz_ = n / g.nxy, rem = n - nz_ * g.nxy, ny_ = rem / g.nx, nx_ = rem - ny_ * g.nx;
@@ -264,6 +272,11 @@ __global__ void k_spread_lb(const T* __restrict__ A, T* __restrict__ B, Dev d, i
     int bz = nz_ - ((k2 >> 2) & 1); if (bz < 0) bz += g.nz;
     int cell = bx + g.nx * (by + g.ny * bz);
     for (int q = d.head[R.node_off + cell]; q >= 0; q = d.next[q]) {
+      if (g.ngp) {
+        // with the nearest-grid-point transfer only q's nearest node counts
+        const Stencil sq = make_stencil(g, &d.rs[3 * q]);
+        if (!corner_used(g, sq, k2)) continue;
+      }
       int key = (q - R.slot_off) * 8 + k2;
       if (cnt < MAXCONTRIB) {
         int j = cnt++;

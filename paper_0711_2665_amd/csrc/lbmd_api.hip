@@ -166,6 +166,8 @@ int validate_one(const lb_desc* d, int r) {
   if (d->nb < 0) return fail(LB_ERR_ARG, "replica %d: negative bead count", r);
   if (d->n_sub < 1) return fail(LB_ERR_ARG, "replica %d: n_sub must be >= 1", r);
   if (d->mts_outer < 0) return fail(LB_ERR_ARG, "replica %d: mts_outer must be >= 0", r);
+  if (d->coupling != LB_COUPLING_TRILINEAR && d->coupling != LB_COUPLING_NGP)
+    return fail(LB_ERR_ARG, "replica %d: unknown coupling %d", r, d->coupling);
   if (d->mts_outer > 0 && (d->n_sub % d->mts_outer != 0 || d->n_sub / d->mts_outer > MTS_MAX_INNER))
     return fail(LB_ERR_ARG, "replica %d: mts_outer must divide n_sub into at most %d sub-steps per outer step", r,
                 MTS_MAX_INNER);
@@ -209,6 +211,7 @@ Geom make_geom(const lb_desc* d) {
   g.t0 = d->wall_axis == 0 ? 1 : 0;
   g.t1 = d->wall_axis == 2 ? 1 : 2;
   if (d->wall_axis < 0) { g.t0 = 0; g.t1 = 1; }
+  g.ngp = d->coupling == LB_COUPLING_NGP ? 1 : 0;
   int n0 = ext(g, g.t0), n1 = ext(g, g.t1);
   g.lo0 = n0 / 2 - d->pore_h / 2; g.hi0 = g.lo0 + d->pore_h - 1;
   g.lo1 = n1 / 2 - d->pore_h / 2; g.hi1 = g.lo1 + d->pore_h - 1;
@@ -590,6 +593,9 @@ int adj_check(const lb_ctx* c, int nsteps, int K) {
   if (!(c->reps[0].mp.gamma > 0.0)) return fail(LB_ERR_ARG, "the adjoint needs gamma > 0");
   if (c->reps[0].lp.fluct) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs an athermal fluid (fluid_kT = 0)");
   if (c->mts > 0) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs the uniform sub-cycle (mts_outer = 0)");
+  if (c->d[0].coupling != LB_COUPLING_TRILINEAR)
+    return fail(LB_ERR_UNSUPPORTED, "the adjoint needs the trilinear transfer (the nearest-grid-point one is not "
+                                    "differentiable in the positions)");
   if (nsteps < 1 || K < 1) return fail(LB_ERR_ARG, "nsteps and K must be >= 1");
   if (c->prof_on) return fail(LB_ERR_ARG, "profiling is active");
   return LB_OK;

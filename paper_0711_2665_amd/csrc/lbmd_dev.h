@@ -113,6 +113,7 @@ struct Geom {
   int wall_axis, wall_pos;
   int t0, t1;           // transverse axes
   int lo0, hi0, lo1, hi1;  // pore block
+  int ngp;              // bead <-> lattice transfer at the nearest node (else trilinear)
 };
 
 __host__ __device__ inline int ext(const Geom& g, int a) { return a == 0 ? g.nx : (a == 1 ? g.ny : g.nz); }
@@ -287,6 +288,12 @@ __device__ inline Stencil make_stencil(const Geom& g, const double* rp) {
   if (!(w2 >= 0.0 && w2 < (double)g.nz)) w2 = 0.0;
   s.b[0] = (int)floor(w0); s.b[1] = (int)floor(w1); s.b[2] = (int)floor(w2);
   s.d[0] = w0 - (double)s.b[0]; s.d[1] = w1 - (double)s.b[1]; s.d[2] = w2 - (double)s.b[2];
+  if (g.ngp) {
+    // nearest grid point: weight 1 at the nearest corner (the upper one
+    // along an axis whose fraction is at least 1/2), 0 at the others
+#pragma unroll
+    for (int a = 0; a < 3; ++a) s.d[a] = s.d[a] >= 0.5 ? 1.0 : 0.0;
+  }
   return s;
 }
 // corner k = (k&1, k>>1&1, k>>2&1): node index and weight
@@ -301,6 +308,14 @@ __device__ inline double corner_weight(const Stencil& s, int k) {
   double wy = ((k >> 1) & 1) ? s.d[1] : 1.0 - s.d[1];
   double wz = ((k >> 2) & 1) ? s.d[2] : 1.0 - s.d[2];
   return wx * wy * wz;
+}
+// Whether corner k takes part in the transfer: every corner of the
+// trilinear stencil; only the nearest node with the nearest-grid-point one
+// (the others carry no force, so they are neither marked nor updated by the
+// spreading).
+__device__ inline bool corner_used(const Geom& g, const Stencil& s, int k) {
+  if (!g.ngp) return true;
+  return (k & 1) == (int)s.d[0] && ((k >> 1) & 1) == (int)s.d[1] && ((k >> 2) & 1) == (int)s.d[2];
 }
 
 }  // namespace lbmd

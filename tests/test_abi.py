@@ -78,6 +78,7 @@ def test_desc_layout_matches_header(tmp_path):
     (dict(mts_outer=3), "mts_outer"),
     (dict(mts_outer=1), "mts_outer"),
     (dict(mts_outer=-1), "mts_outer"),
+    (dict(coupling=2), "coupling"),
 ])
 def test_host_validation(bad, msg):
     from paper_0711_2665_amd import lbmd
