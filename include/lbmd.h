@@ -66,7 +66,7 @@ enum {
 };
 
 /* Number of doubles lb_observables writes. */
-#define LB_NOBS 23
+#define LB_NOBS 25
 
 /*
  * Run description.  The geometry follows Sec. 4: one wall plane normal to
@@ -318,8 +318,10 @@ int md_relax(lb_ctx* ctx, int nsub_total, double gamma_relax);
  * [10] beads in the pore channel, [11] R_U, [12] R_T, [13] R_eff with
  * nu = 0.6 (Sec. 4, Eq. (R_eff)), [14] dW_H/dt = gamma sum v.u_p and
  * [15] dW_E/dt = sum F_drive.v (Sec. 4, translocation work), [16..21] wall
- * momentum ledgers (not tracked on the device: NaN), [22] step count.
- * Sums are FP64. */
+ * momentum ledgers (not tracked on the device: NaN), [22] step count,
+ * [23] and [24] the viscous drag along the wall normal, m gamma (u_p - v)
+ * summed over the untranslocated and the translocated beads (Sec. 4, the
+ * drag forces on the two parts).  Sums are FP64. */
 int lb_observables(lb_ctx* ctx, double* out_dev);
 
 /* Checkpoint: copies the current populations (every replica, the storage

@@ -878,9 +878,10 @@ struct Sim {
   // [9] translocated fraction, [10] beads in the field region, [11] R_U,
   // [12] R_T, [13] R_eff (nu = 0.6, Eq. (R_eff)), [14] dW_H/dt = gamma sum v.u_p,
   // [15] dW_E/dt = sum F_drive.v, [16..18] bounce-back wall ledger,
-  // [19..21] spread-on-solid ledger, [22] step.
+  // [19..21] spread-on-solid ledger, [22] step, [23] drag on the
+  // untranslocated part, [24] drag on the translocated part.
   void observables(double* out) const {
-    for (int k = 0; k < 23; ++k) out[k] = 0.0;
+    for (int k = 0; k < 25; ++k) out[k] = 0.0;
     // Mass and momentum are accumulated as deviations from the rest state
     // (f_i - w_i), which keeps the FP64 sums accurate; the fluid node count is
     // added at the end (sum_i w_i c_i = 0).
@@ -918,6 +919,10 @@ struct Sim {
           out[15] += val(fdrive) * val(v[3 * p + an]);
         }
         for (int a = 0; a < 3; ++a) out[14] += val(gamma) * val(v[3 * p + a]) * val(up[3 * p + a]);
+        // viscous drag along the wall normal, m gamma (u_p - v), on the
+        // untranslocated [23] and translocated [24] parts (Sec. 4)
+        const double drag = m * val(gamma) * (val(up[3 * p + an]) - val(v[3 * p + an]));
+        out[tr ? 24 : 23] += drag;
       }
       out[4] = m * ke / (3.0 * nb);
       out[8] = zsum / nb;

@@ -189,7 +189,7 @@ class Oracle:
         return out.reshape(3, nz, ny, nx)
 
     def observables(self):
-        out = np.empty(23)
+        out = np.empty(25)
         self.L.or_observables(self.h, _dp(out))
         return out
 

@@ -416,10 +416,11 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
   double tot[4];
   for (int a = 0; a < 4; ++a) tot[a] = block_sum(fl[a], sh);
   const int an = g.wall_axis >= 0 ? g.wall_axis : 2;
-  double acc[12];
-  for (int a = 0; a < 12; ++a) acc[a] = 0.0;
+  double acc[14];
+  for (int a = 0; a < 14; ++a) acc[a] = 0.0;
   // 0 sum v^2, 1-3 momentum, 4 normal coordinate, 5 translocated, 6 in field,
-  // 7 dW_E, 8 dW_H, 9-11 sum of r over translocated beads
+  // 7 dW_E, 8 dW_H, 9-11 sum of r over translocated beads, 12-13 drag along
+  // the normal on the untranslocated and translocated parts
   for (int p = t; p < nb; p += 256) {
     const int s = so + p;
     double v0 = d.v[3 * s], v1 = d.v[3 * s + 1], v2 = d.v[3 * s + 2];
@@ -432,9 +433,10 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
     if (tr) { acc[5] += 1.0; acc[9] += rp[0]; acc[10] += rp[1]; acc[11] += rp[2]; }
     if (in_field(g, rp)) { acc[6] += 1.0; acc[7] += P.f_drive * d.v[3 * s + an]; }
     acc[8] += P.gamma * (v0 * d.up[3 * s] + v1 * d.up[3 * s + 1] + v2 * d.up[3 * s + 2]);
+    acc[tr ? 13 : 12] += P.m * P.gamma * (d.up[3 * s + an] - d.v[3 * s + an]);
   }
-  double res[12];
-  for (int a = 0; a < 12; ++a) res[a] = block_sum(acc[a], sh);
+  double res[14];
+  for (int a = 0; a < 14; ++a) res[a] = block_sum(acc[a], sh);
   const double ntr = res[5], nun = (double)nb - ntr;
   double cu_s[3] = {0.0, 0.0, 0.0};
   for (int p = t; p < nb; p += 256) {
@@ -474,6 +476,7 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
     o[14] = res[8]; o[15] = res[7];
     for (int a = 16; a < 22; ++a) o[a] = __builtin_nan("");
     o[22] = (double)d.ctrl->step;
+    o[23] = res[12]; o[24] = res[13];
   }
 }
 

@@ -21,7 +21,7 @@
 namespace lbmd {
 
 constexpr int MD_BPB = 16;                   // beads per MD workgroup (slot padding)
-constexpr int NOBS = 23;                     // observables per replica
+constexpr int NOBS = 25;                     // observables per replica
 constexpr int MAX_REPLICAS = 1024;
 constexpr int TILE_MIN = 256;                // smallest sweep tile (nodes)
 constexpr int OBS_TILE = 4096;               // nodes per fluid-reduction tile

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblbmd.so")
 
 LB_OK, LB_ERR_ARG, LB_ERR_DEVICE, LB_ERR_UNSTABLE, LB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 LB_FP64, LB_FP32_DEV = 0, 1
-LB_NOBS = 23
+LB_NOBS = 25
 Q = 19
 
 OBS_NAMES = ["mass", "px", "py", "pz", "T_beads", "bpx", "bpy", "bpz", "mean_normal", "translocated",

@@ -232,7 +232,7 @@ def test_coupled_c0_fp64_matches_oracle(orc):
         go = s.observables().cpu().numpy()
         oo = o.observables()
         oo2 = o2.observables()
-        for k in list(range(16)) + [22]:
+        for k in list(range(16)) + [22, 23, 24]:
             scale = TOL64 * max(1.0, abs(oo[k]))
             bound = scale if k in (0, 22) or target == 1 else max(scale, 100 * abs(oo2[k] - oo[k]))
             assert abs(go[k] - oo[k]) <= bound, (target, k, go[k], oo[k], oo2[k])
