@@ -22,7 +22,7 @@ import math
 
 import numpy as np
 
-from .workloads import BASE, initial_chain, scaled
+from .workloads import BASE, initial_chain
 
 # observable indices (lb_observables)
 OBS = dict(R_U=11, R_T=12, R_eff=13, dWH_dt=14, dWE_dt=15, N_r=10, translocated=9, drag_U=23, drag_T=24)
