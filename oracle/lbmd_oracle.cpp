@@ -231,6 +231,7 @@ typedef struct {
   double fluid_kT;     // thermal energy of the fluid noise (0: athermal BGK fluid)
   int mts_outer;       // 0: n_sub uniform sub-steps; M > 0: the multiple-time-step cycle with M outer steps
   int coupling;        // bead <-> lattice transfer: 0 trilinear, 1 nearest grid point
+  int constraints;     // 0: harmonic bonds; 1: rigid bonds |r_{p+1} - r_p| = r0 (SHAKE / RATTLE)
 } or_desc;
 }
 
@@ -668,8 +669,10 @@ struct Sim {
     if (use_cells) build_candidates(pos, cand);
     for (int p = 0; p < nb; ++p) {
       R Fp[3] = {R(0.0), R(0.0), R(0.0)};
-      if (p > 0) bond_force(pos, p, p - 1, Fp);
-      if (p < nb - 1) bond_force(pos, p, p + 1, Fp);
+      if (!d.constraints) {
+        if (p > 0) bond_force(pos, p, p - 1, Fp);
+        if (p < nb - 1) bond_force(pos, p, p + 1, Fp);
+      }
       for (int q = p - 1; q <= p + 1; ++q) {
         if (q < 1 || q > nb - 2) continue;
         R Fm[3], F0[3], Fq[3];
@@ -720,7 +723,7 @@ struct Sim {
   double energy(const std::vector<R>& pos) const {
     double E = 0.0;
     auto P = [&](int p, int a) { return val(pos[3 * p + a]); };
-    for (int p = 0; p + 1 < nb; ++p) {
+    for (int p = 0; p + 1 < nb && !d.constraints; ++p) {
       double dd[3], s = 0.0;
       for (int a = 0; a < 3; ++a) { dd[a] = P(p + 1, a) - P(p, a); s += dd[a] * dd[a]; }
       double dl = std::sqrt(s) - d.r0;
@@ -775,6 +778,10 @@ struct Sim {
       md_subcycle_mts(couple, field_on, n_counter);
       return;
     }
+    if (d.constraints) {
+      md_subcycle_constrained(couple, field_on, n_counter);
+      return;
+    }
     std::vector<R> Fc((size_t)3 * nb);
     for (int s = 0; s < d.n_sub; ++s) {
       for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
@@ -790,6 +797,125 @@ struct Sim {
           J[3 * p + a] = J[3 * p + a] - R(m) * (omE * (u - vold) + sx);
         }
       }
+      for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
+    }
+  }
+
+  // ---- rigid bonds (Sec. 2, Eq. (SPValgo) with its SHAKE and RATTLE steps) ---
+  // Constraints sigma_k = |s_k|^2 - r0^2 = 0, s_k = r_k - r_{k+1}, replace the
+  // harmonic bonds (equal masses).  For a linear chain both projections are
+  // tridiagonal systems in the bond multipliers, solved directly (Thomas
+  // algorithm): RATTLE's is linear and needs one solve; SHAKE's is solved by
+  // Newton iterations, each a tridiagonal solve of the linearised
+  // constraints, until the worst bond is within SHAKE_TOL r0^2 (at most
+  // CONSTRAINT_MAXIT iterations, else the run is flagged).  Bead p takes the
+  // corrections of its bonds p (+) and p-1 (-) in that order.
+  static constexpr double SHAKE_TOL = 1e-13;
+  static constexpr int CONSTRAINT_MAXIT = 50;
+  bool constraint_failed = false;
+  // x solves a[k] x[k-1] + b[k] x[k] + c[k] x[k+1] = d[k], k = 0..n-1
+  static void tridiag(int n, const std::vector<R>& a, const std::vector<R>& b, const std::vector<R>& c,
+                      const std::vector<R>& d, std::vector<R>& x) {
+    std::vector<R> cp((size_t)n), dp((size_t)n);
+    cp[0] = c[0] / b[0];
+    dp[0] = d[0] / b[0];
+    for (int k = 1; k < n; ++k) {
+      const R den = b[k] - a[k] * cp[k - 1];
+      cp[k] = c[k] / den;
+      dp[k] = (d[k] - a[k] * dp[k - 1]) / den;
+    }
+    x.assign((size_t)n, R(0.0));
+    x[n - 1] = dp[n - 1];
+    for (int k = n - 2; k >= 0; --k) x[k] = dp[k] - cp[k] * x[k + 1];
+  }
+  static R dot3(const R* u, const R* w) { return u[0] * w[0] + u[1] * w[1] + u[2] * w[2]; }
+  // bead p += lam[p] e[p] - lam[p-1] e[p-1]  (e[k]: the vector of bond k)
+  void apply_bonds(std::vector<R>& y, const std::vector<R>& lam, const std::vector<R>& e) const {
+    for (int p = 0; p < nb; ++p)
+      for (int a = 0; a < 3; ++a) {
+        if (p < nb - 1) y[3 * p + a] = y[3 * p + a] + lam[p] * e[3 * p + a];
+        if (p > 0) y[3 * p + a] = y[3 * p + a] - lam[p - 1] * e[3 * (p - 1) + a];
+      }
+  }
+  // SHAKE: moves x (the drifted positions) along the bond vectors of ref
+  // (the positions before the drift) until every bond has length r0.
+  void shake(std::vector<R>& x, const std::vector<R>& ref) {
+    const int nbond = nb - 1;
+    if (nbond < 1) return;
+    const double d2 = d.r0 * d.r0;
+    std::vector<R> rv((size_t)3 * nbond), sv((size_t)3 * nbond), a(nbond), b(nbond), c(nbond), rhs(nbond), dl;
+    for (int k = 0; k < nbond; ++k)
+      for (int q = 0; q < 3; ++q) rv[3 * k + q] = ref[3 * k + q] - ref[3 * (k + 1) + q];
+    for (int it = 0;; ++it) {
+      double worst = 0.0;
+      for (int k = 0; k < nbond; ++k) {
+        for (int q = 0; q < 3; ++q) sv[3 * k + q] = x[3 * k + q] - x[3 * (k + 1) + q];
+        const R sig = dot3(&sv[3 * k], &sv[3 * k]) - R(d2);
+        rhs[k] = -sig;
+        worst = std::max(worst, std::fabs(val(sig)));
+      }
+      if (worst <= SHAKE_TOL * d2) return;
+      if (it == CONSTRAINT_MAXIT) { constraint_failed = true; return; }
+      for (int k = 0; k < nbond; ++k) {
+        b[k] = R(4.0) * dot3(&sv[3 * k], &rv[3 * k]);
+        a[k] = k > 0 ? R(-2.0) * dot3(&sv[3 * k], &rv[3 * (k - 1)]) : R(0.0);
+        c[k] = k < nbond - 1 ? R(-2.0) * dot3(&sv[3 * k], &rv[3 * (k + 1)]) : R(0.0);
+      }
+      tridiag(nbond, a, b, c, rhs, dl);
+      apply_bonds(x, dl, rv);
+    }
+  }
+  // RATTLE: removes from vel the relative velocity along every bond of x.
+  void rattle(std::vector<R>& vel, const std::vector<R>& x) {
+    const int nbond = nb - 1;
+    if (nbond < 1) return;
+    std::vector<R> rv((size_t)3 * nbond), a(nbond), b(nbond), c(nbond), rhs(nbond), mu;
+    for (int k = 0; k < nbond; ++k)
+      for (int q = 0; q < 3; ++q) rv[3 * k + q] = x[3 * k + q] - x[3 * (k + 1) + q];
+    for (int k = 0; k < nbond; ++k) {
+      R w[3];
+      for (int q = 0; q < 3; ++q) w[q] = vel[3 * k + q] - vel[3 * (k + 1) + q];
+      rhs[k] = -dot3(&rv[3 * k], w);
+      b[k] = R(2.0) * dot3(&rv[3 * k], &rv[3 * k]);
+      a[k] = k > 0 ? -dot3(&rv[3 * k], &rv[3 * (k - 1)]) : R(0.0);
+      c[k] = k < nbond - 1 ? -dot3(&rv[3 * k], &rv[3 * (k + 1)]) : R(0.0);
+    }
+    tridiag(nbond, a, b, c, rhs, mu);
+    apply_bonds(vel, mu, rv);
+  }
+  // The uniform sub-cycle with rigid bonds: per sub-step
+  //   ref = r;  r += h/2 v;  SHAKE(r; ref), and v takes the same constraint
+  //   impulse, v += (r_shaken - r_drifted) / (h/2);
+  //   v = e v + (1-e)/(m gamma) (F(r) + gamma u_p) + sig xi   (F without bonds);
+  //   RATTLE(v; r);  r += h/2 v
+  // Reading: the printed scheme moves the positions onto the constraints
+  // without the velocity; the constraint force acts during the drift, so the
+  // velocity takes its impulse too (else every RATTLE removes the velocity
+  // the bond's rotation turned along it, and a free rigid rotor loses energy
+  // step after step).  J collects the friction + noise impulse as in the
+  // unconstrained cycle (the constraint corrections are internal and carry
+  // no momentum).
+  void md_subcycle_constrained(bool couple, bool field_on, uint32_t n_counter) {
+    std::vector<R> Fc((size_t)3 * nb), ref, rd;
+    for (int s = 0; s < d.n_sub; ++s) {
+      ref = r;
+      for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
+      rd = r;
+      shake(r, ref);
+      for (int k = 0; k < 3 * nb; ++k) v[k] = v[k] + (r[k] - rd[k]) / R(hh);
+      forces(r, Fc, field_on);
+      for (int p = 0; p < nb; ++p) {
+        double xi[3] = {0.0, 0.0, 0.0};
+        if (val(sig) != 0.0) gauss3(d.seed, d.replica, n_counter, (uint32_t)s, (uint32_t)p, xi);
+        for (int a = 0; a < 3; ++a) {
+          R u = couple ? up[3 * p + a] : R(0.0);
+          R vold = v[3 * p + a];
+          R sx = sig * R(xi[a]);
+          v[3 * p + a] = e * vold + cf * (Fc[3 * p + a] + gamma * u) + sx;
+          J[3 * p + a] = J[3 * p + a] - R(m) * (omE * (u - vold) + sx);
+        }
+      }
+      rattle(v, r);
       for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
     }
   }
@@ -962,6 +1088,7 @@ void* or_create(const or_desc* d, const double* r0, const double* v0) {
   if (!d || d->nx <= 0 || d->ny <= 0 || d->nz <= 0 || !(d->tau > 0.5) || d->n_sub <= 0) return nullptr;
   if (d->mts_outer < 0 || (d->mts_outer > 0 && d->n_sub % d->mts_outer != 0)) return nullptr;
   if (d->coupling != 0 && d->coupling != 1) return nullptr;
+  if (d->constraints != 0 && (d->constraints != 1 || d->mts_outer > 0)) return nullptr;
   SimD* s = new SimD();
   s->init(*d, r0, v0);
   return s;
@@ -1089,6 +1216,21 @@ void or_md_only(void* h, int nsteps, int field_on) {
   }
 }
 double or_energy(void* h) { auto* s = (SimD*)h; return s->energy(s->r); }
+// The constraint projections alone, on caller arrays [nb][3]; returns 1 if a
+// projection ran out of sweeps at any point of the run so far.
+void or_shake(void* h, double* x, const double* ref) {
+  auto* s = (SimD*)h;
+  std::vector<double> xv(x, x + 3 * s->nb), rv(ref, ref + 3 * s->nb);
+  s->shake(xv, rv);
+  std::memcpy(x, xv.data(), xv.size() * sizeof(double));
+}
+void or_rattle(void* h, double* vel, const double* x) {
+  auto* s = (SimD*)h;
+  std::vector<double> vv(vel, vel + 3 * s->nb), xv(x, x + 3 * s->nb);
+  s->rattle(vv, xv);
+  std::memcpy(vel, vv.data(), vv.size() * sizeof(double));
+}
+int or_constraint_failed(void* h) { return ((SimD*)h)->constraint_failed ? 1 : 0; }
 int or_in_field(void* h, const double* rp) { return ((SimD*)h)->in_field(rp) ? 1 : 0; }
 void or_set_use_cells(void* h, int on) { ((SimD*)h)->use_cells = on != 0; }
 int or_get_use_cells(void* h) { return ((SimD*)h)->use_cells ? 1 : 0; }

@@ -28,7 +28,7 @@ class OrDesc(C.Structure):
         ("kappa", C.c_double), ("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double),
         ("gamma", C.c_double), ("kT", C.c_double), ("f_drive", C.c_double),
         ("n_sub", C.c_int), ("seed", C.c_uint32), ("replica", C.c_uint32),
-        ("fluid_kT", C.c_double), ("mts_outer", C.c_int), ("coupling", C.c_int),
+        ("fluid_kT", C.c_double), ("mts_outer", C.c_int), ("coupling", C.c_int), ("constraints", C.c_int),
     ]
 
 
@@ -61,6 +61,10 @@ def _declare(L):
     L.or_collide.argtypes = [_P, _DP, _DP, _DP]
     L.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
     L.or_gauss3.argtypes = [C.c_uint32] * 5 + [_DP]
+    L.or_shake.argtypes = [_P, _DP, _DP]
+    L.or_rattle.argtypes = [_P, _DP, _DP]
+    L.or_constraint_failed.restype = C.c_int
+    L.or_constraint_failed.argtypes = [_P]
     L.or_mode_poly.restype = C.c_double
     L.or_mode_poly.argtypes = [C.c_int, C.c_int]
     L.or_fluid_normals.argtypes = [C.c_uint32] * 4 + [_DP]
@@ -115,6 +119,7 @@ def make_desc(cfg):
     d.fluid_kT = cfg.get("fluid_kT", 0.0)
     d.mts_outer = cfg.get("mts_outer", 0)
     d.coupling = cfg.get("coupling", 0)
+    d.constraints = cfg.get("constraints", 0)
     return d
 
 
@@ -246,6 +251,21 @@ class Oracle:
 
     def energy(self):
         return float(self.L.or_energy(self.h))
+
+    def shake(self, x, ref):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1).copy()
+        ref = np.ascontiguousarray(ref, dtype=np.float64).reshape(-1)
+        self.L.or_shake(self.h, _dp(x), _dp(ref))
+        return x.reshape(self.nb, 3)
+
+    def rattle(self, vel, x):
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1).copy()
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        self.L.or_rattle(self.h, _dp(vel), _dp(x))
+        return vel.reshape(self.nb, 3)
+
+    def constraint_failed(self):
+        return bool(self.L.or_constraint_failed(self.h))
 
     def in_field(self, rp):
         rp = np.ascontiguousarray(rp, dtype=np.float64)
