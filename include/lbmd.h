@@ -117,6 +117,15 @@ typedef struct lb_desc {
                              bead, trilinear weights) or LB_COUPLING_NGP (the
                              paper's: the nearest node, the upper one along an
                              axis where the fraction is 1/2)                 */
+  int32_t constraints;    /* 0: harmonic bonds k_bond/2 (|d| - r0)^2.  1: rigid
+                             bonds |r_{p+1} - r_p| = r0 (Sec. 2, Eq. (SPValgo)
+                             with its SHAKE and RATTLE steps; k_bond unused):
+                             per sub-step the drifted positions are projected
+                             onto the bonds along the bonds at the sub-step's
+                             start and the velocity takes the same impulse;
+                             after the kick the relative velocities along the
+                             bonds are removed.  Needs mts_outer = 0 and
+                             nb <= 1024                                      */
 } lb_desc;
 
 /* Byte sizes of the caller-allocated device buffers (256-byte aligned), and
@@ -151,8 +160,8 @@ typedef struct lb_ctx lb_ctx;
  * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
  * gamma, kT or fluid_kT, rc outside (0, 3], nb > 0 without a positive
  * mass, nb > 0 with a wall on a lattice with an extent below 6, or an
- * mts_outer that is negative or does not divide n_sub into at most 40, or
- * an unknown coupling. */
+ * mts_outer that is negative or does not divide n_sub into at most 40, an
+ * unknown coupling, or rigid bonds with mts_outer > 0 or nb > 1024. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
 
 /* As lb_buffer_sizes for nrep replicas d[0..nrep-1] in one context.  All
@@ -282,9 +291,9 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * that step, recomputed segment by segment from checkpoints taken every K
  * steps of the forward pass.
  * Supported: one-replica contexts with 1 <= nb <= 128, gamma > 0, an
- * athermal fluid (fluid_kT = 0), the uniform sub-cycle (mts_outer = 0) and
- * the trilinear transfer (LB_ERR_UNSUPPORTED / LB_ERR_ARG otherwise); either
- * precision.
+ * athermal fluid (fluid_kT = 0), the uniform sub-cycle (mts_outer = 0),
+ * harmonic bonds and the trilinear transfer (LB_ERR_UNSUPPORTED / LB_ERR_ARG
+ * otherwise); either precision.
  *
  * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1
  *   checkpoints of lb_sizes.state_bytes, K population arrays of tape, the

@@ -838,31 +838,44 @@ struct Sim {
       }
   }
   // SHAKE: moves x (the drifted positions) along the bond vectors of ref
-  // (the positions before the drift) until every bond has length r0.
-  void shake(std::vector<R>& x, const std::vector<R>& ref) {
+  // (the positions before the drift) until every bond has length r0.  The
+  // correction dx is accumulated apart from x (x = x_drifted + dx), so that
+  // the velocity impulse dx / (h/2) keeps its relative precision; dx is
+  // returned in *dx_out when given.
+  void shake(std::vector<R>& x, const std::vector<R>& ref, std::vector<R>* dx_out = nullptr) {
     const int nbond = nb - 1;
-    if (nbond < 1) return;
+    std::vector<R> dx((size_t)3 * nb, R(0.0));
+    if (nbond < 1) {
+      if (dx_out) *dx_out = dx;
+      return;
+    }
     const double d2 = d.r0 * d.r0;
+    const std::vector<R> x0 = x;
     std::vector<R> rv((size_t)3 * nbond), sv((size_t)3 * nbond), a(nbond), b(nbond), c(nbond), rhs(nbond), dl;
     for (int k = 0; k < nbond; ++k)
       for (int q = 0; q < 3; ++q) rv[3 * k + q] = ref[3 * k + q] - ref[3 * (k + 1) + q];
+    auto finish = [&]() {
+      for (int k = 0; k < 3 * nb; ++k) x[k] = x0[k] + dx[k];
+      if (dx_out) *dx_out = dx;
+    };
     for (int it = 0;; ++it) {
       double worst = 0.0;
       for (int k = 0; k < nbond; ++k) {
-        for (int q = 0; q < 3; ++q) sv[3 * k + q] = x[3 * k + q] - x[3 * (k + 1) + q];
+        for (int q = 0; q < 3; ++q)
+          sv[3 * k + q] = (x0[3 * k + q] + dx[3 * k + q]) - (x0[3 * (k + 1) + q] + dx[3 * (k + 1) + q]);
         const R sig = dot3(&sv[3 * k], &sv[3 * k]) - R(d2);
         rhs[k] = -sig;
         worst = std::max(worst, std::fabs(val(sig)));
       }
-      if (worst <= SHAKE_TOL * d2) return;
-      if (it == CONSTRAINT_MAXIT) { constraint_failed = true; return; }
+      if (worst <= SHAKE_TOL * d2) { finish(); return; }
+      if (it == CONSTRAINT_MAXIT) { constraint_failed = true; finish(); return; }
       for (int k = 0; k < nbond; ++k) {
         b[k] = R(4.0) * dot3(&sv[3 * k], &rv[3 * k]);
         a[k] = k > 0 ? R(-2.0) * dot3(&sv[3 * k], &rv[3 * (k - 1)]) : R(0.0);
         c[k] = k < nbond - 1 ? R(-2.0) * dot3(&sv[3 * k], &rv[3 * (k + 1)]) : R(0.0);
       }
       tridiag(nbond, a, b, c, rhs, dl);
-      apply_bonds(x, dl, rv);
+      apply_bonds(dx, dl, rv);
     }
   }
   // RATTLE: removes from vel the relative velocity along every bond of x.
@@ -885,7 +898,7 @@ struct Sim {
   }
   // The uniform sub-cycle with rigid bonds: per sub-step
   //   ref = r;  r += h/2 v;  SHAKE(r; ref), and v takes the same constraint
-  //   impulse, v += (r_shaken - r_drifted) / (h/2);
+  //   impulse, v += dx / (h/2) with dx the SHAKE correction;
   //   v = e v + (1-e)/(m gamma) (F(r) + gamma u_p) + sig xi   (F without bonds);
   //   RATTLE(v; r);  r += h/2 v
   // Reading: the printed scheme moves the positions onto the constraints
@@ -896,13 +909,12 @@ struct Sim {
   // unconstrained cycle (the constraint corrections are internal and carry
   // no momentum).
   void md_subcycle_constrained(bool couple, bool field_on, uint32_t n_counter) {
-    std::vector<R> Fc((size_t)3 * nb), ref, rd;
+    std::vector<R> Fc((size_t)3 * nb), ref, dx;
     for (int s = 0; s < d.n_sub; ++s) {
       ref = r;
       for (int k = 0; k < 3 * nb; ++k) r[k] = r[k] + R(hh) * v[k];
-      rd = r;
-      shake(r, ref);
-      for (int k = 0; k < 3 * nb; ++k) v[k] = v[k] + (r[k] - rd[k]) / R(hh);
+      shake(r, ref, &dx);
+      for (int k = 0; k < 3 * nb; ++k) v[k] = v[k] + dx[k] / R(hh);
       forces(r, Fc, field_on);
       for (int p = 0; p < nb; ++p) {
         double xi[3] = {0.0, 0.0, 0.0};

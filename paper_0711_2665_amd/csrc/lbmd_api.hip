@@ -168,6 +168,11 @@ int validate_one(const lb_desc* d, int r) {
   if (d->mts_outer < 0) return fail(LB_ERR_ARG, "replica %d: mts_outer must be >= 0", r);
   if (d->coupling != LB_COUPLING_TRILINEAR && d->coupling != LB_COUPLING_NGP)
     return fail(LB_ERR_ARG, "replica %d: unknown coupling %d", r, d->coupling);
+  if (d->constraints != 0 && d->constraints != 1)
+    return fail(LB_ERR_ARG, "replica %d: constraints must be 0 or 1", r);
+  if (d->constraints == 1 && (d->mts_outer != 0 || d->nb > MAX_CONSTRAINED_BEADS))
+    return fail(LB_ERR_ARG, "replica %d: rigid bonds need the uniform sub-cycle and at most %d beads", r,
+                MAX_CONSTRAINED_BEADS);
   if (d->mts_outer > 0 && (d->n_sub % d->mts_outer != 0 || d->n_sub / d->mts_outer > MTS_MAX_INNER))
     return fail(LB_ERR_ARG, "replica %d: mts_outer must divide n_sub into at most %d sub-steps per outer step", r,
                 MTS_MAX_INNER);
@@ -252,6 +257,7 @@ MdParams make_md(const lb_desc* d, double skin) {
   const int cr = d->rc > 2.0 ? 3 : 2;       // ceil(rc) for 1 < rc <= 3 (rc <= 1: the 2-window still covers it)
   P.wlo = 1 - cr;
   P.whi = cr;
+  P.constrained = d->constraints == 1 ? 1 : 0;
   return P;
 }
 
@@ -323,6 +329,7 @@ struct lb_ctx {
   bool any_noise = false;
   bool any_fluct = false;    // some replica has a fluctuating fluid
   int mts = 0;               // outer steps of the multiple-time-step sub-cycle (0: uniform sub-steps)
+  bool any_constrained = false;  // some replica has rigid bonds
   bool noise_ready = false;  // the noise slot of the current population parity holds this step's noise
   SweepCfg sweep;
   int ntiles = 0;
@@ -479,7 +486,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   else launch_gather<double, false>(A, D, c->nslots, start, sb);
   MdOverride none{};
   if (c->mts > 0) launch_md_cycle_mts(D, c->nslots, c->nrep, c->n_sub, c->mts, sb, false);
-  else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb, false);
+  else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb, false, c->any_constrained);
   if (c->step_lists) acc(hipEventRecord(c->mdone, sb));
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
@@ -593,6 +600,7 @@ int adj_check(const lb_ctx* c, int nsteps, int K) {
   if (!(c->reps[0].mp.gamma > 0.0)) return fail(LB_ERR_ARG, "the adjoint needs gamma > 0");
   if (c->reps[0].lp.fluct) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs an athermal fluid (fluid_kT = 0)");
   if (c->mts > 0) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs the uniform sub-cycle (mts_outer = 0)");
+  if (c->any_constrained) return fail(LB_ERR_UNSUPPORTED, "the adjoint needs harmonic bonds (constraints = 0)");
   if (c->d[0].coupling != LB_COUPLING_TRILINEAR)
     return fail(LB_ERR_UNSUPPORTED, "the adjoint needs the trilinear transfer (the nearest-grid-point one is not "
                                     "differentiable in the positions)");
@@ -711,6 +719,7 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     R.mp = make_md(&d[r], skin);
     if (R.mp.nb > 0 && R.mp.sig != 0.0) c->any_noise = true;
     if (R.lp.fluct) c->any_fluct = true;
+    if (R.mp.constrained && R.mp.nb >= 2) c->any_constrained = true;
     R.node_off = c->pk.node_off[r];
     R.slot_off = c->pk.slot_off[r];
     R.nslot = (int)round_up(d[r].nb, MD_BPB);
@@ -942,7 +951,7 @@ int md_relax(lb_ctx* c, int nsub_total, double gamma_relax) {
   int left = nsub_total;
   while (left > 0) {
     int n = left < c->n_sub ? left : c->n_sub;
-    launch_md_cycle(c->D, c->nslots, c->nrep, n, ov, c->s);
+    launch_md_cycle(c->D, c->nslots, c->nrep, n, ov, c->s, true, c->any_constrained);
     left -= n;
   }
   launch_zero_v(c->D, c->nslots, c->s);

@@ -165,6 +165,7 @@ struct MdParams {
   double halfskin2;     // (skin/2)^2
   double kick;          // multiple-time-step cycle: (dt/2)/m with dt = 1/M (0 without it)
   int wlo, whi;         // wall-site window offsets: 1 - ceil(rc) .. ceil(rc)
+  int constrained;      // rigid bonds (SHAKE / RATTLE) instead of harmonic ones
 };
 
 // ---- Philox4x32-10 (Salmon et al., SC'11) and Box-Muller ------------------

@@ -164,13 +164,16 @@ void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 // replicas without noise and by the relaxation).
 // prologue = false: the cycle's opening (launch_md_begin and the start of the
 // sub-cycle) was done already, by launch_md_begin and launch_gather
+// constrained: some replica has rigid bonds (a k_md_constraint launch after
+// the opening and after every sub-step; chains without them skip it)
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s,
-                     bool prologue = true);
+                     bool prologue = true, bool constrained = false);
 void launch_md_begin(const Dev& d, int nrep, hipStream_t s);
 // The multiple-time-step sub-cycle of a coupled step: M outer steps of
 // n_sub / M SPV sub-steps with the bonded forces, between kicks of the slow
 // forces (bead LJ, wall, field); noise from d.xi as in launch_md_cycle.
-constexpr int MTS_MAX_INNER = 40;   // inner sub-steps per outer step (the inner kernel's halo is 2 per sub-step)
+constexpr int MTS_MAX_INNER = 40;
+constexpr int MAX_CONSTRAINED_BEADS = 1024;   // rigid bonds: one workgroup per chain   // inner sub-steps per outer step (the inner kernel's halo is 2 per sub-step)
 void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s, bool prologue = true);
 // Noise of one sub-cycle into d.xi, for the step counter + step_offset.
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s);

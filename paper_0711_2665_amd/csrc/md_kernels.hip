@@ -465,7 +465,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     for (int o1 = P.wlo + lane; o1 <= P.whi; o1 += MD_LANES)
       sh.wmask[bslot][o1 - WLO] = p < P.nb ? wall_row(P, g, rp, o1, &sh.wallF[bslot][WSPAN * (o1 - WLO)]) : 0u;
     // ---- lane 0: bonds now, the rest after the barrier
-    if (!SLOW && lead) {
+    if (!SLOW && lead && !P.constrained) {
       if (p > 0) bond_add(P, rp, rm, F);
       if (p < P.nb - 1) bond_add(P, rp, rq, F);
     }
@@ -551,6 +551,9 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     finite = finite && isfinite(vn[a]);
   }
   if (!finite) atomicOr(&d.ctrl->err, E_BEADS);
+  // rigid bonds: RATTLE, the drift and the next SHAKE follow in
+  // k_md_constraint, which also sets the rebuild words
+  if (P.constrained) return;
   if (d.mdtape) {
     double* tp = d.mdtape + ((size_t)s * P.nb + p) * 6;
     tp[0] = rp[0]; tp[1] = rp[1]; tp[2] = rp[2];
@@ -796,21 +799,245 @@ void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {
   hipLaunchKernelGGL(k_md_invalidate, dim3(1), dim3(256), 0, s, d.rb, nrep);
 }
 
+// ---------------------------------------------------------------------------
+// Rigid bonds (Sec. 2, Eq. (SPValgo) with its SHAKE and RATTLE steps), one
+// workgroup per chain (nb <= CON_WG).  Mode START opens the sub-cycle:
+// ref = r, x = r + h/2 v (the gather's r_mid), SHAKE(x; ref), v += (x -
+// x_drifted)/(h/2).  Mode STEP s follows the kick of sub-step s:
+// RATTLE(v; x) at the sub-step's positions x, r = x + h/2 v, and unless it is
+// the last sub-step the opening of the next: ref = r, x = r + h/2 v,
+// SHAKE(x; ref), v += (x - x_drifted)/(h/2), x stored as the next r_mid.
+// Both projections are tridiagonal systems in the bond multipliers: RATTLE's
+// is solved once; SHAKE's linearised constraints by Newton iterations until
+// the worst bond is within CON_TOL r0^2.  Each system is solved by parallel
+// cyclic reduction in LDS (thread k owns bond k); bead p adds the
+// corrections of its bonds p (+) and p-1 (-) in that order.
+// ---------------------------------------------------------------------------
+constexpr int CON_WG = 1024;
+constexpr double CON_TOL = 1e-13;
+constexpr int CON_MAXIT = 50;
+
+struct ConShared {
+  double x[CON_WG][3];      // positions
+  double e[CON_WG][3];      // bond vectors of the system's coefficients
+  double w[CON_WG][3];      // velocities (RATTLE)
+  double a[CON_WG], b[CON_WG], c[CON_WG], r[CON_WG];
+  double red[CON_WG / 64];
+};
+
+// max over the workgroup (exact, any order)
+__device__ inline double con_max(double x, ConShared& sh) {
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh.red[wv] = x;
+  __syncthreads();
+  double m = 0.0;
+  for (int k = 0; k < CON_WG / 64; ++k) m = fmax(m, sh.red[k]);
+  return m;
+}
+
+// Solves a[k] y[k-1] + b[k] y[k] + c[k] y[k+1] = r[k], k < n, in place
+// (parallel cyclic reduction; rows beyond the ends read as identity rows);
+// returns thread k's y[k].
+__device__ inline double con_pcr(ConShared& sh, int n) {
+  const int k = threadIdx.x;
+  for (int h = 1; h < n; h <<= 1) {
+    double ai = 0.0, bi = 1.0, ci = 0.0, ri = 0.0;
+    double am = 0.0, bm = 1.0, cm = 0.0, rm = 0.0, ap = 0.0, bp = 1.0, cp = 0.0, rp = 0.0;
+    if (k < n) {
+      ai = sh.a[k]; bi = sh.b[k]; ci = sh.c[k]; ri = sh.r[k];
+      if (k - h >= 0) { am = sh.a[k - h]; bm = sh.b[k - h]; cm = sh.c[k - h]; rm = sh.r[k - h]; }
+      if (k + h < n) { ap = sh.a[k + h]; bp = sh.b[k + h]; cp = sh.c[k + h]; rp = sh.r[k + h]; }
+    }
+    __syncthreads();
+    if (k < n) {
+      const double k1 = ai / bm, k2 = ci / bp;
+      sh.a[k] = -(am * k1);
+      sh.b[k] = bi - cm * k1 - ap * k2;
+      sh.c[k] = -(cp * k2);
+      sh.r[k] = ri - rm * k1 - rp * k2;
+    }
+    __syncthreads();
+  }
+  return k < n ? sh.r[k] / sh.b[k] : 0.0;
+}
+
+__device__ inline double dot3v(const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
+
+// SHAKE of the drifted positions sh.x along the bonds held in sh.e (the
+// reference bonds): the correction is accumulated in sh.w (x = x_drifted +
+// dx, x itself left as drifted), so that the velocity impulse dx / (h/2)
+// keeps its relative precision
+__device__ inline void con_shake(ConShared& sh, int nb, double d2, uint32_t* err) {
+  const int k = threadIdx.x, nbond = nb - 1;
+  for (int it = 0;; ++it) {
+    double sv[3] = {0.0, 0.0, 0.0}, sig = 0.0;
+    if (k < nbond) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sv[a] = (sh.x[k][a] + sh.w[k][a]) - (sh.x[k + 1][a] + sh.w[k + 1][a]);
+      sig = dot3v(sv, sv) - d2;
+    }
+    const double worst = con_max(fabs(sig), sh);
+    if (worst <= CON_TOL * d2) return;
+    if (it == CON_MAXIT) {
+      if (k == 0) atomicOr(err, E_BEADS);
+      return;
+    }
+    if (k < nbond) {
+      sh.b[k] = 4.0 * dot3v(sv, sh.e[k]);
+      sh.a[k] = k > 0 ? -2.0 * dot3v(sv, sh.e[k - 1]) : 0.0;
+      sh.c[k] = k < nbond - 1 ? -2.0 * dot3v(sv, sh.e[k + 1]) : 0.0;
+      sh.r[k] = -sig;
+    }
+    __syncthreads();
+    const double lam = con_pcr(sh, nbond);
+    // every thread has read what it needs; multipliers to sh.r, then apply
+    sh.r[k] = lam;
+    __syncthreads();
+    if (k < nb) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double y = sh.w[k][a];
+        if (k < nbond) y = y + sh.r[k] * sh.e[k][a];
+        if (k > 0) y = y - sh.r[k - 1] * sh.e[k - 1][a];
+        sh.w[k][a] = y;                       // own entry only
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(CON_WG) void k_md_constraint(Dev d, int nslots, int mode, int s, int last) {
+  __shared__ ConShared sh;
+  const int rep = blockIdx.x;
+  const Rep& R = d.reps[rep];
+  const int nb = R.mp.nb;
+  if (nb < 2 || !R.mp.constrained) return;   // uniform in the workgroup
+  const int k = threadIdx.x;
+  const int slot = R.slot_off + k;
+  const double hh = R.mp.hh, d2 = R.mp.r0 * R.mp.r0;
+  const double* rin = (s & 1) ? d.rmid1 : d.rmid0;   // this sub-step's positions (STEP)
+  double* rout = (s & 1) ? d.rmid0 : d.rmid1;        // the next sub-step's
+  double v[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0};
+  const bool own = k < nb;
+  if (own) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = d.v[3 * slot + a];
+  }
+  bool open_next = true;
+  if (mode == 0) {
+    // START: r is the step's start, the gather stored r_mid = r + h/2 v in rmid0
+    if (own) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) r[a] = d.r[3 * slot + a];
+    }
+    rout = d.rmid0;
+  } else {
+    // RATTLE at the sub-step's positions
+    if (own) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { sh.x[k][a] = rin[3 * slot + a]; sh.w[k][a] = v[a]; }
+    }
+    __syncthreads();
+    const int nbond = nb - 1;
+    double rv[3] = {0.0, 0.0, 0.0};
+    if (k < nbond) {
+      double ww[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { rv[a] = sh.x[k][a] - sh.x[k + 1][a]; ww[a] = sh.w[k][a] - sh.w[k + 1][a]; }
+      sh.b[k] = 2.0 * dot3v(rv, rv);
+      sh.r[k] = -dot3v(rv, ww);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sh.e[k][a] = rv[a];
+    }
+    __syncthreads();
+    if (k < nbond) {
+      sh.a[k] = k > 0 ? -dot3v(rv, sh.e[k - 1]) : 0.0;
+      sh.c[k] = k < nbond - 1 ? -dot3v(rv, sh.e[k + 1]) : 0.0;
+    }
+    __syncthreads();
+    const double mu = con_pcr(sh, nbond);
+    sh.r[k] = mu;
+    __syncthreads();
+    if (own) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (k < nbond) v[a] = v[a] + sh.r[k] * sh.e[k][a];
+        if (k > 0) v[a] = v[a] - sh.r[k - 1] * sh.e[k - 1][a];
+        r[a] = sh.x[k][a] + hh * v[a];
+      }
+    }
+    open_next = !last;
+    if (last && own) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { d.r[3 * slot + a] = r[a]; d.v[3 * slot + a] = v[a]; }
+    }
+    __syncthreads();
+  }
+  if (!open_next) return;
+  // the opening of the next sub-step: ref = r, x = r + h/2 v, SHAKE
+  double xd[3] = {0.0, 0.0, 0.0};
+  if (own) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      xd[a] = r[a] + hh * v[a];
+      sh.x[k][a] = xd[a];
+      sh.w[k][a] = r[a];
+    }
+  }
+  __syncthreads();
+  if (k < nb - 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sh.e[k][a] = sh.w[k][a] - sh.w[k + 1][a];
+  }
+  __syncthreads();
+  if (own) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sh.w[k][a] = 0.0;    // the SHAKE correction
+  }
+  __syncthreads();
+  con_shake(sh, nb, d2, &d.ctrl->err);
+  if (!own) return;
+  double d2r = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double dx = sh.w[k][a];
+    const double x = xd[a] + dx;
+    v[a] = v[a] + dx / hh;
+    rout[3 * slot + a] = x;
+    d.v[3 * slot + a] = v[a];
+    const double dd = x - d.ref[3 * slot + a];
+    d2r += dd * dd;
+    const double db = x - d.rbin[3 * slot + a];
+    b2 += db * db;
+  }
+  const int w = mode == 0 ? 0 : (s + 1) % 3;
+  if (d2r > R.mp.halfskin2) d.rb[4 * rep + w] = 1u;
+  if (!(b2 <= CELL_MARGIN * CELL_MARGIN)) d.cst[4 * rep + w] = 1u;
+}
+
 void launch_md_begin(const Dev& d, int nrep, hipStream_t s) {
   hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
 }
 
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s,
-                     bool prologue) {
+                     bool prologue, bool constrained) {
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
   if (prologue) {
     hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
     hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov, 0);
   }
-  for (int k = 0; k < n_sub; ++k)
+  if (constrained)
+    hipLaunchKernelGGL(k_md_constraint, dim3((unsigned)nrep), dim3(CON_WG), 0, s, d, nslots, 0, 0, 0);
+  for (int k = 0; k < n_sub; ++k) {
     hipLaunchKernelGGL(k_md_substep<false>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, ov, nslots, k,
                        k == n_sub - 1 ? 1 : 0);
+    if (constrained)
+      hipLaunchKernelGGL(k_md_constraint, dim3((unsigned)nrep), dim3(CON_WG), 0, s, d, nslots, 1, k,
+                         k == n_sub - 1 ? 1 : 0);
+  }
 }
 
 void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s, bool prologue) {

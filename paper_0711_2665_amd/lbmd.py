@@ -33,7 +33,7 @@ class LbDesc(C.Structure):
         ("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double),
         ("gamma", C.c_double), ("kT", C.c_double), ("f_drive", C.c_double),
         ("n_sub", C.c_int32), ("seed", C.c_uint32), ("replica", C.c_uint32),
-        ("fluid_kT", C.c_double), ("mts_outer", C.c_int32), ("coupling", C.c_int32),
+        ("fluid_kT", C.c_double), ("mts_outer", C.c_int32), ("coupling", C.c_int32), ("constraints", C.c_int32),
     ]
 
 
@@ -142,6 +142,7 @@ def _fill_desc(d, cfg, precision):
     d.fluid_kT = cfg.get("fluid_kT", 0.0)
     d.mts_outer = cfg.get("mts_outer", 0)
     d.coupling = cfg.get("coupling", 0)
+    d.constraints = cfg.get("constraints", 0)
 
 
 def make_descs(cfgs, precision=LB_FP64):

@@ -79,6 +79,9 @@ def test_desc_layout_matches_header(tmp_path):
     (dict(mts_outer=1), "mts_outer"),
     (dict(mts_outer=-1), "mts_outer"),
     (dict(coupling=2), "coupling"),
+    (dict(constraints=2), "constraints"),
+    (dict(constraints=1, nb=2000, shape=(64, 64, 64)), "rigid bonds"),
+    (dict(constraints=1, mts_outer=5), "rigid bonds"),
 ])
 def test_host_validation(bad, msg):
     from paper_0711_2665_amd import lbmd

@@ -1,0 +1,137 @@
+"""GPU parity of the rigid bonds (Sec. 2, Eq. (SPValgo) with its SHAKE and
+RATTLE steps): the constraint kernel solves the bond multipliers' tridiagonal
+systems by parallel cyclic reduction, the oracle by the Thomas algorithm, so
+the two round differently from the first sub-step on.  The measure of that is
+the oracle's own divergence from a copy whose initial positions moved by one
+ulp (the envelope): after one step the GPU stays within 1e-12 or 10x the
+envelope (the friction impulse J, a small difference of velocities, sits at
+~4e-12 relative in both), after 5 and 20 steps within 1e-12 or 100x.  FP32
+storage within its bound; bonds held at r0; an ensemble mixing rigid and
+harmonic bonds equals its runs alone bit for bit."""
+import numpy as np
+import pytest
+
+from paper_0711_2665_amd.workloads import C0, initial_chain, scaled
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max()
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
+
+
+def _start(orc, cfg, precision=None):
+    from paper_0711_2665_amd import lbmd
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(cfg["relax_substeps"], cfg["gamma_relax"])
+    rr = o.beads()["r"]
+    o = orc.Oracle(cfg, rr, np.zeros_like(rr))
+    s = lbmd.Simulation(cfg, rr, None, precision=lbmd.LB_FP64 if precision is None else precision)
+    return o, s
+
+
+@pytest.mark.parametrize("extra", [dict(kT=0.0, kappa=0.0), {}], ids=["deterministic", "noise_bending"])
+def test_rigid_bonds_fp64_match_oracle(orc, extra):
+    torch = _torch()
+    cfg = scaled(C0, constraints=1, **extra)
+    o, s = _start(orc, cfg)
+    r0 = o.beads()["r"]
+    o2 = orc.Oracle(cfg, np.nextafter(r0, np.inf), np.zeros_like(r0))
+    fluid = o.flags() == 0
+    done = 0
+    for target in (1, 5, 20):
+        o.couple_step(target - done)
+        o2.couple_step(target - done)
+        s.couple_step(target - done)
+        done = target
+        torch.cuda.synchronize()
+        ob, ob2 = o.beads(), o2.beads()
+        sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+        rows = {"pops": (_rel(s.pops().cpu().numpy()[:, fluid], o.pops()[:, fluid]),
+                         _rel(o2.pops()[:, fluid], o.pops()[:, fluid]))}
+        for k in ("r", "v", "up", "J"):
+            rows[k] = (_rel(sb[k], ob[k]), _rel(ob2[k], ob[k]))
+        print(f"rigid bonds {extra} step {target}: " + ", ".join(f"{k} gpu {g:.1e} / envelope {e:.1e}"
+                                                               for k, (g, e) in rows.items()), flush=True)
+        for k, (g, e) in rows.items():
+            bound = max(TOL64, (10 if target == 1 else 100) * e)
+            assert g <= bound, (target, k, g, e)
+        b = np.linalg.norm(np.diff(sb["r"], axis=0), axis=1)
+        assert np.abs(b - cfg["r0"]).max() < 1e-4
+    s.check()
+    assert not o.constraint_failed()
+
+
+def test_rigid_bonds_fp32_deviation_error(orc):
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, constraints=1)
+    o, s = _start(orc, cfg, precision=lbmd.LB_FP32_DEV)
+    fluid = o.flags() == 0
+    _, w, _ = orc.tables()
+    o.couple_step(30)
+    s.couple_step(30)
+    torch.cuda.synchronize()
+    fo = o.pops()[:, fluid] - w[:, None]
+    fs = s.pops().double().cpu().numpy()[:, fluid]
+    err_f = np.abs(fs - fo).max()
+    rg, ro = s.beads()["r"].cpu().numpy(), o.beads()["r"]
+    print(f"fp32-dev rigid bonds c0 30 steps: |f - f64|_max {err_f:.3e}, |r - r64|_max {np.abs(rg - ro).max():.3e}",
+          flush=True)
+    assert err_f < 1e-6
+    assert np.abs(rg - ro).max() < 1e-4
+
+
+def test_rigid_and_harmonic_replicas_in_one_ensemble():
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = [
+        scaled(C0, name="c0r", shape=(16, 12, 20), wall_axis=2, wall_pos=10, pore_h=3, nb=12, seed=11, replica=0,
+               init_seed=5, constraints=1),
+        scaled(C0, name="c1h", shape=(20, 16, 16), wall_axis=0, wall_pos=10, pore_h=4, nb=20, seed=12, replica=1,
+               init_seed=6),
+        scaled(C0, name="c2r", shape=(40, 32, 32), wall_axis=0, wall_pos=20, pore_h=4, nb=300, seed=13, replica=2,
+               init_seed=7, constraints=1),
+    ]
+    r0s = [initial_chain(c)[0] for c in cfgs]
+    ens = lbmd.Ensemble(cfgs, r0s, precision=lbmd.LB_FP32_DEV)
+    ens.relax(300, 1.0)
+    for n in (3, 4):
+        ens.run(n, graph=True)
+        ens.observables()
+    torch.cuda.synchronize()
+    ens.check()
+    for k, cfg in enumerate(cfgs):
+        s = lbmd.Simulation(cfg, r0s[k], precision=lbmd.LB_FP32_DEV)
+        s.relax(300, 1.0)
+        s.couple_step(7)
+        torch.cuda.synchronize()
+        nd = int((ens.pops(k) != s.pops()).sum())
+        bd = {n: int((ens.beads(k)[n] != s.beads()[n]).sum()) for n in ("r", "v", "J")}
+        print(f"rigid/harmonic ensemble replica {k}: pops differing {nd}, beads {bd}", flush=True)
+        assert nd == 0 and all(v == 0 for v in bd.values()), (k, nd, bd)
+        s.close()
+
+
+def test_adjoint_rejects_rigid_bonds():
+    _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=(16, 16, 16), wall_pos=8, nb=8, constraints=1)
+    r, _ = initial_chain(cfg)
+    s = lbmd.Simulation(cfg, r)
+    with pytest.raises(lbmd.LbError) as e:
+        s.adjoint_sizes(4, 2)
+    assert e.value.code == lbmd.LB_ERR_UNSUPPORTED

@@ -154,8 +154,7 @@ def test_constrained_coupled_run_conserves_momentum(orc):
     o.couple_step(20)
     P1 = o.observables()
     assert np.abs(P1[5:8] - P0[5:8]).max() > 1e-3
-    # the constraint corrections are equal and opposite before rounding; the
-    # SHAKE impulse divides their rounded difference by h/2, so the ledger
-    # closes to ~1e-12 after 1000 sub-steps rather than to the last bit
-    assert np.abs((P1[1:4] + P1[5:8]) - (P0[1:4] + P0[5:8])).max() < 1e-11
+    # the constraint corrections are equal and opposite pairs along each bond,
+    # kept apart from the positions, so the ledger closes to rounding
+    assert np.abs((P1[1:4] + P1[5:8]) - (P0[1:4] + P0[5:8])).max() < 1e-12
     assert not o.constraint_failed()
