@@ -22,8 +22,11 @@ MLUPS and translocation steps), the adjoint on the 64^3 gradient workload
 (adjoint steps/s in FP64 and FP32, a finite-difference check), the same
 workload with a fluctuating fluid (noise on the non-conserved modes drawn in
 the sweep), the same lattice and chain with the paper's soft bead LJ under
-the multiple-time-step cycle and under uniform sub-steps, and the FP64 CPU
-oracle timed on a bounded sample.
+the multiple-time-step cycle and under uniform sub-steps, FP32 deviation
+storage against FP64 storage over time on the 128^3 system with 400 beads at
+three frictions (errors of rho - 1, u and r, MLUPS of both), and the FP64 CPU
+oracle timed on a bounded sample.  A line on stderr marks the end of each
+leg.
 """
 import argparse
 import json
@@ -36,6 +39,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak, GB/s
 Q = 19
+
+
+def progress(msg):
+    """One line on stderr when a leg of the benchmark has finished."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def lb_bytes_per_update(elem_bytes):
@@ -244,6 +252,25 @@ def run_adjoint(nsteps, K, horizons):
     return out
 
 
+def run_precision_study(steps):
+    """The 128^3 system with 400 beads in both storages from the same relaxed
+    chain, at each of its frictions: errors of rho - 1, u (relative to max |u|)
+    and r against FP64 every 1/5 of the run, beside the envelope (the FP64
+    run's distance from an FP64 run whose chain moved by one ulp), and the
+    MLUPS of both storages."""
+    from paper_0711_2665_amd.precision_study import run_gammas
+    from paper_0711_2665_amd.workloads import C1
+    n = C1["steps"] if steps is None else steps
+    res = run_gammas(C1, n, max(1, n // 5))
+    keys = ("step", "rho_err_max", "rho_err_rms", "rho_dev_max", "u_max", "u_err_max_rel", "u_err_rms_rel",
+            "r_err_max", "r_err_rms", "env_rho_max", "env_u_max_rel", "env_r_max")
+    return {"workload": C1["name"], "steps": n,
+            "runs": [{"gamma": r["gamma"],
+                      "mlups": {k: round(v, 1) for k, v in r["mlups"].items()},
+                      "series": [{k: (row[k] if k == "step" else float(f"{row[k]:.3e}")) for k in keys}
+                                 for row in r["series"]]} for r in res]}
+
+
 def run_cpu_baseline(cfg, steps):
     """The FP64 oracle as it stands, on a bounded sample of the same workload:
     `steps` coupled steps of the full lattice and chain (the chain given a
@@ -277,6 +304,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--no-thermal", action="store_true")
     ap.add_argument("--no-mts", action="store_true")
+    ap.add_argument("--no-precision-study", action="store_true")
+    ap.add_argument("--c1-steps", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -289,6 +318,7 @@ def main():
     cells = nx * ny * nz
 
     main_run = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    progress(f"{cfg['name']} {args.precision}: {1e3 * main_run['seconds'] / args.steps:.4f} ms per step")
     ms_per_step = 1e3 * main_run["seconds"] / args.steps
     mlups = cells * args.steps / main_run["seconds"] / 1e6
     elem = 4 if args.precision == "fp32dev" else 8
@@ -340,6 +370,7 @@ def main():
                        "eager_ms_per_step": round(1e3 * r64["eager_seconds"] / k64, 4),
                        "sweep_alone": sweep_alone(r64, cells, 8),
                        "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
+        progress("fp64 done")
     if not args.no_thermal:
         # the same workload with a fluctuating fluid at the beads' temperature
         from paper_0711_2665_amd.workloads import scaled
@@ -356,6 +387,7 @@ def main():
                                 "sweep_alone": sweep_alone(rt, cells, elem),
                                 "lb_sweep_gbs": round(acht, 1), "lb_sweep_frac": round(acht / PEAK_HBM_GBS, 4),
                                 "lb_sweep_mean_launch_ms": round(rt["lb_ms"], 5)}
+        progress("thermal fluid done")
     if not args.no_mts and args.workload == "c3":
         # the paper's bead LJ on the same lattice and chain, with the
         # multiple-time-step cycle (5 outer x 20 sub-steps) and, for
@@ -375,10 +407,16 @@ def main():
             "uniform_100_substeps": {"value": round(cells * km / ru["seconds"] / 1e6, 1), "unit": "MLUPS",
                                      "ms_per_step": round(1e3 * ru["seconds"] / km, 4),
                                      "bead_phase_ms": round(ru["bead_ms"], 4)}}
+        progress("multiple-time-step cycle done")
     if not args.no_ensemble and args.workload == "c3":
         out["ensemble"] = run_ensemble(args.ensemble_steps, 20, 200)
+        progress("ensemble done")
     if not args.no_adjoint and args.workload == "c3":
         out["adjoint"] = run_adjoint(args.adjoint_steps, 100, (5, 20, 50, 100))
+        progress("adjoint done")
+    if not args.no_precision_study and args.workload == "c3":
+        out["fp32_vs_fp64"] = run_precision_study(args.c1_steps)
+        progress("FP32 against FP64 study done")
     if not args.no_cpu:
         cb = run_cpu_baseline(cfg, args.cpu_steps)
         out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "MLUPS", "cores": cb["cores"],

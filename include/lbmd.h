@@ -40,6 +40,12 @@
  *     lb_last_error().  No C++ exception crosses this boundary.
  *   - Units: lattice units, lattice spacing = LB time step = 1.
  *   - Node index: c = x + nx * (y + ny * z).
+ *   - Directions: population i moves along the D3Q19 velocity c_i (Sec. 2),
+ *     in this order: 0 rest; 1, 2 = +x, -x; 3, 4 = +y, -y; 5, 6 = +z, -z;
+ *     7, 8 = (1,1,0), (-1,-1,0); 9, 10 = (1,-1,0), (-1,1,0); 11, 12 =
+ *     (1,0,1), (-1,0,-1); 13, 14 = (1,0,-1), (-1,0,1); 15, 16 = (0,1,1),
+ *     (0,-1,-1); 17, 18 = (0,1,-1), (0,-1,1) (opposites adjacent); weights
+ *     1/3, 1/18, 1/36 for rest, axis and diagonal directions.
  */
 #ifndef LBMD_H
 #define LBMD_H

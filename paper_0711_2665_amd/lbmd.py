@@ -18,6 +18,12 @@ LB_OK, LB_ERR_ARG, LB_ERR_DEVICE, LB_ERR_UNSTABLE, LB_ERR_UNSUPPORTED = 0, -1, -
 LB_FP64, LB_FP32_DEV = 0, 1
 LB_NOBS = 25
 Q = 19
+# The population order of the library's storage (documented in the header):
+# rest, +-x, +-y, +-z, then the xy, xz and yz diagonals, opposites adjacent.
+VELOCITIES = ((0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+              (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
+              (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1))
+WEIGHTS = (1.0 / 3.0,) + (1.0 / 18.0,) * 6 + (1.0 / 36.0,) * 12
 
 OBS_NAMES = ["mass", "px", "py", "pz", "T_beads", "bpx", "bpy", "bpz", "mean_normal", "translocated",
              "N_r", "R_U", "R_T", "R_eff", "dWH_dt", "dWE_dt", "wall_bb_x", "wall_bb_y", "wall_bb_z",

@@ -127,3 +127,19 @@ def test_ensemble_sizes_pack_replicas():
         lbmd.ensemble_sizes([cfgs[0], dict(cfgs[2], tau=0.4)])
     assert "replica 1" in str(e.value)
 
+
+
+def test_binding_direction_order_is_the_oracles(orc):
+    """The binding's D3Q19 table (the header's documented storage order) is
+    the oracle's; the GPU parity tests compare populations index by index
+    with the oracle, so it is also the library's."""
+    import numpy as np
+    from paper_0711_2665_amd import lbmd
+    c, w, opp = orc.tables()
+    assert np.array_equal(np.asarray(lbmd.VELOCITIES, dtype=np.float64), np.asarray(c, dtype=np.float64))
+    assert np.array_equal(np.asarray(lbmd.WEIGHTS), np.asarray(w))
+    # the header's text lists the same order
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "lbmd.h")).read()
+    for i, ci in enumerate(lbmd.VELOCITIES):
+        if sum(abs(x) for x in ci) == 2:
+            assert "(" + ",".join(str(x) for x in ci) + ")" in hdr.replace(" ", ""), (i, ci)
