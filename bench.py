@@ -168,6 +168,10 @@ def run_ensemble(steps, warmup, eager_steps):
     by_len = {}
     for c, t in zip(cfgs, tx):
         by_len.setdefault(c["nb"], []).append(t)
+    # the duration histogram of the replicas that translocated, with the
+    # most probable time (Freedman-Diaconis bins)
+    from paper_0711_2665_amd.translocation import most_probable_time
+    mp, counts, edges = most_probable_time(done) if done else (None, None, None)
     res = {
         "replicas": len(cfgs), "cells": cells, "beads": beads, "steps": steps,
         "value": round(cells * steps / graph_s / 1e6, 1), "unit": "MLUPS (aggregate)",
@@ -177,6 +181,9 @@ def run_ensemble(steps, warmup, eager_steps):
         "sweep_layout": {k: tune[k] for k in ("tile_nodes", "order", "grid", "cap")},
         "translocation": {"steps_run": total_steps, "translocated": len(done), "censored": len(tx) - len(done),
                           "steps": done,
+                          "histogram": {"counts": counts.tolist() if counts is not None else [],
+                                        "bin_edges": [round(float(e), 1) for e in edges] if edges is not None else [],
+                                        "most_probable": mp},
                           "by_chain_length": {str(k): sorted(t for t in v if t >= 0) for k, v in sorted(by_len.items())}},
     }
     del ens
