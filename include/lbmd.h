@@ -24,9 +24,10 @@
  * Conventions (all entry points):
  *   - Ownership: the caller allocates every device buffer (sizes from
  *     lb_buffer_sizes / lb_ensemble_sizes) and keeps it alive until
- *     lb_destroy; the library borrows the pointers and never allocates
- *     device memory.  It owns host objects only: a second stream, events,
- *     and the captured graph of lb_ensemble_run.
+ *     lb_destroy; the library borrows the pointers and allocates no device
+ *     memory, except the temporary state snapshot of lb_autotune_step
+ *     (freed before that call returns).  It owns host objects only: a
+ *     second stream, events, and the captured graph of lb_ensemble_run.
  *   - Streams: every call enqueues work on the stream given to lb_init and
  *     returns without synchronising, except where a call says that it
  *     synchronises.

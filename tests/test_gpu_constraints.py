@@ -135,3 +135,37 @@ def test_adjoint_rejects_rigid_bonds():
     with pytest.raises(lbmd.LbError) as e:
         s.adjoint_sizes(4, 2)
     assert e.value.code == lbmd.LB_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("nb,shape", [(2, (16, 16, 16)), (1024, (48, 48, 48))], ids=["one_bond", "max_1024"])
+def test_rigid_bonds_extreme_chain_lengths(orc, nb, shape):
+    """The smallest chain (one bond: the systems have one unknown and the
+    reduction no round) and the largest one workgroup holds (1024 beads, ten
+    reduction rounds): three coupled steps without noise or bending within
+    1e-12 or 100x the one-ulp envelope, every bond at r0."""
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C0, shape=shape, wall_pos=shape[2] // 2, nb=nb, kT=0.0, kappa=0.0, constraints=1, init_seed=21)
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(500, 1.0)
+    r0 = o.beads()["r"]
+    v0 = np.zeros_like(r0)
+    v0[:, 2] = 0.05
+    o = orc.Oracle(cfg, r0, v0)
+    o2 = orc.Oracle(cfg, np.nextafter(r0, np.inf), v0)
+    s = lbmd.Simulation(cfg, r0, v0)
+    o.couple_step(3)
+    o2.couple_step(3)
+    s.couple_step(3)
+    torch.cuda.synchronize()
+    s.check()
+    ob, ob2 = o.beads(), o2.beads()
+    sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+    for k in ("r", "v", "J"):
+        g, e = _rel(sb[k], ob[k]), _rel(ob2[k], ob[k])
+        print(f"rigid bonds nb={nb}: {k} gpu {g:.1e} / envelope {e:.1e}", flush=True)
+        assert g <= max(TOL64, 100 * e), (k, g, e)
+    b = np.linalg.norm(np.diff(sb["r"], axis=0), axis=1)
+    assert np.abs(b - cfg["r0"]).max() < 1e-4
+    assert not o.constraint_failed()
