@@ -1,0 +1,100 @@
+"""GPU parity at the full size of the large single-run workload (512 x 256 x
+256 lattice, 33.5 M nodes, wall normal to x with a 7 x 7 pore, one
+8000-bead chain) in the launch configuration the benchmark times: the sweep
+layout chosen by the coupled-step autotuner and steps replayed from the
+captured two-step graph.  The oracle runs the same two coupled steps on the
+host (about 10 GB of FP64 populations); every population of every fluid node
+and every bead field is compared.
+
+- FP64 storage, no noise and no bending (no transcendental functions on the
+  path): bit for bit.
+- FP32 deviation storage, the workload as benchmarked (noise and bending
+  on): |f - (f64 - w)| < 1e-6 and |r - r64| < 1e-4, the bounds of the small
+  system.
+"""
+import numpy as np
+import pytest
+
+from paper_0711_2665_amd.workloads import C3, initial_chain, scaled
+
+pytestmark = pytest.mark.gpu
+
+RELAX = 300
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _oracle_start(orc, cfg):
+    """The oracle relaxes the seeded coil (MD only); both sides start from
+    its positions with v = 0 and the fluid at rest."""
+    r, v = initial_chain(cfg)
+    o = orc.Oracle(cfg, r, v)
+    o.relax(RELAX, cfg["gamma_relax"])
+    rr = o.beads()["r"].copy()
+    del o
+    return orc.Oracle(cfg, rr, np.zeros_like(rr)), rr
+
+
+def _gpu_two_steps(cfg, rr, precision):
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    s = lbmd.Simulation(cfg, rr, None, precision=precision)
+    tune = s.autotune(reps=2, coupled=True)         # restores the state it times
+    s.run(2, graph=True)
+    torch.cuda.synchronize()
+    s.check()
+    print(f"full size {cfg['name']}: layout {tune}", flush=True)
+    return s
+
+
+def test_full_size_fp64_bitwise(orc):
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C3, kT=0.0, kappa=0.0)
+    o, rr = _oracle_start(orc, cfg)
+    s = _gpu_two_steps(cfg, rr, lbmd.LB_FP64)
+    o.couple_step(2)
+    fluid = (o.flags() == 0).reshape(-1)
+    op = o.pops().reshape(19, -1)
+    gp = s.pops().reshape(19, -1)
+    ndiff = 0
+    for i in range(19):
+        ndiff += int((gp[i].cpu().numpy()[fluid] != op[i][fluid]).sum())
+    sb = {k: t.cpu().numpy() for k, t in s.beads().items()}
+    ob = o.beads()
+    bdiff = {k: int((sb[k] != ob[k]).sum()) for k in ("r", "v", "up", "J")}
+    print(f"full size FP64, 2 steps: populations differing {ndiff} of {19 * int(fluid.sum())}, beads {bdiff}",
+          flush=True)
+    assert ndiff == 0
+    assert all(v == 0 for v in bdiff.values()), bdiff
+    assert np.abs(ob["r"] - rr).max() > 1e-3                      # the chain moved
+    s.close()
+
+
+def test_full_size_fp32_deviation_as_benchmarked(orc):
+    from paper_0711_2665_amd import lbmd
+    cfg = C3
+    o, rr = _oracle_start(orc, cfg)
+    s = _gpu_two_steps(cfg, rr, lbmd.LB_FP32_DEV)
+    o.couple_step(2)
+    _, w, _ = orc.tables()
+    fluid = (o.flags() == 0).reshape(-1)
+    op = o.pops().reshape(19, -1)
+    gp = s.pops().reshape(19, -1)
+    err = 0.0
+    dev = 0.0
+    for i in range(19):
+        fo = op[i][fluid] - w[i]
+        err = max(err, float(np.abs(gp[i].double().cpu().numpy()[fluid] - fo).max()))
+        dev = max(dev, float(np.abs(fo).max()))
+    rg, ro = s.beads()["r"].cpu().numpy(), o.beads()["r"]
+    print(f"full size FP32 deviations, 2 steps: |f - f64|_max {err:.3e} (max |f - w| {dev:.3e}), "
+          f"|r - r64|_max {np.abs(rg - ro).max():.3e}", flush=True)
+    assert dev > 1e-4                                             # the chain forced the fluid
+    assert err < 1e-6
+    assert np.abs(rg - ro).max() < 1e-4
+    s.close()
