@@ -11,11 +11,17 @@ and every bead field is compared.
 - FP32 deviation storage, the workload as benchmarked (noise and bending
   on): |f - (f64 - w)| < 1e-6 and |r - r64| < 1e-4, the bounds of the small
   system.
+
+Both also for the same lattice and chain with the paper's bead LJ under the
+multiple-time-step cycle (5 outer x 20 inner sub-steps), and for the
+benchmarked ensemble (64 uneven replicas, 28.3 M nodes, 14050 beads, one
+context) on a sample of replicas that includes the largest lattice and the
+longest chains; there the oracle runs each sampled replica alone.
 """
 import numpy as np
 import pytest
 
-from paper_0711_2665_amd.workloads import C3, initial_chain, scaled
+from paper_0711_2665_amd.workloads import C3, C3M, ensemble_configs, initial_chain, scaled
 
 pytestmark = pytest.mark.gpu
 
@@ -52,9 +58,10 @@ def _gpu_two_steps(cfg, rr, precision):
     return s
 
 
-def test_full_size_fp64_bitwise(orc):
+@pytest.mark.parametrize("base", [C3, C3M], ids=["uniform", "mts_paper_lj"])
+def test_full_size_fp64_bitwise(orc, base):
     from paper_0711_2665_amd import lbmd
-    cfg = scaled(C3, kT=0.0, kappa=0.0)
+    cfg = scaled(base, kT=0.0, kappa=0.0)
     o, rr = _oracle_start(orc, cfg)
     s = _gpu_two_steps(cfg, rr, lbmd.LB_FP64)
     o.couple_step(2)
@@ -75,9 +82,9 @@ def test_full_size_fp64_bitwise(orc):
     s.close()
 
 
-def test_full_size_fp32_deviation_as_benchmarked(orc):
+@pytest.mark.parametrize("cfg", [C3, C3M], ids=["uniform", "mts_paper_lj"])
+def test_full_size_fp32_deviation_as_benchmarked(orc, cfg):
     from paper_0711_2665_amd import lbmd
-    cfg = C3
     o, rr = _oracle_start(orc, cfg)
     s = _gpu_two_steps(cfg, rr, lbmd.LB_FP32_DEV)
     o.couple_step(2)
@@ -98,3 +105,55 @@ def test_full_size_fp32_deviation_as_benchmarked(orc):
     assert err < 1e-6
     assert np.abs(rg - ro).max() < 1e-4
     s.close()
+
+
+def _sample(cfgs):
+    """Replicas to compare: the largest lattice, the longest chain, the
+    shortest chain and the first replica."""
+    size = [c["shape"][0] * c["shape"][1] * c["shape"][2] for c in cfgs]
+    pick = {0, int(np.argmax(size)), int(np.argmax([c["nb"] for c in cfgs])), int(np.argmin([c["nb"] for c in cfgs]))}
+    return sorted(pick)
+
+
+@pytest.mark.parametrize("precision", ["fp64_bitwise", "fp32dev_as_benchmarked"])
+def test_full_size_ensemble_sampled_replicas(orc, precision):
+    torch = _torch()
+    from paper_0711_2665_amd import lbmd
+    cfgs = ensemble_configs(64)
+    if precision == "fp64_bitwise":
+        cfgs = [scaled(c, kT=0.0, kappa=0.0) for c in cfgs]
+    prec = lbmd.LB_FP64 if precision == "fp64_bitwise" else lbmd.LB_FP32_DEV
+    rr = []
+    for c in cfgs:                                   # the oracle relaxes every coil
+        r, v = initial_chain(c)
+        o = orc.Oracle(c, r, v)
+        o.relax(RELAX, c["gamma_relax"])
+        rr.append(o.beads()["r"].copy())
+        del o
+    ens = lbmd.Ensemble(cfgs, rr, precision=prec)
+    tune = ens.autotune(reps=2, coupled=True)
+    ens.run(2, graph=True)
+    torch.cuda.synchronize()
+    ens.check()
+    print(f"full-size ensemble {precision}: layout {tune}", flush=True)
+    _, w, _ = orc.tables()
+    for k in _sample(cfgs):
+        o = orc.Oracle(cfgs[k], rr[k], np.zeros_like(rr[k]))
+        o.couple_step(2)
+        fluid = (o.flags() == 0).reshape(-1)
+        op = o.pops().reshape(19, -1)[:, fluid]
+        gp = ens.pops(k).reshape(19, -1).double().cpu().numpy()[:, fluid]
+        gb = {n: t.cpu().numpy() for n, t in ens.beads(k).items()}
+        ob = o.beads()
+        tag = f"replica {k} ({cfgs[k]['shape']}, {cfgs[k]['nb']} beads)"
+        if precision == "fp64_bitwise":
+            bd = {n: int((gb[n] != ob[n]).sum()) for n in ("r", "v", "up", "J")}
+            print(f"{tag}: populations differing {int((gp != op).sum())}, beads {bd}", flush=True)
+            assert np.array_equal(gp, op)
+            assert all(v == 0 for v in bd.values()), (k, bd)
+        else:
+            err = float(np.abs(gp - (op - w[:, None])).max())
+            er = float(np.abs(gb["r"] - ob["r"]).max())
+            print(f"{tag}: |f - f64|_max {err:.3e}, |r - r64|_max {er:.3e}", flush=True)
+            assert err < 1e-6 and er < 1e-4, (k, err, er)
+    ens.close()
