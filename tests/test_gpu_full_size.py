@@ -12,7 +12,8 @@ and every bead field is compared.
   on): |f - (f64 - w)| < 1e-6 and |r - r64| < 1e-4, the bounds of the small
   system.
 
-Both also for the same lattice and chain with the paper's bead LJ under the
+The fluctuating-fluid leg (fluid kT = bead kT) in both storages, and both
+checks above also for the same lattice and chain with the paper's bead LJ under the
 multiple-time-step cycle (5 outer x 20 inner sub-steps), and for the
 benchmarked ensemble (64 uneven replicas, 28.3 M nodes, 14050 beads, one
 context) on a sample of replicas that includes the largest lattice and the
@@ -104,6 +105,56 @@ def test_full_size_fp32_deviation_as_benchmarked(orc, cfg):
     assert dev > 1e-4                                             # the chain forced the fluid
     assert err < 1e-6
     assert np.abs(rg - ro).max() < 1e-4
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_full_size_fluctuating_fluid(orc, precision):
+    """The benchmark's fluctuating-fluid leg (fluid kT = bead kT): FP64
+    within 1e-12 relative (the device's and the host's log and sin/cos may
+    differ in the last bit).  FP32 deviation storage draws the fluid normals
+    in FP32: a uniform (x + 1/2) 2^-32 within 2^-25 of 1 rounds to 1, so its
+    Box-Muller radius sqrt(-2 ln u) comes out 0 instead of at most
+    sqrt(2 * 2^-25).  Over the 5e8 draws of a full-size step a few do, and
+    each moves populations by at most that radius times
+    w_i sum_k |e_ki| a_k / b_k (a_k the mode's noise amplitude at the largest
+    density): the bound of the FP32 test, plus 1e-8 for the storage."""
+    from paper_0711_2665_amd import lbmd
+    cfg = scaled(C3, fluid_kT=C3["kT"])
+    o, rr = _oracle_start(orc, cfg)
+    s = _gpu_two_steps(cfg, rr, lbmd.LB_FP64 if precision == "fp64" else lbmd.LB_FP32_DEV)
+    o.couple_step(2)
+    _, w, _ = orc.tables()
+    fluid = (o.flags() == 0).reshape(-1)
+    op = o.pops().reshape(19, -1)
+    gp = s.pops().reshape(19, -1)
+    err = dev = fmax = 0.0
+    rho = np.zeros(int(fluid.sum()))
+    for i in range(19):
+        rho += op[i][fluid]
+        fo = op[i][fluid]
+        fg = gp[i].double().cpu().numpy()[fluid]
+        if precision == "fp32dev":
+            fo = fo - w[i]
+        err = max(err, float(np.abs(fg - fo).max()))
+        dev = max(dev, float(np.abs(op[i][fluid] - w[i]).max()))
+        fmax = max(fmax, float(np.abs(fo).max()))
+    er = float(np.abs(s.beads()["r"].cpu().numpy() - o.beads()["r"]).max())
+    print(f"full size fluctuating fluid {precision}, 2 steps: |f - f_oracle|_max {err:.3e} "
+          f"(max |f - w| {dev:.3e}, max |f| {fmax:.3e}), |r - r_oracle|_max {er:.3e}", flush=True)
+    assert dev > 1e-3                                            # the noise is on
+    if precision == "fp64":
+        assert err <= 1e-12 * fmax
+        assert er <= 1e-12 * float(np.abs(rr).max())
+    else:
+        E = orc.mode_basis()
+        b = (w[None, :] * E * E).sum(1)
+        om = 1.0 / cfg["tau"]
+        amp = np.sqrt(3.0 * rho.max() * cfg["fluid_kT"] * (1.0 - (1.0 - om) ** 2) * b[4:])
+        tail = np.sqrt(2.0 * 2.0 ** -25) * (w * (np.abs(E[4:, :]) * (amp / b[4:])[:, None]).sum(0)).max()
+        print(f"FP32 noise-tail bound {tail:.3e}", flush=True)
+        assert err <= tail + 1e-8
+        assert er < 1e-4
     s.close()
 
 
