@@ -174,8 +174,24 @@ __device__ inline auto collide_node(const T f[Q], T out[Q], const T* __restrict_
 // with key (fseed, frep) and counters (n, c, b, 1), b = 0..3: uniforms
 // (x + 1/2) 2^-32, Box-Muller on the pairs (u0, u1) and (u2, u3), cosine then
 // sine.  FP64: double log, sincos and sqrt.  FP32 deviation storage: the
-// hardware log2, sqrt and sin/cos of a fraction of a turn.
+// hardware log2 (through the complement near 1), sqrt and sin/cos of a
+// fraction of a turn.
 // ---------------------------------------------------------------------------
+// -2 ln u in FP32 for the uniform u = (x + 1/2) 2^-32.  Near 1 the FP32 u
+// itself is off by up to 2^-25 (it rounds to 1 for the top 2^7 values of x),
+// so above 1 - 2^-6 the complement t = 1 - u = (~x + 1/2) 2^-32, which FP32
+// holds to its own precision, gives -ln(1 - t) = t + t^2/2 + t^3/3 + t^4/4
+// (the next term is below 2^-24 of the sum); below, the hardware log2.
+__device__ inline float neg2_log_uniform(uint32_t x) {
+  const float s32 = 2.3283064365386963e-10f;     // 2^-32
+  const float u = fmaf((float)x, s32, 0.5f * s32);
+  const float t = fmaf((float)(~x), s32, 0.5f * s32);
+  const float series = 2.0f * (t * fmaf(t, fmaf(t, fmaf(t, 0.25f, 0.33333334f), 0.5f), 1.0f));
+  const float m2ln2 = -1.3862943611198906f;       // -2 ln 2: -2 ln u = -2 ln 2 log2 u
+  const float hw = m2ln2 * __builtin_amdgcn_logf(u);
+  return t <= 0.015625f ? series : hw;
+}
+
 template <typename T, bool DEV, typename R>
 __device__ inline void fluid_noise(const LbParams& p, uint32_t n, int c, R rho, T f[Q]) {
   // s[k-4] = famp[k-4] r_k
@@ -187,11 +203,9 @@ __device__ inline void fluid_noise(const LbParams& p, uint32_t n, int c, R rho, 
     R r[4];
     if constexpr (DEV) {
       const float s32 = 2.3283064365386963e-10f;   // 2^-32
-      const float u0 = fmaf((float)x0, s32, 0.5f * s32), u1 = fmaf((float)x1, s32, 0.5f * s32);
-      const float u2 = fmaf((float)x2, s32, 0.5f * s32), u3 = fmaf((float)x3, s32, 0.5f * s32);
-      const float m2ln2 = -1.3862943611198906f;     // -2 ln 2: -2 ln u = -2 ln 2 log2 u
-      const float ra = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
-      const float rb = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+      const float u1 = fmaf((float)x1, s32, 0.5f * s32), u3 = fmaf((float)x3, s32, 0.5f * s32);
+      const float ra = __builtin_amdgcn_sqrtf(neg2_log_uniform(x0));
+      const float rb = __builtin_amdgcn_sqrtf(neg2_log_uniform(x2));
       r[0] = ra * __builtin_amdgcn_cosf(u1);
       r[1] = ra * __builtin_amdgcn_sinf(u1);
       r[2] = rb * __builtin_amdgcn_cosf(u3);

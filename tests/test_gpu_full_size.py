@@ -113,12 +113,14 @@ def test_full_size_fluctuating_fluid(orc, precision):
     """The benchmark's fluctuating-fluid leg (fluid kT = bead kT): FP64
     within 1e-12 relative (the device's and the host's log and sin/cos may
     differ in the last bit).  FP32 deviation storage draws the fluid normals
-    in FP32: a uniform (x + 1/2) 2^-32 within 2^-25 of 1 rounds to 1, so its
-    Box-Muller radius sqrt(-2 ln u) comes out 0 instead of at most
-    sqrt(2 * 2^-25).  Over the 5e8 draws of a full-size step a few do, and
-    each moves populations by at most that radius times
-    w_i sum_k |e_ki| a_k / b_k (a_k the mode's noise amplitude at the largest
-    density): the bound of the FP32 test, plus 1e-8 for the storage."""
+    in FP32; the Box-Muller radius sqrt(-2 ln u) is then off by at most
+    4e-7 (above u = 1 - 2^-6 it comes from the exact complement 1 - u; below,
+    the FP32 u is within 2^-25 of the uniform and the radius at least
+    sqrt(2 * 2^-6), plus the hardware log2's own error), and a radius error
+    moves populations by at most that much times w_i sum_k |e_ki| a_k / b_k
+    (a_k the mode's noise amplitude at the largest density): the bound of
+    the FP32 test, plus 16 FP32 ulps of the largest deviation for the
+    storage and the collision."""
     from paper_0711_2665_amd import lbmd
     cfg = scaled(C3, fluid_kT=C3["kT"])
     o, rr = _oracle_start(orc, cfg)
@@ -151,9 +153,9 @@ def test_full_size_fluctuating_fluid(orc, precision):
         b = (w[None, :] * E * E).sum(1)
         om = 1.0 / cfg["tau"]
         amp = np.sqrt(3.0 * rho.max() * cfg["fluid_kT"] * (1.0 - (1.0 - om) ** 2) * b[4:])
-        tail = np.sqrt(2.0 * 2.0 ** -25) * (w * (np.abs(E[4:, :]) * (amp / b[4:])[:, None]).sum(0)).max()
+        tail = 4e-7 * (w * (np.abs(E[4:, :]) * (amp / b[4:])[:, None]).sum(0)).max()
         print(f"FP32 noise-tail bound {tail:.3e}", flush=True)
-        assert err <= tail + 1e-8
+        assert err <= tail + 16 * 2.0 ** -24 * dev             # + 16 FP32 ulps of the largest deviation
         assert er < 1e-4
     s.close()
 
