@@ -93,8 +93,10 @@ __device__ inline void lj_dd(const MdParams& P, Dd d0, Dd d1, Dd d2, Dd F[3]) {
 }
 
 // Wall sites within r_c of the bead (r_c <= 3): the sites of the wall plane
-// in the 6 x 6 window at offsets -2..3 around the base node, minus the pore
-// block; the derivative of the wrapped position is that of r.
+// at offsets P.wlo..P.whi (1 - ceil(r_c)..ceil(r_c), within -2..3) around the
+// base node, minus the pore block -- the rows outside hold no site within
+// r_c, so the hit sites and their order are those of the full 6 x 6 window;
+// the derivative of the wrapped position is that of r.
 __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, Dd F[3]) {
   if (g.wall_axis < 0) return;
   const double w[3] = {wrapc(rp[0].v, g.nx), wrapc(rp[1].v, g.ny), wrapc(rp[2].v, g.nz)};
@@ -104,14 +106,14 @@ __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, D
   int off = g.wall_pos - b[a];               // offset along the normal reaching the plane
   if (off < -2) off += n[a];
   if (off > 3) off -= n[a];
-  if (off < -2 || off > 3) return;
+  if (off < P.wlo || off > P.whi) return;
   int site[3];
   site[a] = b[a] + off;
-  for (int o1 = -2; o1 <= 3; ++o1) {
+  for (int o1 = P.wlo; o1 <= P.whi; ++o1) {
     const int u1 = b[t1] + o1;
     const int v1 = u1 < 0 ? u1 + n[t1] : (u1 >= n[t1] ? u1 - n[t1] : u1);
     const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
-    for (int o0 = -2; o0 <= 3; ++o0) {
+    for (int o0 = P.wlo; o0 <= P.whi; ++o0) {
       const int u0 = b[t0] + o0;
       const int v0 = u0 < 0 ? u0 + n[t0] : (u0 >= n[t0] ? u0 - n[t0] : u0);
       const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
