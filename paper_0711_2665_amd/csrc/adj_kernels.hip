@@ -285,6 +285,19 @@ __device__ inline void chain_forces(const MdParams& P, const Geom& g, const doub
   bead_force_dd(P, g, pos, dir, av, ad, p, lane, on, F, dF);
 }
 
+// The bead noise of every sub-step of the step being reversed, drawn in
+// parallel before the serial reverse sub-cycle (the forward's draws: key
+// (seed, replica), counter (step, s, p, 0)); one thread per (s, p).
+__global__ void k_adj_noise(Dev d, double* __restrict__ xi, uint32_t step, int nb, int n_sub) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb * n_sub) return;
+  const MdParams& P = d.reps[0].mp;
+  const int s = t / nb, p = t - s * nb;
+  double x[3];
+  gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, x);
+  for (int c = 0; c < 3; ++c) xi[(size_t)t * 3 + c] = x[c];
+}
+
 __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const double* __restrict__ mdt,
                                                    const double* __restrict__ upt, uint32_t step, double kT) {
   extern __shared__ double lds[];
@@ -333,7 +346,8 @@ __global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const doubl
       const bool field = P.field_on && in_field(g, rm);
       if (field) f[g.wall_axis] += P.f_drive;
       double xi[3] = {0.0, 0.0, 0.0};
-      if (P.sig != 0.0 && lead) gauss3(P.seed, P.replica, step, (uint32_t)s, (uint32_t)p, xi);
+      if (P.sig != 0.0 && lead)
+        for (int c = 0; c < 3; ++c) xi[c] = a.xi[((size_t)s * nb + p) * 3 + c];
       for (int c = 0; c < 3; ++c) {
         const double vo = mdt[((size_t)s * nb + p) * 6 + 3 + c];
         if (lead) {
@@ -507,10 +521,13 @@ template <typename T, bool DEV>
 void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const Dev& d, const Dev& dspread,
                              const AdjBufs& a, const double* mdt, const double* upt,
                              const double* Jt, uint32_t step, double kT, int ntiles, int tile_nodes, int nslots,
-                             int nb, hipStream_t s) {
+                             int nb, int n_sub, hipStream_t s) {
   launch_bead_prep(d, nslots, s);
   hipLaunchKernelGGL((k_adj_spread_t<T>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)lamB, d, a, Jt, nb);
   size_t lds = sizeof(double) * (24 * (size_t)nb + 2 * (ADJ_WG / ADJ_LANES));
+  if (kT != 0.0) {   // sigma > 0 exactly when kT > 0 (gamma > 0 here)
+    hipLaunchKernelGGL(k_adj_noise, dim3(nblk((long)nb * n_sub, 256)), dim3(256), 0, s, d, a.xi, step, nb, n_sub);
+  }
   hipLaunchKernelGGL(k_adj_md, dim3(1), dim3(ADJ_WG), lds, s, d, a, mdt, upt, step, kT);
   hipLaunchKernelGGL((k_adj_gather_t<T, DEV>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)A, d, a, nb);
   launch_spread<T>(dspread, nslots, s);
@@ -529,9 +546,9 @@ void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s) {
 
 template void launch_adj_reverse_step<double, false>(const void*, const void*, void*, const Dev&, const Dev&,
                                                      const AdjBufs&, const double*, const double*, const double*,
-                                                     uint32_t, double, int, int, int, int, hipStream_t);
+                                                     uint32_t, double, int, int, int, int, int, hipStream_t);
 template void launch_adj_reverse_step<float, true>(const void*, const void*, void*, const Dev&, const Dev&,
                                                    const AdjBufs&, const double*, const double*, const double*,
-                                                   uint32_t, double, int, int, int, int, hipStream_t);
+                                                   uint32_t, double, int, int, int, int, int, hipStream_t);
 
 }  // namespace lbmd

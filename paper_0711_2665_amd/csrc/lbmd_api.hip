@@ -566,7 +566,7 @@ int build_graph(lb_ctx* c) {
 // Workspace of the adjoint: checkpoints every K steps (and the final state),
 // the per-step tape of one segment, adjoint fields.
 struct AdjLayout {
-  size_t ckpt, tape_pops, tape_beads, lamA, lamB, lamu, lbead, mdtape, par, total;
+  size_t ckpt, tape_pops, tape_beads, lamA, lamB, lamu, lbead, mdtape, xi, par, total;
   size_t pops_slot, bead_arr, md_arr;
   int nseg;
 };
@@ -587,6 +587,7 @@ AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
   L.lamu = o; o += align256(es * 3 * (size_t)c->pk.nodes);
   L.lbead = o; o += 5 * L.bead_arr;
   L.mdtape = o; o += (size_t)K * L.md_arr;
+  L.xi = o; o += align256(sizeof(double) * 3 * (size_t)c->d[0].nb * (size_t)c->n_sub);
   L.par = o; o += 256;
   L.total = o;
   return L;
@@ -1307,6 +1308,7 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
   a.lrs = (double*)(w + L.lbead + 4 * L.bead_arr);
   a.lamu = w + L.lamu;
   a.par = (double*)(w + L.par);
+  a.xi = (double*)(w + L.xi);
   void* lamB = w + L.lamB;   // adjoint of the populations after the step being reversed
   void* lamA = w + L.lamA;
   acc(hipMemsetAsync(lamB, 0, L.pops_slot, c->s));
@@ -1349,11 +1351,11 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
       if (c->dev)
         launch_adj_reverse_step<float, true>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_bead(j, 2),
                                              tape_bead(j, 3), step, kT, c->ntiles, c->sweep.tile_nodes, c->nslots,
-                                             nb, c->s);
+                                             nb, c->n_sub, c->s);
       else
         launch_adj_reverse_step<double, false>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_bead(j, 2),
                                                tape_bead(j, 3), step, kT, c->ntiles, c->sweep.tile_nodes,
-                                               c->nslots, nb, c->s);
+                                               c->nslots, nb, c->n_sub, c->s);
       std::swap(lamA, lamB);
     }
   }

@@ -150,13 +150,14 @@ struct AdjBufs {
 
   void* lamu;       // [3][N] (storage type) adjoint of the gathered node velocity
   double* par;      // [4]: dL/dgamma, dL/dF_drive accumulators
+  double* xi;       // [n_sub][nb][3] the bead noise of the step being reversed
 };
 void launch_adj_init(const double* dLdr, const double* dLdv, const AdjBufs& a, int nb, hipStream_t s);
 template <typename T, bool DEV>
 void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const Dev& d, const Dev& dspread,
                              const AdjBufs& a, const double* mdt, const double* upt,
                              const double* Jt, uint32_t step, double kT, int ntiles, int tile_nodes, int nslots,
-                             int nb, hipStream_t s);
+                             int nb, int n_sub, hipStream_t s);
 void launch_adj_finish(const AdjBufs& a, double* grads, int nb, hipStream_t s);
 
 // MD sub-cycle of all replicas: n_sub launches, one per sub-step, reading
