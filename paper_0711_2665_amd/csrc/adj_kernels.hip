@@ -130,19 +130,19 @@ __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, D
 // Bending forces of the angle centred at q (1 <= q <= nb - 2) at positions
 // pos with direction dir, value and derivative, into LDS rows av[q], ad[q]:
 // [0..2] force on q-1, [3..5] on q, [6..8] on q+1.
+// The three vertex forces are independent: the caller gives vertex w to
+// lane w of the bead.
 __device__ inline void angle_to_lds(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int q,
-                                    double (*av)[9], double (*ad)[9]) {
+                                    int w, double (*av)[9], double (*ad)[9]) {
   Dd ra[3], rb[3], rc[3];
   for (int a = 0; a < 3; ++a) {
     ra[a] = Dd{pos[q - 1][a], dir[q - 1][a]};
     rb[a] = Dd{pos[q][a], dir[q][a]};
     rc[a] = Dd{pos[q + 1][a], dir[q + 1][a]};
   }
-  for (int w = 0; w < 3; ++w) {
-    Dd F[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-    angle_dd(P, ra, rb, rc, w, F);
-    for (int a = 0; a < 3; ++a) { av[q][3 * w + a] = F[a].v; ad[q][3 * w + a] = F[a].d; }
-  }
+  Dd F[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  angle_dd(P, ra, rb, rc, w, F);
+  for (int a = 0; a < 3; ++a) { av[q][3 * w + a] = F[a].v; ad[q][3 * w + a] = F[a].d; }
 }
 
 // Conservative force on chain bead p at positions pos with direction dir
@@ -280,7 +280,7 @@ __device__ inline void chain_forces(const MdParams& P, const Geom& g, const doub
                                     double (*av)[9], double (*ad)[9], int p, int lane, bool on, double F[3],
                                     double dF[3]) {
   const int nb = P.nb;
-  if (lane == 0 && p >= 1 && p <= nb - 2) angle_to_lds(P, pos, dir, p, av, ad);
+  if (lane < 3 && p >= 1 && p <= nb - 2) angle_to_lds(P, pos, dir, p, lane, av, ad);
   __syncthreads();
   bead_force_dd(P, g, pos, dir, av, ad, p, lane, on, F, dF);
 }
