@@ -153,19 +153,46 @@ __device__ inline void angle_to_lds(const MdParams& P, const double (*pos)[3], c
 // p+1) and the wall sites.  The four partial sums are combined in a fixed
 // order with cross-lane reads, so every lane of the bead ends with F, dF.
 // The field is added by the caller (constant in r).
+constexpr int ADJ_MAXHIT = 16;   // partners within r_c kept per lane (j = lane mod 4)
+
 __device__ inline void bead_force_dd(const MdParams& P, const Geom& g, const double (*pos)[3],
                                      const double (*dir)[3], const double (*av)[9], const double (*ad)[9], int p,
                                      int lane, bool on, double F[3], double dF[3]) {
   const int nb = P.nb;
   Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
   if (on) {
+    // the partners within r_c first, in ascending j, then their dual LJ
+    // terms in that order: the lanes of a wave then evaluate the LJ terms
+    // together instead of one scan iteration at a time (more than
+    // ADJ_MAXHIT partners: the same sum in one pass)
+    int hit[ADJ_MAXHIT];
+    int nh = 0;
     for (int j = lane; j < nb; j += 4) {
       if (j == p) continue;
       const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
       const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
       const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
       if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
-      lj_dd(P, Dd{e0, dir[p][0] - dir[j][0]}, Dd{e1, dir[p][1] - dir[j][1]}, Dd{e2, dir[p][2] - dir[j][2]}, S);
+      if (nh < ADJ_MAXHIT) hit[nh] = j;
+      ++nh;
+    }
+    if (nh <= ADJ_MAXHIT) {
+      for (int k = 0; k < nh; ++k) {
+        const int j = hit[k];
+        const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
+        const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
+        const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
+        lj_dd(P, Dd{e0, dir[p][0] - dir[j][0]}, Dd{e1, dir[p][1] - dir[j][1]}, Dd{e2, dir[p][2] - dir[j][2]}, S);
+      }
+    } else {
+      for (int j = lane; j < nb; j += 4) {
+        if (j == p) continue;
+        const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
+        const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
+        const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
+        if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+        lj_dd(P, Dd{e0, dir[p][0] - dir[j][0]}, Dd{e1, dir[p][1] - dir[j][1]}, Dd{e2, dir[p][2] - dir[j][2]}, S);
+      }
     }
     if (lane == 0) {
       Dd rp[3] = {Dd{pos[p][0], dir[p][0]}, Dd{pos[p][1], dir[p][1]}, Dd{pos[p][2], dir[p][2]}};
