@@ -303,8 +303,9 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * otherwise); either precision.
  *
  * lb_adjoint_sizes: workspace bytes for (nsteps, K): nsteps/K + 1
- *   checkpoints of lb_sizes.state_bytes, K population arrays of tape, the
- *   adjoint fields.  Host only.
+ *   checkpoints of lb_sizes.state_bytes, K population arrays and bead
+ *   sub-cycle records of tape, the adjoint fields, and one step's bead noise
+ *   (n_sub x nb x 3 doubles).  Host only.
  * lb_adjoint_forward: runs nsteps coupled steps from the current state (as
  *   md_couple_step does) and records the checkpoints in ws (device, at
  *   least the size above, 256-byte aligned, owned by the caller, kept until
