@@ -1141,6 +1141,12 @@ void or_set_beads(void* h, const double* r, const double* v) {
   if (r) std::memcpy(s->r.data(), r, n * sizeof(double));
   if (v) std::memcpy(s->v.data(), v, n * sizeof(double));
 }
+// Sets the fluid velocity at the beads, u_p (the value the next observables
+// read; a coupled step overwrites it with its gather).
+void or_set_up(void* h, const double* up) {
+  auto* s = (SimD*)h;
+  std::memcpy(s->up.data(), up, (size_t)3 * s->nb * sizeof(double));
+}
 void or_get_force(void* h, double* out) { auto* s = (SimD*)h; std::memcpy(out, s->F.data(), sizeof(double) * s->F.size()); }
 void or_observables(void* h, double* out) { ((SimD*)h)->observables(out); }
 long long or_step_count(void* h) { return ((SimD*)h)->step; }

@@ -52,6 +52,7 @@ def _declare(L):
     L.or_get_flags.argtypes = [_P, C.POINTER(C.c_uint8)]
     L.or_get_beads.argtypes = [_P, _DP, _DP, _DP, _DP]
     L.or_set_beads.argtypes = [_P, _DP, _DP]
+    L.or_set_up.argtypes = [_P, _DP]
     L.or_get_force.argtypes = [_P, _DP]
     L.or_observables.argtypes = [_P, _DP]
     L.or_step_count.restype = C.c_longlong
@@ -186,6 +187,12 @@ class Oracle:
         r = None if r is None else np.ascontiguousarray(r, dtype=np.float64).reshape(-1)
         v = None if v is None else np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
         self.L.or_set_beads(self.h, _dp(r), _dp(v))
+
+    def set_up(self, up):
+        """Sets the fluid velocity at the beads (read by the next observables)."""
+        up = np.ascontiguousarray(up, dtype=np.float64).reshape(-1)
+        assert up.size == 3 * self.nb
+        self.L.or_set_up(self.h, _dp(up))
 
     def force_field(self):
         out = np.empty(3 * self.N)
