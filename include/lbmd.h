@@ -25,9 +25,10 @@
  *   - Ownership: the caller allocates every device buffer (sizes from
  *     lb_buffer_sizes / lb_ensemble_sizes) and keeps it alive until
  *     lb_destroy; the library borrows the pointers and allocates no device
- *     memory, except the temporary state snapshot of lb_autotune_step
- *     (freed before that call returns).  It owns host objects only: a
- *     second stream, events, and the captured graph of lb_ensemble_run.
+ *     memory (scratch areas such as the autotuner's state snapshot or the
+ *     adjoint's checkpoints are buffers of the caller too).  It owns host
+ *     objects only: two streams of its own, events, and the captured graph
+ *     of lb_ensemble_run.
  *   - Streams: every call enqueues work on the stream given to lb_init and
  *     returns without synchronising, except where a call says that it
  *     synchronises.
@@ -72,8 +73,17 @@ enum {
   LB_FP32_DEV = 1  /* f_i - w_i in float, collision in float, bead side FP64 */
 };
 
-/* Number of doubles lb_observables writes. */
+/* Number of doubles lb_observables writes per replica. */
 #define LB_NOBS 25
+
+/* Groups of observables (the which_mask of lb_observables). */
+enum {
+  LB_OBS_FLUID = 1,     /* [0..3]: fluid mass and momentum (a pass over the lattice) */
+  LB_OBS_BEADS = 2,     /* [4..15], [23], [24]: bead quantities                      */
+  LB_OBS_LEDGERS = 4,   /* [16..21]: wall momentum ledgers                           */
+  LB_OBS_STEP = 8,      /* [22]: step count                                          */
+  LB_OBS_ALL = 15
+};
 
 /*
  * Run description.  The geometry follows Sec. 4: one wall plane normal to
@@ -93,7 +103,11 @@ typedef struct lb_desc {
   int32_t wall_pos;       /* 2 <= wall_pos <= n - 3 along wall_axis          */
   int32_t pore_h;         /* 0 <= pore_h <= transverse extent                */
   int32_t nb;             /* beads in the chain (0: fluid only)              */
-  double mass;            /* bead mass                                        */
+  double mass;            /* bead mass; 1 whenever gamma > 0 (the exponential
+                             kick of Sec. 2, Eq. (SPValgo), treats gamma as a
+                             rate and its friction term as gamma u_p, which
+                             gives the impulse m (1 - e)(u - v) that the fluid
+                             takes only at unit mass)                        */
   double k_bond, r0;      /* harmonic bond constant and rest length          */
   double kappa;           /* bending constant, V = kappa phi^2 / 2           */
   double eps, sigma, rc;  /* truncated LJ (bead-bead and bead-wall site),
@@ -148,6 +162,8 @@ typedef struct lb_sizes {
   size_t state_bytes;  /* size of the buffer lb_get_state writes              */
   size_t nodes;        /* packed lattice nodes (all replicas, with padding)   */
   size_t bead_slots;   /* bead slots (all replicas, with padding)             */
+  size_t snapshot_bytes; /* scratch lb_autotune_step needs: a copy of the
+                            populations, force, beads and work buffers         */
 } lb_sizes;
 
 /* Device pointers (hipMalloc'ed or torch CUDA tensors), 256-byte aligned. */
@@ -166,7 +182,8 @@ typedef struct lb_ctx lb_ctx;
  * LB_ERR_ARG: extents <= 0 or 19 N > 2^31 - 1, tau <= 0.5, a wall plane
  * outside [2, n-3], a pore wider than the face, nb < 0, n_sub < 1, negative
  * gamma, kT or fluid_kT, rc outside (0, 3], nb > 0 without a positive
- * mass, nb > 0 with a wall on a lattice with an extent below 6, or an
+ * mass, a mass other than 1 with gamma > 0, nb > 0 with a wall on a lattice
+ * with an extent below 6, or an
  * mts_outer that is negative or does not divide n_sub into at most 40, an
  * unknown coupling, or rigid bonds with mts_outer > 0 or nb > 1024. */
 int lb_buffer_sizes(const lb_desc* d, lb_sizes* out);
@@ -270,19 +287,23 @@ int lb_autotune(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
  * the sweep alone (the sweep shares the memory system with the bead phase
  * that runs beside it): per candidate, 2 ceil(reps / 2) coupled steps
  * replayed from the two-step graph are timed.  The complete device state
- * (current populations, beads, work area, force field) is copied to a
- * temporary device buffer first (hipMalloc'd here, about pops_bytes +
- * force_bytes + beads_bytes + work_bytes) and restored after every
- * candidate, with the step count: the state and every later result are
- * unchanged.  *out_ms is the mean coupled-step time (as measured when the
- * entry was cached).
- * Synchronises the stream.  LB_ERR_ARG: reps < 1; LB_ERR_DEVICE: a HIP call
- * failed (the state is restored when the snapshot exists). */
-int lb_autotune_step(lb_ctx* ctx, int reps, int* out_cfg, double* out_ms);
+ * (current populations, beads, work area, force field) is first copied to
+ * snap_dev, a device buffer of the caller of at least
+ * lb_sizes.snapshot_bytes (256-byte aligned; unused when the layout is
+ * already cached), and restored after every candidate, with the step count:
+ * the state and every later result are unchanged.  *out_ms is the mean
+ * coupled-step time (as measured when the entry was cached).  No device
+ * memory is allocated.
+ * Synchronises the stream.  LB_ERR_ARG: reps < 1, snap_dev NULL, too small
+ * or misaligned (the layout not being cached); LB_ERR_DEVICE: a HIP call
+ * failed (the state is restored from the snapshot). */
+int lb_autotune_step(lb_ctx* ctx, int reps, void* snap_dev, size_t snap_bytes, int* out_cfg, double* out_ms);
 
 /* Sets the friction rate gamma (>= 0) and the pore force F_drive of
  * replica rep and recomputes its SPV coefficients (e = exp(-gamma h), the
- * noise amplitude from the replica's kT).  Synchronises the stream. */
+ * noise amplitude from the replica's kT).  Synchronises the stream.
+ * LB_ERR_ARG: rep out of range, a negative or non-finite value, or gamma > 0
+ * on a chain whose mass is not 1. */
 int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
 
 /*
@@ -328,22 +349,28 @@ int lb_adjoint_run(lb_ctx* ctx, int nsteps, int K, void* ws_dev, size_t ws_bytes
 int md_relax(lb_ctx* ctx, int nsub_total, double gamma_relax);
 
 /* Writes LB_NOBS doubles per replica to out_dev (device memory; replica r
- * at out_dev + LB_NOBS r): [0] fluid mass,
+ * at out_dev + LB_NOBS r), the groups of which_mask (LB_OBS_* bits; entries
+ * of groups not asked for are left as they are; LB_ERR_ARG for unknown
+ * bits): [0] fluid mass,
  * [1..3] fluid momentum (Sec. 3: global momentum reductions), [4] bead
  * temperature m<v^2>/3 (Sec. 2: the monitored bead temperature), [5..7] bead
  * momentum, [8] mean unwrapped normal coordinate, [9] translocated fraction,
  * [10] beads in the pore channel, [11] R_U, [12] R_T, [13] R_eff with
  * nu = 0.6 (Sec. 4, Eq. (R_eff)), [14] dW_H/dt = gamma sum v.u_p and
- * [15] dW_E/dt = sum F_drive.v (Sec. 4, translocation work), [16..21] wall
- * momentum ledgers (not tracked on the device: NaN), [22] step count,
- * [23] and [24] the viscous drag along the wall normal, m gamma (u_p - v)
- * summed over the untranslocated and the translocated beads (Sec. 4, the
- * drag forces on the two parts).  Sums are FP64. */
-int lb_observables(lb_ctx* ctx, double* out_dev);
+ * [15] dW_E/dt = sum F_drive.v (Sec. 4, translocation work), [16..18] the
+ * momentum the wall has taken by bounce-back since lb_init, sum over steps
+ * and links (x, i) with x - c_i solid of 2 f_opp(i)(x) c_opp(i), and
+ * [19..21] the bead impulse the spreading dropped on solid nodes since
+ * lb_init, sum of W_k J_p over solid corners (the two wall terms of the
+ * bead-fluid momentum balance, Sec. 2, Eq. (momentum_cons)), [22] step
+ * count, [23] and [24] the viscous drag along the wall normal, m gamma
+ * (u_p - v) summed over the untranslocated and the translocated beads
+ * (Sec. 4, the drag forces on the two parts).  Sums are FP64. */
+int lb_observables(lb_ctx* ctx, double* out_dev, int which_mask);
 
 /* Checkpoint: copies the current populations (every replica, the storage
- * type), r and v of every bead slot, the step counter (uint64) and the
- * translocation steps to dst_dev (device, lb_sizes.state_bytes) / restores
+ * type), r and v of every bead slot, the step counter (uint64), the
+ * translocation steps and the wall ledgers to dst_dev (device, lb_sizes.state_bytes) / restores
  * them from src_dev.  Device to device, enqueued on the stream;
  * lb_set_state synchronises it to read back the step counter. */
 int lb_get_state(lb_ctx* ctx, void* dst_dev);

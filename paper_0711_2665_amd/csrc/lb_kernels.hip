@@ -351,7 +351,7 @@ __global__ void k_step_tick(Dev d, int nrep, int with_beads) {
 // tile, then per replica the partials are summed in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
-__global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, Dev d) {
+__global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, Dev d, double* __restrict__ part) {
   constexpr int tile_nodes = OBS_TILE;
   __shared__ double sh[4][256];
   const Tile tl = d.otiles[blockIdx.x];
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, Dev
       for (int a = 0; a < 4; ++a) sh[a][threadIdx.x] += sh[a][threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x < 4) d.part[4 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x < 4) part[4 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Block-wide sum of 256 values (fixed tree order); every thread gets it.
@@ -400,8 +400,11 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // Observables of replica blockIdx.x (one block of 256 threads per replica),
-// out[NOBS * r + k] in the order documented in lbmd.h.
-__global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__ out) {
+// out[NOBS * r + k] in the order documented in lbmd.h, for the groups in
+// mask (bit 0: fluid sums from part, 1: bead quantities, 2: wall ledgers,
+// 3: step count); other entries are not written.
+__global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__ out, int mask,
+                                                     const double* __restrict__ part) {
   __shared__ double sh[256];
   const int rep = blockIdx.x;
   const Rep& R = d.reps[rep];
@@ -410,11 +413,24 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
   const int t = threadIdx.x;
   const int nb = P.nb;
   const int so = R.slot_off;
-  double fl[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = R.tile_begin + t; k < R.tile_end; k += 256)
-    for (int a = 0; a < 4; ++a) fl[a] += d.part[4 * (size_t)k + a];
-  double tot[4];
-  for (int a = 0; a < 4; ++a) tot[a] = block_sum(fl[a], sh);
+  double* o = out + (size_t)NOBS * rep;
+  if (mask & 1) {
+    double fl[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = R.tile_begin + t; k < R.tile_end; k += 256)
+      for (int a = 0; a < 4; ++a) fl[a] += part[4 * (size_t)k + a];
+    double tot[4];
+    for (int a = 0; a < 4; ++a) tot[a] = block_sum(fl[a], sh);
+    if (t == 0) {
+      o[0] = R.nfluid + tot[0];
+      o[1] = tot[1]; o[2] = tot[2]; o[3] = tot[3];
+    }
+  }
+  if (t == 0) {
+    if (mask & 4)
+      for (int a = 0; a < NLEDGER; ++a) o[16 + a] = d.ledger[NLEDGER * rep + a];
+    if (mask & 8) o[22] = (double)d.ctrl->step;
+  }
+  if (!(mask & 2)) return;   // uniform in the block
   const int an = g.wall_axis >= 0 ? g.wall_axis : 2;
   double acc[14];
   for (int a = 0; a < 14; ++a) acc[a] = 0.0;
@@ -461,9 +477,6 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
   ru = block_sum(ru, sh);
   rt = block_sum(rt, sh);
   if (t == 0) {
-    double* o = out + (size_t)NOBS * rep;
-    o[0] = R.nfluid + tot[0];
-    o[1] = tot[1]; o[2] = tot[2]; o[3] = tot[3];
     o[4] = nb > 0 ? P.m * res[0] / (3.0 * nb) : 0.0;
     o[5] = res[1]; o[6] = res[2]; o[7] = res[3];
     o[8] = nb > 0 ? res[4] / nb : 0.0;
@@ -474,9 +487,85 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
     o[11] = RU; o[12] = RT;
     o[13] = pow(pow(RT, 0.6) + pow(RU, 0.6), 1.0 / 0.6);
     o[14] = res[8]; o[15] = res[7];
-    for (int a = 16; a < 22; ++a) o[a] = __builtin_nan("");
-    o[22] = (double)d.ctrl->step;
     o[23] = res[12]; o[24] = res[13];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wall momentum ledgers (the momentum the wall takes, for the bead-fluid
+// momentum balance of Sec. 2, Eq. (momentum_cons), with walls).
+// Bounce-back: the population f_opp(i)(x) that leaves fluid node x towards a
+// solid upstream node x - c_i returns as f_i(x), so the wall takes
+// 2 f_opp(i)(x) c_opp(i); f from the post-collision array A the step pulls
+// from (f = A + w_i in deviation storage).  Block b of the wall-link list
+// sums its entries (fixed tree order) into lpart[3 b + a]; k_ledger_sum
+// then adds each replica's blocks in order to its cumulative ledger.
+// ---------------------------------------------------------------------------
+template <typename T, bool DEV>
+__global__ __launch_bounds__(LEDGER_BLOCK) void k_ledger_bb(const T* __restrict__ A, Dev d) {
+  __shared__ double sh[LEDGER_BLOCK];
+  const WallLink e = d.wlinks[(size_t)blockIdx.x * LEDGER_BLOCK + threadIdx.x];
+  double s[3] = {0.0, 0.0, 0.0};
+  if (e.mask) {
+    const Rep& R = d.reps[e.rep];
+    const size_t N = (size_t)R.lp.N;
+    const T* Ar = A + (size_t)Q * R.node_off;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (!((e.mask >> i) & 1u)) continue;
+      const int o = opp(i);
+      double f = (double)Ar[(size_t)o * N + (size_t)e.node];
+      if (DEV) f += wgt(o);
+      const double f2 = 2.0 * f;
+      s[0] += f2 * (double)cx(o);
+      s[1] += f2 * (double)cy(o);
+      s[2] += f2 * (double)cz(o);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double v = block_sum(s[a], sh);
+    if (threadIdx.x == 0) d.lpart[3 * (size_t)blockIdx.x + a] = v;
+  }
+}
+
+// One thread per replica: the step's bounce-back momentum, summed over the
+// replica's blocks in order, added to its ledger.
+__global__ void k_ledger_sum(Dev d, int nrep) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrep) return;
+  const Rep& R = d.reps[r];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = R.wl_begin; b < R.wl_end; ++b)
+    for (int a = 0; a < 3; ++a) s[a] += d.lpart[3 * (size_t)b + a];
+  for (int a = 0; a < 3; ++a) d.ledger[NLEDGER * r + a] += s[a];
+}
+
+// Spread-on-solid: the share W_k J_p of the step's impulse that the
+// spreading drops because corner k of bead p is solid.  One block per
+// replica; beads strided over the threads, then a fixed-order tree sum.
+__global__ __launch_bounds__(256) void k_ledger_sp(Dev d) {
+  __shared__ double sh[256];
+  const int rep = blockIdx.x;
+  const Rep& R = d.reps[rep];
+  const Geom& g = R.g;
+  const uint8_t* fr = d.flags + R.node_off;
+  double s[3] = {0.0, 0.0, 0.0};
+  if (g.wall_axis >= 0) {
+    for (int p = threadIdx.x; p < R.mp.nb; p += 256) {
+      const int slot = R.slot_off + p;
+      const double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
+      const Stencil st = make_stencil(g, rp);
+      for (int k = 0; k < 8; ++k) {
+        if (!corner_used(g, st, k)) continue;
+        if (!(fr[corner_node(g, st, k)] & F_SOLID)) continue;
+        const double W = corner_weight(st, k);
+        for (int a = 0; a < 3; ++a) s[a] += W * d.J[3 * slot + a];
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const double v = block_sum(s[a], sh);
+    if (threadIdx.x == 0) d.ledger[NLEDGER * rep + 3 + a] += v;
   }
 }
 
@@ -559,9 +648,22 @@ void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_
 }
 
 template <typename T, bool DEV>
-void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s) {
-  hipLaunchKernelGGL((k_fluid_sums<T, DEV>), dim3((unsigned)n_otiles), dim3(256), 0, s, (const T*)A, d);
-  hipLaunchKernelGGL(k_observables, dim3((unsigned)nrep), dim3(256), 0, s, d, out);
+void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, int mask, double* part,
+                        hipStream_t s) {
+  if ((mask & 1) && n_otiles > 0)
+    hipLaunchKernelGGL((k_fluid_sums<T, DEV>), dim3((unsigned)n_otiles), dim3(256), 0, s, (const T*)A, d, part);
+  hipLaunchKernelGGL(k_observables, dim3((unsigned)nrep), dim3(256), 0, s, d, out, mask, (const double*)part);
+}
+
+template <typename T, bool DEV>
+void launch_ledger_bb(const void* A, const Dev& d, int nblk, int nrep, hipStream_t s) {
+  if (nblk <= 0) return;
+  hipLaunchKernelGGL((k_ledger_bb<T, DEV>), dim3((unsigned)nblk), dim3(LEDGER_BLOCK), 0, s, (const T*)A, d);
+  hipLaunchKernelGGL(k_ledger_sum, dim3(blocks_for(nrep, 64)), dim3(64), 0, s, d, nrep);
+}
+
+void launch_ledger_sp(const Dev& d, int nrep, hipStream_t s) {
+  hipLaunchKernelGGL(k_ledger_sp, dim3((unsigned)nrep), dim3(256), 0, s, d);
 }
 
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);
@@ -576,7 +678,10 @@ template void launch_spread<double>(const Dev&, int, hipStream_t);
 template void launch_spread_lb<double, false>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_spread_lb<float, true>(const void*, void*, const Dev&, int, hipStream_t);
 template void launch_spread<float>(const Dev&, int, hipStream_t);
-template void launch_observables<double, false>(const void*, const Dev&, int, int, double*, hipStream_t);
-template void launch_observables<float, true>(const void*, const Dev&, int, int, double*, hipStream_t);
+template void launch_observables<double, false>(const void*, const Dev&, int, int, double*, int, double*,
+                                                hipStream_t);
+template void launch_observables<float, true>(const void*, const Dev&, int, int, double*, int, double*, hipStream_t);
+template void launch_ledger_bb<double, false>(const void*, const Dev&, int, int, hipStream_t);
+template void launch_ledger_bb<float, true>(const void*, const Dev&, int, int, hipStream_t);
 
 }  // namespace lbmd

@@ -65,7 +65,17 @@ struct Packing {
   int slots_alloc = 1;              // slots, at least 1 (array sizing)
   long sweep_tiles_max = 0;         // tiles of the sweep at TILE_MIN
   long obs_tiles = 0;
+  long wl_blocks_max = 0;           // wall-link list blocks (LEDGER_BLOCK entries each), upper bound
 };
+
+// Fluid nodes with a solid upstream neighbour lie in the three planes around
+// the wall (|c_i| <= 1 along the normal), so their count is at most three
+// plane areas.
+long wall_link_bound(const lb_desc& d) {
+  if (d.wall_axis < 0) return 0;
+  const long area = (long)d.nx * d.ny * d.nz / (d.wall_axis == 0 ? d.nx : (d.wall_axis == 1 ? d.ny : d.nz));
+  return 3 * area;
+}
 
 Packing packing(const lb_desc* d, int nrep) {
   Packing pk;
@@ -77,6 +87,7 @@ Packing packing(const lb_desc* d, int nrep) {
     pk.slots += (int)round_up(d[r].nb, MD_BPB);
     pk.sweep_tiles_max += (N + TILE_MIN - 1) / TILE_MIN;
     pk.obs_tiles += (N + OBS_TILE - 1) / OBS_TILE;
+    pk.wl_blocks_max += (wall_link_bound(d[r]) + LEDGER_BLOCK - 1) / LEDGER_BLOCK;
   }
   pk.slots_alloc = pk.slots > 0 ? pk.slots : 1;
   return pk;
@@ -84,7 +95,7 @@ Packing packing(const lb_desc* d, int nrep) {
 
 struct WorkLayout {
   size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
-      tX, notdone, ccount, cbuf, rbin, cst;
+      tX, notdone, ccount, cbuf, rbin, cst, wlinks, ledger, lpart;
   size_t nbuckets;
   size_t total;
 };
@@ -120,6 +131,9 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   w.cbuf = take(sizeof(int) * CELL_CAP * w.nbuckets);
   w.rbin = take(sizeof(double) * 3 * ns);
   w.cst = take(sizeof(uint32_t) * 4 * R);
+  w.wlinks = take(sizeof(WallLink) * LEDGER_BLOCK * (size_t)pk.wl_blocks_max);
+  w.ledger = take(sizeof(double) * NLEDGER * R);
+  w.lpart = take(sizeof(double) * 3 * (size_t)(pk.wl_blocks_max > 0 ? pk.wl_blocks_max : 1));
   w.total = o;
   return w;
 }
@@ -129,7 +143,7 @@ size_t elem_size(const lb_desc* d) { return d->precision == LB_FP64 ? sizeof(dou
 // Byte layout of the state buffer: populations, then r and v of every slot,
 // then the step counter, then the per-replica translocation steps.
 struct StateLayout {
-  size_t pops, r, v, step, tX, total;
+  size_t pops, r, v, step, tX, ledger, total;
 };
 StateLayout state_layout(const lb_desc* d, int nrep, const Packing& pk) {
   StateLayout s;
@@ -140,6 +154,7 @@ StateLayout state_layout(const lb_desc* d, int nrep, const Packing& pk) {
   s.v = take(sizeof(double) * 3 * (size_t)pk.slots_alloc);
   s.step = take(sizeof(uint64_t));
   s.tX = take(sizeof(int64_t) * (size_t)nrep);
+  s.ledger = take(sizeof(double) * NLEDGER * (size_t)nrep);
   s.total = o;
   return s;
 }
@@ -179,6 +194,9 @@ int validate_one(const lb_desc* d, int r) {
   if (d->nb > 0) {
     if (!(d->mass > 0.0)) return fail(LB_ERR_ARG, "replica %d: bead mass must be positive", r);
     if (!(d->gamma >= 0.0) || !(d->kT >= 0.0)) return fail(LB_ERR_ARG, "replica %d: gamma and kT must be >= 0", r);
+    if (d->gamma > 0.0 && d->mass != 1.0)
+      return fail(LB_ERR_ARG, "replica %d: a chain coupled with gamma > 0 needs mass 1 (the kick's drift towards the "
+                              "fluid is (1 - e) u / m, while the impulse the fluid takes is m (1 - e)(u - v))", r);
     if (!(d->rc > 0.0) || d->rc > 3.0) return fail(LB_ERR_ARG, "replica %d: rc must lie in (0, 3]", r);
     if (!(d->sigma > 0.0)) return fail(LB_ERR_ARG, "replica %d: sigma must be positive", r);
     if ((long)d->nb > (1L << 24)) return fail(LB_ERR_ARG, "replica %d: too many beads", r);
@@ -280,8 +298,9 @@ void fluid_noise_params(LbParams& lp, const lb_desc& d) {
 }
 
 // Solid / near-wall flags of one replica (Sec. 4: wall plane with a square
-// pore); returns the number of fluid nodes.
-long build_flags(const Geom& g, uint8_t* fl) {
+// pore); returns the number of fluid nodes.  Appends the replica's fluid
+// nodes with solid upstream neighbours, in node order, to links.
+long build_flags(const Geom& g, uint8_t* fl, int rep, std::vector<WallLink>& links) {
   long nfluid = 0;
   for (int z = 0; z < g.nz; ++z)
     for (int y = 0; y < g.ny; ++y)
@@ -293,8 +312,13 @@ long build_flags(const Geom& g, uint8_t* fl) {
         size_t cidx = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
         if (fl[cidx] & F_SOLID) continue;
         ++nfluid;
+        uint32_t mask = 0u;
         for (int i = 1; i < Q; ++i)
-          if (site_solid(g, x - cx(i), y - cy(i), z - cz(i))) { fl[cidx] |= F_NEAR; break; }
+          if (site_solid(g, x - cx(i), y - cy(i), z - cz(i))) mask |= 1u << i;
+        if (mask) {
+          fl[cidx] |= F_NEAR;
+          links.push_back(WallLink{rep, (int)cidx, mask, 0});
+        }
       }
   return nfluid;
 }
@@ -333,6 +357,7 @@ struct lb_ctx {
   bool noise_ready = false;  // the noise slot of the current population parity holds this step's noise
   SweepCfg sweep;
   int ntiles = 0;
+  int wl_blocks = 0;         // blocks of the wall-link list (bounce-back ledger)
   int64_t steps = 0;
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
@@ -441,6 +466,12 @@ void ensure_lists(lb_ctx* c, hipStream_t st) {
   c->lists_stale = false;
 }
 
+// The bounce-back ledger of a step that pulls from A, on stream st.
+void ledger_bb(lb_ctx* c, const void* A, hipStream_t st) {
+  if (c->dev) launch_ledger_bb<float, true>(A, c->D, c->wl_blocks, c->nrep, st);
+  else launch_ledger_bb<double, false>(A, c->D, c->wl_blocks, c->nrep, st);
+}
+
 // One fluid-only step on stream st.
 void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
   c->noise_ready = false;
@@ -449,6 +480,7 @@ void enqueue_lb_step(lb_ctx* c, hipStream_t st) {
   prof_mark(c, 2, st);
   sweep(c, 0, st);
   prof_mark(c, 3, st);
+  ledger_bb(c, cur_pops(c), st);
   launch_step_end(c->D, 0, 0, c->nrep, st);
   c->cur ^= 1;
   prof_next(c);
@@ -473,8 +505,10 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   prof_mark(c, 2, c->s2);
   sweep_ab(c, A, B, 1, c->s2);
   prof_mark(c, 3, c->s2);
-  // the next step's noise, into the other slot, after the sweep: off the
-  // bead stream's path
+  // the wall's bounce-back momentum of this step (reads A, which no kernel
+  // of this step writes), and the next step's noise, into the other slot,
+  // after the sweep: off the bead stream's path
+  ledger_bb(c, A, c->s2);
   if (c->any_noise) launch_md_noise(with_noise_slot(c, c->cur ^ 1), c->nslots, c->n_sub, 1, c->s2);
   // long chains: the lists of this step were built at the end of the
   // previous one (beside the spreading), unless the positions changed since
@@ -487,15 +521,18 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   MdOverride none{};
   if (c->mts > 0) launch_md_cycle_mts(D, c->nslots, c->nrep, c->n_sub, c->mts, sb, false);
   else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb, false, c->any_constrained);
-  if (c->step_lists) acc(hipEventRecord(c->mdone, sb));
+  acc(hipEventRecord(c->mdone, sb));
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
   prof_mark(c, 1, sb);
+  // on the sweep stream (done by now) once J is final, beside the
+  // spreading, which writes none of their arrays, and enqueued after it so
+  // that a replayed graph issues the spreading first: the share of the
+  // impulse that falls on solid nodes; for long chains the next step's
+  // lists from r(n+1)
+  acc(hipStreamWaitEvent(c->s2, c->mdone, 0));
+  launch_ledger_sp(D, c->nrep, c->s2);
   if (c->step_lists) {
-    // the next step's lists from r(n+1), on the sweep stream (done by now)
-    // beside the spreading, which touches none of their arrays; enqueued
-    // after the spreading so that a replayed graph issues that first
-    acc(hipStreamWaitEvent(c->s2, c->mdone, 0));
     launch_nbr_build(D, c->nslots, c->nrep, c->s2);
     c->lists_stale = false;
   }
@@ -547,6 +584,20 @@ int build_graph(lb_ctx* c) {
   c->capturing = false;
   c->cur = cur0;
   int rc = take_acc("graph capture");
+  // every stream the steps forked joined back before the end of the capture:
+  // none of them may still be capturing (work enqueued on it later would
+  // otherwise belong to a graph that no longer exists)
+  if (!rc && e2 == hipSuccess) {
+    for (hipStream_t side : {c->s1, c->s2}) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      hipError_t e3 = hipStreamIsCapturing(side, &cs);
+      if (e3 != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        rc = fail(LB_ERR_DEVICE, "graph capture: a forked stream is still capturing (%s)",
+                  e3 != hipSuccess ? hipGetErrorString(e3) : "status not none");
+        break;
+      }
+    }
+  }
   if (e2 != hipSuccess || rc) {
     if (g) (void)hipGraphDestroy(g);
     return rc ? rc : fail(LB_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e2));
@@ -620,6 +671,8 @@ void restore_state(lb_ctx* c, const char* st, void* dst_pops) {
   acc(hipMemcpyAsync(c->D.v, st + c->sl.v, nb3, hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(&c->D.ctrl->step, st + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(c->D.tX, st + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->D.ledger, st + c->sl.ledger, sizeof(double) * NLEDGER * c->nrep, hipMemcpyDeviceToDevice,
+                     c->s));
   launch_md_invalidate(c->D, c->nrep, c->s);
   c->lists_stale = true;
   c->noise_ready = false;
@@ -644,6 +697,7 @@ int lb_ensemble_sizes(const lb_desc* d, int nrep, lb_sizes* out) {
   out->beads_bytes = align256(sizeof(double) * 15 * (size_t)pk.slots_alloc);
   out->work_bytes = work_layout(d, nrep, pk).total;
   out->state_bytes = state_layout(d, nrep, pk).total;
+  out->snapshot_bytes = out->pops_bytes + out->force_bytes + out->beads_bytes + align256(out->work_bytes);
   out->nodes = (size_t)pk.nodes;
   out->bead_slots = (size_t)pk.slots_alloc;
   return LB_OK;
@@ -706,6 +760,7 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   std::vector<uint8_t> fl((size_t)nodes, F_SOLID);   // alignment padding is solid
   std::vector<int> slot_rep(ns, 0);
   std::vector<Tile> ot;
+  std::vector<WallLink> links;
   c->reps.resize(nrep);
   for (int r = 0; r < nrep; ++r) {
     Rep& R = c->reps[r];
@@ -725,7 +780,10 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
     R.slot_off = c->pk.slot_off[r];
     R.nslot = (int)round_up(d[r].nb, MD_BPB);
     for (int k = 0; k < R.nslot; ++k) slot_rep[(size_t)R.slot_off + k] = r;
-    R.nfluid = (double)build_flags(R.g, fl.data() + R.node_off);
+    R.wl_begin = (int)(links.size() / LEDGER_BLOCK);
+    R.nfluid = (double)build_flags(R.g, fl.data() + R.node_off, r, links);
+    while (links.size() % LEDGER_BLOCK) links.push_back(WallLink{r, 0, 0u, 0});
+    R.wl_end = (int)(links.size() / LEDGER_BLOCK);
     {
       const int n[3] = {d[r].nx, d[r].ny, d[r].nz};
       const double side = d[r].rc + skin + CELL_MARGIN;
@@ -770,12 +828,23 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   D.cst = (uint32_t*)(w + c->wl.cst);
   D.cmask = (uint32_t)(c->wl.nbuckets - 1);
   D.ctrl = (Ctrl*)(w + c->wl.ctrl);
+  D.wlinks = (const WallLink*)(w + c->wl.wlinks);
+  D.ledger = (double*)(w + c->wl.ledger);
+  D.lpart = (double*)(w + c->wl.lpart);
+  c->wl_blocks = (int)(links.size() / LEDGER_BLOCK);
+  if ((long)c->wl_blocks > c->pk.wl_blocks_max) {
+    lb_destroy(c);
+    return fail(LB_ERR_ARG, "internal: wall-link list exceeds its bound");
+  }
 
   hipStream_t s = c->s;
   acc(hipMemcpyAsync(b->flags, fl.data(), (size_t)nodes, hipMemcpyHostToDevice, s));
   acc(hipMemcpyAsync(w + c->wl.reps, c->reps.data(), sizeof(Rep) * nrep, hipMemcpyHostToDevice, s));
   acc(hipMemcpyAsync(w + c->wl.otiles, ot.data(), sizeof(Tile) * ot.size(), hipMemcpyHostToDevice, s));
   acc(hipMemcpyAsync(w + c->wl.slot_rep, slot_rep.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
+  if (!links.empty())
+    acc(hipMemcpyAsync(w + c->wl.wlinks, links.data(), sizeof(WallLink) * links.size(), hipMemcpyHostToDevice, s));
+  launch_fill_f64(D.ledger, (long)NLEDGER * nrep, 0.0, s);
   // rest populations, replica by replica ([19][N_r] from element 19 node_off)
   for (int r = 0; r < nrep; ++r) {
     const size_t off = elem_size(d) * Q * (size_t)c->reps[r].node_off;
@@ -960,11 +1029,13 @@ int md_relax(lb_ctx* c, int nsub_total, double gamma_relax) {
   return check_hip("md_relax");
 }
 
-int lb_observables(lb_ctx* c, double* out_dev) {
+int lb_observables(lb_ctx* c, double* out_dev, int which_mask) {
   if (!c || !out_dev) return fail(LB_ERR_ARG, "bad arguments");
+  if (which_mask & ~LB_OBS_ALL) return fail(LB_ERR_ARG, "unknown observable group in the mask 0x%x", which_mask);
+  if (!which_mask) return LB_OK;
   const int no = (int)c->pk.obs_tiles;
-  if (c->dev) launch_observables<float, true>(cur_pops(c), c->D, no, c->nrep, out_dev, c->s);
-  else launch_observables<double, false>(cur_pops(c), c->D, no, c->nrep, out_dev, c->s);
+  if (c->dev) launch_observables<float, true>(cur_pops(c), c->D, no, c->nrep, out_dev, which_mask, c->D.part, c->s);
+  else launch_observables<double, false>(cur_pops(c), c->D, no, c->nrep, out_dev, which_mask, c->D.part, c->s);
   return check_hip("lb_observables");
 }
 
@@ -978,6 +1049,8 @@ int lb_get_state(lb_ctx* c, void* dst) {
   acc(hipMemcpyAsync(o + c->sl.v, c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(o + c->sl.step, &c->D.ctrl->step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(o + c->sl.tX, c->D.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(o + c->sl.ledger, c->D.ledger, sizeof(double) * NLEDGER * c->nrep, hipMemcpyDeviceToDevice,
+                     c->s));
   return check_hip("lb_get_state");
 }
 
@@ -991,6 +1064,8 @@ int lb_set_state(lb_ctx* c, const void* src) {
   acc(hipMemcpyAsync(c->D.v, o + c->sl.v, nb3, hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(&c->D.ctrl->step, o + c->sl.step, sizeof(uint64_t), hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(c->D.tX, o + c->sl.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToDevice, c->s));
+  acc(hipMemcpyAsync(c->D.ledger, o + c->sl.ledger, sizeof(double) * NLEDGER * c->nrep, hipMemcpyDeviceToDevice,
+                     c->s));
   launch_md_invalidate(c->D, c->nrep, c->s);
   c->lists_stale = true;
   c->noise_ready = false;
@@ -1085,8 +1160,9 @@ std::vector<SweepCfg> sweep_candidates() {
 }
 
 // Device copy of everything a coupled step reads or writes (current
-// populations, beads, work area, force field) and the host fields that
-// follow it, so that timed trial steps leave no trace.
+// populations, beads, work area, force field), in a buffer of the caller,
+// and the host fields that follow it, so that timed trial steps leave no
+// trace.
 struct Snapshot {
   char* mem = nullptr;
   size_t pops = 0, beads = 0, work = 0, force = 0;
@@ -1096,14 +1172,19 @@ struct Snapshot {
   bool noise_ready = false;
 };
 
-int snapshot_take(lb_ctx* c, Snapshot& S) {
+size_t snapshot_bytes(const lb_ctx* c) {
+  const size_t es = c->dev ? sizeof(float) : sizeof(double);
+  return align256(es * Q * (size_t)c->pk.nodes) + align256(sizeof(double) * 15 * (size_t)c->pk.slots_alloc) +
+         align256(c->wl.total) + align256(es * 3 * (size_t)c->pk.nodes);
+}
+
+int snapshot_take(lb_ctx* c, Snapshot& S, char* mem) {
   const size_t es = c->dev ? sizeof(float) : sizeof(double);
   S.pops = align256(es * Q * (size_t)c->pk.nodes);
   S.beads = align256(sizeof(double) * 15 * (size_t)c->pk.slots_alloc);
   S.work = align256(c->wl.total);
   S.force = align256(es * 3 * (size_t)c->pk.nodes);
-  hipError_t e = hipMalloc((void**)&S.mem, S.pops + S.beads + S.work + S.force);
-  if (e != hipSuccess) { S.mem = nullptr; return fail(LB_ERR_DEVICE, "snapshot: %s", hipGetErrorString(e)); }
+  S.mem = mem;
   char* o = S.mem;
   acc(hipMemcpyAsync(o, cur_pops(c), S.pops, hipMemcpyDeviceToDevice, c->s));
   acc(hipMemcpyAsync(o + S.pops, c->b.beads, S.beads, hipMemcpyDeviceToDevice, c->s));
@@ -1139,7 +1220,7 @@ void snapshot_restore(lb_ctx* c, const Snapshot& S) {
 // the choice between layouts that perform alike) and caches it, with its
 // time, per packing, precision, sweep variant (athermal or fluctuating fluid)
 // and mode.
-int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms) {
+int tune_layout(lb_ctx* c, int reps, bool coupled, char* snap, size_t snap_bytes, int* out_cfg, double* out_ms) {
   if (!c || reps < 1) return fail(LB_ERR_ARG, "bad arguments");
   static std::map<std::string, std::pair<SweepCfg, double>> cache;
   std::string key = coupled ? "step:" : "sweep:";
@@ -1167,7 +1248,14 @@ int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms)
     const bool prof = c->prof_on;
     c->prof_on = false;
     Snapshot S;
-    int rc = coupled ? snapshot_take(c, S) : LB_OK;
+    int rc = LB_OK;
+    if (coupled) {
+      if (!snap || snap_bytes < snapshot_bytes(c) || ((uintptr_t)snap & 255))
+        rc = fail(LB_ERR_ARG, "snapshot buffer: need %zu bytes, 256-byte aligned (got %zu)", snapshot_bytes(c),
+                  snap_bytes);
+      else
+        rc = snapshot_take(c, S, snap);
+    }
     std::vector<double> times;
     for (size_t k = 0; k < cand.size() && !rc; ++k) {
       rc = upload_tiles(c, cand[k]);
@@ -1198,7 +1286,6 @@ int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms)
     if (S.mem) {
       if (rc) snapshot_restore(c, S);
       hipError_t e = hipStreamSynchronize(c->s);
-      (void)hipFree(S.mem);
       if (!rc && e != hipSuccess) rc = fail(LB_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
     }
     drop_graph(c);
@@ -1231,16 +1318,18 @@ int tune_layout(lb_ctx* c, int reps, bool coupled, int* out_cfg, double* out_ms)
 extern "C" {
 
 int lb_autotune(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
-  return tune_layout(c, reps, false, out_cfg, out_ms);
+  return tune_layout(c, reps, false, nullptr, 0, out_cfg, out_ms);
 }
 
-int lb_autotune_step(lb_ctx* c, int reps, int* out_cfg, double* out_ms) {
-  return tune_layout(c, reps, true, out_cfg, out_ms);
+int lb_autotune_step(lb_ctx* c, int reps, void* snap_dev, size_t snap_bytes, int* out_cfg, double* out_ms) {
+  return tune_layout(c, reps, true, (char*)snap_dev, snap_bytes, out_cfg, out_ms);
 }
 
 int lb_set_coupling(lb_ctx* c, int rep, double gamma, double f_drive) {
   if (!c || rep < 0 || rep >= c->nrep || !(gamma >= 0.0) || !std::isfinite(gamma) || !std::isfinite(f_drive))
     return fail(LB_ERR_ARG, "bad arguments");
+  if (gamma > 0.0 && c->d[rep].nb > 0 && c->d[rep].mass != 1.0)
+    return fail(LB_ERR_ARG, "a chain coupled with gamma > 0 needs mass 1");
   Rep& R = c->reps[rep];
   R.mp.f_drive = f_drive;
   spv_coefficients(R.mp, gamma, c->d[rep].kT, 1.0 / (double)c->n_sub);

@@ -56,6 +56,8 @@ struct Rep {
   int nslot;        // bead slots (multiple of MD_BPB)
   int tile_begin;   // reduction tiles [tile_begin, tile_end)
   int tile_end;
+  int wl_begin;     // bounce-back ledger blocks [wl_begin, wl_end) of the wall-link list
+  int wl_end;
   double nfluid;    // fluid nodes (for the mass observable)
   int ncell[3];     // neighbour-search cells per axis (side >= r_c + skin)
 };
@@ -64,6 +66,19 @@ struct Tile {
   int rep;
   int start;
 };
+
+// A fluid node with links to solid upstream nodes: bit i of mask is set when
+// x - c_i is solid (the population f_i(x) is then bounced back).  Entries of
+// one replica are contiguous and padded (mask 0) to a multiple of
+// LEDGER_BLOCK, so that every reduction block holds one replica.
+struct WallLink {
+  int rep;
+  int node;
+  uint32_t mask;
+  int pad;
+};
+constexpr int LEDGER_BLOCK = 256;
+constexpr int NLEDGER = 6;                   // per replica: bounce-back [3], spread-on-solid [3]
 
 // Every device array a kernel may touch.
 struct Dev {
@@ -105,6 +120,12 @@ struct Dev {
                     // from its binned position at that sub-step (the table is not usable)
   uint32_t cmask;   // buckets - 1 (a power of two minus one)
   Ctrl* ctrl;
+  // wall momentum ledgers (cumulative, FP64, per replica [NLEDGER]):
+  // momentum the wall took by bounce-back, bead reaction that fell on solid
+  // nodes; the wall-link list and one partial sum per list block
+  const WallLink* wlinks;
+  double* ledger;
+  double* lpart;
 };
 
 // MD coefficients that replace the replicas' own during the pre-relaxation
@@ -136,8 +157,19 @@ void launch_spread(const Dev& d, int nslots, hipStream_t s);
 template <typename T, bool DEV>
 void launch_spread_lb(const void* A, void* B, const Dev& d, int nslots, hipStream_t s);
 void launch_step_end(const Dev& d, int nslots, int maxlist, int nrep, hipStream_t s);
+// Observables into out[NOBS * r + k]; groups of the lb_observables mask
+// (bit 0 fluid sums, 1 bead quantities, 2 wall ledgers, 3 step count); the
+// entries of groups not asked for are left as they are.  part: the fluid
+// partial sums (n_otiles x 4 doubles).
 template <typename T, bool DEV>
-void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, hipStream_t s);
+void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, double* out, int mask, double* part,
+                        hipStream_t s);
+// Wall ledgers of one step: the bounce-back momentum of the links in the
+// wall-link list (from the populations A the step reads; nblk list blocks),
+// and the bead impulse of the step's spreading that falls on solid nodes.
+template <typename T, bool DEV>
+void launch_ledger_bb(const void* A, const Dev& d, int nblk, int nrep, hipStream_t s);
+void launch_ledger_sp(const Dev& d, int nrep, hipStream_t s);
 
 // Adjoint pass (one replica, chains of at most MAX_ADJ_BEADS beads).
 constexpr int MAX_ADJ_BEADS = 128;

@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(HERE, "liblbmd.so")
 LB_OK, LB_ERR_ARG, LB_ERR_DEVICE, LB_ERR_UNSTABLE, LB_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 LB_FP64, LB_FP32_DEV = 0, 1
 LB_NOBS = 25
+# groups of lb_observables' mask
+LB_OBS_FLUID, LB_OBS_BEADS, LB_OBS_LEDGERS, LB_OBS_STEP = 1, 2, 4, 8
+LB_OBS_ALL = 15
 Q = 19
 # The population order of the library's storage (documented in the header):
 # rest, +-x, +-y, +-z, then the xy, xz and yz diagonals, opposites adjacent.
@@ -27,7 +30,7 @@ WEIGHTS = (1.0 / 3.0,) + (1.0 / 18.0,) * 6 + (1.0 / 36.0,) * 12
 
 OBS_NAMES = ["mass", "px", "py", "pz", "T_beads", "bpx", "bpy", "bpz", "mean_normal", "translocated",
              "N_r", "R_U", "R_T", "R_eff", "dWH_dt", "dWE_dt", "wall_bb_x", "wall_bb_y", "wall_bb_z",
-             "wall_sp_x", "wall_sp_y", "wall_sp_z", "step"]
+             "wall_sp_x", "wall_sp_y", "wall_sp_z", "step", "drag_U", "drag_T"]
 
 
 class LbDesc(C.Structure):
@@ -45,7 +48,7 @@ class LbDesc(C.Structure):
 
 class LbSizes(C.Structure):
     _fields_ = [(n, C.c_size_t) for n in ("pops_bytes", "flags_bytes", "force_bytes", "beads_bytes",
-                                          "work_bytes", "state_bytes", "nodes", "bead_slots")]
+                                          "work_bytes", "state_bytes", "nodes", "bead_slots", "snapshot_bytes")]
 
 
 class LbBuffers(C.Structure):
@@ -90,14 +93,14 @@ def _declare(L):
     L.lb_ensemble_translocation.argtypes = [P, C.POINTER(C.c_int64)]
     L.lb_sweep_config.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
     L.lb_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
-    L.lb_autotune_step.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.lb_autotune_step.argtypes = [P, C.c_int, P, C.c_size_t, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.md_relax.argtypes = [P, C.c_int, C.c_double]
     L.lb_set_coupling.argtypes = [P, C.c_int, C.c_double, C.c_double]
     L.lb_adjoint_sizes.argtypes = [P, C.c_int, C.c_int, C.POINTER(C.c_size_t)]
     L.lb_adjoint_forward.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t]
     L.lb_adjoint_backward.argtypes = [P, P, P, P]
     L.lb_adjoint_run.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t, P, P]
-    L.lb_observables.argtypes = [P, P]
+    L.lb_observables.argtypes = [P, P, C.c_int]
     L.lb_get_state.argtypes = [P, P]
     L.lb_set_state.argtypes = [P, P]
     L.lb_current_pops.argtypes = [P]
@@ -304,8 +307,14 @@ class Context:
         of the state that is restored afterwards)."""
         cfg = (C.c_int * 4)()
         ms = C.c_double()
-        fn = lib().lb_autotune_step if coupled else lib().lb_autotune
-        _raise(fn(self.ctx, int(reps), cfg, C.byref(ms)))
+        if coupled:
+            # the snapshot buffer the library fills and restores from
+            n = int(self.sizes["snapshot_bytes"])
+            snap = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+            _raise(lib().lb_autotune_step(self.ctx, int(reps), C.c_void_p(snap.data_ptr()), n, cfg, C.byref(ms)))
+            del snap
+        else:
+            _raise(lib().lb_autotune(self.ctx, int(reps), cfg, C.byref(ms)))
         return dict(tile_nodes=cfg[0], order=cfg[1], grid=cfg[2], cap=cfg[3], ms=ms.value)
 
     def translocation_steps(self):
@@ -364,9 +373,11 @@ class Context:
             out[name] = b[3 * ns * k + 3 * o: 3 * ns * k + 3 * (o + nb)].view(nb, 3)
         return out
 
-    def observables(self):
-        """[nrep, LB_NOBS] float64 on the device (see lb_observables)."""
-        _raise(lib().lb_observables(self.ctx, C.c_void_p(self._obs.data_ptr())))
+    def observables(self, mask=LB_OBS_ALL):
+        """[nrep, LB_NOBS] float64 on the device (see lb_observables); the
+        groups outside mask are NaN."""
+        self._obs.fill_(float("nan"))
+        _raise(lib().lb_observables(self.ctx, C.c_void_p(self._obs.data_ptr()), int(mask)))
         return self._obs.view(self.nrep, LB_NOBS)
 
     def get_state(self):
@@ -389,8 +400,8 @@ class Simulation(Context):
         self.shape = self.shapes[0]
         self.N = self.Ns[0]
 
-    def observables(self):
-        return super().observables()[0]
+    def observables(self, mask=LB_OBS_ALL):
+        return super().observables(mask)[0]
 
 
 class Ensemble(Context):

@@ -71,6 +71,7 @@ def test_desc_layout_matches_header(tmp_path):
     (dict(n_sub=0), "n_sub"),
     (dict(nb=-1), "negative"),
     (dict(nb=3, mass=0.0), "mass"),
+    (dict(nb=3, mass=2.0, gamma=0.1), "mass 1"),
     (dict(nb=3, rc=3.5), "rc"),
     (dict(nb=3, wall_axis=2, wall_pos=2, shape=(16, 5, 8)), "extents >= 6"),
     (dict(shape=(1024, 1024, 128)), "too large"),
@@ -95,6 +96,16 @@ def test_host_validation(bad, msg):
     assert msg in str(e.value)
 
 
+def test_unit_mass_needed_only_with_friction():
+    # the exponential kick's friction term is exact only at unit mass; an
+    # uncoupled chain (gamma = 0) may carry any positive mass
+    from paper_0711_2665_amd import lbmd
+    from paper_0711_2665_amd.workloads import BASE
+    cfg = dict(BASE)
+    cfg.update(shape=(16, 16, 16), wall_axis=-1, wall_pos=0, pore_h=0, nb=3, mass=2.0, gamma=0.0)
+    lbmd.buffer_sizes(cfg)
+
+
 def test_buffer_sizes_are_aligned_and_exact():
     from paper_0711_2665_amd import lbmd
     from paper_0711_2665_amd.workloads import C3
@@ -104,6 +115,7 @@ def test_buffer_sizes_are_aligned_and_exact():
     assert s["flags_bytes"] == N
     assert all(v % 256 == 0 for k, v in s.items() if k.endswith("_bytes"))
     assert s["nodes"] == N and s["bead_slots"] == 8000
+    assert s["snapshot_bytes"] >= s["pops_bytes"] + s["force_bytes"] + s["beads_bytes"] + s["work_bytes"]
     s64 = lbmd.buffer_sizes(C3, lbmd.LB_FP64)
     assert s64["pops_bytes"] == 19 * N * 8
 

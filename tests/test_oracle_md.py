@@ -307,6 +307,29 @@ def test_momentum_ledger_with_walls(orc):
     assert np.abs(total(P1) - total(P0)).max() < 5e-11
 
 
+def test_momentum_ledger_with_beads_on_the_wall(orc):
+    """The spread-on-solid term of the ledger: without bead LJ (so no wall
+    force) and without field, beads straddling the solid part of the wall
+    drop part of their impulse on solid nodes; fluid + beads + both wall
+    ledgers still conserve momentum."""
+    cfg = scaled(C0, shape=(16, 16, 16), wall_pos=8, nb=6, n_sub=50, f_drive=0.0, kT=1e-3, eps=0.0)
+    r = np.array([[2.3 + 0.9 * k, 3.4, 7.6 + 0.12 * k] for k in range(6)])
+    rng = np.random.default_rng(6)
+    o = orc.Oracle(cfg, r, 0.05 * rng.standard_normal(r.shape))
+    P0 = o.observables()
+    o.couple_step(40)
+    P1 = o.observables()
+
+    def total(P):
+        return P[1:4] + P[5:8] + P[16:19] + P[19:22]
+
+    assert np.abs(P1[19:22]).max() > 1e-6                 # impulse fell on the wall
+    assert np.abs(total(P1) - total(P0)).max() < 5e-11
+    # without the spread-on-solid term the balance fails by that term
+    part = P1[1:4] + P1[5:8] + P1[16:19] - (P0[1:4] + P0[5:8] + P0[16:19])
+    assert np.abs(part).max() > 1e-7
+
+
 # -- P13: equipartition of free beads under the OU kick: starting from rest,
 #    <v_a^2> = kT/m (1 - exp(-2 gamma t)) exactly in expectation
 
