@@ -410,7 +410,7 @@ struct Sim {
     // A_opp(i)(x) into the wall and came back as f_i(x): the wall took
     // 2 A_opp(i)(x) c_opp(i).  Summed per z plane, then over planes in order.
     std::vector<R> plane_ledger((size_t)3 * nz, R(0.0));
-#pragma omp parallel for schedule(static) if (std::is_same<R, double>::value)
+#pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z) {
       R f[Q], out[Q], Fx[3];
       for (int y = 0; y < ny; ++y)
@@ -1271,6 +1271,28 @@ int or_jvp(const or_desc* d, const double* r0, const double* v0, int nsteps, con
   L = L / Dual((double)d->nb);
   out[0] = L.v;
   out[1] = L.d;
+  return 0;
+}
+
+// As or_jvp, recording L and its derivative after every step: out[2 k],
+// out[2 k + 1] after step k + 1 (k < nsteps).
+int or_jvp_series(const or_desc* d, const double* r0, const double* v0, int nsteps, const double* dr0,
+                  double dgamma, double dfdrive, double* out) {
+  if (!d || d->nb <= 0 || d->wall_axis < 0) return -1;
+  Sim<Dual> s;
+  s.init(*d, r0, v0);
+  for (int k = 0; k < 3 * d->nb; ++k) s.r[k] = Dual(r0[k], dr0 ? dr0[k] : 0.0);
+  s.gamma = Dual(d->gamma, dgamma);
+  s.fdrive = Dual(d->f_drive, dfdrive);
+  s.set_spv_coefficients(s.gamma, d->kT);
+  for (int k = 0; k < nsteps; ++k) {
+    s.couple_step();
+    Dual L(0.0, 0.0);
+    for (int p = 0; p < d->nb; ++p) L += s.r[3 * p + d->wall_axis];
+    L = L / Dual((double)d->nb);
+    out[2 * k] = L.v;
+    out[2 * k + 1] = L.d;
+  }
   return 0;
 }
 

@@ -86,6 +86,8 @@ def _declare(L):
     L.or_md_only.argtypes = [_P, C.c_int, C.c_int]
     L.or_jvp.restype = C.c_int
     L.or_jvp.argtypes = [C.POINTER(OrDesc), _DP, _DP, C.c_int, _DP, C.c_double, C.c_double, _DP]
+    L.or_jvp_series.restype = C.c_int
+    L.or_jvp_series.argtypes = [C.POINTER(OrDesc), _DP, _DP, C.c_int, _DP, C.c_double, C.c_double, _DP]
 
 
 def _dp(a):
@@ -344,3 +346,16 @@ def jvp(cfg, r0, v0, nsteps, dr0=None, dgamma=0.0, dfdrive=0.0):
     if rc != 0:
         raise ValueError("jvp needs beads and a wall")
     return float(out[0]), float(out[1])
+
+
+def jvp_series(cfg, r0, v0, nsteps, dr0=None, dgamma=0.0, dfdrive=0.0):
+    """As jvp, after every step: arrays L[k], dL[k] after step k + 1."""
+    d = make_desc(cfg)
+    r0 = np.ascontiguousarray(r0, dtype=np.float64).reshape(-1)
+    v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1)
+    dr = None if dr0 is None else np.ascontiguousarray(dr0, dtype=np.float64).reshape(-1)
+    out = np.empty(2 * nsteps)
+    rc = lib().or_jvp_series(C.byref(d), _dp(r0), _dp(v0), nsteps, _dp(dr), dgamma, dfdrive, _dp(out))
+    if rc != 0:
+        raise ValueError("jvp needs beads and a wall")
+    return out[0::2].copy(), out[1::2].copy()
