@@ -368,6 +368,19 @@ int md_relax(lb_ctx* ctx, int nsub_total, double gamma_relax);
  * (Sec. 4, the drag forces on the two parts).  Sums are FP64. */
 int lb_observables(lb_ctx* ctx, double* out_dev, int which_mask);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * lb_observables, with the fluid reduction's partial sums in a static
+ * device array the library holds on each GPU for the life of the process
+ * (4 doubles per reduction tile of 4096 nodes, at most 16384 tiles, i.e.
+ * packed lattices of up to 67,108,864 nodes; 512 KiB), instead of the
+ * context's work buffer.  The caller still provides out_dev.  Allocates
+ * nothing.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (other streams, other threads) race and must be ordered by the
+ * caller.  LB_ERR_ARG: as lb_observables, or LB_OBS_FLUID asked for on a
+ * context whose packed lattice exceeds the limit. */
+int lb_observables_static(lb_ctx* ctx, double* out_dev, int which_mask);
+
 /* Checkpoint: copies the current populations (every replica, the storage
  * type), r and v of every bead slot, the step counter (uint64), the
  * translocation steps and the wall ledgers to dst_dev (device, lb_sizes.state_bytes) / restores

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,13 @@
 #include "lbmd_kernels.h"
 
 using namespace lbmd;
+
+// Partial sums of lb_observables_static's fluid reduction (4 doubles per
+// reduction tile of OBS_TILE nodes): device memory the library reserves for
+// callers that cannot allocate.  Each GPU holds its own copy for the life of
+// the process; its address is resolved once per device (static_scratch).
+constexpr int STATIC_OBS_TILES = 16384;     // packed lattices of up to 16384 x OBS_TILE = 67,108,864 nodes
+static __device__ __align__(256) double scratch[4 * STATIC_OBS_TILES];
 
 namespace {
 
@@ -336,6 +344,8 @@ struct SweepCfg {
 struct lb_ctx {
   std::vector<lb_desc> d;
   int nrep = 1;
+  int device = 0;            // HIP device current at creation
+  double* scratch_dev = nullptr;  // that device's address of the static scratch array
   lb_buffers b;
   hipStream_t s;
   int cur;          // 0: pops_a holds the current populations
@@ -383,6 +393,25 @@ struct lb_ctx {
 namespace {
 
 void* cur_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_a : c->b.pops_b; }
+
+// Device address of the static scratch array on device dev (the current
+// device), resolved once per device under a lock.  In host code the array's
+// name only stands in for the symbol; the kernels get this address.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[MAX_DEVICES] = {};
+int static_scratch(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(LB_ERR_DEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return fail(LB_ERR_DEVICE, "static scratch: %s", hipGetErrorString(e));
+    g_scratch_addr[dev] = (double*)p;
+  }
+  *out = g_scratch_addr[dev];
+  return LB_OK;
+}
 void* other_pops(lb_ctx* c) { return c->cur == 0 ? c->b.pops_b : c->b.pops_a; }
 
 // Sweep tiles in launch order.  Order 0 lists each replica's tiles in node
@@ -725,6 +754,12 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   lb_ctx* c = new lb_ctx();
   c->d.assign(d, d + nrep);
   c->nrep = nrep;
+  {
+    hipError_t e = hipGetDevice(&c->device);
+    int rcs = e == hipSuccess ? static_scratch(c->device, &c->scratch_dev) : fail(LB_ERR_DEVICE, "hipGetDevice: %s",
+                                                                                     hipGetErrorString(e));
+    if (rcs) { delete c; return rcs; }
+  }
   c->b = *b;
   c->s = (hipStream_t)stream;
   {
@@ -1037,6 +1072,21 @@ int lb_observables(lb_ctx* c, double* out_dev, int which_mask) {
   if (c->dev) launch_observables<float, true>(cur_pops(c), c->D, no, c->nrep, out_dev, which_mask, c->D.part, c->s);
   else launch_observables<double, false>(cur_pops(c), c->D, no, c->nrep, out_dev, which_mask, c->D.part, c->s);
   return check_hip("lb_observables");
+}
+
+int lb_observables_static(lb_ctx* c, double* out_dev, int which_mask) {
+  if (!c || !out_dev) return fail(LB_ERR_ARG, "bad arguments");
+  if (which_mask & ~LB_OBS_ALL) return fail(LB_ERR_ARG, "unknown observable group in the mask 0x%x", which_mask);
+  const long no = c->pk.obs_tiles;
+  if ((which_mask & LB_OBS_FLUID) && no > STATIC_OBS_TILES)
+    return fail(LB_ERR_ARG, "lattice too large for the static scratch: %ld reduction tiles of %d nodes > %d", no,
+                OBS_TILE, STATIC_OBS_TILES);
+  if (!which_mask) return LB_OK;
+  if (c->dev)
+    launch_observables<float, true>(cur_pops(c), c->D, (int)no, c->nrep, out_dev, which_mask, c->scratch_dev, c->s);
+  else
+    launch_observables<double, false>(cur_pops(c), c->D, (int)no, c->nrep, out_dev, which_mask, c->scratch_dev, c->s);
+  return check_hip("lb_observables_static");
 }
 
 int lb_get_state(lb_ctx* c, void* dst) {

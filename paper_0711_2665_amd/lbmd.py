@@ -101,6 +101,7 @@ def _declare(L):
     L.lb_adjoint_backward.argtypes = [P, P, P, P]
     L.lb_adjoint_run.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t, P, P]
     L.lb_observables.argtypes = [P, P, C.c_int]
+    L.lb_observables_static.argtypes = [P, P, C.c_int]
     L.lb_get_state.argtypes = [P, P]
     L.lb_set_state.argtypes = [P, P]
     L.lb_current_pops.argtypes = [P]
@@ -379,6 +380,13 @@ class Context:
         self._obs.fill_(float("nan"))
         _raise(lib().lb_observables(self.ctx, C.c_void_p(self._obs.data_ptr()), int(mask)))
         return self._obs.view(self.nrep, LB_NOBS)
+
+    def observables_static(self, out, mask=LB_OBS_ALL):
+        """lb_observables_static into the caller's float64 device tensor out
+        (at least nrep * LB_NOBS elements): no allocation on any side."""
+        assert out.dtype == self.torch.float64 and out.is_cuda and out.numel() >= LB_NOBS * self.nrep
+        _raise(lib().lb_observables_static(self.ctx, C.c_void_p(out.data_ptr()), int(mask)))
+        return out
 
     def get_state(self):
         st = self.torch.empty(self.sizes["state_bytes"], dtype=self.torch.uint8, device=self.device)
