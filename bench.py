@@ -191,16 +191,29 @@ def run_ensemble(steps, warmup, eager_steps):
     return res
 
 
+VALIDATED_HORIZON = 200   # steps at which the FP64 adjoint of the benchmarked workload matches the oracle's
+                          # forward-mode derivative to 1e-8 (tests/test_gpu_adjoint_horizon.py)
+
+
 def run_adjoint(nsteps, K, horizons):
     """The gradient workload: 64^3, 100-bead chain, pore 3 x 3, loss = mean
     normal coordinate after the run, gradient w.r.t. gamma, F_drive and the
     initial positions by the library's adjoint with checkpoints every K
     steps.  Timed over nsteps coupled steps in FP64 and FP32 deviation
-    storage.  The bead dynamics is chaotic, so the derivative of the discrete
-    map grows with the horizon and finite differences stop resolving it once
-    trajectories cross interpolation kinks inside the difference interval;
-    the check therefore scans short horizons: central difference of dL/dgamma
-    (h = 1e-6, FP64) against the adjoint, and FP32 against FP64."""
+    storage.
+
+    The bead dynamics is chaotic: the derivative of the discrete map grows
+    roughly like exp(0.013 n), and the last-bit differences between two FP64
+    evaluations of the same map (the GPU's and the host's log, sin, cos,
+    atan2) are amplified as much.  The FP64 adjoint matches the oracle's
+    forward-mode derivative to 1e-8 up to VALIDATED_HORIZON steps (the GPU
+    test); the gradients reported there are the validated ones.  The values
+    over the full nsteps are reported too, marked chaos-dominated, with the
+    spread between FP32 and FP64 storage: they are the derivative of each
+    run's own trajectory and do not agree between precisions.  Finite
+    differences (h = 1e-6 in gamma, FP64) resolve the derivative only over
+    short horizons, before trajectories cross interpolation kinks inside the
+    difference interval; the scan shows where."""
     import numpy as np
     import torch
     from paper_0711_2665_amd import lbmd
@@ -212,6 +225,7 @@ def run_adjoint(nsteps, K, horizons):
     dLdr = np.zeros((cfg["nb"], 3))
     dLdr[:, cfg["wall_axis"]] = 1.0 / cfg["nb"]
     sims = {}
+    full = {}
     for name, prec in (("fp64", lbmd.LB_FP64), ("fp32dev", lbmd.LB_FP32_DEV)):
         sim = lbmd.Simulation(cfg, r, v, precision=prec, device="cuda:0")
         sim.relax(cfg["relax_substeps"], cfg["gamma_relax"])
@@ -226,14 +240,15 @@ def run_adjoint(nsteps, K, horizons):
         t2 = time.perf_counter()
         sim.check()
         out[name] = {"adjoint_steps_per_s": round(nsteps / (t2 - t0), 2), "forward_s": round(t1 - t0, 3),
-                     "reverse_s": round(t2 - t1, 3), "dL_dgamma": float(g[0]), "dL_dF_drive": float(g[1])}
+                     "reverse_s": round(t2 - t1, 3)}
+        full[name] = {"dL_dgamma": float(g[0]), "dL_dF_drive": float(g[1])}
         sims[name] = (sim, st)
 
     def grad(name, T):
         sim, st = sims[name]
         sim.set_state(st)
         sim.set_coupling(cfg["gamma"], cfg["f_drive"])
-        sim.adjoint_forward(T, K)
+        sim.adjoint_forward(T, min(K, T))
         return sim.adjoint_backward(dLdr).cpu().numpy()
 
     def loss(T, gamma):
@@ -243,6 +258,25 @@ def run_adjoint(nsteps, K, horizons):
         sim.couple_step(T)
         return float(sim.beads()["r"][:, cfg["wall_axis"]].mean())
 
+    def spread(a, b):
+        return abs(a - b) / max(abs(b), 1e-300)
+
+    gv = {name: grad(name, VALIDATED_HORIZON) for name in sims}
+    out["validated_horizon"] = {
+        "steps": VALIDATED_HORIZON,
+        "criterion": "FP64 adjoint within 1e-8 of the FP64 oracle's forward-mode derivative in dgamma, dF_drive "
+                     "and a random direction of r(0) (the deterministic variant, kT = 0 and kappa = 0, "
+                     "matches over the full horizon)",
+        "fp64": {"dL_dgamma": float(gv["fp64"][0]), "dL_dF_drive": float(gv["fp64"][1])},
+        "fp32dev": {"dL_dgamma": float(gv["fp32dev"][0]), "dL_dF_drive": float(gv["fp32dev"][1])},
+        "fp32dev_rel_diff": {"dL_dgamma": spread(gv["fp32dev"][0], gv["fp64"][0]),
+                             "dL_dF_drive": spread(gv["fp32dev"][1], gv["fp64"][1])}}
+    out["full_horizon"] = {
+        "steps": nsteps, "chaos_dominated": True,
+        "note": "derivative of each run's own trajectory past the validated horizon; FP32 and FP64 storage, "
+                "and two FP64 codes, disagree here",
+        "fp64": full["fp64"], "fp32dev": full["fp32dev"],
+        "fp32dev_rel_diff": {k: spread(full["fp32dev"][k], full["fp64"][k]) for k in ("dL_dgamma", "dL_dF_drive")}}
     h = 1e-6
     scan = []
     for T in horizons:
@@ -250,9 +284,9 @@ def run_adjoint(nsteps, K, horizons):
         g32 = grad("fp32dev", T)
         fd = (loss(T, cfg["gamma"] + h) - loss(T, cfg["gamma"] - h)) / (2 * h)
         scan.append({"steps": T, "dL_dgamma_adjoint": float(g64[0]), "dL_dgamma_fd": fd,
-                     "fd_rel_diff": abs(float(g64[0]) - fd) / max(abs(fd), 1e-300),
-                     "fp32dev_rel_diff": abs(float(g32[0] - g64[0])) / max(abs(float(g64[0])), 1e-300)})
-    out["horizon_scan"] = scan
+                     "fd_rel_diff": spread(float(g64[0]), fd),
+                     "fp32dev_rel_diff": spread(float(g32[0]), float(g64[0]))})
+    out["fd_scan"] = scan
     for name in list(sims):
         del sims[name]
     torch.cuda.empty_cache()

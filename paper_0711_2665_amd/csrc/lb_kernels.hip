@@ -541,28 +541,40 @@ __global__ void k_ledger_sum(Dev d, int nrep) {
 }
 
 // Spread-on-solid: the share W_k J_p of the step's impulse that the
-// spreading drops because corner k of bead p is solid.  One block per
-// replica; beads strided over the threads, then a fixed-order tree sum.
-__global__ __launch_bounds__(256) void k_ledger_sp(Dev d) {
+// spreading drops because corner k of bead p is solid.  One thread per bead
+// slot writes its share (corners in order) to lsp; k_ledger_sp_sum then adds
+// each replica's beads in a fixed order (strided per thread, then a tree).
+__global__ void k_ledger_sp(Dev d, int nslots) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  const Rep& R = d.reps[d.slot_rep[slot]];
+  const Geom& g = R.g;
+  double s[3] = {0.0, 0.0, 0.0};
+  if (g.wall_axis >= 0 && slot - R.slot_off < R.mp.nb) {
+    const uint8_t* fr = d.flags + R.node_off;
+    const double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
+    const Stencil st = make_stencil(g, rp);
+    uint8_t fl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) fl[k] = fr[corner_node(g, st, k)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (!corner_used(g, st, k) || !(fl[k] & F_SOLID)) continue;
+      const double W = corner_weight(st, k);
+      for (int a = 0; a < 3; ++a) s[a] += W * d.J[3 * slot + a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) d.lsp[3 * (size_t)slot + a] = s[a];
+}
+
+__global__ __launch_bounds__(256) void k_ledger_sp_sum(Dev d) {
   __shared__ double sh[256];
   const int rep = blockIdx.x;
   const Rep& R = d.reps[rep];
-  const Geom& g = R.g;
-  const uint8_t* fr = d.flags + R.node_off;
   double s[3] = {0.0, 0.0, 0.0};
-  if (g.wall_axis >= 0) {
-    for (int p = threadIdx.x; p < R.mp.nb; p += 256) {
-      const int slot = R.slot_off + p;
-      const double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
-      const Stencil st = make_stencil(g, rp);
-      for (int k = 0; k < 8; ++k) {
-        if (!corner_used(g, st, k)) continue;
-        if (!(fr[corner_node(g, st, k)] & F_SOLID)) continue;
-        const double W = corner_weight(st, k);
-        for (int a = 0; a < 3; ++a) s[a] += W * d.J[3 * slot + a];
-      }
-    }
-  }
+  if (R.g.wall_axis >= 0)
+    for (int p = threadIdx.x; p < R.mp.nb; p += 256)
+      for (int a = 0; a < 3; ++a) s[a] += d.lsp[3 * (size_t)(R.slot_off + p) + a];
   for (int a = 0; a < 3; ++a) {
     const double v = block_sum(s[a], sh);
     if (threadIdx.x == 0) d.ledger[NLEDGER * rep + 3 + a] += v;
@@ -662,8 +674,10 @@ void launch_ledger_bb(const void* A, const Dev& d, int nblk, int nrep, hipStream
   hipLaunchKernelGGL(k_ledger_sum, dim3(blocks_for(nrep, 64)), dim3(64), 0, s, d, nrep);
 }
 
-void launch_ledger_sp(const Dev& d, int nrep, hipStream_t s) {
-  hipLaunchKernelGGL(k_ledger_sp, dim3((unsigned)nrep), dim3(256), 0, s, d);
+void launch_ledger_sp(const Dev& d, int nslots, int nrep, hipStream_t s) {
+  if (nslots <= 0) return;
+  hipLaunchKernelGGL(k_ledger_sp, dim3(blocks_for(nslots, 64)), dim3(64), 0, s, d, nslots);
+  hipLaunchKernelGGL(k_ledger_sp_sum, dim3((unsigned)nrep), dim3(256), 0, s, d);
 }
 
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);

@@ -103,7 +103,7 @@ Packing packing(const lb_desc* d, int nrep) {
 
 struct WorkLayout {
   size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
-      tX, notdone, ccount, cbuf, rbin, cst, wlinks, ledger, lpart;
+      tX, notdone, ccount, cbuf, rbin, cst, wlinks, ledger, lpart, lsp;
   size_t nbuckets;
   size_t total;
 };
@@ -142,6 +142,7 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   w.wlinks = take(sizeof(WallLink) * LEDGER_BLOCK * (size_t)pk.wl_blocks_max);
   w.ledger = take(sizeof(double) * NLEDGER * R);
   w.lpart = take(sizeof(double) * 3 * (size_t)(pk.wl_blocks_max > 0 ? pk.wl_blocks_max : 1));
+  w.lsp = take(sizeof(double) * 3 * ns);
   w.total = o;
   return w;
 }
@@ -560,7 +561,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   // impulse that falls on solid nodes; for long chains the next step's
   // lists from r(n+1)
   acc(hipStreamWaitEvent(c->s2, c->mdone, 0));
-  launch_ledger_sp(D, c->nrep, c->s2);
+  launch_ledger_sp(D, c->nslots, c->nrep, c->s2);
   if (c->step_lists) {
     launch_nbr_build(D, c->nslots, c->nrep, c->s2);
     c->lists_stale = false;
@@ -866,6 +867,7 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   D.wlinks = (const WallLink*)(w + c->wl.wlinks);
   D.ledger = (double*)(w + c->wl.ledger);
   D.lpart = (double*)(w + c->wl.lpart);
+  D.lsp = (double*)(w + c->wl.lsp);
   c->wl_blocks = (int)(links.size() / LEDGER_BLOCK);
   if ((long)c->wl_blocks > c->pk.wl_blocks_max) {
     lb_destroy(c);

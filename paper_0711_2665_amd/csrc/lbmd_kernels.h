@@ -126,6 +126,7 @@ struct Dev {
   const WallLink* wlinks;
   double* ledger;
   double* lpart;
+  double* lsp;      // per slot [3]: the step's spread-on-solid share of the bead
 };
 
 // MD coefficients that replace the replicas' own during the pre-relaxation
@@ -169,7 +170,7 @@ void launch_observables(const void* A, const Dev& d, int n_otiles, int nrep, dou
 // and the bead impulse of the step's spreading that falls on solid nodes.
 template <typename T, bool DEV>
 void launch_ledger_bb(const void* A, const Dev& d, int nblk, int nrep, hipStream_t s);
-void launch_ledger_sp(const Dev& d, int nrep, hipStream_t s);
+void launch_ledger_sp(const Dev& d, int nslots, int nrep, hipStream_t s);
 
 // Adjoint pass (one replica, chains of at most MAX_ADJ_BEADS beads).
 constexpr int MAX_ADJ_BEADS = 128;

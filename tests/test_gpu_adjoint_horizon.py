@@ -1,37 +1,75 @@
-"""The adjoint on the 64^3 / 100-bead gradient workload at a horizon where
-finite differences no longer resolve the derivative (the trajectories cross
-trilinear-interpolation kinks inside the difference interval): the FP64
-adjoint must still equal the oracle's forward-mode derivative of the same
-discrete map."""
+"""The adjoint on the 64^3 / 100-bead gradient workload at long horizons,
+against the oracle's forward-mode derivative of the same discrete map (three
+directions: gamma, F_drive, a random direction of the initial positions).
+
+With the bead noise and bending (the workload as benchmarked) the GPU and the
+oracle evaluate log, sin, cos and atan2 with different last bits, and the
+chaotic bead dynamics amplifies that difference: the derivative itself grows
+roughly like exp(0.013 n), and the two FP64 derivatives agree to 1e-8 up to
+200 steps (2.8e-9 there, 3.7e-7 at 300, uncorrelated past about 1500).  200
+steps is therefore the horizon at which the benchmark's gradient is
+validated.  Without noise and bending (kT = 0, kappa = 0) the two forward
+trajectories are bit for bit equal, and the adjoint must reproduce the
+oracle's derivative over the workload's full 2000 steps although it grows
+to ~1e284 there: that checks the reverse pass itself over the whole horizon,
+checkpoints included."""
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
-from paper_0711_2665_amd.workloads import C4, initial_chain
+from paper_0711_2665_amd.workloads import C4, initial_chain, scaled
 
 pytestmark = pytest.mark.gpu
 
 
-def test_adjoint_c4_50_steps_matches_oracle_jvp(orc):
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_0711_2665_amd import lbmd
-    cfg, T = C4, 50
+def _start(orc, cfg):
     r, v = initial_chain(cfg)
     o = orc.Oracle(cfg, r, v)
     o.relax(cfg["relax_substeps"], cfg["gamma_relax"])
-    r0 = o.beads()["r"]
-    v0 = np.zeros_like(r0)
+    return o.beads()["r"]
+
+
+def _oracle_series(orc, cfg, r0, d, T):
+    """The oracle's dL/dgamma, dL/dF_drive and dL/dr0 . d after each of T
+    steps (three dual-number runs side by side, 5 host threads each)."""
+    def one(kw):
+        orc.set_threads(5)
+        return orc.jvp_series(cfg, r0, np.zeros_like(r0), T, **kw)[1]
+    with ThreadPoolExecutor(3) as ex:
+        futs = [ex.submit(one, kw) for kw in (dict(dgamma=1.0), dict(dfdrive=1.0), dict(dr0=d))]
+        return [f.result() for f in futs]
+
+
+def _adjoint(cfg, r0, d, H, K):
+    from paper_0711_2665_amd import lbmd
     sim = lbmd.Simulation(cfg, r0)
     dLdr = np.zeros_like(r0)
     dLdr[:, cfg["wall_axis"]] = 1.0 / cfg["nb"]
-    sim.adjoint_forward(T, 10)
+    sim.adjoint_forward(H, K)
     g = sim.adjoint_backward(dLdr).cpu().numpy()
-    _, dg = orc.jvp(cfg, r0, v0, T, dgamma=1.0)
+    sim.check()
+    return np.array([g[0], g[1], float((g[2:].reshape(-1, 3) * d).sum())])
+
+
+def _compare(orc, cfg, horizons, K, tol):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r0 = _start(orc, cfg)
     d = np.random.default_rng(11).standard_normal(r0.shape)
-    _, dd = orc.jvp(cfg, r0, v0, T, dr0=d)
-    got = float((g[2:].reshape(-1, 3) * d).sum())
-    print(f"c4 {T} steps: dL/dgamma adjoint {g[0]:.12e} oracle {dg:.12e}; "
-          f"dL/dr0.dir adjoint {got:.12e} oracle {dd:.12e}", flush=True)
-    assert abs(g[0] - dg) <= 1e-8 * abs(dg)
-    assert abs(got - dd) <= 1e-8 * abs(dd)
+    series = _oracle_series(orc, cfg, r0, d, max(horizons))
+    for H in horizons:
+        got = _adjoint(cfg, r0, d, H, K)
+        ref = np.array([s[H - 1] for s in series])
+        rel = np.abs(got - ref) / np.abs(ref)
+        print(f"H={H}: adjoint {got} oracle {ref} rel {rel}", flush=True)
+        assert (rel <= tol).all(), (H, rel)
+
+
+def test_adjoint_c4_matches_oracle_jvp_up_to_the_validated_horizon(orc):
+    _compare(orc, C4, (20, 50, 100, 200), 10, 1e-8)
+
+
+def test_adjoint_c4_deterministic_matches_oracle_jvp_over_the_full_horizon(orc):
+    _compare(orc, scaled(C4, kT=0.0, kappa=0.0), (500, 1000, 2000), 100, 1e-10)

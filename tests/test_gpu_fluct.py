@@ -155,7 +155,7 @@ def test_fluctuating_lb_only_fp32_deviation_matches_oracle(orc, shape, axis, pos
     b = (o.pops() - w[:, None, None, None])[:, fluid]
     err = np.abs(a - b).max() / np.abs(b).max()
     print(f"fp32-dev fluctuating lb-only {shape}: rel err of deviations {err:.2e}", flush=True)
-    assert err < 1e-5
+    assert err < 2e-6                       # measured 1.7e-7, 2.2e-7
 
 
 def _ens_cfgs():

@@ -115,7 +115,9 @@ def test_rest_start_on_unaligned_lattice_matches_oracle(orc, precision):
     if precision == "fp64":
         assert np.array_equal(a, b)
     else:
-        assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
+        rel = np.abs(a - b).max() / np.abs(b).max()
+        print(f"fp32-dev unaligned rest start, 10 steps: rel err of deviations {rel:.2e}", flush=True)
+        assert rel <= 5e-6                 # the 20-step LB-only runs measure 4.5e-7
 
 
 def test_poiseuille_on_gpu_matches_closed_form():
@@ -405,7 +407,7 @@ def test_lb_only_fp32_deviation_matches_oracle(orc, shape, axis, pos):
     b = (o.pops() - w[:, None, None, None])[:, fluid]
     err = np.abs(a - b).max() / np.abs(b).max()
     print(f"fp32-dev lb-only {shape}: rel err of deviations {err:.2e}", flush=True)
-    assert err < 1e-5
+    assert err < 5e-6                      # measured 4.5e-7
 
 
 def test_fp32_deviation_rest_state_is_exact():
@@ -433,8 +435,8 @@ def test_fp32_deviation_coupled_c0_error(orc):
     rg, ro = s.beads()["r"].cpu().numpy(), o.beads()["r"]
     print(f"fp32-dev c0 50 steps: |f - f64|_max {err_f:.3e} (max |f - w| {np.abs(fo).max():.3e}), "
           f"|r - r64|_max {np.abs(rg - ro).max():.3e}", flush=True)
-    assert err_f < 1e-6
-    assert np.abs(rg - ro).max() < 1e-4
+    assert err_f < 3e-9                    # measured 2.4e-10
+    assert np.abs(rg - ro).max() < 5e-8     # measured 4.9e-9
 
 
 def test_watchdog_flags_nan_population(orc):
