@@ -74,6 +74,7 @@ struct Packing {
   long sweep_tiles_max = 0;         // tiles of the sweep at TILE_MIN
   long obs_tiles = 0;
   long wl_blocks_max = 0;           // wall-link list blocks (LEDGER_BLOCK entries each), upper bound
+  int nseg = 0;                     // chain segments of the fused sub-cycle (FUSED_OWN beads each)
 };
 
 // Fluid nodes with a solid upstream neighbour lie in the three planes around
@@ -96,6 +97,7 @@ Packing packing(const lb_desc* d, int nrep) {
     pk.sweep_tiles_max += (N + TILE_MIN - 1) / TILE_MIN;
     pk.obs_tiles += (N + OBS_TILE - 1) / OBS_TILE;
     pk.wl_blocks_max += (wall_link_bound(d[r]) + LEDGER_BLOCK - 1) / LEDGER_BLOCK;
+    pk.nseg += (d[r].nb + FUSED_OWN - 1) / FUSED_OWN;
   }
   pk.slots_alloc = pk.slots > 0 ? pk.slots : 1;
   return pk;
@@ -103,7 +105,7 @@ Packing packing(const lb_desc* d, int nrep) {
 
 struct WorkLayout {
   size_t ctrl, reps, tiles, otiles, slot_rep, head, next, base, touched, nbr, ncnt, rb, rmid0, rmid1, ref, part, xi,
-      tX, notdone, ccount, cbuf, rbin, cst, wlinks, ledger, lpart, lsp;
+      tX, notdone, ccount, cbuf, rbin, cst, wlinks, ledger, lpart, lsp, fseg, rmS, vS, JS, fang, redo;
   size_t nbuckets;
   size_t total;
 };
@@ -143,6 +145,12 @@ WorkLayout work_layout(const lb_desc* d, int nrep, const Packing& pk) {
   w.ledger = take(sizeof(double) * NLEDGER * R);
   w.lpart = take(sizeof(double) * 3 * (size_t)(pk.wl_blocks_max > 0 ? pk.wl_blocks_max : 1));
   w.lsp = take(sizeof(double) * 3 * ns);
+  w.fseg = take(sizeof(FusedSeg) * (size_t)(pk.nseg > 0 ? pk.nseg : 1));
+  w.rmS = take(sizeof(double) * 3 * ns);
+  w.vS = take(sizeof(double) * 3 * ns);
+  w.JS = take(sizeof(double) * 3 * ns);
+  w.fang = take(sizeof(double) * 9 * ns);
+  w.redo = take(sizeof(int) * R);
   w.total = o;
   return w;
 }
@@ -197,6 +205,11 @@ int validate_one(const lb_desc* d, int r) {
   if (d->constraints == 1 && (d->mts_outer != 0 || d->nb > MAX_CONSTRAINED_BEADS))
     return fail(LB_ERR_ARG, "replica %d: rigid bonds need the uniform sub-cycle and at most %d beads", r,
                 MAX_CONSTRAINED_BEADS);
+  if (d->md_block != 0 &&
+      (d->md_block < 2 || d->md_block > FUSED_K || d->n_sub % d->md_block != 0 || d->mts_outer != 0 ||
+       d->constraints != 0))
+    return fail(LB_ERR_ARG, "replica %d: md_block must be 0, or divide n_sub and lie in [2, %d] with the uniform "
+                            "sub-cycle and harmonic bonds", r, FUSED_K);
   if (d->mts_outer > 0 && (d->n_sub % d->mts_outer != 0 || d->n_sub / d->mts_outer > MTS_MAX_INNER))
     return fail(LB_ERR_ARG, "replica %d: mts_outer must divide n_sub into at most %d sub-steps per outer step", r,
                 MTS_MAX_INNER);
@@ -225,6 +238,7 @@ int validate(const lb_desc* d, int nrep) {
     if (d[r].precision != d[0].precision) return fail(LB_ERR_ARG, "replica %d: all replicas need one precision", r);
     if (d[r].n_sub != d[0].n_sub) return fail(LB_ERR_ARG, "replica %d: all replicas need one n_sub", r);
     if (d[r].mts_outer != d[0].mts_outer) return fail(LB_ERR_ARG, "replica %d: all replicas need one mts_outer", r);
+    if (d[r].md_block != d[0].md_block) return fail(LB_ERR_ARG, "replica %d: all replicas need one md_block", r);
     nodes += round_up((long)d[r].nx * d[r].ny * d[r].nz, NODE_ALIGN);
     slots += round_up(d[r].nb, MD_BPB);
   }
@@ -369,6 +383,9 @@ struct lb_ctx {
   SweepCfg sweep;
   int ntiles = 0;
   int wl_blocks = 0;         // blocks of the wall-link list (bounce-back ledger)
+  int fusedK = 0;            // sub-steps per fused block of the uniform sub-cycle (0: one launch per sub-step)
+  int fusedK_max = 0;        // the block length the context supports (0: none)
+  FusedBufs fb{};
   int64_t steps = 0;
   // second stream for the sweep over the nodes without bead force, which
   // runs concurrently with the bead phase; fork/join events
@@ -550,6 +567,8 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   else launch_gather<double, false>(A, D, c->nslots, start, sb);
   MdOverride none{};
   if (c->mts > 0) launch_md_cycle_mts(D, c->nslots, c->nrep, c->n_sub, c->mts, sb, false);
+  else if (c->fusedK > 0 && !D.mdtape)
+    launch_md_cycle_fused(D, c->fb, c->pk.nseg, c->nslots, c->nrep, c->n_sub, c->fusedK, sb);
   else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb, false, c->any_constrained);
   acc(hipEventRecord(c->mdone, sb));
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
@@ -788,7 +807,14 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   c->nslots = c->pk.slots;
   c->maxlist = 8 * c->nslots;
   for (int r = 0; r < nrep; ++r) c->step_lists = c->step_lists || d[r].nb >= STEP_LISTS_MIN_BEADS;
-  const double skin = c->step_lists ? SKIN_STEP : SKIN;
+  // the fused sub-cycle (asked for at creation; uniform sub-steps, harmonic
+  // bonds) certifies its blocks against lists built at every LB step
+  if (d[0].md_block > 0 && c->pk.nseg > 0) {
+    c->fusedK_max = d[0].md_block;
+    c->step_lists = true;
+    c->fusedK = c->fusedK_max;
+  }
+  const double skin = c->fusedK_max > 0 ? SKIN_FUSED : (c->step_lists ? SKIN_STEP : SKIN);
   const size_t ns = (size_t)c->pk.slots_alloc;
   const long nodes = c->pk.nodes;
 
@@ -868,6 +894,13 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   D.ledger = (double*)(w + c->wl.ledger);
   D.lpart = (double*)(w + c->wl.lpart);
   D.lsp = (double*)(w + c->wl.lsp);
+  D.redo = (int*)(w + c->wl.redo);
+  c->fb.seg = (const FusedSeg*)(w + c->wl.fseg);
+  c->fb.rmS = (double*)(w + c->wl.rmS);
+  c->fb.vS = (double*)(w + c->wl.vS);
+  c->fb.JS = (double*)(w + c->wl.JS);
+  c->fb.ang = (double*)(w + c->wl.fang);
+  c->fb.redo = D.redo;
   c->wl_blocks = (int)(links.size() / LEDGER_BLOCK);
   if ((long)c->wl_blocks > c->pk.wl_blocks_max) {
     lb_destroy(c);
@@ -881,6 +914,12 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   acc(hipMemcpyAsync(w + c->wl.slot_rep, slot_rep.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s));
   if (!links.empty())
     acc(hipMemcpyAsync(w + c->wl.wlinks, links.data(), sizeof(WallLink) * links.size(), hipMemcpyHostToDevice, s));
+  std::vector<FusedSeg> segs;
+  for (int r = 0; r < nrep; ++r)
+    for (int a = 0; a < d[r].nb; a += FUSED_OWN) segs.push_back(FusedSeg{r, a, std::min(a + FUSED_OWN, d[r].nb), 0});
+  if (!segs.empty())
+    acc(hipMemcpyAsync(w + c->wl.fseg, segs.data(), sizeof(FusedSeg) * segs.size(), hipMemcpyHostToDevice, s));
+  launch_fill_i32(D.redo, nrep, -1, s);
   launch_fill_f64(D.ledger, (long)NLEDGER * nrep, 0.0, s);
   // rest populations, replica by replica ([19][N_r] from element 19 node_off)
   for (int r = 0; r < nrep; ++r) {
@@ -1167,6 +1206,9 @@ int lb_diagnostics(lb_ctx* c, int64_t* out) {
   out[4] = (int64_t)h.step;
   out[5] = (int64_t)h.forced_total;
   out[6] = (int64_t)h.cell_rebuilds;
+  out[7] = (int64_t)h.fused_blocks;
+  out[8] = (int64_t)h.fused_redos;
+  for (int k = 0; k < 5; ++k) out[9 + k] = (int64_t)h.fused_why[k];
   return LB_OK;
 }
 
@@ -1175,6 +1217,17 @@ int lb_ensemble_translocation(lb_ctx* c, int64_t* out_host) {
   hipError_t e = hipStreamSynchronize(c->s);
   if (e == hipSuccess) e = hipMemcpy(out_host, c->D.tX, sizeof(int64_t) * c->nrep, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(LB_ERR_DEVICE, "translocation read: %s", hipGetErrorString(e));
+  return LB_OK;
+}
+
+int lb_md_fused(lb_ctx* c, int K) {
+  if (!c || K < 0) return fail(LB_ERR_ARG, "bad arguments");
+  if (K > 0 && c->fusedK_max == 0)
+    return fail(LB_ERR_UNSUPPORTED, "the fused sub-cycle needs a context created with md_block > 0 and a chain");
+  if (K > 0 && (K < 2 || K > c->fusedK_max || c->n_sub % K != 0))
+    return fail(LB_ERR_ARG, "block length must divide n_sub and lie in [2, %d]", c->fusedK_max);
+  if (K != c->fusedK) drop_graph(c);
+  c->fusedK = K;
   return LB_OK;
 }
 

@@ -86,6 +86,8 @@ constexpr int MAXNBR = 48;        // neighbour-list capacity per bead
 constexpr int MAXCONTRIB = 64;    // bead contributions gathered per node
 constexpr double SKIN = 0.4;      // neighbour-list skin (lists rebuilt when a bead moved skin/2)
 constexpr double SKIN_STEP = 0.6; // skin when lists are rebuilt at every coupled step (long chains)
+constexpr double SKIN_FUSED = 1.2;// skin of the per-step lists of the fused sub-cycle: a block certifies while
+                                  // every bead is within SKIN_FUSED / 2 - 0.1 of where the lists were built
 constexpr int STEP_LISTS_MIN_BEADS = 1024;  // chains this long get per-step cell-list builds
 // Cells of the neighbour-search table are at least r_c + skin + CELL_MARGIN
 // wide, so the table stays usable for a rebuild inside a sub-cycle while no
@@ -101,7 +103,14 @@ struct Ctrl {
   uint64_t substeps;         // MD sub-steps so far (diagnostic)
   uint64_t forced_total;     // nodes carrying bead force, summed over steps (diagnostic)
   uint64_t cell_rebuilds;    // of the rebuilds, those that used the cell table (diagnostic)
-  uint32_t pad[52];
+  uint64_t fused_blocks;     // fused sub-step blocks completed (diagnostic)
+  uint64_t fused_redos;      // replica sub-cycles redone from a failed block (diagnostic)
+  // why fused blocks failed (diagnostic, per failing workgroup): lists not
+  // valid or a bead too far from where they were built, too many close
+  // partners, the set over its capacity, the closure not settled, a bead past
+  // the displacement bound
+  uint32_t fused_why[5];
+  uint32_t pad[43];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 

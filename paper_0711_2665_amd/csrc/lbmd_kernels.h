@@ -120,6 +120,8 @@ struct Dev {
                     // from its binned position at that sub-step (the table is not usable)
   uint32_t cmask;   // buckets - 1 (a power of two minus one)
   Ctrl* ctrl;
+  int* redo;        // per replica: first sub-step the fused sub-cycle leaves to the per-sub-step
+                    // launches (-1: none); reset at every cycle's opening
   // wall momentum ledgers (cumulative, FP64, per replica [NLEDGER]):
   // momentum the wall took by bounce-back, bead reaction that fell on solid
   // nodes; the wall-link list and one partial sum per list block
@@ -209,6 +211,34 @@ void launch_md_begin(const Dev& d, int nrep, hipStream_t s);
 constexpr int MTS_MAX_INNER = 40;
 constexpr int MAX_CONSTRAINED_BEADS = 1024;   // rigid bonds: one workgroup per chain   // inner sub-steps per outer step (the inner kernel's halo is 2 per sub-step)
 void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, hipStream_t s, bool prologue = true);
+
+// The uniform sub-cycle in blocks of K sub-steps, one launch per block:
+// workgroup w advances the chain segment [a, b) of replica rep through the
+// block, with the beads that can reach the segment within K sub-steps (its
+// dependency cone: chain neighbours and close pair partners from the cell
+// table) computed again alongside (see k_md_fused).  The state at a block's
+// start is kept (the blocks alternate between the canonical arrays and the
+// shadow ones); a block that cannot certify its result (a bead moved farther
+// than FUSED_DELTA within it, or off its binned cell-table position by more
+// than CELL_MARGIN, or a cone too large) leaves its replica to one
+// workgroup that redoes the cycle from that block's start (k_md_redo).
+// Results equal the per-sub-step cycle bit for bit.
+struct FusedSeg {
+  int rep, a, b, pad;
+};
+struct FusedBufs {
+  const FusedSeg* seg;
+  double* rmS;      // shadow [slots][3] r_mid, v, J
+  double* vS;
+  double* JS;
+  double* ang;      // [slots][9] the redo's angle forces
+  int* redo;        // per replica: first sub-step to redo, -1 when none
+};
+constexpr int FUSED_OWN = 48;                // chain beads a workgroup owns
+constexpr int FUSED_K = 10;                  // sub-steps per block (the largest divisor of n_sub up to it)
+constexpr double FUSED_DELTA = 0.1;          // displacement bound within a block
+void launch_md_cycle_fused(const Dev& d, const FusedBufs& fb, int nseg, int nslots, int nrep, int n_sub, int K,
+                           hipStream_t s);
 // Noise of one sub-cycle into d.xi, for the step counter + step_offset.
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s);
 void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);

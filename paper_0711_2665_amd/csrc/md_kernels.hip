@@ -26,8 +26,9 @@ namespace lbmd {
 // Per replica r, rb[4 r + 0..2] are the three rotating rebuild flags and
 // rb[4 r + 3] the "lists invalid" request from the host (initialisation,
 // restored state).
-__global__ void k_md_begin(uint32_t* rb, uint32_t* cst, int nrep) {
+__global__ void k_md_begin(uint32_t* rb, uint32_t* cst, int nrep, int* redo) {
   for (int r = threadIdx.x; r < nrep; r += blockDim.x) {
+    if (redo) redo[r] = -1;
     uint32_t* w = rb + 4 * r;
     w[0] = w[3];
     w[1] = 0u;
@@ -116,9 +117,41 @@ __global__ void k_md_noise(Dev d, int nslots, int n_sub, int step_offset) {
   d.xi[3 * k] = x[0]; d.xi[3 * k + 1] = x[1]; d.xi[3 * k + 2] = x[2];
 }
 
-// Component a of the bending forces of the angle at (ra, rb, rc): out[0] on
-// the first bead, out[1] on the centre, out[2] on the third -- the operations
-// of angle_add for that component, so the values a per-bead evaluation gives.
+// The bending angle at (ra, rb, rc) and what its forces need: the bond
+// vectors, their cross product n, |n| = s, b1.b2 = c, phi = atan2(s, c),
+// s^2 + c^2 and kappa phi.  s = 0 (straight or folded) has no unique
+// gradient: its forces are exactly 0.
+struct AngleCore {
+  double b1[3], b2[3], n[3];
+  double s, c, den, kp;
+};
+__device__ inline bool angle_core(const MdParams& P, const double* ra, const double* rb, const double* rc,
+                                  AngleCore& A) {
+  for (int a = 0; a < 3; ++a) { A.b1[a] = rb[a] - ra[a]; A.b2[a] = rc[a] - rb[a]; }
+  A.n[0] = A.b1[1] * A.b2[2] - A.b1[2] * A.b2[1];
+  A.n[1] = A.b1[2] * A.b2[0] - A.b1[0] * A.b2[2];
+  A.n[2] = A.b1[0] * A.b2[1] - A.b1[1] * A.b2[0];
+  A.s = sqrt(A.n[0] * A.n[0] + A.n[1] * A.n[1] + A.n[2] * A.n[2]);
+  A.c = A.b1[0] * A.b2[0] + A.b1[1] * A.b2[1] + A.b1[2] * A.b2[2];
+  if (A.s == 0.0) return false;
+  const double phi = atan2(A.s, A.c);
+  A.den = A.s * A.s + A.c * A.c;
+  A.kp = P.kappa * phi;
+  return true;
+}
+// Component a of the angle's forces: out[0] on the first bead, out[1] on the
+// centre, out[2] on the third -- the operations of angle_component (and of
+// angle_add) for that component, evaluated from one AngleCore.
+__device__ inline void angle_part(const AngleCore& A, int a, double out[3]) {
+  const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+  double g1 = A.b2[a1] * A.n[a2] - A.b2[a2] * A.n[a1];
+  double g2 = A.n[a1] * A.b1[a2] - A.n[a2] * A.b1[a1];
+  double d1 = (A.c * g1 / A.s - A.s * A.b2[a]) / A.den;
+  double d2 = (A.c * g2 / A.s - A.s * A.b1[a]) / A.den;
+  out[0] = 0.0 + A.kp * d1;
+  out[1] = 0.0 + -(A.kp * (d1 - d2));
+  out[2] = 0.0 + -(A.kp * d2);
+}
 __device__ inline void angle_component(const MdParams& P, const double* ra, const double* rb, const double* rc,
                                        int a, double out[3]) {
   double b1[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
@@ -1018,7 +1051,7 @@ __global__ __launch_bounds__(CON_WG) void k_md_constraint(Dev d, int nslots, int
 }
 
 void launch_md_begin(const Dev& d, int nrep, hipStream_t s) {
-  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+  hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep, d.redo);
 }
 
 void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOverride& ov, hipStream_t s,
@@ -1026,7 +1059,7 @@ void launch_md_cycle(const Dev& d, int nslots, int nrep, int n_sub, const MdOver
   if (nslots <= 0 || n_sub <= 0) return;
   unsigned nblk = (unsigned)(nslots / MD_BPB);
   if (prologue) {
-    hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+    hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep, d.redo);
     hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, ov, 0);
   }
   if (constrained)
@@ -1048,7 +1081,7 @@ void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, h
   const unsigned nin = (unsigned)((nslots + own - 1) / own);
   MdOverride none{};
   if (prologue) {
-    hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep);
+    hipLaunchKernelGGL(k_md_begin, dim3(1), dim3(256), 0, s, d.rb, d.cst, nrep, d.redo);
     hipLaunchKernelGGL(k_md_start, dim3((nslots + 255) / 256), dim3(256), 0, s, d, nslots, none, 1);
   }
   for (int o = 0; o < M; ++o) {
@@ -1056,6 +1089,673 @@ void launch_md_cycle_mts(const Dev& d, int nslots, int nrep, int n_sub, int M, h
     hipLaunchKernelGGL(k_md_inner, dim3(nin), dim3(IN_WG), 0, s, d, nslots, o, Mb);
   }
   hipLaunchKernelGGL(k_md_substep<true>, dim3(nblk), dim3(3 * MD_WG), 0, s, d, none, nslots, M, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Fused sub-steps: one launch advances a block of K uniform sub-steps.
+//
+// Workgroup w owns the chain segment [a, b) of replica rep.  Over one
+// sub-step a bead's new state depends on its own state and on the positions
+// of its chain neighbours p-2 .. p+2 (bonds, and the angles centred at p-1,
+// p, p+1) and of its pair partners within r_c.  Give every bead its level:
+// its distance from [a, b) in that dependency graph.  A bead of level k must
+// be exact for the first K - k sub-steps of the block, which needs its
+// dependencies (level <= k + 1) exact for one sub-step less, so the set S of
+// beads of level <= K, each advanced from the positions in S, leaves [a, b)
+// exact after K sub-steps even though the beads at S's rim go wrong (the halo
+// argument of overlapped tiling).  S is a union of chain spans: [a, b)
+// widened by 2K (level 0 inside, +1 per two chain links), and for every
+// close partner j of a bead of level k < K that is not yet in S with level
+// <= k + 1, a span around j of level k + 1, widened by 2 (K - k - 1).
+//
+// Pair partners are the entries of the neighbour lists (built at the start
+// of the LB step, radius r_c + skin) within close = r_c + 2 FUSED_DELTA at
+// the block's start.  Partners farther than that stay beyond r_c for the
+// whole block as long as no bead moves more than FUSED_DELTA within it, so
+// they contribute nothing; and a list holds every bead within close of its
+// bead as long as every bead is within skin/2 - FUSED_DELTA of where the
+// lists were built.  Both conditions are checked, each workgroup on the
+// beads it owns: if every workgroup of the replica finds them true, no bead
+// of the replica violated them and the block equals the per-sub-step
+// computation bit for bit (the same operations in the same order: bonds, the
+// three angles, pair partners in ascending order, wall sites in ascending
+// order, field, then the kick; only pairs within r_c ever add a term, so the
+// list a partner came from does not matter).  Otherwise the replica's redo
+// marker is set to the block's first sub-step, later blocks of the replica
+// return at once, and k_md_redo redoes the replica from there in one
+// workgroup.  A block reads its start state from one set of arrays (the
+// canonical r_mid0, v, J, or the shadow ones) and writes the other, so that
+// the start state of a block that fails is still there.
+// ---------------------------------------------------------------------------
+constexpr int FU_LANES = 4;        // lanes per bead in the sub-steps
+constexpr int FU_CAP = 128;        // beads of S
+constexpr int FU_WG = FU_LANES * FU_CAP;
+constexpr int FU_NS = 16;          // spans of S (before merging)
+constexpr int FU_NC = 16;          // close partners per bead
+constexpr int FU_ROUNDS = 6;       // closure rounds
+constexpr int FU_LD = 16;          // list entries loaded together
+
+struct FuSpan {
+  int blo, bhi;                    // base interval (level lv inside)
+  int lv;
+};
+
+struct FuShared {
+  double pos[2][FU_CAP][3];        // positions at the sub-step's start / the next one
+  double ang[FU_CAP][9];           // forces of the angle centred at the bead (first, centre, third)
+  double bnd[FU_CAP][6];           // the bead's bond forces towards its predecessor and successor
+  int lst[FU_CAP][FU_NC];          // close partners: chain indices, then local indices; ascending
+  unsigned char lcnt[FU_CAP];
+  unsigned char lev[FU_CAP];       // level of the bead (K + 1: not needed)
+  unsigned char angok[FU_CAP];     // the angle centred at the bead is evaluated
+  FuSpan span[FU_NS];
+  int nspan;
+  int ilo[FU_NS], ihi[FU_NS], ioff[FU_NS + 1];   // S as sorted disjoint chain intervals
+  int niv;
+  int nreq;
+  FuSpan req[FU_NS];
+  int ctl;                         // set-up state, written by thread 0 only, between barriers:
+                                   // 0 go on, 1 closure complete, 2 cannot certify, 3 an earlier block failed
+  int ovf;                         // a request or a partner list did not fit
+  int far;                         // a bead of the segment moved too far from where the lists were built
+};
+
+// chain index of local index li, and local index of chain index q (-1 if
+// not in S); S is the concatenation of the sorted disjoint intervals
+__device__ inline int fu_chain(const FuShared& sh, int li) {
+  for (int k = 0; k < sh.niv; ++k)
+    if (li < sh.ioff[k + 1]) return sh.ilo[k] + (li - sh.ioff[k]);
+  return -1;
+}
+__device__ inline int fu_local(const FuShared& sh, int q) {
+  for (int k = 0; k < sh.niv; ++k)
+    if (q >= sh.ilo[k] && q < sh.ihi[k]) return sh.ioff[k] + (q - sh.ilo[k]);
+  return -1;
+}
+// level of chain bead q: the least over the spans of lv + ceil(distance to
+// the span's base / 2), K + 1 when above K (then not in S)
+__device__ inline int fu_level(const FuShared& sh, int q, int K) {
+  int best = K + 1;
+  for (int k = 0; k < sh.nspan; ++k) {
+    const FuSpan& p = sh.span[k];
+    const int dist = q < p.blo ? p.blo - q : (q >= p.bhi ? q - p.bhi + 1 : 0);
+    const int l = p.lv + (dist + 1) / 2;
+    best = l < best ? l : best;
+  }
+  return best;
+}
+// S from the spans (one thread): every bead of level <= K, as sorted
+// disjoint chain intervals.  False when S exceeds its capacity.
+__device__ inline bool fu_build(FuShared& sh, int K, int nb) {
+  int lo[FU_NS], hi[FU_NS];
+  const int n = sh.nspan;
+  for (int k = 0; k < n; ++k) {
+    const int w = 2 * (K - sh.span[k].lv);
+    lo[k] = max(0, sh.span[k].blo - w);
+    hi[k] = min(nb, sh.span[k].bhi + w);
+  }
+  for (int i = 1; i < n; ++i) {
+    const int l = lo[i], h = hi[i];
+    int m = i;
+    while (m > 0 && lo[m - 1] > l) { lo[m] = lo[m - 1]; hi[m] = hi[m - 1]; --m; }
+    lo[m] = l; hi[m] = h;
+  }
+  int k = 0;
+  for (int i = 1; i < n; ++i) {
+    if (lo[i] <= hi[k]) { hi[k] = max(hi[k], hi[i]); continue; }
+    ++k;
+    lo[k] = lo[i]; hi[k] = hi[i];
+  }
+  const int niv = k + 1;
+  int tot = 0;
+  for (int i = 0; i < niv; ++i) tot += hi[i] - lo[i];
+  if (tot > FU_CAP) return false;
+  sh.niv = niv;
+  sh.ioff[0] = 0;
+  for (int i = 0; i < niv; ++i) { sh.ilo[i] = lo[i]; sh.ihi[i] = hi[i]; sh.ioff[i + 1] = sh.ioff[i] + hi[i] - lo[i]; }
+  return true;
+}
+
+// The beads of the replica within sqrt(r2max) of position x (any bead but
+// chain index self), from the neighbour-search cell table, in ascending
+// chain order: at most cap of them into out (returns their number, cap + 1
+// if more).  Every bead within range is found while every bead of the
+// replica lies within CELL_MARGIN of the position the table binned it at
+// and sqrt(r2max) + CELL_MARGIN does not exceed the cell side.
+__device__ inline int cell_partners(const Dev& d, const Rep& R, int rep, const double* pos, int self,
+                                    const double* x, double r2max, int* out, int cap) {
+  const Geom& g = R.g;
+  const int so = R.slot_off;
+  int c[3];
+  bead_cell(R, x, c);
+  int n = 0;
+  for (int k = 0; k < 27; ++k) {
+    const int dx = k % 3 - 1, dy = (k / 3) % 3 - 1, dz = k / 9 - 1;
+    const uint32_t b = cell_bucket(rep, (c[0] + dx + R.ncell[0]) % R.ncell[0], (c[1] + dy + R.ncell[1]) % R.ncell[1],
+                                   (c[2] + dz + R.ncell[2]) % R.ncell[2], d.cmask);
+    const int m = min(d.ccount[b], CELL_CAP);
+    for (int e = 0; e < m; ++e) {
+      const int sl = d.cbuf[(size_t)b * CELL_CAP + e];
+      if (d.slot_rep[sl] != rep) continue;
+      const int j = sl - so;
+      if (j == self) continue;
+      const double e0 = min_image(x[0] - pos[3 * sl], g.nx);
+      const double e1 = min_image(x[1] - pos[3 * sl + 1], g.ny);
+      const double e2 = min_image(x[2] - pos[3 * sl + 2], g.nz);
+      if (!(e0 * e0 + e1 * e1 + e2 * e2 < r2max)) continue;
+      // a bucket reached from two of the 27 cells (few cells per axis, or
+      // hash collisions) gives its beads twice: keep each once
+      int i = n;
+      while (i > 0 && out[i - 1] > j) --i;
+      if (i > 0 && out[i - 1] == j) continue;
+      if (n == cap) return cap + 1;
+      for (int m2 = n; m2 > i; --m2) out[m2] = out[m2 - 1];
+      out[i] = j;
+      ++n;
+    }
+  }
+  return n;
+}
+
+// The wall sites' forces on a bead at rp, added to F in ascending site order
+// (rows o1, then o0): the sites and operations of wall_row, summed as the
+// sub-step kernel sums them.
+__device__ inline void fu_wall(const MdParams& P, const Geom& g, const double* rp, double F[3]) {
+  if (g.wall_axis < 0) return;
+  const double w0 = wrapc(rp[0], g.nx), w1 = wrapc(rp[1], g.ny), w2 = wrapc(rp[2], g.nz);
+  const int b0 = (int)floor(w0), b1 = (int)floor(w1), b2 = (int)floor(w2);
+  const int a = g.wall_axis;
+  const int ba = a == 0 ? b0 : (a == 1 ? b1 : b2);
+  const int na = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+  const int bt0 = a == 0 ? b1 : b0, n0 = a == 0 ? g.ny : g.nx;
+  const int bt1 = a == 2 ? b1 : b2, n1 = a == 2 ? g.ny : g.nz;
+  int off = g.wall_pos - ba;
+  if (off < WLO) off += na;
+  if (off > WHI) off -= na;
+  if (off < P.wlo || off > P.whi) return;
+  const int sa = ba + off;
+  for (int o1 = P.wlo; o1 <= P.whi; ++o1) {
+    const int u1 = bt1 + o1;
+    const int v1 = u1 < 0 ? u1 + n1 : (u1 >= n1 ? u1 - n1 : u1);
+    const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
+    for (int o0 = P.wlo; o0 <= P.whi; ++o0) {
+      const int u0 = bt0 + o0;
+      const int v0 = u0 < 0 ? u0 + n0 : (u0 >= n0 ? u0 - n0 : u0);
+      const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
+      if (in0 && in1) continue;
+      const int sx = a == 0 ? sa : u0;
+      const int sy = a == 1 ? sa : (a == 0 ? u0 : u1);
+      const int sz = a == 2 ? sa : u1;
+      const double d0 = w0 - (double)sx, d1 = w1 - (double)sy, d2 = w2 - (double)sz;
+      if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rc2)) continue;
+      double Fs[3] = {0.0, 0.0, 0.0};
+      lj_add(P, d0, d1, d2, Fs);
+      F[0] += Fs[0]; F[1] += Fs[1]; F[2] += Fs[2];
+    }
+  }
+}
+
+// The force on chain bead q at rp in the order of the sub-step kernel: bonds
+// to q-1 (at rm) and q+1 (at rq), the angles centred at q-1 (third-bead
+// part a3), q (centre part ac) and q+1 (first-bead part a1) -- each NULL when
+// not added --, the pair partners at base + 3 idx[0..np-1] in ascending
+// chain order (terms within r_c only), the wall sites, the field.
+__device__ inline void fu_force(const MdParams& P, const Geom& g, int q, const double* rp, const double* rm,
+                                const double* rq, const double* a3, const double* ac, const double* a1,
+                                const double* base, const int* idx, int np, double F[3]) {
+  F[0] = 0.0; F[1] = 0.0; F[2] = 0.0;
+  if (!P.constrained) {
+    if (q > 0 && rm) bond_add(P, rp, rm, F);
+    if (q < P.nb - 1 && rq) bond_add(P, rp, rq, F);
+  }
+  if (a3) { F[0] += a3[6]; F[1] += a3[7]; F[2] += a3[8]; }
+  if (ac) { F[0] += ac[3]; F[1] += ac[4]; F[2] += ac[5]; }
+  if (a1) { F[0] += a1[0]; F[1] += a1[1]; F[2] += a1[2]; }
+  for (int k = 0; k < np; ++k) {
+    const double* qp = base + 3 * (size_t)idx[k];
+    const double e0 = min_image(rp[0] - qp[0], g.nx);
+    const double e1 = min_image(rp[1] - qp[1], g.ny);
+    const double e2 = min_image(rp[2] - qp[2], g.nz);
+    if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+    double Fp[3] = {0.0, 0.0, 0.0};
+    lj_add(P, e0, e1, e2, Fp);
+    F[0] += Fp[0]; F[1] += Fp[1]; F[2] += Fp[2];
+  }
+  fu_wall(P, g, rp, F);
+  if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
+}
+
+// All nine force components of the angle at (ra, rb, rc) into o (first,
+// centre, third bead, each x, y, z), 0 for a straight or folded angle.
+__device__ inline void fu_angle(const MdParams& P, const double* ra, const double* rb, const double* rc, double* o) {
+  AngleCore A;
+  if (angle_core(P, ra, rb, rc, A)) {
+    for (int a = 0; a < 3; ++a) {
+      double f[3];
+      angle_part(A, a, f);
+      o[a] = f[0]; o[3 + a] = f[1]; o[6 + a] = f[2];
+    }
+  } else {
+    for (int k = 0; k < 9; ++k) o[k] = 0.0;
+  }
+}
+
+// The SPV kick and drifts of one sub-step (as the sub-step kernel): v, J
+// updated; returns r_mid of the next sub-step in x (or, when last, the end
+// position).
+__device__ inline bool fu_kick(const MdParams& P, const double F[3], const double* u, const double* xi, double* v,
+                               double* J, const double* rp, bool last, double x[3]) {
+  bool fin = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double uu = P.couple ? u[a] : 0.0;
+    const double xx = P.sig != 0.0 ? xi[a] : 0.0;
+    const double sx = P.sig * xx;
+    const double vn = P.e * v[a] + P.cf * (F[a] + P.gamma * uu) + sx;
+    J[a] = J[a] - P.m * (P.omE * (uu - v[a]) + sx);
+    v[a] = vn;
+    fin = fin && isfinite(vn);
+    const double re = rp[a] + P.hh * vn;
+    x[a] = last ? re : re + P.hh * vn;
+  }
+  return fin;
+}
+
+__device__ inline void fu_fail(const Dev& d, const FusedBufs& fb, int rep, int s0) {
+  if (atomicCAS(&fb.redo[rep], -1, s0) == -1) atomicAdd((unsigned long long*)&d.ctrl->fused_redos, 1ull);
+}
+
+// Block j = s0 / K of the sub-cycle.  iset: the set holding the block's start
+// state (0: r_mid0, v, J; 1: the shadow arrays); the other receives the end
+// state (the last block writes the final positions to r).
+__global__ __launch_bounds__(FU_WG) void k_md_fused(Dev d, FusedBufs fb, int nslots, int s0, int K, int last,
+                                                    int iset) {
+  __shared__ FuShared sh;
+  const FusedSeg seg = fb.seg[blockIdx.x];
+  const int rep = seg.rep;
+  const Rep& R = d.reps[rep];
+  const MdParams P = R.mp;
+  const Geom g = R.g;
+  const int so = R.slot_off, nb = P.nb;
+  const int t = threadIdx.x;
+  const double* rin = iset ? fb.rmS : d.rmid0;
+  const double* vin = iset ? fb.vS : d.v;
+  const double* Jin = iset ? fb.JS : d.J;
+  double* rout = iset ? d.rmid0 : fb.rmS;
+  double* vout = iset ? d.v : fb.vS;
+  double* Jout = iset ? d.J : fb.JS;
+  const double close = sqrt(P.rc2) + 2.0 * FUSED_DELTA + 1e-9;
+  const double close2 = close * close;
+  if (t == 0) {
+    // an earlier block of the replica failed (another workgroup may set the
+    // marker during this launch: thread 0 reads it once for the workgroup)
+    sh.ctl = fb.redo[rep] >= 0 ? 3 : (d.rb[4 * rep] != 0u ? 2 : 0);   // lists not valid at the cycle's start
+    if (sh.ctl == 2) atomicAdd(&d.ctrl->fused_why[0], 1u);
+    sh.ovf = 0;
+    sh.far = 0;
+    sh.nspan = 1;
+    sh.span[0] = FuSpan{seg.a, seg.b, 0};
+    sh.nreq = 0;
+    if (!fu_build(sh, K, nb)) sh.ctl = 2;
+  }
+  __syncthreads();
+  if (sh.ctl == 3) return;                        // uniform
+  // the lists must hold every close partner: each workgroup checks its own beads
+  const double keep = sqrt(P.halfskin2) - FUSED_DELTA;
+  bool held = keep > 0.0;
+  for (int q = seg.a + t; q < seg.b; q += FU_WG) {
+    const int sl = so + q;
+    double b2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { const double db = rin[3 * sl + a] - d.ref[3 * sl + a]; b2 += db * db; }
+    held = held && b2 <= keep * keep;
+  }
+  if (!held) sh.far = 1;
+  // ---- closure.  Every thread reads sh.ctl right after a barrier; thread
+  // 0 writes it only between the two barriers of a round.
+  for (int round = 0;; ++round) {
+    __syncthreads();
+    if (sh.ctl != 0) break;
+    const int n = sh.ioff[sh.niv];
+    if (t < n) {
+      const int q = fu_chain(sh, t);
+      const int lv = fu_level(sh, q, K);
+      sh.lev[t] = (unsigned char)lv;
+      sh.lcnt[t] = 0;
+      if (lv < K) {
+        // the list and the positions of its first entries, loads issued
+        // together; entries beyond FU_LD in a slower loop
+        const int sl = so + q;
+        const double x[3] = {rin[3 * sl], rin[3 * sl + 1], rin[3 * sl + 2]};
+        const int cnt = d.ncnt[sl];
+        const int* row = d.nbr + (size_t)sl * MAXNBR;
+        int e[FU_LD];
+#pragma unroll
+        for (int k = 0; k < FU_LD; ++k) e[k] = row[k];
+        double pj[FU_LD][3];
+#pragma unroll
+        for (int k = 0; k < FU_LD; ++k) {
+          const int js = so + (k < cnt ? e[k] : q);
+          pj[k][0] = rin[3 * js]; pj[k][1] = rin[3 * js + 1]; pj[k][2] = rin[3 * js + 2];
+        }
+        int c = 0;
+        bool full = false;
+        // one entry: keep it if close; request a span if it needs a lower level
+        auto take = [&](int j, const double* y) {
+          const double e0 = min_image(x[0] - y[0], g.nx);
+          const double e1 = min_image(x[1] - y[1], g.ny);
+          const double e2 = min_image(x[2] - y[2], g.nz);
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < close2)) return;
+          if (c == FU_NC) { full = true; return; }
+          sh.lst[t][c++] = j;
+          if (fu_level(sh, j, K) <= lv + 1) return;
+          const int at = atomicAdd(&sh.nreq, 1);
+          if (at < FU_NS) sh.req[at] = FuSpan{j, j + 1, lv + 1};
+          else sh.ovf = 1;
+        };
+#pragma unroll
+        for (int k = 0; k < FU_LD; ++k)
+          if (k < cnt) take(e[k], pj[k]);
+        for (int k = FU_LD; k < cnt; ++k) {
+          const int j = row[k];
+          const double y[3] = {rin[3 * (so + j)], rin[3 * (so + j) + 1], rin[3 * (so + j) + 2]};
+          take(j, y);
+        }
+        if (full) sh.ovf = 1;
+        sh.lcnt[t] = (unsigned char)c;
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      int c = 0, why = -1;
+      if (sh.far) { c = 2; why = 0; }
+      else if (sh.ovf) { c = 2; why = 1; }
+      else if (sh.nreq == 0) c = 1;
+      else if (sh.nspan + sh.nreq > FU_NS) { c = 2; why = 2; }
+      else {
+        for (int k = 0; k < sh.nreq; ++k) sh.span[sh.nspan + k] = sh.req[k];
+        sh.nspan += sh.nreq;
+        if (!fu_build(sh, K, nb)) { c = 2; why = 2; }
+        else if (round + 1 == FU_ROUNDS) { c = 2; why = 3; }   // the closure did not settle
+      }
+      if (why >= 0) atomicAdd(&d.ctrl->fused_why[why], 1u);
+      sh.ctl = c;
+      sh.nreq = 0;
+    }
+  }
+  if (sh.ctl != 1) {                              // uniform: read after the barrier
+    if (t == 0) fu_fail(d, fb, rep, s0);
+    return;
+  }
+  const int n = sh.ioff[sh.niv];
+  // ---- sub-steps: FU_LANES lanes per bead b of S.  Lanes 0-2 evaluate
+  // component l of the angle centred at the bead, lane 3 its two bond forces;
+  // lane 0 (the lead) then adds every contribution in the order of the
+  // sub-step kernel, kicks and drifts the bead.
+  const int b = t / FU_LANES, l = t % FU_LANES;
+  const bool act = b < n;
+  const bool lead = act && l == 0;
+  const int q = act ? fu_chain(sh, b) : 0;
+  const int slot = so + q;
+  const bool own = lead && q >= seg.a && q < seg.b;
+  const int lm1 = act && q > 0 ? fu_local(sh, q - 1) : -1;
+  const int lp1 = act && q < nb - 1 ? fu_local(sh, q + 1) : -1;
+  const bool angle_here = act && q >= 1 && q <= nb - 2 && lm1 >= 0 && lp1 >= 0;
+  double rp[3] = {0.0, 0.0, 0.0}, rm0[3] = {0.0, 0.0, 0.0}, vo[3] = {0.0, 0.0, 0.0}, Jo[3] = {0.0, 0.0, 0.0};
+  double ul[3] = {0.0, 0.0, 0.0};
+  int lc = 0;
+  if (lead) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      rp[a] = rin[3 * slot + a];
+      rm0[a] = rp[a];
+      vo[a] = vin[3 * slot + a];
+      Jo[a] = Jin[3 * slot + a];
+      ul[a] = P.couple ? d.up[3 * slot + a] : 0.0;
+      sh.pos[0][b][a] = rp[a];
+    }
+    sh.angok[b] = angle_here ? 1 : 0;
+    // partners to local indices (a bead of level < K has every close
+    // partner in S by the closure; one that did not would be left out rather
+    // than read outside S; a bead of level K needs none)
+    const int c0 = sh.lev[b] < K ? sh.lcnt[b] : 0;
+    for (int k = 0; k < c0; ++k) {
+      const int lj = fu_local(sh, sh.lst[b][k]);
+      if (lj >= 0) sh.lst[b][lc++] = lj;
+    }
+  }
+  bool viol = false, fin = true;
+  double rfin[3] = {0.0, 0.0, 0.0};
+  double xn[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) xn[a] = lead && P.sig != 0.0 ? d.xi[(size_t)3 * ((size_t)s0 * nslots + slot) + a] : 0.0;
+  __syncthreads();
+  for (int s = s0; s < s0 + K; ++s) {
+    const int cb = (s - s0) & 1;
+    double xl[3] = {xn[0], xn[1], xn[2]};
+    if (lead && P.sig != 0.0 && s + 1 < s0 + K) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xn[a] = d.xi[(size_t)3 * ((size_t)(s + 1) * nslots + slot) + a];
+    }
+    // ---- phase 1: angle components, bonds
+    if (act) {
+      if (l < 3) {
+        if (angle_here) {
+          double f[3];
+          angle_component(P, sh.pos[cb][lm1], sh.pos[cb][b], sh.pos[cb][lp1], l, f);
+          sh.ang[b][l] = f[0]; sh.ang[b][3 + l] = f[1]; sh.ang[b][6 + l] = f[2];
+        }
+      } else {
+        double F1[3] = {0.0, 0.0, 0.0}, F2[3] = {0.0, 0.0, 0.0};
+        if (!P.constrained) {
+          if (q > 0 && lm1 >= 0) bond_add(P, sh.pos[cb][b], sh.pos[cb][lm1], F1);
+          if (q < nb - 1 && lp1 >= 0) bond_add(P, sh.pos[cb][b], sh.pos[cb][lp1], F2);
+        }
+        for (int a = 0; a < 3; ++a) { sh.bnd[b][a] = F1[a]; sh.bnd[b][3 + a] = F2[a]; }
+      }
+    }
+    __syncthreads();
+    // ---- phase 2: the lead adds, kicks and drifts
+    if (lead) {
+      double F[3] = {0.0, 0.0, 0.0};
+      if (!P.constrained) {
+        if (q > 0 && lm1 >= 0) { F[0] += sh.bnd[b][0]; F[1] += sh.bnd[b][1]; F[2] += sh.bnd[b][2]; }
+        if (q < nb - 1 && lp1 >= 0) { F[0] += sh.bnd[b][3]; F[1] += sh.bnd[b][4]; F[2] += sh.bnd[b][5]; }
+      }
+      if (q - 1 >= 1 && q - 1 <= nb - 2 && lm1 >= 0 && sh.angok[lm1]) {
+        const double* A = sh.ang[lm1]; F[0] += A[6]; F[1] += A[7]; F[2] += A[8];
+      }
+      if (angle_here) { const double* A = sh.ang[b]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
+      if (q + 1 >= 1 && q + 1 <= nb - 2 && lp1 >= 0 && sh.angok[lp1]) {
+        const double* A = sh.ang[lp1]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2];
+      }
+      for (int k = 0; k < lc; ++k) {
+        const double* qp = sh.pos[cb][sh.lst[b][k]];
+        const double e0 = min_image(rp[0] - qp[0], g.nx);
+        const double e1 = min_image(rp[1] - qp[1], g.ny);
+        const double e2 = min_image(rp[2] - qp[2], g.nz);
+        if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+        double Fp[3] = {0.0, 0.0, 0.0};
+        lj_add(P, e0, e1, e2, Fp);
+        F[0] += Fp[0]; F[1] += Fp[1]; F[2] += Fp[2];
+      }
+      fu_wall(P, g, rp, F);
+      if (P.field_on && in_field(g, rp)) F[g.wall_axis] += P.f_drive;
+      const bool fl = last && s == s0 + K - 1;
+      double x[3];
+      fin = fu_kick(P, F, ul, xl, vo, Jo, rp, fl, x) && fin;
+      if (fl) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) rfin[a] = x[a];
+      } else {
+        double dd2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          rp[a] = x[a];
+          sh.pos[cb ^ 1][b][a] = x[a];
+          const double dm = x[a] - rm0[a];
+          dd2 += dm * dm;
+        }
+        // the positions of the block's next sub-steps stay within the bound
+        if (own && s + 1 < s0 + K && !(dd2 <= FUSED_DELTA * FUSED_DELTA)) viol = true;
+      }
+    }
+    __syncthreads();
+  }
+  if (own && !fin) atomicOr(&d.ctrl->err, E_BEADS);
+  if (__syncthreads_or(viol ? 1 : 0)) {
+    if (t == 0) {
+      atomicAdd(&d.ctrl->fused_why[4], 1u);
+      fu_fail(d, fb, rep, s0);
+    }
+    return;
+  }
+  if (blockIdx.x == 0 && t == 0) atomicAdd((unsigned long long*)&d.ctrl->fused_blocks, 1ull);
+  if (!own) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vout[3 * slot + a] = vo[a];
+    Jout[3 * slot + a] = Jo[a];
+    if (last) d.r[3 * slot + a] = rfin[a];
+    else rout[3 * slot + a] = rp[a];
+  }
+}
+
+// After the fused blocks, one workgroup per replica.  A replica whose block
+// failed at sub-step sp is redone from that block's start state to the end
+// of the cycle, sub-step by sub-step, with barriers: the angles of every
+// centre, then every bead's force, kick and drifts; the positions alternate
+// between r_mid0 and r_mid1.  A bead's pair partners within r_c, in
+// ascending order, come from the step's neighbour lists while every bead
+// lies within half the skin of where they were built, else from the cell
+// table while every bead lies within CELL_MARGIN of where it was binned,
+// else from all beads of the chain.  A replica whose last block wrote the
+// shadow set gets v and J copied back.
+constexpr int RD_WG = 1024;
+constexpr int RD_NC = 32;          // pair partners within r_c of one bead
+
+__global__ __launch_bounds__(RD_WG) void k_md_redo(Dev d, FusedBufs fb, double* ang, int nslots, int n_sub, int K) {
+  __shared__ int any_far, any_off;
+  const int rep = blockIdx.x;
+  const Rep& R = d.reps[rep];
+  const MdParams P = R.mp;
+  const Geom g = R.g;
+  const int so = R.slot_off, nb = P.nb;
+  const int t = threadIdx.x;
+  const int sp = fb.redo[rep];                    // constant during this launch
+  const int M = n_sub / K;
+  if (sp < 0) {
+    if (M & 1)
+      for (int q = t; q < nb; q += RD_WG)
+        for (int a = 0; a < 3; ++a) {
+          d.v[3 * (so + q) + a] = fb.vS[3 * (so + q) + a];
+          d.J[3 * (so + q) + a] = fb.JS[3 * (so + q) + a];
+        }
+    return;
+  }
+  // the failed block's start state into r_mid0, v, J
+  if ((sp / K) & 1)
+    for (int q = t; q < nb; q += RD_WG)
+      for (int a = 0; a < 3; ++a) {
+        const int i = 3 * (so + q) + a;
+        d.rmid0[i] = fb.rmS[i];
+        d.v[i] = fb.vS[i];
+        d.J[i] = fb.JS[i];
+      }
+  if (t == 0) atomicAdd((unsigned long long*)&d.ctrl->substeps, (unsigned long long)(n_sub - sp));
+  bool fin = true, over = false;
+  for (int s = sp; s < n_sub; ++s) {
+    const double* cur = ((s - sp) & 1) ? d.rmid1 : d.rmid0;
+    double* nxt = ((s - sp) & 1) ? d.rmid0 : d.rmid1;
+    // every bead near the position the lists were built at, the position
+    // the table binned it at?
+    bool near = true, held = d.rb[4 * rep] == 0u;
+    for (int q = t; q < nb; q += RD_WG) {
+      double b2 = 0.0, f2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        const double x = cur[3 * (so + q) + a];
+        const double db = x - d.rbin[3 * (so + q) + a], df = x - d.ref[3 * (so + q) + a];
+        b2 += db * db;
+        f2 += df * df;
+      }
+      near = near && b2 <= CELL_MARGIN * CELL_MARGIN;
+      held = held && f2 <= P.halfskin2;
+    }
+    if (t == 0) { any_far = 0; any_off = 0; }
+    __syncthreads();                              // also orders the previous sub-step's writes
+    if (!near) any_far = 1;
+    if (!held) any_off = 1;
+    for (int q = t; q < nb; q += RD_WG)
+      if (q >= 1 && q <= nb - 2)
+        fu_angle(P, &cur[3 * (so + q - 1)], &cur[3 * (so + q)], &cur[3 * (so + q + 1)], &ang[9 * (size_t)(so + q)]);
+    __syncthreads();
+    const bool lists = any_off == 0, table = any_far == 0;
+    for (int q = t; q < nb; q += RD_WG) {
+      const int sl = so + q;
+      const double rp[3] = {cur[3 * sl], cur[3 * sl + 1], cur[3 * sl + 2]};
+      int part[RD_NC];
+      int np = 0;
+      if (lists) {
+        const int cnt = d.ncnt[sl];
+        for (int k = 0; k < cnt && np <= RD_NC; ++k) {
+          const int j = d.nbr[(size_t)sl * MAXNBR + k];
+          const double e0 = min_image(rp[0] - cur[3 * (so + j)], g.nx);
+          const double e1 = min_image(rp[1] - cur[3 * (so + j) + 1], g.ny);
+          const double e2 = min_image(rp[2] - cur[3 * (so + j) + 2], g.nz);
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+          if (np < RD_NC) part[np] = j;
+          ++np;
+        }
+      } else if (table) {
+        np = cell_partners(d, R, rep, cur, q, rp, P.rc2, part, RD_NC);
+      } else {
+        for (int j = 0; j < nb && np <= RD_NC; ++j) {
+          if (j == q) continue;
+          const double e0 = min_image(rp[0] - cur[3 * (so + j)], g.nx);
+          const double e1 = min_image(rp[1] - cur[3 * (so + j) + 1], g.ny);
+          const double e2 = min_image(rp[2] - cur[3 * (so + j) + 2], g.nz);
+          if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+          if (np < RD_NC) part[np] = j;
+          ++np;
+        }
+      }
+      if (np > RD_NC) { over = true; np = RD_NC; }
+      const double* a3 = (q - 1 >= 1 && q - 1 <= nb - 2) ? &ang[9 * (size_t)(sl - 1)] : nullptr;
+      const double* ac = (q >= 1 && q <= nb - 2) ? &ang[9 * (size_t)sl] : nullptr;
+      const double* a1 = (q + 1 >= 1 && q + 1 <= nb - 2) ? &ang[9 * (size_t)(sl + 1)] : nullptr;
+      double F[3];
+      fu_force(P, g, q, rp, q > 0 ? &cur[3 * (sl - 1)] : nullptr, q < nb - 1 ? &cur[3 * (sl + 1)] : nullptr, a3, ac,
+               a1, cur + 3 * (size_t)so, part, np, F);
+      double v[3] = {d.v[3 * sl], d.v[3 * sl + 1], d.v[3 * sl + 2]};
+      double J[3] = {d.J[3 * sl], d.J[3 * sl + 1], d.J[3 * sl + 2]};
+      double u[3] = {d.up[3 * sl], d.up[3 * sl + 1], d.up[3 * sl + 2]};
+      double xi[3] = {0.0, 0.0, 0.0};
+      if (P.sig != 0.0)
+        for (int a = 0; a < 3; ++a) xi[a] = d.xi[(size_t)3 * ((size_t)s * nslots + sl) + a];
+      const bool fl = s == n_sub - 1;
+      double x[3];
+      fin = fu_kick(P, F, u, xi, v, J, rp, fl, x) && fin;
+      for (int a = 0; a < 3; ++a) {
+        d.v[3 * sl + a] = v[a];
+        d.J[3 * sl + a] = J[a];
+        if (fl) d.r[3 * sl + a] = x[a];
+        else nxt[3 * sl + a] = x[a];
+      }
+    }
+    __syncthreads();                              // the angle buffer is rewritten next
+  }
+  if (!fin) atomicOr(&d.ctrl->err, E_BEADS);
+  if (over) atomicOr(&d.ctrl->err, E_NBRLIST);
+}
+
+void launch_md_cycle_fused(const Dev& d, const FusedBufs& fb, int nseg, int nslots, int nrep, int n_sub, int K,
+                           hipStream_t s) {
+  if (nslots <= 0 || n_sub <= 0 || nseg <= 0) return;
+  const int M = n_sub / K;
+  for (int j = 0; j < M; ++j)
+    hipLaunchKernelGGL(k_md_fused, dim3((unsigned)nseg), dim3(FU_WG), 0, s, d, fb, nslots, j * K, K,
+                       j == M - 1 ? 1 : 0, j & 1);
+  hipLaunchKernelGGL(k_md_redo, dim3((unsigned)nrep), dim3(RD_WG), 0, s, d, fb, fb.ang, nslots, n_sub, K);
 }
 
 void launch_md_noise(const Dev& d, int nslots, int n_sub, int step_offset, hipStream_t s) {

@@ -43,6 +43,7 @@ class LbDesc(C.Structure):
         ("gamma", C.c_double), ("kT", C.c_double), ("f_drive", C.c_double),
         ("n_sub", C.c_int32), ("seed", C.c_uint32), ("replica", C.c_uint32),
         ("fluid_kT", C.c_double), ("mts_outer", C.c_int32), ("coupling", C.c_int32), ("constraints", C.c_int32),
+        ("md_block", C.c_int32),
     ]
 
 
@@ -92,6 +93,7 @@ def _declare(L):
     L.lb_ensemble_run.argtypes = [P, C.c_int, C.c_int]
     L.lb_ensemble_translocation.argtypes = [P, C.POINTER(C.c_int64)]
     L.lb_sweep_config.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
+    L.lb_md_fused.argtypes = [P, C.c_int]
     L.lb_autotune.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.lb_autotune_step.argtypes = [P, C.c_int, P, C.c_size_t, C.POINTER(C.c_int), C.POINTER(C.c_double)]
     L.md_relax.argtypes = [P, C.c_int, C.c_double]
@@ -153,6 +155,7 @@ def _fill_desc(d, cfg, precision):
     d.mts_outer = cfg.get("mts_outer", 0)
     d.coupling = cfg.get("coupling", 0)
     d.constraints = cfg.get("constraints", 0)
+    d.md_block = cfg.get("md_block", 0)
 
 
 def make_descs(cfgs, precision=LB_FP64):
@@ -299,6 +302,11 @@ class Context:
                                          C.c_void_p(out.data_ptr())))
         return out
 
+    def md_fused(self, K):
+        """Sub-steps per fused launch of the uniform MD sub-cycle (0: one
+        launch per sub-step); see lb_md_fused."""
+        _raise(lib().lb_md_fused(self.ctx, int(K)))
+
     def sweep_config(self, tile_nodes, order=0, grid=0, cap=0):
         _raise(lib().lb_sweep_config(self.ctx, int(tile_nodes), int(order), int(grid), int(cap)))
 
@@ -333,10 +341,11 @@ class Context:
         return a.value, b.value, n.value
 
     def diagnostics(self):
-        out = (C.c_int64 * 7)()
+        out = (C.c_int64 * 14)()
         _raise(lib().lb_diagnostics(self.ctx, out))
         return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps", "forced_total",
-                         "cell_rebuilds"), list(out)))
+                         "cell_rebuilds", "fused_blocks", "fused_redos", "why_moved", "why_partners",
+                         "why_capacity", "why_unsettled", "why_displacement"), list(out)))
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))
