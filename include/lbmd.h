@@ -147,14 +147,6 @@ typedef struct lb_desc {
                              after the kick the relative velocities along the
                              bonds are removed.  Needs mts_outer = 0 and
                              nb <= 1024                                      */
-  int32_t md_block;       /* 0: one launch per MD sub-step.  K in [2, 10]
-                             dividing n_sub: the context also supports the
-                             fused sub-cycle of blocks of K sub-steps
-                             (lb_md_fused), with the neighbour lists of every
-                             chain built at every LB step with a skin of 1.2;
-                             it starts in that mode.  Needs mts_outer = 0,
-                             harmonic bonds and a chain; all replicas share
-                             it                                              */
 } lb_desc;
 
 /* Byte sizes of the caller-allocated device buffers (256-byte aligned), and
@@ -261,20 +253,21 @@ int lb_ensemble_run(lb_ctx* ctx, int nsteps, int use_graph);
  * (nrep int64). */
 int lb_ensemble_translocation(lb_ctx* ctx, int64_t* out_host);
 
-/* In a context created with md_block = K0 > 0, the uniform MD sub-cycle
- * (mts_outer = 0, harmonic bonds) can run in blocks of K sub-steps, one
- * launch per block: each workgroup advances a chain segment and recomputes
- * the beads that can reach it within the block (chain neighbours, and pair
- * partners closer than r_c + 0.2 from the step's neighbour lists), then
- * certifies the result (no bead moved more than 0.1 within the block, and
- * every bead was within half the list skin less 0.1 of where the lists were
- * built).  A replica whose block cannot be certified is redone from that
- * block's start by one workgroup (a launch that returns at once when nothing
- * is to be redone), so results equal the per-sub-step cycle of the same
- * context bit for bit.  lb_md_fused(ctx, 0) switches to one launch per
- * sub-step, K > 0 sets the block length.  Drops the captured graph.
- * LB_ERR_UNSUPPORTED: K > 0 in a context created with md_block = 0;
- * LB_ERR_ARG: K < 0, or K not dividing n_sub, below 2 or above K0. */
+/* The uniform MD sub-cycle (mts_outer = 0, harmonic bonds) can run in
+ * blocks of K sub-steps, one launch per block (off by default: on the
+ * workloads measured it is slower than one launch per sub-step): each
+ * workgroup advances a chain segment and recomputes the beads that can reach
+ * it within the block (chain neighbours, and pair partners closer than
+ * r_c + 0.2 from the step's neighbour lists), then certifies the result (no
+ * bead moved more than 0.1 within the block, and every bead was within half
+ * the list skin less 0.1 of where the lists were built).  A replica whose
+ * block cannot be certified is redone from that block's start by one
+ * workgroup (a launch that returns at once when nothing is to be redone), so
+ * results equal the per-sub-step cycle bit for bit.  lb_md_fused(ctx, 0)
+ * switches back to one launch per sub-step.  Drops the captured graph.
+ * LB_ERR_UNSUPPORTED: K > 0 and the context has no chain, or uses the
+ * multiple-time-step cycle or rigid bonds; LB_ERR_ARG: K < 0, or K not
+ * dividing n_sub, below 2 or above 10. */
 int lb_md_fused(lb_ctx* ctx, int K);
 
 /* Sweep layout: tile_nodes (a multiple of 256) consecutive nodes of one
@@ -437,7 +430,7 @@ int64_t lb_step_count(lb_ctx* ctx);
 int lb_profile_start(lb_ctx* ctx, int max_steps);
 int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* nsteps);
 
-/* Diagnostics: synchronises the stream and writes fourteen int64: out[0] =
+/* Diagnostics: synchronises the stream and writes fifteen int64: out[0] =
  * neighbour-list rebuilds inside sub-cycles (summed over replicas), out[1] =
  * MD sub-step launches that did work (with the fused sub-cycle: sub-steps
  * redone, per replica), out[2] = tiles of the sweep, out[3] = watchdog bits,
@@ -450,8 +443,10 @@ int lb_profile_stop(lb_ctx* ctx, double* mean_lb_ms, double* mean_bead_ms, int* 
  * not valid at the cycle's start, or a bead of its segment farther than half
  * the list skin less 0.1 from where they were built, more than 16 close
  * partners of a bead (or 16 new spans in one round), the dependency cone over
- * its capacity (512 beads in 16 spans), the cone not settled in 6 rounds, a
- * bead of the segment moved more than 0.1 within the block. */
+ * its capacity (128 beads in 16 spans), the cone not settled in 6 rounds, a
+ * bead of the segment moved more than 0.1 within the block; out[14] = the
+ * longest neighbour list a per-step build found so far (more than 48 trips
+ * the watchdog, bit 4, which lb_check reports as LB_ERR_UNSTABLE). */
 int lb_diagnostics(lb_ctx* ctx, int64_t* out);
 
 /* Message of the last failed call on this thread (never NULL). */

@@ -205,11 +205,6 @@ int validate_one(const lb_desc* d, int r) {
   if (d->constraints == 1 && (d->mts_outer != 0 || d->nb > MAX_CONSTRAINED_BEADS))
     return fail(LB_ERR_ARG, "replica %d: rigid bonds need the uniform sub-cycle and at most %d beads", r,
                 MAX_CONSTRAINED_BEADS);
-  if (d->md_block != 0 &&
-      (d->md_block < 2 || d->md_block > FUSED_K || d->n_sub % d->md_block != 0 || d->mts_outer != 0 ||
-       d->constraints != 0))
-    return fail(LB_ERR_ARG, "replica %d: md_block must be 0, or divide n_sub and lie in [2, %d] with the uniform "
-                            "sub-cycle and harmonic bonds", r, FUSED_K);
   if (d->mts_outer > 0 && (d->n_sub % d->mts_outer != 0 || d->n_sub / d->mts_outer > MTS_MAX_INNER))
     return fail(LB_ERR_ARG, "replica %d: mts_outer must divide n_sub into at most %d sub-steps per outer step", r,
                 MTS_MAX_INNER);
@@ -238,7 +233,6 @@ int validate(const lb_desc* d, int nrep) {
     if (d[r].precision != d[0].precision) return fail(LB_ERR_ARG, "replica %d: all replicas need one precision", r);
     if (d[r].n_sub != d[0].n_sub) return fail(LB_ERR_ARG, "replica %d: all replicas need one n_sub", r);
     if (d[r].mts_outer != d[0].mts_outer) return fail(LB_ERR_ARG, "replica %d: all replicas need one mts_outer", r);
-    if (d[r].md_block != d[0].md_block) return fail(LB_ERR_ARG, "replica %d: all replicas need one md_block", r);
     nodes += round_up((long)d[r].nx * d[r].ny * d[r].nz, NODE_ALIGN);
     slots += round_up(d[r].nb, MD_BPB);
   }
@@ -806,15 +800,21 @@ int lb_ensemble_init(const lb_desc* d, int nrep, const lb_buffers* b, const doub
   c->sl = state_layout(d, nrep, c->pk);
   c->nslots = c->pk.slots;
   c->maxlist = 8 * c->nslots;
-  for (int r = 0; r < nrep; ++r) c->step_lists = c->step_lists || d[r].nb >= STEP_LISTS_MIN_BEADS;
-  // the fused sub-cycle (asked for at creation; uniform sub-steps, harmonic
-  // bonds) certifies its blocks against lists built at every LB step
-  if (d[0].md_block > 0 && c->pk.nseg > 0) {
-    c->fusedK_max = d[0].md_block;
-    c->step_lists = true;
-    c->fusedK = c->fusedK_max;
+  // every chain's neighbour lists are built from the cell table at every
+  // coupled step, beside the spreading, with a skin wide enough that a
+  // step's motion rarely forces a rebuild inside the sub-cycle
+  c->step_lists = c->nslots > 0;
+  // the fused sub-cycle (uniform sub-steps, harmonic bonds) is available in
+  // blocks of up to FUSED_K sub-steps; it is off until asked for
+  {
+    bool rigid = false;
+    for (int r = 0; r < nrep; ++r) rigid = rigid || (d[r].constraints == 1 && d[r].nb >= 2);
+    if (d[0].mts_outer == 0 && !rigid && c->pk.nseg > 0)
+      for (int K = FUSED_K; K >= 2; --K)
+        if (d[0].n_sub % K == 0) { c->fusedK_max = K; break; }
+    c->fusedK = 0;
   }
-  const double skin = c->fusedK_max > 0 ? SKIN_FUSED : (c->step_lists ? SKIN_STEP : SKIN);
+  const double skin = SKIN_STEP;
   const size_t ns = (size_t)c->pk.slots_alloc;
   const long nodes = c->pk.nodes;
 
@@ -1209,6 +1209,7 @@ int lb_diagnostics(lb_ctx* c, int64_t* out) {
   out[7] = (int64_t)h.fused_blocks;
   out[8] = (int64_t)h.fused_redos;
   for (int k = 0; k < 5; ++k) out[9 + k] = (int64_t)h.fused_why[k];
+  out[14] = (int64_t)h.nbr_max;
   return LB_OK;
 }
 
@@ -1223,7 +1224,7 @@ int lb_ensemble_translocation(lb_ctx* c, int64_t* out_host) {
 int lb_md_fused(lb_ctx* c, int K) {
   if (!c || K < 0) return fail(LB_ERR_ARG, "bad arguments");
   if (K > 0 && c->fusedK_max == 0)
-    return fail(LB_ERR_UNSUPPORTED, "the fused sub-cycle needs a context created with md_block > 0 and a chain");
+    return fail(LB_ERR_UNSUPPORTED, "the fused sub-cycle needs the uniform sub-cycle, harmonic bonds and a chain");
   if (K > 0 && (K < 2 || K > c->fusedK_max || c->n_sub % K != 0))
     return fail(LB_ERR_ARG, "block length must divide n_sub and lie in [2, %d]", c->fusedK_max);
   if (K != c->fusedK) drop_graph(c);

@@ -84,15 +84,19 @@ constexpr uint32_t E_SPREAD = 8u;    // too many beads share a node stencil
 
 constexpr int MAXNBR = 48;        // neighbour-list capacity per bead
 constexpr int MAXCONTRIB = 64;    // bead contributions gathered per node
-constexpr double SKIN = 0.4;      // neighbour-list skin (lists rebuilt when a bead moved skin/2)
-constexpr double SKIN_STEP = 0.6; // skin when lists are rebuilt at every coupled step (long chains)
-constexpr double SKIN_FUSED = 1.2;// skin of the per-step lists of the fused sub-cycle: a block certifies while
-                                  // every bead is within SKIN_FUSED / 2 - 0.1 of where the lists were built
-constexpr int STEP_LISTS_MIN_BEADS = 1024;  // chains this long get per-step cell-list builds
+// Neighbour-list skin.  The lists are built at every coupled step and stay
+// valid while no bead moved more than SKIN_STEP / 2 from where they were
+// built; 1.2 covers a step's motion of a driven chain (narrower skins
+// forced a rebuild inside the sub-cycle in about one step of four at 0.8,
+// every step at 0.6).  A sphere of r_c + 1.2 = 2.32 around a bead holds
+// about 44 others at the density of a dense LJ liquid (0.85 per sigma^3),
+// below MAXNBR; denser packing trips the list-overflow watchdog.
+constexpr double SKIN_STEP = 1.2;
 // Cells of the neighbour-search table are at least r_c + skin + CELL_MARGIN
 // wide, so the table stays usable for a rebuild inside a sub-cycle while no
-// bead has moved more than CELL_MARGIN from where it was binned.
-constexpr double CELL_MARGIN = 0.5;
+// bead has moved more than CELL_MARGIN from where it was binned.  It exceeds
+// half the skin, so the first rebuild a cycle needs can use the table.
+constexpr double CELL_MARGIN = 0.7;
 
 // Control block at the head of the work buffer.
 struct Ctrl {
@@ -110,7 +114,8 @@ struct Ctrl {
   // partners, the set over its capacity, the closure not settled, a bead past
   // the displacement bound
   uint32_t fused_why[5];
-  uint32_t pad[43];
+  uint32_t nbr_max;          // longest neighbour list a per-step build found (diagnostic)
+  uint32_t pad[42];
 };
 static_assert(sizeof(Ctrl) == 256, "control block is one 256-byte line");
 

@@ -803,6 +803,9 @@ __global__ __launch_bounds__(LB_LANES * LB_BEADS) void k_list_build(Dev d, int n
   // ascending chain order, the MAXNBR smallest kept
   int nc = ncand[lb];
   if (nc > MAXNBR) atomicOr(&d.ctrl->err, E_NBRLIST);
+  // read first: once the maximum is reached, most beads skip the atomic
+  if ((uint32_t)nc > __hip_atomic_load(&d.ctrl->nbr_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&d.ctrl->nbr_max, (uint32_t)nc);
   if (nc > LB_CAND) nc = LB_CAND;
   int* c = cand[lb];
   for (int i = 1; i < nc; ++i) {

@@ -43,7 +43,6 @@ class LbDesc(C.Structure):
         ("gamma", C.c_double), ("kT", C.c_double), ("f_drive", C.c_double),
         ("n_sub", C.c_int32), ("seed", C.c_uint32), ("replica", C.c_uint32),
         ("fluid_kT", C.c_double), ("mts_outer", C.c_int32), ("coupling", C.c_int32), ("constraints", C.c_int32),
-        ("md_block", C.c_int32),
     ]
 
 
@@ -155,7 +154,6 @@ def _fill_desc(d, cfg, precision):
     d.mts_outer = cfg.get("mts_outer", 0)
     d.coupling = cfg.get("coupling", 0)
     d.constraints = cfg.get("constraints", 0)
-    d.md_block = cfg.get("md_block", 0)
 
 
 def make_descs(cfgs, precision=LB_FP64):
@@ -341,11 +339,11 @@ class Context:
         return a.value, b.value, n.value
 
     def diagnostics(self):
-        out = (C.c_int64 * 14)()
+        out = (C.c_int64 * 15)()
         _raise(lib().lb_diagnostics(self.ctx, out))
         return dict(zip(("rebuilds", "substeps", "sweep_tiles", "watchdog", "steps", "forced_total",
                          "cell_rebuilds", "fused_blocks", "fused_redos", "why_moved", "why_partners",
-                         "why_capacity", "why_unsettled", "why_displacement"), list(out)))
+                         "why_capacity", "why_unsettled", "why_displacement", "nbr_max"), list(out)))
 
     def step_count(self):
         return int(lib().lb_step_count(self.ctx))

@@ -83,12 +83,6 @@ def test_desc_layout_matches_header(tmp_path):
     (dict(constraints=2), "constraints"),
     (dict(constraints=1, nb=2000, shape=(64, 64, 64)), "rigid bonds"),
     (dict(constraints=1, mts_outer=5), "rigid bonds"),
-    (dict(md_block=3), "md_block"),
-    (dict(md_block=1), "md_block"),
-    (dict(md_block=20), "md_block"),
-    (dict(md_block=-2), "md_block"),
-    (dict(md_block=10, mts_outer=5), "md_block"),
-    (dict(md_block=10, constraints=1), "md_block"),
 ])
 def test_host_validation(bad, msg):
     from paper_0711_2665_amd import lbmd

@@ -1,5 +1,5 @@
-"""The fused MD sub-cycle (opt-in at creation with md_block; blocks of K
-sub-steps per launch, each workgroup
+"""The fused MD sub-cycle (off by default; blocks of K sub-steps per
+launch, each workgroup
 recomputing the chain neighbours and close partners that can reach its
 segment) against one launch per sub-step, through the C ABI: bit for bit on
 every population and bead field, with the bead noise and bending on (both
@@ -9,9 +9,7 @@ segments with their per-step lists, an ensemble of uneven replicas replayed
 from the captured graph, block lengths 10, 5 and 2, and a drifting chain
 fast enough to leave the cell table's margin inside the cycle, so that
 blocks fail their check and the replica is redone from the failed block by
-one workgroup.  Both sides of every comparison are contexts created with
-md_block = 10 (lists built at every step with the fused skin), one switched
-to a launch per sub-step."""
+one workgroup."""
 import numpy as np
 import pytest
 
@@ -46,10 +44,9 @@ def _same(a, b, tag):
 
 def _pair(cfg, precision, relax=300):
     from paper_0711_2665_amd import lbmd
-    cfg = scaled(cfg, md_block=10)
     r, v = initial_chain(cfg)
     sims = []
-    for K in (None, 0):
+    for K in (10, None):
         s = lbmd.Simulation(cfg, r, v, precision=precision)
         s.relax(relax, 1.0)
         if K is not None:
@@ -100,10 +97,10 @@ def test_fused_drifting_chain_redoes_failed_blocks():
     launch per sub-step (whose lists are rebuilt inside the cycle)."""
     torch = _torch()
     from paper_0711_2665_amd import lbmd
-    cfg = scaled(C0, shape=(40, 40, 40), wall_pos=20, nb=1100, init_seed=9, md_block=10)
+    cfg = scaled(C0, shape=(40, 40, 40), wall_pos=20, nb=1100, init_seed=9)
     r, v = initial_chain(cfg)
     sims = []
-    for K in (None, 0):
+    for K in (2, None):
         s = lbmd.Simulation(cfg, r, v, precision=lbmd.LB_FP64)
         s.relax(300, 1.0)
         vv = np.zeros((cfg["nb"], 3))
@@ -113,7 +110,6 @@ def test_fused_drifting_chain_redoes_failed_blocks():
             s.md_fused(K)
         sims.append(s)
     fused, plain = sims
-    fused.md_fused(2)
     fused.couple_step(3)
     plain.couple_step(3)
     _same(_state(fused), _state(plain), "drifting 1100 beads")
@@ -130,13 +126,13 @@ def test_fused_ensemble_graph_replay(prec):
     torch = _torch()
     from paper_0711_2665_amd import lbmd
     p = lbmd.LB_FP64 if prec == "fp64" else lbmd.LB_FP32_DEV
-    cfgs = [scaled(C0, shape=(32, 32, 32), nb=20, seed=3, replica=0, md_block=10),
-            scaled(C0, shape=(40, 36, 44), wall_pos=22, nb=700, seed=4, replica=1, init_seed=4, md_block=10),
-            scaled(C0, shape=(24, 24, 24), wall_axis=-1, wall_pos=0, pore_h=0, nb=0, replica=2, md_block=10),
-            scaled(C0, shape=(36, 36, 36), wall_pos=18, nb=260, seed=5, replica=3, init_seed=6, md_block=10)]
+    cfgs = [scaled(C0, shape=(32, 32, 32), nb=20, seed=3, replica=0),
+            scaled(C0, shape=(40, 36, 44), wall_pos=22, nb=700, seed=4, replica=1, init_seed=4),
+            scaled(C0, shape=(24, 24, 24), wall_axis=-1, wall_pos=0, pore_h=0, nb=0, replica=2),
+            scaled(C0, shape=(36, 36, 36), wall_pos=18, nb=260, seed=5, replica=3, init_seed=6)]
     r0s = [initial_chain(c)[0] if c["nb"] > 0 else None for c in cfgs]
     ens = []
-    for K in (None, 0):
+    for K in (10, None):
         e = lbmd.Ensemble(cfgs, r0s, precision=p)
         e.relax(300, 1.0)
         if K is not None:
@@ -153,14 +149,16 @@ def test_fused_ensemble_graph_replay(prec):
 def test_fused_switch_is_validated():
     _torch()
     from paper_0711_2665_amd import lbmd
-    s = lbmd.Simulation(scaled(C0, md_block=10), initial_chain(C0)[0])
+    s = lbmd.Simulation(C0, initial_chain(C0)[0])
+    assert s.diagnostics()["fused_blocks"] == 0
     for bad in (-1, 1, 3, 20):
         with pytest.raises(lbmd.LbError):
             s.md_fused(bad)
     s.md_fused(5)
     s.md_fused(0)
-    plain = lbmd.Simulation(C0, initial_chain(C0)[0])
+    mts = scaled(C0, mts_outer=5)
+    m = lbmd.Simulation(mts, initial_chain(mts)[0])
     with pytest.raises(lbmd.LbError) as e:
-        plain.md_fused(10)
+        m.md_fused(10)
     assert e.value.code == lbmd.LB_ERR_UNSUPPORTED
-    plain.md_fused(0)
+    m.md_fused(0)

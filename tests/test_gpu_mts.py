@@ -85,7 +85,7 @@ def test_mts_long_chain_across_segments_bitwise(orc):
     o.relax(300, 1.0)
     r0 = o.beads()["r"]
     v0 = np.zeros_like(r0)
-    v0[:, 0] = 0.45
+    v0[:, 0] = 0.9
     o = orc.Oracle(cfg, r0, v0)
     s = lbmd.Simulation(cfg, r0, v0)
     o.couple_step(3)

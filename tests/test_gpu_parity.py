@@ -303,12 +303,12 @@ def test_long_chain_with_per_step_lists_bitwise(orc):
 
 
 def test_long_chain_rebuilds_inside_the_cycle_bitwise(orc):
-    """The 1100-bead chain with a uniform drift of 0.45 per step parallel to
+    """The 1100-bead chain with a uniform drift of 1.5 per step parallel to
     the wall: beads pass half the skin inside a sub-cycle, so lists are
     rebuilt there -- from the cell table while every bead is within its
     margin of where it was binned, else by the full scan.  Three coupled
-    steps (kT = 0, kappa = 0) must equal the oracle bit for bit, and the
-    table must have served some of the rebuilds."""
+    steps (kT = 0, kappa = 0) must equal the oracle bit for bit, and both
+    kinds of rebuild must have run."""
     torch = _torch()
     from paper_0711_2665_amd import lbmd
     cfg = scaled(C0, shape=(40, 40, 40), wall_pos=20, nb=1100, kT=0.0, kappa=0.0, init_seed=9)
@@ -317,7 +317,7 @@ def test_long_chain_rebuilds_inside_the_cycle_bitwise(orc):
     o.relax(300, 1.0)
     r0 = o.beads()["r"]
     v0 = np.zeros_like(r0)
-    v0[:, 0] = 0.45
+    v0[:, 0] = 1.5
     o = orc.Oracle(cfg, r0, v0)
     s = lbmd.Simulation(cfg, r0, v0)
     o.couple_step(3)
@@ -334,7 +334,7 @@ def test_long_chain_rebuilds_inside_the_cycle_bitwise(orc):
     assert np.array_equal(a, b)
     for k in ("r", "v", "up", "J"):
         assert np.array_equal(sb[k], ob[k]), k
-    assert diag["cell_rebuilds"] >= 1 and diag["rebuilds"] >= diag["cell_rebuilds"]
+    assert diag["cell_rebuilds"] >= 1 and diag["rebuilds"] > diag["cell_rebuilds"]
 
 
 def test_long_chain_graph_replay_equals_eager_steps(orc):
