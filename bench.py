@@ -312,21 +312,73 @@ def run_precision_study(steps):
                                  for row in r["series"]]} for r in res]}
 
 
-def run_cpu_baseline(cfg, steps):
-    """The FP64 oracle as it stands, on a bounded sample of the same workload:
-    `steps` coupled steps of the full lattice and chain (the chain given a
-    short oracle relaxation first), all host threads."""
+def cpu_model():
+    """Model name and logical CPU count of the host, from /proc/cpuinfo."""
+    name, n = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    n += 1
+                    name = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return name, n or os.cpu_count()
+
+
+def _time_oracle(cfg, steps, relax):
+    """Seconds of `steps` coupled FP64 oracle steps of the whole workload
+    (after `relax` oracle relaxation sub-steps and one untimed step)."""
     import oracle
     from paper_0711_2665_amd.workloads import initial_chain
     r, v = initial_chain(cfg)
     o = oracle.Oracle(cfg, r, v)
-    o.relax(200, cfg["gamma_relax"])
+    o.relax(relax, cfg["gamma_relax"])
     o.couple_step(1)
     t0 = time.perf_counter()
     o.couple_step(steps)
-    t1 = time.perf_counter()
-    cells = cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2]
-    return dict(value=cells * steps / (t1 - t0) / 1e6, cores=oracle.max_threads(), seconds=t1 - t0)
+    return time.perf_counter() - t0
+
+
+def run_cpu_baseline(cfg, steps, full=True):
+    """The FP64 oracle as it stands, timed on the host: the benchmarked
+    workload on a bounded sample (`steps` coupled steps of the full lattice
+    and chain after a short relaxation) on all host threads and on one; with
+    `full`, also the 32^3 / 20-bead parity workload (200 steps) and the
+    64^3 / 100-bead gradient workload (2000 steps) in full on all threads, a
+    stated sample of each on one thread, and a sample of the 128^3 / 400-bead
+    workload."""
+    import oracle
+    from paper_0711_2665_amd.workloads import C0, C1, C4
+
+    def mlups(c, n, sec):
+        return c["shape"][0] * c["shape"][1] * c["shape"][2] * n / sec / 1e6
+
+    allthr = oracle.max_threads()
+    runs = []
+
+    def one(c, n, thr, relax, what):
+        oracle.set_threads(thr)
+        sec = _time_oracle(c, n, relax)
+        runs.append({"workload": c["name"], "steps": n, "threads": thr, "seconds": round(sec, 2),
+                     "MLUPS": round(mlups(c, n, sec), 3), "what": what})
+        return sec
+
+    try:
+        sec = one(cfg, steps, allthr, 200, "sample")
+        sec1 = one(cfg, 1, 1, 200, "sample")
+        if full:
+            one(C0, C0["steps"], allthr, C0["relax_substeps"], "full")
+            one(C0, C0["steps"], 1, C0["relax_substeps"], "full")
+            one(C4, C4["steps"], allthr, C4["relax_substeps"], "full")
+            one(C4, 50, 1, C4["relax_substeps"], "sample")
+            one(C1, 5, allthr, C1["relax_substeps"], "sample")
+    finally:
+        oracle.set_threads(allthr)
+    model, logical = cpu_model()
+    return dict(value=mlups(cfg, steps, sec), cores=allthr, seconds=sec,
+                single_thread=mlups(cfg, 1, sec1), single_seconds=sec1, runs=runs,
+                cpu_model=model, logical_cpus=logical)
 
 
 def main():
@@ -338,6 +390,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-quick", action="store_true", help="only the benchmarked workload's samples")
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=5000)
@@ -459,11 +512,19 @@ def main():
         out["fp32_vs_fp64"] = run_precision_study(args.c1_steps)
         progress("FP32 against FP64 study done")
     if not args.no_cpu:
-        cb = run_cpu_baseline(cfg, args.cpu_steps)
+        cb = run_cpu_baseline(cfg, args.cpu_steps, full=not args.cpu_quick)
         out["cpu_baseline"] = {"value": round(cb["value"], 3), "unit": "MLUPS", "cores": cb["cores"],
                                "kind": "oracle",
                                "sample": f"{args.cpu_steps} coupled FP64 steps of the full {nx}x{ny}x{nz} lattice "
-                                         f"with the {cfg['nb']}-bead chain ({cb['seconds']:.1f} s)"}
+                                         f"with the {cfg['nb']}-bead chain ({cb['seconds']:.1f} s)",
+                               "cpu_model": cb["cpu_model"], "logical_cpus": cb["logical_cpus"],
+                               "single_thread": {"value": round(cb["single_thread"], 3), "unit": "MLUPS",
+                                                 "sample": f"1 coupled FP64 step of the same lattice and chain "
+                                                           f"({cb['single_seconds']:.1f} s)"},
+                               "runs": cb["runs"],
+                               "note": "the oracle as it stands (plain FP64 C++, OpenMP over nodes), a reported "
+                                       "baseline and not a target"}
+        progress("CPU baseline done")
     print(json.dumps(out), flush=True)
 
 

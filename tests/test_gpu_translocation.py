@@ -21,7 +21,7 @@ def _torch():
 def test_translocation_step_matches_oracle(orc):
     torch = _torch()
     from paper_0711_2665_amd import lbmd
-    cfg = tl.replica_configs(12, 1, edge=16, kT=0.0, kappa=0.0)[0]
+    cfg = tl.replica_configs(12, 1, shape=(16, 16, 16), tau=1.0, kT=0.0, kappa=0.0)[0]
     r, v = initial_chain(cfg)
     o = orc.Oracle(cfg, r, v)
     o.relax(cfg["relax_substeps"], cfg["gamma_relax"])
@@ -45,7 +45,7 @@ def test_translocation_step_matches_oracle(orc):
 def test_campaign_replicas_equal_runs_alone():
     torch = _torch()
     from paper_0711_2665_amd import lbmd
-    res = tl.run_length(10, 4, max_steps=1500, sample_every=25, edge=16)
+    res = tl.run_length(10, 4, max_steps=1500, sample_every=25, shape=(16, 16, 16), tau=1.0)
     total = int(res["steps"][-1])
     print("campaign t_X", res["tX"], "steps run", total, flush=True)
     assert res["obs"].shape == (len(res["steps"]), 4, lbmd.LB_NOBS)
@@ -66,7 +66,7 @@ def test_campaign_replicas_equal_runs_alone():
 
 def test_campaign_driver_over_two_lengths():
     _torch()
-    out = tl.run_campaign([8, 14], 3, max_steps=1500, sample_every=50, edge=16)
+    out = tl.run_campaign([8, 14], 3, max_steps=1500, sample_every=50, shape=(16, 16, 16), tau=1.0)
     print({k: v for k, v in out.items() if k != "lengths"},
           [(s["length"], s["events"], s["most_probable"]) for s in out["lengths"]], flush=True)
     assert [s["length"] for s in out["lengths"]] == [8, 14]

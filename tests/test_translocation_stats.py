@@ -6,6 +6,7 @@ import math
 import numpy as np
 
 from paper_0711_2665_amd import translocation as tl
+from paper_0711_2665_amd.workloads import initial_chain
 
 
 def test_most_probable_time_finds_the_mode_of_a_skewed_distribution():
@@ -38,12 +39,42 @@ def test_scaling_exponent_recovers_a_power_law():
 
 
 def test_replica_configs_follow_the_paper_geometry():
+    # Sec. 4, Numerical Set-up: N_x x N_x/2 x N_x/2 with N_x = 80 up to 400
+    # beads and 100 beyond, the wall normal to x at N_x/2 with a 3 x 3 hole,
+    # kinematic viscosity 0.1, kT = 1e-4, F_drive = 0.02, gamma = 0.1
     cfgs = tl.replica_configs(50, 6)
     assert len(cfgs) == 6 and len({c["seed"] for c in cfgs}) == 6 and len({c["init_seed"] for c in cfgs}) == 6
     for k, c in enumerate(cfgs):
-        assert c["wall_axis"] == 0 and c["wall_pos"] == c["shape"][0] // 2 and c["pore_h"] == 3
+        assert c["shape"] == (80, 40, 40)
+        assert c["wall_axis"] == 0 and c["wall_pos"] == 40 and c["pore_h"] == 3
+        assert abs((c["tau"] - 0.5) / 3.0 - 0.1) < 1e-15
+        assert c["kT"] == 1e-4 and c["f_drive"] == 0.02 and c["gamma"] == 0.1
         assert c["nb"] == 50 and c["replica"] == k
-    assert tl.replica_configs(300, 1)[0]["shape"][0] > tl.replica_configs(50, 1)[0]["shape"][0]
+    assert tl.replica_configs(400, 1)[0]["shape"] == (80, 40, 40)
+    assert tl.replica_configs(500, 1)[0]["shape"] == (100, 50, 50)
+    # the chain starts on one side of the wall with its first bead at the pore
+    c = cfgs[0]
+    r, _ = initial_chain(c)
+    assert (r[:, 0] < c["wall_pos"]).all()
+    assert abs(r[0, 0] - (c["wall_pos"] - 1.0)) < 1e-12
+    assert abs(r[0, 1] - 20.0) < 1e-12 and abs(r[0, 2] - 20.0) < 1e-12
+
+
+def test_lambda_r_and_drive_of_synthetic_events():
+    nobs = 25
+    steps = np.array([0, 10, 20, 30])
+    obs = np.zeros((steps.size, 2, nobs))
+    obs[0, :, tl.OBS["R_U"]] = [4.0, 5.0]
+    obs[:, :, tl.OBS["R_T"]] = [[0.0, 0.0], [1.0, 1.5], [2.0, 2.5], [3.0, 3.5]]
+    obs[:, :, tl.OBS["N_r"]] = 3.0
+    obs[:, :, tl.OBS["drag_U"]] = -0.01
+    obs[:, :, tl.OBS["drag_T"]] = -0.02
+    s = tl.summarize(dict(length=10, tX=[20, 30], obs=obs, steps=steps, f_drive=0.02))
+    assert abs(s["lambda_R"] - 0.5 * (2.0 / 4.0 + 3.5 / 5.0)) < 1e-15
+    assert abs(s["mean_drive"] - 0.06) < 1e-15 and abs(s["mean_drag_total"] + 0.03) < 1e-15
+    # without a start sample lambda_R is not defined
+    s = tl.summarize(dict(length=10, tX=[20, 30], obs=obs[1:], steps=steps[1:], f_drive=0.02))
+    assert np.isnan(s["lambda_R"])
 
 
 def test_summary_of_synthetic_events():
