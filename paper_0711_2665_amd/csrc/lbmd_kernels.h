@@ -100,7 +100,7 @@ struct Dev {
   int* base;        // per slot: base node (replica-local index)
   int2* touched;    // (replica, node) of the nodes carrying bead force
   // MD sub-cycle
-  int* nbr;         // [slot][MAXNBR] chain indices
+  int* nbr;         // [slot][MAXNBR] slots of the partners, ascending
   int* ncnt;        // per slot
   double* ref;      // per slot [3]: positions at the last list build
   double* rmid0;    // per slot [3]: force-evaluation positions, double buffered

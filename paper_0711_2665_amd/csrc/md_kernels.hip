@@ -204,7 +204,7 @@ struct MdShared {
   uint32_t hit[MD_BPB][MD_LANES];            // lane l, bit m: entry l + 4m is within r_c
   uint32_t wmask[MD_BPB][WSPAN];             // row o1 - WLO: which sites o0 - WLO of the row are set
   int cnt[MD_BPB];
-  int lst[MD_BPB][MAXNBR];                   // the neighbour list in use (chain indices)
+  int lst[MD_BPB][MAXNBR];                   // the neighbour list in use (partner slots)
   // the list rebuild's scratch is dead before the wall sites are written
   union {
     struct {
@@ -378,13 +378,12 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
           for (int e = 0; e < n; ++e) {
             const int q = d.cbuf[(size_t)b * CELL_CAP + e];
             if (d.slot_rep[q] != rep || q == slot) continue;
-            const int jj = q - so;
-            double d0 = min_image(rp[0] - rin[3 * jj], g.nx);
-            double d1 = min_image(rp[1] - rin[3 * jj + 1], g.ny);
-            double d2 = min_image(rp[2] - rin[3 * jj + 2], g.nz);
+            double d0 = min_image(rp[0] - rabs[3 * q], g.nx);
+            double d1 = min_image(rp[1] - rabs[3 * q + 1], g.ny);
+            double d2 = min_image(rp[2] - rabs[3 * q + 2], g.nz);
             if (!(d0 * d0 + d1 * d1 + d2 * d2 < P.rlist2)) continue;
             const int at = atomicAdd(&sh.cnt[bslot], 1);
-            if (at < MAXNBR) sh.lst[bslot][at] = jj;
+            if (at < MAXNBR) sh.lst[bslot][at] = q;
             else sh.over = 1;
           }
         }
@@ -429,7 +428,7 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
           while (mm) {
             int tt = __builtin_ctzll(mm);
             mm &= mm - 1;
-            if (c < MAXNBR) sh.lst[bslot][c] = base + tt;
+            if (c < MAXNBR) sh.lst[bslot][c] = so + base + tt;
             else sh.over = 1;
             ++c;
           }
@@ -507,8 +506,8 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     double q[NB_PER_LANE][3];
 #pragma unroll
     for (int m = 0; m < NB_PER_LANE; ++m) {
-      const int j = jl[m] >= 0 ? jl[m] : p0;   // an unused entry reads a valid slot
-      q[m][0] = rin[3 * j]; q[m][1] = rin[3 * j + 1]; q[m][2] = rin[3 * j + 2];
+      const int j = jl[m] >= 0 ? jl[m] : slot0;   // an unused entry reads a valid slot
+      q[m][0] = rabs[3 * j]; q[m][1] = rabs[3 * j + 1]; q[m][2] = rabs[3 * j + 2];
     }
     uint32_t hit = 0;
 #pragma unroll
@@ -538,9 +537,24 @@ __global__ __launch_bounds__(3 * MD_WG) void k_md_substep(Dev d, MdOverride ov, 
     if (p >= 1 && p <= nb - 2) { const double* A = sh.ang[p - q0]; F[0] += A[3]; F[1] += A[4]; F[2] += A[5]; }
     if (p + 1 >= 1 && p + 1 <= nb - 2) { const double* A = sh.ang[p + 1 - q0]; F[0] += A[0]; F[1] += A[1]; F[2] += A[2]; }
   }
-  for (int k = 0; k < cnt_b; ++k) {
-    if (!((sh.hit[bslot][k % MD_LANES] >> (k / MD_LANES)) & 1u)) continue;
-    F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
+  // the list entries with a pair force, in list order: entry k is bit
+  // k / 4 of lane k % 4's word; interleaved into one mask so that only the
+  // hits are visited (lists are much longer than the pairs within r_c)
+  {
+    uint32_t h[MD_LANES];
+#pragma unroll
+    for (int l = 0; l < MD_LANES; ++l) h[l] = sh.hit[bslot][l];
+    uint64_t hm = 0;
+#pragma unroll
+    for (int e = 0; e < NB_PER_LANE; ++e)
+#pragma unroll
+      for (int l = 0; l < MD_LANES; ++l) hm |= (uint64_t)((h[l] >> e) & 1u) << (MD_LANES * e + l);
+    (void)cnt_b;
+    while (hm) {
+      const int k = __builtin_ctzll(hm);
+      hm &= hm - 1;
+      F[0] += sh.pairF[bslot][k][0]; F[1] += sh.pairF[bslot][k][1]; F[2] += sh.pairF[bslot][k][2];
+    }
   }
   // the wall sites within r_c, in ascending site order (set bits only: most
   // beads have none)
@@ -715,7 +729,7 @@ __global__ __launch_bounds__(IN_WG) void k_md_inner(Dev d, int nslots, int o, in
 // Neighbour lists from the hashed cell table, once per coupled step.  Each
 // bead is examined by 32 lanes, one per distinct bucket of its 27 neighbour
 // cells; the lanes collect the other beads of its chain within r_c + skin,
-// and one lane sorts them into ascending chain order -- the list the
+// and one lane sorts their slots into ascending (chain) order -- the list the
 // in-kernel scan would build.  A bucket that overflows leaves its replica's
 // lists marked invalid (and the table unusable), so the first sub-step
 // rebuilds them by the full scan: the same lists, found slower.
@@ -795,7 +809,7 @@ __global__ __launch_bounds__(LB_LANES * LB_BEADS) void k_list_build(Dev d, int n
       double d2 = min_image(rp[2] - d.r[3 * q + 2], g.nz);
       if (!(d0 * d0 + d1 * d1 + d2 * d2 < rl2)) continue;
       const int at = atomicAdd(&ncand[lb], 1);
-      if (at < LB_CAND) cand[lb][at] = q - so;
+      if (at < LB_CAND) cand[lb][at] = q;
     }
   }
   __syncthreads();
@@ -1438,7 +1452,7 @@ __global__ __launch_bounds__(FU_WG) void k_md_fused(Dev d, FusedBufs fb, int nsl
         double pj[FU_LD][3];
 #pragma unroll
         for (int k = 0; k < FU_LD; ++k) {
-          const int js = so + (k < cnt ? e[k] : q);
+          const int js = k < cnt ? e[k] : sl;    // list entries are slots
           pj[k][0] = rin[3 * js]; pj[k][1] = rin[3 * js + 1]; pj[k][2] = rin[3 * js + 2];
         }
         int c = 0;
@@ -1458,11 +1472,11 @@ __global__ __launch_bounds__(FU_WG) void k_md_fused(Dev d, FusedBufs fb, int nsl
         };
 #pragma unroll
         for (int k = 0; k < FU_LD; ++k)
-          if (k < cnt) take(e[k], pj[k]);
+          if (k < cnt) take(e[k] - so, pj[k]);
         for (int k = FU_LD; k < cnt; ++k) {
-          const int j = row[k];
-          const double y[3] = {rin[3 * (so + j)], rin[3 * (so + j) + 1], rin[3 * (so + j) + 2]};
-          take(j, y);
+          const int js = row[k];
+          const double y[3] = {rin[3 * js], rin[3 * js + 1], rin[3 * js + 2]};
+          take(js - so, y);
         }
         if (full) sh.ovf = 1;
         sh.lcnt[t] = (unsigned char)c;
@@ -1701,7 +1715,7 @@ __global__ __launch_bounds__(RD_WG) void k_md_redo(Dev d, FusedBufs fb, double* 
       if (lists) {
         const int cnt = d.ncnt[sl];
         for (int k = 0; k < cnt && np <= RD_NC; ++k) {
-          const int j = d.nbr[(size_t)sl * MAXNBR + k];
+          const int j = d.nbr[(size_t)sl * MAXNBR + k] - so;   // list entries are slots
           const double e0 = min_image(rp[0] - cur[3 * (so + j)], g.nx);
           const double e1 = min_image(rp[1] - cur[3 * (so + j) + 1], g.ny);
           const double e2 = min_image(rp[2] - cur[3 * (so + j) + 2], g.nz);
