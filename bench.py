@@ -72,6 +72,27 @@ def measured_traffic(workload, precision, layout, thermal=False):
     return None
 
 
+def profiled_launch(workload, precision, layout, mean_ms, alg_bytes):
+    """The committed rocprofv3 kernel trace of the coupled step for this
+    workload and storage: its file, the sweep layout and kernel source it was
+    taken on, the sweep's mean launch over the trace's timed dispatches, and
+    the roofline fraction that mean gives, beside this run's (None if there
+    is no trace)."""
+    from paper_0711_2665_amd.build import kernel_source_hash
+    base = os.path.join("profiles", f"coupled_step_{precision}_{workload}_kernels")
+    path = os.path.join(ROOT, base + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    prof_ms = d["mean_launch_ms"]
+    return {"file": base + ".md", "layout": d.get("layout"), "same_layout": d.get("layout") == layout,
+            "same_kernel_source": d.get("kernel_source_hash") == kernel_source_hash(),
+            "dispatches": d["dispatches"], "mean_launch_ms": round(prof_ms, 5),
+            "frac": round(alg_bytes / (prof_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "vs_this_run": round(prof_ms / mean_ms - 1.0, 4)}
+
+
 def sweep_alone(run, cells, elem):
     """Roofline of the sweep run alone over every fluid node in the layout
     the sweep-only autotuner picks (in the coupled step the layout is picked
@@ -84,7 +105,7 @@ def sweep_alone(run, cells, elem):
             "bytes_per_launch": int(nbytes), "achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
-def run_gpu(cfg, precision_name, steps, warmup):
+def run_gpu(cfg, precision_name, steps, warmup, layout=None):
     """Relax, time the sweep alone (autotuner, sweep-only mode), choose the
     sweep layout by timing whole coupled steps, then:
     `steps` coupled steps replayed from the captured two-step HIP graph (the
@@ -102,7 +123,11 @@ def run_gpu(cfg, precision_name, steps, warmup):
     # the sweep alone (every fluid node, nothing beside it), in the layout
     # that is fastest for it, timed by the autotuner with HIP events
     alone = sim.autotune(reps=10)
-    tune = sim.autotune(reps=10, coupled=True)
+    if layout is None:
+        tune = sim.autotune(reps=10, coupled=True)
+    else:
+        sim.sweep_config(*layout)
+        tune = dict(zip(("tile_nodes", "order", "grid", "cap"), layout))
     sim.run(warmup + (warmup & 1), graph=True)          # capture, warm replays
     torch.cuda.synchronize()
     sim.check()
@@ -400,7 +425,11 @@ def main():
     ap.add_argument("--no-mts", action="store_true")
     ap.add_argument("--no-precision-study", action="store_true")
     ap.add_argument("--c1-steps", type=int, default=None)
+    ap.add_argument("--sweep-layout", default=None,
+                    help="tile_nodes,order,grid,cap of the coupled step's sweep instead of the coupled autotuner's "
+                         "choice (profiling runs pin the layout the autotuner picks)")
     args = ap.parse_args()
+    pinned = tuple(int(x) for x in args.sweep_layout.split(",")) if args.sweep_layout else None
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
@@ -411,7 +440,7 @@ def main():
     nx, ny, nz = cfg["shape"]
     cells = nx * ny * nz
 
-    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup)
+    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, pinned)
     progress(f"{cfg['name']} {args.precision}: {1e3 * main_run['seconds'] / args.steps:.4f} ms per step")
     ms_per_step = 1e3 * main_run["seconds"] / args.steps
     mlups = cells * args.steps / main_run["seconds"] / 1e6
@@ -441,7 +470,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "k_lb (fused stream+collide)", "bytes_per_launch": alg_bytes,
-                     "mean_launch_ms": round(main_run["lb_ms"], 5)},
+                     "mean_launch_ms": round(main_run["lb_ms"], 5),
+                     "traffic_from": (f"profiles/lb_sweep_{args.precision}_{args.workload}_counters.md"
+                                      if traffic is not None else None),
+                     "profile": profiled_launch(args.workload, args.precision, layout, main_run["lb_ms"],
+                                                alg_bytes)},
         "sweep_layout": layout,
         "sweep_alone": sweep_alone(main_run, cells, elem),
         "timing": "graph replay of the coupled step; roofline from the same kernels in eager steps",
@@ -458,12 +491,18 @@ def main():
         k64 = max(20, args.steps // 4)
         r64 = run_gpu(cfg, "fp64", k64, max(5, args.warmup // 4))
         u64 = r64["nfluid"] - r64["forced_per_step"]
-        ach64 = (u64 * lb_bytes_per_update(8) + (cells - u64)) / (r64["lb_ms"] * 1e-3) / 1e9
+        alg64 = int(round(u64 * lb_bytes_per_update(8) + (cells - u64)))
+        ach64 = alg64 / (r64["lb_ms"] * 1e-3) / 1e9
+        lay64 = {k: r64["tune"][k] for k in ("tile_nodes", "order", "grid", "cap")}
         out["fp64"] = {"value": round(cells * k64 / r64["seconds"] / 1e6, 1), "unit": "MLUPS", "steps": k64,
                        "ms_per_step": round(1e3 * r64["seconds"] / k64, 4),
                        "eager_ms_per_step": round(1e3 * r64["eager_seconds"] / k64, 4),
+                       "sweep_layout": lay64,
                        "sweep_alone": sweep_alone(r64, cells, 8),
-                       "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4)}
+                       "lb_sweep_bytes_per_launch": alg64, "lb_sweep_mean_launch_ms": round(r64["lb_ms"], 5),
+                       "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4),
+                       "lb_sweep_traffic": measured_traffic(args.workload, "fp64", lay64),
+                       "profile": profiled_launch(args.workload, "fp64", lay64, r64["lb_ms"], alg64)}
         progress("fp64 done")
     if not args.no_thermal:
         # the same workload with a fluctuating fluid at the beads' temperature

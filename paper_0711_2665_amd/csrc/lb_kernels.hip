@@ -384,13 +384,14 @@ __global__ __launch_bounds__(256) void k_fluid_sums(const T* __restrict__ A, Dev
   if (threadIdx.x < 4) part[4 * (size_t)blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// Block-wide sum of 256 values (fixed tree order); every thread gets it.
+// Block-wide sum of NT values (fixed tree order); every thread gets it.
+template <int NT = 256>
 __device__ inline double block_sum(double v, double* sh) {
   int t = threadIdx.x;
   __syncthreads();
   sh[t] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (t < w) sh[t] += sh[t + w];
     __syncthreads();
   }
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(256) void k_observables(Dev d, double* __restrict__
 // 2 f_opp(i)(x) c_opp(i); f from the post-collision array A the step pulls
 // from (f = A + w_i in deviation storage).  Block b of the wall-link list
 // sums its entries (fixed tree order) into lpart[3 b + a]; k_ledger_sum
-// then adds each replica's blocks in order to its cumulative ledger.
+// then adds each replica's blocks in a fixed order to its cumulative ledger.
 // ---------------------------------------------------------------------------
 template <typename T, bool DEV>
 __global__ __launch_bounds__(LEDGER_BLOCK) void k_ledger_bb(const T* __restrict__ A, Dev d) {
@@ -528,16 +529,19 @@ __global__ __launch_bounds__(LEDGER_BLOCK) void k_ledger_bb(const T* __restrict_
   }
 }
 
-// One thread per replica: the step's bounce-back momentum, summed over the
-// replica's blocks in order, added to its ledger.
-__global__ void k_ledger_sum(Dev d, int nrep) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrep) return;
-  const Rep& R = d.reps[r];
+// One workgroup per replica: the step's bounce-back momentum, the replica's
+// block sums added in a fixed order (strided per thread, then a tree), added
+// to its ledger.
+__global__ __launch_bounds__(256) void k_ledger_sum(Dev d) {
+  __shared__ double sh[256];
+  const Rep& R = d.reps[blockIdx.x];
   double s[3] = {0.0, 0.0, 0.0};
-  for (int b = R.wl_begin; b < R.wl_end; ++b)
+  for (int b = R.wl_begin + (int)threadIdx.x; b < R.wl_end; b += 256)
     for (int a = 0; a < 3; ++a) s[a] += d.lpart[3 * (size_t)b + a];
-  for (int a = 0; a < 3; ++a) d.ledger[NLEDGER * r + a] += s[a];
+  for (int a = 0; a < 3; ++a) {
+    const double v = block_sum(s[a], sh);
+    if (threadIdx.x == 0) d.ledger[NLEDGER * blockIdx.x + a] += v;
+  }
 }
 
 // Spread-on-solid: the share W_k J_p of the step's impulse that the
@@ -546,37 +550,19 @@ __global__ void k_ledger_sum(Dev d, int nrep) {
 // each replica's beads in a fixed order (strided per thread, then a tree).
 __global__ void k_ledger_sp(Dev d, int nslots) {
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
-  const Rep& R = d.reps[d.slot_rep[slot]];
-  const Geom& g = R.g;
-  double s[3] = {0.0, 0.0, 0.0};
-  if (g.wall_axis >= 0 && slot - R.slot_off < R.mp.nb) {
-    const uint8_t* fr = d.flags + R.node_off;
-    const double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
-    const Stencil st = make_stencil(g, rp);
-    uint8_t fl[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) fl[k] = fr[corner_node(g, st, k)];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      if (!corner_used(g, st, k) || !(fl[k] & F_SOLID)) continue;
-      const double W = corner_weight(st, k);
-      for (int a = 0; a < 3; ++a) s[a] += W * d.J[3 * slot + a];
-    }
-  }
-  for (int a = 0; a < 3; ++a) d.lsp[3 * (size_t)slot + a] = s[a];
+  if (slot < nslots) ledger_sp_share(d, slot);
 }
 
-__global__ __launch_bounds__(256) void k_ledger_sp_sum(Dev d) {
-  __shared__ double sh[256];
+__global__ __launch_bounds__(1024) void k_ledger_sp_sum(Dev d) {
+  __shared__ double sh[1024];
   const int rep = blockIdx.x;
   const Rep& R = d.reps[rep];
   double s[3] = {0.0, 0.0, 0.0};
   if (R.g.wall_axis >= 0)
-    for (int p = threadIdx.x; p < R.mp.nb; p += 256)
+    for (int p = threadIdx.x; p < R.mp.nb; p += 1024)
       for (int a = 0; a < 3; ++a) s[a] += d.lsp[3 * (size_t)(R.slot_off + p) + a];
   for (int a = 0; a < 3; ++a) {
-    const double v = block_sum(s[a], sh);
+    const double v = block_sum<1024>(s[a], sh);
     if (threadIdx.x == 0) d.ledger[NLEDGER * rep + 3 + a] += v;
   }
 }
@@ -671,13 +657,13 @@ template <typename T, bool DEV>
 void launch_ledger_bb(const void* A, const Dev& d, int nblk, int nrep, hipStream_t s) {
   if (nblk <= 0) return;
   hipLaunchKernelGGL((k_ledger_bb<T, DEV>), dim3((unsigned)nblk), dim3(LEDGER_BLOCK), 0, s, (const T*)A, d);
-  hipLaunchKernelGGL(k_ledger_sum, dim3(blocks_for(nrep, 64)), dim3(64), 0, s, d, nrep);
+  hipLaunchKernelGGL(k_ledger_sum, dim3((unsigned)nrep), dim3(256), 0, s, d);
 }
 
 void launch_ledger_sp(const Dev& d, int nslots, int nrep, hipStream_t s) {
   if (nslots <= 0) return;
   hipLaunchKernelGGL(k_ledger_sp, dim3(blocks_for(nslots, 64)), dim3(64), 0, s, d, nslots);
-  hipLaunchKernelGGL(k_ledger_sp_sum, dim3((unsigned)nrep), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_ledger_sp_sum, dim3((unsigned)nrep), dim3(1024), 0, s, d);
 }
 
 template void launch_fill_rest<double, false>(void*, long, hipStream_t);

@@ -574,10 +574,11 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   // impulse that falls on solid nodes; for long chains the next step's
   // lists from r(n+1)
   acc(hipStreamWaitEvent(c->s2, c->mdone, 0));
-  launch_ledger_sp(D, c->nslots, c->nrep, c->s2);
   if (c->step_lists) {
-    launch_nbr_build(D, c->nslots, c->nrep, c->s2);
+    launch_step_tail(D, c->nslots, c->nrep, true, c->s2);
     c->lists_stale = false;
+  } else {
+    launch_ledger_sp(D, c->nslots, c->nrep, c->s2);
   }
   acc(hipEventRecord(c->join, c->s2));
   acc(hipEventRecord(c->join1, sb));

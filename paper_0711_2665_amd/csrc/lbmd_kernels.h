@@ -247,4 +247,41 @@ void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s);
 void launch_nbr_build(const Dev& d, int nslots, int nrep, hipStream_t s);
 void launch_zero_v(const Dev& d, int nslots, hipStream_t s);
 
+// Spread-on-solid ledger of one bead slot: the share W_k J_p of the step's
+// impulse that the spreading drops because corner k of the bead's stencil
+// (at the spread positions rs) is solid, corners in order, into lsp.  The
+// wall is the only solid, so a stencil (base node and base + 1 along each
+// axis) reaches it only from within one spacing below the plane.
+__device__ inline void ledger_sp_share(const Dev& d, int slot) {
+  const Rep& R = d.reps[d.slot_rep[slot]];
+  const Geom& g = R.g;
+  double s[3] = {0.0, 0.0, 0.0};
+  const double rp[3] = {d.rs[3 * slot], d.rs[3 * slot + 1], d.rs[3 * slot + 2]};
+  bool near = g.wall_axis >= 0 && slot - R.slot_off < R.mp.nb;
+  if (near) {
+    const double wn = wrapc(rp[g.wall_axis], ext(g, g.wall_axis));
+    near = wn >= g.wall_pos - 1.0 && wn < g.wall_pos + 1.0;
+  }
+  if (near) {
+    const uint8_t* fr = d.flags + R.node_off;
+    const Stencil st = make_stencil(g, rp);
+    uint8_t fl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) fl[k] = fr[corner_node(g, st, k)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (!corner_used(g, st, k) || !(fl[k] & F_SOLID)) continue;
+      const double W = corner_weight(st, k);
+      for (int a = 0; a < 3; ++a) s[a] += W * d.J[3 * slot + a];
+    }
+  }
+  for (int a = 0; a < 3; ++a) d.lsp[3 * (size_t)slot + a] = s[a];
+}
+
+// The end of a coupled step on the sweep stream, once J is final: the
+// spread-on-solid ledger (shares per slot, then each replica's beads added
+// in a fixed order into its ledger) fused with the next step's neighbour
+// lists (cell table cleared, beads binned, lists built): three launches.
+void launch_step_tail(const Dev& d, int nslots, int nrep, bool ledger, hipStream_t s);
+
 }  // namespace lbmd

@@ -740,9 +740,7 @@ __global__ void k_cell_clear(int* __restrict__ ccount, int nbuckets, uint32_t* _
   if (k < nrep) rb[4 * k + 3] = 0u;          // valid unless a bucket overflows below
 }
 
-__global__ void k_cell_insert(Dev d, int nslots) {
-  int slot = blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= nslots) return;
+__device__ inline void cell_insert_slot(const Dev& d, int slot) {
   const int rep = d.slot_rep[slot];
   const Rep& R = d.reps[rep];
   if (slot - R.slot_off >= R.mp.nb) return;
@@ -755,6 +753,11 @@ __global__ void k_cell_insert(Dev d, int nslots) {
   // the table is not used inside the sub-cycle
 #pragma unroll
   for (int a = 0; a < 3; ++a) d.rbin[3 * slot + a] = pos < CELL_CAP ? d.r[3 * slot + a] : 1e300;
+}
+
+__global__ void k_cell_insert(Dev d, int nslots) {
+  int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot < nslots) cell_insert_slot(d, slot);
 }
 
 constexpr int LB_LANES = 32;                 // lanes per bead in the list build (27 cells)
@@ -833,6 +836,57 @@ __global__ __launch_bounds__(LB_LANES * LB_BEADS) void k_list_build(Dev d, int n
   for (int i = 0; i < nc; ++i) row[i] = c[i];
   d.ncnt[slot] = nc;
   d.ref[3 * slot] = rp[0]; d.ref[3 * slot + 1] = rp[1]; d.ref[3 * slot + 2] = rp[2];
+}
+
+// k_cell_clear with the spread-on-solid shares: k < nbuckets clears a bucket,
+// k < nrep validates a replica's lists, k < nslots writes a slot's share.
+__global__ void k_tail_clear(Dev d, int nbuckets, int nrep, int nslots, int ledger) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nbuckets) d.ccount[k] = 0;
+  if (k < nrep) d.rb[4 * k + 3] = 0u;
+  if (ledger && k < nslots) ledger_sp_share(d, k);
+}
+
+// k_cell_insert in the first `nins` workgroups; after them one workgroup per
+// replica adds its beads' shares (strided per thread, then a fixed tree)
+// into its ledger.
+constexpr int TAIL_WG = 1024;
+__global__ __launch_bounds__(TAIL_WG) void k_tail_insert(Dev d, int nslots, int nins) {
+  if ((int)blockIdx.x < nins) {                  // uniform in the workgroup
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot < nslots) cell_insert_slot(d, slot);
+    return;
+  }
+  __shared__ double sh[TAIL_WG];
+  const int rep = blockIdx.x - nins;
+  const Rep& R = d.reps[rep];
+  double s[3] = {0.0, 0.0, 0.0};
+  if (R.g.wall_axis >= 0)
+    for (int p = threadIdx.x; p < R.mp.nb; p += TAIL_WG)
+      for (int a = 0; a < 3; ++a) s[a] += d.lsp[3 * (size_t)(R.slot_off + p) + a];
+  for (int a = 0; a < 3; ++a) {
+    __syncthreads();
+    sh[threadIdx.x] = s[a];
+    __syncthreads();
+    for (int w = TAIL_WG / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) d.ledger[NLEDGER * rep + 3 + a] += sh[0];
+  }
+}
+
+void launch_step_tail(const Dev& d, int nslots, int nrep, bool ledger, hipStream_t s) {
+  if (nslots <= 0) return;
+  const int nb = (int)d.cmask + 1;
+  int n = nb > nrep ? nb : nrep;
+  if (nslots > n) n = nslots;
+  hipLaunchKernelGGL(k_tail_clear, dim3((n + 255) / 256), dim3(256), 0, s, d, nb, nrep, nslots, ledger ? 1 : 0);
+  const int nins = (nslots + TAIL_WG - 1) / TAIL_WG;
+  hipLaunchKernelGGL(k_tail_insert, dim3((unsigned)(nins + (ledger ? nrep : 0))), dim3(TAIL_WG), 0, s, d, nslots,
+                     nins);
+  hipLaunchKernelGGL(k_list_build, dim3((nslots + LB_BEADS - 1) / LB_BEADS), dim3(LB_LANES * LB_BEADS), 0, s, d,
+                     nslots);
 }
 
 void launch_nbr_build(const Dev& d, int nslots, int nrep, hipStream_t s) {

@@ -1,9 +1,10 @@
 """Text summaries of rocprofv3 results (the SQLite databases rocprofv3 writes)
 for the profiles folder.
 
-    # kernel table of a --kernel-trace --stats run
+    # kernel table of a --kernel-trace --stats run (with --json, the mean of
+    # the selected dispatches and the kernel source hash for bench.py)
     python -m paper_0711_2665_amd.rocprof_summary trace --db DB --out profiles/X.md \
-        --command "the rocprofv3 command" [--kernel k_lb --last 200]
+        --command "the rocprofv3 command" [--kernel k_lb --last 200 --json profiles/X.json --layout '{...}']
 
     # one coupled step as a timeline (kernel starts relative to the end of the
     # previous step, sub-step durations summarised)
@@ -62,6 +63,14 @@ def trace(a):
         if a.last:
             sel = sel[-a.last:]
         d = [r[3] for r in sel]
+        if d and a.json:
+            from .build import kernel_source_hash
+            rec = dict(kernel=a.kernel, dispatches=len(d), mean_launch_ms=sum(d) / len(d) / 1e6,
+                       min_launch_ms=min(d) / 1e6, max_launch_ms=max(d) / 1e6, grid=sel[-1][4],
+                       workgroup=sel[-1][5], command=a.command, kernel_source_hash=kernel_source_hash(),
+                       layout=json.loads(a.layout) if a.layout else None)
+            with open(a.json, "w") as fh:
+                json.dump(rec, fh, indent=1)
         if d:
             lines += ["", f"{len(d)} dispatches of `{a.kernel}` in the timed region"
                       f"{f' (the last {a.skip_last} dispatches, later in the run, excluded)' if a.skip_last else ''}: "
@@ -173,6 +182,8 @@ def main():
     t.add_argument("--kernel", default="")
     t.add_argument("--last", type=int, default=0)
     t.add_argument("--skip-last", type=int, default=0)
+    t.add_argument("--json", default="", help="also write the selected dispatches' mean here")
+    t.add_argument("--layout", default="", help="the sweep layout of the run, as JSON (recorded in --json)")
     tl = sub.add_parser("timeline")
     tl.add_argument("--db", required=True)
     tl.add_argument("--out", required=True)
