@@ -335,7 +335,7 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * conservative forces), gathering -- using the populations and bead state of
  * that step, recomputed segment by segment from checkpoints taken every K
  * steps of the forward pass.
- * Supported: one-replica contexts with 1 <= nb <= 128, gamma > 0, an
+ * Supported: one-replica contexts with 1 <= nb <= 16384, gamma > 0, an
  * athermal fluid (fluid_kT = 0), the uniform sub-cycle (mts_outer = 0),
  * harmonic bonds and the trilinear transfer (LB_ERR_UNSUPPORTED / LB_ERR_ARG
  * otherwise); either precision.

@@ -127,107 +127,6 @@ __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, D
   }
 }
 
-// Bending forces of the angle centred at q (1 <= q <= nb - 2) at positions
-// pos with direction dir, value and derivative, into LDS rows av[q], ad[q]:
-// [0..2] force on q-1, [3..5] on q, [6..8] on q+1.
-// The three vertex forces are independent: the caller gives vertex w to
-// lane w of the bead.
-__device__ inline void angle_to_lds(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int q,
-                                    int w, double (*av)[9], double (*ad)[9]) {
-  Dd ra[3], rb[3], rc[3];
-  for (int a = 0; a < 3; ++a) {
-    ra[a] = Dd{pos[q - 1][a], dir[q - 1][a]};
-    rb[a] = Dd{pos[q][a], dir[q][a]};
-    rc[a] = Dd{pos[q + 1][a], dir[q + 1][a]};
-  }
-  Dd F[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  angle_dd(P, ra, rb, rc, w, F);
-  for (int a = 0; a < 3; ++a) { av[q][3 * w + a] = F[a].v; ad[q][3 * w + a] = F[a].d; }
-}
-
-// Conservative force on chain bead p at positions pos with direction dir
-// (nb x 3, LDS), value and directional derivative, computed by the 4 lanes
-// of the bead: lane l scans the pair partners j = l, l + 4, ... within r_c
-// (distance screen in plain doubles, dual arithmetic only inside r_c); lane
-// 0 adds the bonds, the angle forces from LDS (angles centred at p-1, p,
-// p+1) and the wall sites.  The four partial sums are combined in a fixed
-// order with cross-lane reads, so every lane of the bead ends with F, dF.
-// The field is added by the caller (constant in r).
-constexpr int ADJ_MAXHIT = 16;   // partners within r_c kept per lane (j = lane mod 4)
-
-__device__ inline void bead_force_dd(const MdParams& P, const Geom& g, const double (*pos)[3],
-                                     const double (*dir)[3], const double (*av)[9], const double (*ad)[9], int p,
-                                     int lane, bool on, double F[3], double dF[3]) {
-  const int nb = P.nb;
-  Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  if (on) {
-    // the partners within r_c first, in ascending j, then their dual LJ
-    // terms in that order: the lanes of a wave then evaluate the LJ terms
-    // together instead of one scan iteration at a time (more than
-    // ADJ_MAXHIT partners: the same sum in one pass)
-    int hit[ADJ_MAXHIT];
-    int nh = 0;
-    for (int j = lane; j < nb; j += 4) {
-      if (j == p) continue;
-      const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
-      const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
-      const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
-      if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
-      if (nh < ADJ_MAXHIT) hit[nh] = j;
-      ++nh;
-    }
-    if (nh <= ADJ_MAXHIT) {
-      for (int k = 0; k < nh; ++k) {
-        const int j = hit[k];
-        const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
-        const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
-        const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
-        lj_dd(P, Dd{e0, dir[p][0] - dir[j][0]}, Dd{e1, dir[p][1] - dir[j][1]}, Dd{e2, dir[p][2] - dir[j][2]}, S);
-      }
-    } else {
-      for (int j = lane; j < nb; j += 4) {
-        if (j == p) continue;
-        const double e0 = min_image(pos[p][0] - pos[j][0], g.nx);
-        const double e1 = min_image(pos[p][1] - pos[j][1], g.ny);
-        const double e2 = min_image(pos[p][2] - pos[j][2], g.nz);
-        if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
-        lj_dd(P, Dd{e0, dir[p][0] - dir[j][0]}, Dd{e1, dir[p][1] - dir[j][1]}, Dd{e2, dir[p][2] - dir[j][2]}, S);
-      }
-    }
-    if (lane == 0) {
-      Dd rp[3] = {Dd{pos[p][0], dir[p][0]}, Dd{pos[p][1], dir[p][1]}, Dd{pos[p][2], dir[p][2]}};
-      if (p > 0) {
-        Dd rq[3] = {Dd{pos[p - 1][0], dir[p - 1][0]}, Dd{pos[p - 1][1], dir[p - 1][1]},
-                    Dd{pos[p - 1][2], dir[p - 1][2]}};
-        bond_dd(P, rp, rq, S);
-      }
-      if (p < nb - 1) {
-        Dd rq[3] = {Dd{pos[p + 1][0], dir[p + 1][0]}, Dd{pos[p + 1][1], dir[p + 1][1]},
-                    Dd{pos[p + 1][2], dir[p + 1][2]}};
-        bond_dd(P, rp, rq, S);
-      }
-      if (p - 1 >= 1 && p - 1 <= nb - 2)
-        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p - 1][6 + a], ad[p - 1][6 + a]};
-      if (p >= 1 && p <= nb - 2)
-        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p][3 + a], ad[p][3 + a]};
-      if (p + 1 >= 1 && p + 1 <= nb - 2)
-        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[p + 1][a], ad[p + 1][a]};
-      wall_dd(P, g, rp, S);
-    }
-  }
-  // (lane0 + lane1) + (lane2 + lane3), the same on every lane of the bead
-  const int base = (int)(threadIdx.x & 63u) & ~3;
-  for (int a = 0; a < 3; ++a) {
-    double v[4], d[4];
-    for (int l = 0; l < 4; ++l) {
-      v[l] = __shfl(S[a].v, base + l, 64);
-      d[l] = __shfl(S[a].d, base + l, 64);
-    }
-    F[a] = (v[0] + v[1]) + (v[2] + v[3]);
-    dF[a] = (d[0] + d[1]) + (d[2] + d[3]);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Initial adjoint: lam_r = dL/dr(final), lam_v = dL/dv(final) or 0, lam_A = 0,
 // parameter accumulators 0.
@@ -259,6 +158,7 @@ __device__ inline double dweight(const Stencil& s, int k, int a) {
 template <typename T>
 __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, const double* __restrict__ Jt, int nb) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) *a.lok = 0;                      // the list check of this step follows
   if (p >= nb) return;
   const Rep& R = d.reps[0];
   const size_t N = (size_t)R.lp.N;
@@ -289,32 +189,49 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 }
 
 // ---------------------------------------------------------------------------
-// MD sub-cycle transpose of one chain, one workgroup, four lanes per bead.
-// The force positions r_mid and the velocities at the start of every
-// sub-step come from the tape the forward sub-cycle wrote while the segment
-// was recomputed; the sub-steps are reversed.  On entry lr, lv hold
-// the adjoint of r, v after the step and lJ that of the impulse J; on exit
-// lr, lv hold the adjoint of r_n, v_n through the sub-cycle and lup that of
-// u_p.  The parameter adjoints are added to par[0] (gamma) and par[1]
-// (F_drive).
+// MD sub-cycle transpose, one launch per sub-step (in reverse order), 16
+// beads per 64-lane workgroup, four lanes per bead.  The force positions
+// r_mid and the velocities at the start of every sub-step come from the
+// tape the forward sub-cycle wrote while the segment was recomputed.  On
+// entry lr, lv hold the adjoint of r, v after the step and lJ that of the
+// impulse J; the launches alternate between (lr, lv) and (lr2, lv2), so that
+// a launch reads every bead's adjoint before the sub-step and writes the
+// other pair; k_adj_md_fin leaves the adjoint of r_n, v_n through the
+// sub-cycle in lr, lv.  lup collects the adjoint of u_p, gacc per bead the
+// terms of dL/dgamma and dL/dF_drive, which k_adj_md_fin adds over the
+// beads in a fixed order to par[0] and par[1].
+//
+// Per sub-step and bead, with lvt = lv + hh lr (the second half drift):
+// the direction of the force derivative is dir = cf lvt (the kick), the
+// derivative dF of the conservative force along the field of directions
+// (for conservative forces (dF/dr)^T lvt = dF/dr lvt) enters lr, and lv
+// goes back through the kick and the first half drift.
 // ---------------------------------------------------------------------------
 constexpr int ADJ_LANES = 4;
-constexpr int ADJ_WG = ADJ_LANES * MAX_ADJ_BEADS;
+constexpr int AS_BPB = 16;                   // beads per workgroup
+constexpr int AS_WG = ADJ_LANES * AS_BPB;    // one wave
+constexpr int AS_SPAN = AS_BPB + 4;          // beads p0 - 2 .. p0 + 17 in LDS
+constexpr int AS_FIN = 1024;                 // threads of k_adj_md_fin
 
-// Forces on every bead at the positions in pos with direction dir: angles
-// into LDS first (one thread per angle), then the per-bead sums.
-__device__ inline void chain_forces(const MdParams& P, const Geom& g, const double (*pos)[3], const double (*dir)[3],
-                                    double (*av)[9], double (*ad)[9], int p, int lane, bool on, double F[3],
-                                    double dF[3]) {
-  const int nb = P.nb;
-  if (lane < 3 && p >= 1 && p <= nb - 2) angle_to_lds(P, pos, dir, p, lane, av, ad);
-  __syncthreads();
-  bead_force_dd(P, g, pos, dir, av, ad, p, lane, on, F, dF);
+// Bending forces of the angle centred at local index qi of pos/dir (value
+// and derivative), vertex w, into one LDS row: [0..2] force on the bead
+// before the centre, [3..5] on the centre, [6..8] on the bead after it.
+__device__ inline void angle_dual(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int qi, int w,
+                                  double* av, double* ad) {
+  Dd ra[3], rb[3], rc[3];
+  for (int a = 0; a < 3; ++a) {
+    ra[a] = Dd{pos[qi - 1][a], dir[qi - 1][a]};
+    rb[a] = Dd{pos[qi][a], dir[qi][a]};
+    rc[a] = Dd{pos[qi + 1][a], dir[qi + 1][a]};
+  }
+  Dd F[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  angle_dd(P, ra, rb, rc, w, F);
+  for (int a = 0; a < 3; ++a) { av[3 * w + a] = F[a].v; ad[3 * w + a] = F[a].d; }
 }
 
 // The bead noise of every sub-step of the step being reversed, drawn in
-// parallel before the serial reverse sub-cycle (the forward's draws: key
-// (seed, replica), counter (step, s, p, 0)); one thread per (s, p).
+// parallel before the reverse sub-cycle (the forward's draws: key (seed,
+// replica), counter (step, s, p, 0)); one thread per (s, p).
 __global__ void k_adj_noise(Dev d, double* __restrict__ xi, uint32_t step, int nb, int n_sub) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nb * n_sub) return;
@@ -325,92 +242,213 @@ __global__ void k_adj_noise(Dev d, double* __restrict__ xi, uint32_t step, int n
   for (int c = 0; c < 3; ++c) xi[(size_t)t * 3 + c] = x[c];
 }
 
-__global__ __launch_bounds__(ADJ_WG) void k_adj_md(Dev d, AdjBufs a, const double* __restrict__ mdt,
-                                                   const double* __restrict__ upt, uint32_t step, double kT) {
-  extern __shared__ double lds[];
+// The neighbour lists built at the reversed step's start positions hold
+// every pair within r_c at the sub-steps' force positions while no bead is
+// farther than half the skin from where they were built (and no bucket of
+// the cell table overflowed); else the reverse sub-steps scan all pairs.
+__global__ void k_adj_lcheck(Dev d, AdjBufs a, const double* __restrict__ mdt, int nb, int n_sub) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && d.rb[3] != 0u) atomicOr(a.lok, 1);
+  if (t >= nb * n_sub) return;
+  const int p = t % nb;
+  double d2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double x = mdt[(size_t)t * 6 + c] - d.ref[3 * p + c];
+    d2 += x * x;
+  }
+  if (!(d2 <= d.reps[0].mp.halfskin2)) atomicOr(a.lok, 1);
+}
+
+// Conservative force on bead p (value and derivative along dir), by the four
+// lanes of the bead: lane l takes the pair partners j with j mod 4 = l in
+// ascending j (from the step's list, or from all beads), first collecting
+// those within r_c, then evaluating their dual LJ terms together; lane 0
+// adds the bonds, the angle forces from LDS and the wall sites.  The four
+// partial sums are combined in a fixed order, the same on every lane.
+// pl: local index of p in pos/dir; al: local row of the angle centred at p.
+constexpr int ADJ_MAXHIT = 16;
+
+__device__ inline void bead_force_sub(const MdParams& P, const Geom& g, const Dev& d, const double (*pos)[3],
+                                      const double (*dir)[3], const double (*av)[9], const double (*ad)[9], int p,
+                                      int pl, int al, int lane, bool on, bool lists,
+                                      const double* __restrict__ rms, const double* __restrict__ lrin,
+                                      const double* __restrict__ lvin, double F[3], double dF[3]) {
+  const int nb = P.nb;
+  Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  if (on) {
+    const double xp[3] = {pos[pl][0], pos[pl][1], pos[pl][2]};
+    const double dp[3] = {dir[pl][0], dir[pl][1], dir[pl][2]};
+    auto lj_with = [&](int j) {
+      const double e0 = min_image(xp[0] - rms[6 * (size_t)j], g.nx);
+      const double e1 = min_image(xp[1] - rms[6 * (size_t)j + 1], g.ny);
+      const double e2 = min_image(xp[2] - rms[6 * (size_t)j + 2], g.nz);
+      double dj[3];
+      for (int c = 0; c < 3; ++c) dj[c] = P.cf * (lvin[3 * j + c] + P.hh * lrin[3 * j + c]);
+      lj_dd(P, Dd{e0, dp[0] - dj[0]}, Dd{e1, dp[1] - dj[1]}, Dd{e2, dp[2] - dj[2]}, S);
+    };
+    auto close = [&](int j) {
+      const double e0 = min_image(xp[0] - rms[6 * (size_t)j], g.nx);
+      const double e1 = min_image(xp[1] - rms[6 * (size_t)j + 1], g.ny);
+      const double e2 = min_image(xp[2] - rms[6 * (size_t)j + 2], g.nz);
+      return e0 * e0 + e1 * e1 + e2 * e2 < P.rc2;
+    };
+    int hit[ADJ_MAXHIT];
+    int nh = 0;
+    const int cnt = lists ? d.ncnt[p] : 0;
+    const int* row = d.nbr + (size_t)p * MAXNBR;
+    if (lists) {
+      for (int k = 0; k < cnt; ++k) {
+        const int j = row[k];
+        if ((j & 3) != lane || !close(j)) continue;
+        if (nh < ADJ_MAXHIT) hit[nh] = j;
+        ++nh;
+      }
+    } else {
+      for (int j = lane; j < nb; j += 4) {
+        if (j == p || !close(j)) continue;
+        if (nh < ADJ_MAXHIT) hit[nh] = j;
+        ++nh;
+      }
+    }
+    if (nh <= ADJ_MAXHIT) {
+      for (int k = 0; k < nh; ++k) lj_with(hit[k]);
+    } else if (lists) {
+      for (int k = 0; k < cnt; ++k) {
+        const int j = row[k];
+        if ((j & 3) == lane && close(j)) lj_with(j);
+      }
+    } else {
+      for (int j = lane; j < nb; j += 4)
+        if (j != p && close(j)) lj_with(j);
+    }
+    if (lane == 0) {
+      Dd rp[3] = {Dd{xp[0], dp[0]}, Dd{xp[1], dp[1]}, Dd{xp[2], dp[2]}};
+      if (p > 0) {
+        Dd rq[3] = {Dd{pos[pl - 1][0], dir[pl - 1][0]}, Dd{pos[pl - 1][1], dir[pl - 1][1]},
+                    Dd{pos[pl - 1][2], dir[pl - 1][2]}};
+        bond_dd(P, rp, rq, S);
+      }
+      if (p < nb - 1) {
+        Dd rq[3] = {Dd{pos[pl + 1][0], dir[pl + 1][0]}, Dd{pos[pl + 1][1], dir[pl + 1][1]},
+                    Dd{pos[pl + 1][2], dir[pl + 1][2]}};
+        bond_dd(P, rp, rq, S);
+      }
+      if (p - 1 >= 1 && p - 1 <= nb - 2)
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[al - 1][6 + a], ad[al - 1][6 + a]};
+      if (p >= 1 && p <= nb - 2)
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[al][3 + a], ad[al][3 + a]};
+      if (p + 1 >= 1 && p + 1 <= nb - 2)
+        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[al + 1][a], ad[al + 1][a]};
+      wall_dd(P, g, rp, S);
+    }
+  }
+  // (lane0 + lane1) + (lane2 + lane3), the same on every lane of the bead
+  const int base = (int)(threadIdx.x & 63u) & ~3;
+  for (int a = 0; a < 3; ++a) {
+    double v[4], dd[4];
+    for (int l = 0; l < 4; ++l) {
+      v[l] = __shfl(S[a].v, base + l, 64);
+      dd[l] = __shfl(S[a].d, base + l, 64);
+    }
+    F[a] = (v[0] + v[1]) + (v[2] + v[3]);
+    dF[a] = (dd[0] + dd[1]) + (dd[2] + dd[3]);
+  }
+}
+
+// Reverse sub-step s, the k-th launch of the reversed cycle (k = n_sub - 1 - s).
+__global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const double* __restrict__ mdt,
+                                                   const double* __restrict__ upt, int s, int k, double kT) {
+  __shared__ double pos[AS_SPAN][3], dir[AS_SPAN][3];
+  __shared__ double av[AS_BPB + 2][9], ad[AS_BPB + 2][9];
   const Rep& R = d.reps[0];
   const MdParams P = R.mp;
   const Geom g = R.g;
-  const int nb = P.nb, n_sub = P.n_sub;
-  double(*pos)[3] = (double(*)[3])lds;
-  double(*dir)[3] = (double(*)[3])(lds + 3 * nb);
-  double(*av)[9] = (double(*)[9])(lds + 6 * nb);
-  double(*ad)[9] = (double(*)[9])(lds + 15 * nb);
-  double* red = lds + 24 * nb;            // 2 x (ADJ_WG / ADJ_LANES) reduction scratch
-  const int p = threadIdx.x / ADJ_LANES, lane = threadIdx.x % ADJ_LANES;
-  const bool on = p < nb;
-  const bool lead = on && lane == 0;
-  double u[3];
-  for (int c = 0; c < 3; ++c) u[c] = on ? upt[3 * p + c] : 0.0;
-  // the forward sub-cycle recorded r_mid and v at the start of every
-  // sub-step: mdt[s][p][0..2] and [3..5]
-  // ---- reverse
+  const int nb = P.nb;
+  const int p0 = blockIdx.x * AS_BPB;
+  const int t = threadIdx.x, b = t / ADJ_LANES, lane = t % ADJ_LANES, p = p0 + b;
+  const bool on = p < nb, lead = on && lane == 0;
+  const bool first = k == 0;
+  const double* lrin = (k & 1) ? a.lr2 : a.lr;
+  const double* lvin = (k & 1) ? a.lv2 : a.lv;
+  double* lrout = (k & 1) ? a.lr : a.lr2;
+  double* lvout = (k & 1) ? a.lv : a.lv2;
+  const double* rms = mdt + (size_t)s * nb * 6;   // [nb][6]: r_mid, v at the start of sub-step s
+  const bool lists = *a.lok == 0;
+  // positions and directions of beads p0 - 2 .. p0 + 17
+  if (t < AS_SPAN) {
+    const int q = p0 - 2 + t;
+    if (q >= 0 && q < nb)
+      for (int c = 0; c < 3; ++c) {
+        pos[t][c] = rms[6 * (size_t)q + c];
+        dir[t][c] = P.cf * (lvin[3 * q + c] + P.hh * lrin[3 * q + c]);
+      }
+  }
+  __syncthreads();
+  // the angles centred at p0 - 1 .. p0 + 16 (row = centre - p0 + 1): lanes
+  // 0-2 of bead b take vertex `lane` of the angle centred at p0 + b, lane 3
+  // of beads 0-5 the vertices of the two angles just outside
+  int cen = -1, w = 0;
+  if (lane < 3) { cen = p; w = lane; }
+  else if (b < 6) { cen = b < 3 ? p0 - 1 : p0 + AS_BPB; w = b % 3; }
+  if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, w, av[cen - p0 + 1], ad[cen - p0 + 1]);
+  __syncthreads();
+  double f[3], df[3];
+  bead_force_sub(P, g, d, pos, dir, av, ad, p, b + 2, b + 1, lane, on, lists, rms, lrin, lvin, f, df);
+  if (!lead) return;
   const double h = 2.0 * P.hh;
   const double gam = P.gamma;
   const double de = -h * P.e, domE = h * P.e;
   const double dcf = (h * P.e) / (P.m * gam) - P.omE / (P.m * gam * gam);
   const double dsig = P.sig > 0.0 ? ((kT / P.m) * (h * P.e * P.e)) / P.sig : 0.0;
-  double lr[3], lv[3], lJ[3], lu[3];
+  const double rm[3] = {pos[b + 2][0], pos[b + 2][1], pos[b + 2][2]};
+  const bool field = P.field_on && in_field(g, rm);
+  if (field) f[g.wall_axis] += P.f_drive;
+  double xi[3] = {0.0, 0.0, 0.0};
+  if (P.sig != 0.0)
+    for (int c = 0; c < 3; ++c) xi[c] = a.xi[((size_t)s * nb + p) * 3 + c];
+  double acc_g = first ? 0.0 : a.gacc[3 * p], acc_f = first ? 0.0 : a.gacc[3 * p + 1];
   for (int c = 0; c < 3; ++c) {
-    lr[c] = on ? a.lr[3 * p + c] : 0.0;
-    lv[c] = on ? a.lv[3 * p + c] : 0.0;
-    lJ[c] = on ? a.lJ[3 * p + c] : 0.0;
-    lu[c] = 0.0;
+    const double lr = lrin[3 * p + c], lv = lvin[3 * p + c], lJ = a.lJ[3 * p + c], u = upt[3 * p + c];
+    const double lvt = lv + P.hh * lr;
+    const double vo = rms[6 * (size_t)p + 3 + c];
+    acc_g += lvt * (vo * de + (f[c] + gam * u) * dcf + P.cf * u + xi[c] * dsig);
+    acc_g += lJ * (-P.m) * ((u - vo) * domE + xi[c] * dsig);
+    const double lu = first ? 0.0 : a.lup[3 * p + c];
+    a.lup[3 * p + c] = lu + (P.cf * gam * lvt - P.m * P.omE * lJ);
+    const double lrm = lr + df[c];
+    lrout[3 * p + c] = lrm;
+    lvout[3 * p + c] = P.e * lvt + P.m * P.omE * lJ + P.hh * lrm;
   }
-  double acc_g = 0.0, acc_f = 0.0;
-  for (int s = n_sub - 1; s >= 0; --s) {
-    double lvt[3], rm[3];
-    for (int c = 0; c < 3; ++c) {
-      lvt[c] = lv[c] + P.hh * lr[c];
-      rm[c] = on ? mdt[((size_t)s * nb + p) * 6 + c] : 0.0;
-    }
-    if (lead)
-      for (int c = 0; c < 3; ++c) { pos[p][c] = rm[c]; dir[p][c] = P.cf * lvt[c]; }
-    __syncthreads();
-    double f[3], df[3];
-    chain_forces(P, g, pos, dir, av, ad, p, lane, on, f, df);
-    if (on) {
-      const bool field = P.field_on && in_field(g, rm);
-      if (field) f[g.wall_axis] += P.f_drive;
-      double xi[3] = {0.0, 0.0, 0.0};
-      if (P.sig != 0.0 && lead)
-        for (int c = 0; c < 3; ++c) xi[c] = a.xi[((size_t)s * nb + p) * 3 + c];
-      for (int c = 0; c < 3; ++c) {
-        const double vo = mdt[((size_t)s * nb + p) * 6 + 3 + c];
-        if (lead) {
-          acc_g += lvt[c] * (vo * de + (f[c] + gam * u[c]) * dcf + P.cf * u[c] + xi[c] * dsig);
-          acc_g += lJ[c] * (-P.m) * ((u[c] - vo) * domE + xi[c] * dsig);
-        }
-        lu[c] += P.cf * gam * lvt[c] - P.m * P.omE * lJ[c];
-        const double lrm = lr[c] + df[c];
-        lr[c] = lrm;
-        lv[c] = P.e * lvt[c] + P.m * P.omE * lJ[c] + P.hh * lrm;
-      }
-      if (lead && field) acc_f += P.cf * lvt[g.wall_axis];
-    }
-    __syncthreads();
-  }
-  if (lead) {
-    for (int c = 0; c < 3; ++c) {
-      a.lr[3 * p + c] = lr[c];
-      a.lv[3 * p + c] = lv[c];
-      a.lup[3 * p + c] = lu[c];
-    }
-  }
-  // parameter adjoints: fixed-order tree over the beads (lane-0 values)
-  constexpr int NB_ = ADJ_WG / ADJ_LANES;
-  if (lane == 0) {
-    red[p] = acc_g;
-    red[NB_ + p] = acc_f;
+  if (field) acc_f += P.cf * (lvin[3 * p + g.wall_axis] + P.hh * lrin[3 * p + g.wall_axis]);
+  a.gacc[3 * p] = acc_g;
+  a.gacc[3 * p + 1] = acc_f;
+}
+
+// After the reversed cycle: lr, lv from the pair the last launch wrote, and
+// the parameter terms added over the beads in a fixed order (beads p, p + M,
+// ... summed per slot, then a tree over M = the least power of two >= nb,
+// at least 128 and at most AS_FIN).
+__global__ __launch_bounds__(AS_FIN) void k_adj_md_fin(AdjBufs a, int nb, int n_sub) {
+  __shared__ double red[2][AS_FIN];
+  const int t = threadIdx.x;
+  if (n_sub & 1)
+    for (int i = t; i < 3 * nb; i += AS_FIN) { a.lr[i] = a.lr2[i]; a.lv[i] = a.lv2[i]; }
+  int M = 128;
+  while (M < nb && M < AS_FIN) M *= 2;
+  if (t < M) {
+    double sg = 0.0, sf = 0.0;
+    for (int p = t; p < nb; p += M) { sg += a.gacc[3 * p]; sf += a.gacc[3 * p + 1]; }
+    red[0][t] = sg;
+    red[1][t] = sf;
   }
   __syncthreads();
-  for (int w = NB_ / 2; w > 0; w >>= 1) {
-    if (lane == 0 && p < w) { red[p] += red[p + w]; red[NB_ + p] += red[NB_ + p + w]; }
+  for (int w = M / 2; w > 0; w >>= 1) {
+    if (t < w) { red[0][t] += red[0][t + w]; red[1][t] += red[1][t + w]; }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    a.par[0] += red[0];
-    a.par[1] += red[NB_];
+  if (t == 0) {
+    a.par[0] += red[0][0];
+    a.par[1] += red[1][0];
   }
 }
 
@@ -551,11 +589,16 @@ void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const 
                              int nb, int n_sub, hipStream_t s) {
   launch_bead_prep(d, nslots, s);
   hipLaunchKernelGGL((k_adj_spread_t<T>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)lamB, d, a, Jt, nb);
-  size_t lds = sizeof(double) * (24 * (size_t)nb + 2 * (ADJ_WG / ADJ_LANES));
+  // neighbour lists at the step's start positions (d.r is the tape's r_n),
+  // checked against every sub-step's force positions
+  launch_nbr_build(d, nslots, 1, s);
+  hipLaunchKernelGGL(k_adj_lcheck, dim3(nblk((long)nb * n_sub, 256)), dim3(256), 0, s, d, a, mdt, nb, n_sub);
   if (kT != 0.0) {   // sigma > 0 exactly when kT > 0 (gamma > 0 here)
     hipLaunchKernelGGL(k_adj_noise, dim3(nblk((long)nb * n_sub, 256)), dim3(256), 0, s, d, a.xi, step, nb, n_sub);
   }
-  hipLaunchKernelGGL(k_adj_md, dim3(1), dim3(ADJ_WG), lds, s, d, a, mdt, upt, step, kT);
+  for (int k = 0; k < n_sub; ++k)
+    hipLaunchKernelGGL(k_adj_sub, dim3(nblk(nb, AS_BPB)), dim3(AS_WG), 0, s, d, a, mdt, upt, n_sub - 1 - k, k, kT);
+  hipLaunchKernelGGL(k_adj_md_fin, dim3(1), dim3(AS_FIN), 0, s, a, nb, n_sub);
   hipLaunchKernelGGL((k_adj_gather_t<T, DEV>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)A, d, a, nb);
   launch_spread<T>(dspread, nslots, s);
   hipLaunchKernelGGL((k_adj_lb<T, DEV>), dim3((unsigned)ntiles), dim3(256), 0, s, (const T*)A, (const T*)lamB,

@@ -680,7 +680,7 @@ AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
   L.lamA = o; o += L.pops_slot;
   L.lamB = o; o += L.pops_slot;
   L.lamu = o; o += align256(es * 3 * (size_t)c->pk.nodes);
-  L.lbead = o; o += 5 * L.bead_arr;
+  L.lbead = o; o += 8 * L.bead_arr;
   L.mdtape = o; o += (size_t)K * L.md_arr;
   L.xi = o; o += align256(sizeof(double) * 3 * (size_t)c->d[0].nb * (size_t)c->n_sub);
   L.par = o; o += 256;
@@ -1502,8 +1502,12 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
   a.lJ = (double*)(w + L.lbead + 2 * L.bead_arr);
   a.lup = (double*)(w + L.lbead + 3 * L.bead_arr);
   a.lrs = (double*)(w + L.lbead + 4 * L.bead_arr);
+  a.lr2 = (double*)(w + L.lbead + 5 * L.bead_arr);
+  a.lv2 = (double*)(w + L.lbead + 6 * L.bead_arr);
+  a.gacc = (double*)(w + L.lbead + 7 * L.bead_arr);
   a.lamu = w + L.lamu;
   a.par = (double*)(w + L.par);
+  a.lok = (int*)(w + L.par + 128);
   a.xi = (double*)(w + L.xi);
   void* lamB = w + L.lamB;   // adjoint of the populations after the step being reversed
   void* lamA = w + L.lamA;

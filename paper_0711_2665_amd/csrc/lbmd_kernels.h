@@ -175,13 +175,17 @@ void launch_ledger_bb(const void* A, const Dev& d, int nblk, int nrep, hipStream
 void launch_ledger_sp(const Dev& d, int nslots, int nrep, hipStream_t s);
 
 // Adjoint pass (one replica, chains of at most MAX_ADJ_BEADS beads).
-constexpr int MAX_ADJ_BEADS = 128;
+constexpr int MAX_ADJ_BEADS = 16384;
 struct AdjBufs {
   double* lr;       // [slots][3] adjoint of r
   double* lv;       // [slots][3] adjoint of v
   double* lJ;       // [slots][3] adjoint of the impulse J
   double* lup;      // [slots][3] adjoint of u_p
   double* lrs;      // [slots][3] position term of the spreading transpose
+  double* lr2;      // [slots][3] the other buffer of lr during the reversed sub-cycle
+  double* lv2;      // [slots][3] the other buffer of lv
+  double* gacc;     // [slots][3] per bead: dL/dgamma and dL/dF_drive terms of the reversed cycle
+  int* lok;         // 0 while the reversed step's neighbour lists hold every close pair
 
   void* lamu;       // [3][N] (storage type) adjoint of the gathered node velocity
   double* par;      // [4]: dL/dgamma, dL/dF_drive accumulators
