@@ -260,17 +260,17 @@ __global__ void k_adj_lcheck(Dev d, AdjBufs a, const double* __restrict__ mdt, i
 }
 
 // Conservative force on bead p (value and derivative along dir), by the four
-// lanes of the bead: lane l takes the pair partners j with j mod 4 = l in
-// ascending j (from the step's list, or from all beads), first collecting
-// those within r_c, then evaluating their dual LJ terms together; lane 0
-// adds the bonds, the angle forces from LDS and the wall sites.  The four
-// partial sums are combined in a fixed order, the same on every lane.
+// lanes of the bead: lane l adds the dual LJ terms of the pair partners j
+// with j mod 4 = l within r_c in ascending j (from the step's list, or from
+// all beads); lane 0 adds the bonds, the angle forces from LDS and the wall
+// sites.  The four partial sums are combined in a fixed order, the same on
+// every lane.
 // pl: local index of p in pos/dir; al: local row of the angle centred at p.
-constexpr int ADJ_MAXHIT = 16;
+constexpr int ADJ_NCAND = 12;    // list entries of one lane whose positions are loaded together
 
 __device__ inline void bead_force_sub(const MdParams& P, const Geom& g, const Dev& d, const double (*pos)[3],
                                       const double (*dir)[3], const double (*av)[9], const double (*ad)[9], int p,
-                                      int pl, int al, int lane, bool on, bool lists,
+                                      int pl, int al, int lane, bool on, bool lists, const int* lrow, int cnt,
                                       const double* __restrict__ rms, const double* __restrict__ lrin,
                                       const double* __restrict__ lvin, double F[3], double dF[3]) {
   const int nb = P.nb;
@@ -292,30 +292,43 @@ __device__ inline void bead_force_sub(const MdParams& P, const Geom& g, const De
       const double e2 = min_image(xp[2] - rms[6 * (size_t)j + 2], g.nz);
       return e0 * e0 + e1 * e1 + e2 * e2 < P.rc2;
     };
-    int hit[ADJ_MAXHIT];
-    int nh = 0;
-    const int cnt = lists ? d.ncnt[p] : 0;
-    const int* row = d.nbr + (size_t)p * MAXNBR;
     if (lists) {
-      for (int k = 0; k < cnt; ++k) {
-        const int j = row[k];
-        if ((j & 3) != lane || !close(j)) continue;
-        if (nh < ADJ_MAXHIT) hit[nh] = j;
-        ++nh;
+      // this lane's entries (j mod 4 = lane, ascending) as a mask over the
+      // staged list; the positions of the first ADJ_NCAND loaded together,
+      // then the dual LJ terms of those within r_c, in that order
+      const int* row = lrow;
+      uint64_t mk = 0;
+      for (int k = 0; k < cnt; ++k)
+        if ((row[k] & 3) == lane) mk |= 1ull << k;
+      int jm[ADJ_NCAND];
+#pragma unroll
+      for (int m = 0; m < ADJ_NCAND; ++m) {
+        jm[m] = -1;
+        if (mk) {
+          jm[m] = row[__builtin_ctzll(mk)];
+          mk &= mk - 1;
+        }
       }
-    } else {
-      for (int j = lane; j < nb; j += 4) {
-        if (j == p || !close(j)) continue;
-        if (nh < ADJ_MAXHIT) hit[nh] = j;
-        ++nh;
+      double pj[ADJ_NCAND][3];
+#pragma unroll
+      for (int m = 0; m < ADJ_NCAND; ++m) {
+        const int j = jm[m] >= 0 ? jm[m] : p;
+        pj[m][0] = rms[6 * (size_t)j]; pj[m][1] = rms[6 * (size_t)j + 1]; pj[m][2] = rms[6 * (size_t)j + 2];
       }
-    }
-    if (nh <= ADJ_MAXHIT) {
-      for (int k = 0; k < nh; ++k) lj_with(hit[k]);
-    } else if (lists) {
-      for (int k = 0; k < cnt; ++k) {
-        const int j = row[k];
-        if ((j & 3) == lane && close(j)) lj_with(j);
+#pragma unroll
+      for (int m = 0; m < ADJ_NCAND; ++m) {
+        if (jm[m] < 0) continue;
+        const double e0 = min_image(xp[0] - pj[m][0], g.nx);
+        const double e1 = min_image(xp[1] - pj[m][1], g.ny);
+        const double e2 = min_image(xp[2] - pj[m][2], g.nz);
+        if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+        lj_with(jm[m]);
+      }
+      // entries beyond the first ADJ_NCAND, one at a time
+      while (mk) {
+        const int j = row[__builtin_ctzll(mk)];
+        mk &= mk - 1;
+        if (close(j)) lj_with(j);
       }
     } else {
       for (int j = lane; j < nb; j += 4)
@@ -360,6 +373,7 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
                                                    const double* __restrict__ upt, int s, int k, double kT) {
   __shared__ double pos[AS_SPAN][3], dir[AS_SPAN][3];
   __shared__ double av[AS_BPB + 2][9], ad[AS_BPB + 2][9];
+  __shared__ int lrow[AS_BPB][MAXNBR];
   const Rep& R = d.reps[0];
   const MdParams P = R.mp;
   const Geom g = R.g;
@@ -374,6 +388,17 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
   double* lvout = (k & 1) ? a.lv : a.lv2;
   const double* rms = mdt + (size_t)s * nb * 6;   // [nb][6]: r_mid, v at the start of sub-step s
   const bool lists = *a.lok == 0;
+  // the bead's neighbour list into LDS (lane l loads entries l, l + 4, ...)
+  int cnt = 0;
+  if (lists && on) {
+    cnt = d.ncnt[p];
+    const int* row = d.nbr + (size_t)p * MAXNBR;
+#pragma unroll
+    for (int m = 0; m < MAXNBR / ADJ_LANES; ++m) {
+      const int k = lane + ADJ_LANES * m;
+      lrow[b][k] = k < cnt ? row[k] : -1;
+    }
+  }
   // positions and directions of beads p0 - 2 .. p0 + 17
   if (t < AS_SPAN) {
     const int q = p0 - 2 + t;
@@ -393,7 +418,8 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
   if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, w, av[cen - p0 + 1], ad[cen - p0 + 1]);
   __syncthreads();
   double f[3], df[3];
-  bead_force_sub(P, g, d, pos, dir, av, ad, p, b + 2, b + 1, lane, on, lists, rms, lrin, lvin, f, df);
+  bead_force_sub(P, g, d, pos, dir, av, ad, p, b + 2, b + 1, lane, on, lists, lrow[b], cnt, rms, lrin, lvin, f,
+                 df);
   if (!lead) return;
   const double h = 2.0 * P.hh;
   const double gam = P.gamma;
