@@ -10,8 +10,11 @@ library's production path.  The default workload is the large single run:
 pore, one 8000-bead chain, FP32 deviation storage of the populations.
 Inputs are synthetic (seeded self-avoiding coil, relaxed on the GPU before
 timing) and resident in HBM before the timed region.  The sweep's tile
-layout is chosen by the library's autotuner (timing whole coupled steps)
-before timing.
+layout is the one the committed kernel trace of the coupled step was taken
+in (profiles/coupled_step_<storage>_<workload>_kernels.json, the coupled
+autotuner's choice when it was taken), so that the roofline line and the
+trace describe the same launches; the autotuner's choice on the GPU at hand
+is timed beside it (--sweep-layout auto times that instead).
 
 Prints one JSON line: the metric (MLUPS of the whole coupled step), the
 roofline of the dominant kernel (the LB sweep, timed with HIP events inside
@@ -105,7 +108,18 @@ def sweep_alone(run, cells, elem):
             "bytes_per_launch": int(nbytes), "achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
-def run_gpu(cfg, precision_name, steps, warmup, layout=None):
+def profile_layout(workload, precision):
+    """The sweep layout of the committed kernel trace of the coupled step
+    (profiles/coupled_step_<storage>_<workload>_kernels.json), or None."""
+    path = os.path.join(ROOT, "profiles", f"coupled_step_{precision}_{workload}_kernels.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        lay = json.load(fh).get("layout")
+    return tuple(lay[k] for k in ("tile_nodes", "order", "grid", "cap")) if lay else None
+
+
+def run_gpu(cfg, precision_name, steps, warmup, layout=None, compare_autotuned=False):
     """Relax, time the sweep alone (autotuner, sweep-only mode), choose the
     sweep layout by timing whole coupled steps, then:
     `steps` coupled steps replayed from the captured two-step HIP graph (the
@@ -123,9 +137,23 @@ def run_gpu(cfg, precision_name, steps, warmup, layout=None):
     # the sweep alone (every fluid node, nothing beside it), in the layout
     # that is fastest for it, timed by the autotuner with HIP events
     alone = sim.autotune(reps=10)
+    auto = None
     if layout is None:
         tune = sim.autotune(reps=10, coupled=True)
     else:
+        if compare_autotuned:
+            # the coupled autotuner's choice on this GPU, timed like the
+            # headline when it differs from the pinned layout
+            at = sim.autotune(reps=10, coupled=True)
+            alay = tuple(at[k] for k in ("tile_nodes", "order", "grid", "cap"))
+            auto = {"layout": {k: at[k] for k in ("tile_nodes", "order", "grid", "cap")}}
+            if alay != tuple(layout):
+                sim.run(warmup + (warmup & 1), graph=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.run(steps, graph=True)
+                torch.cuda.synchronize()
+                auto["ms_per_step"] = round(1e3 * (time.perf_counter() - t0) / steps, 4)
         sim.sweep_config(*layout)
         tune = dict(zip(("tile_nodes", "order", "grid", "cap"), layout))
     sim.run(warmup + (warmup & 1), graph=True)          # capture, warm replays
@@ -136,7 +164,7 @@ def run_gpu(cfg, precision_name, steps, warmup, layout=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sim.check()
-    out = dict(seconds=t1 - t0, tune=tune, alone=alone)
+    out = dict(seconds=t1 - t0, tune=tune, alone=alone, autotuned=auto)
     diag0 = sim.diagnostics()
     sim.profile_start(steps)
     torch.cuda.synchronize()
@@ -425,22 +453,44 @@ def main():
     ap.add_argument("--no-mts", action="store_true")
     ap.add_argument("--no-precision-study", action="store_true")
     ap.add_argument("--c1-steps", type=int, default=None)
-    ap.add_argument("--sweep-layout", default=None,
-                    help="tile_nodes,order,grid,cap of the coupled step's sweep instead of the coupled autotuner's "
-                         "choice (profiling runs pin the layout the autotuner picks)")
+    ap.add_argument("--only", choices=["ensemble", "adjoint"], default=None,
+                    help="run only this leg and print its object (profiling runs)")
+    ap.add_argument("--sweep-layout", default="profiled",
+                    help="the coupled step's sweep layout: tile_nodes,order,grid,cap; 'profiled' (the default) "
+                         "takes the layout of the committed kernel trace, so that the roofline line and "
+                         "profiles/ describe the same launches (the coupled autotuner's own choice is timed "
+                         "beside it); 'auto' takes the coupled autotuner's choice")
     args = ap.parse_args()
-    pinned = tuple(int(x) for x in args.sweep_layout.split(",")) if args.sweep_layout else None
+
+    def layout_arg(prec):
+        if args.sweep_layout == "auto":
+            return None, "coupled autotuner"
+        if args.sweep_layout == "profiled":
+            lay = profile_layout(args.workload, prec)
+            return (lay, "committed kernel trace") if lay else (None, "coupled autotuner (no kernel trace)")
+        return tuple(int(x) for x in args.sweep_layout.split(",")), "argument"
+    pinned, pinned_from = layout_arg(args.precision)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU decomposition is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
+
+    if args.only:
+        # one leg alone (for profiling runs): its object as the JSON line
+        if args.only == "ensemble":
+            res = run_ensemble(args.ensemble_steps, 20, 200)
+        else:
+            res = run_adjoint(args.adjoint_steps, 100, (5, 20, 50, 100))
+        print(json.dumps({args.only: res}), flush=True)
+        return
 
     from paper_0711_2665_amd.workloads import CONFIGS
     cfg = CONFIGS[args.workload]
     nx, ny, nz = cfg["shape"]
     cells = nx * ny * nz
 
-    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, pinned)
+    main_run = run_gpu(cfg, args.precision, args.steps, args.warmup, pinned,
+                       compare_autotuned=args.sweep_layout == "profiled")
     progress(f"{cfg['name']} {args.precision}: {1e3 * main_run['seconds'] / args.steps:.4f} ms per step")
     ms_per_step = 1e3 * main_run["seconds"] / args.steps
     mlups = cells * args.steps / main_run["seconds"] / 1e6
@@ -476,6 +526,8 @@ def main():
                      "profile": profiled_launch(args.workload, args.precision, layout, main_run["lb_ms"],
                                                 alg_bytes)},
         "sweep_layout": layout,
+        "sweep_layout_from": pinned_from,
+        "autotuned": main_run["autotuned"],
         "sweep_alone": sweep_alone(main_run, cells, elem),
         "timing": "graph replay of the coupled step; roofline from the same kernels in eager steps",
         "eager": {"value": round(cells * args.steps / main_run["eager_seconds"] / 1e6, 1), "unit": "MLUPS",
@@ -489,7 +541,8 @@ def main():
     }
     if not args.no_fp64 and args.precision == "fp32dev":
         k64 = max(20, args.steps // 4)
-        r64 = run_gpu(cfg, "fp64", k64, max(5, args.warmup // 4))
+        p64, p64_from = layout_arg("fp64")
+        r64 = run_gpu(cfg, "fp64", k64, max(5, args.warmup // 4), p64)
         u64 = r64["nfluid"] - r64["forced_per_step"]
         alg64 = int(round(u64 * lb_bytes_per_update(8) + (cells - u64)))
         ach64 = alg64 / (r64["lb_ms"] * 1e-3) / 1e9
@@ -497,7 +550,7 @@ def main():
         out["fp64"] = {"value": round(cells * k64 / r64["seconds"] / 1e6, 1), "unit": "MLUPS", "steps": k64,
                        "ms_per_step": round(1e3 * r64["seconds"] / k64, 4),
                        "eager_ms_per_step": round(1e3 * r64["eager_seconds"] / k64, 4),
-                       "sweep_layout": lay64,
+                       "sweep_layout": lay64, "sweep_layout_from": p64_from,
                        "sweep_alone": sweep_alone(r64, cells, 8),
                        "lb_sweep_bytes_per_launch": alg64, "lb_sweep_mean_launch_ms": round(r64["lb_ms"], 5),
                        "lb_sweep_gbs": round(ach64, 1), "lb_sweep_frac": round(ach64 / PEAK_HBM_GBS, 4),
