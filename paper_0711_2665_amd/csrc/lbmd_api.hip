@@ -391,6 +391,12 @@ struct lb_ctx {
   hipGraphExec_t gexec = nullptr;
   int graph_cur = -1;
   bool capturing = false;
+  // the capture each step event was last recorded in (0: outside any): a
+  // wait inside a capture must use a record of the same capture, else the
+  // graph would depend on nodes of another (possibly destroyed) graph
+  uint64_t cap_gen = 0;
+  std::map<hipEvent_t, uint64_t> ev_gen;
+  bool stale_wait = false;
   // adjoint: the forward pass recorded by lb_adjoint_forward
   int adj_n = 0, adj_K = 0;
   int64_t adj_step0 = 0;
@@ -474,6 +480,20 @@ void prof_next(lb_ctx* c) {
   if (!c->capturing && c->prof_on && c->prof_n < c->prof_max) ++c->prof_n;
 }
 
+// Event record and wait of the step's fork/join structure, with the capture
+// the record belongs to kept on the host (see lb_ctx::ev_gen).
+void ev_record(lb_ctx* c, hipEvent_t e, hipStream_t st) {
+  acc(hipEventRecord(e, st));
+  c->ev_gen[e] = c->capturing ? c->cap_gen : 0;
+}
+void ev_wait(lb_ctx* c, hipStream_t st, hipEvent_t e) {
+  if (c->capturing) {
+    auto it = c->ev_gen.find(e);
+    if (it == c->ev_gen.end() || it->second != c->cap_gen) c->stale_wait = true;
+  }
+  acc(hipStreamWaitEvent(st, e, 0));
+}
+
 void sweep_ab(lb_ctx* c, const void* A, void* B, int skip_forced, hipStream_t st) {
   const SweepCfg& w = c->sweep;
   if (c->dev)
@@ -537,12 +557,12 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   ensure_noise(c, st);
   const Dev D = with_noise_slot(c, c->cur);
   hipStream_t sb = c->s1;
-  acc(hipEventRecord(c->fork, st));
-  acc(hipStreamWaitEvent(sb, c->fork, 0));
+  ev_record(c, c->fork, st);
+  ev_wait(c, sb, c->fork);
   prof_mark(c, 0, sb);
   launch_bead_prep(D, c->nslots, sb);
-  acc(hipEventRecord(c->prep, sb));
-  acc(hipStreamWaitEvent(c->s2, c->prep, 0));
+  ev_record(c, c->prep, sb);
+  ev_wait(c, c->s2, c->prep);
   prof_mark(c, 2, c->s2);
   sweep_ab(c, A, B, 1, c->s2);
   prof_mark(c, 3, c->s2);
@@ -564,7 +584,7 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   else if (c->fusedK > 0 && !D.mdtape)
     launch_md_cycle_fused(D, c->fb, c->pk.nseg, c->nslots, c->nrep, c->n_sub, c->fusedK, sb);
   else launch_md_cycle(D, c->nslots, c->nrep, c->n_sub, none, sb, false, c->any_constrained);
-  acc(hipEventRecord(c->mdone, sb));
+  ev_record(c, c->mdone, sb);
   if (c->dev) launch_spread_lb<float, true>(A, B, D, c->nslots, sb);
   else launch_spread_lb<double, false>(A, B, D, c->nslots, sb);
   prof_mark(c, 1, sb);
@@ -573,17 +593,17 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   // that a replayed graph issues the spreading first: the share of the
   // impulse that falls on solid nodes; for long chains the next step's
   // lists from r(n+1)
-  acc(hipStreamWaitEvent(c->s2, c->mdone, 0));
+  ev_wait(c, c->s2, c->mdone);
   if (c->step_lists) {
     launch_step_tail(D, c->nslots, c->nrep, true, c->s2);
     c->lists_stale = false;
   } else {
     launch_ledger_sp(D, c->nslots, c->nrep, c->s2);
   }
-  acc(hipEventRecord(c->join, c->s2));
-  acc(hipEventRecord(c->join1, sb));
-  acc(hipStreamWaitEvent(st, c->join, 0));
-  acc(hipStreamWaitEvent(st, c->join1, 0));
+  ev_record(c, c->join, c->s2);
+  ev_record(c, c->join1, sb);
+  ev_wait(c, st, c->join);
+  ev_wait(c, st, c->join1);
   launch_step_end(D, c->nslots, c->maxlist, c->nrep, st);
   c->noise_ready = c->any_noise;
   prof_next(c);
@@ -616,6 +636,8 @@ int build_graph(lb_ctx* c) {
   ensure_lists(c, c->s);
   const int cur0 = c->cur;
   c->capturing = true;
+  ++c->cap_gen;
+  c->stale_wait = false;
   hipError_t e = hipStreamBeginCapture(c->scap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     c->capturing = false;
@@ -628,6 +650,9 @@ int build_graph(lb_ctx* c) {
   c->capturing = false;
   c->cur = cur0;
   int rc = take_acc("graph capture");
+  // every wait inside the capture used a record made inside it
+  if (!rc && c->stale_wait)
+    rc = fail(LB_ERR_DEVICE, "graph capture: a stream waited on an event recorded outside the capture");
   // every stream the steps forked joined back before the end of the capture:
   // none of them may still be capturing (work enqueued on it later would
   // otherwise belong to a graph that no longer exists)

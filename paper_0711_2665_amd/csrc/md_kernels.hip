@@ -914,8 +914,9 @@ void launch_md_invalidate(const Dev& d, int nrep, hipStream_t s) {
 // Both projections are tridiagonal systems in the bond multipliers: RATTLE's
 // is solved once; SHAKE's linearised constraints by Newton iterations until
 // the worst bond is within CON_TOL r0^2.  Each system is solved by parallel
-// cyclic reduction in LDS (thread k owns bond k); bead p adds the
-// corrections of its bonds p (+) and p-1 (-) in that order.
+// cyclic reduction in LDS (thread k owns bond k), or for chains of at most
+// 32 beads by the Thomas algorithm on one lane; bead p adds the corrections
+// of its bonds p (+) and p-1 (-) in that order.
 // ---------------------------------------------------------------------------
 constexpr int CON_WG = 1024;
 constexpr double CON_TOL = 1e-13;
@@ -967,6 +968,30 @@ __device__ inline double con_pcr(ConShared& sh, int n) {
   return k < n ? sh.r[k] / sh.b[k] : 0.0;
 }
 
+// The same system by the Thomas algorithm on one lane (forward elimination,
+// then back substitution), for short chains: n - 1 dependent rows cost less
+// than the reduction's barriers, and the result rounds as the textbook
+// solve does.  Returns thread k's y[k].
+constexpr int CON_THOMAS_MAX = 31;
+__device__ inline double con_thomas(ConShared& sh, int n) {
+  const int k = threadIdx.x;
+  if (k == 0 && n > 0) {
+    sh.c[0] = sh.c[0] / sh.b[0];
+    sh.r[0] = sh.r[0] / sh.b[0];
+    for (int i = 1; i < n; ++i) {
+      const double den = sh.b[i] - sh.a[i] * sh.c[i - 1];
+      sh.c[i] = sh.c[i] / den;
+      sh.r[i] = (sh.r[i] - sh.a[i] * sh.r[i - 1]) / den;
+    }
+    for (int i = n - 2; i >= 0; --i) sh.r[i] = sh.r[i] - sh.c[i] * sh.r[i + 1];
+  }
+  __syncthreads();
+  return k < n ? sh.r[k] : 0.0;
+}
+__device__ inline double con_solve(ConShared& sh, int n) {
+  return n <= CON_THOMAS_MAX ? con_thomas(sh, n) : con_pcr(sh, n);   // uniform in the workgroup
+}
+
 __device__ inline double dot3v(const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
 
 // SHAKE of the drifted positions sh.x along the bonds held in sh.e (the
@@ -995,7 +1020,7 @@ __device__ inline void con_shake(ConShared& sh, int nb, double d2, uint32_t* err
       sh.r[k] = -sig;
     }
     __syncthreads();
-    const double lam = con_pcr(sh, nbond);
+    const double lam = con_solve(sh, nbond);
     // every thread has read what it needs; multipliers to sh.r, then apply
     sh.r[k] = lam;
     __syncthreads();
@@ -1061,7 +1086,7 @@ __global__ __launch_bounds__(CON_WG) void k_md_constraint(Dev d, int nslots, int
       sh.c[k] = k < nbond - 1 ? -dot3v(rv, sh.e[k + 1]) : 0.0;
     }
     __syncthreads();
-    const double mu = con_pcr(sh, nbond);
+    const double mu = con_solve(sh, nbond);
     sh.r[k] = mu;
     __syncthreads();
     if (own) {

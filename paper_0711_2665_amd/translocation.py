@@ -96,7 +96,7 @@ def scaling_exponent(lengths, taus):
 
 
 def run_length(length, replicas, max_steps, sample_every=50, precision=None, relax=None, device="cuda:0",
-               graph=True, **kw):
+               graph=True, progress=None, **kw):
     """One ensemble of `replicas` chains of `length` beads, relaxed, then
     stepped in chunks of `sample_every` until every replica has translocated
     or `max_steps` are done.  Returns the translocation steps (-1: censored),
@@ -118,7 +118,12 @@ def run_length(length, replicas, max_steps, sample_every=50, precision=None, rel
         done += n
         samples.append(ens.observables().clone())
         when.append(ens.step_count() - step0)
-        if all(t >= 0 for t in ens.translocation_steps()):
+        tx_now = ens.translocation_steps()
+        if progress is not None and len(samples) % progress == 0:
+            import sys
+            print(f"N_0 = {length}: {done} steps, {sum(t >= 0 for t in tx_now)} of {replicas} translocated",
+                  file=sys.stderr, flush=True)
+        if all(t >= 0 for t in tx_now):
             break
     torch.cuda.synchronize()
     ens.check()
@@ -175,6 +180,9 @@ def run_campaign(lengths, replicas, max_steps, sample_every=50, **kw):
     out = []
     for L in lengths:
         out.append(summarize(run_length(L, replicas, max_steps, sample_every=sample_every, **kw)))
+        if kw.get("progress") is not None:
+            import sys
+            print(f"N_0 = {L} done: {out[-1]['events']} events", file=sys.stderr, flush=True)
     ok = [s for s in out if s["events"] > 0 and np.isfinite(s["most_probable"])]
     alpha, se = scaling_exponent([s["length"] for s in ok], [s["most_probable"] for s in ok]) if len(ok) >= 2 \
         else (float("nan"), float("nan"))
@@ -227,7 +235,7 @@ def main():
     ap.add_argument("--md", help="write the text record here")
     a = ap.parse_args()
     t0 = time.perf_counter()
-    out = run_campaign(a.lengths, a.replicas, a.max_steps, sample_every=a.sample_every)
+    out = run_campaign(a.lengths, a.replicas, a.max_steps, sample_every=a.sample_every, progress=20)
     out.update(replicas=a.replicas, max_steps=a.max_steps)
     sec = time.perf_counter() - t0
     text = json.dumps(out)
