@@ -396,7 +396,9 @@ struct lb_ctx {
   // graph would depend on nodes of another (possibly destroyed) graph
   uint64_t cap_gen = 0;
   std::map<hipEvent_t, uint64_t> ev_gen;
+  std::map<hipEvent_t, hipStream_t> ev_stream;   // the stream of each event's last record
   bool stale_wait = false;
+  bool back_wait = false;      // inside a capture, the bead stream waited on the sweep stream
   // adjoint: the forward pass recorded by lb_adjoint_forward
   int adj_n = 0, adj_K = 0;
   int64_t adj_step0 = 0;
@@ -485,11 +487,15 @@ void prof_next(lb_ctx* c) {
 void ev_record(lb_ctx* c, hipEvent_t e, hipStream_t st) {
   acc(hipEventRecord(e, st));
   c->ev_gen[e] = c->capturing ? c->cap_gen : 0;
+  c->ev_stream[e] = st;
 }
 void ev_wait(lb_ctx* c, hipStream_t st, hipEvent_t e) {
   if (c->capturing) {
     auto it = c->ev_gen.find(e);
     if (it == c->ev_gen.end() || it->second != c->cap_gen) c->stale_wait = true;
+    // the forked streams depend on each other in one direction only: the
+    // sweep stream waits on the bead stream, never the reverse
+    if (st == c->s1 && c->ev_stream[e] == c->s2) c->back_wait = true;
   }
   acc(hipStreamWaitEvent(st, e, 0));
 }
@@ -571,8 +577,8 @@ void enqueue_coupled_step_ab(lb_ctx* c, const void* A, void* B, hipStream_t st) 
   // after the sweep: off the bead stream's path
   ledger_bb(c, A, c->s2);
   if (c->any_noise) launch_md_noise(with_noise_slot(c, c->cur ^ 1), c->nslots, c->n_sub, 1, c->s2);
-  // long chains: the lists of this step were built at the end of the
-  // previous one (beside the spreading), unless the positions changed since
+  // the lists of this step were built at the end of the previous one
+  // (beside the spreading), unless the positions changed since
   if (c->step_lists && c->lists_stale) launch_nbr_build(D, c->nslots, c->nrep, sb);
   // the gather also opens the sub-cycle (after its flag reset)
   launch_md_begin(D, c->nrep, sb);
@@ -638,6 +644,7 @@ int build_graph(lb_ctx* c) {
   c->capturing = true;
   ++c->cap_gen;
   c->stale_wait = false;
+  c->back_wait = false;
   hipError_t e = hipStreamBeginCapture(c->scap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     c->capturing = false;
@@ -653,6 +660,9 @@ int build_graph(lb_ctx* c) {
   // every wait inside the capture used a record made inside it
   if (!rc && c->stale_wait)
     rc = fail(LB_ERR_DEVICE, "graph capture: a stream waited on an event recorded outside the capture");
+  if (!rc && c->back_wait)
+    rc = fail(LB_ERR_DEVICE, "graph capture: the bead stream waited on the sweep stream (the forked streams "
+                             "may depend on each other in one direction only)");
   // every stream the steps forked joined back before the end of the capture:
   // none of them may still be capturing (work enqueued on it later would
   // otherwise belong to a graph that no longer exists)
