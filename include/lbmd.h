@@ -347,7 +347,9 @@ int lb_set_coupling(lb_ctx* ctx, int rep, double gamma, double f_drive);
  * lb_adjoint_forward: runs nsteps coupled steps from the current state (as
  *   md_couple_step does) and records the checkpoints in ws (device, at
  *   least the size above, 256-byte aligned, owned by the caller, kept until
- *   the backward call).
+ *   the backward call).  With K >= nsteps (one segment) it also writes the
+ *   tape, and the backward pass does not recompute the horizon; the
+ *   gradients are the same bit for bit as with any other K.
  * lb_adjoint_backward: dLdr_dev (and dLdv_dev, may be NULL for zero): [nb][3]
  *   doubles on the device, the loss gradient at the final state.  Writes
  *   grads_dev[0] = dL/dgamma, [1] = dL/dF_drive, [2 ..] = dL/dr_start

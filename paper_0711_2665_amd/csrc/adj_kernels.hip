@@ -83,12 +83,18 @@ __device__ inline void angle_dd(const MdParams& P, const Dd* ra, const Dd* rb, c
 }
 
 __device__ inline void lj_dd(const MdParams& P, Dd d0, Dd d1, Dd d2, Dd F[3]) {
-  Dd r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  const Dd r2 = d0 * d0 + d1 * d1 + d2 * d2;
   if (!(r2.v < P.rc2)) return;
-  Dd sr2 = mkd(P.sig2) / r2;
-  Dd sr6 = sr2 * sr2 * sr2;
-  Dd sr12 = sr6 * sr6;
-  Dd coef = P.eps24 * (2.0 * sr12 - sr6) / r2;
+  // one division: with q = 1 / r2, d(sig2 q) = -(sig2 q) q dr2 and
+  // d(x q) = (dx - (x q) dr2) q
+  const double q = 1.0 / r2.v;
+  const double s2 = P.sig2 * q;
+  const Dd sr2{s2, -s2 * q * r2.d};
+  const Dd sr6 = sr2 * sr2 * sr2;
+  const Dd sr12 = sr6 * sr6;
+  const Dd num = P.eps24 * (2.0 * sr12 - sr6);
+  const double cv = num.v * q;
+  const Dd coef{cv, (num.d - cv * r2.d) * q};
   F[0] = F[0] + coef * d0; F[1] = F[1] + coef * d1; F[2] = F[2] + coef * d2;
 }
 
@@ -97,7 +103,10 @@ __device__ inline void lj_dd(const MdParams& P, Dd d0, Dd d1, Dd d2, Dd F[3]) {
 // base node, minus the pore block -- the rows outside hold no site within
 // r_c, so the hit sites and their order are those of the full 6 x 6 window;
 // the derivative of the wrapped position is that of r.
-__device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, Dd F[3]) {
+// Sites are numbered row by row over the window; a caller with several lanes
+// takes those whose number is `part` modulo `nparts`.
+__device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, Dd F[3], int part = 0,
+                               int nparts = 1) {
   if (g.wall_axis < 0) return;
   const double w[3] = {wrapc(rp[0].v, g.nx), wrapc(rp[1].v, g.ny), wrapc(rp[2].v, g.nz)};
   const int b[3] = {(int)floor(w[0]), (int)floor(w[1]), (int)floor(w[2])};
@@ -109,21 +118,21 @@ __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, D
   if (off < P.wlo || off > P.whi) return;
   int site[3];
   site[a] = b[a] + off;
-  for (int o1 = P.wlo; o1 <= P.whi; ++o1) {
+  const int nw = P.whi - P.wlo + 1;
+  for (int num = part; num < nw * nw; num += nparts) {
+    const int o1 = P.wlo + num / nw, o0 = P.wlo + num % nw;
     const int u1 = b[t1] + o1;
     const int v1 = u1 < 0 ? u1 + n[t1] : (u1 >= n[t1] ? u1 - n[t1] : u1);
     const bool in1 = v1 >= g.lo1 && v1 <= g.hi1;
-    for (int o0 = P.wlo; o0 <= P.whi; ++o0) {
-      const int u0 = b[t0] + o0;
-      const int v0 = u0 < 0 ? u0 + n[t0] : (u0 >= n[t0] ? u0 - n[t0] : u0);
-      const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
-      if (in0 && in1) continue;              // pore node: fluid
-      site[t0] = u0;
-      site[t1] = u1;
-      const double e0 = w[0] - (double)site[0], e1 = w[1] - (double)site[1], e2 = w[2] - (double)site[2];
-      if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
-      lj_dd(P, Dd{e0, rp[0].d}, Dd{e1, rp[1].d}, Dd{e2, rp[2].d}, F);
-    }
+    const int u0 = b[t0] + o0;
+    const int v0 = u0 < 0 ? u0 + n[t0] : (u0 >= n[t0] ? u0 - n[t0] : u0);
+    const bool in0 = v0 >= g.lo0 && v0 <= g.hi0;
+    if (in0 && in1) continue;              // pore node: fluid
+    site[t0] = u0;
+    site[t1] = u1;
+    const double e0 = w[0] - (double)site[0], e1 = w[1] - (double)site[1], e2 = w[2] - (double)site[2];
+    if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
+    lj_dd(P, Dd{e0, rp[0].d}, Dd{e1, rp[1].d}, Dd{e2, rp[2].d}, F);
   }
 }
 
@@ -189,10 +198,11 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 }
 
 // ---------------------------------------------------------------------------
-// MD sub-cycle transpose, one launch per sub-step (in reverse order), 16
-// beads per 64-lane workgroup, four lanes per bead.  The force positions
-// r_mid and the velocities at the start of every sub-step come from the
-// tape the forward sub-cycle wrote while the segment was recomputed.  On
+// MD sub-cycle transpose, one launch per sub-step (in reverse order), four
+// beads per two-wave workgroup.  The force positions r_mid and the
+// velocities at the start of every sub-step come from the tape the forward
+// sub-cycle wrote (while the segment was recomputed, or in the forward pass
+// of a one-segment horizon).  On
 // entry lr, lv hold the adjoint of r, v after the step and lJ that of the
 // impulse J; the launches alternate between (lr, lv) and (lr2, lv2), so that
 // a launch reads every bead's adjoint before the sub-step and writes the
@@ -207,11 +217,15 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 // (for conservative forces (dF/dr)^T lvt = dF/dr lvt) enters lr, and lv
 // goes back through the kick and the first half drift.
 // ---------------------------------------------------------------------------
-constexpr int ADJ_LANES = 4;
-constexpr int AS_BPB = 16;                   // beads per workgroup
-constexpr int AS_WG = ADJ_LANES * AS_BPB;    // one wave
-constexpr int AS_SPAN = AS_BPB + 4;          // beads p0 - 2 .. p0 + 17 in LDS
+constexpr int ADJ_LANES = 16;                // lanes per bead in the pair wave (a power of two)
+constexpr int AS_BPB = 64 / ADJ_LANES;       // beads per workgroup
+constexpr int AS_WG = 128;                   // wave 0: pair and wall terms; wave 1: bonds and angles
+constexpr int AS_SPAN = AS_BPB + 4;          // beads p0 - 2 .. p0 + AS_BPB + 1 in LDS
+constexpr int ADJ_PER_LANE = MAXNBR / ADJ_LANES;   // list entries per lane
 constexpr int AS_FIN = 1024;                 // threads of k_adj_md_fin
+static_assert((ADJ_LANES & (ADJ_LANES - 1)) == 0 && 64 % ADJ_LANES == 0, "lanes per bead: a power of two");
+static_assert(MAXNBR % ADJ_LANES == 0, "whole list entries per lane");
+static_assert(3 * (AS_BPB + 2) + 2 * AS_BPB <= 64, "one thread of wave 1 per angle vertex and per bond");
 
 // Bending forces of the angle centred at local index qi of pos/dir (value
 // and derivative), vertex w, into one LDS row: [0..2] force on the bead
@@ -246,9 +260,15 @@ __global__ void k_adj_noise(Dev d, double* __restrict__ xi, uint32_t step, int n
 // every pair within r_c at the sub-steps' force positions while no bead is
 // farther than half the skin from where they were built (and no bucket of
 // the cell table overflowed); else the reverse sub-steps scan all pairs.
+// Also writes the directions the first reversed sub-step reads.
 __global__ void k_adj_lcheck(Dev d, AdjBufs a, const double* __restrict__ mdt, int nb, int n_sub) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0 && d.rb[3] != 0u) atomicOr(a.lok, 1);
+  if (t < nb) {
+    // the first reversed sub-step's directions cf (lv + hh lr)
+    const MdParams& P = d.reps[0].mp;
+    for (int c = 0; c < 3; ++c) a.dirA[3 * t + c] = P.cf * (a.lv[3 * t + c] + P.hh * a.lr[3 * t + c]);
+  }
   if (t >= nb * n_sub) return;
   const int p = t % nb;
   double d2 = 0.0;
@@ -259,193 +279,184 @@ __global__ void k_adj_lcheck(Dev d, AdjBufs a, const double* __restrict__ mdt, i
   if (!(d2 <= d.reps[0].mp.halfskin2)) atomicOr(a.lok, 1);
 }
 
-// Conservative force on bead p (value and derivative along dir), by the four
-// lanes of the bead: lane l adds the dual LJ terms of the pair partners j
-// with j mod 4 = l within r_c in ascending j (from the step's list, or from
-// all beads); lane 0 adds the bonds, the angle forces from LDS and the wall
-// sites.  The four partial sums are combined in a fixed order, the same on
-// every lane.
-// pl: local index of p in pos/dir; al: local row of the angle centred at p.
-constexpr int ADJ_NCAND = 12;    // list entries of one lane whose positions are loaded together
-
-__device__ inline void bead_force_sub(const MdParams& P, const Geom& g, const Dev& d, const double (*pos)[3],
-                                      const double (*dir)[3], const double (*av)[9], const double (*ad)[9], int p,
-                                      int pl, int al, int lane, bool on, bool lists, const int* lrow, int cnt,
-                                      const double* __restrict__ rms, const double* __restrict__ lrin,
-                                      const double* __restrict__ lvin, double F[3], double dF[3]) {
-  const int nb = P.nb;
-  Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  if (on) {
-    const double xp[3] = {pos[pl][0], pos[pl][1], pos[pl][2]};
-    const double dp[3] = {dir[pl][0], dir[pl][1], dir[pl][2]};
-    auto lj_with = [&](int j) {
-      const double e0 = min_image(xp[0] - rms[6 * (size_t)j], g.nx);
-      const double e1 = min_image(xp[1] - rms[6 * (size_t)j + 1], g.ny);
-      const double e2 = min_image(xp[2] - rms[6 * (size_t)j + 2], g.nz);
-      double dj[3];
-      for (int c = 0; c < 3; ++c) dj[c] = P.cf * (lvin[3 * j + c] + P.hh * lrin[3 * j + c]);
-      lj_dd(P, Dd{e0, dp[0] - dj[0]}, Dd{e1, dp[1] - dj[1]}, Dd{e2, dp[2] - dj[2]}, S);
-    };
-    auto close = [&](int j) {
-      const double e0 = min_image(xp[0] - rms[6 * (size_t)j], g.nx);
-      const double e1 = min_image(xp[1] - rms[6 * (size_t)j + 1], g.ny);
-      const double e2 = min_image(xp[2] - rms[6 * (size_t)j + 2], g.nz);
-      return e0 * e0 + e1 * e1 + e2 * e2 < P.rc2;
-    };
-    if (lists) {
-      // this lane's entries (j mod 4 = lane, ascending) as a mask over the
-      // staged list; the positions of the first ADJ_NCAND loaded together,
-      // then the dual LJ terms of those within r_c, in that order
-      const int* row = lrow;
-      uint64_t mk = 0;
-      for (int k = 0; k < cnt; ++k)
-        if ((row[k] & 3) == lane) mk |= 1ull << k;
-      int jm[ADJ_NCAND];
-#pragma unroll
-      for (int m = 0; m < ADJ_NCAND; ++m) {
-        jm[m] = -1;
-        if (mk) {
-          jm[m] = row[__builtin_ctzll(mk)];
-          mk &= mk - 1;
-        }
-      }
-      double pj[ADJ_NCAND][3];
-#pragma unroll
-      for (int m = 0; m < ADJ_NCAND; ++m) {
-        const int j = jm[m] >= 0 ? jm[m] : p;
-        pj[m][0] = rms[6 * (size_t)j]; pj[m][1] = rms[6 * (size_t)j + 1]; pj[m][2] = rms[6 * (size_t)j + 2];
-      }
-#pragma unroll
-      for (int m = 0; m < ADJ_NCAND; ++m) {
-        if (jm[m] < 0) continue;
-        const double e0 = min_image(xp[0] - pj[m][0], g.nx);
-        const double e1 = min_image(xp[1] - pj[m][1], g.ny);
-        const double e2 = min_image(xp[2] - pj[m][2], g.nz);
-        if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
-        lj_with(jm[m]);
-      }
-      // entries beyond the first ADJ_NCAND, one at a time
-      while (mk) {
-        const int j = row[__builtin_ctzll(mk)];
-        mk &= mk - 1;
-        if (close(j)) lj_with(j);
-      }
-    } else {
-      for (int j = lane; j < nb; j += 4)
-        if (j != p && close(j)) lj_with(j);
-    }
-    if (lane == 0) {
-      Dd rp[3] = {Dd{xp[0], dp[0]}, Dd{xp[1], dp[1]}, Dd{xp[2], dp[2]}};
-      if (p > 0) {
-        Dd rq[3] = {Dd{pos[pl - 1][0], dir[pl - 1][0]}, Dd{pos[pl - 1][1], dir[pl - 1][1]},
-                    Dd{pos[pl - 1][2], dir[pl - 1][2]}};
-        bond_dd(P, rp, rq, S);
-      }
-      if (p < nb - 1) {
-        Dd rq[3] = {Dd{pos[pl + 1][0], dir[pl + 1][0]}, Dd{pos[pl + 1][1], dir[pl + 1][1]},
-                    Dd{pos[pl + 1][2], dir[pl + 1][2]}};
-        bond_dd(P, rp, rq, S);
-      }
-      if (p - 1 >= 1 && p - 1 <= nb - 2)
-        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[al - 1][6 + a], ad[al - 1][6 + a]};
-      if (p >= 1 && p <= nb - 2)
-        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[al][3 + a], ad[al][3 + a]};
-      if (p + 1 >= 1 && p + 1 <= nb - 2)
-        for (int a = 0; a < 3; ++a) S[a] = S[a] + Dd{av[al + 1][a], ad[al + 1][a]};
-      wall_dd(P, g, rp, S);
-    }
-  }
-  // (lane0 + lane1) + (lane2 + lane3), the same on every lane of the bead
-  const int base = (int)(threadIdx.x & 63u) & ~3;
-  for (int a = 0; a < 3; ++a) {
-    double v[4], dd[4];
-    for (int l = 0; l < 4; ++l) {
-      v[l] = __shfl(S[a].v, base + l, 64);
-      dd[l] = __shfl(S[a].d, base + l, 64);
-    }
-    F[a] = (v[0] + v[1]) + (v[2] + v[3]);
-    dF[a] = (dd[0] + dd[1]) + (dd[2] + dd[3]);
-  }
-}
-
-// Reverse sub-step s, the k-th launch of the reversed cycle (k = n_sub - 1 - s).
+// Reverse sub-step s, the k-th launch of the reversed cycle (k = n_sub - 1 - s),
+// for beads p0 .. p0 + AS_BPB - 1.  The conservative force on bead p (value
+// and derivative along the directions dir) is split over two waves that run
+// side by side:
+//   wave 0, ADJ_LANES lanes per bead: lane l adds the dual LJ terms of the
+//   list entries l, l + ADJ_LANES, ... that lie within r_c (in list order,
+//   which is ascending j), or without lists those of the beads j = l mod
+//   ADJ_LANES in ascending j, then the wall sites numbered l modulo
+//   ADJ_LANES; a butterfly over the bead's lanes leaves the sum on every
+//   lane;
+//   wave 1: the bonds of each bead and the vertices of the angles centred at
+//   p0 - 1 .. p0 + AS_BPB, into LDS.
+// The bead's force is then the pair-and-wall sum plus the bond to p - 1, the
+// bond to p + 1 and the angle terms (centred at p - 1, p, p + 1), in that
+// order.
+// Every address of the first loads comes from the arguments (nb included),
+// so they do not wait for the parameter block.
 __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const double* __restrict__ mdt,
-                                                   const double* __restrict__ upt, int s, int k, double kT) {
+                                                   const double* __restrict__ upt, int nb, int s, int k,
+                                                   double kT) {
   __shared__ double pos[AS_SPAN][3], dir[AS_SPAN][3];
   __shared__ double av[AS_BPB + 2][9], ad[AS_BPB + 2][9];
-  __shared__ int lrow[AS_BPB][MAXNBR];
+  __shared__ double bv[AS_BPB][2][3], bd[AS_BPB][2][3];
   const Rep& R = d.reps[0];
   const MdParams P = R.mp;
   const Geom g = R.g;
-  const int nb = P.nb;
   const int p0 = blockIdx.x * AS_BPB;
-  const int t = threadIdx.x, b = t / ADJ_LANES, lane = t % ADJ_LANES, p = p0 + b;
-  const bool on = p < nb, lead = on && lane == 0;
+  const int t = threadIdx.x;
+  const bool pairw = t < 64;
+  const int u = t & 63, b = u / ADJ_LANES, lane = u % ADJ_LANES, p = p0 + b;
+  const bool on = p < nb, lead = pairw && on && lane == 0;
   const bool first = k == 0;
   const double* lrin = (k & 1) ? a.lr2 : a.lr;
   const double* lvin = (k & 1) ? a.lv2 : a.lv;
   double* lrout = (k & 1) ? a.lr : a.lr2;
   double* lvout = (k & 1) ? a.lv : a.lv2;
+  // every bead's direction cf (lv + hh lr), written by the previous launch
+  // (the first from k_adj_lcheck)
+  const double* dirin = (k & 1) ? a.dirB : a.dirA;
+  double* dirout = (k & 1) ? a.dirA : a.dirB;
   const double* rms = mdt + (size_t)s * nb * 6;   // [nb][6]: r_mid, v at the start of sub-step s
   const bool lists = *a.lok == 0;
-  // the bead's neighbour list into LDS (lane l loads entries l, l + 4, ...)
-  int cnt = 0;
-  if (lists && on) {
-    cnt = d.ncnt[p];
-    const int* row = d.nbr + (size_t)p * MAXNBR;
+  // the adding lane's own state, loaded first
+  double olr[3] = {0.0, 0.0, 0.0}, olv[3] = {0.0, 0.0, 0.0}, olJ[3] = {0.0, 0.0, 0.0}, ou[3] = {0.0, 0.0, 0.0};
+  double ovo[3] = {0.0, 0.0, 0.0}, oxi[3] = {0.0, 0.0, 0.0}, olu[3] = {0.0, 0.0, 0.0};
+  double og = 0.0, of = 0.0;
+  if (lead) {
 #pragma unroll
-    for (int m = 0; m < MAXNBR / ADJ_LANES; ++m) {
-      const int k = lane + ADJ_LANES * m;
-      lrow[b][k] = k < cnt ? row[k] : -1;
+    for (int c = 0; c < 3; ++c) {
+      olr[c] = lrin[3 * p + c];
+      olv[c] = lvin[3 * p + c];
+      olJ[c] = a.lJ[3 * p + c];
+      ou[c] = upt[3 * p + c];
+      ovo[c] = rms[6 * (size_t)p + 3 + c];
+      if (kT != 0.0) oxi[c] = a.xi[((size_t)s * nb + p) * 3 + c];   // drawn when kT > 0 (sigma > 0)
+      if (!first) olu[c] = a.lup[3 * p + c];
     }
+    if (!first) { og = a.gacc[3 * p]; of = a.gacc[3 * p + 1]; }
   }
-  // positions and directions of beads p0 - 2 .. p0 + 17
-  if (t < AS_SPAN) {
-    const int q = p0 - 2 + t;
+  // wave 0: the bead's own position and direction, this lane's list
+  // entries (all loaded at once; those past the count are dropped, and the
+  // lists are dropped when the flag says they do not hold)
+  double xp[3] = {0.0, 0.0, 0.0}, dp[3] = {0.0, 0.0, 0.0};
+  int jm[ADJ_PER_LANE];
+#pragma unroll
+  for (int m = 0; m < ADJ_PER_LANE; ++m) jm[m] = -1;
+  if (pairw && on) {
+    for (int c = 0; c < 3; ++c) { xp[c] = rms[6 * (size_t)p + c]; dp[c] = dirin[3 * p + c]; }
+    const int cnt = d.ncnt[p];
+    const int* row = d.nbr + (size_t)p * MAXNBR;
+    int e[ADJ_PER_LANE];
+#pragma unroll
+    for (int m = 0; m < ADJ_PER_LANE; ++m) e[m] = row[lane + ADJ_LANES * m];
+#pragma unroll
+    for (int m = 0; m < ADJ_PER_LANE; ++m)
+      if (lists && lane + ADJ_LANES * m < cnt) jm[m] = e[m];
+  }
+  // wave 1: positions and directions of beads p0 - 2 .. p0 + AS_BPB + 1
+  if (!pairw && u < AS_SPAN) {
+    const int q = p0 - 2 + u;
     if (q >= 0 && q < nb)
       for (int c = 0; c < 3; ++c) {
-        pos[t][c] = rms[6 * (size_t)q + c];
-        dir[t][c] = P.cf * (lvin[3 * q + c] + P.hh * lrin[3 * q + c]);
+        pos[u][c] = rms[6 * (size_t)q + c];
+        dir[u][c] = dirin[3 * q + c];
       }
   }
   __syncthreads();
-  // the angles centred at p0 - 1 .. p0 + 16 (row = centre - p0 + 1): lanes
-  // 0-2 of bead b take vertex `lane` of the angle centred at p0 + b, lane 3
-  // of beads 0-5 the vertices of the two angles just outside
-  int cen = -1, w = 0;
-  if (lane < 3) { cen = p; w = lane; }
-  else if (b < 6) { cen = b < 3 ? p0 - 1 : p0 + AS_BPB; w = b % 3; }
-  if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, w, av[cen - p0 + 1], ad[cen - p0 + 1]);
+  Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  if (!pairw) {
+    if (u < 3 * (AS_BPB + 2)) {
+      // vertex u mod 3 of the angle centred at p0 - 1 + u / 3 (row u / 3)
+      const int cen = p0 - 1 + u / 3;
+      if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, u % 3, av[u / 3], ad[u / 3]);
+    } else if (u < 3 * (AS_BPB + 2) + 2 * AS_BPB) {
+      // bond of bead bb to bb - 1 (side 0) or bb + 1 (side 1)
+      const int bb = (u - 3 * (AS_BPB + 2)) / 2, side = (u - 3 * (AS_BPB + 2)) % 2;
+      const int q = p0 + bb, o = side ? q + 1 : q - 1;
+      if (q < nb && o >= 0 && o < nb) {
+        const int ql = bb + 2, ol = side ? ql + 1 : ql - 1;
+        Dd rp[3] = {Dd{pos[ql][0], dir[ql][0]}, Dd{pos[ql][1], dir[ql][1]}, Dd{pos[ql][2], dir[ql][2]}};
+        Dd rq[3] = {Dd{pos[ol][0], dir[ol][0]}, Dd{pos[ol][1], dir[ol][1]}, Dd{pos[ol][2], dir[ol][2]}};
+        bond_dd(P, rp, rq, S);
+      }
+      for (int c = 0; c < 3; ++c) { bv[bb][side][c] = S[c].v; bd[bb][side][c] = S[c].d; }
+    }
+  } else {
+    if (on) {
+      auto lj_with = [&](const double* rj, const double* dj) {
+        const double e0 = min_image(xp[0] - rj[0], g.nx);
+        const double e1 = min_image(xp[1] - rj[1], g.ny);
+        const double e2 = min_image(xp[2] - rj[2], g.nz);
+        lj_dd(P, Dd{e0, dp[0] - dj[0]}, Dd{e1, dp[1] - dj[1]}, Dd{e2, dp[2] - dj[2]}, S);
+      };
+      if (lists) {
+        // the entries' positions and directions loaded together
+        double ej[ADJ_PER_LANE][3], dj[ADJ_PER_LANE][3];
+#pragma unroll
+        for (int m = 0; m < ADJ_PER_LANE; ++m) {
+          const int j = jm[m] >= 0 ? jm[m] : p;
+          for (int c = 0; c < 3; ++c) { ej[m][c] = rms[6 * (size_t)j + c]; dj[m][c] = dirin[3 * j + c]; }
+        }
+#pragma unroll
+        for (int m = 0; m < ADJ_PER_LANE; ++m)
+          if (jm[m] >= 0) lj_with(ej[m], dj[m]);
+      } else {
+        for (int j = lane; j < nb; j += ADJ_LANES)
+          if (j != p) {
+            const double rj[3] = {rms[6 * (size_t)j], rms[6 * (size_t)j + 1], rms[6 * (size_t)j + 2]};
+            const double dj[3] = {dirin[3 * j], dirin[3 * j + 1], dirin[3 * j + 2]};
+            lj_with(rj, dj);
+          }
+      }
+      Dd rp[3] = {Dd{xp[0], dp[0]}, Dd{xp[1], dp[1]}, Dd{xp[2], dp[2]}};
+      wall_dd(P, g, rp, S, lane, ADJ_LANES);
+    }
+    // butterfly over the bead's lanes (contiguous and ADJ_LANES-aligned in
+    // the wave): a + b on one side of each exchange and b + a on the other
+    // round to the same value
+#pragma unroll
+    for (int off = ADJ_LANES / 2; off > 0; off >>= 1)
+      for (int c = 0; c < 3; ++c) {
+        S[c].v = S[c].v + __shfl_xor(S[c].v, off, 64);
+        S[c].d = S[c].d + __shfl_xor(S[c].d, off, 64);
+      }
+  }
   __syncthreads();
-  double f[3], df[3];
-  bead_force_sub(P, g, d, pos, dir, av, ad, p, b + 2, b + 1, lane, on, lists, lrow[b], cnt, rms, lrin, lvin, f,
-                 df);
   if (!lead) return;
+  const int al = b + 1;   // row of the angle centred at p
+  for (int c = 0; c < 3; ++c) {
+    if (p > 0) S[c] = S[c] + Dd{bv[b][0][c], bd[b][0][c]};
+    if (p < nb - 1) S[c] = S[c] + Dd{bv[b][1][c], bd[b][1][c]};
+    if (p - 1 >= 1 && p - 1 <= nb - 2) S[c] = S[c] + Dd{av[al - 1][6 + c], ad[al - 1][6 + c]};
+    if (p >= 1 && p <= nb - 2) S[c] = S[c] + Dd{av[al][3 + c], ad[al][3 + c]};
+    if (p + 1 >= 1 && p + 1 <= nb - 2) S[c] = S[c] + Dd{av[al + 1][c], ad[al + 1][c]};
+  }
+  double f[3] = {S[0].v, S[1].v, S[2].v}, df[3] = {S[0].d, S[1].d, S[2].d};
   const double h = 2.0 * P.hh;
   const double gam = P.gamma;
   const double de = -h * P.e, domE = h * P.e;
   const double dcf = (h * P.e) / (P.m * gam) - P.omE / (P.m * gam * gam);
   const double dsig = P.sig > 0.0 ? ((kT / P.m) * (h * P.e * P.e)) / P.sig : 0.0;
-  const double rm[3] = {pos[b + 2][0], pos[b + 2][1], pos[b + 2][2]};
-  const bool field = P.field_on && in_field(g, rm);
+  const bool field = P.field_on && in_field(g, xp);
   if (field) f[g.wall_axis] += P.f_drive;
-  double xi[3] = {0.0, 0.0, 0.0};
-  if (P.sig != 0.0)
-    for (int c = 0; c < 3; ++c) xi[c] = a.xi[((size_t)s * nb + p) * 3 + c];
-  double acc_g = first ? 0.0 : a.gacc[3 * p], acc_f = first ? 0.0 : a.gacc[3 * p + 1];
+  double acc_g = og, acc_f = of;
   for (int c = 0; c < 3; ++c) {
-    const double lr = lrin[3 * p + c], lv = lvin[3 * p + c], lJ = a.lJ[3 * p + c], u = upt[3 * p + c];
+    const double lr = olr[c], lv = olv[c], lJ = olJ[c], u = ou[c];
     const double lvt = lv + P.hh * lr;
-    const double vo = rms[6 * (size_t)p + 3 + c];
-    acc_g += lvt * (vo * de + (f[c] + gam * u) * dcf + P.cf * u + xi[c] * dsig);
-    acc_g += lJ * (-P.m) * ((u - vo) * domE + xi[c] * dsig);
-    const double lu = first ? 0.0 : a.lup[3 * p + c];
-    a.lup[3 * p + c] = lu + (P.cf * gam * lvt - P.m * P.omE * lJ);
+    const double vo = ovo[c];
+    acc_g += lvt * (vo * de + (f[c] + gam * u) * dcf + P.cf * u + oxi[c] * dsig);
+    acc_g += lJ * (-P.m) * ((u - vo) * domE + oxi[c] * dsig);
+    a.lup[3 * p + c] = olu[c] + (P.cf * gam * lvt - P.m * P.omE * lJ);
     const double lrm = lr + df[c];
+    const double lvn = P.e * lvt + P.m * P.omE * lJ + P.hh * lrm;
     lrout[3 * p + c] = lrm;
-    lvout[3 * p + c] = P.e * lvt + P.m * P.omE * lJ + P.hh * lrm;
+    lvout[3 * p + c] = lvn;
+    dirout[3 * p + c] = P.cf * (lvn + P.hh * lrm);
   }
-  if (field) acc_f += P.cf * (lvin[3 * p + g.wall_axis] + P.hh * lrin[3 * p + g.wall_axis]);
+  if (field) acc_f += dp[g.wall_axis];
   a.gacc[3 * p] = acc_g;
   a.gacc[3 * p + 1] = acc_f;
 }
@@ -623,7 +634,8 @@ void launch_adj_reverse_step(const void* A, const void* lamB, void* lamA, const 
     hipLaunchKernelGGL(k_adj_noise, dim3(nblk((long)nb * n_sub, 256)), dim3(256), 0, s, d, a.xi, step, nb, n_sub);
   }
   for (int k = 0; k < n_sub; ++k)
-    hipLaunchKernelGGL(k_adj_sub, dim3(nblk(nb, AS_BPB)), dim3(AS_WG), 0, s, d, a, mdt, upt, n_sub - 1 - k, k, kT);
+    hipLaunchKernelGGL(k_adj_sub, dim3(nblk(nb, AS_BPB)), dim3(AS_WG), 0, s, d, a, mdt, upt, nb, n_sub - 1 - k, k,
+                       kT);
   hipLaunchKernelGGL(k_adj_md_fin, dim3(1), dim3(AS_FIN), 0, s, a, nb, n_sub);
   hipLaunchKernelGGL((k_adj_gather_t<T, DEV>), dim3(nblk(nb, 64)), dim3(64), 0, s, (const T*)A, d, a, nb);
   launch_spread<T>(dspread, nslots, s);

@@ -401,6 +401,7 @@ struct lb_ctx {
   bool back_wait = false;      // inside a capture, the bead stream waited on the sweep stream
   // adjoint: the forward pass recorded by lb_adjoint_forward
   int adj_n = 0, adj_K = 0;
+  bool adj_taped = false;   // the forward pass recorded the whole horizon's tape
   int64_t adj_step0 = 0;
   char* adj_ws = nullptr;
   // kernel timing (lb_profile_start / lb_profile_stop)
@@ -715,7 +716,7 @@ AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
   L.lamA = o; o += L.pops_slot;
   L.lamB = o; o += L.pops_slot;
   L.lamu = o; o += align256(es * 3 * (size_t)c->pk.nodes);
-  L.lbead = o; o += 8 * L.bead_arr;
+  L.lbead = o; o += 10 * L.bead_arr;
   L.mdtape = o; o += (size_t)K * L.md_arr;
   L.xi = o; o += align256(sizeof(double) * 3 * (size_t)c->d[0].nb * (size_t)c->n_sub);
   L.par = o; o += 256;
@@ -755,6 +756,33 @@ void restore_state(lb_ctx* c, const char* st, void* dst_pops) {
   launch_md_invalidate(c->D, c->nrep, c->s);
   c->lists_stale = true;
   c->noise_ready = false;
+}
+
+// Runs steps n0 .. n0 + len - 1 from the checkpoint of that segment (the
+// state at n0, already in the context's arrays or in `ckpt`), writing the
+// tape the reverse steps read: populations before each step, r, v, u_p, J
+// of each step and the sub-steps' r_mid, v.  The last step's populations go
+// to other_pops(c).
+void record_segment(lb_ctx* c, const AdjLayout& L, char* w, const char* ckpt, int len) {
+  auto tape_pops = [&](int j) { return (void*)(w + L.tape_pops + (size_t)j * L.pops_slot); };
+  auto tape_bead = [&](int j, int which) {
+    return (double*)(w + L.tape_beads + ((size_t)j * 4 + which) * L.bead_arr);
+  };
+  const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
+  restore_state(c, ckpt, tape_pops(0));
+  for (int j = 0; j < len; ++j) {
+    acc(hipMemcpyAsync(tape_bead(j, 0), c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
+    acc(hipMemcpyAsync(tape_bead(j, 1), c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
+    void* B = j + 1 < len ? tape_pops(j + 1) : other_pops(c);
+    c->D.mdtape = (double*)(w + L.mdtape + (size_t)j * L.md_arr);
+    // these steps keep the population parity, so the noise slot does not
+    // alternate: every step draws its own noise
+    c->noise_ready = false;
+    enqueue_coupled_step_ab(c, tape_pops(j), B, c->s);
+    c->D.mdtape = nullptr;
+    acc(hipMemcpyAsync(tape_bead(j, 2), c->D.up, nb3, hipMemcpyDeviceToDevice, c->s));
+    acc(hipMemcpyAsync(tape_bead(j, 3), c->D.J, nb3, hipMemcpyDeviceToDevice, c->s));
+  }
 }
 
 }  // namespace
@@ -1505,19 +1533,31 @@ int lb_adjoint_forward(lb_ctx* c, int nsteps, int K, void* ws, size_t ws_bytes) 
   if (ws_bytes < L.total) return fail(LB_ERR_ARG, "workspace too small (%zu < %zu bytes)", ws_bytes, L.total);
   if (((uintptr_t)ws) & 255) return fail(LB_ERR_ARG, "workspace is not 256-byte aligned");
   char* w = (char*)ws;
+  c->adj_ws = nullptr;
   c->adj_step0 = c->steps;
   rc = lb_get_state(c, w + L.ckpt);
   if (rc) return rc;
-  for (int seg = 0; seg < L.nseg; ++seg) {
-    int len = std::min(K, nsteps - seg * K);
-    for (int k = 0; k < len; ++k) enqueue_coupled_step(c, c->s);
-    c->steps += len;
-    rc = lb_get_state(c, w + L.ckpt + (size_t)(seg + 1) * c->sl.total);
+  if (L.nseg == 1) {
+    // one segment: the forward pass writes the tape itself, and the
+    // backward pass reverses it without recomputing the horizon
+    record_segment(c, L, w, w + L.ckpt, nsteps);
+    c->cur ^= 1;   // the last step wrote other_pops
+    c->steps += nsteps;
+    rc = lb_get_state(c, w + L.ckpt + c->sl.total);
     if (rc) return rc;
+  } else {
+    for (int seg = 0; seg < L.nseg; ++seg) {
+      int len = std::min(K, nsteps - seg * K);
+      for (int k = 0; k < len; ++k) enqueue_coupled_step(c, c->s);
+      c->steps += len;
+      rc = lb_get_state(c, w + L.ckpt + (size_t)(seg + 1) * c->sl.total);
+      if (rc) return rc;
+    }
   }
   c->adj_n = nsteps;
   c->adj_K = K;
   c->adj_ws = w;
+  c->adj_taped = L.nseg == 1;
   return check_hip("lb_adjoint_forward");
 }
 
@@ -1540,6 +1580,8 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
   a.lr2 = (double*)(w + L.lbead + 5 * L.bead_arr);
   a.lv2 = (double*)(w + L.lbead + 6 * L.bead_arr);
   a.gacc = (double*)(w + L.lbead + 7 * L.bead_arr);
+  a.dirA = (double*)(w + L.lbead + 8 * L.bead_arr);
+  a.dirB = (double*)(w + L.lbead + 9 * L.bead_arr);
   a.lamu = w + L.lamu;
   a.par = (double*)(w + L.par);
   a.lok = (int*)(w + L.par + 128);
@@ -1554,26 +1596,13 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
   auto tape_bead = [&](int j, int which) {
     return (double*)(w + L.tape_beads + ((size_t)j * 4 + which) * L.bead_arr);
   };
-  const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
   const double kT = c->d[0].kT;
   for (int seg = L.nseg - 1; seg >= 0; --seg) {
     const int n0 = seg * K;
     const int len = std::min(K, nsteps - n0);
-    // recompute the segment from its checkpoint, writing the tape
-    restore_state(c, w + L.ckpt + (size_t)seg * c->sl.total, tape_pops(0));
-    for (int j = 0; j < len; ++j) {
-      acc(hipMemcpyAsync(tape_bead(j, 0), c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
-      acc(hipMemcpyAsync(tape_bead(j, 1), c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
-      void* B = j + 1 < len ? tape_pops(j + 1) : other_pops(c);
-      c->D.mdtape = (double*)(w + L.mdtape + (size_t)j * L.md_arr);
-      // these steps keep the population parity, so the noise slot does not
-      // alternate: every step draws its own noise
-      c->noise_ready = false;
-      enqueue_coupled_step_ab(c, tape_pops(j), B, c->s);
-      c->D.mdtape = nullptr;
-      acc(hipMemcpyAsync(tape_bead(j, 2), c->D.up, nb3, hipMemcpyDeviceToDevice, c->s));
-      acc(hipMemcpyAsync(tape_bead(j, 3), c->D.J, nb3, hipMemcpyDeviceToDevice, c->s));
-    }
+    // recompute the segment from its checkpoint, writing the tape (a
+    // one-segment horizon was taped by the forward pass)
+    if (!c->adj_taped) record_segment(c, L, w, w + L.ckpt + (size_t)seg * c->sl.total, len);
     // reverse the segment's steps
     for (int j = len - 1; j >= 0; --j) {
       Dev da = c->D;

@@ -185,6 +185,8 @@ struct AdjBufs {
   double* lr2;      // [slots][3] the other buffer of lr during the reversed sub-cycle
   double* lv2;      // [slots][3] the other buffer of lv
   double* gacc;     // [slots][3] per bead: dL/dgamma and dL/dF_drive terms of the reversed cycle
+  double* dirA;     // [slots][3] the force derivative's direction cf (lv + hh lr) of each bead,
+  double* dirB;     //   alternating between the reversed sub-steps
   int* lok;         // 0 while the reversed step's neighbour lists hold every close pair
 
   void* lamu;       // [3][N] (storage type) adjoint of the gathered node velocity

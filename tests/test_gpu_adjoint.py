@@ -143,10 +143,11 @@ def test_adjoint_leaves_the_forward_end_state(orc):
     sim.couple_step(NSTEPS)
     torch.cuda.synchronize()
     want_p, want_r = sim.pops().clone(), sim.beads()["r"].clone()
-    _adjoint(sim, st, CFG, NSTEPS, 5)
-    torch.cuda.synchronize()
-    assert torch.equal(sim.pops(), want_p) and torch.equal(sim.beads()["r"], want_r)
-    assert sim.step_count() == NSTEPS
+    for K in (5, NSTEPS):   # recomputed segments; the tape written by the forward pass
+        _adjoint(sim, st, CFG, NSTEPS, K)
+        torch.cuda.synchronize()
+        assert torch.equal(sim.pops(), want_p) and torch.equal(sim.beads()["r"], want_r)
+        assert sim.step_count() == NSTEPS
     sim.check()
 
 
