@@ -253,7 +253,9 @@ def run_adjoint(nsteps, K, horizons):
     normal coordinate after the run, gradient w.r.t. gamma, F_drive and the
     initial positions by the library's adjoint with checkpoints every K
     steps.  Timed over nsteps coupled steps in FP64 and FP32 deviation
-    storage.
+    storage, and again as one segment (the forward pass writes the whole
+    horizon's tape into HBM, and the backward pass does not recompute it;
+    the gradient is the same bit for bit).
 
     The bead dynamics is chaotic: the derivative of the discrete map grows
     roughly like exp(0.013 n), and the last-bit differences between two FP64
@@ -295,6 +297,24 @@ def run_adjoint(nsteps, K, horizons):
         out[name] = {"adjoint_steps_per_s": round(nsteps / (t2 - t0), 2), "forward_s": round(t1 - t0, 3),
                      "reverse_s": round(t2 - t1, 3)}
         full[name] = {"dL_dgamma": float(g[0]), "dL_dF_drive": float(g[1])}
+        # the same horizon as one segment: the forward pass writes the whole
+        # tape (held in HBM) and the backward pass does not recompute it
+        sim.set_state(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.adjoint_forward(nsteps, nsteps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g1 = sim.adjoint_backward(dLdr).cpu().numpy()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        sim.check()
+        out[name]["one_segment"] = {
+            "adjoint_steps_per_s": round(nsteps / (t2 - t0), 2), "forward_s": round(t1 - t0, 3),
+            "reverse_s": round(t2 - t1, 3), "workspace_GB": round(sim.adjoint_sizes(nsteps, nsteps) / 1e9, 2),
+            "same_gradient_bits": bool(np.array_equal(g, g1))}
+        sim._adj_ws = None
+        torch.cuda.empty_cache()
         sims[name] = (sim, st)
 
     def grad(name, T):

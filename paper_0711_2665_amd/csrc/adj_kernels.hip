@@ -59,7 +59,10 @@ __device__ inline void bond_dd(const MdParams& P, const Dd* rp, const Dd* rq, Dd
   F[0] = F[0] + coef * d0; F[1] = F[1] + coef * d1; F[2] = F[2] + coef * d2;
 }
 
-__device__ inline void angle_dd(const MdParams& P, const Dd* ra, const Dd* rb, const Dd* rc, int which, Dd F[3]) {
+// The three vertex forces of the bending term at once (F0 on the bead
+// before the centre, F1 on the centre, F2 on the bead after it).
+__device__ inline void angle_dd3(const MdParams& P, const Dd* ra, const Dd* rb, const Dd* rc, Dd F0[3], Dd F1[3],
+                                 Dd F2[3]) {
   Dd b1[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
   Dd b2[3] = {rc[0] - rb[0], rc[1] - rb[1], rc[2] - rb[2]};
   Dd n[3] = {b1[1] * b2[2] - b1[2] * b2[1], b1[2] * b2[0] - b1[0] * b2[2], b1[0] * b2[1] - b1[1] * b2[0]};
@@ -68,17 +71,17 @@ __device__ inline void angle_dd(const MdParams& P, const Dd* ra, const Dd* rb, c
   if (s.v == 0.0) return;
   Dd phi = datan2(s, c);
   Dd den = s * s + c * c;
-  Dd g1[3] = {b2[1] * n[2] - b2[2] * n[1], b2[2] * n[0] - b2[0] * n[2], b2[0] * n[1] - b2[1] * n[0]};
-  Dd g2[3] = {n[1] * b1[2] - n[2] * b1[1], n[2] * b1[0] - n[0] * b1[2], n[0] * b1[1] - n[1] * b1[0]};
   Dd kp = P.kappa * phi;
   for (int a = 0; a < 3; ++a) {
-    Dd d1 = (c * g1[a] / s - s * b2[a]) / den;
-    Dd d2 = (c * g2[a] / s - s * b1[a]) / den;
-    Dd f;
-    if (which == 0) f = kp * d1;
-    else if (which == 1) f = -(kp * (d1 - d2));
-    else f = -(kp * d2);
-    F[a] = F[a] + f;
+    // component a of b2 x n and of n x b1
+    const int a1 = a == 2 ? 0 : a + 1, a2 = a == 0 ? 2 : a - 1;
+    const Dd g1 = b2[a1] * n[a2] - b2[a2] * n[a1];
+    const Dd g2 = n[a1] * b1[a2] - n[a2] * b1[a1];
+    Dd d1 = (c * g1 / s - s * b2[a]) / den;
+    Dd d2 = (c * g2 / s - s * b1[a]) / den;
+    F0[a] = F0[a] + kp * d1;
+    F1[a] = F1[a] + -(kp * (d1 - d2));
+    F2[a] = F2[a] + -(kp * d2);
   }
 }
 
@@ -225,12 +228,12 @@ constexpr int ADJ_PER_LANE = MAXNBR / ADJ_LANES;   // list entries per lane
 constexpr int AS_FIN = 1024;                 // threads of k_adj_md_fin
 static_assert((ADJ_LANES & (ADJ_LANES - 1)) == 0 && 64 % ADJ_LANES == 0, "lanes per bead: a power of two");
 static_assert(MAXNBR % ADJ_LANES == 0, "whole list entries per lane");
-static_assert(3 * (AS_BPB + 2) + 2 * AS_BPB <= 64, "one thread of wave 1 per angle vertex and per bond");
+static_assert(AS_BPB + 2 <= 32 && 32 + 2 * AS_BPB <= 64, "one thread of wave 1 per angle and per bond");
 
-// Bending forces of the angle centred at local index qi of pos/dir (value
-// and derivative), vertex w, into one LDS row: [0..2] force on the bead
-// before the centre, [3..5] on the centre, [6..8] on the bead after it.
-__device__ inline void angle_dual(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int qi, int w,
+// Bending forces of the angle centred at index qi of pos/dir (value and
+// derivative) into one LDS row: [0..2] force on the bead before the centre,
+// [3..5] on the centre, [6..8] on the bead after it.
+__device__ inline void angle_dual(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int qi,
                                   double* av, double* ad) {
   Dd ra[3], rb[3], rc[3];
   for (int a = 0; a < 3; ++a) {
@@ -238,9 +241,90 @@ __device__ inline void angle_dual(const MdParams& P, const double (*pos)[3], con
     rb[a] = Dd{pos[qi][a], dir[qi][a]};
     rc[a] = Dd{pos[qi + 1][a], dir[qi + 1][a]};
   }
-  Dd F[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  angle_dd(P, ra, rb, rc, w, F);
-  for (int a = 0; a < 3; ++a) { av[3 * w + a] = F[a].v; ad[3 * w + a] = F[a].d; }
+  Dd F0[3] = {mkd(0.0), mkd(0.0), mkd(0.0)}, F1[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  Dd F2[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  angle_dd3(P, ra, rb, rc, F0, F1, F2);
+  for (int a = 0; a < 3; ++a) {
+    av[a] = F0[a].v; ad[a] = F0[a].d;
+    av[3 + a] = F1[a].v; ad[3 + a] = F1[a].d;
+    av[6 + a] = F2[a].v; ad[6 + a] = F2[a].d;
+  }
+}
+
+// Bond force on the bead at index ql of pos/dir from the one at ol.
+__device__ inline void bond_dual(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int ql, int ol,
+                                 double* bv, double* bd) {
+  Dd rp[3] = {Dd{pos[ql][0], dir[ql][0]}, Dd{pos[ql][1], dir[ql][1]}, Dd{pos[ql][2], dir[ql][2]}};
+  Dd rq[3] = {Dd{pos[ol][0], dir[ol][0]}, Dd{pos[ol][1], dir[ol][1]}, Dd{pos[ol][2], dir[ol][2]}};
+  Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+  bond_dd(P, rp, rq, S);
+  for (int c = 0; c < 3; ++c) { bv[c] = S[c].v; bd[c] = S[c].d; }
+}
+
+// Dual LJ term of the pair (bead at xp with direction dp, partner at rj
+// with direction dj), if within r_c.
+__device__ inline void lj_pair(const MdParams& P, const Geom& g, const double* xp, const double* dp,
+                               const double* rj, const double* dj, Dd S[3]) {
+  const double e0 = min_image(xp[0] - rj[0], g.nx);
+  const double e1 = min_image(xp[1] - rj[1], g.ny);
+  const double e2 = min_image(xp[2] - rj[2], g.nz);
+  lj_dd(P, Dd{e0, dp[0] - dj[0]}, Dd{e1, dp[1] - dj[1]}, Dd{e2, dp[2] - dj[2]}, S);
+}
+
+// Butterfly over the ADJ_LANES lanes of one bead (contiguous and aligned in
+// the wave, all active): a + b on one side of each exchange and b + a on
+// the other round to the same value, so every lane ends with the same sum.
+__device__ inline void lanes_sum(Dd S[3]) {
+#pragma unroll
+  for (int off = ADJ_LANES / 2; off > 0; off >>= 1)
+    for (int c = 0; c < 3; ++c) {
+      S[c].v = S[c].v + __shfl_xor(S[c].v, off, 64);
+      S[c].d = S[c].d + __shfl_xor(S[c].d, off, 64);
+    }
+}
+
+// The conservative force on bead p from its parts, in a fixed order: the
+// pair-and-wall sum, the bond to p - 1, the bond to p + 1, the angle terms
+// centred at p - 1, p, p + 1 (rows am, a0, ap of av/ad).
+__device__ inline void add_bonded(Dd S[3], int p, int nb, const double* bm_v, const double* bm_d,
+                                  const double* bp_v, const double* bp_d, const double* am_v, const double* am_d,
+                                  const double* a0_v, const double* a0_d, const double* ap_v, const double* ap_d) {
+  for (int c = 0; c < 3; ++c) {
+    if (p > 0) S[c] = S[c] + Dd{bm_v[c], bm_d[c]};
+    if (p < nb - 1) S[c] = S[c] + Dd{bp_v[c], bp_d[c]};
+    if (p - 1 >= 1 && p - 1 <= nb - 2) S[c] = S[c] + Dd{am_v[6 + c], am_d[6 + c]};
+    if (p >= 1 && p <= nb - 2) S[c] = S[c] + Dd{a0_v[3 + c], a0_d[3 + c]};
+    if (p + 1 >= 1 && p + 1 <= nb - 2) S[c] = S[c] + Dd{ap_v[c], ap_d[c]};
+  }
+}
+
+// One bead's reverse sub-step given its force (value f, derivative df along
+// the directions): with lvt = lv + hh lr, adds the sub-step's terms of
+// dL/dgamma and dL/dF_drive to accg, accf and that of u_p to lu, and gives
+// the adjoint before the sub-step (lrm, lvn) and the bead's next direction
+// dn = cf (lvn + hh lrm).  xp, dp: the bead's force position and direction.
+__device__ inline void bead_reverse(const MdParams& P, const Geom& g, double kT, const double* xp, const double* dp,
+                                    const Dd* S, const double* lr, const double* lv, const double* lJ,
+                                    const double* u, const double* vo, const double* xi, double* lu, double& accg,
+                                    double& accf, double* lrm, double* lvn, double* dn) {
+  double f[3] = {S[0].v, S[1].v, S[2].v}, df[3] = {S[0].d, S[1].d, S[2].d};
+  const double h = 2.0 * P.hh;
+  const double gam = P.gamma;
+  const double de = -h * P.e, domE = h * P.e;
+  const double dcf = (h * P.e) / (P.m * gam) - P.omE / (P.m * gam * gam);
+  const double dsig = P.sig > 0.0 ? ((kT / P.m) * (h * P.e * P.e)) / P.sig : 0.0;
+  const bool field = P.field_on && in_field(g, xp);
+  if (field) f[g.wall_axis] += P.f_drive;
+  for (int c = 0; c < 3; ++c) {
+    const double lvt = lv[c] + P.hh * lr[c];
+    accg += lvt * (vo[c] * de + (f[c] + gam * u[c]) * dcf + P.cf * u[c] + xi[c] * dsig);
+    accg += lJ[c] * (-P.m) * ((u[c] - vo[c]) * domE + xi[c] * dsig);
+    lu[c] = lu[c] + (P.cf * gam * lvt - P.m * P.omE * lJ[c]);
+    lrm[c] = lr[c] + df[c];
+    lvn[c] = P.e * lvt + P.m * P.omE * lJ[c] + P.hh * lrm[c];
+    dn[c] = P.cf * (lvn[c] + P.hh * lrm[c]);
+  }
+  if (field) accf += dp[g.wall_axis];
 }
 
 // The bead noise of every sub-step of the step being reversed, drawn in
@@ -289,8 +373,8 @@ __global__ void k_adj_lcheck(Dev d, AdjBufs a, const double* __restrict__ mdt, i
 //   ADJ_LANES in ascending j, then the wall sites numbered l modulo
 //   ADJ_LANES; a butterfly over the bead's lanes leaves the sum on every
 //   lane;
-//   wave 1: the bonds of each bead and the vertices of the angles centred at
-//   p0 - 1 .. p0 + AS_BPB, into LDS.
+//   wave 1: the angles centred at p0 - 1 .. p0 + AS_BPB and the two bonds of
+//   each bead, into LDS.
 // The bead's force is then the pair-and-wall sum plus the bond to p - 1, the
 // bond to p + 1 and the angle terms (centred at p - 1, p, p + 1), in that
 // order.
@@ -368,30 +452,18 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
   __syncthreads();
   Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
   if (!pairw) {
-    if (u < 3 * (AS_BPB + 2)) {
-      // vertex u mod 3 of the angle centred at p0 - 1 + u / 3 (row u / 3)
-      const int cen = p0 - 1 + u / 3;
-      if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, u % 3, av[u / 3], ad[u / 3]);
-    } else if (u < 3 * (AS_BPB + 2) + 2 * AS_BPB) {
+    if (u < AS_BPB + 2) {
+      // the angle centred at p0 - 1 + u (row u)
+      const int cen = p0 - 1 + u;
+      if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, av[u], ad[u]);
+    } else if (u >= 32 && u < 32 + 2 * AS_BPB) {
       // bond of bead bb to bb - 1 (side 0) or bb + 1 (side 1)
-      const int bb = (u - 3 * (AS_BPB + 2)) / 2, side = (u - 3 * (AS_BPB + 2)) % 2;
+      const int bb = (u - 32) / 2, side = (u - 32) % 2;
       const int q = p0 + bb, o = side ? q + 1 : q - 1;
-      if (q < nb && o >= 0 && o < nb) {
-        const int ql = bb + 2, ol = side ? ql + 1 : ql - 1;
-        Dd rp[3] = {Dd{pos[ql][0], dir[ql][0]}, Dd{pos[ql][1], dir[ql][1]}, Dd{pos[ql][2], dir[ql][2]}};
-        Dd rq[3] = {Dd{pos[ol][0], dir[ol][0]}, Dd{pos[ol][1], dir[ol][1]}, Dd{pos[ol][2], dir[ol][2]}};
-        bond_dd(P, rp, rq, S);
-      }
-      for (int c = 0; c < 3; ++c) { bv[bb][side][c] = S[c].v; bd[bb][side][c] = S[c].d; }
+      if (q < nb && o >= 0 && o < nb) bond_dual(P, pos, dir, bb + 2, side ? bb + 3 : bb + 1, bv[bb][side], bd[bb][side]);
     }
   } else {
     if (on) {
-      auto lj_with = [&](const double* rj, const double* dj) {
-        const double e0 = min_image(xp[0] - rj[0], g.nx);
-        const double e1 = min_image(xp[1] - rj[1], g.ny);
-        const double e2 = min_image(xp[2] - rj[2], g.nz);
-        lj_dd(P, Dd{e0, dp[0] - dj[0]}, Dd{e1, dp[1] - dj[1]}, Dd{e2, dp[2] - dj[2]}, S);
-      };
       if (lists) {
         // the entries' positions and directions loaded together
         double ej[ADJ_PER_LANE][3], dj[ADJ_PER_LANE][3];
@@ -402,63 +474,35 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
         }
 #pragma unroll
         for (int m = 0; m < ADJ_PER_LANE; ++m)
-          if (jm[m] >= 0) lj_with(ej[m], dj[m]);
+          if (jm[m] >= 0) lj_pair(P, g, xp, dp, ej[m], dj[m], S);
       } else {
         for (int j = lane; j < nb; j += ADJ_LANES)
           if (j != p) {
             const double rj[3] = {rms[6 * (size_t)j], rms[6 * (size_t)j + 1], rms[6 * (size_t)j + 2]};
             const double dj[3] = {dirin[3 * j], dirin[3 * j + 1], dirin[3 * j + 2]};
-            lj_with(rj, dj);
+            lj_pair(P, g, xp, dp, rj, dj, S);
           }
       }
       Dd rp[3] = {Dd{xp[0], dp[0]}, Dd{xp[1], dp[1]}, Dd{xp[2], dp[2]}};
       wall_dd(P, g, rp, S, lane, ADJ_LANES);
     }
-    // butterfly over the bead's lanes (contiguous and ADJ_LANES-aligned in
-    // the wave): a + b on one side of each exchange and b + a on the other
-    // round to the same value
-#pragma unroll
-    for (int off = ADJ_LANES / 2; off > 0; off >>= 1)
-      for (int c = 0; c < 3; ++c) {
-        S[c].v = S[c].v + __shfl_xor(S[c].v, off, 64);
-        S[c].d = S[c].d + __shfl_xor(S[c].d, off, 64);
-      }
+    lanes_sum(S);
   }
   __syncthreads();
   if (!lead) return;
   const int al = b + 1;   // row of the angle centred at p
+  add_bonded(S, p, nb, bv[b][0], bd[b][0], bv[b][1], bd[b][1], av[al - 1], ad[al - 1], av[al], ad[al], av[al + 1],
+             ad[al + 1]);
+  double lrm[3], lvn[3], dn[3];
+  bead_reverse(P, g, kT, xp, dp, S, olr, olv, olJ, ou, ovo, oxi, olu, og, of, lrm, lvn, dn);
   for (int c = 0; c < 3; ++c) {
-    if (p > 0) S[c] = S[c] + Dd{bv[b][0][c], bd[b][0][c]};
-    if (p < nb - 1) S[c] = S[c] + Dd{bv[b][1][c], bd[b][1][c]};
-    if (p - 1 >= 1 && p - 1 <= nb - 2) S[c] = S[c] + Dd{av[al - 1][6 + c], ad[al - 1][6 + c]};
-    if (p >= 1 && p <= nb - 2) S[c] = S[c] + Dd{av[al][3 + c], ad[al][3 + c]};
-    if (p + 1 >= 1 && p + 1 <= nb - 2) S[c] = S[c] + Dd{av[al + 1][c], ad[al + 1][c]};
+    a.lup[3 * p + c] = olu[c];
+    lrout[3 * p + c] = lrm[c];
+    lvout[3 * p + c] = lvn[c];
+    dirout[3 * p + c] = dn[c];
   }
-  double f[3] = {S[0].v, S[1].v, S[2].v}, df[3] = {S[0].d, S[1].d, S[2].d};
-  const double h = 2.0 * P.hh;
-  const double gam = P.gamma;
-  const double de = -h * P.e, domE = h * P.e;
-  const double dcf = (h * P.e) / (P.m * gam) - P.omE / (P.m * gam * gam);
-  const double dsig = P.sig > 0.0 ? ((kT / P.m) * (h * P.e * P.e)) / P.sig : 0.0;
-  const bool field = P.field_on && in_field(g, xp);
-  if (field) f[g.wall_axis] += P.f_drive;
-  double acc_g = og, acc_f = of;
-  for (int c = 0; c < 3; ++c) {
-    const double lr = olr[c], lv = olv[c], lJ = olJ[c], u = ou[c];
-    const double lvt = lv + P.hh * lr;
-    const double vo = ovo[c];
-    acc_g += lvt * (vo * de + (f[c] + gam * u) * dcf + P.cf * u + oxi[c] * dsig);
-    acc_g += lJ * (-P.m) * ((u - vo) * domE + oxi[c] * dsig);
-    a.lup[3 * p + c] = olu[c] + (P.cf * gam * lvt - P.m * P.omE * lJ);
-    const double lrm = lr + df[c];
-    const double lvn = P.e * lvt + P.m * P.omE * lJ + P.hh * lrm;
-    lrout[3 * p + c] = lrm;
-    lvout[3 * p + c] = lvn;
-    dirout[3 * p + c] = P.cf * (lvn + P.hh * lrm);
-  }
-  if (field) acc_f += dp[g.wall_axis];
-  a.gacc[3 * p] = acc_g;
-  a.gacc[3 * p + 1] = acc_f;
+  a.gacc[3 * p] = og;
+  a.gacc[3 * p + 1] = of;
 }
 
 // After the reversed cycle: lr, lv from the pair the last launch wrote, and
