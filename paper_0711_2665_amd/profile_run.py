@@ -1,7 +1,7 @@
 """Workload driver for rocprofv3 counter runs of the LB sweep.
 
     python -m paper_0711_2665_amd.profile_run --workload c3 --precision fp32dev --steps 5 \
-        --copy-mib 1024 --meta gpurun_out/lb_sweep_meta.json
+        --copy-mib 1024 --meta /tmp/lb_sweep_meta.json
 
 Builds the workload's lattice without beads (with --fluid-kT, a fluctuating
 fluid: the sweep variant that draws the fluid noise) and, for every sweep
