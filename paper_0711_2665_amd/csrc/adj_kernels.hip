@@ -85,31 +85,36 @@ __device__ inline void angle_dd3(const MdParams& P, const Dd* ra, const Dd* rb, 
   }
 }
 
+// The dual LJ force of one pair (separation d0, d1, d2), if within r_c.
+__device__ inline bool lj_term(const MdParams& P, Dd d0, Dd d1, Dd d2, Dd t[3]) {
+  Dd r2 = d0 * d0 + d1 * d1 + d2 * d2;
+  if (!(r2.v < P.rc2)) return false;
+  Dd sr2 = mkd(P.sig2) / r2;
+  Dd sr6 = sr2 * sr2 * sr2;
+  Dd sr12 = sr6 * sr6;
+  Dd coef = P.eps24 * (2.0 * sr12 - sr6) / r2;
+  t[0] = coef * d0; t[1] = coef * d1; t[2] = coef * d2;
+  return true;
+}
 __device__ inline void lj_dd(const MdParams& P, Dd d0, Dd d1, Dd d2, Dd F[3]) {
-  const Dd r2 = d0 * d0 + d1 * d1 + d2 * d2;
-  if (!(r2.v < P.rc2)) return;
-  // one division: with q = 1 / r2, d(sig2 q) = -(sig2 q) q dr2 and
-  // d(x q) = (dx - (x q) dr2) q
-  const double q = 1.0 / r2.v;
-  const double s2 = P.sig2 * q;
-  const Dd sr2{s2, -s2 * q * r2.d};
-  const Dd sr6 = sr2 * sr2 * sr2;
-  const Dd sr12 = sr6 * sr6;
-  const Dd num = P.eps24 * (2.0 * sr12 - sr6);
-  const double cv = num.v * q;
-  const Dd coef{cv, (num.d - cv * r2.d) * q};
-  F[0] = F[0] + coef * d0; F[1] = F[1] + coef * d1; F[2] = F[2] + coef * d2;
+  Dd t[3];
+  if (!lj_term(P, d0, d1, d2, t)) return;
+  F[0] = F[0] + t[0]; F[1] = F[1] + t[1]; F[2] = F[2] + t[2];
 }
 
 // Wall sites within r_c of the bead (r_c <= 3): the sites of the wall plane
 // at offsets P.wlo..P.whi (1 - ceil(r_c)..ceil(r_c), within -2..3) around the
 // base node, minus the pore block -- the rows outside hold no site within
 // r_c, so the hit sites and their order are those of the full 6 x 6 window;
-// the derivative of the wrapped position is that of r.
-// Sites are numbered row by row over the window; a caller with several lanes
-// takes those whose number is `part` modulo `nparts`.
-__device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, Dd F[3], int part = 0,
-                               int nparts = 1) {
+// the derivative of the wrapped position is that of r.  Sites are numbered
+// row by row over the window; the caller's lane `part` of `nparts` stores
+// the dual force of each of its sites (number part modulo nparts) within
+// r_c in wv/wd and marks it in whit (0 for the others).
+constexpr int ADJ_WIN = 36;   // sites in the largest window (a multiple of 4)
+__device__ inline void wall_terms(const MdParams& P, const Geom& g, const Dd* rp, int part, int nparts,
+                                  double (*wv)[3], double (*wd)[3], int8_t* whit) {
+  const int nw = P.whi - P.wlo + 1;
+  for (int num = part; num < nw * nw; num += nparts) whit[num] = 0;
   if (g.wall_axis < 0) return;
   const double w[3] = {wrapc(rp[0].v, g.nx), wrapc(rp[1].v, g.ny), wrapc(rp[2].v, g.nz)};
   const int b[3] = {(int)floor(w[0]), (int)floor(w[1]), (int)floor(w[2])};
@@ -121,7 +126,6 @@ __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, D
   if (off < P.wlo || off > P.whi) return;
   int site[3];
   site[a] = b[a] + off;
-  const int nw = P.whi - P.wlo + 1;
   for (int num = part; num < nw * nw; num += nparts) {
     const int o1 = P.wlo + num / nw, o0 = P.wlo + num % nw;
     const int u1 = b[t1] + o1;
@@ -135,7 +139,10 @@ __device__ inline void wall_dd(const MdParams& P, const Geom& g, const Dd* rp, D
     site[t1] = u1;
     const double e0 = w[0] - (double)site[0], e1 = w[1] - (double)site[1], e2 = w[2] - (double)site[2];
     if (!(e0 * e0 + e1 * e1 + e2 * e2 < P.rc2)) continue;
-    lj_dd(P, Dd{e0, rp[0].d}, Dd{e1, rp[1].d}, Dd{e2, rp[2].d}, F);
+    Dd t3[3];
+    if (!lj_term(P, Dd{e0, rp[0].d}, Dd{e1, rp[1].d}, Dd{e2, rp[2].d}, t3)) continue;
+    for (int c = 0; c < 3; ++c) { wv[num][c] = t3[c].v; wd[num][c] = t3[c].d; }
+    whit[num] = 1;
   }
 }
 
@@ -202,7 +209,7 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 
 // ---------------------------------------------------------------------------
 // MD sub-cycle transpose, one launch per sub-step (in reverse order), four
-// beads per two-wave workgroup.  The force positions r_mid and the
+// beads per three-wave workgroup.  The force positions r_mid and the
 // velocities at the start of every sub-step come from the tape the forward
 // sub-cycle wrote (while the segment was recomputed, or in the forward pass
 // of a one-segment horizon).  On
@@ -222,12 +229,13 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 // ---------------------------------------------------------------------------
 constexpr int ADJ_LANES = 16;                // lanes per bead in the pair wave (a power of two)
 constexpr int AS_BPB = 64 / ADJ_LANES;       // beads per workgroup
-constexpr int AS_WG = 128;                   // wave 0: pair and wall terms; wave 1: bonds and angles
+constexpr int AS_WG = 192;                   // wave 0: pair terms; wave 1: bonds and angles; wave 2: wall sites
 constexpr int AS_SPAN = AS_BPB + 4;          // beads p0 - 2 .. p0 + AS_BPB + 1 in LDS
 constexpr int ADJ_PER_LANE = MAXNBR / ADJ_LANES;   // list entries per lane
 constexpr int AS_FIN = 1024;                 // threads of k_adj_md_fin
 static_assert((ADJ_LANES & (ADJ_LANES - 1)) == 0 && 64 % ADJ_LANES == 0, "lanes per bead: a power of two");
-static_assert(MAXNBR % ADJ_LANES == 0, "whole list entries per lane");
+static_assert(MAXNBR % ADJ_LANES == 0 && MAXNBR % 4 == 0 && MAXNBR <= 64, "whole list entries per lane, one mask");
+static_assert(ADJ_WIN % 4 == 0 && ADJ_WIN <= 64, "wall sites: whole words, one mask");
 static_assert(AS_BPB + 2 <= 32 && 32 + 2 * AS_BPB <= 64, "one thread of wave 1 per angle and per bond");
 
 // Bending forces of the angle centred at index qi of pos/dir (value and
@@ -269,33 +277,6 @@ __device__ inline void lj_pair(const MdParams& P, const Geom& g, const double* x
   const double e1 = min_image(xp[1] - rj[1], g.ny);
   const double e2 = min_image(xp[2] - rj[2], g.nz);
   lj_dd(P, Dd{e0, dp[0] - dj[0]}, Dd{e1, dp[1] - dj[1]}, Dd{e2, dp[2] - dj[2]}, S);
-}
-
-// Butterfly over the ADJ_LANES lanes of one bead (contiguous and aligned in
-// the wave, all active): a + b on one side of each exchange and b + a on
-// the other round to the same value, so every lane ends with the same sum.
-__device__ inline void lanes_sum(Dd S[3]) {
-#pragma unroll
-  for (int off = ADJ_LANES / 2; off > 0; off >>= 1)
-    for (int c = 0; c < 3; ++c) {
-      S[c].v = S[c].v + __shfl_xor(S[c].v, off, 64);
-      S[c].d = S[c].d + __shfl_xor(S[c].d, off, 64);
-    }
-}
-
-// The conservative force on bead p from its parts, in a fixed order: the
-// pair-and-wall sum, the bond to p - 1, the bond to p + 1, the angle terms
-// centred at p - 1, p, p + 1 (rows am, a0, ap of av/ad).
-__device__ inline void add_bonded(Dd S[3], int p, int nb, const double* bm_v, const double* bm_d,
-                                  const double* bp_v, const double* bp_d, const double* am_v, const double* am_d,
-                                  const double* a0_v, const double* a0_d, const double* ap_v, const double* ap_d) {
-  for (int c = 0; c < 3; ++c) {
-    if (p > 0) S[c] = S[c] + Dd{bm_v[c], bm_d[c]};
-    if (p < nb - 1) S[c] = S[c] + Dd{bp_v[c], bp_d[c]};
-    if (p - 1 >= 1 && p - 1 <= nb - 2) S[c] = S[c] + Dd{am_v[6 + c], am_d[6 + c]};
-    if (p >= 1 && p <= nb - 2) S[c] = S[c] + Dd{a0_v[3 + c], a0_d[3 + c]};
-    if (p + 1 >= 1 && p + 1 <= nb - 2) S[c] = S[c] + Dd{ap_v[c], ap_d[c]};
-  }
 }
 
 // One bead's reverse sub-step given its force (value f, derivative df along
@@ -363,21 +344,45 @@ __global__ void k_adj_lcheck(Dev d, AdjBufs a, const double* __restrict__ mdt, i
   if (!(d2 <= d.reps[0].mp.halfskin2)) atomicOr(a.lok, 1);
 }
 
+// S += the terms (v, d)[k] for the set bits k of mask, in ascending k; the
+// loads of four terms are issued before their additions.
+__device__ inline void add_masked(Dd S[3], uint64_t mask, const double (*v)[3], const double (*d)[3]) {
+  while (mask) {
+    int k[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      k[i] = mask ? __builtin_ctzll(mask) : -1;
+      mask &= mask - 1;
+    }
+    double tv[4][3], td[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kk = k[i] >= 0 ? k[i] : k[0];
+      for (int c = 0; c < 3; ++c) { tv[i][c] = v[kk][c]; td[i][c] = d[kk][c]; }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (k[i] >= 0)
+        for (int c = 0; c < 3; ++c) S[c] = S[c] + Dd{tv[i][c], td[i][c]};
+  }
+}
+
 // Reverse sub-step s, the k-th launch of the reversed cycle (k = n_sub - 1 - s),
 // for beads p0 .. p0 + AS_BPB - 1.  The conservative force on bead p (value
-// and derivative along the directions dir) is split over two waves that run
-// side by side:
-//   wave 0, ADJ_LANES lanes per bead: lane l adds the dual LJ terms of the
-//   list entries l, l + ADJ_LANES, ... that lie within r_c (in list order,
-//   which is ascending j), or without lists those of the beads j = l mod
-//   ADJ_LANES in ascending j, then the wall sites numbered l modulo
-//   ADJ_LANES; a butterfly over the bead's lanes leaves the sum on every
-//   lane;
+// and derivative along the directions dir) is evaluated by three waves side
+// by side:
+//   wave 0, ADJ_LANES lanes per bead: lane l takes the dual LJ term of list
+//   entries l, l + ADJ_LANES, ... (those within r_c), stored by list
+//   position;
 //   wave 1: the angles centred at p0 - 1 .. p0 + AS_BPB and the two bonds of
-//   each bead, into LDS.
-// The bead's force is then the pair-and-wall sum plus the bond to p - 1, the
-// bond to p + 1 and the angle terms (centred at p - 1, p, p + 1), in that
-// order.
+//   each bead, into LDS;
+//   wave 2, ADJ_LANES lanes per bead: the wall sites numbered lane modulo
+//   ADJ_LANES, stored by site.
+// The terms are then added in one fixed order: lane l < 4 of the bead adds
+// those of the partners j = l mod 4 in ascending j, lane 0 then the bonds to
+// p - 1 and p + 1, the angle terms centred at p - 1, p, p + 1 and the wall
+// sites in window order, and the force is (S0 + S1) + (S2 + S3).  Without
+// lists lane l < 4 takes its partners from all beads.
 // Every address of the first loads comes from the arguments (nb included),
 // so they do not wait for the parameter block.
 __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const double* __restrict__ mdt,
@@ -386,12 +391,17 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
   __shared__ double pos[AS_SPAN][3], dir[AS_SPAN][3];
   __shared__ double av[AS_BPB + 2][9], ad[AS_BPB + 2][9];
   __shared__ double bv[AS_BPB][2][3], bd[AS_BPB][2][3];
+  __shared__ double tv[AS_BPB][MAXNBR][3], td[AS_BPB][MAXNBR][3];   // pair terms by list position
+  __shared__ double wv[AS_BPB][ADJ_WIN][3], wd[AS_BPB][ADJ_WIN][3]; // wall-site terms by site number
+  __shared__ __align__(16) int8_t tcl[AS_BPB][MAXNBR];             // j mod 4 of an entry with a term, else -1
+  __shared__ __align__(16) int8_t whit[AS_BPB][ADJ_WIN];
   const Rep& R = d.reps[0];
   const MdParams P = R.mp;
   const Geom g = R.g;
   const int p0 = blockIdx.x * AS_BPB;
   const int t = threadIdx.x;
-  const bool pairw = t < 64;
+  const int wave = t / 64;
+  const bool pairw = wave == 0;
   const int u = t & 63, b = u / ADJ_LANES, lane = u % ADJ_LANES, p = p0 + b;
   const bool on = p < nb, lead = pairw && on && lane == 0;
   const bool first = k == 0;
@@ -441,7 +451,7 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
       if (lists && lane + ADJ_LANES * m < cnt) jm[m] = e[m];
   }
   // wave 1: positions and directions of beads p0 - 2 .. p0 + AS_BPB + 1
-  if (!pairw && u < AS_SPAN) {
+  if (wave == 1 && u < AS_SPAN) {
     const int q = p0 - 2 + u;
     if (q >= 0 && q < nb)
       for (int c = 0; c < 3; ++c) {
@@ -451,7 +461,7 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
   }
   __syncthreads();
   Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  if (!pairw) {
+  if (wave == 1) {
     if (u < AS_BPB + 2) {
       // the angle centred at p0 - 1 + u (row u)
       const int cen = p0 - 1 + u;
@@ -462,37 +472,112 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
       const int q = p0 + bb, o = side ? q + 1 : q - 1;
       if (q < nb && o >= 0 && o < nb) bond_dual(P, pos, dir, bb + 2, side ? bb + 3 : bb + 1, bv[bb][side], bd[bb][side]);
     }
-  } else {
+  } else if (wave == 2) {
+    // the wall sites of bead b, numbered lane modulo ADJ_LANES
     if (on) {
-      if (lists) {
-        // the entries' positions and directions loaded together
-        double ej[ADJ_PER_LANE][3], dj[ADJ_PER_LANE][3];
-#pragma unroll
-        for (int m = 0; m < ADJ_PER_LANE; ++m) {
-          const int j = jm[m] >= 0 ? jm[m] : p;
-          for (int c = 0; c < 3; ++c) { ej[m][c] = rms[6 * (size_t)j + c]; dj[m][c] = dirin[3 * j + c]; }
-        }
-#pragma unroll
-        for (int m = 0; m < ADJ_PER_LANE; ++m)
-          if (jm[m] >= 0) lj_pair(P, g, xp, dp, ej[m], dj[m], S);
-      } else {
-        for (int j = lane; j < nb; j += ADJ_LANES)
-          if (j != p) {
-            const double rj[3] = {rms[6 * (size_t)j], rms[6 * (size_t)j + 1], rms[6 * (size_t)j + 2]};
-            const double dj[3] = {dirin[3 * j], dirin[3 * j + 1], dirin[3 * j + 2]};
-            lj_pair(P, g, xp, dp, rj, dj, S);
-          }
-      }
-      Dd rp[3] = {Dd{xp[0], dp[0]}, Dd{xp[1], dp[1]}, Dd{xp[2], dp[2]}};
-      wall_dd(P, g, rp, S, lane, ADJ_LANES);
+      const Dd rp[3] = {Dd{pos[b + 2][0], dir[b + 2][0]}, Dd{pos[b + 2][1], dir[b + 2][1]},
+                        Dd{pos[b + 2][2], dir[b + 2][2]}};
+      wall_terms(P, g, rp, lane, ADJ_LANES, wv[b], wd[b], whit[b]);
     }
-    lanes_sum(S);
+  } else if (on && lists) {
+    {
+      // the entries' positions and directions loaded together, then the
+      // dual LJ term of each entry within r_c, stored by list position
+      double ej[ADJ_PER_LANE][3], dj[ADJ_PER_LANE][3];
+#pragma unroll
+      for (int m = 0; m < ADJ_PER_LANE; ++m) {
+        const int j = jm[m] >= 0 ? jm[m] : p;
+        for (int c = 0; c < 3; ++c) { ej[m][c] = rms[6 * (size_t)j + c]; dj[m][c] = dirin[3 * j + c]; }
+      }
+#pragma unroll
+      for (int m = 0; m < ADJ_PER_LANE; ++m) {
+        const int kk = lane + ADJ_LANES * m;
+        bool hit = false;
+        if (jm[m] >= 0) {
+          const double e0 = min_image(xp[0] - ej[m][0], g.nx);
+          const double e1 = min_image(xp[1] - ej[m][1], g.ny);
+          const double e2 = min_image(xp[2] - ej[m][2], g.nz);
+          Dd t3[3];
+          hit = lj_term(P, Dd{e0, dp[0] - dj[m][0]}, Dd{e1, dp[1] - dj[m][1]}, Dd{e2, dp[2] - dj[m][2]}, t3);
+          if (hit)
+            for (int c = 0; c < 3; ++c) { tv[b][kk][c] = t3[c].v; td[b][kk][c] = t3[c].d; }
+        }
+        tcl[b][kk] = hit ? (int8_t)(jm[m] & 3) : (int8_t)-1;
+      }
+    }
+  }
+  // the pair wave's terms are read back within the wave: a wave-level
+  // barrier orders its LDS stores before the loads below
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // Lane l < 4 of the bead adds the pair terms of its partners j = l mod 4
+  // in ascending j (list order; without lists it takes them from all beads
+  // itself) while the bonded wave works; after the barrier lane 0 adds the
+  // bond to p - 1, the bond to p + 1, the angle terms centred at p - 1, p,
+  // p + 1 and the wall sites in window order; the four sums are combined as
+  // (S0 + S1) + (S2 + S3).
+  if (pairw && on && lane < 4) {
+    if (lists) {
+      // the class's entries as a mask over the list, read four at a time
+      uint64_t mk = 0;
+#pragma unroll
+      for (int q = 0; q < MAXNBR / 4; ++q) {
+        const uint32_t w4 = reinterpret_cast<const uint32_t*>(tcl[b])[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if ((int8_t)(w4 >> (8 * e)) == lane) mk |= 1ull << (4 * q + e);
+      }
+      add_masked(S, mk, tv[b], td[b]);
+    } else {
+      for (int j = lane; j < nb; j += 4)
+        if (j != p) {
+          const double rj[3] = {rms[6 * (size_t)j], rms[6 * (size_t)j + 1], rms[6 * (size_t)j + 2]};
+          const double dj[3] = {dirin[3 * j], dirin[3 * j + 1], dirin[3 * j + 2]};
+          lj_pair(P, g, xp, dp, rj, dj, S);
+        }
+    }
   }
   __syncthreads();
+  if (pairw && on && lane < 4) {
+    if (lane == 0) {
+      const int al = b + 1;   // row of the angle centred at p
+      for (int c = 0; c < 3; ++c) {
+        if (p > 0) S[c] = S[c] + Dd{bv[b][0][c], bd[b][0][c]};
+        if (p < nb - 1) S[c] = S[c] + Dd{bv[b][1][c], bd[b][1][c]};
+      }
+      for (int c = 0; c < 3; ++c) {
+        if (p - 1 >= 1 && p - 1 <= nb - 2) S[c] = S[c] + Dd{av[al - 1][6 + c], ad[al - 1][6 + c]};
+        if (p >= 1 && p <= nb - 2) S[c] = S[c] + Dd{av[al][3 + c], ad[al][3 + c]};
+        if (p + 1 >= 1 && p + 1 <= nb - 2) S[c] = S[c] + Dd{av[al + 1][c], ad[al + 1][c]};
+      }
+      const int nw = P.whi - P.wlo + 1;
+      uint64_t wm = 0;
+#pragma unroll
+      for (int q = 0; q < ADJ_WIN / 4; ++q) {
+        const uint32_t w4 = reinterpret_cast<const uint32_t*>(whit[b])[q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (4 * q + e < nw * nw && ((w4 >> (8 * e)) & 0xffu) != 0u) wm |= 1ull << (4 * q + e);
+      }
+      add_masked(S, wm, wv[b], wd[b]);
+    }
+  }
+  // every lane of the wave takes part in the exchange; the bead's lanes 0-3
+  // are lanes base .. base + 3 of the wave
+  const int base = u & ~(ADJ_LANES - 1);
+  double F[3], dF[3];
+  for (int c = 0; c < 3; ++c) {
+    double v4[4], d4[4];
+    for (int l = 0; l < 4; ++l) {
+      v4[l] = __shfl(S[c].v, base + l, 64);
+      d4[l] = __shfl(S[c].d, base + l, 64);
+    }
+    F[c] = (v4[0] + v4[1]) + (v4[2] + v4[3]);
+    dF[c] = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+  }
   if (!lead) return;
-  const int al = b + 1;   // row of the angle centred at p
-  add_bonded(S, p, nb, bv[b][0], bd[b][0], bv[b][1], bd[b][1], av[al - 1], ad[al - 1], av[al], ad[al], av[al + 1],
-             ad[al + 1]);
+  for (int c = 0; c < 3; ++c) S[c] = Dd{F[c], dF[c]};
   double lrm[3], lvn[3], dn[3];
   bead_reverse(P, g, kT, xp, dp, S, olr, olv, olJ, ou, ovo, oxi, olu, og, of, lrm, lvn, dn);
   for (int c = 0; c < 3; ++c) {
