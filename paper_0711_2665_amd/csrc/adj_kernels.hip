@@ -59,10 +59,12 @@ __device__ inline void bond_dd(const MdParams& P, const Dd* rp, const Dd* rq, Dd
   F[0] = F[0] + coef * d0; F[1] = F[1] + coef * d1; F[2] = F[2] + coef * d2;
 }
 
-// The three vertex forces of the bending term at once (F0 on the bead
-// before the centre, F1 on the centre, F2 on the bead after it).
-__device__ inline void angle_dd3(const MdParams& P, const Dd* ra, const Dd* rb, const Dd* rc, Dd F0[3], Dd F1[3],
-                                 Dd F2[3]) {
+// Component a of the three vertex forces of the bending term (out[0] on
+// the bead before the centre, out[1] on the centre, out[2] on the bead after
+// it), each 0 + its term; 0 for a straight or folded angle.
+__device__ inline void angle_dd_comp(const MdParams& P, const Dd* ra, const Dd* rb, const Dd* rc, int a,
+                                     Dd out[3]) {
+  out[0] = mkd(0.0); out[1] = mkd(0.0); out[2] = mkd(0.0);
   Dd b1[3] = {rb[0] - ra[0], rb[1] - ra[1], rb[2] - ra[2]};
   Dd b2[3] = {rc[0] - rb[0], rc[1] - rb[1], rc[2] - rb[2]};
   Dd n[3] = {b1[1] * b2[2] - b1[2] * b2[1], b1[2] * b2[0] - b1[0] * b2[2], b1[0] * b2[1] - b1[1] * b2[0]};
@@ -72,17 +74,20 @@ __device__ inline void angle_dd3(const MdParams& P, const Dd* ra, const Dd* rb, 
   Dd phi = datan2(s, c);
   Dd den = s * s + c * c;
   Dd kp = P.kappa * phi;
-  for (int a = 0; a < 3; ++a) {
-    // component a of b2 x n and of n x b1
-    const int a1 = a == 2 ? 0 : a + 1, a2 = a == 0 ? 2 : a - 1;
-    const Dd g1 = b2[a1] * n[a2] - b2[a2] * n[a1];
-    const Dd g2 = n[a1] * b1[a2] - n[a2] * b1[a1];
-    Dd d1 = (c * g1 / s - s * b2[a]) / den;
-    Dd d2 = (c * g2 / s - s * b1[a]) / den;
-    F0[a] = F0[a] + kp * d1;
-    F1[a] = F1[a] + -(kp * (d1 - d2));
-    F2[a] = F2[a] + -(kp * d2);
+  // component a of b2 x n and of n x b1 (constant indices in each branch)
+  Dd g1, g2, b1a, b2a;
+  if (a == 0) {
+    g1 = b2[1] * n[2] - b2[2] * n[1]; g2 = n[1] * b1[2] - n[2] * b1[1]; b1a = b1[0]; b2a = b2[0];
+  } else if (a == 1) {
+    g1 = b2[2] * n[0] - b2[0] * n[2]; g2 = n[2] * b1[0] - n[0] * b1[2]; b1a = b1[1]; b2a = b2[1];
+  } else {
+    g1 = b2[0] * n[1] - b2[1] * n[0]; g2 = n[0] * b1[1] - n[1] * b1[0]; b1a = b1[2]; b2a = b2[2];
   }
+  Dd d1 = (c * g1 / s - s * b2a) / den;
+  Dd d2 = (c * g2 / s - s * b1a) / den;
+  out[0] = out[0] + kp * d1;
+  out[1] = out[1] + -(kp * (d1 - d2));
+  out[2] = out[2] + -(kp * d2);
 }
 
 // The dual LJ force of one pair (separation d0, d1, d2), if within r_c.
@@ -230,43 +235,16 @@ __global__ void k_adj_spread_t(const T* __restrict__ lamB, Dev d, AdjBufs a, con
 constexpr int ADJ_LANES = 16;                // lanes per bead in the pair wave (a power of two)
 constexpr int AS_BPB = 64 / ADJ_LANES;       // beads per workgroup
 constexpr int AS_WG = 192;                   // wave 0: pair terms; wave 1: bonds and angles; wave 2: wall sites
-constexpr int AS_SPAN = AS_BPB + 4;          // beads p0 - 2 .. p0 + AS_BPB + 1 in LDS
 constexpr int ADJ_PER_LANE = MAXNBR / ADJ_LANES;   // list entries per lane
 constexpr int AS_FIN = 1024;                 // threads of k_adj_md_fin
 static_assert((ADJ_LANES & (ADJ_LANES - 1)) == 0 && 64 % ADJ_LANES == 0, "lanes per bead: a power of two");
 static_assert(MAXNBR % ADJ_LANES == 0 && MAXNBR % 4 == 0 && MAXNBR <= 64, "whole list entries per lane, one mask");
 static_assert(ADJ_WIN % 4 == 0 && ADJ_WIN <= 64, "wall sites: whole words, one mask");
-static_assert(AS_BPB + 2 <= 32 && 32 + 2 * AS_BPB <= 64, "one thread of wave 1 per angle and per bond");
+static_assert(3 * (AS_BPB + 2) <= 32 && 32 + 2 * AS_BPB <= 64, "one thread of wave 1 per angle component and per bond");
 
-// Bending forces of the angle centred at index qi of pos/dir (value and
-// derivative) into one LDS row: [0..2] force on the bead before the centre,
-// [3..5] on the centre, [6..8] on the bead after it.
-__device__ inline void angle_dual(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int qi,
-                                  double* av, double* ad) {
-  Dd ra[3], rb[3], rc[3];
-  for (int a = 0; a < 3; ++a) {
-    ra[a] = Dd{pos[qi - 1][a], dir[qi - 1][a]};
-    rb[a] = Dd{pos[qi][a], dir[qi][a]};
-    rc[a] = Dd{pos[qi + 1][a], dir[qi + 1][a]};
-  }
-  Dd F0[3] = {mkd(0.0), mkd(0.0), mkd(0.0)}, F1[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  Dd F2[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  angle_dd3(P, ra, rb, rc, F0, F1, F2);
-  for (int a = 0; a < 3; ++a) {
-    av[a] = F0[a].v; ad[a] = F0[a].d;
-    av[3 + a] = F1[a].v; ad[3 + a] = F1[a].d;
-    av[6 + a] = F2[a].v; ad[6 + a] = F2[a].d;
-  }
-}
-
-// Bond force on the bead at index ql of pos/dir from the one at ol.
-__device__ inline void bond_dual(const MdParams& P, const double (*pos)[3], const double (*dir)[3], int ql, int ol,
-                                 double* bv, double* bd) {
-  Dd rp[3] = {Dd{pos[ql][0], dir[ql][0]}, Dd{pos[ql][1], dir[ql][1]}, Dd{pos[ql][2], dir[ql][2]}};
-  Dd rq[3] = {Dd{pos[ol][0], dir[ol][0]}, Dd{pos[ol][1], dir[ol][1]}, Dd{pos[ol][2], dir[ol][2]}};
-  Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
-  bond_dd(P, rp, rq, S);
-  for (int c = 0; c < 3; ++c) { bv[c] = S[c].v; bd[c] = S[c].d; }
+// Bead q's force position (from the tape rows rms) and direction as duals.
+__device__ inline void bead_dual(const double* __restrict__ rms, const double* __restrict__ dirin, int q, Dd r[3]) {
+  for (int c = 0; c < 3; ++c) r[c] = Dd{rms[6 * (size_t)q + c], dirin[3 * q + c]};
 }
 
 // Dual LJ term of the pair (bead at xp with direction dp, partner at rj
@@ -374,8 +352,8 @@ __device__ inline void add_masked(Dd S[3], uint64_t mask, const double (*v)[3], 
 //   wave 0, ADJ_LANES lanes per bead: lane l takes the dual LJ term of list
 //   entries l, l + ADJ_LANES, ... (those within r_c), stored by list
 //   position;
-//   wave 1: the angles centred at p0 - 1 .. p0 + AS_BPB and the two bonds of
-//   each bead, into LDS;
+//   wave 1: each component of the angles centred at p0 - 1 .. p0 + AS_BPB
+//   (one lane each) and the two bonds of each bead, into LDS;
 //   wave 2, ADJ_LANES lanes per bead: the wall sites numbered lane modulo
 //   ADJ_LANES, stored by site.
 // The terms are then added in one fixed order: lane l < 4 of the bead adds
@@ -388,7 +366,6 @@ __device__ inline void add_masked(Dd S[3], uint64_t mask, const double (*v)[3], 
 __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const double* __restrict__ mdt,
                                                    const double* __restrict__ upt, int nb, int s, int k,
                                                    double kT) {
-  __shared__ double pos[AS_SPAN][3], dir[AS_SPAN][3];
   __shared__ double av[AS_BPB + 2][9], ad[AS_BPB + 2][9];
   __shared__ double bv[AS_BPB][2][3], bd[AS_BPB][2][3];
   __shared__ double tv[AS_BPB][MAXNBR][3], td[AS_BPB][MAXNBR][3];   // pair terms by list position
@@ -450,33 +427,38 @@ __global__ __launch_bounds__(AS_WG) void k_adj_sub(Dev d, AdjBufs a, const doubl
     for (int m = 0; m < ADJ_PER_LANE; ++m)
       if (lists && lane + ADJ_LANES * m < cnt) jm[m] = e[m];
   }
-  // wave 1: positions and directions of beads p0 - 2 .. p0 + AS_BPB + 1
-  if (wave == 1 && u < AS_SPAN) {
-    const int q = p0 - 2 + u;
-    if (q >= 0 && q < nb)
-      for (int c = 0; c < 3; ++c) {
-        pos[u][c] = rms[6 * (size_t)q + c];
-        dir[u][c] = dirin[3 * q + c];
-      }
-  }
-  __syncthreads();
   Dd S[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
   if (wave == 1) {
-    if (u < AS_BPB + 2) {
-      // the angle centred at p0 - 1 + u (row u)
-      const int cen = p0 - 1 + u;
-      if (cen >= 1 && cen <= nb - 2) angle_dual(P, pos, dir, cen - p0 + 2, av[u], ad[u]);
+    if (u < 3 * (AS_BPB + 2)) {
+      // component u mod 3 of the angle centred at p0 - 1 + u / 3 (row u / 3),
+      // from the three beads' positions and directions loaded here
+      const int row = u / 3, cmp = u % 3, cen = p0 - 1 + row;
+      if (cen >= 1 && cen <= nb - 2) {
+        Dd ra[3], rb[3], rc[3], o3[3];
+        bead_dual(rms, dirin, cen - 1, ra);
+        bead_dual(rms, dirin, cen, rb);
+        bead_dual(rms, dirin, cen + 1, rc);
+        angle_dd_comp(P, ra, rb, rc, cmp, o3);
+        for (int w = 0; w < 3; ++w) { av[row][3 * w + cmp] = o3[w].v; ad[row][3 * w + cmp] = o3[w].d; }
+      }
     } else if (u >= 32 && u < 32 + 2 * AS_BPB) {
       // bond of bead bb to bb - 1 (side 0) or bb + 1 (side 1)
       const int bb = (u - 32) / 2, side = (u - 32) % 2;
       const int q = p0 + bb, o = side ? q + 1 : q - 1;
-      if (q < nb && o >= 0 && o < nb) bond_dual(P, pos, dir, bb + 2, side ? bb + 3 : bb + 1, bv[bb][side], bd[bb][side]);
+      if (q < nb && o >= 0 && o < nb) {
+        Dd rp[3], rq[3];
+        bead_dual(rms, dirin, q, rp);
+        bead_dual(rms, dirin, o, rq);
+        Dd T[3] = {mkd(0.0), mkd(0.0), mkd(0.0)};
+        bond_dd(P, rp, rq, T);
+        for (int c = 0; c < 3; ++c) { bv[bb][side][c] = T[c].v; bd[bb][side][c] = T[c].d; }
+      }
     }
   } else if (wave == 2) {
     // the wall sites of bead b, numbered lane modulo ADJ_LANES
     if (on) {
-      const Dd rp[3] = {Dd{pos[b + 2][0], dir[b + 2][0]}, Dd{pos[b + 2][1], dir[b + 2][1]},
-                        Dd{pos[b + 2][2], dir[b + 2][2]}};
+      Dd rp[3];
+      bead_dual(rms, dirin, p, rp);
       wall_terms(P, g, rp, lane, ADJ_LANES, wv[b], wd[b], whit[b]);
     }
   } else if (on && lists) {
