@@ -699,6 +699,8 @@ int build_graph(lb_ctx* c) {
 struct AdjLayout {
   size_t ckpt, tape_pops, tape_beads, lamA, lamB, lamu, lbead, mdtape, xi, par, total;
   size_t pops_slot, bead_arr, md_arr;
+  size_t upj_arr;      // u_p and J of every slot, one block (they lie together in the bead buffer)
+  size_t tape_entry;   // one step's bead tape: r, then u_p and J
   int nseg;
 };
 
@@ -709,10 +711,12 @@ AdjLayout adj_layout(const lb_ctx* c, int nsteps, int K) {
   L.pops_slot = align256(es * Q * (size_t)c->pk.nodes);
   L.bead_arr = align256(sizeof(double) * 3 * (size_t)c->pk.slots_alloc);
   L.md_arr = align256(sizeof(double) * 6 * (size_t)c->d[0].nb * (size_t)c->n_sub);
+  L.upj_arr = align256(sizeof(double) * 6 * (size_t)c->pk.slots_alloc);
+  L.tape_entry = L.bead_arr + L.upj_arr;
   size_t o = 0;
   L.ckpt = o; o += (size_t)(L.nseg + 1) * c->sl.total;
   L.tape_pops = o; o += (size_t)K * L.pops_slot;
-  L.tape_beads = o; o += (size_t)K * 4 * L.bead_arr;
+  L.tape_beads = o; o += (size_t)K * L.tape_entry;
   L.lamA = o; o += L.pops_slot;
   L.lamB = o; o += L.pops_slot;
   L.lamu = o; o += align256(es * 3 * (size_t)c->pk.nodes);
@@ -765,14 +769,14 @@ void restore_state(lb_ctx* c, const char* st, void* dst_pops) {
 // to other_pops(c).
 void record_segment(lb_ctx* c, const AdjLayout& L, char* w, const char* ckpt, int len) {
   auto tape_pops = [&](int j) { return (void*)(w + L.tape_pops + (size_t)j * L.pops_slot); };
-  auto tape_bead = [&](int j, int which) {
-    return (double*)(w + L.tape_beads + ((size_t)j * 4 + which) * L.bead_arr);
-  };
+  // the step's start positions r, and after the step u_p and J (adjacent in
+  // the bead buffer, so one copy takes both)
+  auto tape_r = [&](int j) { return (double*)(w + L.tape_beads + (size_t)j * L.tape_entry); };
+  auto tape_upj = [&](int j) { return (double*)(w + L.tape_beads + (size_t)j * L.tape_entry + L.bead_arr); };
   const size_t nb3 = sizeof(double) * 3 * (size_t)c->pk.slots_alloc;
   restore_state(c, ckpt, tape_pops(0));
   for (int j = 0; j < len; ++j) {
-    acc(hipMemcpyAsync(tape_bead(j, 0), c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
-    acc(hipMemcpyAsync(tape_bead(j, 1), c->D.v, nb3, hipMemcpyDeviceToDevice, c->s));
+    acc(hipMemcpyAsync(tape_r(j), c->D.r, nb3, hipMemcpyDeviceToDevice, c->s));
     void* B = j + 1 < len ? tape_pops(j + 1) : other_pops(c);
     c->D.mdtape = (double*)(w + L.mdtape + (size_t)j * L.md_arr);
     // these steps keep the population parity, so the noise slot does not
@@ -780,8 +784,7 @@ void record_segment(lb_ctx* c, const AdjLayout& L, char* w, const char* ckpt, in
     c->noise_ready = false;
     enqueue_coupled_step_ab(c, tape_pops(j), B, c->s);
     c->D.mdtape = nullptr;
-    acc(hipMemcpyAsync(tape_bead(j, 2), c->D.up, nb3, hipMemcpyDeviceToDevice, c->s));
-    acc(hipMemcpyAsync(tape_bead(j, 3), c->D.J, nb3, hipMemcpyDeviceToDevice, c->s));
+    acc(hipMemcpyAsync(tape_upj(j), c->D.up, 2 * nb3, hipMemcpyDeviceToDevice, c->s));
   }
 }
 
@@ -1593,9 +1596,9 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
   acc(hipMemsetAsync(a.lamu, 0, es * 3 * (size_t)c->pk.nodes, c->s));
   launch_adj_init(dLdr, dLdv, a, nb, c->s);
   auto tape_pops = [&](int j) { return (void*)(w + L.tape_pops + (size_t)j * L.pops_slot); };
-  auto tape_bead = [&](int j, int which) {
-    return (double*)(w + L.tape_beads + ((size_t)j * 4 + which) * L.bead_arr);
-  };
+  auto tape_r = [&](int j) { return (double*)(w + L.tape_beads + (size_t)j * L.tape_entry); };
+  auto tape_up = [&](int j) { return (double*)(w + L.tape_beads + (size_t)j * L.tape_entry + L.bead_arr); };
+  auto tape_J = [&](int j) { return tape_up(j) + 3 * (size_t)c->pk.slots_alloc; };
   const double kT = c->d[0].kT;
   for (int seg = L.nseg - 1; seg >= 0; --seg) {
     const int n0 = seg * K;
@@ -1606,19 +1609,19 @@ int lb_adjoint_backward(lb_ctx* c, const double* dLdr, const double* dLdv, doubl
     // reverse the segment's steps
     for (int j = len - 1; j >= 0; --j) {
       Dev da = c->D;
-      da.r = tape_bead(j, 0);
+      da.r = tape_r(j);
       Dev ds = da;
       ds.J = a.lup;
       ds.force = a.lamu;
       const uint32_t step = (uint32_t)(c->adj_step0 + n0 + j);
       const double* mdt = (const double*)(w + L.mdtape + (size_t)j * L.md_arr);
       if (c->dev)
-        launch_adj_reverse_step<float, true>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_bead(j, 2),
-                                             tape_bead(j, 3), step, kT, c->ntiles, c->sweep.tile_nodes, c->nslots,
+        launch_adj_reverse_step<float, true>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_up(j),
+                                             tape_J(j), step, kT, c->ntiles, c->sweep.tile_nodes, c->nslots,
                                              nb, c->n_sub, c->s);
       else
-        launch_adj_reverse_step<double, false>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_bead(j, 2),
-                                               tape_bead(j, 3), step, kT, c->ntiles, c->sweep.tile_nodes,
+        launch_adj_reverse_step<double, false>(tape_pops(j), lamB, lamA, da, ds, a, mdt, tape_up(j),
+                                               tape_J(j), step, kT, c->ntiles, c->sweep.tile_nodes,
                                                c->nslots, nb, c->n_sub, c->s);
       std::swap(lamA, lamB);
     }
